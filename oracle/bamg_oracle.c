@@ -1,0 +1,1555 @@
+/*
+ * Plain FP64 CPU oracle of bootstrap-AMG preconditioned GMRES for Markov
+ * chains. TEST INFRASTRUCTURE ONLY: used by the test-suite, the smoke check
+ * and the CPU-baseline leg of the benchmark, never by the product path.
+ * Shares no code with the HIP implementation.
+ *
+ * Readings of the paper that this file adopts where it is silent (each is
+ * named where it is used):
+ *   R-JAC   weighted Jacobi is x <- x + omega D^-1 (b - B x)   (Section 3)
+ *   R-MU    one pass of the inner loop of Algorithm 1 (mu = 1)
+ *   R-KV    k_v = r: all r coarse triplets are carried back up
+ *   R-NSET  the setup uses nu_setup smoothing steps per visit
+ *   R-NORM  after pre-smoothing on level l, v_k is scaled to v^T N_l v = 1
+ *           and u_k (k >= 2) to u^T M_l u = 1 (Section 4.1 assumes unit
+ *           test vectors; the M/N norms keep the (u, v) pairs consistent)
+ *   R-W     LS weights 1/||B v||^2 are divided by their maximum
+ *   R-ACT   the paper picks J_i greedily (cited work); here the fit starts
+ *           from all candidates and, while a weight is negative, drops the
+ *           point with the most negative weight and refits (P rows and Q
+ *           columns alike; Q columns become convex combinations)
+ *   R-RANK  Householder QR without pivoting; a column whose |R_tt| falls
+ *           below 1e-12 * max|R_ss| is dropped (weight 0) and the fit redone
+ *   R-Q     the pattern of Q^T equals that of P (same J_i)
+ *   R-JI    J_i: geometric = coarse points within Chebyshev distance 1;
+ *           algebraic = coarse graph neighbours, ranked by the number of
+ *           common neighbours (ties: smaller index), at most c of them
+ *   R-MIS   algebraic C/F splitting = greedy maximal independent set of the
+ *           symmetrised graph in decreasing pseudo-random priority (stand-in
+ *           for compatible relaxation, whose algorithm the paper cites only)
+ *   R-GAL   Galerkin patterns are structural products; no value dropping;
+ *           the diagonal is always stored
+ *   R-PINV  B_L^+ drops exactly the smallest singular value of B_L
+ *   R-X0    x0 = the level-0 right test vector with the smallest sigma
+ *   R-SIM   u and v are relaxed simultaneously (both from old values)
+ *   R-GM    GMRES: modified Gram-Schmidt, Givens rotations, true scaled
+ *           residual ||Bx||/||x|| tested after every iteration
+ */
+#include "bamg_oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NEW(T, k) ((T *)calloc((size_t)((k) > 0 ? (k) : 1), sizeof(T)))
+
+/* ------------------------------------------------------------------ CSR */
+typedef struct {
+  int nr, nc, nnz;
+  int32_t *rp, *ci;
+  double *v;
+} csr;
+
+static csr csr_new(int nr, int nc, int nnz) {
+  csr A;
+  A.nr = nr;
+  A.nc = nc;
+  A.nnz = nnz;
+  A.rp = NEW(int32_t, nr + 1);
+  A.ci = NEW(int32_t, nnz);
+  A.v = NEW(double, nnz);
+  return A;
+}
+
+static void csr_free(csr *A) {
+  free(A->rp);
+  free(A->ci);
+  free(A->v);
+  memset(A, 0, sizeof(*A));
+}
+
+static csr csr_copy(const csr *A) {
+  csr B = csr_new(A->nr, A->nc, A->nnz);
+  memcpy(B.rp, A->rp, sizeof(int32_t) * (A->nr + 1));
+  memcpy(B.ci, A->ci, sizeof(int32_t) * A->nnz);
+  memcpy(B.v, A->v, sizeof(double) * A->nnz);
+  return B;
+}
+
+static csr csr_identity(int n) {
+  csr I = csr_new(n, n, n);
+  for (int i = 0; i < n; ++i) {
+    I.rp[i + 1] = i + 1;
+    I.ci[i] = i;
+    I.v[i] = 1.0;
+  }
+  return I;
+}
+
+/* Transpose by counting sort: within each output row the entries stay in
+ * increasing column order because input rows are visited in order. */
+static csr csr_transpose(const csr *A) {
+  csr T = csr_new(A->nc, A->nr, A->nnz);
+  for (int k = 0; k < A->nnz; ++k) T.rp[A->ci[k] + 1]++;
+  for (int j = 0; j < A->nc; ++j) T.rp[j + 1] += T.rp[j];
+  int32_t *pos = NEW(int32_t, A->nc);
+  for (int j = 0; j < A->nc; ++j) pos[j] = T.rp[j];
+  for (int i = 0; i < A->nr; ++i)
+    for (int k = A->rp[i]; k < A->rp[i + 1]; ++k) {
+      int p = pos[A->ci[k]]++;
+      T.ci[p] = i;
+      T.v[p] = A->v[k];
+    }
+  free(pos);
+  return T;
+}
+
+static int cmp_i32(const void *a, const void *b) {
+  int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+  return (x > y) - (x < y);
+}
+
+/* Sparse product C = X * Y (Gustavson, dense accumulator). Every structural
+ * product term creates an entry, whatever its value (R-GAL); if force_diag,
+ * the diagonal is stored even when no term reaches it. Columns ascending. */
+static csr csr_matmul(const csr *X, const csr *Y, int force_diag) {
+  int nr = X->nr, nc = Y->nc;
+  int32_t *mark = NEW(int32_t, nc);
+  double *acc = NEW(double, nc);
+  int32_t *cols = NEW(int32_t, nc);
+  for (int j = 0; j < nc; ++j) mark[j] = -1;
+  /* pass 1: count */
+  int32_t *rp = NEW(int32_t, nr + 1);
+  for (int i = 0; i < nr; ++i) {
+    int cnt = 0;
+    if (force_diag && i < nc) {
+      mark[i] = i;
+      cnt++;
+    }
+    for (int a = X->rp[i]; a < X->rp[i + 1]; ++a) {
+      int k = X->ci[a];
+      for (int b = Y->rp[k]; b < Y->rp[k + 1]; ++b) {
+        int j = Y->ci[b];
+        if (mark[j] != i) {
+          mark[j] = i;
+          cnt++;
+        }
+      }
+    }
+    rp[i + 1] = rp[i] + cnt;
+  }
+  csr C = csr_new(nr, nc, rp[nr]);
+  memcpy(C.rp, rp, sizeof(int32_t) * (nr + 1));
+  free(rp);
+  for (int j = 0; j < nc; ++j) mark[j] = -1;
+  /* pass 2: values */
+  for (int i = 0; i < nr; ++i) {
+    int cnt = 0;
+    if (force_diag && i < nc) {
+      mark[i] = i;
+      acc[i] = 0.0;
+      cols[cnt++] = i;
+    }
+    for (int a = X->rp[i]; a < X->rp[i + 1]; ++a) {
+      int k = X->ci[a];
+      double xv = X->v[a];
+      for (int b = Y->rp[k]; b < Y->rp[k + 1]; ++b) {
+        int j = Y->ci[b];
+        if (mark[j] != i) {
+          mark[j] = i;
+          acc[j] = 0.0;
+          cols[cnt++] = j;
+        }
+        acc[j] += xv * Y->v[b];
+      }
+    }
+    qsort(cols, cnt, sizeof(int32_t), cmp_i32);
+    for (int t = 0; t < cnt; ++t) {
+      C.ci[C.rp[i] + t] = cols[t];
+      C.v[C.rp[i] + t] = acc[cols[t]];
+    }
+  }
+  free(mark);
+  free(acc);
+  free(cols);
+  return C;
+}
+
+/* y = A x */
+static void csr_spmv(const csr *A, const double *x, double *y) {
+  for (int i = 0; i < A->nr; ++i) {
+    double s = 0.0;
+    for (int k = A->rp[i]; k < A->rp[i + 1]; ++k) s += A->v[k] * x[A->ci[k]];
+    y[i] = s;
+  }
+}
+
+/* Y = A X for X with r columns, row-major */
+static void csr_spmm(const csr *A, int r, const double *X, double *Y) {
+  for (int i = 0; i < A->nr; ++i)
+    for (int k = 0; k < r; ++k) {
+      double s = 0.0;
+      for (int a = A->rp[i]; a < A->rp[i + 1]; ++a) s += A->v[a] * X[(size_t)A->ci[a] * r + k];
+      Y[(size_t)i * r + k] = s;
+    }
+}
+
+static double dot(int n, const double *x, const double *y) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += x[i] * y[i];
+  return s;
+}
+
+/* ------------------------------------------------------------- Philox */
+/* Philox-4x64-10 counter-based generator (Salmon, Moraes, Dror, Shaw,
+ * "Parallel random numbers: as easy as 1, 2, 3", SC'11): ten rounds of
+ * two 64x64->128 multiplies with a Weyl-sequence key schedule. */
+static void mulhilo64(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo) {
+  unsigned __int128 p = (unsigned __int128)a * b;
+  *hi = (uint64_t)(p >> 64);
+  *lo = (uint64_t)p;
+}
+
+void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+  uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint64_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    uint64_t hi0, lo0, hi1, lo1;
+    mulhilo64(M0, c0, &hi0, &lo0);
+    mulhilo64(M1, c2, &hi1, &lo1);
+    uint64_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+    c0 = n0;
+    c1 = n1;
+    c2 = n2;
+    c3 = n3;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+/* Uniform on [-1, 1) from the top 53 bits of the first Philox word, keyed
+ * by (seed, 0), counter (i, k, side, 0). Random test vectors of Section 4.2. */
+double orc_uniform_pm1(uint64_t seed, uint64_t side, uint64_t k, uint64_t i) {
+  uint64_t ctr[4] = {i, k, side, 0}, key[2] = {seed, 0}, out[4];
+  orc_philox4x64(ctr, key, out);
+  double u = (double)(out[0] >> 11) * (1.0 / 9007199254740992.0);
+  return 2.0 * u - 1.0;
+}
+
+static uint64_t priority_word(uint64_t seed, uint64_t side, int level, int i) {
+  uint64_t ctr[4] = {(uint64_t)i, (uint64_t)level, side, 0}, key[2] = {seed, 0}, out[4];
+  orc_philox4x64(ctr, key, out);
+  return out[0];
+}
+
+/* ------------------------------------------------------- dense helpers */
+/* Cholesky A = L L^T of an SPD n x n row-major matrix; L lower, row-major. */
+static int chol(int n, const double *A, double *L) {
+  memset(L, 0, sizeof(double) * n * n);
+  for (int j = 0; j < n; ++j) {
+    double s = A[j * n + j];
+    for (int k = 0; k < j; ++k) s -= L[j * n + k] * L[j * n + k];
+    if (!(s > 0.0)) return ORC_E_COARSE;
+    double d = sqrt(s);
+    L[j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double t = A[i * n + j];
+      for (int k = 0; k < j; ++k) t -= L[i * n + k] * L[j * n + k];
+      L[i * n + j] = t / d;
+    }
+  }
+  return ORC_OK;
+}
+
+/* Solve L y = b (forward) and L^T y = b (backward), L row-major lower. */
+static void trsv_lower(int n, const double *L, double *b) {
+  for (int i = 0; i < n; ++i) {
+    double s = b[i];
+    for (int k = 0; k < i; ++k) s -= L[i * n + k] * b[k];
+    b[i] = s / L[i * n + i];
+  }
+}
+static void trsv_lower_t(int n, const double *L, double *b) {
+  for (int i = n - 1; i >= 0; --i) {
+    double s = b[i];
+    for (int k = i + 1; k < n; ++k) s -= L[k * n + i] * b[k];
+    b[i] = s / L[i * n + i];
+  }
+}
+
+/* One-sided Jacobi SVD (Hestenes): rotate column pairs of W = B until they
+ * are mutually orthogonal; then B = W J^T with W = U diag(s), V = J.
+ * U, V column-major n x n; s[k] = ||W_k||. Cyclic-by-rows ordering. */
+int orc_svd_jacobi(int n, const double *B, double *s, double *U, double *V) {
+  double *W = NEW(double, (size_t)n * n); /* column-major */
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) W[(size_t)j * n + i] = B[(size_t)i * n + j];
+  for (int i = 0; i < n * n; ++i) V[i] = 0.0;
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  const double tol = 1e-15;
+  int sweep;
+  for (sweep = 0; sweep < 80; ++sweep) {
+    int rotated = 0;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double *wp = W + (size_t)p * n, *wq = W + (size_t)q * n;
+        double al = dot(n, wp, wp), be = dot(n, wq, wq), ga = dot(n, wp, wq);
+        if (fabs(ga) <= tol * sqrt(al * be) || ga == 0.0) continue;
+        rotated = 1;
+        double zeta = (be - al) / (2.0 * ga);
+        double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+        for (int i = 0; i < n; ++i) {
+          double a = wp[i], b = wq[i];
+          wp[i] = c * a - sn * b;
+          wq[i] = sn * a + c * b;
+        }
+        double *vp = V + (size_t)p * n, *vq = V + (size_t)q * n;
+        for (int i = 0; i < n; ++i) {
+          double a = vp[i], b = vq[i];
+          vp[i] = c * a - sn * b;
+          vq[i] = sn * a + c * b;
+        }
+      }
+    if (!rotated) break;
+  }
+  for (int k = 0; k < n; ++k) {
+    double nk = sqrt(dot(n, W + (size_t)k * n, W + (size_t)k * n));
+    s[k] = nk;
+    for (int i = 0; i < n; ++i) U[(size_t)k * n + i] = nk > 0 ? W[(size_t)k * n + i] / nk : 0.0;
+  }
+  free(W);
+  return sweep < 80 ? ORC_OK : ORC_E_COARSE;
+}
+
+/* Order of singular values ascending, ties to the lower index. */
+static double *g_sort_key;
+static int cmp_sig(const void *a, const void *b) {
+  int x = *(const int *)a, y = *(const int *)b;
+  double u = g_sort_key[x], v = g_sort_key[y];
+  if (u < v) return -1;
+  if (u > v) return 1;
+  return (x > y) - (x < y);
+}
+
+/* Generalized singular triplets of eq. generalized_eigenvalue:
+ * B v = sigma M u, B^T u = sigma N v, u^T M u = v^T N v = 1. Reduced to an
+ * ordinary SVD through the Cholesky factors M = L_M L_M^T, N = L_N L_N^T:
+ * Bt = L_M^-1 B L_N^-T = Ut S Vt^T, u = L_M^-T ut, v = L_N^-T vt. */
+int orc_gsvd(int n, const double *B, const double *M, const double *N, double *sigma, double *U,
+             double *V) {
+  double *LM = NEW(double, n * n), *LN = NEW(double, n * n);
+  int st = chol(n, M, LM);
+  if (st == ORC_OK) st = chol(n, N, LN);
+  if (st != ORC_OK) {
+    free(LM);
+    free(LN);
+    return st;
+  }
+  double *X = NEW(double, n * n), *col = NEW(double, n);
+  /* X = L_M^-1 B (column by column) */
+  for (int j = 0; j < n; ++j) {
+    for (int i = 0; i < n; ++i) col[i] = B[i * n + j];
+    trsv_lower(n, LM, col);
+    for (int i = 0; i < n; ++i) X[i * n + j] = col[i];
+  }
+  /* Bt = X L_N^-T: row i of Bt solves L_N y = X[i,:]^T */
+  double *Bt = NEW(double, n * n);
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) col[j] = X[i * n + j];
+    trsv_lower(n, LN, col);
+    for (int j = 0; j < n; ++j) Bt[i * n + j] = col[j];
+  }
+  double *s = NEW(double, n), *Ut = NEW(double, n * n), *Vt = NEW(double, n * n);
+  st = orc_svd_jacobi(n, Bt, s, Ut, Vt);
+  int *ord = NEW(int, n);
+  for (int k = 0; k < n; ++k) ord[k] = k;
+  g_sort_key = s;
+  qsort(ord, n, sizeof(int), cmp_sig);
+  for (int t = 0; t < n; ++t) {
+    int k = ord[t];
+    sigma[t] = s[k];
+    for (int i = 0; i < n; ++i) col[i] = Ut[(size_t)k * n + i];
+    trsv_lower_t(n, LM, col);
+    for (int i = 0; i < n; ++i) U[(size_t)t * n + i] = col[i];
+    for (int i = 0; i < n; ++i) col[i] = Vt[(size_t)k * n + i];
+    trsv_lower_t(n, LN, col);
+    for (int i = 0; i < n; ++i) V[(size_t)t * n + i] = col[i];
+  }
+  free(LM);
+  free(LN);
+  free(X);
+  free(col);
+  free(Bt);
+  free(s);
+  free(Ut);
+  free(Vt);
+  free(ord);
+  return st;
+}
+
+/* Householder QR least squares min ||G p - g||, G rows x m row-major.
+ * R-RANK: columns with |R_tt| <= 1e-12 max|R_ss| are removed and the fit
+ * redone; removed columns get coefficient 0. Returns number kept. */
+static int ls_householder(int rows, int m, const double *G0, const double *g0, double *p) {
+  int active[16];
+  int na = 0;
+  for (int t = 0; t < m; ++t) {
+    p[t] = 0.0;
+    if (t < rows) active[na++] = t;
+  }
+  double G[64 * 16], g[64], R[16];
+  for (;;) {
+    if (na == 0) return 0;
+    for (int k = 0; k < rows; ++k) {
+      for (int a = 0; a < na; ++a) G[k * na + a] = G0[k * m + active[a]];
+      g[k] = g0[k];
+    }
+    for (int a = 0; a < na; ++a) {
+      double nrm = 0.0;
+      for (int k = a; k < rows; ++k) nrm += G[k * na + a] * G[k * na + a];
+      nrm = sqrt(nrm);
+      double x0 = G[a * na + a];
+      double alpha = x0 >= 0 ? -nrm : nrm;
+      R[a] = alpha;
+      if (nrm == 0.0) continue;
+      /* v = x - alpha e1, stored in place in column a */
+      G[a * na + a] = x0 - alpha;
+      double vtv = 0.0;
+      for (int k = a; k < rows; ++k) vtv += G[k * na + a] * G[k * na + a];
+      if (vtv == 0.0) continue;
+      for (int b = a + 1; b < na; ++b) {
+        double s = 0.0;
+        for (int k = a; k < rows; ++k) s += G[k * na + a] * G[k * na + b];
+        s = 2.0 * s / vtv;
+        for (int k = a; k < rows; ++k) G[k * na + b] -= s * G[k * na + a];
+      }
+      double s = 0.0;
+      for (int k = a; k < rows; ++k) s += G[k * na + a] * g[k];
+      s = 2.0 * s / vtv;
+      for (int k = a; k < rows; ++k) g[k] -= s * G[k * na + a];
+    }
+    double rmax = 0.0;
+    for (int a = 0; a < na; ++a) rmax = fmax(rmax, fabs(R[a]));
+    int drop = -1;
+    for (int a = 0; a < na; ++a)
+      if (!(fabs(R[a]) > 1e-12 * rmax)) {
+        drop = a;
+        break;
+      }
+    if (drop >= 0) {
+      for (int a = drop; a + 1 < na; ++a) active[a] = active[a + 1];
+      na--;
+      continue;
+    }
+    /* back substitution: R is the diagonal R[] plus the strict upper part of G */
+    double x[16];
+    for (int a = na - 1; a >= 0; --a) {
+      double s = g[a];
+      for (int b = a + 1; b < na; ++b) s -= G[a * na + b] * x[b];
+      x[a] = s / R[a];
+    }
+    for (int a = 0; a < na; ++a) p[active[a]] = x[a];
+    return na;
+  }
+}
+
+/* eq. ls_interpolation: minimise sum_k w_k (g_k - sum_t p_t G_kt)^2. */
+int orc_ls_row(int r, int m, const double *G, const double *g, const double *w, double *p) {
+  if (r > 64 || m > 16) return ORC_E_ARG;
+  double Gw[64 * 16], gw[64];
+  for (int k = 0; k < r; ++k) {
+    double s = sqrt(w[k]);
+    for (int t = 0; t < m; ++t) Gw[k * m + t] = s * G[k * m + t];
+    gw[k] = s * g[k];
+  }
+  ls_householder(r, m, Gw, gw, p);
+  return ORC_OK;
+}
+
+/* Section 5: the constant vector (test vector k = 0) is matched exactly,
+ * i.e. sum_t q_t = 1, and the other r-1 vectors are fitted in the weighted
+ * LS sense. The last coefficient is eliminated, q_m = 1 - sum_{t<m} q_t,
+ * which leaves an unconstrained LS in the differences to the last point. */
+int orc_ls_row_sum1(int r, int m, const double *G, const double *g, const double *w, double *q) {
+  if (r > 64 || m > 16 || m < 1) return ORC_E_ARG;
+  if (m == 1) {
+    q[0] = 1.0;
+    return ORC_OK;
+  }
+  int rows = r - 1, mm = m - 1;
+  double Gd[64 * 16], gd[64], x[16];
+  for (int k = 1; k < r; ++k) {
+    double s = sqrt(w[k]);
+    double last = G[k * m + (m - 1)];
+    for (int t = 0; t < mm; ++t) Gd[(k - 1) * mm + t] = s * (G[k * m + t] - last);
+    gd[k - 1] = s * (g[k] - last);
+  }
+  ls_householder(rows, mm, Gd, gd, x);
+  double sum = 0.0;
+  for (int t = 0; t < mm; ++t) {
+    q[t] = x[t];
+    sum += x[t];
+  }
+  q[m - 1] = 1.0 - sum;
+  return ORC_OK;
+}
+
+/* ------------------------------------------------ coarsening (integer) */
+typedef struct {
+  uint64_t key;
+  int32_t i;
+} prio;
+static int cmp_prio_desc(const void *a, const void *b) {
+  const prio *x = (const prio *)a, *y = (const prio *)b;
+  if (x->key != y->key) return x->key < y->key ? 1 : -1;
+  return (x->i < y->i) - (x->i > y->i);
+}
+
+/* R-MIS: visit vertices in decreasing (priority, index); an undecided vertex
+ * becomes C and its undecided neighbours become F. cf: 1 = C, 0 = F. */
+int orc_mis(int n, const int32_t *rp, const int32_t *ci, uint64_t seed, int level, int32_t *cf) {
+  prio *ord = NEW(prio, n);
+  for (int i = 0; i < n; ++i) {
+    ord[i].key = priority_word(seed, 2, level, i);
+    ord[i].i = i;
+  }
+  qsort(ord, n, sizeof(prio), cmp_prio_desc);
+  for (int i = 0; i < n; ++i) cf[i] = -1;
+  for (int t = 0; t < n; ++t) {
+    int v = ord[t].i;
+    if (cf[v] != -1) continue;
+    cf[v] = 1;
+    for (int k = rp[v]; k < rp[v + 1]; ++k)
+      if (cf[ci[k]] == -1) cf[ci[k]] = 0;
+  }
+  free(ord);
+  return ORC_OK;
+}
+
+/* Greedy distance-2 colouring of the rows of a matrix in decreasing
+ * pseudo-random priority: rows that share a column get different colours,
+ * each row takes the smallest colour not used by earlier rows it conflicts
+ * with. (rp, ci) = rows, (crp, cci) = the columns' row lists. */
+int orc_row_colouring(int n, const int32_t *rp, const int32_t *ci, const int32_t *crp,
+                      const int32_t *cci, int32_t *colour) {
+  prio *ord = NEW(prio, n);
+  for (int i = 0; i < n; ++i) {
+    ord[i].key = priority_word(0x4b41435aULL, 3, 0, i);
+    ord[i].i = i;
+  }
+  qsort(ord, n, sizeof(prio), cmp_prio_desc);
+  for (int i = 0; i < n; ++i) colour[i] = -1;
+  int32_t *used = NEW(int32_t, n + 1);
+  for (int i = 0; i <= n; ++i) used[i] = -1;
+  for (int t = 0; t < n; ++t) {
+    int v = ord[t].i;
+    for (int a = rp[v]; a < rp[v + 1]; ++a) {
+      int j = ci[a];
+      for (int b = crp[j]; b < crp[j + 1]; ++b) {
+        int w = cci[b];
+        if (w != v && colour[w] >= 0) used[colour[w]] = v;
+      }
+    }
+    int c = 0;
+    while (used[c] == v) ++c;
+    colour[v] = c;
+  }
+  free(used);
+  free(ord);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------- levels */
+typedef struct {
+  int n, nc, nx, ny, gkind; /* gkind: 0 none, 1 line, 2 grid */
+  csr B, Bt, M, N;
+  double *d;
+  int32_t *cf, *cidx, *cpts;
+  csr P, Qt, Q, Pt; /* P, Qt: n x nc (same pattern); Q, Pt: nc x n */
+  csr G;            /* symmetrised graph of B without diagonal */
+  int32_t *colB, *colBt, ncolB, ncolBt; /* Kaczmarz row colourings */
+  double *U, *V;
+} level;
+
+struct orc_ctx {
+  orc_options o;
+  int L; /* number of levels; level L-1 is the coarsest */
+  level lv[32];
+  double *sigma;
+  double *bdag; /* coarsest pseudo-inverse, row-major */
+  double *x0;
+};
+
+void orc_default_options(orc_options *o) {
+  memset(o, 0, sizeof(*o));
+  o->r = 8;
+  o->setup_cycles = 1;
+  o->nu_pre = 3;
+  o->nu_post = 3;
+  o->nu_setup = 3;
+  o->omega = 0.7;
+  o->max_interp = 4;
+  o->max_levels = 16;
+  o->coarse_max = 289;
+  o->coarsening = ORC_COARSEN_GEOM;
+  o->geom_kind = 2;
+  o->seed = 14024001ULL;
+  o->smoother = ORC_SMOOTH_JACOBI;
+  o->interp_rule = 1;
+}
+
+/* symmetrised pattern of B without the diagonal (for MIS and J_i) */
+static csr sym_graph(const csr *B, const csr *Bt) {
+  int n = B->nr;
+  int32_t *rp = NEW(int32_t, n + 1);
+  int32_t *tmp = NEW(int32_t, B->nnz + Bt->nnz);
+  int pos = 0;
+  for (int i = 0; i < n; ++i) {
+    int a = B->rp[i], ae = B->rp[i + 1], b = Bt->rp[i], be = Bt->rp[i + 1];
+    while (a < ae || b < be) {
+      int j;
+      if (b >= be || (a < ae && B->ci[a] < Bt->ci[b]))
+        j = B->ci[a++];
+      else if (a >= ae || Bt->ci[b] < B->ci[a])
+        j = Bt->ci[b++];
+      else {
+        j = B->ci[a++];
+        b++;
+      }
+      if (j != i) tmp[pos++] = j;
+    }
+    rp[i + 1] = pos;
+  }
+  csr G = csr_new(n, n, pos);
+  memcpy(G.rp, rp, sizeof(int32_t) * (n + 1));
+  memcpy(G.ci, tmp, sizeof(int32_t) * pos);
+  for (int k = 0; k < pos; ++k) G.v[k] = 1.0;
+  free(rp);
+  free(tmp);
+  return G;
+}
+
+/* C/F splitting of level l (Section 3; geometric rule of Section 7 or the
+ * R-MIS stand-in), coarse numbering in increasing fine index. */
+static void coarsen(orc_ctx *c, int l) {
+  level *L = &c->lv[l];
+  int n = L->n;
+  L->cf = NEW(int32_t, n);
+  L->cidx = NEW(int32_t, n);
+  if (c->o.coarsening == ORC_COARSEN_GEOM && L->gkind == 2) {
+    for (int s = 0; s < n; ++s) {
+      int ix = s % L->nx, iy = s / L->nx;
+      L->cf[s] = (ix % 2 == 0 && iy % 2 == 0);
+    }
+  } else if (c->o.coarsening == ORC_COARSEN_GEOM && L->gkind == 1) {
+    for (int s = 0; s < n; ++s) L->cf[s] = (s % 2 == 0);
+  } else {
+    orc_mis(n, L->G.rp, L->G.ci, c->o.seed, l, L->cf);
+  }
+  int nc = 0;
+  for (int s = 0; s < n; ++s) L->cidx[s] = L->cf[s] ? nc++ : -1;
+  L->nc = nc;
+  L->cpts = NEW(int32_t, nc);
+  for (int s = 0; s < n; ++s)
+    if (L->cf[s]) L->cpts[L->cidx[s]] = s;
+}
+
+typedef struct {
+  int score, j;
+} cand;
+static int cmp_cand(const void *a, const void *b) {
+  const cand *x = (const cand *)a, *y = (const cand *)b;
+  if (x->score != y->score) return y->score - x->score;
+  return x->j - y->j;
+}
+
+/* Interpolation sets J_i (Section 4.1, R-JI) -> pattern of P (eq.
+ * Pstructure: identity on C rows). Entries hold coarse indices, ascending. */
+static void build_P_pattern(orc_ctx *c, int l) {
+  level *L = &c->lv[l];
+  int n = L->n, cap = c->o.max_interp;
+  int32_t *rp = NEW(int32_t, n + 1);
+  int32_t *buf = NEW(int32_t, (size_t)n * (cap > 9 ? cap : 9));
+  int pos = 0;
+  int32_t *mark = NEW(int32_t, n);
+  for (int s = 0; s < n; ++s) mark[s] = -1;
+  cand *cs = NEW(cand, n);
+  for (int i = 0; i < n; ++i) {
+    int start = pos;
+    if (L->cf[i]) {
+      buf[pos++] = L->cidx[i];
+    } else if (c->o.coarsening == ORC_COARSEN_GEOM && L->gkind == 2) {
+      int ix = i % L->nx, iy = i / L->nx;
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          int jx = ix + dx, jy = iy + dy;
+          if (jx < 0 || jy < 0 || jx >= L->nx || jy >= L->ny) continue;
+          int j = jy * L->nx + jx;
+          if (L->cf[j] && pos - start < cap) buf[pos++] = L->cidx[j];
+        }
+    } else if (c->o.coarsening == ORC_COARSEN_GEOM && L->gkind == 1) {
+      if (i - 1 >= 0 && L->cf[i - 1] && pos - start < cap) buf[pos++] = L->cidx[i - 1];
+      if (i + 1 < n && L->cf[i + 1] && pos - start < cap) buf[pos++] = L->cidx[i + 1];
+    } else {
+      /* coarse neighbours ranked by common-neighbour count */
+      for (int k = L->G.rp[i]; k < L->G.rp[i + 1]; ++k) mark[L->G.ci[k]] = i;
+      int nc = 0;
+      for (int k = L->G.rp[i]; k < L->G.rp[i + 1]; ++k) {
+        int j = L->G.ci[k];
+        if (!L->cf[j]) continue;
+        int sc = 0;
+        for (int q = L->G.rp[j]; q < L->G.rp[j + 1]; ++q) sc += (mark[L->G.ci[q]] == i);
+        cs[nc].score = sc;
+        cs[nc].j = j;
+        nc++;
+      }
+      qsort(cs, nc, sizeof(cand), cmp_cand);
+      for (int t = 0; t < nc && t < cap; ++t) buf[pos++] = L->cidx[cs[t].j];
+      qsort(buf + start, pos - start, sizeof(int32_t), cmp_i32);
+    }
+    rp[i + 1] = pos;
+  }
+  L->P = csr_new(n, L->nc, pos);
+  memcpy(L->P.rp, rp, sizeof(int32_t) * (n + 1));
+  memcpy(L->P.ci, buf, sizeof(int32_t) * pos);
+  for (int i = 0; i < n; ++i)
+    if (L->cf[i]) L->P.v[L->P.rp[i]] = 1.0;
+  L->Qt = csr_copy(&L->P);
+  free(rp);
+  free(buf);
+  free(mark);
+  free(cs);
+}
+
+static void level_free(level *L) {
+  csr_free(&L->B);
+  csr_free(&L->Bt);
+  csr_free(&L->M);
+  csr_free(&L->N);
+  csr_free(&L->P);
+  csr_free(&L->Qt);
+  csr_free(&L->Q);
+  csr_free(&L->Pt);
+  csr_free(&L->G);
+  free(L->d);
+  free(L->cf);
+  free(L->cidx);
+  free(L->cpts);
+  free(L->colB);
+  free(L->colBt);
+  free(L->U);
+  free(L->V);
+}
+
+static void set_operator(level *L, csr B) {
+  csr_free(&L->B);
+  csr_free(&L->Bt);
+  L->B = B;
+  L->Bt = csr_transpose(&L->B);
+  free(L->d);
+  L->d = NEW(double, L->n);
+  for (int i = 0; i < L->n; ++i)
+    for (int k = L->B.rp[i]; k < L->B.rp[i + 1]; ++k)
+      if (L->B.ci[k] == i) L->d[i] = L->B.v[k];
+}
+
+/* Galerkin products of Algorithm 1: B_{l+1} = Q B P, M_{l+1} = Q M Q^T,
+ * N_{l+1} = P^T N P (R-GAL). Also refreshes Q and P^T from Q^T and P. */
+static void galerkin(orc_ctx *c, int l) {
+  level *L = &c->lv[l], *C = &c->lv[l + 1];
+  csr_free(&L->Q);
+  csr_free(&L->Pt);
+  L->Q = csr_transpose(&L->Qt);
+  L->Pt = csr_transpose(&L->P);
+  csr BP = csr_matmul(&L->B, &L->P, 0);
+  csr Bc = csr_matmul(&L->Q, &BP, 1);
+  csr MQt = csr_matmul(&L->M, &L->Qt, 0);
+  csr Mc = csr_matmul(&L->Q, &MQt, 1);
+  csr NP = csr_matmul(&L->N, &L->P, 0);
+  csr Nc = csr_matmul(&L->Pt, &NP, 1);
+  csr_free(&BP);
+  csr_free(&MQt);
+  csr_free(&NP);
+  set_operator(C, Bc);
+  csr_free(&C->M);
+  csr_free(&C->N);
+  C->M = Mc;
+  C->N = Nc;
+}
+
+/* ---------------------------------------------------------- smoothing */
+/* One sweep of the stationary smoother on B_l x = b (eq. smoothing:eq).
+ * Jacobi: F = D / omega (R-JAC). Kaczmarz: row projections in colour order. */
+static void smooth_vec(const orc_ctx *c, const level *L, int transpose, const double *b,
+                       double *x) {
+  const csr *A = transpose ? &L->Bt : &L->B;
+  int n = L->n;
+  if (c->o.smoother == ORC_SMOOTH_KACZMARZ) {
+    const int32_t *col = transpose ? L->colBt : L->colB;
+    int ncol = transpose ? L->ncolBt : L->ncolB;
+    for (int cc = 0; cc < ncol; ++cc)
+      for (int i = 0; i < n; ++i) {
+        if (col[i] != cc) continue;
+        double ax = 0.0, nn = 0.0;
+        for (int k = A->rp[i]; k < A->rp[i + 1]; ++k) {
+          ax += A->v[k] * x[A->ci[k]];
+          nn += A->v[k] * A->v[k];
+        }
+        double t = (b[i] - ax) / nn;
+        for (int k = A->rp[i]; k < A->rp[i + 1]; ++k) x[A->ci[k]] += t * A->v[k];
+      }
+    return;
+  }
+  double *ax = NEW(double, n);
+  csr_spmv(A, x, ax);
+  for (int i = 0; i < n; ++i) x[i] += c->o.omega / L->d[i] * (b[i] - ax[i]);
+  free(ax);
+}
+
+int orc_smooth(const orc_ctx *c, int l, const double *b, double *x) {
+  if (l < 0 || l >= c->L - 1) return ORC_E_ARG;
+  smooth_vec(c, &c->lv[l], 0, b, x);
+  return ORC_OK;
+}
+
+/* sigma_k by the generalized Rayleigh quotient (eq. singular_value). */
+static void update_sigma(orc_ctx *c, level *L) {
+  int n = L->n, r = c->o.r;
+  double *u = NEW(double, n), *v = NEW(double, n), *t = NEW(double, n);
+  for (int k = 0; k < r; ++k) {
+    for (int i = 0; i < n; ++i) {
+      u[i] = L->U[(size_t)i * r + k];
+      v[i] = L->V[(size_t)i * r + k];
+    }
+    csr_spmv(&L->B, v, t);
+    double ubv = dot(n, u, t);
+    csr_spmv(&L->M, u, t);
+    double umu = dot(n, u, t);
+    csr_spmv(&L->N, v, t);
+    double vnv = dot(n, v, t);
+    double den = sqrt(umu * vnv);
+    c->sigma[k] = den > 0 ? ubv / den : 0.0;
+  }
+  free(u);
+  free(v);
+  free(t);
+}
+
+/* nu_setup relaxation steps on the r test-vector pairs (Algorithm 1):
+ * homogeneous (with_rhs = 0) or with right-hand sides sigma M u for v and
+ * sigma N v for u, sigma updated after every step. Column 0 of U is the
+ * constant vector and is never relaxed (Section 5). */
+static void relax_pairs(orc_ctx *c, level *L, int with_rhs) {
+  int n = L->n, r = c->o.r;
+  double *u = NEW(double, n), *v = NEW(double, n), *bu = NEW(double, n), *bv = NEW(double, n);
+  for (int s = 0; s < c->o.nu_setup; ++s) {
+    for (int k = 0; k < r; ++k) {
+      for (int i = 0; i < n; ++i) {
+        u[i] = L->U[(size_t)i * r + k];
+        v[i] = L->V[(size_t)i * r + k];
+      }
+      if (with_rhs) {
+        csr_spmv(&L->M, u, bv);
+        csr_spmv(&L->N, v, bu);
+        for (int i = 0; i < n; ++i) {
+          bv[i] *= c->sigma[k];
+          bu[i] *= c->sigma[k];
+        }
+      } else {
+        memset(bv, 0, sizeof(double) * n);
+        memset(bu, 0, sizeof(double) * n);
+      }
+      /* R-SIM: both right-hand sides were formed from the old u and v */
+      smooth_vec(c, L, 0, bv, v);
+      if (k > 0) smooth_vec(c, L, 1, bu, u);
+      for (int i = 0; i < n; ++i) {
+        L->V[(size_t)i * r + k] = v[i];
+        if (k > 0) L->U[(size_t)i * r + k] = u[i];
+      }
+    }
+    if (with_rhs) update_sigma(c, L);
+  }
+  free(u);
+  free(v);
+  free(bu);
+  free(bv);
+}
+
+/* R-NORM */
+static void normalize_pairs(orc_ctx *c, level *L) {
+  int n = L->n, r = c->o.r;
+  double *x = NEW(double, n), *t = NEW(double, n);
+  for (int k = 0; k < r; ++k) {
+    for (int i = 0; i < n; ++i) x[i] = L->V[(size_t)i * r + k];
+    csr_spmv(&L->N, x, t);
+    double s = dot(n, x, t);
+    if (s > 0) {
+      s = 1.0 / sqrt(s);
+      for (int i = 0; i < n; ++i) L->V[(size_t)i * r + k] *= s;
+    }
+    if (k == 0) continue;
+    for (int i = 0; i < n; ++i) x[i] = L->U[(size_t)i * r + k];
+    csr_spmv(&L->M, x, t);
+    s = dot(n, x, t);
+    if (s > 0) {
+      s = 1.0 / sqrt(s);
+      for (int i = 0; i < n; ++i) L->U[(size_t)i * r + k] *= s;
+    }
+  }
+  free(x);
+  free(t);
+}
+
+/* Weighted LS value of a P-row fit on the active columns (sum1 = 0) or of a
+ * Q-column fit with the sum-to-one constraint (sum1 = 1); coefficients of
+ * inactive columns are 0. Returns the LS functional. */
+static double fit_subset(int r, int m, const double *G, const double *g, const double *w,
+                         const int *act, int sum1, double *p) {
+  double Gs[64 * 16], ps[16];
+  int na = 0, idx[16];
+  for (int t = 0; t < m; ++t)
+    if (act[t]) idx[na++] = t;
+  for (int k = 0; k < r; ++k)
+    for (int a = 0; a < na; ++a) Gs[k * na + a] = G[k * m + idx[a]];
+  if (sum1)
+    orc_ls_row_sum1(r, na, Gs, g, w, ps);
+  else
+    orc_ls_row(r, na, Gs, g, w, ps);
+  for (int t = 0; t < m; ++t) p[t] = 0.0;
+  for (int a = 0; a < na; ++a) p[idx[a]] = ps[a];
+  double f = 0.0;
+  for (int k = sum1 ? 1 : 0; k < r; ++k) {
+    double e = g[k];
+    for (int t = 0; t < m; ++t) e -= p[t] * G[k * m + t];
+    f += w[k] * e * e;
+  }
+  return f;
+}
+
+/* Interpolation weights of one F point. rule 0: plain LS over all of J_i
+ * (eq. ls_interpolation). rule 1 (R-ACT): active set -- while a weight is
+ * negative, the point with the most negative weight leaves J_i and the fit
+ * is redone; at least one point always stays. Removed points keep their
+ * structural entry with weight 0. */
+static void fit_point(int rule, int r, int m, const double *G, const double *g, const double *w,
+                      int sum1, double *p) {
+  int act[16];
+  for (int t = 0; t < m; ++t) act[t] = 1;
+  int na = m;
+  for (;;) {
+    fit_subset(r, m, G, g, w, act, sum1, p);
+    if (rule == 0 || na == 1) return;
+    int worst = -1;
+    for (int t = 0; t < m; ++t)
+      if (act[t] && p[t] < 0.0 && (worst < 0 || p[t] < p[worst])) worst = t;
+    if (worst < 0) return;
+    act[worst] = 0;
+    na--;
+  }
+}
+
+/* LS fits of all P rows and Q columns of level l (eq. ls_interpolation,
+ * eq. ls_weights, Section 5 constraint). */
+static void fit_transfer(orc_ctx *c, level *L) {
+  int n = L->n, r = c->o.r;
+  double *wv = NEW(double, r), *wu = NEW(double, r);
+  double *x = NEW(double, n), *t = NEW(double, n);
+  double minv = INFINITY, minu = INFINITY;
+  for (int k = 0; k < r; ++k) {
+    for (int i = 0; i < n; ++i) x[i] = L->V[(size_t)i * r + k];
+    csr_spmv(&L->B, x, t);
+    wv[k] = fmax(dot(n, t, t), 2.2250738585072014e-308);
+    minv = fmin(minv, wv[k]);
+    if (k == 0) continue;
+    for (int i = 0; i < n; ++i) x[i] = L->U[(size_t)i * r + k];
+    csr_spmv(&L->Bt, x, t);
+    wu[k] = fmax(dot(n, t, t), 2.2250738585072014e-308);
+    minu = fmin(minu, wu[k]);
+  }
+  /* R-W: omega_k = 1/||Bv_k||^2 scaled by its maximum */
+  for (int k = 0; k < r; ++k) {
+    wv[k] = minv / wv[k];
+    wu[k] = k > 0 ? minu / wu[k] : 0.0;
+  }
+  double G[64 * 16], g[64], p[16];
+  for (int i = 0; i < n; ++i) {
+    if (L->cf[i]) {
+      L->P.v[L->P.rp[i]] = 1.0;
+      L->Qt.v[L->Qt.rp[i]] = 1.0;
+      continue;
+    }
+    int a = L->P.rp[i], m = L->P.rp[i + 1] - a;
+    for (int k = 0; k < r; ++k) {
+      for (int tt = 0; tt < m; ++tt) G[k * m + tt] = L->V[(size_t)L->cpts[L->P.ci[a + tt]] * r + k];
+      g[k] = L->V[(size_t)i * r + k];
+    }
+    fit_point(c->o.interp_rule, r, m, G, g, wv, 0, p);
+    for (int tt = 0; tt < m; ++tt) L->P.v[a + tt] = p[tt];
+    for (int k = 0; k < r; ++k) {
+      for (int tt = 0; tt < m; ++tt) G[k * m + tt] = L->U[(size_t)L->cpts[L->P.ci[a + tt]] * r + k];
+      g[k] = L->U[(size_t)i * r + k];
+    }
+    fit_point(c->o.interp_rule, r, m, G, g, wu, 1, p);
+    for (int tt = 0; tt < m; ++tt) L->Qt.v[a + tt] = p[tt];
+  }
+  free(wv);
+  free(wu);
+  free(x);
+  free(t);
+}
+
+static double *dense_of(const csr *A) {
+  double *D = NEW(double, (size_t)A->nr * A->nc);
+  for (int i = 0; i < A->nr; ++i)
+    for (int k = A->rp[i]; k < A->rp[i + 1]; ++k) D[(size_t)i * A->nc + A->ci[k]] += A->v[k];
+  return D;
+}
+
+/* Coarsest level of Algorithm 1: the r smallest generalized singular
+ * triplets. U column 0 is the constant vector (Section 5); each pair's sign
+ * is fixed so that sum_i v_i >= 0 (signs do not change the LS fits). */
+static int coarsest_triplets(orc_ctx *c, level *L) {
+  int n = L->n, r = c->o.r;
+  if (r > n) return ORC_E_COARSE;
+  double *B = dense_of(&L->B), *M = dense_of(&L->M), *N = dense_of(&L->N);
+  double *s = NEW(double, n), *U = NEW(double, (size_t)n * n), *V = NEW(double, (size_t)n * n);
+  int st = orc_gsvd(n, B, M, N, s, U, V);
+  if (st == ORC_OK) {
+    for (int k = 0; k < r; ++k) {
+      double sv = 0.0;
+      for (int i = 0; i < n; ++i) sv += V[(size_t)k * n + i];
+      double sg = sv < 0 ? -1.0 : 1.0;
+      c->sigma[k] = s[k];
+      for (int i = 0; i < n; ++i) {
+        L->V[(size_t)i * r + k] = sg * V[(size_t)k * n + i];
+        L->U[(size_t)i * r + k] = k == 0 ? 1.0 : sg * U[(size_t)k * n + i];
+      }
+    }
+  }
+  free(B);
+  free(M);
+  free(N);
+  free(s);
+  free(U);
+  free(V);
+  return st;
+}
+
+/* bamg_mle (Algorithm 1) with R-MU, R-KV, R-NSET, R-NORM. */
+static int mle(orc_ctx *c, int l, int cycle) {
+  level *L = &c->lv[l];
+  int r = c->o.r;
+  if (l == c->L - 1) return coarsest_triplets(c, L);
+  relax_pairs(c, L, cycle > 1);
+  normalize_pairs(c, L);
+  fit_transfer(c, L);
+  galerkin(c, l);
+  level *C = &c->lv[l + 1];
+  for (int a = 0; a < C->n; ++a)
+    for (int k = 0; k < r; ++k) {
+      C->U[(size_t)a * r + k] = L->U[(size_t)L->cpts[a] * r + k];
+      C->V[(size_t)a * r + k] = L->V[(size_t)L->cpts[a] * r + k];
+    }
+  int st = mle(c, l + 1, cycle);
+  if (st != ORC_OK) return st;
+  csr_spmm(&L->Qt, r, C->U, L->U);
+  csr_spmm(&L->P, r, C->V, L->V);
+  for (int i = 0; i < L->n; ++i) L->U[(size_t)i * r] = 1.0;
+  relax_pairs(c, L, 1);
+  return ORC_OK;
+}
+
+/* Strong connectivity: every state reachable from state 0 along edges of A
+ * and of A^T (Section 2). */
+static int strongly_connected(const csr *A, const csr *At) {
+  int n = A->nr;
+  int32_t *seen = NEW(int32_t, n), *stack = NEW(int32_t, n);
+  int ok = 1;
+  for (int pass = 0; pass < 2 && ok; ++pass) {
+    const csr *G = pass ? At : A;
+    memset(seen, 0, sizeof(int32_t) * n);
+    int sp = 0, cnt = 1;
+    stack[sp++] = 0;
+    seen[0] = 1;
+    while (sp) {
+      int v = stack[--sp];
+      for (int k = G->rp[v]; k < G->rp[v + 1]; ++k) {
+        int w = G->ci[k];
+        if (!seen[w]) {
+          seen[w] = 1;
+          cnt++;
+          stack[sp++] = w;
+        }
+      }
+    }
+    ok = cnt == n;
+  }
+  free(seen);
+  free(stack);
+  return ok;
+}
+
+static void colour_level(level *L) {
+  csr Bt = L->Bt; /* columns of B = rows of B^T */
+  L->colB = NEW(int32_t, L->n);
+  L->colBt = NEW(int32_t, L->n);
+  orc_row_colouring(L->n, L->B.rp, L->B.ci, Bt.rp, Bt.ci, L->colB);
+  orc_row_colouring(L->n, Bt.rp, Bt.ci, L->B.rp, L->B.ci, L->colBt);
+  L->ncolB = L->ncolBt = 0;
+  for (int i = 0; i < L->n; ++i) {
+    if (L->colB[i] + 1 > L->ncolB) L->ncolB = L->colB[i] + 1;
+    if (L->colBt[i] + 1 > L->ncolBt) L->ncolBt = L->colBt[i] + 1;
+  }
+}
+
+int orc_setup(int64_t n64, const int32_t *rp, const int32_t *ci, const double *a,
+              const orc_options *opt, orc_ctx **out) {
+  if (!out || !rp || !ci || !a || !opt || n64 < 2 || n64 > 0x7fffffff) return ORC_E_ARG;
+  if (opt->r < 2 || opt->r > 64 || opt->max_interp < 1 || opt->max_interp > 16) return ORC_E_ARG;
+  int n = (int)n64;
+  /* O1: validate (Section 2) and form B = I - A with the diagonal stored */
+  csr A = csr_new(n, n, rp[n]);
+  memcpy(A.rp, rp, sizeof(int32_t) * (n + 1));
+  memcpy(A.ci, ci, sizeof(int32_t) * rp[n]);
+  memcpy(A.v, a, sizeof(double) * rp[n]);
+  for (int i = 0; i < n; ++i)
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      if (ci[k] < 0 || ci[k] >= n || (k > rp[i] && ci[k] <= ci[k - 1])) {
+        csr_free(&A);
+        return ORC_E_ARG;
+      }
+    }
+  double *colsum = NEW(double, n);
+  int bad = 0;
+  for (int k = 0; k < A.nnz; ++k) {
+    if (!(A.v[k] >= 0.0)) bad = 1;
+    colsum[A.ci[k]] += A.v[k];
+  }
+  for (int j = 0; j < n; ++j)
+    if (!(fabs(colsum[j] - 1.0) <= 1e-12)) bad = 1;
+  free(colsum);
+  if (bad) {
+    csr_free(&A);
+    return ORC_E_NOT_STOCHASTIC;
+  }
+  csr At = csr_transpose(&A);
+  int conn = strongly_connected(&A, &At);
+  csr_free(&At);
+  if (!conn) {
+    csr_free(&A);
+    return ORC_E_REDUCIBLE;
+  }
+  csr I = csr_identity(n);
+  /* B = I - A: structural union of I and A */
+  csr B = csr_new(n, n, 0);
+  {
+    int32_t *brp = NEW(int32_t, n + 1);
+    int cnt = 0;
+    for (int i = 0; i < n; ++i) {
+      int hasd = 0;
+      for (int k = rp[i]; k < rp[i + 1]; ++k) hasd |= (ci[k] == i);
+      cnt += rp[i + 1] - rp[i] + !hasd;
+      brp[i + 1] = cnt;
+    }
+    csr_free(&B);
+    B = csr_new(n, n, cnt);
+    memcpy(B.rp, brp, sizeof(int32_t) * (n + 1));
+    free(brp);
+    for (int i = 0; i < n; ++i) {
+      int p = B.rp[i], placed = 0;
+      for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        if (!placed && ci[k] > i) {
+          B.ci[p] = i;
+          B.v[p++] = 1.0;
+          placed = 1;
+        }
+        B.ci[p] = ci[k];
+        B.v[p++] = (ci[k] == i ? 1.0 : 0.0) - a[k];
+        if (ci[k] == i) placed = 1;
+      }
+      if (!placed) {
+        B.ci[p] = i;
+        B.v[p++] = 1.0;
+      }
+    }
+  }
+  csr_free(&A);
+  csr_free(&I);
+
+  orc_ctx *c = NEW(orc_ctx, 1);
+  c->o = *opt;
+  int r = opt->r;
+  c->sigma = NEW(double, r);
+  level *L0 = &c->lv[0];
+  L0->n = n;
+  L0->gkind = opt->coarsening == ORC_COARSEN_GEOM ? opt->geom_kind : 0;
+  L0->nx = opt->nx;
+  L0->ny = opt->ny;
+  if (L0->gkind == 2 && (int64_t)opt->nx * opt->ny != n) {
+    csr_free(&B);
+    orc_destroy(c);
+    return ORC_E_ARG;
+  }
+  set_operator(L0, B);
+  for (int i = 0; i < n; ++i)
+    if (!(L0->d[i] > 0.0)) {
+      orc_destroy(c);
+      return ORC_E_BAD_DIAG;
+    }
+  L0->M = csr_identity(n);
+  L0->N = csr_identity(n);
+
+  /* O2: structure of the whole hierarchy (integer; patterns only). The
+   * transfer values are placeholders here and are fitted in the cycles. */
+  int l = 0;
+  for (;;) {
+    level *L = &c->lv[l];
+    L->U = NEW(double, (size_t)L->n * r);
+    L->V = NEW(double, (size_t)L->n * r);
+    if (opt->smoother == ORC_SMOOTH_KACZMARZ) colour_level(L);
+    if (L->n <= opt->coarse_max || l == opt->max_levels - 1 || l == 31) break;
+    L->G = sym_graph(&L->B, &L->Bt);
+    coarsen(c, l);
+    if (L->nc == 0 || L->nc >= L->n) break;
+    build_P_pattern(c, l);
+    level *C = &c->lv[l + 1];
+    C->n = L->nc;
+    C->gkind = L->gkind;
+    C->nx = (L->nx + 1) / 2;
+    C->ny = L->gkind == 2 ? (L->ny + 1) / 2 : 1;
+    for (int i = 0; i < L->n; ++i)
+      if (!L->cf[i]) {
+        int a0 = L->P.rp[i], m = L->P.rp[i + 1] - a0;
+        for (int t = 0; t < m; ++t) L->P.v[a0 + t] = L->Qt.v[a0 + t] = 1.0 / m;
+      }
+    galerkin(c, l);
+    ++l;
+  }
+  c->L = l + 1;
+
+  /* O3: random test vectors (Section 4.2), U column 0 = constant vector */
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < r; ++k) {
+      L0->V[(size_t)i * r + k] = orc_uniform_pm1(opt->seed, 0, k, i);
+      L0->U[(size_t)i * r + k] = k == 0 ? 1.0 : orc_uniform_pm1(opt->seed, 1, k, i);
+    }
+
+  /* O4: setup cycles */
+  int st = ORC_OK;
+  for (int cyc = 1; cyc <= opt->setup_cycles && st == ORC_OK; ++cyc) st = mle(c, 0, cyc);
+  if (st == ORC_OK)
+    for (int q = 1; q < c->L; ++q)
+      for (int i = 0; i < c->lv[q].n; ++i)
+        if (!(fabs(c->lv[q].d[i]) > 0.0) || !isfinite(c->lv[q].d[i])) st = ORC_E_BAD_DIAG;
+  if (st != ORC_OK) {
+    orc_destroy(c);
+    return st;
+  }
+
+  /* O5: coarsest pseudo-inverse (R-PINV) and x0 (R-X0) */
+  level *LL = &c->lv[c->L - 1];
+  int nL = LL->n;
+  double *BL = dense_of(&LL->B);
+  double *s = NEW(double, nL), *U = NEW(double, (size_t)nL * nL), *V = NEW(double, (size_t)nL * nL);
+  st = orc_svd_jacobi(nL, BL, s, U, V);
+  int kmin = 0;
+  double smax = 0.0;
+  for (int k = 0; k < nL; ++k) {
+    if (s[k] < s[kmin]) kmin = k;
+    smax = fmax(smax, s[k]);
+  }
+  double s2 = INFINITY;
+  for (int k = 0; k < nL; ++k)
+    if (k != kmin) s2 = fmin(s2, s[k]);
+  if (!(s[kmin] <= 1e-10 * smax) || !(s2 > 1e-13 * smax)) st = ORC_E_COARSE;
+  c->bdag = NEW(double, (size_t)nL * nL);
+  for (int k = 0; k < nL; ++k) {
+    if (k == kmin) continue;
+    for (int i = 0; i < nL; ++i) {
+      double vi = V[(size_t)k * nL + i] / s[k];
+      for (int j = 0; j < nL; ++j) c->bdag[(size_t)i * nL + j] += vi * U[(size_t)k * nL + j];
+    }
+  }
+  free(BL);
+  free(s);
+  free(U);
+  free(V);
+  int kx = 0;
+  for (int k = 1; k < r; ++k)
+    if (c->sigma[k] < c->sigma[kx]) kx = k;
+  c->x0 = NEW(double, n);
+  double sx = 0.0;
+  for (int i = 0; i < n; ++i) sx += L0->V[(size_t)i * r + kx];
+  for (int i = 0; i < n; ++i) c->x0[i] = L0->V[(size_t)i * r + kx] / sx;
+  if (st != ORC_OK) {
+    orc_destroy(c);
+    return st;
+  }
+  *out = c;
+  return ORC_OK;
+}
+
+void orc_destroy(orc_ctx *c) {
+  if (!c) return;
+  for (int l = 0; l < 32; ++l) level_free(&c->lv[l]);
+  free(c->sigma);
+  free(c->bdag);
+  free(c->x0);
+  free(c);
+}
+
+int orc_num_levels(const orc_ctx *c) { return c->L; }
+
+int orc_level_dims(const orc_ctx *c, int l, int64_t d[6]) {
+  if (l < 0 || l >= c->L) return ORC_E_ARG;
+  const level *L = &c->lv[l];
+  d[0] = L->n;
+  d[1] = l < c->L - 1 ? L->nc : 0;
+  d[2] = L->B.nnz;
+  d[3] = L->M.nnz;
+  d[4] = l < c->L - 1 ? L->P.nnz : 0;
+  d[5] = d[4];
+  return ORC_OK;
+}
+
+int orc_level_csr(const orc_ctx *c, int l, int what, int32_t *rp, int32_t *ci, double *v) {
+  if (l < 0 || l >= c->L) return ORC_E_ARG;
+  const level *L = &c->lv[l];
+  const csr *A;
+  switch (what) {
+    case 0: A = &L->B; break;
+    case 1: A = &L->Bt; break;
+    case 2: A = &L->M; break;
+    case 3: A = &L->N; break;
+    case 4: A = &L->P; break;
+    case 5: A = &L->Q; break;
+    case 6: A = &L->Qt; break;
+    default: return ORC_E_ARG;
+  }
+  if (what >= 4 && l == c->L - 1) return ORC_E_ARG;
+  if (rp) memcpy(rp, A->rp, sizeof(int32_t) * (A->nr + 1));
+  if (ci) memcpy(ci, A->ci, sizeof(int32_t) * A->nnz);
+  if (v) memcpy(v, A->v, sizeof(double) * A->nnz);
+  return ORC_OK;
+}
+
+int orc_level_cf(const orc_ctx *c, int l, int32_t *cf, int32_t *cidx) {
+  if (l < 0 || l >= c->L - 1) return ORC_E_ARG;
+  const level *L = &c->lv[l];
+  if (cf) memcpy(cf, L->cf, sizeof(int32_t) * L->n);
+  if (cidx) memcpy(cidx, L->cidx, sizeof(int32_t) * L->n);
+  return ORC_OK;
+}
+
+int orc_level_vectors(const orc_ctx *c, int l, double *U, double *V) {
+  if (l < 0 || l >= c->L) return ORC_E_ARG;
+  const level *L = &c->lv[l];
+  size_t sz = sizeof(double) * (size_t)L->n * c->o.r;
+  if (U) memcpy(U, L->U, sz);
+  if (V) memcpy(V, L->V, sz);
+  return ORC_OK;
+}
+
+int orc_sigma(const orc_ctx *c, double *sigma) {
+  memcpy(sigma, c->sigma, sizeof(double) * c->o.r);
+  return ORC_OK;
+}
+
+int orc_x0(const orc_ctx *c, double *x0) {
+  memcpy(x0, c->x0, sizeof(double) * c->lv[0].n);
+  return ORC_OK;
+}
+
+int orc_coarse_pinv(const orc_ctx *c, double *bdag) {
+  int nL = c->lv[c->L - 1].n;
+  memcpy(bdag, c->bdag, sizeof(double) * (size_t)nL * nL);
+  return ORC_OK;
+}
+
+int orc_complexity(const orc_ctx *c, double *oc, double *og) {
+  double sb = 0, sn = 0;
+  for (int l = 0; l < c->L; ++l) {
+    sb += c->lv[l].B.nnz;
+    sn += c->lv[l].n;
+  }
+  *oc = sb / c->lv[0].B.nnz;
+  *og = sn / c->lv[0].n;
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------ V-cycle */
+/* Section 3 and Section 6: nu_pre smoothing steps from x = 0, residual,
+ * restriction by Q, recursive coarse correction (pseudo-inverse on the
+ * coarsest level, eq. coarse_grid_correction), interpolation by P,
+ * nu_post smoothing steps. */
+static void vcycle_rec(const orc_ctx *c, int l, const double *b, double *x) {
+  const level *L = &c->lv[l];
+  int n = L->n;
+  if (l == c->L - 1) {
+    for (int i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < n; ++j) s += c->bdag[(size_t)i * n + j] * b[j];
+      x[i] = s;
+    }
+    return;
+  }
+  memset(x, 0, sizeof(double) * n);
+  for (int s = 0; s < c->o.nu_pre; ++s) smooth_vec(c, L, 0, b, x);
+  double *res = NEW(double, n);
+  csr_spmv(&L->B, x, res);
+  for (int i = 0; i < n; ++i) res[i] = b[i] - res[i];
+  int nc = L->nc;
+  double *bc = NEW(double, nc), *xc = NEW(double, nc);
+  csr_spmv(&L->Q, res, bc);
+  vcycle_rec(c, l + 1, bc, xc);
+  double *corr = NEW(double, n);
+  csr_spmv(&L->P, xc, corr);
+  for (int i = 0; i < n; ++i) x[i] += corr[i];
+  for (int s = 0; s < c->o.nu_post; ++s) smooth_vec(c, L, 0, b, x);
+  free(res);
+  free(bc);
+  free(xc);
+  free(corr);
+}
+
+int orc_vcycle(const orc_ctx *c, const double *b, double *x) {
+  vcycle_rec(c, 0, b, x);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------- GMRES */
+static double scaled_residual(const csr *B, const double *x, double *tmp) {
+  int n = B->nr;
+  csr_spmv(B, x, tmp);
+  double nb = sqrt(dot(n, tmp, tmp)), nx = sqrt(dot(n, x, x));
+  return nx > 0 ? nb / nx : INFINITY;
+}
+
+/* GMRES(m) on the residual equation B e = -B x0 with left preconditioner
+ * C = one V-cycle (eq. residual, eq. prec_residual read as C B e =
+ * -C B x0). R-GM. The iterate x = x0 + e is formed after every step and the
+ * scaled residual ||Bx||/||x|| decides convergence (Section 7). */
+int orc_gmres(const orc_ctx *c, double *x, int32_t m, double tol, int32_t maxit, int32_t use_x0,
+              int32_t precondition, orc_info *info) {
+  const level *L0 = &c->lv[0];
+  int n = L0->n;
+  if (m < 1 || m > 200) return ORC_E_ARG;
+  if (!use_x0) memcpy(x, c->x0, sizeof(double) * n);
+  double *Vk = NEW(double, (size_t)n * (m + 1));
+  double *H = NEW(double, (size_t)(m + 1) * m);
+  double *cs = NEW(double, m), *sn = NEW(double, m), *g = NEW(double, m + 1), *y = NEW(double, m);
+  double *w = NEW(double, n), *t = NEW(double, n), *xt = NEW(double, n);
+  int it = 0, restarts = 0, conv = 0, breakdowns = 0, st = ORC_OK;
+  double rel = scaled_residual(&L0->B, x, t);
+  if (rel < tol) conv = 1;
+  while (!conv && it < maxit) {
+    /* r0 = -B x0, z = C r0 */
+    csr_spmv(&L0->B, x, t);
+    for (int i = 0; i < n; ++i) t[i] = -t[i];
+    if (precondition)
+      vcycle_rec(c, 0, t, w);
+    else
+      memcpy(w, t, sizeof(double) * n);
+    double beta = sqrt(dot(n, w, w));
+    if (beta == 0.0) break;
+    for (int i = 0; i < n; ++i) Vk[i] = w[i] / beta;
+    memset(g, 0, sizeof(double) * (m + 1));
+    g[0] = beta;
+    int j, used = 0, broke = 0;
+    for (j = 0; j < m && it < maxit; ++j) {
+      double *vj = Vk + (size_t)j * n;
+      csr_spmv(&L0->B, vj, t);
+      if (precondition)
+        vcycle_rec(c, 0, t, w);
+      else
+        memcpy(w, t, sizeof(double) * n);
+      double wnorm0 = sqrt(dot(n, w, w));
+      for (int i = 0; i <= j; ++i) {
+        double *vi = Vk + (size_t)i * n;
+        double h = dot(n, w, vi);
+        H[i * m + j] = h;
+        for (int q = 0; q < n; ++q) w[q] -= h * vi[q];
+      }
+      double hn = sqrt(dot(n, w, w));
+      H[(j + 1) * m + j] = hn;
+      if (hn > 1e-14 * wnorm0)
+        for (int q = 0; q < n; ++q) Vk[(size_t)(j + 1) * n + q] = w[q] / hn;
+      else
+        broke = 1;
+      /* Givens rotations */
+      for (int i = 0; i < j; ++i) {
+        double a = H[i * m + j], b = H[(i + 1) * m + j];
+        H[i * m + j] = cs[i] * a + sn[i] * b;
+        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+      }
+      double a = H[j * m + j], b = H[(j + 1) * m + j];
+      double den = sqrt(a * a + b * b);
+      cs[j] = den > 0 ? a / den : 1.0;
+      sn[j] = den > 0 ? b / den : 0.0;
+      H[j * m + j] = den;
+      H[(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++it;
+      used = j + 1;
+      /* y = R^-1 g, x = x0 + V y, true scaled residual */
+      for (int i = used - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int q = i + 1; q < used; ++q) s -= H[i * m + q] * y[q];
+        y[i] = s / H[i * m + i];
+      }
+      memcpy(xt, x, sizeof(double) * n);
+      for (int i = 0; i < used; ++i)
+        for (int q = 0; q < n; ++q) xt[q] += y[i] * Vk[(size_t)i * n + q];
+      rel = scaled_residual(&L0->B, xt, t);
+      if (rel < tol) {
+        conv = 1;
+        break;
+      }
+      if (broke) break;
+    }
+    if (used > 0) memcpy(x, xt, sizeof(double) * n);
+    if (broke && !conv) {
+      if (++breakdowns >= 2) {
+        st = ORC_E_BREAKDOWN;
+        break;
+      }
+    }
+    if (!conv) ++restarts;
+  }
+  /* O8: scale to 1^T x = 1 */
+  double sx = 0.0, xmin = INFINITY;
+  for (int i = 0; i < n; ++i) sx += x[i];
+  for (int i = 0; i < n; ++i) {
+    x[i] /= sx;
+    xmin = fmin(xmin, x[i]);
+  }
+  if (info) {
+    info->iterations = it;
+    info->restarts = restarts;
+    info->converged = conv;
+    info->rel_residual = rel;
+    info->x_min = xmin;
+  }
+  free(Vk);
+  free(H);
+  free(cs);
+  free(sn);
+  free(g);
+  free(y);
+  free(w);
+  free(t);
+  free(xt);
+  if (st != ORC_OK) return st;
+  return conv ? ORC_OK : ORC_NOT_CONVERGED;
+}
