@@ -1,0 +1,190 @@
+/*
+ * bamg.h -- C ABI of the MI355X (gfx950) implementation of bootstrap
+ * algebraic multigrid (BAMG) preconditioned GMRES for the stationary vector
+ * of an irreducible Markov chain.
+ *
+ * Method: Brannick, Kahl, Sokolovic, "An adaptively constructed algebraic
+ * multigrid preconditioner for irreducible Markov chains". Given the
+ * column-stochastic transition matrix A (a_ij = p_ji, Section 2), find
+ * x > 0 with A x = x, i.e. B x = 0 with B = I - A (eq. Bx0). A bootstrap
+ * setup (Algorithm 1, Sections 4 and 5) builds a multigrid hierarchy from
+ * relaxed left/right test vectors by least-squares fits of interpolation P
+ * and restriction Q and Petrov-Galerkin products Q B P; one V-cycle with a
+ * zero initial guess is then the preconditioner C of GMRES on the residual
+ * equation C B e = -C B x0 (Section 6), stopped when ||Bx||/||x|| < tol
+ * (Section 7).
+ *
+ * Conventions for every call:
+ *  - Return value: bamg_status. 0 = success; > 0 = warning, the outputs are
+ *    valid; < 0 = error, the outputs are unspecified and no handle passed in
+ *    is changed. No C++ exception crosses this boundary.
+ *  - Indices are 0-based int32, values FP64 unless stated.
+ *  - "device" pointers are HIP device memory on the current device; "host"
+ *    pointers are ordinary host memory. Input arrays are only read during
+ *    the call (they are copied); the library keeps no reference to them.
+ *  - hip_stream is a hipStream_t passed as void* (NULL = the null stream).
+ *    All device work of a call is enqueued on it; calls that fill host
+ *    outputs synchronise that stream before returning.
+ *  - A handle is not thread-safe: calls on one handle must not overlap.
+ *    Distinct handles are independent.
+ */
+#ifndef BAMG_H
+#define BAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bamg_status;
+enum {
+  BAMG_OK = 0,
+  BAMG_NOT_CONVERGED = 1,      /* iteration cap reached; best iterate returned */
+  BAMG_E_ARG = -1,             /* bad argument, size or option */
+  BAMG_E_NOT_STOCHASTIC = -2,  /* a_ij < 0 or a column sum differs from 1 by > 1e-12 */
+  BAMG_E_REDUCIBLE = -3,       /* the chain's graph is not strongly connected */
+  BAMG_E_BAD_DIAG = -4,        /* a zero or non-finite diagonal entry of some B_l */
+  BAMG_E_COARSE = -5,          /* coarsest operator not of rank n_L - 1, or SVD failed */
+  BAMG_E_BREAKDOWN = -6,       /* GMRES broke down twice without converging */
+  BAMG_E_NONFINITE = -7,       /* NaN or Inf met in an iterate */
+  BAMG_E_DEVICE = -8,          /* a HIP runtime call failed */
+  BAMG_E_NOMEM = -9            /* device allocation failed */
+};
+
+enum { BAMG_COARSEN_GEOMETRIC = 0, BAMG_COARSEN_MIS = 1 };
+enum { BAMG_SMOOTH_JACOBI = 0, BAMG_SMOOTH_KACZMARZ = 1 };
+enum { BAMG_PRECISION_FP64 = 0, BAMG_PRECISION_MIXED = 1 };
+enum { BAMG_DTYPE_F64 = 0, BAMG_DTYPE_F32 = 1 };
+enum { BAMG_GEOM_NONE = 0, BAMG_GEOM_LINE = 1, BAMG_GEOM_GRID2D = 2 };
+
+/* Transition matrix A in CSR by destination state: row i lists the states j
+ * with p_ji > 0 and holds a_ij = p_ji (Section 2). Columns strictly
+ * ascending within each row. on_device != 0: the three arrays are device
+ * pointers; otherwise host pointers. */
+typedef struct {
+  int64_t n, nnz;
+  const int32_t *row_ptr; /* n + 1 */
+  const int32_t *col_idx; /* nnz */
+  const double *val;      /* nnz */
+  int32_t on_device;
+} bamg_csr;
+
+/* Optional geometry: kind BAMG_GEOM_GRID2D with state index iy*nx + ix
+ * (nx*ny == n), or BAMG_GEOM_LINE with nx == n. Used by geometric
+ * coarsening, which takes every other point in each direction (Section 7). */
+typedef struct {
+  int32_t kind, nx, ny;
+} bamg_geometry;
+
+/* Options. bamg_default_options fills the paper's standard parameters
+ * (Section 7): r = 8 test vectors, 3 + 3 weighted-Jacobi sweeps with
+ * omega = 0.7, interpolation from at most c = 4 coarse points. */
+typedef struct {
+  int32_t r;            /* test vectors per side, 2..16 (Section 4.1) */
+  int32_t setup_cycles; /* 1 = BAMG, 2 = BAMG^2 (Section 7) */
+  int32_t nu_pre, nu_post; /* V-cycle smoothing steps (Section 3) */
+  int32_t nu_setup;     /* smoothing steps per level visit in the setup (Algorithm 1) */
+  double omega;         /* Jacobi damping: x <- x + omega D^-1 (b - B x) */
+  int32_t max_interp;   /* c: at most c interpolation points per F point, 1..8 */
+  int32_t max_levels;   /* cap on the number of levels, >= 2 */
+  int32_t coarse_max;   /* stop coarsening once n_l <= coarse_max (<= 2048) */
+  int32_t coarsening;   /* BAMG_COARSEN_GEOMETRIC (needs geometry) or BAMG_COARSEN_MIS */
+  uint64_t seed;        /* test vectors and MIS priorities (Philox-4x64-10) */
+  int32_t smoother;     /* BAMG_SMOOTH_JACOBI or BAMG_SMOOTH_KACZMARZ (Section 3) */
+  int32_t precision;    /* BAMG_PRECISION_FP64 or BAMG_PRECISION_MIXED */
+  int32_t interp_rule;  /* 0 = plain LS over J_i, 1 = LS with negative weights removed */
+  int32_t validate;     /* 1 = check stochasticity and strong connectivity */
+} bamg_options;
+
+/* Device allocator used for every library allocation (NULL = hipMalloc /
+ * hipFree). alloc returns NULL on failure. */
+typedef struct {
+  void *ctx;
+  void *(*alloc)(void *ctx, size_t bytes, void *hip_stream);
+  void (*free)(void *ctx, void *ptr, void *hip_stream);
+} bamg_allocator;
+
+typedef struct {
+  int32_t iterations;    /* preconditioned GMRES iterations after the setup (Section 7) */
+  int32_t restarts;
+  int32_t converged;
+  int32_t breakdowns;
+  double rel_residual;   /* final ||Bx||_2 / ||x||_2, FP64 */
+  double x_min;          /* min_i x_i after scaling to 1^T x = 1 */
+  double t_solve_ms;     /* host wall time of the call */
+} bamg_solve_info;
+
+typedef struct bamg_handle bamg_handle;
+
+/* Fill *out with the defaults above. */
+bamg_status bamg_default_options(bamg_options *out);
+
+/* Validate A, build B = I - A (eq. Bx0), the integer structure of the
+ * hierarchy (C/F splittings, interpolation sets J_i, Galerkin patterns),
+ * then run setup_cycles bootstrap cycles (Algorithm 1 with the constraint
+ * 1^T Q = 1^T of Section 5), the coarsest pseudo-inverse (eq.
+ * coarse_grid_correction) and the initial iterate x0 (Section 6).
+ * geom may be NULL. alloc may be NULL. On success *out owns all device
+ * memory of the hierarchy; free it with bamg_destroy. */
+bamg_status bamg_setup(const bamg_csr *A, const bamg_geometry *geom, const bamg_options *opt,
+                       const bamg_allocator *alloc, void *hip_stream, bamg_handle **out);
+
+/* One V-cycle with zero initial guess, x = C b (Section 6, eq.
+ * iterate_preconditioner). b and x are device arrays of n values of type
+ * dtype (BAMG_DTYPE_F64 or, for a mixed-precision handle, BAMG_DTYPE_F32);
+ * they must not overlap. Asynchronous on hip_stream. */
+bamg_status bamg_vcycle(bamg_handle *h, const void *b, void *x, int32_t dtype, void *hip_stream);
+
+/* GMRES(restart) on the preconditioned residual equation C B e = -C B x0
+ * (Section 6, eq. prec_residual), Arnoldi in FP64 with classical
+ * Gram-Schmidt applied twice, the true scaled residual ||Bx||/||x|| tested
+ * after every iteration (Section 7). x: device, n FP64; on entry the
+ * initial iterate if use_x0 != 0 (else the setup's x0 is used); on exit the
+ * iterate scaled to 1^T x = 1. info (host, may be NULL) is filled after a
+ * stream synchronisation. */
+bamg_status bamg_gmres_solve(bamg_handle *h, void *x, int32_t restart, double tol,
+                             int32_t max_iters, int32_t use_x0, bamg_solve_info *info,
+                             void *hip_stream);
+
+/* Hierarchy summary (host outputs, each may be NULL): number of levels,
+ * n_l and nnz(B_l) for l < *levels (arrays sized >= 32), operator and grid
+ * complexity (Section 4.1 eq. operator_complexity_def, Section 7). */
+bamg_status bamg_hierarchy_info(const bamg_handle *h, int32_t *levels, int64_t *n_l,
+                                int64_t *nnz_l, double *oc, double *og);
+
+/* Copy one level out to host buffers (for checking and checkpoints).
+ * what: 0 = B_l, 1 = B_l^T, 2 = M_l, 3 = N_l, 4 = P_l (n_l x n_{l+1}, fine
+ * rows), 5 = Q_l (n_{l+1} x n_l, coarse rows), 6 = Q_l^T (fine rows, the
+ * pattern of P_l). nnz is read from bamg_level_nnz. Values are FP64
+ * (converted for a mixed-precision handle). Any output may be NULL. */
+bamg_status bamg_level_nnz(const bamg_handle *h, int32_t l, int32_t what, int64_t *rows,
+                           int64_t *nnz);
+bamg_status bamg_level_csr(const bamg_handle *h, int32_t l, int32_t what, int32_t *row_ptr,
+                           int32_t *col_idx, double *val);
+/* C/F splitting of level l < levels-1: cf[i] = 1 for C points; cidx[i] the
+ * coarse index or -1. Host outputs of n_l int32 each, may be NULL. */
+bamg_status bamg_level_cf(const bamg_handle *h, int32_t l, int32_t *cf, int32_t *cidx);
+/* Test vectors of level l after the last setup cycle: U, V host n_l x r
+ * row-major FP64; sigma host r values. Any output may be NULL. */
+bamg_status bamg_level_vectors(const bamg_handle *h, int32_t l, double *U, double *V);
+bamg_status bamg_sigma(const bamg_handle *h, double *sigma);
+/* x0 of Section 6 (device n FP64 output), the coarsest pseudo-inverse
+ * (host n_L x n_L row-major FP64 output). */
+bamg_status bamg_x0(const bamg_handle *h, void *x_device, void *hip_stream);
+bamg_status bamg_coarse_pinv(const bamg_handle *h, double *bdag);
+
+/* Free every resource of h (NULL is ignored). */
+void bamg_destroy(bamg_handle *h);
+
+/* Static description of a status code. */
+const char *bamg_status_string(bamg_status s);
+
+/* Text of the last error on this thread (empty if none). */
+const char *bamg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,298 @@
+"""Python binding of the BAMG HIP library (``libbamg.so``, C ABI in
+``include/bamg.h``): bootstrap-AMG preconditioned GMRES for the stationary
+vector of an irreducible Markov chain on an MI355X.
+
+This module only marshals arguments: torch tensors provide device memory and
+the HIP stream; every step of the method runs in the library's kernels. It
+fails loudly when the library is not built or no GPU is present; there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbamg.so")
+
+OK = 0
+NOT_CONVERGED = 1
+COARSEN_GEOMETRIC, COARSEN_MIS = 0, 1
+SMOOTH_JACOBI, SMOOTH_KACZMARZ = 0, 1
+PRECISION_FP64, PRECISION_MIXED = 0, 1
+DTYPE_F64, DTYPE_F32 = 0, 1
+GEOM_NONE, GEOM_LINE, GEOM_GRID2D = 0, 1, 2
+WHAT = {"B": 0, "Bt": 1, "M": 2, "N": 3, "P": 4, "Q": 5, "Qt": 6}
+
+
+class BamgError(RuntimeError):
+    def __init__(self, code, msg=""):
+        super().__init__(f"bamg status {code}: {status_string(code)} {msg}".strip())
+        self.code = code
+
+
+class Csr(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("row_ptr", C.c_void_p),
+                ("col_idx", C.c_void_p), ("val", C.c_void_p), ("on_device", C.c_int32)]
+
+
+class Geometry(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32)]
+
+
+class Options(C.Structure):
+    _fields_ = [("r", C.c_int32), ("setup_cycles", C.c_int32), ("nu_pre", C.c_int32),
+                ("nu_post", C.c_int32), ("nu_setup", C.c_int32), ("omega", C.c_double),
+                ("max_interp", C.c_int32), ("max_levels", C.c_int32), ("coarse_max", C.c_int32),
+                ("coarsening", C.c_int32), ("seed", C.c_uint64), ("smoother", C.c_int32),
+                ("precision", C.c_int32), ("interp_rule", C.c_int32), ("validate", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
+                ("breakdowns", C.c_int32), ("rel_residual", C.c_double), ("x_min", C.c_double),
+                ("t_solve_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libbamg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        # torch's HIP runtime must be the one the library binds to (same
+        # SONAME): load it first so there is a single runtime in the process
+        import torch  # noqa: F401
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run paper_1402_4005_amd/build.py "
+                               "(or __graft_entry__.build()) first")
+        L = C.CDLL(LIB_PATH)
+        P, V = C.POINTER, C.c_void_p
+        L.bamg_default_options.argtypes = [P(Options)]
+        L.bamg_setup.argtypes = [P(Csr), P(Geometry), P(Options), V, V, P(V)]
+        L.bamg_vcycle.argtypes = [V, V, V, C.c_int32, V]
+        L.bamg_gmres_solve.argtypes = [V, V, C.c_int32, C.c_double, C.c_int32, C.c_int32,
+                                       P(SolveInfo), V]
+        L.bamg_hierarchy_info.argtypes = [V, V, V, V, V, V]
+        L.bamg_level_nnz.argtypes = [V, C.c_int32, C.c_int32, V, V]
+        L.bamg_level_csr.argtypes = [V, C.c_int32, C.c_int32, V, V, V]
+        L.bamg_level_cf.argtypes = [V, C.c_int32, V, V]
+        L.bamg_level_vectors.argtypes = [V, C.c_int32, V, V]
+        L.bamg_sigma.argtypes = [V, V]
+        L.bamg_x0.argtypes = [V, V, V]
+        L.bamg_coarse_pinv.argtypes = [V, V]
+        L.bamg_destroy.argtypes = [V]
+        L.bamg_destroy.restype = None
+        L.bamg_status_string.argtypes = [C.c_int32]
+        L.bamg_status_string.restype = C.c_char_p
+        L.bamg_last_error.argtypes = []
+        L.bamg_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def status_string(code) -> str:
+    try:
+        return lib().bamg_status_string(code).decode()
+    except Exception:
+        return "?"
+
+
+def _check(code):
+    if code < 0:
+        raise BamgError(code, lib().bamg_last_error().decode())
+    return code
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    _check(lib().bamg_default_options(C.byref(o)))
+    names = {
+        "coarsening": {"geom": COARSEN_GEOMETRIC, "geometric": COARSEN_GEOMETRIC, "mis": COARSEN_MIS},
+        "smoother": {"jacobi": SMOOTH_JACOBI, "kaczmarz": SMOOTH_KACZMARZ},
+        "precision": {"fp64": PRECISION_FP64, "mixed": PRECISION_MIXED},
+    }
+    for k, v in kw.items():
+        if k in names and isinstance(v, str):
+            v = names[k][v]
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the BAMG library runs only on the device")
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Hierarchy:
+    """A BAMG hierarchy set up on the GPU (wraps ``bamg_handle``).
+
+    ``A`` is the column-stochastic transition matrix in CSR by destination
+    state: ``indptr``/``indices``/``data`` as numpy arrays (host) or torch
+    CUDA tensors (device; int32, int32, float64).
+    """
+
+    def __init__(self, indptr, indices, data, geom=(0, 0, 0), opts: Options | None = None,
+                 stream=None):
+        torch = _torch()
+        self.opts = opts if opts is not None else default_options()
+        on_dev = isinstance(indptr, torch.Tensor)
+        if on_dev:
+            self._keep = (indptr.contiguous().to(torch.int32), indices.contiguous().to(torch.int32),
+                          data.contiguous().to(torch.float64))
+            ptrs = [t.data_ptr() for t in self._keep]
+            n = self._keep[0].numel() - 1
+            nnz = self._keep[1].numel()
+        else:
+            self._keep = (np.ascontiguousarray(indptr, np.int32),
+                          np.ascontiguousarray(indices, np.int32),
+                          np.ascontiguousarray(data, np.float64))
+            ptrs = [a.ctypes.data for a in self._keep]
+            n = len(self._keep[0]) - 1
+            nnz = len(self._keep[1])
+        self.n = n
+        A = Csr(n, nnz, ptrs[0], ptrs[1], ptrs[2], 1 if on_dev else 0)
+        g = Geometry(*geom)
+        h = C.c_void_p()
+        self._stream = _stream(stream)
+        _check(lib().bamg_setup(C.byref(A), C.byref(g), C.byref(self.opts), None, self._stream,
+                                C.byref(h)))
+        self.h = h
+        self.mixed = self.opts.precision == PRECISION_MIXED
+
+    @classmethod
+    def from_chain(cls, chain, opts: Options | None = None, on_device=False, stream=None):
+        if on_device:
+            torch = _torch()
+            return cls(torch.from_numpy(chain.indptr).cuda(), torch.from_numpy(chain.indices).cuda(),
+                       torch.from_numpy(chain.data).cuda(), chain.geom, opts, stream)
+        return cls(chain.indptr, chain.indices, chain.data, chain.geom, opts, stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().bamg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- solve
+    def vcycle(self, b, x=None, stream=None):
+        """x = C b (one V-cycle from zero); b a CUDA tensor of length n."""
+        torch = _torch()
+        dt = DTYPE_F32 if b.dtype == torch.float32 else DTYPE_F64
+        b = b.contiguous()
+        if x is None:
+            x = torch.empty_like(b)
+        _check(lib().bamg_vcycle(self.h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), dt,
+                                 _stream(stream)))
+        return x
+
+    def gmres(self, x=None, restart=20, tol=1e-10, maxit=500, stream=None):
+        """GMRES(restart) on the preconditioned residual equation; returns
+        (x scaled to sum 1, SolveInfo). x: optional CUDA float64 initial iterate."""
+        torch = _torch()
+        use_x0 = x is not None
+        if x is None:
+            x = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        info = SolveInfo()
+        st = lib().bamg_gmres_solve(self.h, C.c_void_p(x.data_ptr()), restart, tol, maxit,
+                                    1 if use_x0 else 0, C.byref(info), _stream(stream))
+        _check(st)
+        return x, info
+
+    # ------------------------------------------------------------ inspection
+    def info(self):
+        lv = C.c_int32()
+        nl = np.zeros(32, np.int64)
+        nz = np.zeros(32, np.int64)
+        oc, og = C.c_double(), C.c_double()
+        _check(lib().bamg_hierarchy_info(self.h, C.byref(lv), nl.ctypes.data, nz.ctypes.data,
+                                         C.byref(oc), C.byref(og)))
+        L = lv.value
+        return {"levels": L, "n": nl[:L].tolist(), "nnz": nz[:L].tolist(), "oc": oc.value,
+                "og": og.value}
+
+    @property
+    def levels(self):
+        return self.info()["levels"]
+
+    def csr(self, l, what):
+        code = WHAT[what]
+        rows, nnz = C.c_int64(), C.c_int64()
+        _check(lib().bamg_level_nnz(self.h, l, code, C.byref(rows), C.byref(nnz)))
+        rp = np.zeros(rows.value + 1, np.int32)
+        ci = np.zeros(nnz.value, np.int32)
+        v = np.zeros(nnz.value, np.float64)
+        _check(lib().bamg_level_csr(self.h, l, code, rp.ctypes.data, ci.ctypes.data, v.ctypes.data))
+        return rp, ci, v
+
+    def scipy(self, l, what):
+        import scipy.sparse as sp
+        rp, ci, v = self.csr(l, what)
+        info = self.info()
+        n = info["n"][l]
+        nc = info["n"][l + 1] if l + 1 < info["levels"] else n
+        shape = {"P": (n, nc), "Qt": (n, nc), "Q": (nc, n)}.get(what, (n, n))
+        return sp.csr_matrix((v, ci, rp), shape=shape)
+
+    def cf(self, l):
+        n = self.info()["n"][l]
+        cf = np.zeros(n, np.int32)
+        cidx = np.zeros(n, np.int32)
+        _check(lib().bamg_level_cf(self.h, l, cf.ctypes.data, cidx.ctypes.data))
+        return cf, cidx
+
+    def vectors(self, l):
+        n = self.info()["n"][l]
+        r = self.opts.r
+        U = np.zeros((n, r))
+        V = np.zeros((n, r))
+        _check(lib().bamg_level_vectors(self.h, l, U.ctypes.data, V.ctypes.data))
+        return U, V
+
+    def sigma(self):
+        s = np.zeros(self.opts.r)
+        _check(lib().bamg_sigma(self.h, s.ctypes.data))
+        return s
+
+    def x0(self):
+        torch = _torch()
+        x = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        _check(lib().bamg_x0(self.h, C.c_void_p(x.data_ptr()), _stream(None)))
+        return x
+
+    def coarse_pinv(self):
+        info = self.info()
+        nL = info["n"][-1]
+        B = np.zeros((nL, nL))
+        _check(lib().bamg_coarse_pinv(self.h, B.ctypes.data))
+        return B
+
+
+def options_for(chain, **kw) -> Options:
+    """Options with the chain's geometry: geometric coarsening on a grid or a
+    line, greedy MIS coarsening otherwise."""
+    kind = chain.geom[0]
+    base = {"coarsening": COARSEN_GEOMETRIC if kind else COARSEN_MIS}
+    base.update(kw)
+    return default_options(**base)

@@ -1,0 +1,362 @@
+// C ABI of the library (include/bamg.h): argument checks, error translation
+// (no exception crosses the boundary), device memory ownership.
+#include <cstring>
+#include <string>
+
+#include "bamg_internal.h"
+
+namespace bamg {
+
+static thread_local std::string g_last_error;
+
+void fail(bamg_status code, const std::string &msg) { throw Error{code, msg}; }
+
+void check_hip(hipError_t e, const char *what, const char *file, int line) {
+  if (e == hipSuccess) return;
+  const bamg_status code = (e == hipErrorOutOfMemory) ? BAMG_E_NOMEM : BAMG_E_DEVICE;
+  throw Error{code, std::string(what) + ": " + hipGetErrorString(e) + " at " + file + ":" +
+                        std::to_string(line)};
+}
+
+void *Pool::raw(size_t bytes) {
+  void *p = nullptr;
+  if (custom) {
+    p = a.alloc(a.ctx, bytes, (void *)s);
+    if (!p) throw Error{BAMG_E_NOMEM, "caller allocator returned NULL"};
+  } else {
+    const hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error{BAMG_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)};
+    }
+  }
+  live.push_back(p);
+  return p;
+}
+
+void Pool::release(void *p) { deferred.push_back(p); }
+
+static void free_one(Pool &pool, void *p) {
+  if (pool.custom)
+    pool.a.free(pool.a.ctx, p, (void *)pool.s);
+  else
+    (void)hipFree(p);
+}
+
+void Pool::flush() {
+  if (deferred.empty()) return;
+  (void)hipStreamSynchronize(s);
+  for (void *p : deferred) {
+    for (size_t i = 0; i < live.size(); ++i)
+      if (live[i] == p) {
+        live[i] = live.back();
+        live.pop_back();
+        break;
+      }
+    free_one(*this, p);
+  }
+  deferred.clear();
+}
+
+void Pool::release_all() {
+  (void)hipStreamSynchronize(s);
+  for (void *p : live) free_one(*this, p);
+  live.clear();
+  deferred.clear();
+}
+
+static bamg_status translate(const Error &e) {
+  g_last_error = e.msg;
+  return e.code;
+}
+
+}  // namespace bamg
+
+using namespace bamg;
+
+#define BAMG_TRY try {
+#define BAMG_CATCH                                                                          \
+  }                                                                                         \
+  catch (const Error &e) {                                                                  \
+    return translate(e);                                                                    \
+  }                                                                                         \
+  catch (const std::bad_alloc &) {                                                          \
+    g_last_error = "host allocation failed";                                                \
+    return BAMG_E_NOMEM;                                                                    \
+  }                                                                                         \
+  catch (...) {                                                                             \
+    g_last_error = "unexpected exception";                                                  \
+    return BAMG_E_DEVICE;                                                                   \
+  }
+
+extern "C" {
+
+bamg_status bamg_default_options(bamg_options *o) {
+  if (!o) return BAMG_E_ARG;
+  std::memset(o, 0, sizeof(*o));
+  o->r = 8;
+  o->setup_cycles = 1;
+  o->nu_pre = 3;
+  o->nu_post = 3;
+  o->nu_setup = 3;
+  o->omega = 0.7;
+  o->max_interp = 4;
+  o->max_levels = 16;
+  o->coarse_max = 289;
+  o->coarsening = BAMG_COARSEN_GEOMETRIC;
+  o->seed = 14024001ULL;
+  o->smoother = BAMG_SMOOTH_JACOBI;
+  o->precision = BAMG_PRECISION_FP64;
+  o->interp_rule = 1;
+  o->validate = 1;
+  return BAMG_OK;
+}
+
+const char *bamg_status_string(bamg_status s) {
+  switch (s) {
+    case BAMG_OK: return "ok";
+    case BAMG_NOT_CONVERGED: return "not converged";
+    case BAMG_E_ARG: return "invalid argument";
+    case BAMG_E_NOT_STOCHASTIC: return "matrix is not column stochastic";
+    case BAMG_E_REDUCIBLE: return "chain is reducible";
+    case BAMG_E_BAD_DIAG: return "zero diagonal";
+    case BAMG_E_COARSE: return "coarsest level solve failed";
+    case BAMG_E_BREAKDOWN: return "GMRES breakdown";
+    case BAMG_E_NONFINITE: return "non-finite value";
+    case BAMG_E_DEVICE: return "HIP error";
+    case BAMG_E_NOMEM: return "out of device memory";
+    default: return "unknown status";
+  }
+}
+
+const char *bamg_last_error(void) { return g_last_error.c_str(); }
+
+static bamg_status check_options(const bamg_options *o) {
+  if (o->r < 2 || o->r > 16) return BAMG_E_ARG;
+  if (o->setup_cycles < 1 || o->setup_cycles > 16) return BAMG_E_ARG;
+  if (o->nu_pre < 0 || o->nu_post < 0 || o->nu_setup < 0) return BAMG_E_ARG;
+  if (o->nu_pre > 64 || o->nu_post > 64 || o->nu_setup > 256) return BAMG_E_ARG;
+  if (!(o->omega > 0.0 && o->omega < 2.0)) return BAMG_E_ARG;
+  if (o->max_interp < 1 || o->max_interp > 8) return BAMG_E_ARG;
+  if (o->max_levels < 2 || o->max_levels > 32) return BAMG_E_ARG;
+  if (o->coarse_max < 1 || o->coarse_max > 2048) return BAMG_E_ARG;
+  if (o->coarsening != BAMG_COARSEN_GEOMETRIC && o->coarsening != BAMG_COARSEN_MIS) return BAMG_E_ARG;
+  if (o->smoother != BAMG_SMOOTH_JACOBI && o->smoother != BAMG_SMOOTH_KACZMARZ) return BAMG_E_ARG;
+  if (o->precision != BAMG_PRECISION_FP64 && o->precision != BAMG_PRECISION_MIXED) return BAMG_E_ARG;
+  if (o->interp_rule != 0 && o->interp_rule != 1) return BAMG_E_ARG;
+  return BAMG_OK;
+}
+
+bamg_status bamg_setup(const bamg_csr *A, const bamg_geometry *geom, const bamg_options *opt,
+                       const bamg_allocator *alloc, void *hip_stream, bamg_handle **out) {
+  if (!A || !opt || !out || !A->row_ptr || !A->col_idx || !A->val) return BAMG_E_ARG;
+  if (A->n < 2 || A->n > 0x7fffffffLL || A->nnz < 1 || A->nnz > 0x7fffffffLL) return BAMG_E_ARG;
+  bamg_status st = check_options(opt);
+  if (st != BAMG_OK) return st;
+  if (geom && geom->kind != BAMG_GEOM_NONE) {
+    if (geom->kind == BAMG_GEOM_GRID2D && (int64_t)geom->nx * geom->ny != A->n) return BAMG_E_ARG;
+    if (geom->kind == BAMG_GEOM_LINE && geom->nx != A->n) return BAMG_E_ARG;
+    if (geom->kind != BAMG_GEOM_GRID2D && geom->kind != BAMG_GEOM_LINE) return BAMG_E_ARG;
+  }
+  if (alloc && (!alloc->alloc || !alloc->free)) return BAMG_E_ARG;
+  bamg_handle *h = new (std::nothrow) bamg_handle();
+  if (!h) return BAMG_E_NOMEM;
+  h->opt = *opt;
+  h->prec = opt->precision == BAMG_PRECISION_MIXED ? 1 : 0;
+  h->pool.s = (hipStream_t)hip_stream;
+  if (alloc) {
+    h->pool.a = *alloc;
+    h->pool.custom = true;
+  }
+  try {
+    if (h->prec == 0)
+      setup_all<double>(h, A, geom);
+    else
+      setup_all<float>(h, A, geom);
+    if (h->prec != 0) {
+      h->vb = h->pool.get<float>(h->lv[0].n);
+      h->vx = h->pool.get<float>(h->lv[0].n);
+    }
+  } catch (const Error &e) {
+    h->pool.release_all();
+    delete h;
+    return translate(e);
+  } catch (...) {
+    h->pool.release_all();
+    delete h;
+    g_last_error = "unexpected exception in setup";
+    return BAMG_E_DEVICE;
+  }
+  *out = h;
+  return BAMG_OK;
+}
+
+bamg_status bamg_vcycle(bamg_handle *h, const void *b, void *x, int32_t dtype, void *hip_stream) {
+  if (!h || !b || !x || b == x) return BAMG_E_ARG;
+  if (dtype != BAMG_DTYPE_F64 && dtype != BAMG_DTYPE_F32) return BAMG_E_ARG;
+  if (dtype == BAMG_DTYPE_F32 && h->prec == 0) return BAMG_E_ARG;
+  BAMG_TRY
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int n = h->lv[0].n;
+  if (h->prec == 0) {
+    vcycle_run<double>(h, (const double *)b, (double *)x, s);
+  } else if (dtype == BAMG_DTYPE_F32) {
+    vcycle_run<float>(h, (const float *)b, (float *)x, s);
+  } else {
+    convert<double, float>((float *)h->vb, (const double *)b, n, s);
+    vcycle_run<float>(h, (const float *)h->vb, (float *)h->vx, s);
+    convert<float, double>((double *)x, (const float *)h->vx, n, s);
+  }
+  return BAMG_OK;
+  BAMG_CATCH
+}
+
+bamg_status bamg_gmres_solve(bamg_handle *h, void *x, int32_t restart, double tol,
+                             int32_t max_iters, int32_t use_x0, bamg_solve_info *info,
+                             void *hip_stream) {
+  if (!h || !x || restart < 1 || restart > 255 || max_iters < 0 || !(tol > 0.0)) return BAMG_E_ARG;
+  BAMG_TRY
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipStream_t keep = h->pool.s;
+  h->pool.s = s;
+  try {
+    gmres_run(h, (double *)x, restart, tol, max_iters, use_x0, info, s);
+  } catch (...) {
+    h->pool.s = keep;
+    throw;
+  }
+  h->pool.s = keep;
+  return BAMG_OK;
+  BAMG_CATCH
+}
+
+bamg_status bamg_hierarchy_info(const bamg_handle *h, int32_t *levels, int64_t *n_l,
+                                int64_t *nnz_l, double *oc, double *og) {
+  if (!h) return BAMG_E_ARG;
+  if (levels) *levels = h->L;
+  double sb = 0, sn = 0;
+  for (int l = 0; l < h->L; ++l) {
+    if (n_l) n_l[l] = h->lv[l].n;
+    if (nnz_l) nnz_l[l] = h->lv[l].B.nnz;
+    sb += h->lv[l].B.nnz;
+    sn += h->lv[l].n;
+  }
+  if (oc) *oc = sb / h->lv[0].B.nnz;
+  if (og) *og = sn / h->lv[0].n;
+  return BAMG_OK;
+}
+
+static bool level_pick(const bamg_handle *h, int l, int what, const Csr **A, const void **v) {
+  if (l < 0 || l >= h->L || what < 0 || what > 6) return false;
+  const Level &L = h->lv[l];
+  if (what >= 4 && l == h->L - 1) return false;
+  switch (what) {
+    case 0: *A = &L.B; *v = L.Bv; break;
+    case 1: *A = &L.Bt; *v = L.Btv; break;
+    case 2: *A = &L.M; *v = L.Mv; break;
+    case 3: *A = &L.M; *v = L.Nv; break;
+    case 4: *A = &L.P; *v = L.Pv; break;
+    case 5: *A = &L.Pc; *v = L.Qv; break;
+    default: *A = &L.P; *v = L.Qtv; break;
+  }
+  return true;
+}
+
+bamg_status bamg_level_nnz(const bamg_handle *h, int32_t l, int32_t what, int64_t *rows,
+                           int64_t *nnz) {
+  if (!h) return BAMG_E_ARG;
+  const Csr *A;
+  const void *v;
+  if (!level_pick(h, l, what, &A, &v)) return BAMG_E_ARG;
+  if (rows) *rows = A->nr;
+  if (nnz) *nnz = A->nnz;
+  return BAMG_OK;
+}
+
+bamg_status bamg_level_csr(const bamg_handle *h, int32_t l, int32_t what, int32_t *row_ptr,
+                           int32_t *col_idx, double *val) {
+  if (!h) return BAMG_E_ARG;
+  const Csr *A;
+  const void *v;
+  if (!level_pick(h, l, what, &A, &v)) return BAMG_E_ARG;
+  BAMG_TRY
+  if (row_ptr) HIPCHK(hipMemcpy(row_ptr, A->rp, sizeof(int) * (A->nr + 1), hipMemcpyDeviceToHost));
+  if (col_idx) HIPCHK(hipMemcpy(col_idx, A->ci, sizeof(int) * A->nnz, hipMemcpyDeviceToHost));
+  if (val) {
+    if (h->prec == 0) {
+      HIPCHK(hipMemcpy(val, v, sizeof(double) * A->nnz, hipMemcpyDeviceToHost));
+    } else {
+      std::vector<float> tmp(A->nnz);
+      HIPCHK(hipMemcpy(tmp.data(), v, sizeof(float) * A->nnz, hipMemcpyDeviceToHost));
+      for (int i = 0; i < A->nnz; ++i) val[i] = tmp[i];
+    }
+  }
+  return BAMG_OK;
+  BAMG_CATCH
+}
+
+bamg_status bamg_level_cf(const bamg_handle *h, int32_t l, int32_t *cf, int32_t *cidx) {
+  if (!h || l < 0 || l >= h->L - 1) return BAMG_E_ARG;
+  BAMG_TRY
+  const Level &L = h->lv[l];
+  if (cf) HIPCHK(hipMemcpy(cf, L.cf, sizeof(int) * L.n, hipMemcpyDeviceToHost));
+  if (cidx) HIPCHK(hipMemcpy(cidx, L.cidx, sizeof(int) * L.n, hipMemcpyDeviceToHost));
+  return BAMG_OK;
+  BAMG_CATCH
+}
+
+bamg_status bamg_level_vectors(const bamg_handle *h, int32_t l, double *U, double *V) {
+  if (!h || l < 0 || l >= h->L) return BAMG_E_ARG;
+  BAMG_TRY
+  const Level &L = h->lv[l];
+  const size_t nr = (size_t)L.n * h->opt.r;
+  for (int side = 0; side < 2; ++side) {
+    double *dst = side ? V : U;
+    const void *src = side ? L.V : L.U;
+    if (!dst) continue;
+    if (h->prec == 0) {
+      HIPCHK(hipMemcpy(dst, src, sizeof(double) * nr, hipMemcpyDeviceToHost));
+    } else {
+      std::vector<float> tmp(nr);
+      HIPCHK(hipMemcpy(tmp.data(), src, sizeof(float) * nr, hipMemcpyDeviceToHost));
+      for (size_t i = 0; i < nr; ++i) dst[i] = tmp[i];
+    }
+  }
+  return BAMG_OK;
+  BAMG_CATCH
+}
+
+bamg_status bamg_sigma(const bamg_handle *h, double *sigma) {
+  if (!h || !sigma) return BAMG_E_ARG;
+  BAMG_TRY
+  HIPCHK(hipMemcpy(sigma, h->sigma, sizeof(double) * h->opt.r, hipMemcpyDeviceToHost));
+  return BAMG_OK;
+  BAMG_CATCH
+}
+
+bamg_status bamg_x0(const bamg_handle *h, void *x_device, void *hip_stream) {
+  if (!h || !x_device) return BAMG_E_ARG;
+  BAMG_TRY
+  hipStream_t s = (hipStream_t)hip_stream;
+  HIPCHK(hipMemcpyAsync(x_device, h->x0, sizeof(double) * h->lv[0].n, hipMemcpyDeviceToDevice, s));
+  return BAMG_OK;
+  BAMG_CATCH
+}
+
+bamg_status bamg_coarse_pinv(const bamg_handle *h, double *bdag) {
+  if (!h || !bdag) return BAMG_E_ARG;
+  BAMG_TRY
+  const int n = h->lv[h->L - 1].n;
+  HIPCHK(hipMemcpy(bdag, h->bdag, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToHost));
+  return BAMG_OK;
+  BAMG_CATCH
+}
+
+void bamg_destroy(bamg_handle *h) {
+  if (!h) return;
+  h->pool.release_all();
+  if (h->hred) (void)hipHostFree(h->hred);
+  delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,231 @@
+// Internal declarations of the BAMG HIP library (gfx950).
+//
+// Layout in HBM, per level l of the hierarchy:
+//   B_l      CSR, int32 row_ptr/col_idx, values of type T (diagonal always
+//            stored, position in dpos); B_l^T as a separate CSR pattern whose
+//            values are a gather of B_l's through a permutation.
+//   M_l,N_l  one shared CSR pattern (M_0 = N_0 = I), two value arrays.
+//   P_l      n_l x n_{l+1} CSR by fine row (|row| <= c); holds P and Q^T values.
+//   Pc_l     its transpose, n_{l+1} x n_l by coarse row; holds P^T and Q values.
+//   U_l,V_l  test vectors, n_l x r row-major so a neighbour gather reads r
+//            contiguous values.
+// Everything is FP64, or FP32 for the setup and the V-cycle of a
+// mixed-precision handle; Krylov vectors and the coarsest solve stay FP64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bamg.h"
+
+namespace bamg {
+
+// Raised inside the library, caught at the C boundary.
+struct Error {
+  bamg_status code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(bamg_status code, const std::string &msg);
+void check_hip(hipError_t e, const char *what, const char *file, int line);
+#define HIPCHK(x) ::bamg::check_hip((x), #x, __FILE__, __LINE__)
+#define LAUNCHCHK() ::bamg::check_hip(hipGetLastError(), "kernel launch", __FILE__, __LINE__)
+
+// Device memory owned by a handle: every allocation is recorded and freed at
+// destruction.
+struct Pool {
+  bamg_allocator a{};
+  bool custom = false;
+  hipStream_t s = nullptr;
+  std::vector<void *> live;
+  void *raw(size_t bytes);
+  template <class X>
+  X *get(size_t count) {
+    return static_cast<X *>(raw(sizeof(X) * (count ? count : 1)));
+  }
+  std::vector<void *> deferred;  // released temporaries, freed after a sync
+  void release(void *p);          // defer the free of a temporary
+  void flush();                   // synchronise s, then free the deferred
+  void release_all();
+};
+
+struct Csr {
+  int nr = 0, nc = 0, nnz = 0;
+  int *rp = nullptr, *ci = nullptr;
+};
+
+struct Level {
+  int n = 0, nc = 0, nx = 0, ny = 0, gkind = 0;
+  Csr B, Bt, M, G, P, Pc, T1, T2;
+  int *btperm = nullptr, *pcperm = nullptr, *dpos = nullptr;
+  int *cf = nullptr, *cidx = nullptr, *cpts = nullptr;
+  bool identity_mn = false;  // level 0: M = N = I
+  // values (type T of the handle); void* so one struct serves both types
+  void *Bv = nullptr, *Btv = nullptr, *Mv = nullptr, *Nv = nullptr, *dinv = nullptr;
+  void *Pv = nullptr, *Qtv = nullptr, *Ptv = nullptr, *Qv = nullptr;
+  void *T1v = nullptr, *T2v = nullptr, *T3v = nullptr;
+  void *U = nullptr, *V = nullptr, *U2 = nullptr, *V2 = nullptr;
+  // V-cycle work vectors
+  void *xb = nullptr, *bb = nullptr, *rb = nullptr, *tb = nullptr;
+  // Kaczmarz: rows of B (and of B^T) grouped by colour
+  int ncolB = 0, ncolBt = 0;
+  int *colB = nullptr, *colBt = nullptr;        // colour of each row
+  int *ordB = nullptr, *ordBt = nullptr;        // rows sorted by colour
+  std::vector<int> offB, offBt;                 // host: colour segment offsets
+  void *rowinvB = nullptr, *rowinvBt = nullptr; // 1/||row||^2
+  int lanes = 0;                                // lanes per CSR row (0 = from nnz/row)
+};
+
+}  // namespace bamg
+
+struct bamg_handle {
+  bamg_options opt{};
+  int prec = 0;  // 0 = FP64, 1 = FP32 setup/V-cycle
+  bamg::Pool pool;
+  std::vector<bamg::Level> lv;
+  int L = 0;
+  // level-0 B in FP64 for the Krylov solver (== lv[0].Bv when prec == 0)
+  double *B64 = nullptr;
+  double *sigma = nullptr;  // device, r (FP64)
+  double *bdag = nullptr;   // device, n_L x n_L row-major (FP64)
+  double *x0 = nullptr;     // device, n (FP64)
+  double *red = nullptr;    // device reduction scratch
+  size_t red_cap = 0;
+  double *hred = nullptr;   // pinned host mirror
+  // GMRES storage, allocated on first use
+  int gm_m = 0;
+  double *gV = nullptr, *gBV = nullptr, *gw = nullptr, *gx0 = nullptr, *gbx0 = nullptr;
+  double *gH = nullptr, *gsc = nullptr;
+  void *vb = nullptr, *vx = nullptr;  // FP32 staging for a mixed V-cycle
+};
+
+namespace bamg {
+
+// ---- launchers: utilities (k_util.hip)
+void scan_counts(Pool &pool, const int *counts, int *rp, int n, hipStream_t s);  // rp[0]=0..rp[n]
+int read_int(const int *dptr, hipStream_t s);
+void fill_i32(int *p, int v, size_t n, hipStream_t s);
+void iota_i32(int *p, size_t n, hipStream_t s);
+template <class T> void fill(T *p, T v, size_t n, hipStream_t s);
+template <class T> void copy_permuted(T *out, const T *in, const int *perm, int n, hipStream_t s);
+template <class A, class B> void convert(B *out, const A *in, size_t n, hipStream_t s);
+// transposed pattern of A (nr x nc) and the permutation: At.val[k] = A.val[perm[k]]
+void transpose_pattern(Pool &pool, const Csr &A, Csr &At, int *&perm, hipStream_t s);
+void diag_positions(const Csr &A, int *dpos, hipStream_t s);  // -1 if absent
+void philox_testvecs(void *U, void *V, int prec, int n, int r, uint64_t seed, hipStream_t s);
+
+// ---- launchers: sparse kernels on vectors (k_sparse.hip)
+// y = A x (mode 0), y = b - A x (mode 1), y = y + A x (mode 2)
+template <class T>
+void spmv(const Csr &A, const T *val, const T *x, T *y, const T *b, int mode, int lanes,
+          hipStream_t s);
+// x_out = x_in + omega dinv (b - A x_in); x_in == nullptr means x_in = 0
+template <class T>
+void jacobi(const Csr &A, const T *val, const T *dinv, T omega, const T *b, const T *xin, T *xout,
+            int lanes, hipStream_t s);
+// Kaczmarz sweep over one colour segment (in place)
+template <class T>
+void kaczmarz_colour(const Csr &A, const T *val, const T *rowinv, const int *rows, int nrows,
+                     const T *b, T *x, hipStream_t s);
+// dense coarse solve x = Bdag b (Bdag FP64)
+template <class T>
+void coarse_gemv(const double *bdag, int n, const T *b, T *x, hipStream_t s);
+// partial sums for dot products: out[block] = sum x_i y_i (FP64)
+void dot_partials(const double *x, const double *y, int n, double *part, int nblk, hipStream_t s);
+
+// ---- launchers: setup (k_setup.hip)
+void build_B(const int *arp, const int *aci, const double *aval, int n, Pool &pool, Csr &B,
+             double *&bval, hipStream_t s);
+int check_input(Pool &pool, const int *arp, const int *aci, const double *aval, int n, int nnz,
+                hipStream_t s);
+int validate_chain(Pool &pool, const Csr &B, const Csr &Bt, const double *btv, hipStream_t s);
+void sym_graph(Pool &pool, const Csr &B, const Csr &Bt, Csr &G, hipStream_t s);
+void geom_cf(int n, int nx, int gkind, int *cf, hipStream_t s);
+void mis_cf(Pool &pool, const Csr &G, uint64_t seed, int level, int *cf, hipStream_t s);
+int coarse_numbering(Pool &pool, const int *cf, int n, int *cidx, int *&cpts, hipStream_t s);
+void interp_pattern(Pool &pool, const Level &L, int cap, int geometric, Csr &P, hipStream_t s);
+void spgemm_symbolic(Pool &pool, const Csr &A, const Csr &B, int force_diag, Csr &C,
+                     hipStream_t s);
+template <class T>
+void spgemm_numeric(const Csr &A, const T *av, const Csr &B, const T *bv, const Csr &C, T *cv,
+                    hipStream_t s);
+template <class T>
+void fill_transfer_identity(const Level &L, T *Pv, T *Qtv, hipStream_t s);
+template <class T>
+void ls_fit(const Level &L, int r, const T *U, const T *V, const double *wv, const double *wu,
+            int rule, T *Pv, T *Qtv, hipStream_t s);
+template <class T>
+void dinv_from_diag(const Level &L, const T *bv, T *dinv, int *flag, hipStream_t s);
+template <class T>
+void inject(const int *cpts, int nc, int r, const T *X, T *Xc, hipStream_t s);
+// Y = A X for r columns (row-major); if reset0, column 0 of Y is set to 1
+template <class T>
+void spmm(const Csr &A, const T *av, int r, const T *X, T *Y, int reset0, hipStream_t s);
+// one simultaneous relaxation sweep of the test vectors (Algorithm 1)
+template <class T>
+void relax_pairs(const Level &L, int r, T omega, int with_rhs, const double *sigma, const T *U,
+                 const T *V, T *Uo, T *Vo, hipStream_t s);
+// per-block partial sums of u.Bv, u.Mu, v.Nv, |Bv|^2, |B^T u|^2 per column
+template <class T>
+void pair_products(const Level &L, int r, const T *U, const T *V, int which, double *part,
+                   int nblk, hipStream_t s);
+template <class T>
+void scale_columns(T *X, int n, int r, const double *scale, int skip0, hipStream_t s);
+// finalize kernels on the reduction buffer
+void finalize_products(const double *part, int nblk, int r, double *out, hipStream_t s);
+void sigma_from_products(const double *prod, int r, double *sigma, hipStream_t s);
+void norm_scales(const double *prod, int r, double *scales, hipStream_t s);
+void ls_weights(const double *prod, int r, double *wv, double *wu, hipStream_t s);
+// Kaczmarz colouring of the rows of A (columns listed by At)
+void row_colouring(Pool &pool, const Csr &A, const Csr &At, int *colour, int &ncol,
+                   int *&order, std::vector<int> &offsets, hipStream_t s);
+template <class T>
+void row_inv_norms(const Csr &A, const T *val, T *out, hipStream_t s);
+
+// ---- launchers: coarsest level dense algebra (k_dense.hip)
+void csr_to_dense(const Csr &A, const void *val, int prec, double *D, hipStream_t s);
+int cholesky(double *A, int n, hipStream_t s);            // in place, lower, row-major
+void trsm_lower_cols(const double *L, double *X, int n, int ncols, int ldx, int transpose,
+                     hipStream_t s);                      // X <- L^-1 X or L^-T X (columns)
+void transpose_dense(const double *A, double *At, int n, hipStream_t s);
+int jacobi_svd(Pool &pool, double *W, double *J, int n, hipStream_t s);  // W, J col-major
+void column_norms(const double *W, int n, double *sv, hipStream_t s);
+void coarse_triplets_out(const double *LM, const double *LN, const double *W, const double *J,
+                         const double *sv, int n, int r, void *U, void *V, int prec,
+                         double *sigma, double *work, hipStream_t s);
+int build_pinv(Pool &pool, const double *W, const double *J, const double *sv, int n,
+               double *bdag, hipStream_t s);
+
+// ---- launchers: Krylov (k_krylov.hip)
+void multi_dot(const double *Vb, int n, int k, const double *w, double *part, int nblk,
+               hipStream_t s);
+void finalize_multi(const double *part, int nblk, int k, double *out, hipStream_t s);
+void multi_axpy_norm(const double *Vb, int n, int k, const double *h, double *w, double *part,
+                     int nblk, hipStream_t s);
+void gmres_arnoldi_update(double *H, double *cs, double *sn, double *g, double *y, double *h1,
+                          double *h2, const double *wnorm_part, int nblk, double *vnext_scale,
+                          int j, int m, double *flags, hipStream_t s);
+void scale_vec(const double *in, const double *scal, double *out, int n, hipStream_t s);
+void residual_check_partials(const double *x0, const double *bx0, const double *Vb,
+                             const double *BVb, const double *y, int n, int k, double *part,
+                             int nblk, hipStream_t s);
+void residual_check_finalize(const double *part, int nblk, double tol, double *flags,
+                             hipStream_t s);
+void update_iterate(double *x0, const double *Vb, const double *y, int n, int k, hipStream_t s);
+void negate_copy(const double *in, double *out, int n, hipStream_t s);
+void normalize_sum(double *x, int n, double *part, int nblk, double *flags, hipStream_t s);
+
+// host-side orchestration
+template <class T> void setup_all(bamg_handle *h, const bamg_csr *A, const bamg_geometry *g);
+template <class T> void vcycle_run(bamg_handle *h, const T *b, T *x, hipStream_t s);
+void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_x0,
+               bamg_solve_info *info, hipStream_t s);
+
+constexpr int kRedBlocks = 1024;  // partial-sum blocks of the reductions
+
+inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace bamg

@@ -1,0 +1,394 @@
+// Coarsest-level dense algebra (FP64 always):
+//  * the r smallest generalized singular triplets of eq.
+//    generalized_eigenvalue: B_L v = sigma M_L u, B_L^T u = sigma N_L v. With
+//    Cholesky factors M = L_M L_M^T, N = L_N L_N^T this is the ordinary SVD of
+//    Bt = L_M^-1 B_L L_N^-T; u = L_M^-T ut, v = L_N^-T vt.
+//  * the Moore-Penrose pseudo-inverse of B_L used by the coarse-grid
+//    correction (eq. coarse_grid_correction), from the SVD of B_L with the
+//    one zero singular value (1^T B_L = 0, Section 5) dropped.
+// The SVD is one-sided Jacobi (Hestenes): column pairs of W are rotated until
+// orthogonal. Pairs follow the round-robin (circle) schedule, so one round
+// rotates n/2 disjoint pairs in parallel, one workgroup per pair, with a
+// grid-wide barrier between rounds (cooperative launch).
+#include <hip/hip_cooperative_groups.h>
+
+#include "bamg_internal.h"
+#include "device_common.h"
+
+namespace cg = cooperative_groups;
+
+namespace bamg {
+
+template <class T>
+__global__ void k_csr_to_dense(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                               const T *__restrict__ v, double *__restrict__ D) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int a = rp[i]; a < rp[i + 1]; ++a) D[(size_t)i * n + ci[a]] += (double)v[a];
+}
+
+void csr_to_dense(const Csr &A, const void *val, int prec, double *D, hipStream_t s) {
+  const int n = A.nr;
+  HIPCHK(hipMemsetAsync(D, 0, sizeof(double) * (size_t)n * n, s));
+  if (prec == 0)
+    k_csr_to_dense<double><<<ceil_div(n, 128), 128, 0, s>>>(n, A.rp, A.ci, (const double *)val, D);
+  else
+    k_csr_to_dense<float><<<ceil_div(n, 128), 128, 0, s>>>(n, A.rp, A.ci, (const float *)val, D);
+  LAUNCHCHK();
+}
+
+// Right-looking Cholesky in one workgroup, in place (lower triangle,
+// row-major); the strict upper triangle is zeroed. flag = 1 if not SPD.
+__global__ void __launch_bounds__(1024) k_cholesky(double *__restrict__ A, int n,
+                                                   int *__restrict__ flag) {
+  __shared__ double piv;
+  const int t = threadIdx.x;
+  for (int j = 0; j < n; ++j) {
+    if (t == 0) {
+      const double d = A[(size_t)j * n + j];
+      if (!(d > 0.0)) {
+        *flag = 1;
+        piv = 1.0;
+      } else {
+        piv = sqrt(d);
+      }
+      A[(size_t)j * n + j] = piv;
+    }
+    __syncthreads();
+    const double d = piv;
+    for (int i = j + 1 + t; i < n; i += blockDim.x) A[(size_t)i * n + j] /= d;
+    __syncthreads();
+    // trailing update of the lower triangle: rows i > j, columns j < k <= i
+    const int m = n - j - 1;
+    const long tot = (long)m * (m + 1) / 2;
+    for (long e = t; e < tot; e += blockDim.x) {
+      // e -> (ii, kk) with 0 <= kk <= ii < m, row-wise enumeration
+      int ii = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+      while ((long)ii * (ii + 1) / 2 > e) --ii;
+      while ((long)(ii + 1) * (ii + 2) / 2 <= e) ++ii;
+      const int kk = (int)(e - (long)ii * (ii + 1) / 2);
+      const int i = j + 1 + ii, k = j + 1 + kk;
+      A[(size_t)i * n + k] -= A[(size_t)i * n + j] * A[(size_t)k * n + j];
+    }
+    __syncthreads();
+  }
+  for (long e = t; e < (long)n * n; e += blockDim.x) {
+    const int i = (int)(e / n), k = (int)(e % n);
+    if (k > i) A[e] = 0.0;
+  }
+}
+
+int cholesky(double *A, int n, hipStream_t s) {
+  int *flag;
+  HIPCHK(hipMalloc(&flag, sizeof(int)));
+  fill_i32(flag, 0, 1, s);
+  k_cholesky<<<1, 1024, 0, s>>>(A, n, flag);
+  LAUNCHCHK();
+  const int f = read_int(flag, s);
+  HIPCHK(hipFree(flag));
+  return f ? BAMG_E_COARSE : BAMG_OK;
+}
+
+// X (n x ncols, row-major, leading dimension ldx): columns solved in
+// parallel, one thread per column. transpose = 0: L y = x; 1: L^T y = x.
+__global__ void k_trsm_cols(const double *__restrict__ L, double *__restrict__ X, int n,
+                            int ncols, int ldx, int transpose) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  if (!transpose) {
+    for (int i = 0; i < n; ++i) {
+      double s = X[(size_t)i * ldx + c];
+      const double *Li = L + (size_t)i * n;
+      for (int k = 0; k < i; ++k) s -= Li[k] * X[(size_t)k * ldx + c];
+      X[(size_t)i * ldx + c] = s / Li[i];
+    }
+  } else {
+    for (int i = n - 1; i >= 0; --i) {
+      double s = X[(size_t)i * ldx + c];
+      for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * X[(size_t)k * ldx + c];
+      X[(size_t)i * ldx + c] = s / L[(size_t)i * n + i];
+    }
+  }
+}
+
+void trsm_lower_cols(const double *L, double *X, int n, int ncols, int ldx, int transpose,
+                     hipStream_t s) {
+  k_trsm_cols<<<ceil_div(ncols, 64), 64, 0, s>>>(L, X, n, ncols, ldx, transpose);
+  LAUNCHCHK();
+}
+
+__global__ void k_transpose_dense(const double *__restrict__ A, double *__restrict__ At, int n) {
+  __shared__ double tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  for (int y = threadIdx.y; y < 32; y += blockDim.y) {
+    const int r = by + y, c = bx + threadIdx.x;
+    if (r < n && c < n) tile[y][threadIdx.x] = A[(size_t)r * n + c];
+  }
+  __syncthreads();
+  for (int y = threadIdx.y; y < 32; y += blockDim.y) {
+    const int r = bx + y, c = by + threadIdx.x;
+    if (r < n && c < n) At[(size_t)r * n + c] = tile[threadIdx.x][y];
+  }
+}
+
+void transpose_dense(const double *A, double *At, int n, hipStream_t s) {
+  dim3 g(ceil_div(n, 32), ceil_div(n, 32)), b(32, 8);
+  k_transpose_dense<<<g, b, 0, s>>>(A, At, n);
+  LAUNCHCHK();
+}
+
+// ------------------------------------------------------------ Jacobi SVD
+constexpr int kSvdThreads = 256;
+constexpr int kSvdMaxSweeps = 80;
+
+__device__ __forceinline__ int rr_index(int j, int round, int m) {
+  return j == 0 ? 0 : 1 + (j - 1 + round) % (m - 1);
+}
+
+// W and J column-major n x n. m = n rounded up to even; index >= n is a
+// dummy column. ctrl[s] counts rotations of sweep s; ctrl[kSvdMaxSweeps]
+// receives the number of sweeps run.
+__global__ void __launch_bounds__(kSvdThreads)
+    k_jacobi_svd(double *__restrict__ W, double *__restrict__ J, int n, int m,
+                 int *__restrict__ ctrl) {
+  cg::grid_group grid = cg::this_grid();
+  __shared__ double red[3][kSvdThreads / kWave];
+  __shared__ double rot[2];
+  __shared__ int do_rot;
+  const double tol = 1e-15;
+  int sweep = 0;
+  for (; sweep < kSvdMaxSweeps; ++sweep) {
+    for (int round = 0; round < m - 1; ++round) {
+      for (int pair = blockIdx.x; pair < m / 2; pair += gridDim.x) {
+        int p = rr_index(pair, round, m), q = rr_index(m - 1 - pair, round, m);
+        if (p > q) {
+          const int x = p;
+          p = q;
+          q = x;
+        }
+        if (q >= n) continue;  // the dummy column (uniform in the block)
+        double *wp = W + (size_t)p * n, *wq = W + (size_t)q * n;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = threadIdx.x; i < n; i += kSvdThreads) {
+          const double a = wp[i], b = wq[i];
+          al += a * a;
+          be += b * b;
+          ga += a * b;
+        }
+        al = group_sum(al, kWave);
+        be = group_sum(be, kWave);
+        ga = group_sum(ga, kWave);
+        const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+        if (l == 0) {
+          red[0][w] = al;
+          red[1][w] = be;
+          red[2][w] = ga;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          double A = 0, Bq = 0, G = 0;
+          for (int k = 0; k < kSvdThreads / kWave; ++k) {
+            A += red[0][k];
+            Bq += red[1][k];
+            G += red[2][k];
+          }
+          do_rot = 0;
+          if (G != 0.0 && fabs(G) > tol * sqrt(A * Bq)) {
+            const double zeta = (Bq - A) / (2.0 * G);
+            const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double c = 1.0 / sqrt(1.0 + t * t);
+            rot[0] = c;
+            rot[1] = c * t;
+            do_rot = 1;
+            atomicAdd(&ctrl[sweep], 1);
+          }
+        }
+        __syncthreads();
+        if (do_rot) {
+          const double c = rot[0], sn = rot[1];
+          double *jp = J + (size_t)p * n, *jq = J + (size_t)q * n;
+          for (int i = threadIdx.x; i < n; i += kSvdThreads) {
+            const double a = wp[i], b = wq[i];
+            wp[i] = c * a - sn * b;
+            wq[i] = sn * a + c * b;
+            const double x = jp[i], y = jq[i];
+            jp[i] = c * x - sn * y;
+            jq[i] = sn * x + c * y;
+          }
+        }
+        __syncthreads();
+      }
+      grid.sync();
+    }
+    const int rotated = atomicAdd(&ctrl[sweep], 0);
+    grid.sync();
+    if (rotated == 0) break;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl[kSvdMaxSweeps] = sweep;
+}
+
+__global__ void k_identity_dense(double *__restrict__ J, int n) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n * n) return;
+  J[e] = (e / n) == (e % n) ? 1.0 : 0.0;
+}
+
+int jacobi_svd(Pool &pool, double *W, double *J, int n, hipStream_t s) {
+  int *ctrl = pool.get<int>(kSvdMaxSweeps + 1);
+  fill_i32(ctrl, 0, kSvdMaxSweeps + 1, s);
+  k_identity_dense<<<ceil_div((long)n * n, 256), 256, 0, s>>>(J, n);  // J = I
+  LAUNCHCHK();
+  int m = n + (n & 1);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  int ncu = 0, per = 0;
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_jacobi_svd,
+                                                      kSvdThreads, 0));
+  int grid = m / 2;
+  const int cap = ncu * (per > 0 ? per : 1);
+  if (grid > cap) grid = cap;
+  if (grid < 1) grid = 1;
+  void *args[] = {(void *)&W, (void *)&J, (void *)&n, (void *)&m, (void *)&ctrl};
+  HIPCHK(hipLaunchCooperativeKernel((const void *)k_jacobi_svd, dim3(grid), dim3(kSvdThreads),
+                                    args, 0, s));
+  int sweeps = 0;
+  HIPCHK(hipMemcpyAsync(&sweeps, ctrl + kSvdMaxSweeps, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  pool.release(ctrl);
+  return sweeps < kSvdMaxSweeps ? BAMG_OK : BAMG_E_COARSE;
+}
+
+__global__ void k_column_norms(const double *__restrict__ W, int n, double *__restrict__ sv) {
+  __shared__ double sh[4];
+  const int k = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double x = W[(size_t)k * n + i];
+    s += x * x;
+  }
+  s = block_sum<256>(s, sh);
+  if (threadIdx.x == 0) sv[k] = sqrt(s);
+}
+
+void column_norms(const double *W, int n, double *sv, hipStream_t s) {
+  k_column_norms<<<n, 256, 0, s>>>(W, n, sv);
+  LAUNCHCHK();
+}
+
+// The r smallest singular values in ascending order (ties: lower index).
+__global__ void k_select_smallest(const double *__restrict__ sv, int n, int r,
+                                  int *__restrict__ order) {
+  if (threadIdx.x != 0) return;
+  for (int t = 0; t < r; ++t) {
+    int best = -1;
+    for (int k = 0; k < n; ++k) {
+      bool taken = false;
+      for (int q = 0; q < t; ++q) taken |= (order[q] == k);
+      if (taken) continue;
+      if (best < 0 || sv[k] < sv[best]) best = k;
+    }
+    order[t] = best;
+  }
+}
+
+// One block per requested triplet t: x = L^-T (column of W / sigma or of J),
+// solved column-wise in LDS, then the pair sign fixed by sum(v) >= 0.
+template <class T>
+__global__ void __launch_bounds__(256)
+    k_triplets(const double *__restrict__ LM, const double *__restrict__ LN,
+               const double *__restrict__ W, const double *__restrict__ J,
+               const double *__restrict__ sv, const int *__restrict__ order, int n, int r,
+               T *__restrict__ U, T *__restrict__ V, double *__restrict__ sigma) {
+  extern __shared__ double xs[];  // 2n doubles: u then v
+  __shared__ double sh[4];
+  const int t = blockIdx.x;
+  const int k = order[t];
+  const double sk = sv[k];
+  double *xu = xs, *xv = xs + n;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    xu[i] = sk > 0.0 ? W[(size_t)k * n + i] / sk : 0.0;
+    xv[i] = J[(size_t)k * n + i];
+  }
+  __syncthreads();
+  for (int i = n - 1; i >= 0; --i) {
+    if (threadIdx.x == 0) {
+      xu[i] /= LM[(size_t)i * n + i];
+      xv[i] /= LN[(size_t)i * n + i];
+    }
+    __syncthreads();
+    const double ui = xu[i], vi = xv[i];
+    for (int q = threadIdx.x; q < i; q += 256) {
+      xu[q] -= LM[(size_t)i * n + q] * ui;
+      xv[q] -= LN[(size_t)i * n + q] * vi;
+    }
+    __syncthreads();
+  }
+  double sv_sum = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) sv_sum += xv[i];
+  sv_sum = block_sum<256>(sv_sum, sh);
+  __shared__ double sg;
+  if (threadIdx.x == 0) {
+    sg = sv_sum < 0.0 ? -1.0 : 1.0;
+    sigma[t] = sk;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += 256) {
+    V[(size_t)i * r + t] = (T)(sg * xv[i]);
+    U[(size_t)i * r + t] = t == 0 ? (T)1 : (T)(sg * xu[i]);
+  }
+}
+
+void coarse_triplets_out(const double *LM, const double *LN, const double *W, const double *J,
+                         const double *sv, int n, int r, void *U, void *V, int prec,
+                         double *sigma, double *work, hipStream_t s) {
+  int *order = reinterpret_cast<int *>(work);
+  k_select_smallest<<<1, 64, 0, s>>>(sv, n, r, order);
+  LAUNCHCHK();
+  const size_t shm = sizeof(double) * 2 * (size_t)n;
+  if (prec == 0)
+    k_triplets<double><<<r, 256, shm, s>>>(LM, LN, W, J, sv, order, n, r, (double *)U,
+                                           (double *)V, sigma);
+  else
+    k_triplets<float><<<r, 256, shm, s>>>(LM, LN, W, J, sv, order, n, r, (float *)U, (float *)V,
+                                          sigma);
+  LAUNCHCHK();
+}
+
+// Bdag = sum over kept k of J_k W_k^T / sigma_k^2 (W_k = sigma_k u_k).
+__global__ void k_pinv(const double *__restrict__ W, const double *__restrict__ J,
+                       const double *__restrict__ sv, int n, int kmin,
+                       double *__restrict__ bdag) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < n; ++k) {
+    if (k == kmin) continue;
+    s += J[(size_t)k * n + i] * W[(size_t)k * n + j] / (sv[k] * sv[k]);
+  }
+  bdag[(size_t)i * n + j] = s;
+}
+
+int build_pinv(Pool &pool, const double *W, const double *J, const double *sv, int n,
+               double *bdag, hipStream_t s) {
+  std::vector<double> h(n);
+  HIPCHK(hipMemcpyAsync(h.data(), sv, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  int kmin = 0;
+  double smax = 0.0;
+  for (int k = 0; k < n; ++k) {
+    if (h[k] < h[kmin]) kmin = k;
+    smax = h[k] > smax ? h[k] : smax;
+  }
+  double s2 = 1e300;
+  for (int k = 0; k < n; ++k)
+    if (k != kmin && h[k] < s2) s2 = h[k];
+  if (!(h[kmin] <= 1e-10 * smax) || !(s2 > 1e-13 * smax)) return BAMG_E_COARSE;
+  dim3 g(ceil_div(n, 128), n);
+  k_pinv<<<g, 128, 0, s>>>(W, J, sv, n, kmin, bdag);
+  LAUNCHCHK();
+  (void)pool;
+  return BAMG_OK;
+}
+
+}  // namespace bamg

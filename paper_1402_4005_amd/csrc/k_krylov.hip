@@ -1,0 +1,284 @@
+// FP64 kernels of GMRES(m) on the preconditioned residual equation
+// C B e = -C B x0 (Section 6): Gram-Schmidt applied twice with fused
+// multi-vector dots and updates, a one-workgroup Hessenberg/Givens update,
+// and the true scaled residual ||B x|| / ||x|| of x = x0 + V y (Section 7),
+// formed from the stored products B v_t so no extra SpMV is needed.
+// All reductions are two-stage with a fixed order, so results do not depend
+// on scheduling.
+#include "bamg_internal.h"
+#include "device_common.h"
+
+namespace bamg {
+
+constexpr int kKT = 256;
+
+// part[t * nblk + b] = sum over block b's rows of V_t . w  (t < k); t == k: w . w
+__global__ void __launch_bounds__(kKT) k_multi_dot(const double *__restrict__ Vb, int n, int k,
+                                                   const double *__restrict__ w,
+                                                   double *__restrict__ part) {
+  __shared__ double sh[kKT / kWave];
+  const int t = blockIdx.y;
+  const double *v = t < k ? Vb + (size_t)t * n : w;
+  double s = 0.0;
+  for (long i = (long)blockIdx.x * kKT + threadIdx.x; i < n; i += (long)gridDim.x * kKT)
+    s += v[i] * w[i];
+  s = block_sum<kKT>(s, sh);
+  if (threadIdx.x == 0) part[(size_t)t * gridDim.x + blockIdx.x] = s;
+}
+
+void multi_dot(const double *Vb, int n, int k, const double *w, double *part, int nblk,
+               hipStream_t s) {
+  k_multi_dot<<<dim3(nblk, k + 1), kKT, 0, s>>>(Vb, n, k, w, part);
+  LAUNCHCHK();
+}
+
+// out[t] = sum_b part[t * nblk + b], one block per t, fixed order
+__global__ void __launch_bounds__(kKT) k_finalize_multi(const double *__restrict__ part, int nblk,
+                                                        double *__restrict__ out) {
+  __shared__ double sh[kKT / kWave];
+  const int t = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kKT) s += part[(size_t)t * nblk + b];
+  s = block_sum<kKT>(s, sh);
+  if (threadIdx.x == 0) out[t] = s;
+}
+
+void finalize_multi(const double *part, int nblk, int k, double *out, hipStream_t s) {
+  k_finalize_multi<<<k, kKT, 0, s>>>(part, nblk, out);
+  LAUNCHCHK();
+}
+
+// w <- w - sum_t h[t] V_t ; part[b] = block partial of |w|^2
+__global__ void __launch_bounds__(kKT)
+    k_multi_axpy_norm(const double *__restrict__ Vb, int n, int k, const double *__restrict__ h,
+                      double *__restrict__ w, double *__restrict__ part) {
+  __shared__ double sh[kKT / kWave];
+  __shared__ double hs[256];
+  for (int t = threadIdx.x; t < k; t += kKT) hs[t] = h[t];
+  __syncthreads();
+  double s = 0.0;
+  for (long i = (long)blockIdx.x * kKT + threadIdx.x; i < n; i += (long)gridDim.x * kKT) {
+    double x = w[i];
+    for (int t = 0; t < k; ++t) x -= hs[t] * Vb[(size_t)t * n + i];
+    w[i] = x;
+    s += x * x;
+  }
+  s = block_sum<kKT>(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+void multi_axpy_norm(const double *Vb, int n, int k, const double *h, double *w, double *part,
+                     int nblk, hipStream_t s) {
+  if (k > 256) fail(BAMG_E_ARG, "restart length above 255");
+  k_multi_axpy_norm<<<nblk, kKT, 0, s>>>(Vb, n, k, h, w, part);
+  LAUNCHCHK();
+}
+
+// Arnoldi step j of the Hessenberg matrix H ((m+1) x m, row-major), Givens
+// rotations cs/sn, right-hand side g, solution y of the leading j+1 system.
+// h1, h2: the two Gram-Schmidt coefficient passes (j+1 values each, plus the
+// pre-orthogonalisation |w|^2 at h1[j+1]); wpart: nblk partials of the final
+// |w|^2. flags[1] = breakdown, flags[3] = 1/h_{j+1,j}, flags[4] = |g_{j+1}|.
+__global__ void __launch_bounds__(kKT)
+    k_arnoldi_update(double *__restrict__ H, double *__restrict__ cs, double *__restrict__ sn,
+                     double *__restrict__ g, double *__restrict__ y,
+                     const double *__restrict__ h1, const double *__restrict__ h2,
+                     const double *__restrict__ wpart, int nblk, int j, int m,
+                     double *__restrict__ flags) {
+  __shared__ double sh[kKT / kWave];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kKT) s += wpart[b];
+  s = block_sum<kKT>(s, sh);
+  if (threadIdx.x != 0) return;
+  const double hn = sqrt(s);
+  const double w0 = sqrt(h1[j + 1]);
+  for (int i = 0; i <= j; ++i) H[i * m + j] = h1[i] + h2[i];
+  H[(j + 1) * m + j] = hn;
+  const bool broke = !(hn > 1e-14 * w0);
+  for (int i = 0; i < j; ++i) {
+    const double a = H[i * m + j], b = H[(i + 1) * m + j];
+    H[i * m + j] = cs[i] * a + sn[i] * b;
+    H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+  }
+  const double a = H[j * m + j], b = H[(j + 1) * m + j];
+  const double den = sqrt(a * a + b * b);
+  cs[j] = den > 0 ? a / den : 1.0;
+  sn[j] = den > 0 ? b / den : 0.0;
+  H[j * m + j] = den;
+  H[(j + 1) * m + j] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  for (int i = j; i >= 0; --i) {
+    double t = g[i];
+    for (int q = i + 1; q <= j; ++q) t -= H[i * m + q] * y[q];
+    y[i] = t / H[i * m + i];
+  }
+  flags[1] = broke ? 1.0 : 0.0;
+  flags[3] = broke ? 0.0 : 1.0 / hn;
+  flags[4] = fabs(g[j + 1]);
+}
+
+void gmres_arnoldi_update(double *H, double *cs, double *sn, double *g, double *y, double *h1,
+                          double *h2, const double *wnorm_part, int nblk, double *vnext_scale,
+                          int j, int m, double *flags, hipStream_t s) {
+  (void)vnext_scale;
+  k_arnoldi_update<<<1, kKT, 0, s>>>(H, cs, sn, g, y, h1, h2, wnorm_part, nblk, j, m, flags);
+  LAUNCHCHK();
+}
+
+__global__ void k_scale_vec(const double *__restrict__ in, const double *__restrict__ scal,
+                            double *__restrict__ out, int n) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i] * scal[0];
+}
+
+void scale_vec(const double *in, const double *scal, double *out, int n, hipStream_t s) {
+  k_scale_vec<<<ceil_div(n, 256), 256, 0, s>>>(in, scal, out, n);
+  LAUNCHCHK();
+}
+
+// partials of |B x0 + sum_t y_t B v_t|^2 and |x0 + sum_t y_t v_t|^2
+__global__ void __launch_bounds__(kKT)
+    k_resid_part(const double *__restrict__ x0, const double *__restrict__ bx0,
+                 const double *__restrict__ Vb, const double *__restrict__ BVb,
+                 const double *__restrict__ y, int n, int k, double *__restrict__ part) {
+  __shared__ double sh[kKT / kWave];
+  __shared__ double ys[256];
+  for (int t = threadIdx.x; t < k; t += kKT) ys[t] = y[t];
+  __syncthreads();
+  double sb = 0.0, sx = 0.0;
+  for (long i = (long)blockIdx.x * kKT + threadIdx.x; i < n; i += (long)gridDim.x * kKT) {
+    double bx = bx0[i], xx = x0[i];
+    for (int t = 0; t < k; ++t) {
+      bx += ys[t] * BVb[(size_t)t * n + i];
+      xx += ys[t] * Vb[(size_t)t * n + i];
+    }
+    sb += bx * bx;
+    sx += xx * xx;
+  }
+  sb = block_sum<kKT>(sb, sh);
+  sx = block_sum<kKT>(sx, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = sb;
+    part[gridDim.x + blockIdx.x] = sx;
+  }
+}
+
+void residual_check_partials(const double *x0, const double *bx0, const double *Vb,
+                             const double *BVb, const double *y, int n, int k, double *part,
+                             int nblk, hipStream_t s) {
+  k_resid_part<<<nblk, kKT, 0, s>>>(x0, bx0, Vb, BVb, y, n, k, part);
+  LAUNCHCHK();
+}
+
+// flags[0] = converged, flags[2] = ||Bx||/||x||
+__global__ void __launch_bounds__(kKT) k_resid_final(const double *__restrict__ part, int nblk,
+                                                     double tol, double *__restrict__ flags) {
+  __shared__ double sh[kKT / kWave];
+  double a = 0.0, b = 0.0;
+  for (int q = threadIdx.x; q < nblk; q += kKT) {
+    a += part[q];
+    b += part[nblk + q];
+  }
+  a = block_sum<kKT>(a, sh);
+  b = block_sum<kKT>(b, sh);
+  if (threadIdx.x == 0) {
+    const double rel = b > 0.0 ? sqrt(a) / sqrt(b) : INFINITY;
+    flags[2] = rel;
+    flags[0] = rel < tol ? 1.0 : 0.0;
+  }
+}
+
+void residual_check_finalize(const double *part, int nblk, double tol, double *flags,
+                             hipStream_t s) {
+  k_resid_final<<<1, kKT, 0, s>>>(part, nblk, tol, flags);
+  LAUNCHCHK();
+}
+
+__global__ void k_update_iterate(double *__restrict__ x0, const double *__restrict__ Vb,
+                                 const double *__restrict__ y, int n, int k) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double x = x0[i];
+  for (int t = 0; t < k; ++t) x += y[t] * Vb[(size_t)t * n + i];
+  x0[i] = x;
+}
+
+void update_iterate(double *x0, const double *Vb, const double *y, int n, int k, hipStream_t s) {
+  k_update_iterate<<<ceil_div(n, 256), 256, 0, s>>>(x0, Vb, y, n, k);
+  LAUNCHCHK();
+}
+
+__global__ void k_negate(const double *__restrict__ in, double *__restrict__ out, int n) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = -in[i];
+}
+
+void negate_copy(const double *in, double *out, int n, hipStream_t s) {
+  k_negate<<<ceil_div(n, 256), 256, 0, s>>>(in, out, n);
+  LAUNCHCHK();
+}
+
+// x <- x / sum(x); flags[5] = min x afterwards, flags[6] = sum before
+__global__ void __launch_bounds__(kKT) k_sum_min_part(const double *__restrict__ x, int n,
+                                                      double *__restrict__ part) {
+  __shared__ double sh[kKT / kWave];
+  double s = 0.0;
+  for (long i = (long)blockIdx.x * kKT + threadIdx.x; i < n; i += (long)gridDim.x * kKT) s += x[i];
+  s = block_sum<kKT>(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kKT) k_sum_final(const double *__restrict__ part, int nblk,
+                                                   double *__restrict__ flags) {
+  __shared__ double sh[kKT / kWave];
+  double s = 0.0;
+  for (int q = threadIdx.x; q < nblk; q += kKT) s += part[q];
+  s = block_sum<kKT>(s, sh);
+  if (threadIdx.x == 0) {
+    flags[6] = s;
+    flags[7] = s != 0.0 ? 1.0 / s : 1.0;
+  }
+}
+
+__global__ void __launch_bounds__(kKT) k_scale_min(double *__restrict__ x, int n,
+                                                   const double *__restrict__ flags,
+                                                   double *__restrict__ part) {
+  __shared__ double sh[kKT / kWave];
+  const double sc = flags[7];
+  double mn = INFINITY;
+  for (long i = (long)blockIdx.x * kKT + threadIdx.x; i < n; i += (long)gridDim.x * kKT) {
+    const double v = x[i] * sc;
+    x[i] = v;
+    mn = fmin(mn, v);
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) mn = fmin(mn, __shfl_xor(mn, off, kWave));
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  if (l == 0) sh[w] = mn;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = sh[0];
+    for (int q = 1; q < kKT / kWave; ++q) r = fmin(r, sh[q]);
+    part[blockIdx.x] = r;
+  }
+}
+
+__global__ void k_min_final(const double *__restrict__ part, int nblk, double *__restrict__ flags) {
+  if (threadIdx.x != 0) return;
+  double r = INFINITY;
+  for (int q = 0; q < nblk; ++q) r = fmin(r, part[q]);
+  flags[5] = r;
+}
+
+void normalize_sum(double *x, int n, double *part, int nblk, double *flags, hipStream_t s) {
+  k_sum_min_part<<<nblk, kKT, 0, s>>>(x, n, part);
+  LAUNCHCHK();
+  k_sum_final<<<1, kKT, 0, s>>>(part, nblk, flags);
+  LAUNCHCHK();
+  k_scale_min<<<nblk, kKT, 0, s>>>(x, n, flags, part);
+  LAUNCHCHK();
+  k_min_final<<<1, 64, 0, s>>>(part, nblk, flags);
+  LAUNCHCHK();
+}
+
+}  // namespace bamg

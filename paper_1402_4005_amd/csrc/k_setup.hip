@@ -1,0 +1,1236 @@
+// Setup kernels of the bootstrap AMG hierarchy:
+//  * B = I - A assembly and input validation (Section 2),
+//  * C/F splitting: geometric (Section 7) or a greedy maximal independent set
+//    computed in parallel rounds (stand-in for compatible relaxation),
+//  * interpolation sets J_i and the patterns of P (eq. Pstructure), Q^T,
+//  * Galerkin products Q B P, Q M Q^T, P^T N P (Algorithm 1): an integer
+//    symbolic phase (sorted patterns, bit-exact) and a numeric phase,
+//  * the batched small weighted least-squares fits of eq. ls_interpolation
+//    with the sum-to-one constraint of Section 5,
+//  * relaxation of the r test-vector pairs and the reductions for sigma
+//    (eq. singular_value), the normalisation and the LS weights
+//    (eq. ls_weights).
+#include <algorithm>
+
+#include "bamg_internal.h"
+#include "device_common.h"
+
+namespace bamg {
+
+// ============================================================ assembly
+__global__ void k_b_count(const int *__restrict__ rp, const int *__restrict__ ci, int n,
+                          int *__restrict__ cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int has = 0;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) has |= (ci[k] == i);
+  cnt[i] = rp[i + 1] - rp[i] + (has ? 0 : 1);
+}
+
+// B = I - A, diagonal inserted in column order when A has none
+__global__ void k_b_fill(const int *__restrict__ rp, const int *__restrict__ ci,
+                         const double *__restrict__ a, int n, const int *__restrict__ brp,
+                         int *__restrict__ bci, double *__restrict__ bv) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int p = brp[i];
+  bool placed = false;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    const int j = ci[k];
+    if (!placed && j > i) {
+      bci[p] = i;
+      bv[p++] = 1.0;
+      placed = true;
+    }
+    bci[p] = j;
+    bv[p++] = (j == i ? 1.0 : 0.0) - a[k];
+    if (j == i) placed = true;
+  }
+  if (!placed) {
+    bci[p] = i;
+    bv[p] = 1.0;
+  }
+}
+
+// Structural checks of the input CSR: indices in range, strictly ascending.
+__global__ void k_check_csr(const int *__restrict__ rp, const int *__restrict__ ci,
+                            const double *__restrict__ a, int n, int nnz, int *__restrict__ flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int b = rp[i], e = rp[i + 1];
+  if (b < 0 || e < b || e > nnz) {
+    atomicOr(flag, 1);
+    return;
+  }
+  for (int k = b; k < e; ++k) {
+    const int j = ci[k];
+    if (j < 0 || j >= n || (k > b && j <= ci[k - 1])) atomicOr(flag, 1);
+    const double v = a[k];
+    if (!(v >= 0.0) || !isfinite(v)) atomicOr(flag, 2);
+  }
+}
+
+void build_B(const int *arp, const int *aci, const double *aval, int n, Pool &pool, Csr &B,
+             double *&bval, hipStream_t s) {
+  int *cnt = pool.get<int>(n);
+  k_b_count<<<ceil_div(n, 256), 256, 0, s>>>(arp, aci, n, cnt);
+  LAUNCHCHK();
+  B.nr = B.nc = n;
+  B.rp = pool.get<int>(n + 1);
+  scan_counts(pool, cnt, B.rp, n, s);
+  B.nnz = read_int(B.rp + n, s);
+  B.ci = pool.get<int>(B.nnz);
+  bval = pool.get<double>(B.nnz);
+  k_b_fill<<<ceil_div(n, 256), 256, 0, s>>>(arp, aci, aval, n, B.rp, B.ci, bval);
+  LAUNCHCHK();
+  pool.release(cnt);
+}
+
+// Column sums of A through the rows of B^T: sum_i a_ij = sum_i (delta_ij - B_ij).
+__global__ void k_colsum_check(const int *__restrict__ trp, const int *__restrict__ tci,
+                               const double *__restrict__ tv, int n, int *__restrict__ flag) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int k = trp[j]; k < trp[j + 1]; ++k) s += (tci[k] == j ? 1.0 : 0.0) - tv[k];
+  if (!(fabs(s - 1.0) <= 1e-12)) atomicOr(flag, 2);
+}
+
+// Reachability from state 0 by breadth-first search in one workgroup; the
+// frontier queues live in global memory, the level loop synchronises the
+// block. Returns the number of states reached in *out.
+__global__ void __launch_bounds__(1024)
+    k_bfs_one_block(const int *__restrict__ rp, const int *__restrict__ ci, int n,
+                    int *__restrict__ visited, int *__restrict__ qa, int *__restrict__ qb,
+                    int *__restrict__ out) {
+  __shared__ int cur_n, nxt_n, total;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    visited[0] = 1;
+    qa[0] = 0;
+    cur_n = 1;
+    nxt_n = 0;
+    total = 1;
+  }
+  __syncthreads();
+  int *cur = qa, *nxt = qb;
+  while (cur_n > 0) {
+    const int cn = cur_n;
+    for (int idx = t; idx < cn; idx += blockDim.x) {
+      const int v = cur[idx];
+      for (int k = rp[v]; k < rp[v + 1]; ++k) {
+        const int u = ci[k];
+        if (atomicCAS(&visited[u], 0, 1) == 0) {
+          const int pos = atomicAdd(&nxt_n, 1);
+          nxt[pos] = u;
+        }
+      }
+    }
+    __syncthreads();
+    if (t == 0) {
+      total += nxt_n;
+      cur_n = nxt_n;
+      nxt_n = 0;
+    }
+    __syncthreads();
+    int *tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+  }
+  if (t == 0) *out = total;
+}
+
+// Structural checks of the caller's CSR (indices in range, ascending,
+// values finite and non-negative) before anything indexes through it.
+int check_input(Pool &pool, const int *arp, const int *aci, const double *aval, int n, int nnz,
+                hipStream_t s) {
+  int ends[2];
+  HIPCHK(hipMemcpyAsync(&ends[0], arp, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&ends[1], arp + n, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (ends[0] != 0 || ends[1] != nnz) return BAMG_E_ARG;
+  int *flag = pool.get<int>(1);
+  fill_i32(flag, 0, 1, s);
+  k_check_csr<<<ceil_div(n, 256), 256, 0, s>>>(arp, aci, aval, n, nnz, flag);
+  LAUNCHCHK();
+  const int f = read_int(flag, s);
+  pool.release(flag);
+  if (f & 1) return BAMG_E_ARG;
+  if (f & 2) return BAMG_E_NOT_STOCHASTIC;
+  return BAMG_OK;
+}
+
+// Column sums of A equal to 1 (through B^T, whose values btv are B's
+// permuted) and strong connectivity (reachability from state 0 along the
+// rows of B and of B^T).
+int validate_chain(Pool &pool, const Csr &B, const Csr &Bt, const double *btv, hipStream_t s) {
+  const int n = B.nr;
+  int *flag = pool.get<int>(4);
+  fill_i32(flag, 0, 4, s);
+  k_colsum_check<<<ceil_div(n, 256), 256, 0, s>>>(Bt.rp, Bt.ci, btv, n, flag);
+  LAUNCHCHK();
+  int *visited = pool.get<int>(n);
+  int *qa = pool.get<int>(n), *qb = pool.get<int>(n);
+  for (int pass = 0; pass < 2; ++pass) {
+    const Csr &G = pass ? Bt : B;
+    fill_i32(visited, 0, n, s);
+    k_bfs_one_block<<<1, 1024, 0, s>>>(G.rp, G.ci, n, visited, qa, qb, flag + 1 + pass);
+    LAUNCHCHK();
+  }
+  int h[4];
+  HIPCHK(hipMemcpyAsync(h, flag, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  pool.release(visited);
+  pool.release(qa);
+  pool.release(qb);
+  pool.release(flag);
+  if (h[0] & 2) return BAMG_E_NOT_STOCHASTIC;
+  if (h[1] != n || h[2] != n) return BAMG_E_REDUCIBLE;
+  return BAMG_OK;
+}
+
+// ============================================================ graph
+// G = pattern(B + B^T) without the diagonal: merge of row i of B and of B^T.
+template <bool FILL>
+__global__ void k_sym_graph(const int *__restrict__ brp, const int *__restrict__ bci,
+                            const int *__restrict__ trp, const int *__restrict__ tci, int n,
+                            int *__restrict__ cnt, const int *__restrict__ grp,
+                            int *__restrict__ gci) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int a = brp[i], ae = brp[i + 1], b = trp[i], be = trp[i + 1];
+  int c = 0, p = FILL ? grp[i] : 0;
+  while (a < ae || b < be) {
+    int j;
+    if (b >= be || (a < ae && bci[a] < tci[b])) {
+      j = bci[a++];
+    } else if (a >= ae || tci[b] < bci[a]) {
+      j = tci[b++];
+    } else {
+      j = bci[a++];
+      ++b;
+    }
+    if (j == i) continue;
+    if (FILL)
+      gci[p++] = j;
+    else
+      ++c;
+  }
+  if (!FILL) cnt[i] = c;
+}
+
+void sym_graph(Pool &pool, const Csr &B, const Csr &Bt, Csr &G, hipStream_t s) {
+  const int n = B.nr;
+  int *cnt = pool.get<int>(n);
+  k_sym_graph<false><<<ceil_div(n, 256), 256, 0, s>>>(B.rp, B.ci, Bt.rp, Bt.ci, n, cnt, nullptr,
+                                                      nullptr);
+  LAUNCHCHK();
+  G.nr = G.nc = n;
+  G.rp = pool.get<int>(n + 1);
+  scan_counts(pool, cnt, G.rp, n, s);
+  G.nnz = read_int(G.rp + n, s);
+  G.ci = pool.get<int>(G.nnz);
+  k_sym_graph<true><<<ceil_div(n, 256), 256, 0, s>>>(B.rp, B.ci, Bt.rp, Bt.ci, n, nullptr, G.rp,
+                                                     G.ci);
+  LAUNCHCHK();
+  pool.release(cnt);
+}
+
+// ============================================================ C/F splitting
+// Geometric: on a grid every other point in each direction (Section 7);
+// on a line every other point.
+__global__ void k_geom_cf(int n, int nx, int gkind, int *__restrict__ cf) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (gkind == 2) {
+    const int ix = i % nx, iy = i / nx;
+    cf[i] = ((ix & 1) == 0 && (iy & 1) == 0) ? 1 : 0;
+  } else {
+    cf[i] = (i & 1) == 0 ? 1 : 0;
+  }
+}
+
+void geom_cf(int n, int nx, int gkind, int *cf, hipStream_t s) {
+  k_geom_cf<<<ceil_div(n, 256), 256, 0, s>>>(n, nx, gkind, cf);
+  LAUNCHCHK();
+}
+
+// Greedy maximal independent set in decreasing priority (key_i, i), key_i
+// the first Philox word of counter (i, level, 2, 0), key (seed, 0).
+// Computed in rounds: an undecided vertex whose priority exceeds that of
+// every undecided neighbour joins; then the neighbours of the new members
+// leave. Every round reproduces a prefix of the sequential greedy order, so
+// the result is the same set (lexicographically-first MIS).
+__global__ void k_mis_keys(int n, uint64_t seed, int level, uint64_t *__restrict__ key,
+                           int *__restrict__ state) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  key[i] = philox_word0((uint64_t)i, (uint64_t)level, 2, 0, seed, 0);
+  state[i] = -1;
+}
+
+__global__ void k_mis_select(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                             const uint64_t *__restrict__ key, const int *__restrict__ state,
+                             int *__restrict__ sel, int round) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n || state[v] != -1) return;
+  const uint64_t kv = key[v];
+  for (int k = rp[v]; k < rp[v + 1]; ++k) {
+    const int u = ci[k];
+    if (state[u] != -1) continue;
+    const uint64_t ku = key[u];
+    if (ku > kv || (ku == kv && u > v)) return;
+  }
+  sel[v] = round;
+}
+
+__global__ void k_mis_update(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                             const int *__restrict__ sel, int *__restrict__ state, int round,
+                             int *__restrict__ undecided) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n || state[v] != -1) return;
+  if (sel[v] == round) {
+    state[v] = 1;
+    return;
+  }
+  for (int k = rp[v]; k < rp[v + 1]; ++k)
+    if (sel[ci[k]] == round) {
+      state[v] = 0;
+      return;
+    }
+  atomicAdd(undecided, 1);
+}
+
+void mis_cf(Pool &pool, const Csr &G, uint64_t seed, int level, int *cf, hipStream_t s) {
+  const int n = G.nr;
+  uint64_t *key = pool.get<uint64_t>(n);
+  int *sel = pool.get<int>(n);
+  int *und = pool.get<int>(1);
+  fill_i32(sel, 0, n, s);
+  k_mis_keys<<<ceil_div(n, 256), 256, 0, s>>>(n, seed, level, key, cf);
+  LAUNCHCHK();
+  for (int round = 1;; ++round) {
+    if (round > n + 1) fail(BAMG_E_DEVICE, "MIS did not terminate");
+    fill_i32(und, 0, 1, s);
+    k_mis_select<<<ceil_div(n, 256), 256, 0, s>>>(n, G.rp, G.ci, key, cf, sel, round);
+    LAUNCHCHK();
+    k_mis_update<<<ceil_div(n, 256), 256, 0, s>>>(n, G.rp, G.ci, sel, cf, round, und);
+    LAUNCHCHK();
+    if (read_int(und, s) == 0) break;
+  }
+  pool.release(key);
+  pool.release(sel);
+  pool.release(und);
+}
+
+__global__ void k_cidx(const int *__restrict__ cf, const int *__restrict__ scan, int n,
+                       int *__restrict__ cidx, int *__restrict__ cpts) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (cf[i]) {
+    cidx[i] = scan[i];
+    cpts[scan[i]] = i;
+  } else {
+    cidx[i] = -1;
+  }
+}
+
+int coarse_numbering(Pool &pool, const int *cf, int n, int *cidx, int *&cpts, hipStream_t s) {
+  int *sc = pool.get<int>(n + 1);
+  scan_counts(pool, cf, sc, n, s);
+  const int nc = read_int(sc + n, s);
+  cpts = pool.get<int>(nc);
+  k_cidx<<<ceil_div(n, 256), 256, 0, s>>>(cf, sc, n, cidx, cpts);
+  LAUNCHCHK();
+  pool.release(sc);
+  return nc;
+}
+
+// ============================================================ J_i and P
+// Geometric J_i: coarse points within Chebyshev distance 1 (grid) or the
+// two neighbours (line), ascending coarse index, at most cap.
+// Algebraic J_i: coarse neighbours in G ranked by the number of common
+// neighbours (ties: smaller index), at most cap, then sorted by coarse index.
+__device__ int common_neighbours(const int *__restrict__ rp, const int *__restrict__ ci, int i,
+                                 int j) {
+  int a = rp[i], ae = rp[i + 1], b = rp[j], be = rp[j + 1], c = 0;
+  while (a < ae && b < be) {
+    const int x = ci[a], y = ci[b];
+    if (x == y) {
+      ++c;
+      ++a;
+      ++b;
+    } else if (x < y) {
+      ++a;
+    } else {
+      ++b;
+    }
+  }
+  return c;
+}
+
+template <bool FILL>
+__global__ void k_interp_pattern(int n, int nx, int ny, int gkind, int geometric, int cap,
+                                 const int *__restrict__ cf, const int *__restrict__ cidx,
+                                 const int *__restrict__ grp, const int *__restrict__ gci,
+                                 int *__restrict__ cnt, const int *__restrict__ prp,
+                                 int *__restrict__ pci, int *__restrict__ overflow) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int out[16];
+  int m = 0;
+  if (cf[i]) {
+    out[m++] = cidx[i];
+  } else if (geometric && gkind == 2) {
+    const int ix = i % nx, iy = i / nx;
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int jx = ix + dx, jy = iy + dy;
+        if (jx < 0 || jy < 0 || jx >= nx || jy >= ny) continue;
+        const int j = jy * nx + jx;
+        if (cf[j] && m < cap) out[m++] = cidx[j];
+      }
+  } else if (geometric && gkind == 1) {
+    if (i - 1 >= 0 && cf[i - 1] && m < cap) out[m++] = cidx[i - 1];
+    if (i + 1 < n && cf[i + 1] && m < cap) out[m++] = cidx[i + 1];
+  } else {
+    // keep the best `cap` candidates in a small array sorted by (score desc, j asc)
+    int bj[16], bs[16];
+    int nb = 0;
+    for (int k = grp[i]; k < grp[i + 1]; ++k) {
+      const int j = gci[k];
+      if (!cf[j]) continue;
+      const int sc = common_neighbours(grp, gci, i, j);
+      // insertion: j ascending within equal scores holds because neighbours
+      // are visited in ascending j and ties do not displace earlier entries
+      int pos = nb;
+      while (pos > 0 && bs[pos - 1] < sc) --pos;
+      if (pos >= cap) continue;
+      const int last = nb < cap ? nb : cap - 1;
+      for (int q = last; q > pos; --q) {
+        bj[q] = bj[q - 1];
+        bs[q] = bs[q - 1];
+      }
+      bj[pos] = j;
+      bs[pos] = sc;
+      if (nb < cap) ++nb;
+    }
+    for (int q = 0; q < nb; ++q) out[q] = cidx[bj[q]];
+    m = nb;
+    // ascending coarse index
+    for (int p = 1; p < m; ++p) {
+      const int v = out[p];
+      int q = p - 1;
+      while (q >= 0 && out[q] > v) {
+        out[q + 1] = out[q];
+        --q;
+      }
+      out[q + 1] = v;
+    }
+  }
+  if (FILL) {
+    const int p0 = prp[i];
+    for (int q = 0; q < m; ++q) pci[p0 + q] = out[q];
+  } else {
+    cnt[i] = m;
+  }
+}
+
+void interp_pattern(Pool &pool, const Level &L, int cap, int geometric, Csr &P, hipStream_t s) {
+  const int n = L.n;
+  if (cap > 16) fail(BAMG_E_ARG, "max_interp above 16");
+  int *cnt = pool.get<int>(n);
+  int *ovf = pool.get<int>(1);
+  fill_i32(ovf, 0, 1, s);
+  k_interp_pattern<false><<<ceil_div(n, 128), 128, 0, s>>>(
+      n, L.nx, L.ny, L.gkind, geometric, cap, L.cf, L.cidx, L.G.rp, L.G.ci, cnt, nullptr, nullptr,
+      ovf);
+  LAUNCHCHK();
+  P.nr = n;
+  P.nc = L.nc;
+  P.rp = pool.get<int>(n + 1);
+  scan_counts(pool, cnt, P.rp, n, s);
+  P.nnz = read_int(P.rp + n, s);
+  P.ci = pool.get<int>(P.nnz);
+  k_interp_pattern<true><<<ceil_div(n, 128), 128, 0, s>>>(
+      n, L.nx, L.ny, L.gkind, geometric, cap, L.cf, L.cidx, L.G.rp, L.G.ci, nullptr, P.rp, P.ci,
+      ovf);
+  LAUNCHCHK();
+  pool.release(cnt);
+  pool.release(ovf);
+}
+
+// ============================================================ SpGEMM symbolic
+// One wave (block of 64) per row of C = A * B: every product term appends
+// its column to an LDS buffer, the buffer is bitonic-sorted and the distinct
+// columns counted (pass 1) or written (pass 2). The result is the sorted
+// structural product, independent of thread timing.
+constexpr int kSymCap = 4096;
+
+template <bool FILL>
+__global__ void __launch_bounds__(64)
+    k_spgemm_sym(int nr, const int *__restrict__ arp, const int *__restrict__ aci,
+                 const int *__restrict__ brp, const int *__restrict__ bci, int force_diag,
+                 int *__restrict__ cnt, const int *__restrict__ crp, int *__restrict__ cci,
+                 int *__restrict__ overflow) {
+  __shared__ int buf[kSymCap];
+  __shared__ int nbuf;
+  const int row = blockIdx.x, lane = threadIdx.x;
+  if (row >= nr) return;
+  if (lane == 0) nbuf = 0;
+  __syncthreads();
+  if (force_diag && lane == 0) {
+    buf[0] = row;
+    nbuf = 1;
+  }
+  __syncthreads();
+  const int ab = arp[row], ae = arp[row + 1];
+  for (int a = ab + lane; a < ae; a += 64) {
+    const int k = aci[a];
+    for (int b = brp[k]; b < brp[k + 1]; ++b) {
+      const int pos = atomicAdd(&nbuf, 1);
+      if (pos < kSymCap) buf[pos] = bci[b];
+    }
+  }
+  __syncthreads();
+  int cntv = nbuf;
+  if (cntv > kSymCap) {
+    if (lane == 0) atomicOr(overflow, 1);
+    cntv = kSymCap;
+  }
+  int P2 = 1;
+  while (P2 < cntv) P2 <<= 1;
+  for (int i = cntv + lane; i < P2; i += 64) buf[i] = 0x7fffffff;
+  __syncthreads();
+  // bitonic sort of buf[0..P2)
+  for (int size = 2; size <= P2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = lane; i < (P2 >> 1); i += 64) {
+        const int lo = 2 * i - (i & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const int x = buf[lo], y = buf[hi];
+        if ((x > y) == up) {
+          buf[lo] = y;
+          buf[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // distinct values, written in order with a running count per 64-chunk
+  int base = 0;
+  const int out0 = FILL ? crp[row] : 0;
+  for (int c0 = 0; c0 < cntv; c0 += 64) {
+    const int i = c0 + lane;
+    const bool isnew = i < cntv && (i == 0 || buf[i] != buf[i - 1]);
+    const uint64_t mask = __ballot(isnew);
+    const int before = __popcll(mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+    if (FILL && isnew) cci[out0 + base + before] = buf[i];
+    base += __popcll(mask);
+  }
+  if (!FILL && lane == 0) cnt[row] = base;
+}
+
+void spgemm_symbolic(Pool &pool, const Csr &A, const Csr &B, int force_diag, Csr &C,
+                     hipStream_t s) {
+  const int nr = A.nr;
+  int *cnt = pool.get<int>(nr);
+  int *ovf = pool.get<int>(1);
+  fill_i32(ovf, 0, 1, s);
+  if (nr) {
+    k_spgemm_sym<false><<<nr, 64, 0, s>>>(nr, A.rp, A.ci, B.rp, B.ci, force_diag, cnt, nullptr,
+                                          nullptr, ovf);
+    LAUNCHCHK();
+  }
+  if (read_int(ovf, s)) fail(BAMG_E_ARG, "Galerkin row wider than the symbolic buffer");
+  C.nr = nr;
+  C.nc = B.nc;
+  C.rp = pool.get<int>(nr + 1);
+  scan_counts(pool, cnt, C.rp, nr, s);
+  C.nnz = read_int(C.rp + nr, s);
+  C.ci = pool.get<int>(C.nnz);
+  if (nr) {
+    k_spgemm_sym<true><<<nr, 64, 0, s>>>(nr, A.rp, A.ci, B.rp, B.ci, force_diag, nullptr, C.rp,
+                                         C.ci, ovf);
+    LAUNCHCHK();
+  }
+  pool.release(cnt);
+  pool.release(ovf);
+}
+
+// ============================================================ SpGEMM numeric
+// One thread per row of C: terms are added in the order (A column, B column)
+// ascending, each at the position of its column in the sorted row of C.
+template <class T>
+__global__ void k_spgemm_num(int nr, const int *__restrict__ arp, const int *__restrict__ aci,
+                             const T *__restrict__ av, const int *__restrict__ brp,
+                             const int *__restrict__ bci, const T *__restrict__ bv,
+                             const int *__restrict__ crp, const int *__restrict__ cci,
+                             T *__restrict__ cv) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nr) return;
+  const int c0 = crp[i], c1 = crp[i + 1];
+  for (int p = c0; p < c1; ++p) cv[p] = (T)0;
+  for (int a = arp[i]; a < arp[i + 1]; ++a) {
+    const int k = aci[a];
+    const T x = av[a];
+    for (int b = brp[k]; b < brp[k + 1]; ++b) {
+      const int j = bci[b];
+      int lo = c0, hi = c1 - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cci[mid] < j)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      cv[lo] += x * bv[b];
+    }
+  }
+}
+
+template <class T>
+void spgemm_numeric(const Csr &A, const T *av, const Csr &B, const T *bv, const Csr &C, T *cv,
+                    hipStream_t s) {
+  if (!A.nr) return;
+  k_spgemm_num<T><<<ceil_div(A.nr, 128), 128, 0, s>>>(A.nr, A.rp, A.ci, av, B.rp, B.ci, bv, C.rp,
+                                                      C.ci, cv);
+  LAUNCHCHK();
+}
+
+// ============================================================ LS fits
+constexpr int kRMax = 16, kMMax = 8;
+
+// Householder least squares on the columns listed in idx[0..na): minimise
+// || G[:, idx] p - g || over rows [row0, rows). A column whose |R_tt| falls
+// to 1e-12 max|R_ss| or below is removed from idx and the fit redone.
+// Returns the number of columns kept; p[t] for t < na afterwards.
+__device__ int ls_qr(double (&G)[kRMax][kMMax], const double (&g)[kRMax], int row0, int rows,
+                     int (&idx)[kMMax], int na, double (&p)[kMMax]) {
+  for (;;) {
+    if (na == 0) return 0;
+    double W[kRMax][kMMax], h[kRMax], R[kMMax];
+    const int nrow = rows - row0;
+    for (int k = 0; k < nrow; ++k) {
+      for (int a = 0; a < na; ++a) W[k][a] = G[row0 + k][idx[a]];
+      h[k] = g[row0 + k];
+    }
+    const int nq = na < nrow ? na : nrow;
+    for (int a = 0; a < nq; ++a) {
+      double nrm = 0.0;
+      for (int k = a; k < nrow; ++k) nrm += W[k][a] * W[k][a];
+      nrm = sqrt(nrm);
+      const double x0 = W[a][a];
+      const double alpha = x0 >= 0 ? -nrm : nrm;
+      R[a] = alpha;
+      if (nrm == 0.0) continue;
+      W[a][a] = x0 - alpha;
+      double vtv = 0.0;
+      for (int k = a; k < nrow; ++k) vtv += W[k][a] * W[k][a];
+      if (vtv == 0.0) continue;
+      for (int b = a + 1; b < na; ++b) {
+        double s = 0.0;
+        for (int k = a; k < nrow; ++k) s += W[k][a] * W[k][b];
+        s = 2.0 * s / vtv;
+        for (int k = a; k < nrow; ++k) W[k][b] -= s * W[k][a];
+      }
+      double s = 0.0;
+      for (int k = a; k < nrow; ++k) s += W[k][a] * h[k];
+      s = 2.0 * s / vtv;
+      for (int k = a; k < nrow; ++k) h[k] -= s * W[k][a];
+    }
+    // columns beyond the number of rows cannot be determined: drop them
+    if (na > nrow) {
+      na = nrow;
+      continue;
+    }
+    double rmax = 0.0;
+    for (int a = 0; a < na; ++a) rmax = fmax(rmax, fabs(R[a]));
+    int drop = -1;
+    for (int a = 0; a < na; ++a)
+      if (!(fabs(R[a]) > 1e-12 * rmax)) {
+        drop = a;
+        break;
+      }
+    if (drop >= 0) {
+      for (int a = drop; a + 1 < na; ++a) idx[a] = idx[a + 1];
+      --na;
+      continue;
+    }
+    for (int a = na - 1; a >= 0; --a) {
+      double s = h[a];
+      for (int b = a + 1; b < na; ++b) s -= W[a][b] * p[b];
+      p[a] = s / R[a];
+    }
+    return na;
+  }
+}
+
+// One weighted fit over the active points act[]: plain (sum1 = false, rows
+// k = 0..r-1) or with sum-to-one (rows k = 1..r-1, last active point
+// eliminated). Writes coef[0..m) (0 for inactive points).
+__device__ void fit_active(const double (&Gr)[kRMax][kMMax], const double (&gr)[kRMax],
+                           const double *__restrict__ w, int r, int m, bool sum1,
+                           const bool (&act)[kMMax], double (&coef)[kMMax]) {
+  int ids[kMMax];
+  int na = 0;
+  for (int t = 0; t < m; ++t) {
+    coef[t] = 0.0;
+    if (act[t]) ids[na++] = t;
+  }
+  if (na == 0) return;
+  double G[kRMax][kMMax], g[kRMax], p[kMMax];
+  if (!sum1) {
+    for (int k = 0; k < r; ++k) {
+      const double sw = sqrt(w[k]);
+      for (int a = 0; a < na; ++a) G[k][a] = sw * Gr[k][ids[a]];
+      g[k] = sw * gr[k];
+    }
+    int cols[kMMax];
+    for (int a = 0; a < na; ++a) cols[a] = a;
+    const int kept = ls_qr(G, g, 0, r, cols, na, p);
+    for (int a = 0; a < kept; ++a) coef[ids[cols[a]]] = p[a];
+    return;
+  }
+  if (na == 1) {
+    coef[ids[0]] = 1.0;
+    return;
+  }
+  const int last = ids[na - 1], mm = na - 1;
+  for (int k = 1; k < r; ++k) {
+    const double sw = sqrt(w[k]);
+    const double lv = Gr[k][last];
+    for (int a = 0; a < mm; ++a) G[k][a] = sw * (Gr[k][ids[a]] - lv);
+    g[k] = sw * (gr[k] - lv);
+  }
+  int cols[kMMax];
+  for (int a = 0; a < mm; ++a) cols[a] = a;
+  for (int a = 0; a < mm; ++a) p[a] = 0.0;
+  const int kept = ls_qr(G, g, 1, r, cols, mm, p);
+  double sum = 0.0;
+  for (int a = 0; a < kept; ++a) {
+    coef[ids[cols[a]]] = p[a];
+    sum += p[a];
+  }
+  coef[last] = 1.0 - sum;
+}
+
+// rule 1: while a weight is negative, remove the most negative point and
+// refit (at least one point stays).
+__device__ void fit_point(const double (&G)[kRMax][kMMax], const double (&g)[kRMax],
+                          const double *__restrict__ w, int r, int m, bool sum1, int rule,
+                          double (&coef)[kMMax]) {
+  bool act[kMMax];
+  for (int t = 0; t < kMMax; ++t) act[t] = t < m;
+  int na = m;
+  for (;;) {
+    fit_active(G, g, w, r, m, sum1, act, coef);
+    if (rule == 0 || na == 1) return;
+    int worst = -1;
+    for (int t = 0; t < m; ++t)
+      if (act[t] && coef[t] < 0.0 && (worst < 0 || coef[t] < coef[worst])) worst = t;
+    if (worst < 0) return;
+    act[worst] = false;
+    --na;
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(64)
+    k_ls_fit(int n, int r, const int *__restrict__ cf, const int *__restrict__ prp,
+             const int *__restrict__ pci, const int *__restrict__ cpts, const T *__restrict__ U,
+             const T *__restrict__ V, const double *__restrict__ wv,
+             const double *__restrict__ wu, int rule, T *__restrict__ Pv, T *__restrict__ Qtv) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int a0 = prp[i];
+  if (cf[i]) {
+    Pv[a0] = (T)1;
+    Qtv[a0] = (T)1;
+    return;
+  }
+  const int m = prp[i + 1] - a0;
+  int jf[kMMax];
+  for (int t = 0; t < m; ++t) jf[t] = cpts[pci[a0 + t]];
+  double G[kRMax][kMMax], g[kRMax], coef[kMMax];
+  for (int k = 0; k < r; ++k) {
+    for (int t = 0; t < m; ++t) G[k][t] = (double)V[(size_t)jf[t] * r + k];
+    g[k] = (double)V[(size_t)i * r + k];
+  }
+  fit_point(G, g, wv, r, m, false, rule, coef);
+  for (int t = 0; t < m; ++t) Pv[a0 + t] = (T)coef[t];
+  for (int k = 0; k < r; ++k) {
+    for (int t = 0; t < m; ++t) G[k][t] = (double)U[(size_t)jf[t] * r + k];
+    g[k] = (double)U[(size_t)i * r + k];
+  }
+  fit_point(G, g, wu, r, m, true, rule, coef);
+  for (int t = 0; t < m; ++t) Qtv[a0 + t] = (T)coef[t];
+}
+
+template <class T>
+void ls_fit(const Level &L, int r, const T *U, const T *V, const double *wv, const double *wu,
+            int rule, T *Pv, T *Qtv, hipStream_t s) {
+  if (r > kRMax) fail(BAMG_E_ARG, "r above 16");
+  k_ls_fit<T><<<ceil_div(L.n, 64), 64, 0, s>>>(L.n, r, L.cf, L.P.rp, L.P.ci, L.cpts, U, V, wv, wu,
+                                               rule, Pv, Qtv);
+  LAUNCHCHK();
+}
+
+template <class T>
+__global__ void k_fill_transfer_identity(int n, const int *__restrict__ cf,
+                                         const int *__restrict__ prp, T *__restrict__ Pv,
+                                         T *__restrict__ Qtv) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int a0 = prp[i], m = prp[i + 1] - a0;
+  for (int t = 0; t < m; ++t) {
+    Pv[a0 + t] = cf[i] ? (T)1 : (T)(1.0 / m);
+    Qtv[a0 + t] = cf[i] ? (T)1 : (T)(1.0 / m);
+  }
+}
+
+template <class T>
+void fill_transfer_identity(const Level &L, T *Pv, T *Qtv, hipStream_t s) {
+  k_fill_transfer_identity<T><<<ceil_div(L.n, 256), 256, 0, s>>>(L.n, L.cf, L.P.rp, Pv, Qtv);
+  LAUNCHCHK();
+}
+
+// ============================================================ small helpers
+template <class T>
+__global__ void k_dinv(int n, const int *__restrict__ dpos, const T *__restrict__ bv,
+                       T *__restrict__ dinv, int *__restrict__ flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int p = dpos[i];
+  const T d = p >= 0 ? bv[p] : (T)0;
+  if (!(d != (T)0) || !isfinite((double)d)) {
+    atomicOr(flag, 1);
+    dinv[i] = (T)0;
+  } else {
+    dinv[i] = (T)1 / d;
+  }
+}
+
+template <class T>
+void dinv_from_diag(const Level &L, const T *bv, T *dinv, int *flag, hipStream_t s) {
+  fill_i32(flag, 0, 1, s);
+  k_dinv<T><<<ceil_div(L.n, 256), 256, 0, s>>>(L.n, L.dpos, bv, dinv, flag);
+  LAUNCHCHK();
+  if (read_int(flag, s)) fail(BAMG_E_BAD_DIAG, "zero or non-finite diagonal in some B_l");
+}
+
+template <class T>
+__global__ void k_inject(const int *__restrict__ cpts, int nc, int r, const T *__restrict__ X,
+                         T *__restrict__ Xc) {
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)nc * r) return;
+  const int a = (int)(idx / r), k = (int)(idx % r);
+  Xc[idx] = X[(size_t)cpts[a] * r + k];
+}
+
+template <class T>
+void inject(const int *cpts, int nc, int r, const T *X, T *Xc, hipStream_t s) {
+  long tot = (long)nc * r;
+  if (!tot) return;
+  k_inject<T><<<ceil_div(tot, 256), 256, 0, s>>>(cpts, nc, r, X, Xc);
+  LAUNCHCHK();
+}
+
+// Y = A X, r columns row-major; thread per (row, column)
+template <class T>
+__global__ void k_spmm(int nr, int r, const int *__restrict__ rp, const int *__restrict__ ci,
+                       const T *__restrict__ av, const T *__restrict__ X, T *__restrict__ Y,
+                       int reset0) {
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)nr * r) return;
+  const int i = (int)(idx / r), k = (int)(idx % r);
+  if (reset0 && k == 0) {
+    Y[idx] = (T)1;
+    return;
+  }
+  T s = 0;
+  for (int a = rp[i]; a < rp[i + 1]; ++a) s += av[a] * X[(size_t)ci[a] * r + k];
+  Y[idx] = s;
+}
+
+template <class T>
+void spmm(const Csr &A, const T *av, int r, const T *X, T *Y, int reset0, hipStream_t s) {
+  long tot = (long)A.nr * r;
+  if (!tot) return;
+  k_spmm<T><<<ceil_div(tot, 256), 256, 0, s>>>(A.nr, r, A.rp, A.ci, av, X, Y, reset0);
+  LAUNCHCHK();
+}
+
+// ============================================================ relaxation
+// One simultaneous weighted-Jacobi step on all test vectors (Algorithm 1):
+//   v_k <- v_k + omega D^-1 (sigma_k M u_k - B v_k)
+//   u_k <- u_k + omega D^-1 (sigma_k N v_k - B^T u_k)     (k >= 1)
+// with the sigma terms dropped for the homogeneous first pass. Both
+// right-hand sides use the old vectors. Thread per (row, column).
+template <class T>
+__global__ void k_relax_pairs(int n, int r, const int *__restrict__ brp,
+                              const int *__restrict__ bci, const T *__restrict__ bv,
+                              const int *__restrict__ trp, const int *__restrict__ tci,
+                              const T *__restrict__ tv, const int *__restrict__ mrp,
+                              const int *__restrict__ mci, const T *__restrict__ mv,
+                              const T *__restrict__ nv, int identity_mn,
+                              const T *__restrict__ dinv, T omega, int with_rhs,
+                              const double *__restrict__ sigma, const T *__restrict__ U,
+                              const T *__restrict__ V, T *__restrict__ Uo, T *__restrict__ Vo) {
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)n * r) return;
+  const int i = (int)(idx / r), k = (int)(idx % r);
+  const T di = dinv[i];
+  T bvk = 0;
+  for (int a = brp[i]; a < brp[i + 1]; ++a) bvk += bv[a] * V[(size_t)bci[a] * r + k];
+  T rhs_v = 0, rhs_u = 0;
+  if (with_rhs) {
+    const T sg = (T)sigma[k];
+    T mu = 0, nvv = 0;
+    if (identity_mn) {
+      mu = U[idx];
+      nvv = V[idx];
+    } else {
+      for (int a = mrp[i]; a < mrp[i + 1]; ++a) {
+        const size_t j = (size_t)mci[a] * r + k;
+        mu += mv[a] * U[j];
+        nvv += nv[a] * V[j];
+      }
+    }
+    rhs_v = sg * mu;
+    rhs_u = sg * nvv;
+  }
+  Vo[idx] = V[idx] + omega * di * (rhs_v - bvk);
+  if (k == 0) {
+    Uo[idx] = U[idx];
+    return;
+  }
+  T btu = 0;
+  for (int a = trp[i]; a < trp[i + 1]; ++a) btu += tv[a] * U[(size_t)tci[a] * r + k];
+  Uo[idx] = U[idx] + omega * di * (rhs_u - btu);
+}
+
+template <class T>
+void relax_pairs(const Level &L, int r, T omega, int with_rhs, const double *sigma, const T *U,
+                 const T *V, T *Uo, T *Vo, hipStream_t s) {
+  long tot = (long)L.n * r;
+  k_relax_pairs<T><<<ceil_div(tot, 256), 256, 0, s>>>(
+      L.n, r, L.B.rp, L.B.ci, (const T *)L.Bv, L.Bt.rp, L.Bt.ci, (const T *)L.Btv, L.M.rp, L.M.ci,
+      (const T *)L.Mv, (const T *)L.Nv, L.identity_mn ? 1 : 0, (const T *)L.dinv, omega, with_rhs,
+      sigma, U, V, Uo, Vo);
+  LAUNCHCHK();
+}
+
+// Per-block partial sums, FP64, deterministic order. For each column k:
+//   q0 = u.B v, q1 = u.M u, q2 = v.N v, q3 = |B v|^2, q4 = |B^T u|^2
+// `which` bit 0: q0..q2, bit 1: q3, q4. Lanes of a 16-lane group are the
+// columns; a block of 256 threads covers 16 rows per step.
+constexpr int kPPThreads = 256, kPPLanes = 16;
+
+template <class T>
+__global__ void __launch_bounds__(kPPThreads)
+    k_pair_products(int n, int r, const int *__restrict__ brp, const int *__restrict__ bci,
+                    const T *__restrict__ bv, const int *__restrict__ trp,
+                    const int *__restrict__ tci, const T *__restrict__ tv,
+                    const int *__restrict__ mrp, const int *__restrict__ mci,
+                    const T *__restrict__ mv, const T *__restrict__ nv, int identity_mn,
+                    const T *__restrict__ U, const T *__restrict__ V, int which,
+                    double *__restrict__ part) {
+  __shared__ double sh[kPPThreads / kWave][5][kPPLanes];
+  const int k = threadIdx.x % kPPLanes;
+  const int rowoff = threadIdx.x / kPPLanes;  // 0..15
+  double q[5] = {0, 0, 0, 0, 0};
+  if (k < r) {
+    for (long i = (long)blockIdx.x * (kPPThreads / kPPLanes) + rowoff; i < n;
+         i += (long)gridDim.x * (kPPThreads / kPPLanes)) {
+      const size_t ik = (size_t)i * r + k;
+      const double u = (double)U[ik], v = (double)V[ik];
+      double b = 0.0;
+      for (int a = brp[i]; a < brp[i + 1]; ++a) b += (double)bv[a] * (double)V[(size_t)bci[a] * r + k];
+      if (which & 1) {
+        double mu = 0.0, nvv = 0.0;
+        if (identity_mn) {
+          mu = u;
+          nvv = v;
+        } else {
+          for (int a = mrp[i]; a < mrp[i + 1]; ++a) {
+            const size_t j = (size_t)mci[a] * r + k;
+            mu += (double)mv[a] * (double)U[j];
+            nvv += (double)nv[a] * (double)V[j];
+          }
+        }
+        q[0] += u * b;
+        q[1] += u * mu;
+        q[2] += v * nvv;
+      }
+      if (which & 2) {
+        double bt = 0.0;
+        for (int a = trp[i]; a < trp[i + 1]; ++a)
+          bt += (double)tv[a] * (double)U[(size_t)tci[a] * r + k];
+        q[3] += b * b;
+        q[4] += bt * bt;
+      }
+    }
+  }
+  // lanes l, l^16, l^32, l^48 of a wave share the column k
+#pragma unroll
+  for (int t = 0; t < 5; ++t) {
+    double x = q[t];
+    x += __shfl_xor(x, 16, kWave);
+    x += __shfl_xor(x, 32, kWave);
+    q[t] = x;
+  }
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  if (l < kPPLanes)
+    for (int t = 0; t < 5; ++t) sh[w][t][l] = q[t];
+  __syncthreads();
+  if (threadIdx.x < 5 * kPPLanes) {
+    const int t = threadIdx.x / kPPLanes, kk = threadIdx.x % kPPLanes;
+    double s = 0.0;
+    for (int ww = 0; ww < kPPThreads / kWave; ++ww) s += sh[ww][t][kk];
+    part[(size_t)blockIdx.x * 5 * kPPLanes + t * kPPLanes + kk] = s;
+  }
+}
+
+template <class T>
+void pair_products(const Level &L, int r, const T *U, const T *V, int which, double *part,
+                   int nblk, hipStream_t s) {
+  if (r > kPPLanes) fail(BAMG_E_ARG, "r above 16");
+  k_pair_products<T><<<nblk, kPPThreads, 0, s>>>(
+      L.n, r, L.B.rp, L.B.ci, (const T *)L.Bv, L.Bt.rp, L.Bt.ci, (const T *)L.Btv, L.M.rp, L.M.ci,
+      (const T *)L.Mv, (const T *)L.Nv, L.identity_mn ? 1 : 0, U, V, which, part);
+  LAUNCHCHK();
+}
+
+// out[t*16 + k] = sum over blocks, in block order
+__global__ void k_finalize_products(const double *__restrict__ part, int nblk,
+                                    double *__restrict__ out) {
+  const int t = threadIdx.x;  // 0..79
+  if (t >= 5 * kPPLanes) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * 5 * kPPLanes + t];
+  out[t] = s;
+}
+
+void finalize_products(const double *part, int nblk, int r, double *out, hipStream_t s) {
+  (void)r;
+  k_finalize_products<<<1, 5 * kPPLanes, 0, s>>>(part, nblk, out);
+  LAUNCHCHK();
+}
+
+__global__ void k_sigma(const double *__restrict__ q, int r, double *__restrict__ sigma) {
+  const int k = threadIdx.x;
+  if (k >= r) return;
+  const double den = sqrt(q[1 * kPPLanes + k] * q[2 * kPPLanes + k]);
+  sigma[k] = den > 0.0 ? q[k] / den : 0.0;
+}
+void sigma_from_products(const double *prod, int r, double *sigma, hipStream_t s) {
+  k_sigma<<<1, 64, 0, s>>>(prod, r, sigma);
+  LAUNCHCHK();
+}
+
+// scales[k] for V (from v.N v), scales[16 + k] for U (from u.M u, k >= 1)
+__global__ void k_norm_scales(const double *__restrict__ q, int r, double *__restrict__ sc) {
+  const int k = threadIdx.x;
+  if (k >= r) return;
+  const double vv = q[2 * kPPLanes + k], uu = q[1 * kPPLanes + k];
+  sc[k] = vv > 0.0 ? 1.0 / sqrt(vv) : 1.0;
+  sc[kPPLanes + k] = (k > 0 && uu > 0.0) ? 1.0 / sqrt(uu) : 1.0;
+}
+void norm_scales(const double *prod, int r, double *scales, hipStream_t s) {
+  k_norm_scales<<<1, 64, 0, s>>>(prod, r, scales);
+  LAUNCHCHK();
+}
+
+// omega_k = 1/||B v_k||^2 divided by the largest; same for u_k with B^T, k >= 1
+__global__ void k_ls_weights(const double *__restrict__ q, int r, double *__restrict__ wv,
+                             double *__restrict__ wu) {
+  if (threadIdx.x != 0) return;
+  const double tiny = 2.2250738585072014e-308;
+  double minv = INFINITY, minu = INFINITY;
+  double a[kPPLanes], b[kPPLanes];
+  for (int k = 0; k < r; ++k) {
+    a[k] = fmax(q[3 * kPPLanes + k], tiny);
+    minv = fmin(minv, a[k]);
+    b[k] = fmax(q[4 * kPPLanes + k], tiny);
+    if (k > 0) minu = fmin(minu, b[k]);
+  }
+  for (int k = 0; k < r; ++k) {
+    wv[k] = minv / a[k];
+    wu[k] = k > 0 ? minu / b[k] : 0.0;
+  }
+}
+void ls_weights(const double *prod, int r, double *wv, double *wu, hipStream_t s) {
+  k_ls_weights<<<1, 64, 0, s>>>(prod, r, wv, wu);
+  LAUNCHCHK();
+}
+
+template <class T>
+__global__ void k_scale_columns(T *__restrict__ X, int n, int r, const double *__restrict__ sc,
+                                int skip0) {
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)n * r) return;
+  const int k = (int)(idx % r);
+  if (skip0 && k == 0) return;
+  X[idx] = (T)((double)X[idx] * sc[k]);
+}
+template <class T>
+void scale_columns(T *X, int n, int r, const double *scale, int skip0, hipStream_t s) {
+  long tot = (long)n * r;
+  if (!tot) return;
+  k_scale_columns<T><<<ceil_div(tot, 256), 256, 0, s>>>(X, n, r, scale, skip0);
+  LAUNCHCHK();
+}
+
+// ============================================================ Kaczmarz colouring
+// Greedy distance-2 colouring of the rows in decreasing priority (key, i),
+// key the first Philox word of counter (i, 0, 3, 0), key (0x4b41435a, 0):
+// rows sharing a column get different colours. Computed in rounds: a row
+// whose conflicting uncoloured rows all have lower priority takes the
+// smallest colour unused by its coloured conflicts; this reproduces the
+// sequential greedy order.
+__global__ void k_col_keys(int n, uint64_t *__restrict__ key, int *__restrict__ colour) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  key[i] = philox_word0((uint64_t)i, 0, 3, 0, 0x4b41435aULL, 0);
+  colour[i] = -1;
+}
+
+__global__ void k_col_round(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                            const int *__restrict__ crp, const int *__restrict__ cci,
+                            const uint64_t *__restrict__ key, const int *__restrict__ colour_in,
+                            int *__restrict__ colour_out, int *__restrict__ remaining) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  if (colour_in[v] >= 0) {
+    colour_out[v] = colour_in[v];
+    return;
+  }
+  const uint64_t kv = key[v];
+  uint64_t used_lo = 0, used_hi = 0;  // colours 0..127
+  for (int a = rp[v]; a < rp[v + 1]; ++a) {
+    const int j = ci[a];
+    for (int b = crp[j]; b < crp[j + 1]; ++b) {
+      const int w = cci[b];
+      if (w == v) continue;
+      const int cw = colour_in[w];
+      if (cw < 0) {
+        const uint64_t kw = key[w];
+        if (kw > kv || (kw == kv && w > v)) {
+          colour_out[v] = -1;
+          atomicAdd(remaining, 1);
+          return;
+        }
+      } else if (cw < 64) {
+        used_lo |= 1ull << cw;
+      } else if (cw < 128) {
+        used_hi |= 1ull << (cw - 64);
+      }
+    }
+  }
+  int c = 0;
+  if (~used_lo)
+    c = __ffsll((long long)~used_lo) - 1;
+  else if (~used_hi)
+    c = 64 + __ffsll((long long)~used_hi) - 1;
+  else
+    c = 128;
+  colour_out[v] = c;
+}
+
+__global__ void k_count_colour(const int *__restrict__ colour, int n, int *__restrict__ cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicAdd(&cnt[colour[i]], 1);
+}
+
+__global__ void k_order_by_colour(const int *__restrict__ colour, int n,
+                                  const int *__restrict__ off, int *__restrict__ order) {
+  // stable: thread-per-colour scan over rows keeps rows ascending within a colour
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  int p = off[c];
+  for (int i = 0; i < n; ++i)
+    if (colour[i] == c) order[p++] = i;
+}
+
+void row_colouring(Pool &pool, const Csr &A, const Csr &At, int *colour, int &ncol, int *&order,
+                   std::vector<int> &offsets, hipStream_t s) {
+  const int n = A.nr;
+  uint64_t *key = pool.get<uint64_t>(n);
+  int *tmp = pool.get<int>(n);
+  int *rem = pool.get<int>(1);
+  k_col_keys<<<ceil_div(n, 256), 256, 0, s>>>(n, key, colour);
+  LAUNCHCHK();
+  int *cin = colour, *cout = tmp;
+  for (int round = 0;; ++round) {
+    if (round > n + 1) fail(BAMG_E_DEVICE, "colouring did not terminate");
+    fill_i32(rem, 0, 1, s);
+    k_col_round<<<ceil_div(n, 256), 256, 0, s>>>(n, A.rp, A.ci, At.rp, At.ci, key, cin, cout, rem);
+    LAUNCHCHK();
+    std::swap(cin, cout);
+    if (read_int(rem, s) == 0) break;
+  }
+  if (cin != colour)
+    HIPCHK(hipMemcpyAsync(colour, cin, sizeof(int) * n, hipMemcpyDeviceToDevice, s));
+  // number of colours
+  int *cnt = pool.get<int>(130);
+  fill_i32(cnt, 0, 130, s);
+  k_count_colour<<<ceil_div(n, 256), 256, 0, s>>>(colour, n, cnt);
+  LAUNCHCHK();
+  std::vector<int> hc(130);
+  HIPCHK(hipMemcpyAsync(hc.data(), cnt, sizeof(int) * 130, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hc[128] || hc[129]) fail(BAMG_E_ARG, "more than 128 colours in the Kaczmarz colouring");
+  ncol = 0;
+  for (int c = 0; c < 128; ++c)
+    if (hc[c]) ncol = c + 1;
+  offsets.assign(ncol + 1, 0);
+  for (int c = 0; c < ncol; ++c) offsets[c + 1] = offsets[c] + hc[c];
+  int *doff = pool.get<int>(ncol + 1);
+  HIPCHK(hipMemcpyAsync(doff, offsets.data(), sizeof(int) * (ncol + 1), hipMemcpyHostToDevice, s));
+  order = pool.get<int>(n);
+  k_order_by_colour<<<1, ncol, 0, s>>>(colour, n, doff, order);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(s));
+  pool.release(key);
+  pool.release(tmp);
+  pool.release(rem);
+  pool.release(cnt);
+  pool.release(doff);
+}
+
+template <class T>
+__global__ void k_row_inv_norms(int n, const int *__restrict__ rp, const T *__restrict__ v,
+                                T *__restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int a = rp[i]; a < rp[i + 1]; ++a) s += (double)v[a] * (double)v[a];
+  out[i] = (T)(s > 0.0 ? 1.0 / s : 0.0);
+}
+template <class T>
+void row_inv_norms(const Csr &A, const T *val, T *out, hipStream_t s) {
+  k_row_inv_norms<T><<<ceil_div(A.nr, 256), 256, 0, s>>>(A.nr, A.rp, val, out);
+  LAUNCHCHK();
+}
+
+#define INST(T)                                                                              \
+  template void spgemm_numeric<T>(const Csr &, const T *, const Csr &, const T *, const Csr &, \
+                                  T *, hipStream_t);                                         \
+  template void fill_transfer_identity<T>(const Level &, T *, T *, hipStream_t);             \
+  template void ls_fit<T>(const Level &, int, const T *, const T *, const double *,          \
+                          const double *, int, T *, T *, hipStream_t);                       \
+  template void dinv_from_diag<T>(const Level &, const T *, T *, int *, hipStream_t);               \
+  template void inject<T>(const int *, int, int, const T *, T *, hipStream_t);               \
+  template void spmm<T>(const Csr &, const T *, int, const T *, T *, int, hipStream_t);      \
+  template void relax_pairs<T>(const Level &, int, T, int, const double *, const T *,        \
+                               const T *, T *, T *, hipStream_t);                            \
+  template void pair_products<T>(const Level &, int, const T *, const T *, int, double *,    \
+                                 int, hipStream_t);                                          \
+  template void scale_columns<T>(T *, int, int, const double *, int, hipStream_t);           \
+  template void row_inv_norms<T>(const Csr &, const T *, T *, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace bamg

@@ -1,0 +1,427 @@
+// Host orchestration of bamg_setup: validation and B = I - A (Section 2),
+// the integer structure of the hierarchy, the bootstrap cycles (Algorithm 1
+// with the Markov-chain constraint of Section 5), the coarsest
+// pseudo-inverse and x0 (Section 6). Every numeric step is a kernel launch on
+// the handle's stream; the host only reads back sizes and status flags.
+#include <algorithm>
+#include <cmath>
+
+#include "bamg_internal.h"
+#include "device_common.h"
+
+namespace bamg {
+
+namespace {
+
+template <class T>
+struct Setup {
+  bamg_handle *h;
+  hipStream_t s;
+  int r;
+  // reduction scratch
+  double *part = nullptr, *prod = nullptr, *wv = nullptr, *wu = nullptr, *scales = nullptr;
+  int nblk = 0;
+  int *flag = nullptr;
+  // coarsest dense work
+  int nL = 0;
+  double *Bd = nullptr, *Md = nullptr, *Nd = nullptr, *X = nullptr, *W = nullptr, *J = nullptr;
+  double *sv = nullptr, *work = nullptr;
+
+  Pool &pool() { return h->pool; }
+
+  void swap_uv(Level &L) {
+    std::swap(L.U, L.U2);
+    std::swap(L.V, L.V2);
+  }
+
+  void products(Level &L, int which) {
+    pair_products<T>(L, r, (const T *)L.U, (const T *)L.V, which, part, nblk, s);
+    finalize_products(part, nblk, r, prod, s);
+  }
+
+  // nu_setup smoothing steps of Algorithm 1 on the test-vector pairs
+  void relax(Level &L, int with_rhs) {
+    const T om = (T)h->opt.omega;
+    for (int it = 0; it < h->opt.nu_setup; ++it) {
+      if (h->opt.smoother == BAMG_SMOOTH_KACZMARZ) {
+        relax_kaczmarz(L, with_rhs);
+      } else {
+        relax_pairs<T>(L, r, om, with_rhs, h->sigma, (const T *)L.U, (const T *)L.V, (T *)L.U2,
+                       (T *)L.V2, s);
+        swap_uv(L);
+      }
+      if (with_rhs) {
+        products(L, 1);
+        sigma_from_products(prod, r, h->sigma, s);
+      }
+    }
+  }
+
+  // Kaczmarz variant: right-hand sides sigma M u / sigma N v are formed from
+  // the old vectors (kept in U2/V2 as copies), then each column is swept in
+  // colour order in place.
+  void relax_kaczmarz(Level &L, int with_rhs) {
+    const size_t nr = (size_t)L.n * r;
+    T *rhsV = (T *)L.U2, *rhsU = (T *)L.V2;  // scratch: n x r each
+    if (with_rhs) {
+      const void *mv = L.Mv, *nv = L.Nv;
+      spmm<T>(L.M, (const T *)mv, r, (const T *)L.U, rhsV, 0, s);
+      spmm<T>(L.M, (const T *)nv, r, (const T *)L.V, rhsU, 0, s);
+      scale_columns<T>(rhsV, L.n, r, h->sigma, 0, s);
+      scale_columns<T>(rhsU, L.n, r, h->sigma, 0, s);
+    } else {
+      fill<T>(rhsV, (T)0, nr, s);
+      fill<T>(rhsU, (T)0, nr, s);
+    }
+    kaczmarz_block(L, rhsV, (T *)L.V, false, 0);
+    kaczmarz_block(L, rhsU, (T *)L.U, true, 1);
+  }
+
+  // sweep every column of X (n x r, row-major) in place on B_l or B_l^T
+  void kaczmarz_block(Level &L, const T *rhs, T *X, bool transpose, int k0) {
+    T *x = (T *)L.tb, *b = (T *)L.rb;
+    for (int k = k0; k < r; ++k) {
+      column_get(X, L.n, r, k, x);
+      column_get(rhs, L.n, r, k, b);
+      const Csr &A = transpose ? L.Bt : L.B;
+      const T *val = (const T *)(transpose ? L.Btv : L.Bv);
+      const T *ri = (const T *)(transpose ? L.rowinvBt : L.rowinvB);
+      const int *ord = transpose ? L.ordBt : L.ordB;
+      const std::vector<int> &off = transpose ? L.offBt : L.offB;
+      for (size_t c = 0; c + 1 < off.size(); ++c)
+        kaczmarz_colour<T>(A, val, ri, ord + off[c], off[c + 1] - off[c], b, x, s);
+      column_set(X, L.n, r, k, x);
+    }
+  }
+
+  void column_get(const T *X, int n, int r_, int k, T *out);
+  void column_set(T *X, int n, int r_, int k, const T *in);
+
+  void normalize(Level &L) {
+    products(L, 1);
+    norm_scales(prod, r, scales, s);
+    scale_columns<T>((T *)L.V, L.n, r, scales, 0, s);
+    scale_columns<T>((T *)L.U, L.n, r, scales + 16, 1, s);
+  }
+
+  void weights(Level &L) {
+    products(L, 2);
+    ls_weights(prod, r, wv, wu, s);
+  }
+
+  void galerkin(int l) {
+    Level &L = h->lv[l];
+    Level &C = h->lv[l + 1];
+    copy_permuted<T>((T *)L.Ptv, (const T *)L.Pv, L.pcperm, L.P.nnz, s);
+    copy_permuted<T>((T *)L.Qv, (const T *)L.Qtv, L.pcperm, L.P.nnz, s);
+    spgemm_numeric<T>(L.B, (const T *)L.Bv, L.P, (const T *)L.Pv, L.T1, (T *)L.T1v, s);
+    spgemm_numeric<T>(L.Pc, (const T *)L.Qv, L.T1, (const T *)L.T1v, C.B, (T *)C.Bv, s);
+    spgemm_numeric<T>(L.M, (const T *)L.Mv, L.P, (const T *)L.Qtv, L.T2, (T *)L.T2v, s);
+    spgemm_numeric<T>(L.Pc, (const T *)L.Qv, L.T2, (const T *)L.T2v, C.M, (T *)C.Mv, s);
+    spgemm_numeric<T>(L.M, (const T *)L.Nv, L.P, (const T *)L.Pv, L.T2, (T *)L.T3v, s);
+    spgemm_numeric<T>(L.Pc, (const T *)L.Ptv, L.T2, (const T *)L.T3v, C.M, (T *)C.Nv, s);
+    copy_permuted<T>((T *)C.Btv, (const T *)C.Bv, C.btperm, C.B.nnz, s);
+    dinv_from_diag<T>(C, (const T *)C.Bv, (T *)C.dinv, flag, s);
+    if (h->opt.smoother == BAMG_SMOOTH_KACZMARZ) {
+      row_inv_norms<T>(C.B, (const T *)C.Bv, (T *)C.rowinvB, s);
+      row_inv_norms<T>(C.Bt, (const T *)C.Btv, (T *)C.rowinvBt, s);
+    }
+  }
+
+  // Algorithm 1 (bamg_mle) from level l
+  void mle(int l, int cycle) {
+    if (l == h->L - 1) {
+      coarsest();
+      return;
+    }
+    Level &L = h->lv[l];
+    relax(L, cycle > 1);
+    normalize(L);
+    weights(L);
+    ls_fit<T>(L, r, (const T *)L.U, (const T *)L.V, wv, wu, h->opt.interp_rule, (T *)L.Pv,
+              (T *)L.Qtv, s);
+    galerkin(l);
+    Level &C = h->lv[l + 1];
+    inject<T>(L.cpts, C.n, r, (const T *)L.U, (T *)C.U, s);
+    inject<T>(L.cpts, C.n, r, (const T *)L.V, (T *)C.V, s);
+    mle(l + 1, cycle);
+    Level &L2 = h->lv[l];
+    Level &C2 = h->lv[l + 1];
+    spmm<T>(L2.P, (const T *)L2.Qtv, r, (const T *)C2.U, (T *)L2.U, 1, s);
+    spmm<T>(L2.P, (const T *)L2.Pv, r, (const T *)C2.V, (T *)L2.V, 0, s);
+    relax(L2, 1);
+  }
+
+  void alloc_dense(int n) {
+    nL = n;
+    const size_t nn = (size_t)n * n;
+    Bd = pool().template get<double>(nn);
+    Md = pool().template get<double>(nn);
+    Nd = pool().template get<double>(nn);
+    X = pool().template get<double>(nn);
+    W = pool().template get<double>(nn);
+    J = pool().template get<double>(nn);
+    sv = pool().template get<double>(n);
+    work = pool().template get<double>(n + 64);
+  }
+
+  // r smallest generalized singular triplets on the coarsest level
+  void coarsest() {
+    Level &C = h->lv[h->L - 1];
+    const int n = C.n;
+    csr_to_dense(C.B, C.Bv, h->prec, Bd, s);
+    csr_to_dense(C.M, C.Mv, h->prec, Md, s);
+    csr_to_dense(C.M, C.Nv, h->prec, Nd, s);
+    if (cholesky(Md, n, s) != BAMG_OK || cholesky(Nd, n, s) != BAMG_OK)
+      fail(BAMG_E_COARSE, "coarsest M_L or N_L not positive definite");
+    HIPCHK(hipMemcpyAsync(X, Bd, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToDevice, s));
+    trsm_lower_cols(Md, X, n, n, n, 0, s);  // X = L_M^-1 B
+    transpose_dense(X, W, n, s);
+    trsm_lower_cols(Nd, W, n, n, n, 0, s);  // W = L_N^-1 X^T, i.e. Bt column-major
+    if (jacobi_svd(pool(), W, J, n, s) != BAMG_OK) fail(BAMG_E_COARSE, "Jacobi SVD did not converge");
+    column_norms(W, n, sv, s);
+    coarse_triplets_out(Md, Nd, W, J, sv, n, r, C.U, C.V, h->prec, h->sigma, work, s);
+  }
+
+  void pinv() {
+    Level &C = h->lv[h->L - 1];
+    const int n = C.n;
+    csr_to_dense(C.B, C.Bv, h->prec, Bd, s);
+    transpose_dense(Bd, W, n, s);  // W = B_L column-major
+    if (jacobi_svd(pool(), W, J, n, s) != BAMG_OK) fail(BAMG_E_COARSE, "Jacobi SVD did not converge");
+    column_norms(W, n, sv, s);
+    h->bdag = pool().template get<double>((size_t)n * n);
+    if (build_pinv(pool(), W, J, sv, n, h->bdag, s) != BAMG_OK)
+      fail(BAMG_E_COARSE, "coarsest operator is not of rank n_L - 1");
+  }
+};
+
+template <class T>
+__global__ void k_col_get(const T *__restrict__ X, int n, int r, int k, T *__restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = X[(size_t)i * r + k];
+}
+template <class T>
+__global__ void k_col_set(T *__restrict__ X, int n, int r, int k, const T *__restrict__ in) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) X[(size_t)i * r + k] = in[i];
+}
+template <class T>
+void Setup<T>::column_get(const T *Xm, int n, int r_, int k, T *out) {
+  k_col_get<T><<<ceil_div(n, 256), 256, 0, s>>>(Xm, n, r_, k, out);
+  LAUNCHCHK();
+}
+template <class T>
+void Setup<T>::column_set(T *Xm, int n, int r_, int k, const T *in) {
+  k_col_set<T><<<ceil_div(n, 256), 256, 0, s>>>(Xm, n, r_, k, in);
+  LAUNCHCHK();
+}
+
+// x0 = column kx of V on level 0, in FP64
+template <class T>
+__global__ void k_extract_col(const T *__restrict__ V, int n, int r, int k,
+                              double *__restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (double)V[(size_t)i * r + k];
+}
+
+__global__ void k_identity_csr(int n, int *__restrict__ rp, int *__restrict__ ci) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    ci[i] = i;
+    rp[i + 1] = i + 1;
+  }
+  if (i == 0) rp[0] = 0;
+}
+
+}  // namespace
+
+template <class T>
+void setup_all(bamg_handle *h, const bamg_csr *A, const bamg_geometry *geom) {
+  const bamg_options &o = h->opt;
+  Pool &pool = h->pool;
+  hipStream_t s = pool.s;
+  const int n = (int)A->n, nnz = (int)A->nnz, r = o.r;
+  // ---- input on the device
+  const int *arp = A->row_ptr, *aci = A->col_idx;
+  const double *aval = A->val;
+  if (!A->on_device) {
+    int *drp = pool.get<int>(n + 1), *dci = pool.get<int>(nnz);
+    double *dv = pool.get<double>(nnz);
+    HIPCHK(hipMemcpyAsync(drp, arp, sizeof(int) * (n + 1), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dci, aci, sizeof(int) * nnz, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dv, aval, sizeof(double) * nnz, hipMemcpyHostToDevice, s));
+    arp = drp;
+    aci = dci;
+    aval = dv;
+  }
+  int st = check_input(pool, arp, aci, aval, n, nnz, s);
+  if (st != BAMG_OK) fail(st, "input CSR rejected");
+
+  const bool geometric = o.coarsening == BAMG_COARSEN_GEOMETRIC && geom && geom->kind != 0;
+  h->lv.clear();
+  h->lv.emplace_back();
+  {
+    Level &L0 = h->lv[0];
+    L0.n = n;
+    L0.gkind = geometric ? geom->kind : 0;
+    L0.nx = geometric ? geom->nx : 0;
+    L0.ny = geometric ? (geom->kind == 2 ? geom->ny : 1) : 0;
+    double *b64 = nullptr;
+    build_B(arp, aci, aval, n, pool, L0.B, b64, s);
+    transpose_pattern(pool, L0.B, L0.Bt, L0.btperm, s);
+    double *bt64 = pool.get<double>(L0.B.nnz);
+    copy_permuted<double>(bt64, b64, L0.btperm, L0.B.nnz, s);
+    if (o.validate) {
+      st = validate_chain(pool, L0.B, L0.Bt, bt64, s);
+      if (st != BAMG_OK) fail(st, "transition matrix rejected");
+    }
+    L0.dpos = pool.get<int>(n);
+    diag_positions(L0.B, L0.dpos, s);
+    h->B64 = b64;
+    if (h->prec == 0) {
+      L0.Bv = b64;
+      L0.Btv = bt64;
+    } else {
+      L0.Bv = pool.get<T>(L0.B.nnz);
+      L0.Btv = pool.get<T>(L0.B.nnz);
+      convert<double, T>((T *)L0.Bv, b64, L0.B.nnz, s);
+      convert<double, T>((T *)L0.Btv, bt64, L0.B.nnz, s);
+    }
+    L0.M.nr = L0.M.nc = L0.M.nnz = n;
+    L0.M.rp = pool.get<int>(n + 1);
+    L0.M.ci = pool.get<int>(n);
+    k_identity_csr<<<ceil_div(n, 256), 256, 0, s>>>(n, L0.M.rp, L0.M.ci);
+    LAUNCHCHK();
+    L0.Mv = pool.get<T>(n);
+    L0.Nv = pool.get<T>(n);
+    fill<T>((T *)L0.Mv, (T)1, n, s);
+    fill<T>((T *)L0.Nv, (T)1, n, s);
+    L0.identity_mn = true;
+    L0.dinv = pool.get<T>(n);
+  }
+  int *flag = pool.get<int>(4);
+  dinv_from_diag<T>(h->lv[0], (const T *)h->lv[0].Bv, (T *)h->lv[0].dinv, flag, s);
+
+  // ---- integer structure of the hierarchy
+  for (int l = 0;; ++l) {
+    {
+      Level &L = h->lv[l];
+      if (L.n <= o.coarse_max || l == o.max_levels - 1 || l == 31) break;
+      sym_graph(pool, L.B, L.Bt, L.G, s);
+      L.cf = pool.get<int>(L.n);
+      L.cidx = pool.get<int>(L.n);
+      if (geometric)
+        geom_cf(L.n, L.nx, L.gkind, L.cf, s);
+      else
+        mis_cf(pool, L.G, o.seed, l, L.cf, s);
+      L.nc = coarse_numbering(pool, L.cf, L.n, L.cidx, L.cpts, s);
+      if (L.nc == 0 || L.nc >= L.n) break;
+      interp_pattern(pool, L, o.max_interp, geometric ? 1 : 0, L.P, s);
+      transpose_pattern(pool, L.P, L.Pc, L.pcperm, s);
+      spgemm_symbolic(pool, L.B, L.P, 0, L.T1, s);
+      spgemm_symbolic(pool, L.M, L.P, 0, L.T2, s);
+    }
+    Level C;
+    {
+      Level &L = h->lv[l];
+      C.n = L.nc;
+      C.gkind = L.gkind;
+      C.nx = (L.nx + 1) / 2;
+      C.ny = L.gkind == 2 ? (L.ny + 1) / 2 : 1;
+      spgemm_symbolic(pool, L.Pc, L.T1, 1, C.B, s);
+      spgemm_symbolic(pool, L.Pc, L.T2, 1, C.M, s);
+      L.Pv = pool.get<T>(L.P.nnz);
+      L.Qtv = pool.get<T>(L.P.nnz);
+      L.Ptv = pool.get<T>(L.P.nnz);
+      L.Qv = pool.get<T>(L.P.nnz);
+      L.T1v = pool.get<T>(L.T1.nnz);
+      L.T2v = pool.get<T>(L.T2.nnz);
+      L.T3v = pool.get<T>(L.T2.nnz);
+    }
+    transpose_pattern(pool, C.B, C.Bt, C.btperm, s);
+    C.dpos = pool.get<int>(C.n);
+    diag_positions(C.B, C.dpos, s);
+    C.Bv = pool.get<T>(C.B.nnz);
+    C.Btv = pool.get<T>(C.B.nnz);
+    C.Mv = pool.get<T>(C.M.nnz);
+    C.Nv = pool.get<T>(C.M.nnz);
+    C.dinv = pool.get<T>(C.n);
+    h->lv.push_back(C);
+  }
+  h->L = (int)h->lv.size();
+  if (h->L < 2) fail(BAMG_E_ARG, "no coarsening happened (check coarse_max and max_levels)");
+  const int nL = h->lv[h->L - 1].n;
+  if (nL > 2048) fail(BAMG_E_ARG, "coarsest level above 2048 states; lower coarse_max or raise max_levels");
+  if (r > nL) fail(BAMG_E_ARG, "more test vectors than coarsest states");
+
+  // ---- vectors and work space
+  for (int l = 0; l < h->L; ++l) {
+    Level &L = h->lv[l];
+    const size_t nr = (size_t)L.n * r;
+    L.U = pool.get<T>(nr);
+    L.V = pool.get<T>(nr);
+    L.U2 = pool.get<T>(nr);
+    L.V2 = pool.get<T>(nr);
+    L.xb = pool.get<T>(L.n);
+    L.bb = pool.get<T>(L.n);
+    L.rb = pool.get<T>(L.n);
+    L.tb = pool.get<T>(L.n);
+    if (o.smoother == BAMG_SMOOTH_KACZMARZ && l < h->L - 1) {
+      L.colB = pool.get<int>(L.n);
+      L.colBt = pool.get<int>(L.n);
+      row_colouring(pool, L.B, L.Bt, L.colB, L.ncolB, L.ordB, L.offB, s);
+      row_colouring(pool, L.Bt, L.B, L.colBt, L.ncolBt, L.ordBt, L.offBt, s);
+      L.rowinvB = pool.get<T>(L.n);
+      L.rowinvBt = pool.get<T>(L.n);
+      if (l == 0) {
+        row_inv_norms<T>(L.B, (const T *)L.Bv, (T *)L.rowinvB, s);
+        row_inv_norms<T>(L.Bt, (const T *)L.Btv, (T *)L.rowinvBt, s);
+      }
+    }
+  }
+  h->sigma = pool.get<double>(64);
+  fill<double>(h->sigma, 0.0, 64, s);
+
+  Setup<T> S;
+  S.h = h;
+  S.s = s;
+  S.r = r;
+  S.nblk = std::min(kRedBlocks, std::max(1, ceil_div(n, 16 * 16)));
+  S.part = pool.get<double>((size_t)S.nblk * 5 * 16);
+  S.prod = pool.get<double>(5 * 16);
+  S.wv = pool.get<double>(16);
+  S.wu = pool.get<double>(16);
+  S.scales = pool.get<double>(32);
+  S.flag = flag;
+  S.alloc_dense(nL);
+
+  // ---- bootstrap cycles
+  philox_testvecs(h->lv[0].U, h->lv[0].V, h->prec, n, r, o.seed, s);
+  for (int cyc = 1; cyc <= o.setup_cycles; ++cyc) S.mle(0, cyc);
+
+  // ---- coarse pseudo-inverse and x0
+  S.pinv();
+  std::vector<double> sig(r);
+  HIPCHK(hipMemcpyAsync(sig.data(), h->sigma, sizeof(double) * r, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  int kx = 0;
+  for (int k = 1; k < r; ++k)
+    if (sig[k] < sig[kx]) kx = k;
+  h->x0 = pool.get<double>(n);
+  k_extract_col<T><<<ceil_div(n, 256), 256, 0, s>>>((const T *)h->lv[0].V, n, r, kx, h->x0);
+  LAUNCHCHK();
+  const int nb = std::min(kRedBlocks, std::max(1, ceil_div(n, 256)));
+  double *part = pool.get<double>(nb + 8);
+  double *fl = pool.get<double>(16);
+  normalize_sum(h->x0, n, part, nb, fl, s);
+  pool.release(part);
+  pool.release(fl);
+  HIPCHK(hipStreamSynchronize(s));
+  pool.flush();
+}
+
+template void setup_all<double>(bamg_handle *, const bamg_csr *, const bamg_geometry *);
+template void setup_all<float>(bamg_handle *, const bamg_csr *, const bamg_geometry *);
+
+}  // namespace bamg

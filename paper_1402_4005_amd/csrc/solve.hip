@@ -1,0 +1,246 @@
+// Host orchestration of the solve phase: the V-cycle preconditioner
+// (Sections 3 and 6) and GMRES(m) on the residual equation (Section 6) with
+// the stopping test of Section 7.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "bamg_internal.h"
+#include "device_common.h"
+
+namespace bamg {
+
+namespace {
+
+// y = z + A x (the prolongation written into the other smoothing buffer)
+template <class T>
+__global__ void k_spmv_add_into(int nr, const int *__restrict__ rp, const int *__restrict__ ci,
+                                const T *__restrict__ val, const T *__restrict__ x,
+                                const T *__restrict__ z, T *__restrict__ y) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nr) return;
+  T s = 0;
+  for (int a = rp[i]; a < rp[i + 1]; ++a) s += val[a] * x[ci[a]];
+  y[i] = z[i] + s;
+}
+
+template <class T>
+void smooth_steps(bamg_handle *h, Level &L, const T *b, T *x, int steps, bool from_zero,
+                  hipStream_t s) {
+  if (steps <= 0) {
+    if (from_zero) fill<T>(x, (T)0, L.n, s);
+    return;
+  }
+  if (h->opt.smoother == BAMG_SMOOTH_KACZMARZ) {
+    if (from_zero) fill<T>(x, (T)0, L.n, s);
+    for (int it = 0; it < steps; ++it)
+      for (size_t c = 0; c + 1 < L.offB.size(); ++c)
+        kaczmarz_colour<T>(L.B, (const T *)L.Bv, (const T *)L.rowinvB, L.ordB + L.offB[c],
+                           L.offB[c + 1] - L.offB[c], b, x, s);
+    return;
+  }
+  // weighted Jacobi, ping-pong between x and the level's spare buffer so the
+  // last step lands in x
+  const T om = (T)h->opt.omega;
+  T *spare = (T *)L.tb;
+  T *cur = x, *oth = spare;
+  if (from_zero) {
+    T *first = (steps % 2 == 1) ? x : spare;
+    jacobi<T>(L.B, (const T *)L.Bv, (const T *)L.dinv, om, b, nullptr, first, L.lanes, s);
+    cur = first;
+    oth = first == x ? spare : x;
+    --steps;
+  } else if (steps % 2 == 1) {
+    // odd count from x: the caller provided x in the spare buffer instead
+    cur = spare;
+    oth = x;
+  }
+  for (int it = 0; it < steps; ++it) {
+    jacobi<T>(L.B, (const T *)L.Bv, (const T *)L.dinv, om, b, cur, oth, L.lanes, s);
+    std::swap(cur, oth);
+  }
+}
+
+template <class T>
+void vcycle_level(bamg_handle *h, int l, const T *b, T *x, hipStream_t s) {
+  Level &L = h->lv[l];
+  if (l == h->L - 1) {
+    coarse_gemv<T>(h->bdag, L.n, b, x, s);
+    return;
+  }
+  Level &C = h->lv[l + 1];
+  const int nu1 = h->opt.nu_pre, nu2 = h->opt.nu_post;
+  smooth_steps<T>(h, L, b, x, nu1, true, s);
+  spmv<T>(L.B, (const T *)L.Bv, x, (T *)L.rb, b, 1, L.lanes, s);          // r = b - B x
+  spmv<T>(L.Pc, (const T *)L.Qv, (const T *)L.rb, (T *)C.bb, nullptr, 0, 0, s);  // b_c = Q r
+  vcycle_level<T>(h, l + 1, (const T *)C.bb, (T *)C.xb, s);
+  const bool jac = h->opt.smoother != BAMG_SMOOTH_KACZMARZ;
+  if (jac && nu2 % 2 == 1) {
+    // spare = x + P x_c, then an odd number of sweeps ends in x
+    k_spmv_add_into<T><<<ceil_div(L.n, 256), 256, 0, s>>>(L.n, L.P.rp, L.P.ci, (const T *)L.Pv,
+                                                          (const T *)C.xb, x, (T *)L.tb);
+    LAUNCHCHK();
+  } else {
+    spmv<T>(L.P, (const T *)L.Pv, (const T *)C.xb, x, nullptr, 2, 0, s);  // x += P x_c
+  }
+  smooth_steps<T>(h, L, b, x, nu2, false, s);
+}
+
+}  // namespace
+
+template <class T>
+void vcycle_run(bamg_handle *h, const T *b, T *x, hipStream_t s) {
+  vcycle_level<T>(h, 0, b, x, s);
+}
+template void vcycle_run<double>(bamg_handle *, const double *, double *, hipStream_t);
+template void vcycle_run<float>(bamg_handle *, const float *, float *, hipStream_t);
+
+// C applied to an FP64 vector (FP32 inside for a mixed-precision handle)
+static void precondition(bamg_handle *h, const double *b, double *x, hipStream_t s) {
+  if (h->prec == 0) {
+    vcycle_run<double>(h, b, x, s);
+    return;
+  }
+  const int n = h->lv[0].n;
+  convert<double, float>((float *)h->vb, b, n, s);
+  vcycle_run<float>(h, (const float *)h->vb, (float *)h->vx, s);
+  convert<float, double>(x, (const float *)h->vx, n, s);
+}
+
+__global__ void k_krylov_start(const double *__restrict__ h1, double *__restrict__ g, int m,
+                               double *__restrict__ flags) {
+  if (threadIdx.x != 0) return;
+  const double beta = sqrt(h1[0]);
+  for (int i = 0; i <= m; ++i) g[i] = 0.0;
+  g[0] = beta;
+  flags[3] = beta > 0.0 ? 1.0 / beta : 0.0;
+  flags[8] = beta;
+}
+
+void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_x0,
+               bamg_solve_info *info, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  Pool &pool = h->pool;
+  Level &L0 = h->lv[0];
+  const int n = L0.n;
+  const int nblk = std::min(kRedBlocks, std::max(1, ceil_div(n, 256)));
+  if (h->gm_m != m) {
+    // (re)allocate Krylov storage; old buffers stay with the pool until destroy
+    h->gV = pool.get<double>((size_t)(m + 1) * n);
+    h->gBV = pool.get<double>((size_t)m * n);
+    h->gw = pool.get<double>(n);
+    h->gx0 = pool.get<double>(n);
+    h->gbx0 = pool.get<double>(n);
+    h->gH = pool.get<double>((size_t)(m + 1) * m + 4 * (m + 2) + 64);
+    h->gsc = pool.get<double>((size_t)(m + 2) * nblk * 2 + 2 * nblk + 16);
+    if (h->prec != 0) {
+      h->vb = pool.get<float>(n);
+      h->vx = pool.get<float>(n);
+    }
+    if (!h->hred) HIPCHK(hipHostMalloc((void **)&h->hred, sizeof(double) * 16, 0));
+    h->gm_m = m;
+  }
+  double *H = h->gH;
+  double *cs = H + (size_t)(m + 1) * m, *sn = cs + (m + 2), *g = sn + (m + 2), *y = g + (m + 2);
+  double *flags = y + (m + 2);  // 16 values
+  double *part = h->gsc;                          // (m+2) * nblk: multi-dot partials
+  double *part2 = part + (size_t)(m + 2) * nblk;  // nblk: |w|^2 partials
+  double *part3 = part2 + nblk;                   // 2 nblk: residual-check partials
+  double *coef = pool.get<double>(2 * (size_t)(m + 2));
+  double *c1 = coef, *c2 = coef + (m + 2);  // the two Gram-Schmidt passes
+  double *negb = pool.get<double>(n);
+
+  if (use_x0)
+    HIPCHK(hipMemcpyAsync(h->gx0, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  else
+    HIPCHK(hipMemcpyAsync(h->gx0, h->x0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+
+  const Csr &B = L0.B;
+  const int lanes = L0.lanes;
+  double *hf = h->hred;
+  auto read_flags = [&]() {
+    HIPCHK(hipMemcpyAsync(hf, flags, sizeof(double) * 16, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  };
+
+  // initial test on x0
+  spmv<double>(B, h->B64, h->gx0, h->gbx0, nullptr, 0, lanes, s);
+  residual_check_partials(h->gx0, h->gbx0, h->gV, h->gBV, c1, n, 0, part3, nblk, s);
+  residual_check_finalize(part3, nblk, tol, flags, s);
+  read_flags();
+  int it = 0, restarts = 0, breakdowns = 0, conv = hf[0] != 0.0;
+  double rel = hf[2];
+  bamg_status st = BAMG_OK;
+  while (!conv && it < maxit) {
+    spmv<double>(B, h->B64, h->gx0, h->gbx0, nullptr, 0, lanes, s);  // B x0
+    negate_copy(h->gbx0, negb, n, s);                                 // r0 = -B x0
+    precondition(h, negb, h->gw, s);                                  // z = C r0
+    multi_dot(h->gV, n, 0, h->gw, part, nblk, s);
+    finalize_multi(part, nblk, 1, c1, s);
+    k_krylov_start<<<1, 64, 0, s>>>(c1, g, m, flags);
+    LAUNCHCHK();
+    scale_vec(h->gw, flags + 3, h->gV, n, s);  // v_0 = z / beta
+    int used = 0;
+    bool broke = false;
+    for (int j = 0; j < m && it < maxit; ++j) {
+      double *vj = h->gV + (size_t)j * n, *bvj = h->gBV + (size_t)j * n;
+      spmv<double>(B, h->B64, vj, bvj, nullptr, 0, lanes, s);  // B v_j
+      precondition(h, bvj, h->gw, s);                         // w = C B v_j
+      // Gram-Schmidt, twice
+      multi_dot(h->gV, n, j + 1, h->gw, part, nblk, s);
+      finalize_multi(part, nblk, j + 2, c1, s);  // c1[0..j], c1[j+1] = |w|^2
+      multi_axpy_norm(h->gV, n, j + 1, c1, h->gw, part2, nblk, s);
+      multi_dot(h->gV, n, j + 1, h->gw, part, nblk, s);
+      finalize_multi(part, nblk, j + 1, c2, s);
+      multi_axpy_norm(h->gV, n, j + 1, c2, h->gw, part2, nblk, s);
+      gmres_arnoldi_update(H, cs, sn, g, y, c1, c2, part2, nblk, nullptr, j, m, flags, s);
+      scale_vec(h->gw, flags + 3, h->gV + (size_t)(j + 1) * n, n, s);
+      residual_check_partials(h->gx0, h->gbx0, h->gV, h->gBV, y, n, j + 1, part3, nblk, s);
+      residual_check_finalize(part3, nblk, tol, flags, s);
+      read_flags();
+      ++it;
+      used = j + 1;
+      rel = hf[2];
+      if (!std::isfinite(rel)) {
+        st = BAMG_E_NONFINITE;
+        break;
+      }
+      if (hf[0] != 0.0) {
+        conv = 1;
+        break;
+      }
+      if (hf[1] != 0.0) {
+        broke = true;
+        break;
+      }
+    }
+    if (used > 0) update_iterate(h->gx0, h->gV, y, n, used, s);
+    if (st != BAMG_OK) break;
+    if (broke && !conv && ++breakdowns >= 2) {
+      st = BAMG_E_BREAKDOWN;
+      break;
+    }
+    if (!conv) ++restarts;
+  }
+  // scale to 1^T x = 1
+  normalize_sum(h->gx0, n, part, nblk, flags, s);
+  HIPCHK(hipMemcpyAsync(x, h->gx0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  read_flags();
+  if (info) {
+    info->iterations = it;
+    info->restarts = restarts;
+    info->converged = conv;
+    info->breakdowns = breakdowns;
+    info->rel_residual = rel;
+    info->x_min = hf[5];
+    info->t_solve_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  pool.release(coef);
+  pool.release(negb);
+  pool.flush();
+  if (st != BAMG_OK) fail(st, "GMRES failed");
+  if (!conv) throw Error{BAMG_NOT_CONVERGED, "iteration cap reached"};
+}
+
+}  // namespace bamg

@@ -1,0 +1,133 @@
+"""GPU parity tests: the HIP library (through its C ABI) against the FP64 CPU
+oracle on the same seeded inputs. Integer outputs (C/F splittings, coarse
+numbering, every sparsity pattern) must be bit-exact; floating-point outputs
+within the tolerances stated per test; the stationary vector within 1e-10 in
+relative l1 when both sides run to ||Bx||/||x|| < 1e-14."""
+import numpy as np
+import pytest
+
+import chaingen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+bamg = pytest.importorskip("paper_1402_4005_amd")
+
+
+def rel_l1(x, y):
+    return float(np.abs(x - y).sum() / np.abs(y).sum())
+
+
+def rel_max(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def both(ch, **kw):
+    ko = oracle.options_for(ch, **kw)
+    go = bamg.options_for(ch, **kw)
+    h_orc = oracle.Hierarchy(ch, ko)
+    h_gpu = bamg.Hierarchy.from_chain(ch, go)
+    return h_orc, h_gpu
+
+
+def check_structure(ho, hg):
+    assert ho.levels == hg.levels
+    for l in range(ho.levels):
+        assert ho.dims(l)[0] == hg.info()["n"][l]
+        for what in ("B", "Bt", "M"):
+            rp_o, ci_o, _ = ho.csr(l, what)
+            rp_g, ci_g, _ = hg.csr(l, what)
+            assert np.array_equal(rp_o, rp_g), (l, what)
+            assert np.array_equal(ci_o, ci_g), (l, what)
+        if l < ho.levels - 1:
+            cf_o, cidx_o = ho.cf(l)
+            cf_g, cidx_g = hg.cf(l)
+            assert np.array_equal(cf_o, cf_g), l
+            assert np.array_equal(cidx_o, cidx_g), l
+            for what in ("P", "Q", "Qt"):
+                rp_o, ci_o, _ = ho.csr(l, what)
+                rp_g, ci_g, _ = hg.csr(l, what)
+                assert np.array_equal(rp_o, rp_g), (l, what)
+                assert np.array_equal(ci_o, ci_g), (l, what)
+
+
+CASES = [
+    # (name, chain factory, options)
+    ("tandem14_2lev", lambda: chaingen.tandem(14, 11 / 31, 10 / 31, 10 / 31),
+     dict(r=6, max_levels=2, coarse_max=1)),
+    ("tandem14_3lev_bamg2", lambda: chaingen.tandem(14, 11 / 31, 10 / 31, 10 / 31),
+     dict(r=6, max_levels=3, coarse_max=1, setup_cycles=2)),
+    ("tandem33_3lev", lambda: chaingen.tandem(33, 11 / 31, 10 / 31, 10 / 31),
+     dict(r=6, max_levels=3, coarse_max=1)),
+    ("delaunay3000", lambda: chaingen.delaunay_walk(3000, 12),
+     dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=500)),
+    ("birthdeath257", lambda: chaingen.birth_death(257, 0.96),
+     dict(r=8, max_interp=2, coarse_max=29)),
+]
+
+
+@pytest.mark.parametrize("name,make,kw", CASES, ids=[c[0] for c in CASES])
+def test_structure_bit_exact(name, make, kw):
+    ch = make()
+    ho, hg = both(ch, **kw)
+    check_structure(ho, hg)
+
+
+@pytest.mark.parametrize("name,make,kw", CASES, ids=[c[0] for c in CASES])
+def test_operators_and_vectors_close(name, make, kw):
+    ch = make()
+    ho, hg = both(ch, **kw)
+    # level 0 operator is exact input arithmetic
+    assert np.array_equal(ho.csr(0, "B")[2], hg.csr(0, "B")[2])
+    for l in range(ho.levels - 1):
+        for what in ("P", "Qt"):
+            a, b = hg.csr(l, what)[2], ho.csr(l, what)[2]
+            assert rel_max(a, b) < 1e-7, (l, what, rel_max(a, b))
+    for l in range(1, ho.levels):
+        for what in ("B", "M", "N"):
+            a, b = hg.csr(l, what)[2], ho.csr(l, what)[2]
+            assert rel_max(a, b) < 1e-7, (l, what, rel_max(a, b))
+    so, sg = ho.sigma(), hg.sigma()
+    assert np.allclose(np.sort(np.abs(sg)), np.sort(np.abs(so)), rtol=1e-6, atol=1e-12)
+
+
+@pytest.mark.parametrize("name,make,kw", CASES, ids=[c[0] for c in CASES])
+def test_stationary_vector_matches_oracle(name, make, kw):
+    import torch
+    ch = make()
+    ho, hg = both(ch, **kw)
+    xo, io = ho.gmres(m=20, tol=1e-14, maxit=400)
+    xg, ig = hg.gmres(restart=20, tol=1e-14, maxit=400)
+    torch.cuda.synchronize()
+    xg = xg.cpu().numpy()
+    assert ig.converged and io.converged
+    assert rel_l1(xg, xo) < 1e-10, rel_l1(xg, xo)
+    assert abs(xg.sum() - 1) < 1e-12
+
+
+def test_vcycle_close_to_oracle():
+    import torch
+    ch = chaingen.tandem(33, 11 / 31, 10 / 31, 10 / 31)
+    ho, hg = both(ch, r=6, max_levels=3, coarse_max=1)
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(ch.n)
+    xo = ho.vcycle(b)
+    xg = hg.vcycle(torch.from_numpy(b).cuda()).cpu().numpy()
+    assert rel_max(xg, xo) < 1e-7, rel_max(xg, xo)
+
+
+def test_coarse_pinv_matches_numpy():
+    ch = chaingen.tandem(14, 11 / 31, 10 / 31, 10 / 31)
+    _, hg = both(ch, r=6, max_levels=2, coarse_max=1)
+    L = hg.levels - 1
+    BL = hg.scipy(L, "B").toarray()
+    ref = np.linalg.pinv(BL, rcond=1e-10)
+    assert rel_max(hg.coarse_pinv(), ref) < 1e-9
+
+
+def test_error_codes():
+    ch = chaingen.tandem(6, 11 / 31, 10 / 31, 10 / 31)
+    bad = chaingen.Chain(ch.to_scipy() * 1.01, ch.geom)
+    with pytest.raises(bamg.BamgError) as e:
+        bamg.Hierarchy.from_chain(bad, bamg.options_for(ch, r=6, max_levels=2, coarse_max=1))
+    assert e.value.code == -2
