@@ -1,0 +1,200 @@
+"""Benchmark: time for BAMG-preconditioned GMRES to reach ||Bx||/||x|| < 1e-10.
+
+One step = the whole hot path on one synthetic chain whose transition matrix
+is already resident in HBM: bamg_setup (validation, hierarchy structure, one
+bootstrap cycle, coarsest pseudo-inverse) followed by bamg_gmres_solve to the
+tolerance. Default workload: random walk on the Delaunay triangulation of
+262,144 uniform points (p_ij = 1/deg(j)), r = 8 test vectors, c = 3, 5 + 5
+Jacobi sweeps, coarsening until fewer than 100 states remain (Section 7:
+planar-graph level counts are to a coarsest level of < 100 variables),
+GMRES(20), FP64.
+
+Prints one JSON line. `value` is the time to tolerance in ms (lower is
+better). `roofline` covers the dominant kernel (the finest-level weighted
+Jacobi sweep of the V-cycle), timed with HIP events on its launch stream over
+the timed steps; `cpu_baseline` is the FP64 CPU oracle on the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X published HBM3E bandwidth
+
+WORKLOADS = {
+    # name: (kind, size, options)
+    "delaunay262144": ("delaunay", 262144, dict(r=8, max_interp=3, nu_pre=5, nu_post=5,
+                                                 nu_setup=5, coarse_max=99, seed=14024002)),
+    "tandem1025": ("tandem_random", 1025, dict(r=8, max_interp=4, coarse_max=289,
+                                               seed=14024003)),
+    "tandem33": ("tandem", 33, dict(r=6, max_interp=4, max_levels=3, coarse_max=1,
+                                    seed=14024001)),
+}
+
+
+def make_chain(kind, size, seed):
+    import chaingen
+    if kind == "delaunay":
+        return chaingen.delaunay_walk(size, seed)
+    if kind == "tandem_random":
+        return chaingen.tandem(size, *chaingen.tandem_random_rates(seed))
+    return chaingen.tandem(size, 11 / 31, 10 / 31, 10 / 31)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="delaunay262144", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--setup-cycles", type=int, default=1)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--restart", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--vcycle-reps", type=int, default=100)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the method is benchmarked on one MI355X "
+              "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1402_4005_amd as bamg
+
+    kind, size, wopts = WORKLOADS[args.workload]
+    ch = make_chain(kind, size, wopts["seed"])
+    opts = bamg.options_for(ch, precision=args.precision, setup_cycles=args.setup_cycles,
+                            **wopts)
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(ch.indptr).to(dev)
+    ci = torch.from_numpy(ch.indices).to(dev)
+    va = torch.from_numpy(ch.data).to(dev)
+    stream = torch.cuda.current_stream()
+
+    def step(profile=False):
+        h = bamg.Hierarchy(rp, ci, va, ch.geom, opts, stream=stream)
+        if profile:
+            h.profile_begin(0)
+        x, info = h.gmres(restart=args.restart, tol=args.tol, maxit=1000, stream=stream)
+        prof = h.profile_end() if profile else None
+        return h, x, info, prof
+
+    for _ in range(args.warmup):
+        h, x, info, _ = step()
+        h.close()
+    torch.cuda.synchronize()
+
+    # timed region: K whole steps, device-synchronised on both sides
+    launches = 0
+    kms = 0.0
+    kbytes = 0.0
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        h, x, info, prof = step(profile=True)
+        launches += prof[0]
+        kms += prof[1]
+        kbytes += prof[2]
+        infos.append(info)
+        last = h
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+
+    # untimed: accuracy and split of the last step, V-cycle bandwidth
+    hinfo = last.info()
+    xs = x.cpu().numpy()
+    extra = {}
+    if kind == "delaunay":
+        deg = ch.extra["deg"]
+        pi = deg / deg.sum()
+        extra["x_err_rel_l1_vs_closed_form"] = float(np.abs(xs - pi).sum())
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    hs = bamg.Hierarchy(rp, ci, va, ch.geom, opts, stream=stream)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - ts) * 1e3
+    b = torch.randn(ch.n, dtype=torch.float64, device=dev)
+    xv = torch.empty_like(b)
+    hs.vcycle(b, xv)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.vcycle_reps):
+        hs.vcycle(b, xv)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    vc_ms = e0.elapsed_time(e1) / args.vcycle_reps
+    vc_bytes = hs.vcycle_bytes()
+
+    achieved = (kbytes / launches) / (kms / launches * 1e-3) / 1e9 if launches else None
+    roofline = {
+        "kernel": "k_jacobi (finest-level weighted-Jacobi sweep, CSR, 8 lanes/row)",
+        "bound": "hbm",
+        "achieved": round(achieved, 1) if achieved else None,
+        "peak": HBM_PEAK_GBPS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBPS, 4) if achieved else None,
+        "traffic": None,
+        "launches": launches,
+        "avg_us": round(kms / launches * 1e3, 3) if launches else None,
+        "bytes_per_launch": kbytes / launches if launches else None,
+    }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        ko = oracle.options_for(ch, setup_cycles=args.setup_cycles,
+                                **{k: v for k, v in wopts.items()})
+        tc = time.perf_counter()
+        ho = oracle.Hierarchy(ch, ko)
+        xo, io = ho.gmres(m=args.restart, tol=args.tol, maxit=1000)
+        cpu_ms = (time.perf_counter() - tc) * 1e3
+        cpu = {"value": round(cpu_ms, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+               "sample": f"one full solve of the same workload (setup + GMRES to {args.tol:g}), "
+                         f"single thread, {io.iterations} iterations",
+               "x_rel_l1_gpu_vs_oracle": float(np.abs(xs - xo).sum() / np.abs(xo).sum())}
+
+    it = [i.iterations for i in infos]
+    line = {
+        "metric": "time to ||Bx||/||x||<1e-10 (setup + GMRES), FP64",
+        "value": round(ms_per_step, 3),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "n": ch.n, "nnz_A": ch.nnz, "levels": hinfo["levels"], "n_l": hinfo["n"],
+            "oc": round(hinfo["oc"], 3), "og": round(hinfo["og"], 3),
+            "r": opts.r, "c": opts.max_interp, "sweeps": f"{opts.nu_pre}+{opts.nu_post}",
+            "setup_cycles": opts.setup_cycles, "restart": args.restart, "tol": args.tol,
+            "precision": args.precision,
+        },
+        "iterations": it,
+        "setup_ms": round(setup_ms, 3),
+        "vcycle": {"ms": round(vc_ms, 4), "bytes": vc_bytes,
+                   "GBps": round(vc_bytes / (vc_ms * 1e-3) / 1e9, 1)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        **extra,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -175,6 +175,21 @@ bamg_status bamg_sigma(const bamg_handle *h, double *sigma);
 bamg_status bamg_x0(const bamg_handle *h, void *x_device, void *hip_stream);
 bamg_status bamg_coarse_pinv(const bamg_handle *h, double *bdag);
 
+/* Algorithmic HBM bytes of one V-cycle on this hierarchy: every CSR value
+ * and index read once, every vector read or written once per kernel that
+ * touches it, the dense coarsest solve; FP64 or FP32 values as stored. */
+bamg_status bamg_vcycle_bytes(const bamg_handle *h, double *bytes);
+
+/* Kernel timing with HIP events on the launch stream. kernel 0 = the
+ * weighted-Jacobi sweep on the finest level (the V-cycle smoother that
+ * starts from a nonzero iterate). After begin, every run of back-to-back
+ * launches of that kernel on h is bracketed by two events; end synchronises
+ * h's last stream and returns the number of launches, their summed duration
+ * (ms) and their summed algorithmic bytes. */
+bamg_status bamg_kernel_profile_begin(bamg_handle *h, int32_t kernel);
+bamg_status bamg_kernel_profile_end(bamg_handle *h, int64_t *launches, double *ms_total,
+                                    double *bytes_total);
+
 /* Free every resource of h (NULL is ignored). */
 void bamg_destroy(bamg_handle *h);
 

@@ -87,6 +87,9 @@ def lib():
         L.bamg_sigma.argtypes = [V, V]
         L.bamg_x0.argtypes = [V, V, V]
         L.bamg_coarse_pinv.argtypes = [V, V]
+        L.bamg_vcycle_bytes.argtypes = [V, V]
+        L.bamg_kernel_profile_begin.argtypes = [V, C.c_int32]
+        L.bamg_kernel_profile_end.argtypes = [V, V, V, V]
         L.bamg_destroy.argtypes = [V]
         L.bamg_destroy.restype = None
         L.bamg_status_string.argtypes = [C.c_int32]
@@ -280,6 +283,19 @@ class Hierarchy:
         x = torch.empty(self.n, dtype=torch.float64, device="cuda")
         _check(lib().bamg_x0(self.h, C.c_void_p(x.data_ptr()), _stream(None)))
         return x
+
+    def vcycle_bytes(self) -> float:
+        b = C.c_double()
+        _check(lib().bamg_vcycle_bytes(self.h, C.byref(b)))
+        return b.value
+
+    def profile_begin(self, kernel=0):
+        _check(lib().bamg_kernel_profile_begin(self.h, kernel))
+
+    def profile_end(self):
+        n, ms, by = C.c_int64(), C.c_double(), C.c_double()
+        _check(lib().bamg_kernel_profile_end(self.h, C.byref(n), C.byref(ms), C.byref(by)))
+        return n.value, ms.value, by.value
 
     def coarse_pinv(self):
         info = self.info()

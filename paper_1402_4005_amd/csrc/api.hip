@@ -18,10 +18,10 @@ void check_hip(hipError_t e, const char *what, const char *file, int line) {
                         std::to_string(line)};
 }
 
-void *Pool::raw(size_t bytes) {
+static void *device_alloc(Pool &pool, size_t bytes) {
   void *p = nullptr;
-  if (custom) {
-    p = a.alloc(a.ctx, bytes, (void *)s);
+  if (pool.custom) {
+    p = pool.a.alloc(pool.a.ctx, bytes, (void *)pool.s);
     if (!p) throw Error{BAMG_E_NOMEM, "caller allocator returned NULL"};
   } else {
     const hipError_t e = hipMalloc(&p, bytes);
@@ -30,11 +30,8 @@ void *Pool::raw(size_t bytes) {
       throw Error{BAMG_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)};
     }
   }
-  live.push_back(p);
   return p;
 }
-
-void Pool::release(void *p) { deferred.push_back(p); }
 
 static void free_one(Pool &pool, void *p) {
   if (pool.custom)
@@ -43,17 +40,44 @@ static void free_one(Pool &pool, void *p) {
     (void)hipFree(p);
 }
 
+// Small requests are carved out of 32 MiB chunks (256-byte aligned); large
+// ones get their own allocation. Only the latter are ever freed early.
+void *Pool::raw(size_t bytes) {
+  constexpr size_t kChunk = size_t(32) << 20, kAlign = 256;
+  bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+  if (bytes >= kChunk / 4) {
+    void *p = device_alloc(*this, bytes);
+    live.push_back(p);
+    return p;
+  }
+  if (bytes > chunk_left) {
+    chunk_cur = static_cast<char *>(device_alloc(*this, kChunk));
+    live.push_back(chunk_cur);
+    chunks.push_back(chunk_cur);
+    chunk_left = kChunk;
+  }
+  void *p = chunk_cur;
+  chunk_cur += bytes;
+  chunk_left -= bytes;
+  return p;
+}
+
+void Pool::release(void *p) { deferred.push_back(p); }
+
 void Pool::flush() {
   if (deferred.empty()) return;
   (void)hipStreamSynchronize(s);
   for (void *p : deferred) {
     for (size_t i = 0; i < live.size(); ++i)
       if (live[i] == p) {
+        bool is_chunk = false;
+        for (void *c : chunks) is_chunk |= (c == p);
+        if (is_chunk) break;  // first carve of a chunk: keep the chunk
         live[i] = live.back();
         live.pop_back();
+        free_one(*this, p);
         break;
       }
-    free_one(*this, p);
   }
   deferred.clear();
 }
@@ -63,7 +87,36 @@ void Pool::release_all() {
   for (void *p : live) free_one(*this, p);
   live.clear();
   deferred.clear();
+  chunks.clear();
+  chunk_cur = nullptr;
+  chunk_left = 0;
 }
+
+}  // namespace bamg
+
+// Wait for the validation work on the auxiliary stream and release it.
+void bamg_handle::join_validation(bool wait_main) {
+  if (!aux) return;
+  (void)hipStreamSynchronize(aux);
+  if (wait_main) (void)hipStreamSynchronize(pool.s);
+  (void)hipEventDestroy(aux_ready);
+  (void)hipEventDestroy(aux_done);
+  (void)hipStreamDestroy(aux);
+  aux = nullptr;
+  aux_ready = aux_done = nullptr;
+}
+
+// Outcome of the input validation (BAMG_OK when it was not requested).
+int bamg_handle::validation_result() {
+  if (!vflag) return BAMG_OK;
+  int hv[4] = {0, 0, 0, 0};
+  if (hipMemcpyAsync(hv, vflag, sizeof(hv), hipMemcpyDeviceToHost, pool.s) != hipSuccess ||
+      hipStreamSynchronize(pool.s) != hipSuccess)
+    return BAMG_E_DEVICE;
+  return bamg::validation_status(hv, lv.empty() ? 0 : lv[0].n);
+}
+
+namespace bamg {
 
 static bamg_status translate(const Error &e) {
   g_last_error = e.msg;
@@ -178,10 +231,16 @@ bamg_status bamg_setup(const bamg_csr *A, const bamg_geometry *geom, const bamg_
       h->vx = h->pool.get<float>(h->lv[0].n);
     }
   } catch (const Error &e) {
+    // an invalid input explains later failures: report the validation first
+    h->join_validation(true);
+    const int vst = e.code == BAMG_E_DEVICE || e.code == BAMG_E_NOMEM ? BAMG_OK
+                                                                       : h->validation_result();
     h->pool.release_all();
     delete h;
+    if (vst != BAMG_OK) return translate(Error{vst, "transition matrix rejected"});
     return translate(e);
   } catch (...) {
+    h->join_validation(true);
     h->pool.release_all();
     delete h;
     g_last_error = "unexpected exception in setup";
@@ -352,8 +411,60 @@ bamg_status bamg_coarse_pinv(const bamg_handle *h, double *bdag) {
   BAMG_CATCH
 }
 
+bamg_status bamg_vcycle_bytes(const bamg_handle *h, double *bytes) {
+  if (!h || !bytes) return BAMG_E_ARG;
+  const double s = h->prec ? 4.0 : 8.0;
+  const int nu1 = h->opt.nu_pre, nu2 = h->opt.nu_post;
+  double tot = 0.0;
+  for (int l = 0; l + 1 < h->L; ++l) {
+    const Level &L = h->lv[l];
+    const double n = L.n, nnz = L.B.nnz, nc = h->lv[l + 1].n, np = L.P.nnz;
+    const double sweep = nnz * (s + 4) + 4 * (n + 1) + 4 * s * n;
+    const double first = 3 * s * n;
+    const double resid = nnz * (s + 4) + 4 * (n + 1) + 3 * s * n;
+    const double restr = np * (s + 4) + 4 * (nc + 1) + s * (n + nc);
+    const double prol = np * (s + 4) + 4 * (n + 1) + s * (nc + 2 * n);
+    const int sweeps = (nu1 > 0 ? nu1 - 1 : 0) + nu2;
+    tot += sweeps * sweep + (nu1 > 0 ? first : 0) + resid + restr + prol;
+  }
+  const double nL = h->lv[h->L - 1].n;
+  tot += 8.0 * nL * nL + 2 * s * nL;
+  *bytes = tot;
+  return BAMG_OK;
+}
+
+bamg_status bamg_kernel_profile_begin(bamg_handle *h, int32_t kernel) {
+  if (!h || kernel != 0) return BAMG_E_ARG;
+  h->prof_kernel = kernel;
+  h->prof_used = 0;
+  h->prof_bytes = 0.0;
+  h->prof_launches = 0;
+  return BAMG_OK;
+}
+
+bamg_status bamg_kernel_profile_end(bamg_handle *h, int64_t *launches, double *ms_total,
+                                    double *bytes_total) {
+  if (!h) return BAMG_E_ARG;
+  BAMG_TRY
+  double ms = 0.0;
+  if (h->prof_used) HIPCHK(hipStreamSynchronize(h->prof_stream));
+  for (size_t i = 0; i + 1 < h->prof_used; i += 2) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, h->prof_ev[i], h->prof_ev[i + 1]));
+    ms += t;
+  }
+  if (launches) *launches = (int64_t)h->prof_launches;
+  if (ms_total) *ms_total = ms;
+  if (bytes_total) *bytes_total = h->prof_bytes;
+  h->prof_kernel = -1;
+  h->prof_used = 0;
+  return BAMG_OK;
+  BAMG_CATCH
+}
+
 void bamg_destroy(bamg_handle *h) {
   if (!h) return;
+  for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
   h->pool.release_all();
   if (h->hred) (void)hipHostFree(h->hred);
   delete h;

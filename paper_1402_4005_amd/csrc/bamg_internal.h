@@ -46,6 +46,9 @@ struct Pool {
   X *get(size_t count) {
     return static_cast<X *>(raw(sizeof(X) * (count ? count : 1)));
   }
+  std::vector<void *> chunks;    // sub-allocation chunks (in live as well)
+  char *chunk_cur = nullptr;
+  size_t chunk_left = 0;
   std::vector<void *> deferred;  // released temporaries, freed after a sync
   void release(void *p);          // defer the free of a temporary
   void flush();                   // synchronise s, then free the deferred
@@ -100,6 +103,19 @@ struct bamg_handle {
   double *gV = nullptr, *gBV = nullptr, *gw = nullptr, *gx0 = nullptr, *gbx0 = nullptr;
   double *gH = nullptr, *gsc = nullptr;
   void *vb = nullptr, *vx = nullptr;  // FP32 staging for a mixed V-cycle
+  // event timing of one kernel (bamg_kernel_profile_*)
+  int prof_kernel = -1;
+  std::vector<hipEvent_t> prof_ev;  // pairs (start, stop)
+  size_t prof_used = 0;
+  double prof_bytes = 0.0;
+  long prof_launches = 0;
+  hipStream_t prof_stream = nullptr;
+  // input validation running beside the setup on an auxiliary stream
+  hipStream_t aux = nullptr;
+  hipEvent_t aux_ready = nullptr, aux_done = nullptr;
+  int *vflag = nullptr;  // device: [colsum bits, reached forward, reached backward, -]
+  void join_validation(bool wait_main);
+  int validation_result();
 };
 
 namespace bamg {
@@ -141,7 +157,10 @@ void build_B(const int *arp, const int *aci, const double *aval, int n, Pool &po
              double *&bval, hipStream_t s);
 int check_input(Pool &pool, const int *arp, const int *aci, const double *aval, int n, int nnz,
                 hipStream_t s);
-int validate_chain(Pool &pool, const Csr &B, const Csr &Bt, const double *btv, hipStream_t s);
+void colsum_launch(const Csr &Bt, const double *btv, int *flag, hipStream_t s);
+void reach_launch(const Csr &B, const Csr &Bt, int *visited, int *queues, int *flag,
+                  hipStream_t s);
+int validation_status(const int *h, int n);
 void sym_graph(Pool &pool, const Csr &B, const Csr &Bt, Csr &G, hipStream_t s);
 void geom_cf(int n, int nx, int gkind, int *cf, hipStream_t s);
 void mis_cf(Pool &pool, const Csr &G, uint64_t seed, int level, int *cf, hipStream_t s);
@@ -196,6 +215,9 @@ void column_norms(const double *W, int n, double *sv, hipStream_t s);
 void coarse_triplets_out(const double *LM, const double *LN, const double *W, const double *J,
                          const double *sv, int n, int r, void *U, void *V, int prec,
                          double *sigma, double *work, hipStream_t s);
+int coarse_small_max(void);  // largest n the LDS-resident solver takes
+int coarse_small(int mode, int n, int r, const double *Bd, double *Md, double *Nd, void *U,
+                 void *V, int prec, double *sigma, double *bdag, int *flag, hipStream_t s);
 int build_pinv(Pool &pool, const double *W, const double *J, const double *sv, int n,
                double *bdag, hipStream_t s);
 

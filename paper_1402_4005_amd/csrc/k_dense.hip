@@ -392,3 +392,271 @@ int build_pinv(Pool &pool, const double *W, const double *J, const double *sv, i
 }
 
 }  // namespace bamg
+
+namespace bamg {
+
+// ------------------------------------------------ LDS-resident coarse solver
+// One workgroup of 1024 threads solves the whole coarsest-level problem when
+// n is small enough for two n x (n+1) FP64 arrays to live in LDS:
+//   mode 0 (triplets): Cholesky of M and N (in place, global memory), then
+//     C = Bt^T = L_N^-1 B^T L_M^-T in LDS (row k of C = column k of Bt),
+//     one-sided Jacobi on the rows of C with the rotations accumulated in J^T
+//     (LDS), the r smallest sigma, u = L_M^-T C_k / sigma_k and
+//     v = L_N^-T J_k, sign fixed by sum(v) >= 0, u_0 = 1;
+//   mode 1 (pseudo-inverse): the same SVD of B (M = N = I) and
+//     Bdag = sum over k != argmin sigma of J_k (C_k)^T / sigma_k^2.
+// Rows of C and J^T are contiguous, so a pair rotation is two contiguous row
+// updates by one wave; the 16 waves take disjoint pairs of a round.
+constexpr int kSmallThreads = 1024;
+
+// order LDS accesses of one wave: compiler fence plus wave barrier
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ double wave_sum_all(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// right-looking Cholesky in place (lower, row-major, global memory)
+__device__ void chol_block(double *A, int n, int *flag) {
+  __shared__ double piv;
+  const int t = threadIdx.x;
+  for (int j = 0; j < n; ++j) {
+    if (t == 0) {
+      const double d = A[j * n + j];
+      if (!(d > 0.0)) *flag |= 1;
+      piv = d > 0.0 ? sqrt(d) : 1.0;
+      A[j * n + j] = piv;
+    }
+    __syncthreads();
+    const double d = piv;
+    for (int i = j + 1 + t; i < n; i += blockDim.x) A[i * n + j] /= d;
+    __syncthreads();
+    const int m = n - j - 1;
+    for (int e = t; e < m * m; e += blockDim.x) {
+      const int ii = e / m, kk = e % m;
+      if (kk > ii) continue;
+      const int i = j + 1 + ii, k = j + 1 + kk;
+      A[i * n + k] -= A[i * n + j] * A[k * n + j];
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < n * n; e += blockDim.x)
+    if (e % n > e / n) A[e] = 0.0;
+  __syncthreads();
+}
+
+template <class T>
+__global__ void __launch_bounds__(kSmallThreads)
+    k_coarse_small(int mode, int n, int r, const double *__restrict__ Bd, double *__restrict__ Md,
+                   double *__restrict__ Nd, T *__restrict__ U, T *__restrict__ V,
+                   double *__restrict__ sigma, double *__restrict__ bdag, int *__restrict__ flag) {
+  extern __shared__ double lds[];
+  const int ld = n + 1;
+  double *C = lds;                 // n x ld
+  double *Jt = lds + n * ld;       // n x ld, row k = column k of J
+  double *sv = Jt + n * ld;        // n
+  __shared__ int order[16];
+  __shared__ int rotated;
+  __shared__ int kmin;
+  const int t = threadIdx.x, w = t / kWave, lane = t % kWave, nw = kSmallThreads / kWave;
+  if (mode == 0) {
+    chol_block(Md, n, flag);
+    chol_block(Nd, n, flag);
+  }
+  // Y = L_N^-1 B^T (column j per thread), stored in C
+  for (int j = t; j < n; j += blockDim.x) {
+    for (int i = 0; i < n; ++i) {
+      double s = Bd[j * n + i];
+      if (mode == 0) {
+        for (int k = 0; k < i; ++k) s -= Nd[i * n + k] * C[k * ld + j];
+        s /= Nd[i * n + i];
+      }
+      C[i * ld + j] = s;
+    }
+  }
+  __syncthreads();
+  // C = Y L_M^-T (row i per thread, in place)
+  if (mode == 0) {
+    for (int i = t; i < n; i += blockDim.x) {
+      for (int k = 0; k < n; ++k) {
+        double s = C[i * ld + k];
+        for (int j = 0; j < k; ++j) s -= Md[k * n + j] * C[i * ld + j];
+        C[i * ld + k] = s / Md[k * n + k];
+      }
+    }
+  }
+  for (int e = t; e < n * ld; e += blockDim.x) Jt[e] = (e / ld == e % ld) ? 1.0 : 0.0;
+  __syncthreads();
+  // one-sided Jacobi on the rows of C, round-robin pairs
+  const int m = n + (n & 1);
+  const double tol = 1e-15;
+  for (int sweep = 0; sweep < 80; ++sweep) {
+    if (t == 0) rotated = 0;
+    __syncthreads();
+    for (int round = 0; round < m - 1; ++round) {
+      for (int pair = w; pair < m / 2; pair += nw) {
+        int p = rr_index(pair, round, m), q = rr_index(m - 1 - pair, round, m);
+        if (p > q) {
+          const int x = p;
+          p = q;
+          q = x;
+        }
+        if (q >= n) continue;  // dummy column, uniform in the wave
+        double *cp = C + p * ld, *cq = C + q * ld;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = lane; i < n; i += kWave) {
+          const double a = cp[i], b = cq[i];
+          al += a * a;
+          be += b * b;
+          ga += a * b;
+        }
+        al = wave_sum_all(al);
+        be = wave_sum_all(be);
+        ga = wave_sum_all(ga);
+        if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+          double *jp = Jt + p * ld, *jq = Jt + q * ld;
+          for (int i = lane; i < n; i += kWave) {
+            const double a = cp[i], b = cq[i];
+            cp[i] = c * a - sn * b;
+            cq[i] = sn * a + c * b;
+            const double x = jp[i], y = jq[i];
+            jp[i] = c * x - sn * y;
+            jq[i] = sn * x + c * y;
+          }
+          if (lane == 0) rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int any = rotated;
+    __syncthreads();
+    if (!any) break;
+    if (sweep == 79 && t == 0) *flag |= 2;
+  }
+  // singular values
+  for (int k = w; k < n; k += nw) {
+    double s = 0.0;
+    for (int i = lane; i < n; i += kWave) s += C[k * ld + i] * C[k * ld + i];
+    s = wave_sum_all(s);
+    if (lane == 0) sv[k] = sqrt(s);
+  }
+  __syncthreads();
+  if (mode == 1) {
+    if (t == 0) {
+      int km = 0;
+      double smax = 0.0;
+      for (int k = 0; k < n; ++k) {
+        if (sv[k] < sv[km]) km = k;
+        smax = fmax(smax, sv[k]);
+      }
+      double s2 = 1e300;
+      for (int k = 0; k < n; ++k)
+        if (k != km) s2 = fmin(s2, sv[k]);
+      if (!(sv[km] <= 1e-10 * smax) || !(s2 > 1e-13 * smax)) *flag |= 4;
+      kmin = km;
+    }
+    __syncthreads();
+    for (int e = t; e < n * n; e += blockDim.x) {
+      const int i = e / n, j = e % n;
+      double s = 0.0;
+      for (int k = 0; k < n; ++k)
+        if (k != kmin) s += Jt[k * ld + i] * C[k * ld + j] / (sv[k] * sv[k]);
+      bdag[e] = s;
+    }
+    return;
+  }
+  if (t == 0) {
+    for (int q = 0; q < r; ++q) {
+      int best = -1;
+      for (int k = 0; k < n; ++k) {
+        bool taken = false;
+        for (int z = 0; z < q; ++z) taken |= (order[z] == k);
+        if (!taken && (best < 0 || sv[k] < sv[best])) best = k;
+      }
+      order[q] = best;
+    }
+  }
+  __syncthreads();
+  // back-substitutions: wave 2q solves L_M^T u = C_k / sigma_k, wave 2q+1
+  // solves L_N^T v = J_k, in place in the LDS rows (k = order[q]); an entry
+  // is written only by its owning lane (i mod 64)
+  for (int task = w; task < 2 * r; task += nw) {
+    const int q = task / 2, side = task % 2, k = order[q];
+    double *x = side == 0 ? C + k * ld : Jt + k * ld;
+    const double *L = side == 0 ? Md : Nd;
+    if (side == 0) {
+      const double s = sv[k];
+      for (int i = lane; i < n; i += kWave) x[i] = s > 0.0 ? x[i] / s : 0.0;
+    }
+    wave_sync();
+    for (int i = n - 1; i >= 0; --i) {
+      const double xi = mode == 0 ? x[i] / L[i * n + i] : x[i];
+      wave_sync();
+      if (lane == i % kWave) x[i] = xi;
+      for (int z = lane; z < i; z += kWave) x[z] -= L[i * n + z] * xi;
+      wave_sync();
+    }
+  }
+  __syncthreads();
+  // sign of each pair from sum(v); write U, V (n x r row-major) and sigma
+  for (int q = w; q < r; q += nw) {
+    const int k = order[q];
+    double s = 0.0;
+    for (int i = lane; i < n; i += kWave) s += Jt[k * ld + i];
+    s = wave_sum_all(s);
+    const double sg = s < 0.0 ? -1.0 : 1.0;
+    for (int i = lane; i < n; i += kWave) {
+      V[(size_t)i * r + q] = (T)(sg * Jt[k * ld + i]);
+      U[(size_t)i * r + q] = q == 0 ? (T)1 : (T)(sg * C[k * ld + i]);
+    }
+    if (lane == 0) sigma[q] = sv[k];
+  }
+}
+
+size_t coarse_small_lds(int n) { return sizeof(double) * ((size_t)2 * n * (n + 1) + n); }
+
+int coarse_small_max(void) {
+  static int nmax = -1;
+  if (nmax < 0) {
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      lds = 65536;
+    int n = 2;
+    while (coarse_small_lds(n + 1) + 1024 <= (size_t)lds && n < 128) ++n;
+    nmax = n;
+  }
+  return nmax;
+}
+
+int coarse_small(int mode, int n, int r, const double *Bd, double *Md, double *Nd, void *U,
+                 void *V, int prec, double *sigma, double *bdag, int *flag, hipStream_t s) {
+  const size_t shm = coarse_small_lds(n);
+  fill_i32(flag, 0, 1, s);
+  if (prec == 0) {
+    HIPCHK(hipFuncSetAttribute((const void *)k_coarse_small<double>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    k_coarse_small<double><<<1, kSmallThreads, shm, s>>>(mode, n, r, Bd, Md, Nd, (double *)U,
+                                                         (double *)V, sigma, bdag, flag);
+  } else {
+    HIPCHK(hipFuncSetAttribute((const void *)k_coarse_small<float>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    k_coarse_small<float><<<1, kSmallThreads, shm, s>>>(mode, n, r, Bd, Md, Nd, (float *)U,
+                                                        (float *)V, sigma, bdag, flag);
+  }
+  LAUNCHCHK();
+  const int f = read_int(flag, s);
+  if (f & 1) return BAMG_E_COARSE;
+  if (f & 2) return BAMG_E_COARSE;
+  if (f & 4) return BAMG_E_COARSE;
+  return BAMG_OK;
+}
+
+}  // namespace bamg

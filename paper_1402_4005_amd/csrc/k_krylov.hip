@@ -263,11 +263,19 @@ __global__ void __launch_bounds__(kKT) k_scale_min(double *__restrict__ x, int n
   }
 }
 
-__global__ void k_min_final(const double *__restrict__ part, int nblk, double *__restrict__ flags) {
-  if (threadIdx.x != 0) return;
+__global__ void __launch_bounds__(kKT) k_min_final(const double *__restrict__ part, int nblk,
+                                                   double *__restrict__ flags) {
+  __shared__ double sh[kKT / kWave];
   double r = INFINITY;
-  for (int q = 0; q < nblk; ++q) r = fmin(r, part[q]);
-  flags[5] = r;
+  for (int q = threadIdx.x; q < nblk; q += kKT) r = fmin(r, part[q]);
+  for (int off = kWave / 2; off > 0; off >>= 1) r = fmin(r, __shfl_xor(r, off, kWave));
+  if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = sh[0];
+    for (int q = 1; q < kKT / kWave; ++q) m = fmin(m, sh[q]);
+    flags[5] = m;
+  }
 }
 
 void normalize_sum(double *x, int n, double *part, int nblk, double *flags, hipStream_t s) {
@@ -277,7 +285,7 @@ void normalize_sum(double *x, int n, double *part, int nblk, double *flags, hipS
   LAUNCHCHK();
   k_scale_min<<<nblk, kKT, 0, s>>>(x, n, flags, part);
   LAUNCHCHK();
-  k_min_final<<<1, 64, 0, s>>>(part, nblk, flags);
+  k_min_final<<<1, kKT, 0, s>>>(part, nblk, flags);
   LAUNCHCHK();
 }
 

@@ -96,17 +96,29 @@ __global__ void k_colsum_check(const int *__restrict__ trp, const int *__restric
   if (!(fabs(s - 1.0) <= 1e-12)) atomicOr(flag, 2);
 }
 
-// Reachability from state 0 by breadth-first search in one workgroup; the
-// frontier queues live in global memory, the level loop synchronises the
-// block. Returns the number of states reached in *out.
+// Reachability from state 0, forward (block 0, rows of B) and backward
+// (block 1, rows of B^T) in one launch, level-synchronous breadth-first
+// search with the frontier queues in global memory. With LDSMAP the visited
+// set is a bitmap in LDS (n <= kReachLdsStates), so the per-level chain of
+// dependent accesses avoids global atomics.
+constexpr int kReachLdsStates = 1 << 20;
+
+template <bool LDSMAP>
 __global__ void __launch_bounds__(1024)
-    k_bfs_one_block(const int *__restrict__ rp, const int *__restrict__ ci, int n,
-                    int *__restrict__ visited, int *__restrict__ qa, int *__restrict__ qb,
-                    int *__restrict__ out) {
+    k_reach2(const int *__restrict__ rp0, const int *__restrict__ ci0,
+             const int *__restrict__ rp1, const int *__restrict__ ci1, int n,
+             int *__restrict__ visited, int *__restrict__ queues, int *__restrict__ out) {
+  extern __shared__ unsigned bits[];
   __shared__ int cur_n, nxt_n, total;
-  const int t = threadIdx.x;
+  const int b = blockIdx.x, t = threadIdx.x;
+  const int *rp = b ? rp1 : rp0, *ci = b ? ci1 : ci0;
+  int *vis = visited + (size_t)b * n;
+  int *qa = queues + (size_t)b * 2 * n, *qb = qa + n;
+  const int words = (n + 31) >> 5;
+  if (LDSMAP)
+    for (int i = t; i < words; i += blockDim.x) bits[i] = i == 0 ? 1u : 0u;
   if (t == 0) {
-    visited[0] = 1;
+    if (!LDSMAP) vis[0] = 1;
     qa[0] = 0;
     cur_n = 1;
     nxt_n = 0;
@@ -120,10 +132,14 @@ __global__ void __launch_bounds__(1024)
       const int v = cur[idx];
       for (int k = rp[v]; k < rp[v + 1]; ++k) {
         const int u = ci[k];
-        if (atomicCAS(&visited[u], 0, 1) == 0) {
-          const int pos = atomicAdd(&nxt_n, 1);
-          nxt[pos] = u;
+        bool fresh;
+        if (LDSMAP) {
+          const unsigned m = 1u << (u & 31);
+          fresh = (atomicOr(&bits[u >> 5], m) & m) == 0;
+        } else {
+          fresh = atomicCAS(&vis[u], 0, 1) == 0;
         }
+        if (fresh) nxt[atomicAdd(&nxt_n, 1)] = u;
       }
     }
     __syncthreads();
@@ -137,7 +153,27 @@ __global__ void __launch_bounds__(1024)
     cur = nxt;
     nxt = tmp;
   }
-  if (t == 0) *out = total;
+  if (t == 0) out[b] = total;
+}
+
+// Launch the reachability search on stream s (the caller's auxiliary
+// stream); results land in flag[1], flag[2] (states reached each way).
+void reach_launch(const Csr &B, const Csr &Bt, int *visited, int *queues, int *flag,
+                  hipStream_t s) {
+  const int n = B.nr;
+  const size_t shm = sizeof(unsigned) * (size_t)((n + 31) / 32);
+  int dev = 0, maxlds = 65536;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  if (n <= kReachLdsStates && shm + 256 <= (size_t)maxlds) {
+    HIPCHK(hipFuncSetAttribute((const void *)k_reach2<true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    k_reach2<true><<<2, 1024, shm, s>>>(B.rp, B.ci, Bt.rp, Bt.ci, n, visited, queues, flag + 1);
+  } else {
+    fill_i32(visited, 0, 2 * (size_t)n, s);
+    k_reach2<false><<<2, 1024, 0, s>>>(B.rp, B.ci, Bt.rp, Bt.ci, n, visited, queues, flag + 1);
+  }
+  LAUNCHCHK();
 }
 
 // Structural checks of the caller's CSR (indices in range, ascending,
@@ -161,29 +197,15 @@ int check_input(Pool &pool, const int *arp, const int *aci, const double *aval, 
 }
 
 // Column sums of A equal to 1 (through B^T, whose values btv are B's
-// permuted) and strong connectivity (reachability from state 0 along the
-// rows of B and of B^T).
-int validate_chain(Pool &pool, const Csr &B, const Csr &Bt, const double *btv, hipStream_t s) {
-  const int n = B.nr;
-  int *flag = pool.get<int>(4);
-  fill_i32(flag, 0, 4, s);
-  k_colsum_check<<<ceil_div(n, 256), 256, 0, s>>>(Bt.rp, Bt.ci, btv, n, flag);
+// permuted): flag[0] bit 1 on failure. Enqueued on s, read at the join.
+void colsum_launch(const Csr &Bt, const double *btv, int *flag, hipStream_t s) {
+  k_colsum_check<<<ceil_div(Bt.nr, 256), 256, 0, s>>>(Bt.rp, Bt.ci, btv, Bt.nr, flag);
   LAUNCHCHK();
-  int *visited = pool.get<int>(n);
-  int *qa = pool.get<int>(n), *qb = pool.get<int>(n);
-  for (int pass = 0; pass < 2; ++pass) {
-    const Csr &G = pass ? Bt : B;
-    fill_i32(visited, 0, n, s);
-    k_bfs_one_block<<<1, 1024, 0, s>>>(G.rp, G.ci, n, visited, qa, qb, flag + 1 + pass);
-    LAUNCHCHK();
-  }
-  int h[4];
-  HIPCHK(hipMemcpyAsync(h, flag, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  pool.release(visited);
-  pool.release(qa);
-  pool.release(qb);
-  pool.release(flag);
+}
+
+// Status from the validation flags (host copy): stochastic columns, then
+// strong connectivity (all states reached from state 0 both ways).
+int validation_status(const int *h, int n) {
   if (h[0] & 2) return BAMG_E_NOT_STOCHASTIC;
   if (h[1] != n || h[2] != n) return BAMG_E_REDUCIBLE;
   return BAMG_OK;
@@ -1003,19 +1025,20 @@ void pair_products(const Level &L, int r, const T *U, const T *V, int which, dou
   LAUNCHCHK();
 }
 
-// out[t*16 + k] = sum over blocks, in block order
-__global__ void k_finalize_products(const double *__restrict__ part, int nblk,
-                                    double *__restrict__ out) {
-  const int t = threadIdx.x;  // 0..79
-  if (t >= 5 * kPPLanes) return;
+// out[t*16 + k] = sum over blocks; one block per output, fixed reduction tree
+__global__ void __launch_bounds__(256) k_finalize_products(const double *__restrict__ part,
+                                                           int nblk, double *__restrict__ out) {
+  __shared__ double sh[4];
+  const int o = blockIdx.x;  // 0..79
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * 5 * kPPLanes + t];
-  out[t] = s;
+  for (int b = threadIdx.x; b < nblk; b += 256) s += part[(size_t)b * 5 * kPPLanes + o];
+  s = block_sum<256>(s, sh);
+  if (threadIdx.x == 0) out[o] = s;
 }
 
 void finalize_products(const double *part, int nblk, int r, double *out, hipStream_t s) {
   (void)r;
-  k_finalize_products<<<1, 5 * kPPLanes, 0, s>>>(part, nblk, out);
+  k_finalize_products<<<5 * kPPLanes, 256, 0, s>>>(part, nblk, out);
   LAUNCHCHK();
 }
 

@@ -172,6 +172,12 @@ struct Setup {
     csr_to_dense(C.B, C.Bv, h->prec, Bd, s);
     csr_to_dense(C.M, C.Mv, h->prec, Md, s);
     csr_to_dense(C.M, C.Nv, h->prec, Nd, s);
+    if (n <= coarse_small_max()) {
+      if (coarse_small(0, n, r, Bd, Md, Nd, C.U, C.V, h->prec, h->sigma, nullptr, flag, s) !=
+          BAMG_OK)
+        fail(BAMG_E_COARSE, "coarsest generalized SVD failed (M_L, N_L not SPD or no convergence)");
+      return;
+    }
     if (cholesky(Md, n, s) != BAMG_OK || cholesky(Nd, n, s) != BAMG_OK)
       fail(BAMG_E_COARSE, "coarsest M_L or N_L not positive definite");
     HIPCHK(hipMemcpyAsync(X, Bd, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToDevice, s));
@@ -187,10 +193,16 @@ struct Setup {
     Level &C = h->lv[h->L - 1];
     const int n = C.n;
     csr_to_dense(C.B, C.Bv, h->prec, Bd, s);
+    h->bdag = pool().template get<double>((size_t)n * n);
+    if (n <= coarse_small_max()) {
+      if (coarse_small(1, n, r, Bd, nullptr, nullptr, nullptr, nullptr, h->prec, nullptr, h->bdag,
+                       flag, s) != BAMG_OK)
+        fail(BAMG_E_COARSE, "coarsest operator is not of rank n_L - 1");
+      return;
+    }
     transpose_dense(Bd, W, n, s);  // W = B_L column-major
     if (jacobi_svd(pool(), W, J, n, s) != BAMG_OK) fail(BAMG_E_COARSE, "Jacobi SVD did not converge");
     column_norms(W, n, sv, s);
-    h->bdag = pool().template get<double>((size_t)n * n);
     if (build_pinv(pool(), W, J, sv, n, h->bdag, s) != BAMG_OK)
       fail(BAMG_E_COARSE, "coarsest operator is not of rank n_L - 1");
   }
@@ -273,8 +285,23 @@ void setup_all(bamg_handle *h, const bamg_csr *A, const bamg_geometry *geom) {
     double *bt64 = pool.get<double>(L0.B.nnz);
     copy_permuted<double>(bt64, b64, L0.btperm, L0.B.nnz, s);
     if (o.validate) {
-      st = validate_chain(pool, L0.B, L0.Bt, bt64, s);
-      if (st != BAMG_OK) fail(st, "transition matrix rejected");
+      // column sums on the main stream; reachability (a long chain of small
+      // dependent steps on two CUs) beside the setup on an auxiliary stream,
+      // joined before bamg_setup returns
+      h->vflag = pool.get<int>(4);
+      fill_i32(h->vflag, 0, 4, s);
+      colsum_launch(L0.Bt, bt64, h->vflag, s);
+      HIPCHK(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&h->aux_ready, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&h->aux_done, hipEventDisableTiming));
+      HIPCHK(hipEventRecord(h->aux_ready, s));
+      HIPCHK(hipStreamWaitEvent(h->aux, h->aux_ready, 0));
+      int *visited = pool.get<int>(2 * (size_t)n);
+      int *queues = pool.get<int>(4 * (size_t)n);
+      reach_launch(L0.B, L0.Bt, visited, queues, h->vflag, h->aux);
+      HIPCHK(hipEventRecord(h->aux_done, h->aux));
+      pool.release(visited);
+      pool.release(queues);
     }
     L0.dpos = pool.get<int>(n);
     diag_positions(L0.B, L0.dpos, s);
@@ -417,6 +444,9 @@ void setup_all(bamg_handle *h, const bamg_csr *A, const bamg_geometry *geom) {
   normalize_sum(h->x0, n, part, nb, fl, s);
   pool.release(part);
   pool.release(fl);
+  h->join_validation(true);
+  st = h->validation_result();
+  if (st != BAMG_OK) fail(st, "transition matrix rejected");
   HIPCHK(hipStreamSynchronize(s));
   pool.flush();
 }

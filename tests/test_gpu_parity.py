@@ -131,3 +131,30 @@ def test_error_codes():
     with pytest.raises(bamg.BamgError) as e:
         bamg.Hierarchy.from_chain(bad, bamg.options_for(ch, r=6, max_levels=2, coarse_max=1))
     assert e.value.code == -2
+
+
+def test_reducible_chain_rejected():
+    import scipy.sparse as sp
+    # two disjoint 3-cycles with self-loops: column stochastic, not irreducible
+    A = sp.lil_matrix((6, 6))
+    for i in range(3):
+        A[(i + 1) % 3, i] = 0.5
+        A[i, i] = 0.5
+        A[3 + (i + 1) % 3, 3 + i] = 0.5
+        A[3 + i, 3 + i] = 0.5
+    ch = chaingen.Chain(A.tocsr())
+    with pytest.raises(bamg.BamgError) as e:
+        bamg.Hierarchy.from_chain(ch, bamg.default_options(r=2, coarsening="mis", coarse_max=1,
+                                                           max_levels=2))
+    assert e.value.code == -3
+
+
+def test_setup_deterministic():
+    ch = chaingen.delaunay_walk(3000, 12)
+    kw = dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99)
+    h1 = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, **kw))
+    h2 = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, **kw))
+    for l in range(h1.levels):
+        for what in ("B", "M", "N"):
+            assert np.array_equal(h1.csr(l, what)[2], h2.csr(l, what)[2])
+    assert np.array_equal(h1.sigma(), h2.sigma())
