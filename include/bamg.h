@@ -96,6 +96,7 @@ typedef struct {
   int32_t precision;    /* BAMG_PRECISION_FP64 or BAMG_PRECISION_MIXED */
   int32_t interp_rule;  /* 0 = plain LS over J_i, 1 = LS with negative weights removed */
   int32_t validate;     /* 1 = check stochasticity and strong connectivity */
+  int32_t use_graph;    /* 1 = GMRES replays the V-cycle from a captured HIP graph */
 } bamg_options;
 
 /* Device allocator used for every library allocation (NULL = hipMalloc /

@@ -47,7 +47,8 @@ class Options(C.Structure):
                 ("nu_post", C.c_int32), ("nu_setup", C.c_int32), ("omega", C.c_double),
                 ("max_interp", C.c_int32), ("max_levels", C.c_int32), ("coarse_max", C.c_int32),
                 ("coarsening", C.c_int32), ("seed", C.c_uint64), ("smoother", C.c_int32),
-                ("precision", C.c_int32), ("interp_rule", C.c_int32), ("validate", C.c_int32)]
+                ("precision", C.c_int32), ("interp_rule", C.c_int32), ("validate", C.c_int32),
+                ("use_graph", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

@@ -162,6 +162,7 @@ bamg_status bamg_default_options(bamg_options *o) {
   o->precision = BAMG_PRECISION_FP64;
   o->interp_rule = 1;
   o->validate = 1;
+  o->use_graph = 1;
   return BAMG_OK;
 }
 
@@ -216,6 +217,7 @@ bamg_status bamg_setup(const bamg_csr *A, const bamg_geometry *geom, const bamg_
   if (!h) return BAMG_E_NOMEM;
   h->opt = *opt;
   h->prec = opt->precision == BAMG_PRECISION_MIXED ? 1 : 0;
+  h->use_graph = opt->use_graph ? 1 : 0;
   h->pool.s = (hipStream_t)hip_stream;
   if (alloc) {
     h->pool.a = *alloc;
@@ -465,6 +467,8 @@ bamg_status bamg_kernel_profile_end(bamg_handle *h, int64_t *launches, double *m
 void bamg_destroy(bamg_handle *h) {
   if (!h) return;
   for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
+  if (h->vc_exec) (void)hipGraphExecDestroy(h->vc_exec);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   h->pool.release_all();
   if (h->hred) (void)hipHostFree(h->hred);
   delete h;

@@ -103,6 +103,10 @@ struct bamg_handle {
   double *gV = nullptr, *gBV = nullptr, *gw = nullptr, *gx0 = nullptr, *gbx0 = nullptr;
   double *gH = nullptr, *gsc = nullptr;
   void *vb = nullptr, *vx = nullptr;  // FP32 staging for a mixed V-cycle
+  double *vcin = nullptr;             // fixed V-cycle input inside GMRES
+  hipGraphExec_t vc_exec = nullptr;   // captured V-cycle: vcin -> gw
+  hipStream_t cap_stream = nullptr;   // stream the V-cycle is captured on
+  int use_graph = 1;
   // event timing of one kernel (bamg_kernel_profile_*)
   int prof_kernel = -1;
   std::vector<hipEvent_t> prof_ev;  // pairs (start, stop)
@@ -215,6 +219,7 @@ void column_norms(const double *W, int n, double *sv, hipStream_t s);
 void coarse_triplets_out(const double *LM, const double *LN, const double *W, const double *J,
                          const double *sv, int n, int r, void *U, void *V, int prec,
                          double *sigma, double *work, hipStream_t s);
+void zero_colsums(double *D, int n, hipStream_t s);  // D[j][j] -= sum_i D[i][j]
 int coarse_small_max(void);  // largest n the LDS-resident solver takes
 int coarse_small(int mode, int n, int r, const double *Bd, double *Md, double *Nd, void *U,
                  void *V, int prec, double *sigma, double *bdag, int *flag, hipStream_t s);

@@ -491,38 +491,41 @@ __global__ void __launch_bounds__(kSmallThreads)
   }
   for (int e = t; e < n * ld; e += blockDim.x) Jt[e] = (e / ld == e % ld) ? 1.0 : 0.0;
   __syncthreads();
-  // one-sided Jacobi on the rows of C, round-robin pairs
+  // one-sided Jacobi on the rows of C, round-robin pairs; each pair is
+  // handled by a group of kPairLanes lanes so a round's pairs run together
+  constexpr int kPairLanes = 16;
+  const int grp = t / kPairLanes, gl = t % kPairLanes, ngrp = kSmallThreads / kPairLanes;
   const int m = n + (n & 1);
   const double tol = 1e-15;
   for (int sweep = 0; sweep < 80; ++sweep) {
     if (t == 0) rotated = 0;
     __syncthreads();
     for (int round = 0; round < m - 1; ++round) {
-      for (int pair = w; pair < m / 2; pair += nw) {
+      for (int pair = grp; pair < m / 2; pair += ngrp) {
         int p = rr_index(pair, round, m), q = rr_index(m - 1 - pair, round, m);
         if (p > q) {
           const int x = p;
           p = q;
           q = x;
         }
-        if (q >= n) continue;  // dummy column, uniform in the wave
+        if (q >= n) continue;  // dummy column, uniform in the group
         double *cp = C + p * ld, *cq = C + q * ld;
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = lane; i < n; i += kWave) {
+        for (int i = gl; i < n; i += kPairLanes) {
           const double a = cp[i], b = cq[i];
           al += a * a;
           be += b * b;
           ga += a * b;
         }
-        al = wave_sum_all(al);
-        be = wave_sum_all(be);
-        ga = wave_sum_all(ga);
+        al = group_sum(al, kPairLanes);
+        be = group_sum(be, kPairLanes);
+        ga = group_sum(ga, kPairLanes);
         if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
           const double zeta = (be - al) / (2.0 * ga);
           const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
           double *jp = Jt + p * ld, *jq = Jt + q * ld;
-          for (int i = lane; i < n; i += kWave) {
+          for (int i = gl; i < n; i += kPairLanes) {
             const double a = cp[i], b = cq[i];
             cp[i] = c * a - sn * b;
             cq[i] = sn * a + c * b;
@@ -530,7 +533,7 @@ __global__ void __launch_bounds__(kSmallThreads)
             jp[i] = c * x - sn * y;
             jq[i] = sn * x + c * y;
           }
-          if (lane == 0) rotated = 1;
+          if (gl == 0) rotated = 1;
         }
       }
       __syncthreads();
@@ -657,6 +660,27 @@ int coarse_small(int mode, int n, int r, const double *Bd, double *Md, double *N
   if (f & 2) return BAMG_E_COARSE;
   if (f & 4) return BAMG_E_COARSE;
   return BAMG_OK;
+}
+
+}  // namespace bamg
+
+namespace bamg {
+
+// Section 5 makes the column sums of every B_l zero (1^T B_l = 0). A
+// coarsest operator built in FP32 keeps them only to FP32 accuracy; in FP64
+// the residue of each column is moved into its diagonal so the dense
+// operator has the exact left null vector again.
+__global__ void k_zero_colsums(double *__restrict__ D, int n) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += D[(size_t)i * n + j];
+  D[(size_t)j * n + j] -= s;
+}
+
+void zero_colsums(double *D, int n, hipStream_t s) {
+  k_zero_colsums<<<ceil_div(n, 64), 64, 0, s>>>(D, n);
+  LAUNCHCHK();
 }
 
 }  // namespace bamg

@@ -612,12 +612,69 @@ __global__ void k_spgemm_num(int nr, const int *__restrict__ arp, const int *__r
   }
 }
 
+// Same products and term order; rows of C with at most kNumAcc entries
+// accumulate in the thread's private LDS slice (laid out position-major so
+// the threads of a wave hit distinct banks) and are written once.
+constexpr int kNumThreads = 128, kNumAcc = 32;
+
+template <class T>
+__global__ void __launch_bounds__(kNumThreads)
+    k_spgemm_num_lds(int nr, const int *__restrict__ arp, const int *__restrict__ aci,
+                     const T *__restrict__ av, const int *__restrict__ brp,
+                     const int *__restrict__ bci, const T *__restrict__ bv,
+                     const int *__restrict__ crp, const int *__restrict__ cci,
+                     T *__restrict__ cv) {
+  __shared__ T acc[kNumAcc * kNumThreads];
+  const int t = threadIdx.x;
+  const int i = blockIdx.x * kNumThreads + t;
+  if (i >= nr) return;
+  const int c0 = crp[i], c1 = crp[i + 1];
+  if (c1 - c0 > kNumAcc) {
+    for (int p = c0; p < c1; ++p) cv[p] = (T)0;
+    for (int a = arp[i]; a < arp[i + 1]; ++a) {
+      const int k = aci[a];
+      const T x = av[a];
+      for (int b = brp[k]; b < brp[k + 1]; ++b) {
+        const int j = bci[b];
+        int lo = c0, hi = c1 - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (cci[mid] < j)
+            lo = mid + 1;
+          else
+            hi = mid;
+        }
+        cv[lo] += x * bv[b];
+      }
+    }
+    return;
+  }
+  for (int q = 0; q < c1 - c0; ++q) acc[q * kNumThreads + t] = (T)0;
+  for (int a = arp[i]; a < arp[i + 1]; ++a) {
+    const int k = aci[a];
+    const T x = av[a];
+    for (int b = brp[k]; b < brp[k + 1]; ++b) {
+      const int j = bci[b];
+      int lo = c0, hi = c1 - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cci[mid] < j)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      acc[(lo - c0) * kNumThreads + t] += x * bv[b];
+    }
+  }
+  for (int q = 0; q < c1 - c0; ++q) cv[c0 + q] = acc[q * kNumThreads + t];
+}
+
 template <class T>
 void spgemm_numeric(const Csr &A, const T *av, const Csr &B, const T *bv, const Csr &C, T *cv,
                     hipStream_t s) {
   if (!A.nr) return;
-  k_spgemm_num<T><<<ceil_div(A.nr, 128), 128, 0, s>>>(A.nr, A.rp, A.ci, av, B.rp, B.ci, bv, C.rp,
-                                                      C.ci, cv);
+  k_spgemm_num_lds<T><<<ceil_div(A.nr, kNumThreads), kNumThreads, 0, s>>>(
+      A.nr, A.rp, A.ci, av, B.rp, B.ci, bv, C.rp, C.ci, cv);
   LAUNCHCHK();
 }
 
@@ -1233,6 +1290,7 @@ __global__ void k_row_inv_norms(int n, const int *__restrict__ rp, const T *__re
 }
 template <class T>
 void row_inv_norms(const Csr &A, const T *val, T *out, hipStream_t s) {
+  if (!out || !val) fail(BAMG_E_DEVICE, "row_inv_norms: missing buffer");
   k_row_inv_norms<T><<<ceil_div(A.nr, 256), 256, 0, s>>>(A.nr, A.rp, val, out);
   LAUNCHCHK();
 }

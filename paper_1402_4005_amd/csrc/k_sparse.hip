@@ -116,6 +116,7 @@ template <class T>
 void kaczmarz_colour(const Csr &A, const T *val, const T *rowinv, const int *rows, int nrows,
                      const T *b, T *x, hipStream_t s) {
   if (nrows <= 0) return;
+  if (!rowinv || !rows || !val) fail(BAMG_E_DEVICE, "kaczmarz_colour: missing buffer");
   k_kaczmarz<T><<<ceil_div(nrows, 128), 128, 0, s>>>(A.rp, A.ci, val, rowinv, rows, nrows, b, x);
   LAUNCHCHK();
 }

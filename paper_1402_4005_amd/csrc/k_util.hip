@@ -185,6 +185,40 @@ __global__ void k_sort_segments(const int *__restrict__ rp, int nr, int *__restr
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nr) return;
   int a = rp[j], b = rp[j + 1];
+  constexpr int kReg = 32;
+  if (b - a <= kReg) {
+    // short segment: sort in registers, one read and one write per entry
+    int kk[kReg], vv[kReg];
+    const int m = b - a;
+#pragma unroll
+    for (int p = 0; p < kReg; ++p)
+      if (p < m) {
+        kk[p] = key[a + p];
+        vv[p] = val[a + p];
+      }
+#pragma unroll
+    for (int p = 1; p < kReg; ++p) {
+      if (p >= m) break;
+      // insertion of element p, expressed with compile-time indices
+#pragma unroll
+      for (int q = p; q > 0; --q) {
+        if (kk[q - 1] > kk[q]) {
+          const int t0 = kk[q - 1], t1 = vv[q - 1];
+          kk[q - 1] = kk[q];
+          vv[q - 1] = vv[q];
+          kk[q] = t0;
+          vv[q] = t1;
+        }
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < kReg; ++p)
+      if (p < m) {
+        key[a + p] = kk[p];
+        val[a + p] = vv[p];
+      }
+    return;
+  }
   for (int p = a + 1; p < b; ++p) {
     int kk = key[p], vv = val[p];
     int q = p - 1;

@@ -122,7 +122,9 @@ struct Setup {
     spgemm_numeric<T>(L.Pc, (const T *)L.Ptv, L.T2, (const T *)L.T3v, C.M, (T *)C.Nv, s);
     copy_permuted<T>((T *)C.Btv, (const T *)C.Bv, C.btperm, C.B.nnz, s);
     dinv_from_diag<T>(C, (const T *)C.Bv, (T *)C.dinv, flag, s);
-    if (h->opt.smoother == BAMG_SMOOTH_KACZMARZ) {
+    // Kaczmarz row norms exist only where the smoother runs (not on the
+    // coarsest level, which is solved directly)
+    if (h->opt.smoother == BAMG_SMOOTH_KACZMARZ && l + 1 < h->L - 1) {
       row_inv_norms<T>(C.B, (const T *)C.Bv, (T *)C.rowinvB, s);
       row_inv_norms<T>(C.Bt, (const T *)C.Btv, (T *)C.rowinvBt, s);
     }
@@ -170,6 +172,7 @@ struct Setup {
     Level &C = h->lv[h->L - 1];
     const int n = C.n;
     csr_to_dense(C.B, C.Bv, h->prec, Bd, s);
+    if (h->prec) zero_colsums(Bd, n, s);
     csr_to_dense(C.M, C.Mv, h->prec, Md, s);
     csr_to_dense(C.M, C.Nv, h->prec, Nd, s);
     if (n <= coarse_small_max()) {
@@ -193,6 +196,7 @@ struct Setup {
     Level &C = h->lv[h->L - 1];
     const int n = C.n;
     csr_to_dense(C.B, C.Bv, h->prec, Bd, s);
+    if (h->prec) zero_colsums(Bd, n, s);
     h->bdag = pool().template get<double>((size_t)n * n);
     if (n <= coarse_small_max()) {
       if (coarse_small(1, n, r, Bd, nullptr, nullptr, nullptr, nullptr, h->prec, nullptr, h->bdag,

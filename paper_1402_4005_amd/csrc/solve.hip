@@ -127,6 +127,53 @@ static void precondition(bamg_handle *h, const double *b, double *x, hipStream_t
   convert<float, double>(x, (const float *)h->vx, n, s);
 }
 
+// y1 = y2 = A x (the second copy feeds the captured V-cycle)
+__global__ void k_spmv_dual(int nr, const int *__restrict__ rp, const int *__restrict__ ci,
+                            const double *__restrict__ val, const double *__restrict__ x,
+                            double *__restrict__ y1, double *__restrict__ y2) {
+  const int gid = blockIdx.x * 256 + threadIdx.x;
+  const int row = gid / 8, lane = gid % 8;
+  if (row >= nr) return;
+  double sum = 0.0;
+  for (int k = rp[row] + lane; k < rp[row + 1]; k += 8) sum += val[k] * x[ci[k]];
+  sum = group_sum(sum, 8);
+  if (lane == 0) {
+    y1[row] = sum;
+    y2[row] = sum;
+  }
+}
+
+// C applied to the fixed input buffer h->vcin, result in h->gw. The launch
+// sequence of one V-cycle (about ten kernels per level) is captured once
+// into a HIP graph and replayed, which removes per-launch host overhead.
+static void precondition_fixed(bamg_handle *h, hipStream_t s) {
+  if (!h->use_graph || h->prof_kernel >= 0) {
+    precondition(h, h->vcin, h->gw, s);
+    return;
+  }
+  if (!h->vc_exec) {
+    // captured on a library stream (the caller's may be the null stream,
+    // which cannot be captured), launched on the caller's stream
+    if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    hipStream_t cs = h->cap_stream;
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+    hipGraph_t g = nullptr;
+    try {
+      precondition(h, h->vcin, h->gw, cs);
+    } catch (...) {
+      (void)hipStreamEndCapture(cs, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HIPCHK(hipStreamEndCapture(cs, &g));
+    const hipError_t e = hipGraphInstantiate(&h->vc_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(e);
+  }
+  HIPCHK(hipGraphLaunch(h->vc_exec, s));
+}
+
 __global__ void k_krylov_start(const double *__restrict__ h1, double *__restrict__ g, int m,
                                double *__restrict__ flags) {
   if (threadIdx.x != 0) return;
@@ -158,6 +205,11 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
       h->vx = pool.get<float>(n);
     }
     if (!h->hred) HIPCHK(hipHostMalloc((void **)&h->hred, sizeof(double) * 16, 0));
+    if (!h->vcin) h->vcin = pool.get<double>(n);
+    if (h->vc_exec) {
+      (void)hipGraphExecDestroy(h->vc_exec);  // it wrote into the old gw
+      h->vc_exec = nullptr;
+    }
     h->gm_m = m;
   }
   double *H = h->gH;
@@ -168,7 +220,6 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
   double *part3 = part2 + nblk;                   // 2 nblk: residual-check partials
   double *coef = pool.get<double>(2 * (size_t)(m + 2));
   double *c1 = coef, *c2 = coef + (m + 2);  // the two Gram-Schmidt passes
-  double *negb = pool.get<double>(n);
 
   if (use_x0)
     HIPCHK(hipMemcpyAsync(h->gx0, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
@@ -193,8 +244,8 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
   bamg_status st = BAMG_OK;
   while (!conv && it < maxit) {
     spmv<double>(B, h->B64, h->gx0, h->gbx0, nullptr, 0, lanes, s);  // B x0
-    negate_copy(h->gbx0, negb, n, s);                                 // r0 = -B x0
-    precondition(h, negb, h->gw, s);                                  // z = C r0
+    negate_copy(h->gbx0, h->vcin, n, s);                              // r0 = -B x0
+    precondition_fixed(h, s);                                         // z = C r0
     multi_dot(h->gV, n, 0, h->gw, part, nblk, s);
     finalize_multi(part, nblk, 1, c1, s);
     k_krylov_start<<<1, 64, 0, s>>>(c1, g, m, flags);
@@ -204,8 +255,10 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
     bool broke = false;
     for (int j = 0; j < m && it < maxit; ++j) {
       double *vj = h->gV + (size_t)j * n, *bvj = h->gBV + (size_t)j * n;
-      spmv<double>(B, h->B64, vj, bvj, nullptr, 0, lanes, s);  // B v_j
-      precondition(h, bvj, h->gw, s);                         // w = C B v_j
+      k_spmv_dual<<<ceil_div((long)n * 8, 256), 256, 0, s>>>(n, B.rp, B.ci, h->B64, vj, bvj,
+                                                             h->vcin);  // B v_j
+      LAUNCHCHK();
+      precondition_fixed(h, s);  // w = C B v_j
       // Gram-Schmidt, twice
       multi_dot(h->gV, n, j + 1, h->gw, part, nblk, s);
       finalize_multi(part, nblk, j + 2, c1, s);  // c1[0..j], c1[j+1] = |w|^2
@@ -257,7 +310,6 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   pool.release(coef);
-  pool.release(negb);
   pool.flush();
   if (st != BAMG_OK) fail(st, "GMRES failed");
   if (!conv) throw Error{BAMG_NOT_CONVERGED, "iteration cap reached"};

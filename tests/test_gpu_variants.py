@@ -1,0 +1,92 @@
+"""GPU tests of the variants beside plain FP64 Jacobi: the mixed-precision
+form (FP32 setup and V-cycles, FP64 Krylov, residual, normalisation and
+coarsest solve) and the Kaczmarz smoother. Both are compared with the FP64
+CPU oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+
+import chaingen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+bamg = pytest.importorskip("paper_1402_4005_amd")
+
+
+def rel_l1(x, y):
+    return float(np.abs(x - y).sum() / np.abs(y).sum())
+
+
+MIXED = [
+    ("tandem65_random", lambda: chaingen.tandem(65, *chaingen.tandem_random_rates(14024003)),
+     dict(r=8, coarse_max=99)),
+    ("delaunay3000", lambda: chaingen.delaunay_walk(3000, 12),
+     dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99)),
+]
+
+
+@pytest.mark.parametrize("name,make,kw", MIXED, ids=[c[0] for c in MIXED])
+def test_mixed_precision_structure_and_solution(name, make, kw):
+    import torch
+    ch = make()
+    ho = oracle.Hierarchy(ch, oracle.options_for(ch, **kw))
+    hm = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, precision="mixed", **kw))
+    # integer structure does not depend on the precision
+    assert ho.levels == hm.levels
+    for l in range(ho.levels - 1):
+        assert np.array_equal(ho.cf(l)[0], hm.cf(l)[0])
+        for what in ("P", "Q"):
+            assert np.array_equal(ho.csr(l, what)[1], hm.csr(l, what)[1])
+    # FP32 transfer weights agree with the FP64 oracle to FP32 accuracy
+    for l in range(ho.levels - 1):
+        a, b = hm.csr(l, "P")[2], ho.csr(l, "P")[2]
+        assert np.abs(a - b).max() < 2e-3 * max(1.0, np.abs(b).max())
+    xo, io = ho.gmres(m=20, tol=1e-13, maxit=600)
+    xm, im = hm.gmres(restart=20, tol=1e-13, maxit=600)
+    torch.cuda.synchronize()
+    assert im.converged, im.as_dict()
+    # the FP64 true-residual test decides convergence, so x reaches FP64 accuracy
+    assert rel_l1(xm.cpu().numpy(), xo) < 1e-10
+
+
+def test_mixed_vcycle_f32_entry():
+    import torch
+    ch = chaingen.tandem(33, 11 / 31, 10 / 31, 10 / 31)
+    kw = dict(r=6, max_levels=3, coarse_max=1)
+    ho = oracle.Hierarchy(ch, oracle.options_for(ch, **kw))
+    hm = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, precision="mixed", **kw))
+    b = np.random.default_rng(3).standard_normal(ch.n)
+    xo = ho.vcycle(b)
+    x32 = hm.vcycle(torch.from_numpy(b.astype(np.float32)).cuda()).cpu().numpy()
+    x64 = hm.vcycle(torch.from_numpy(b).cuda()).cpu().numpy()
+    scale = np.abs(xo).max()
+    assert np.abs(x32 - xo).max() < 1e-3 * scale
+    assert np.abs(x64 - x32).max() < 1e-6 * scale
+
+
+KACZ = [
+    ("tandem14_2lev", lambda: chaingen.tandem(14, 11 / 31, 10 / 31, 10 / 31),
+     dict(r=6, max_levels=2, coarse_max=1)),
+    ("delaunay1500", lambda: chaingen.delaunay_walk(1500, 4),
+     dict(r=8, max_interp=3, nu_pre=2, nu_post=2, nu_setup=2, coarse_max=99)),
+]
+
+
+@pytest.mark.parametrize("name,make,kw", KACZ, ids=[c[0] for c in KACZ])
+def test_kaczmarz_matches_oracle(name, make, kw):
+    import torch
+    ch = make()
+    ho = oracle.Hierarchy(ch, oracle.options_for(ch, smoother="kaczmarz", **kw))
+    hg = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, smoother="kaczmarz", **kw))
+    for l in range(1, ho.levels):
+        a, b = hg.csr(l, "B")[2], ho.csr(l, "B")[2]
+        assert np.abs(a - b).max() < 1e-8 * np.abs(b).max(), l
+    b = np.random.default_rng(8).standard_normal(ch.n)
+    xo = ho.vcycle(b)
+    xg = hg.vcycle(torch.from_numpy(b).cuda()).cpu().numpy()
+    assert np.abs(xg - xo).max() < 1e-8 * np.abs(xo).max()
+    xo, io = ho.gmres(m=20, tol=1e-13, maxit=400)
+    xg, ig = hg.gmres(restart=20, tol=1e-13, maxit=400)
+    torch.cuda.synchronize()
+    assert ig.converged and io.converged
+    assert rel_l1(xg.cpu().numpy(), xo) < 1e-10
