@@ -25,13 +25,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X published HBM3E bandwidth
+METRIC = ("time to \u2016Bx\u2016/\u2016x\u2016<1e-10 + V-cycle HBM GB/s; "
+          "mixed/learned vs plain FP64")
 
 WORKLOADS = {
     # name: (kind, size, options)
     "delaunay262144": ("delaunay", 262144, dict(r=8, max_interp=3, nu_pre=5, nu_post=5,
                                                  nu_setup=5, coarse_max=99, seed=14024002)),
-    "tandem1025": ("tandem_random", 1025, dict(r=8, max_interp=4, coarse_max=99,
-                                               seed=14024003)),
+    # Table 3's rates (lam = 11/31, mu1 = mu2 = 10/31) on a 1025 x 1025 grid,
+    # 7 levels down to 17 x 17 as in Section 7; 8 test-vector sweeps
+    "tandem1025": ("tandem", 1025, dict(r=8, max_interp=4, coarse_max=300, nu_setup=8,
+                                        seed=14024003)),
+    # rates drawn U[0.2, 0.5] and normalised (seed 14024003: 0.302, 0.230, 0.468)
+    "tandem1025_random": ("tandem_random", 1025, dict(r=8, max_interp=4, coarse_max=300,
+                                                      nu_setup=8, seed=14024003)),
     "tandem33": ("tandem", 33, dict(r=6, max_interp=4, max_levels=3, coarse_max=1,
                                     seed=14024001)),
 }
@@ -58,6 +65,12 @@ def main():
     ap.add_argument("--restart", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--vcycle-reps", type=int, default=100)
+    ap.add_argument("--maxit", type=int, default=1000)
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision comparison run")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device-to-device copies of MIB MiB (the known "
+                         "byte count that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -68,42 +81,83 @@ def main():
     import numpy as np
     import torch
 
+    if args.copy_calibration:
+        nel = args.copy_calibration * (1 << 20) // 8
+        a = torch.ones(nel, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": nel * 8, "bytes_written": nel * 8,
+                          "copies": 5}))
+        return
+
     import paper_1402_4005_amd as bamg
 
     kind, size, wopts = WORKLOADS[args.workload]
     ch = make_chain(kind, size, wopts["seed"])
-    opts = bamg.options_for(ch, precision=args.precision, setup_cycles=args.setup_cycles,
-                            **wopts)
     dev = torch.device("cuda:0")
     rp = torch.from_numpy(ch.indptr).to(dev)
     ci = torch.from_numpy(ch.indices).to(dev)
     va = torch.from_numpy(ch.data).to(dev)
     stream = torch.cuda.current_stream()
 
-    def step(profile=False):
+    def options(precision):
+        return bamg.options_for(ch, precision=precision, setup_cycles=args.setup_cycles,
+                                **wopts)
+
+    def step(opts, profile=False):
         h = bamg.Hierarchy(rp, ci, va, ch.geom, opts, stream=stream)
         if profile:
             h.profile_begin(0)
-        x, info = h.gmres(restart=args.restart, tol=args.tol, maxit=1000, stream=stream)
+        x, info = h.gmres(restart=args.restart, tol=args.tol, maxit=args.maxit, stream=stream)
         prof = h.profile_end() if profile else None
         return h, x, info, prof
 
-    for _ in range(args.warmup):
-        h, x, info, _ = step()
-        h.close()
-    torch.cuda.synchronize()
+    def timed(opts):
+        for _ in range(args.warmup):
+            h, x, info, _ = step(opts)
+            h.close()
+        # timed region: K whole steps, device-synchronised on both sides
+        infos = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            h, x, info, _ = step(opts)
+            infos.append(info)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        return (t1 - t0) * 1e3 / args.steps, h, x, infos
 
-    # timed region: K whole steps, device-synchronised on both sides
-    infos = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        h, x, info, _ = step()
-        infos.append(info)
-        last = h
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    def vcycle_rate(opts):
+        hs = bamg.Hierarchy(rp, ci, va, ch.geom, opts, stream=stream)
+        dt = torch.float64 if opts.precision == 0 else torch.float32
+        b = torch.randn(ch.n, dtype=torch.float64, device=dev).to(dt)
+        xv = torch.empty_like(b)
+        hs.vcycle(b, xv)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.vcycle_reps):
+            hs.vcycle(b, xv)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.vcycle_reps
+        nbytes = hs.vcycle_bytes()
+        hs.close()
+        return {"ms": round(ms, 4), "bytes": nbytes, "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+
+    opts = options(args.precision)
+    try:
+        ms_per_step, last, x, infos = timed(opts)
+    except bamg.BamgError as e:
+        # the method itself failed on this chain (setup or solve status < 0)
+        print(json.dumps({"metric": METRIC, "value": None, "unit": "ms", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup,
+                          "higher_is_better": False, "dtype": args.precision,
+                          "data": "synthetic", "config": {"workload": args.workload,
+                                                          "n": ch.n},
+                          "error": {"status": e.code, "message": str(e)}}))
+        return
 
     # kernel timing: the same K steps again with HIP events around every run of
     # finest-level Jacobi sweeps (event recording bypasses the V-cycle graph)
@@ -111,7 +165,7 @@ def main():
     kms = 0.0
     kbytes = 0.0
     for _ in range(args.steps):
-        hp, _, _, prof = step(profile=True)
+        hp, _, _, prof = step(opts, profile=True)
         launches += prof[0]
         kms += prof[1]
         kbytes += prof[2]
@@ -130,17 +184,26 @@ def main():
     hs = bamg.Hierarchy(rp, ci, va, ch.geom, opts, stream=stream)
     torch.cuda.synchronize()
     setup_ms = (time.perf_counter() - ts) * 1e3
-    b = torch.randn(ch.n, dtype=torch.float64, device=dev)
-    xv = torch.empty_like(b)
-    hs.vcycle(b, xv)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.vcycle_reps):
-        hs.vcycle(b, xv)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    vc_ms = e0.elapsed_time(e1) / args.vcycle_reps
-    vc_bytes = hs.vcycle_bytes()
+    hs.close()
+    vcycle = vcycle_rate(opts)
+
+    # the mixed-precision form on the same workload: FP32 setup and V-cycles,
+    # FP64 Krylov, residual, normalisation and coarsest solve
+    mixed = None
+    if args.precision == "fp64" and not args.no_mixed:
+        mopts = options("mixed")
+        mms, mh, mx, minfos = timed(mopts)
+        mxs = mx.cpu().numpy()
+        mixed = {
+            "ms_per_step": round(mms, 3),
+            "speedup_vs_fp64": round(ms_per_step / mms, 3),
+            "iterations": [i.iterations for i in minfos],
+            "converged": [bool(i.converged) for i in minfos],
+            "x_rel_l1_vs_fp64": float(np.abs(mxs - xs).sum() / np.abs(xs).sum()),
+            "vcycle": vcycle_rate(mopts),
+        }
+        mh.close()
+    last.close()
 
     achieved = (kbytes / launches) / (kms / launches * 1e-3) / 1e9 if launches else None
     roofline = {
@@ -172,7 +235,7 @@ def main():
 
     it = [i.iterations for i in infos]
     line = {
-        "metric": "time to ||Bx||/||x||<1e-10 (setup + GMRES), FP64",
+        "metric": METRIC,
         "value": round(ms_per_step, 3),
         "unit": "ms",
         "n_gpus": 1,
@@ -193,9 +256,10 @@ def main():
             "precision": args.precision,
         },
         "iterations": it,
+        "converged": [bool(i.converged) for i in infos],
         "setup_ms": round(setup_ms, 3),
-        "vcycle": {"ms": round(vc_ms, 4), "bytes": vc_bytes,
-                   "GBps": round(vc_bytes / (vc_ms * 1e-3) / 1e9, 1)},
+        "vcycle": vcycle,
+        "mixed": mixed,
         "roofline": roofline,
         "cpu_baseline": cpu,
         **extra,

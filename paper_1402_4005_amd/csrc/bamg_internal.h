@@ -211,8 +211,8 @@ void row_inv_norms(const Csr &A, const T *val, T *out, hipStream_t s);
 // ---- launchers: coarsest level dense algebra (k_dense.hip)
 void csr_to_dense(const Csr &A, const void *val, int prec, double *D, hipStream_t s);
 int cholesky(double *A, int n, hipStream_t s);            // in place, lower, row-major
-void trsm_lower_cols(const double *L, double *X, int n, int ncols, int ldx, int transpose,
-                     hipStream_t s);                      // X <- L^-1 X or L^-T X (columns)
+void trsm_lower_cols(const double *L, double *X, int n, int ncols, int ldx,
+                     hipStream_t s);  // X <- L^-1 X, column by column
 void transpose_dense(const double *A, double *At, int n, hipStream_t s);
 int jacobi_svd(Pool &pool, double *W, double *J, int n, hipStream_t s);  // W, J col-major
 void column_norms(const double *W, int n, double *sv, hipStream_t s);

@@ -42,7 +42,7 @@ void csr_to_dense(const Csr &A, const void *val, int prec, double *D, hipStream_
 __global__ void __launch_bounds__(1024) k_cholesky(double *__restrict__ A, int n,
                                                    int *__restrict__ flag) {
   __shared__ double piv;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, nt = blockDim.x;
   for (int j = 0; j < n; ++j) {
     if (t == 0) {
       const double d = A[(size_t)j * n + j];
@@ -55,13 +55,13 @@ __global__ void __launch_bounds__(1024) k_cholesky(double *__restrict__ A, int n
       A[(size_t)j * n + j] = piv;
     }
     __syncthreads();
-    const double d = piv;
-    for (int i = j + 1 + t; i < n; i += blockDim.x) A[(size_t)i * n + j] /= d;
+    const double inv = 1.0 / piv;
+    for (int i = j + 1 + t; i < n; i += nt) A[(size_t)i * n + j] *= inv;
     __syncthreads();
     // trailing update of the lower triangle: rows i > j, columns j < k <= i
     const int m = n - j - 1;
     const long tot = (long)m * (m + 1) / 2;
-    for (long e = t; e < tot; e += blockDim.x) {
+    for (long e = t; e < tot; e += nt) {
       // e -> (ii, kk) with 0 <= kk <= ii < m, row-wise enumeration
       int ii = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
       while ((long)ii * (ii + 1) / 2 > e) --ii;
@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(1024) k_cholesky(double *__restrict__ A, int n
     }
     __syncthreads();
   }
-  for (long e = t; e < (long)n * n; e += blockDim.x) {
+  for (long e = t; e < (long)n * n; e += nt) {
     const int i = (int)(e / n), k = (int)(e % n);
     if (k > i) A[e] = 0.0;
   }
@@ -89,31 +89,41 @@ int cholesky(double *A, int n, hipStream_t s) {
   return f ? BAMG_E_COARSE : BAMG_OK;
 }
 
-// X (n x ncols, row-major, leading dimension ldx): columns solved in
-// parallel, one thread per column. transpose = 0: L y = x; 1: L^T y = x.
-__global__ void k_trsm_cols(const double *__restrict__ L, double *__restrict__ X, int n,
-                            int ncols, int ldx, int transpose) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncols) return;
-  if (!transpose) {
-    for (int i = 0; i < n; ++i) {
-      double s = X[(size_t)i * ldx + c];
-      const double *Li = L + (size_t)i * n;
-      for (int k = 0; k < i; ++k) s -= Li[k] * X[(size_t)k * ldx + c];
-      X[(size_t)i * ldx + c] = s / Li[i];
-    }
-  } else {
-    for (int i = n - 1; i >= 0; --i) {
-      double s = X[(size_t)i * ldx + c];
-      for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * X[(size_t)k * ldx + c];
-      X[(size_t)i * ldx + c] = s / L[(size_t)i * n + i];
-    }
+// Forward substitution L Y = X for the columns of X (n x ncols, row-major,
+// leading dimension ldx), in place. Each workgroup holds a slab of sw
+// columns in LDS and eliminates row by row (right-looking): once row k is
+// final, every later row subtracts L[i][k] times it.
+__global__ void __launch_bounds__(1024) k_trsm_slab(const double *__restrict__ L,
+                                                    double *__restrict__ X, int n, int ncols,
+                                                    int ldx, int sw) {
+  extern __shared__ double xs[];  // n x sw
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int c = t % sw, ro = t / sw, nro = nt / sw;
+  const int col = blockIdx.x * sw + c;
+  for (int e = t; e < n * sw; e += nt) {
+    const int i = e / sw, cc = e % sw, g = blockIdx.x * sw + cc;
+    xs[e] = g < ncols ? X[(size_t)i * ldx + g] : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double xk = xs[k * sw + c] / L[(size_t)k * n + k];
+    if (ro == 0 && col < ncols) X[(size_t)k * ldx + col] = xk;
+    for (int i = k + 1 + ro; i < n; i += nro) xs[i * sw + c] -= L[(size_t)i * n + k] * xk;
+    __syncthreads();
   }
 }
 
-void trsm_lower_cols(const double *L, double *X, int n, int ncols, int ldx, int transpose,
-                     hipStream_t s) {
-  k_trsm_cols<<<ceil_div(ncols, 64), 64, 0, s>>>(L, X, n, ncols, ldx, transpose);
+void trsm_lower_cols(const double *L, double *X, int n, int ncols, int ldx, hipStream_t s) {
+  int dev = 0, maxlds = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  int sw = 32;
+  while (sw > 1 && sizeof(double) * (size_t)n * sw > (size_t)maxlds) sw >>= 1;
+  const size_t shm = sizeof(double) * (size_t)n * sw;
+  if (shm > (size_t)maxlds) fail(BAMG_E_ARG, "trsm: matrix too large for an LDS slab");
+  HIPCHK(hipFuncSetAttribute((const void *)k_trsm_slab,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+  k_trsm_slab<<<ceil_div(ncols, sw), 1024, shm, s>>>(L, X, n, ncols, ldx, sw);
   LAUNCHCHK();
 }
 
@@ -138,83 +148,107 @@ void transpose_dense(const double *A, double *At, int n, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ Jacobi SVD
-constexpr int kSvdThreads = 256;
+// Block one-sided Jacobi. The columns of W are split into blocks of bs
+// columns; the blocks are paired by the round-robin schedule, one workgroup
+// per block pair. A workgroup holds its 2 bs columns in LDS and runs one
+// cyclic sweep over all their pairs (again round-robin, bs disjoint pairs at
+// a time, one wave per pair), accumulating the rotations in a 2bs x 2bs
+// matrix R; the matching columns of J are then multiplied by R once. Only
+// the block rounds need a grid-wide barrier, so a sweep costs about 2n
+// workgroup barriers and n/bs grid barriers.
 constexpr int kSvdMaxSweeps = 80;
 
 __device__ __forceinline__ int rr_index(int j, int round, int m) {
   return j == 0 ? 0 : 1 + (j - 1 + round) % (m - 1);
 }
 
-// W and J column-major n x n. m = n rounded up to even; index >= n is a
-// dummy column. ctrl[s] counts rotations of sweep s; ctrl[kSvdMaxSweeps]
-// receives the number of sweeps run.
-__global__ void __launch_bounds__(kSvdThreads)
-    k_jacobi_svd(double *__restrict__ W, double *__restrict__ J, int n, int m,
-                 int *__restrict__ ctrl) {
+// W and J column-major n x n; nbp = number of column blocks rounded up to
+// even (columns >= n are zero and never written). ctrl[s] counts rotations
+// of sweep s; ctrl[kSvdMaxSweeps] receives the number of sweeps run.
+// blockDim.x = 64 * bs; dynamic LDS = (2 bs n + 4 bs^2) doubles.
+__global__ void __launch_bounds__(1024)
+    k_block_jacobi_svd(double *__restrict__ W, double *__restrict__ J, int n, int bs, int nbp,
+                       int *__restrict__ ctrl) {
   cg::grid_group grid = cg::this_grid();
-  __shared__ double red[3][kSvdThreads / kWave];
-  __shared__ double rot[2];
-  __shared__ int do_rot;
+  extern __shared__ double lds[];
+  const int cols = 2 * bs;
+  double *Ws = lds;                         // column c at Ws + c * n
+  double *R = lds + (size_t)cols * n;       // cols x cols, column-major
+  __shared__ int nrot;
+  const int nt = blockDim.x;
+  const int wv = threadIdx.x / kWave, ln = threadIdx.x % kWave;
   const double tol = 1e-15;
   int sweep = 0;
   for (; sweep < kSvdMaxSweeps; ++sweep) {
-    for (int round = 0; round < m - 1; ++round) {
-      for (int pair = blockIdx.x; pair < m / 2; pair += gridDim.x) {
-        int p = rr_index(pair, round, m), q = rr_index(m - 1 - pair, round, m);
-        if (p > q) {
-          const int x = p;
-          p = q;
-          q = x;
+    for (int round = 0; round < nbp - 1; ++round) {
+      for (int pr = blockIdx.x; pr < nbp / 2; pr += gridDim.x) {
+        const int ba = rr_index(pr, round, nbp), bb = rr_index(nbp - 1 - pr, round, nbp);
+        // local column c -> global column
+        auto gcol = [&](int c) { return c < bs ? ba * bs + c : bb * bs + (c - bs); };
+        for (int e = threadIdx.x; e < cols * n; e += nt) {
+          const int c = e / n, i = e % n, g = gcol(c);
+          Ws[e] = g < n ? W[(size_t)g * n + i] : 0.0;
         }
-        if (q >= n) continue;  // the dummy column (uniform in the block)
-        double *wp = W + (size_t)p * n, *wq = W + (size_t)q * n;
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = threadIdx.x; i < n; i += kSvdThreads) {
-          const double a = wp[i], b = wq[i];
-          al += a * a;
-          be += b * b;
-          ga += a * b;
-        }
-        al = group_sum(al, kWave);
-        be = group_sum(be, kWave);
-        ga = group_sum(ga, kWave);
-        const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
-        if (l == 0) {
-          red[0][w] = al;
-          red[1][w] = be;
-          red[2][w] = ga;
-        }
+        for (int e = threadIdx.x; e < cols * cols; e += nt) R[e] = (e / cols) == (e % cols);
+        if (threadIdx.x == 0) nrot = 0;
         __syncthreads();
-        if (threadIdx.x == 0) {
-          double A = 0, Bq = 0, G = 0;
-          for (int k = 0; k < kSvdThreads / kWave; ++k) {
-            A += red[0][k];
-            Bq += red[1][k];
-            G += red[2][k];
+        for (int ir = 0; ir < cols - 1; ++ir) {
+          int p = rr_index(wv, ir, cols), q = rr_index(cols - 1 - wv, ir, cols);
+          if (p > q) {
+            const int x = p;
+            p = q;
+            q = x;
           }
-          do_rot = 0;
-          if (G != 0.0 && fabs(G) > tol * sqrt(A * Bq)) {
-            const double zeta = (Bq - A) / (2.0 * G);
+          double *wp = Ws + (size_t)p * n, *wq = Ws + (size_t)q * n;
+          double al = 0.0, be = 0.0, ga = 0.0;
+          for (int i = ln; i < n; i += kWave) {
+            const double x = wp[i], y = wq[i];
+            al += x * x;
+            be += y * y;
+            ga += x * y;
+          }
+          al = group_sum(al, kWave);
+          be = group_sum(be, kWave);
+          ga = group_sum(ga, kWave);
+          if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+            const double zeta = (be - al) / (2.0 * ga);
             const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double c = 1.0 / sqrt(1.0 + t * t);
-            rot[0] = c;
-            rot[1] = c * t;
-            do_rot = 1;
-            atomicAdd(&ctrl[sweep], 1);
+            const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+            for (int i = ln; i < n; i += kWave) {
+              const double x = wp[i], y = wq[i];
+              wp[i] = c * x - sn * y;
+              wq[i] = sn * x + c * y;
+            }
+            double *rp = R + (size_t)p * cols, *rq = R + (size_t)q * cols;
+            for (int i = ln; i < cols; i += kWave) {
+              const double x = rp[i], y = rq[i];
+              rp[i] = c * x - sn * y;
+              rq[i] = sn * x + c * y;
+            }
+            if (ln == 0) atomicAdd(&nrot, 1);
           }
+          __syncthreads();
+        }
+        for (int e = threadIdx.x; e < cols * n; e += nt) {
+          const int c = e / n, i = e % n, g = gcol(c);
+          if (g < n) W[(size_t)g * n + i] = Ws[e];
         }
         __syncthreads();
-        if (do_rot) {
-          const double c = rot[0], sn = rot[1];
-          double *jp = J + (size_t)p * n, *jq = J + (size_t)q * n;
-          for (int i = threadIdx.x; i < n; i += kSvdThreads) {
-            const double a = wp[i], b = wq[i];
-            wp[i] = c * a - sn * b;
-            wq[i] = sn * a + c * b;
-            const double x = jp[i], y = jq[i];
-            jp[i] = c * x - sn * y;
-            jq[i] = sn * x + c * y;
+        if (nrot > 0) {
+          // J[:, pair] = J[:, pair] R, staged through the (now free) W slice
+          for (int e = threadIdx.x; e < cols * n; e += nt) {
+            const int c = e / n, i = e % n, g = gcol(c);
+            Ws[e] = g < n ? J[(size_t)g * n + i] : 0.0;
           }
+          __syncthreads();
+          for (int e = threadIdx.x; e < cols * n; e += nt) {
+            const int c = e / n, i = e % n, g = gcol(c);
+            if (g >= n) continue;
+            double acc = 0.0;
+            for (int d = 0; d < cols; ++d) acc += Ws[(size_t)d * n + i] * R[(size_t)c * cols + d];
+            J[(size_t)g * n + i] = acc;
+          }
+          if (threadIdx.x == 0) atomicAdd(&ctrl[sweep], nrot);
         }
         __syncthreads();
       }
@@ -233,25 +267,40 @@ __global__ void k_identity_dense(double *__restrict__ J, int n) {
   J[e] = (e / n) == (e % n) ? 1.0 : 0.0;
 }
 
+static size_t block_jacobi_lds(int n, int bs) {
+  return sizeof(double) * ((size_t)2 * bs * n + (size_t)4 * bs * bs);
+}
+
 int jacobi_svd(Pool &pool, double *W, double *J, int n, hipStream_t s) {
+  int dev = 0, maxlds = 0, ncu = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  int bs = 16;
+  while (bs > 1 && block_jacobi_lds(n, bs) + 256 > (size_t)maxlds) bs >>= 1;
+  if (block_jacobi_lds(n, bs) + 256 > (size_t)maxlds)
+    fail(BAMG_E_ARG, "coarsest level too large for the LDS-staged Jacobi SVD");
+  const size_t shm = block_jacobi_lds(n, bs);
+  const int threads = kWave * bs;
+  const int nb = ceil_div(n, bs);
+  int nbp = nb + (nb & 1);
+  if (nbp < 2) nbp = 2;
   int *ctrl = pool.get<int>(kSvdMaxSweeps + 1);
   fill_i32(ctrl, 0, kSvdMaxSweeps + 1, s);
   k_identity_dense<<<ceil_div((long)n * n, 256), 256, 0, s>>>(J, n);  // J = I
   LAUNCHCHK();
-  int m = n + (n & 1);
-  int dev = 0;
-  HIPCHK(hipGetDevice(&dev));
-  int ncu = 0, per = 0;
-  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_jacobi_svd,
-                                                      kSvdThreads, 0));
-  int grid = m / 2;
+  HIPCHK(hipFuncSetAttribute((const void *)k_block_jacobi_svd,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+  int per = 0;
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_block_jacobi_svd,
+                                                      threads, shm));
+  int grid = nbp / 2;
   const int cap = ncu * (per > 0 ? per : 1);
   if (grid > cap) grid = cap;
   if (grid < 1) grid = 1;
-  void *args[] = {(void *)&W, (void *)&J, (void *)&n, (void *)&m, (void *)&ctrl};
-  HIPCHK(hipLaunchCooperativeKernel((const void *)k_jacobi_svd, dim3(grid), dim3(kSvdThreads),
-                                    args, 0, s));
+  void *args[] = {(void *)&W, (void *)&J, (void *)&n, (void *)&bs, (void *)&nbp, (void *)&ctrl};
+  HIPCHK(hipLaunchCooperativeKernel((const void *)k_block_jacobi_svd, dim3(grid), dim3(threads),
+                                    args, shm, s));
   int sweeps = 0;
   HIPCHK(hipMemcpyAsync(&sweeps, ctrl + kSvdMaxSweeps, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));

@@ -184,9 +184,9 @@ struct Setup {
     if (cholesky(Md, n, s) != BAMG_OK || cholesky(Nd, n, s) != BAMG_OK)
       fail(BAMG_E_COARSE, "coarsest M_L or N_L not positive definite");
     HIPCHK(hipMemcpyAsync(X, Bd, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToDevice, s));
-    trsm_lower_cols(Md, X, n, n, n, 0, s);  // X = L_M^-1 B
+    trsm_lower_cols(Md, X, n, n, n, s);  // X = L_M^-1 B
     transpose_dense(X, W, n, s);
-    trsm_lower_cols(Nd, W, n, n, n, 0, s);  // W = L_N^-1 X^T, i.e. Bt column-major
+    trsm_lower_cols(Nd, W, n, n, n, s);  // W = L_N^-1 X^T, i.e. Bt column-major
     if (jacobi_svd(pool(), W, J, n, s) != BAMG_OK) fail(BAMG_E_COARSE, "Jacobi SVD did not converge");
     column_norms(W, n, sv, s);
     coarse_triplets_out(Md, Nd, W, J, sv, n, r, C.U, C.V, h->prec, h->sigma, work, s);

@@ -63,6 +63,9 @@ CASES = [
      dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=500)),
     ("birthdeath257", lambda: chaingen.birth_death(257, 0.96),
      dict(r=8, max_interp=2, coarse_max=29)),
+    # coarsest 17 x 17 = 289 states: the block Jacobi SVD rather than the LDS solver
+    ("tandem65_c289", lambda: chaingen.tandem(65, 11 / 31, 10 / 31, 10 / 31),
+     dict(r=8, max_interp=4, coarse_max=300, nu_setup=5)),
 ]
 
 
@@ -121,6 +124,17 @@ def test_coarse_pinv_matches_numpy():
     _, hg = both(ch, r=6, max_levels=2, coarse_max=1)
     L = hg.levels - 1
     BL = hg.scipy(L, "B").toarray()
+    ref = np.linalg.pinv(BL, rcond=1e-10)
+    assert rel_max(hg.coarse_pinv(), ref) < 1e-9
+
+
+def test_coarse_pinv_block_jacobi_matches_numpy():
+    # 289-state coarsest level: pseudo-inverse through the block Jacobi SVD
+    ch = chaingen.tandem(65, 11 / 31, 10 / 31, 10 / 31)
+    _, hg = both(ch, r=8, max_interp=4, coarse_max=300, nu_setup=5)
+    L = hg.levels - 1
+    BL = hg.scipy(L, "B").toarray()
+    assert BL.shape == (289, 289)
     ref = np.linalg.pinv(BL, rcond=1e-10)
     assert rel_max(hg.coarse_pinv(), ref) < 1e-9
 
