@@ -47,6 +47,16 @@ __device__ __forceinline__ X group_sum(X v, int width) {
   return v;
 }
 
+// The dispatcher hands workgroup b to XCD b % 8. Renumbering so that XCD x
+// owns one contiguous range of logical blocks keeps neighbouring rows (and
+// the vector entries they gather) in one XCD's L2 instead of all eight.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int nblocks) {
+  const int q = nblocks / kXcds, r = nblocks % kXcds;
+  const int x = b % kXcds, k = b / kXcds;
+  return x * q + (x < r ? x : r) + k;
+}
+
 // Block-wide sum of one FP64 value per thread; result valid in thread 0.
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double *sh) {

@@ -17,7 +17,7 @@ __global__ void __launch_bounds__(kSpThreads)
     k_spmv(int nr, const int *__restrict__ rp, const int *__restrict__ ci,
            const T *__restrict__ val, const T *__restrict__ x, T *__restrict__ y,
            const T *__restrict__ b, int mode) {
-  const long gid = (long)blockIdx.x * kSpThreads + threadIdx.x;
+  const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * kSpThreads + threadIdx.x;
   const int row = (int)(gid / LPR), lane = (int)(gid % LPR);
   if (row >= nr) return;  // whole groups leave together
   T sum = 0;
@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(kSpThreads)
     k_jacobi(int nr, const int *__restrict__ rp, const int *__restrict__ ci,
              const T *__restrict__ val, const T *__restrict__ dinv, T omega,
              const T *__restrict__ b, const T *__restrict__ xin, T *__restrict__ xout) {
-  const long gid = (long)blockIdx.x * kSpThreads + threadIdx.x;
+  const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * kSpThreads + threadIdx.x;
   const int row = (int)(gid / LPR), lane = (int)(gid % LPR);
   if (row >= nr) return;
   if (xin == nullptr) {

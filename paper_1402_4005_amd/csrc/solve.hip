@@ -17,7 +17,7 @@ template <class T>
 __global__ void k_spmv_add_into(int nr, const int *__restrict__ rp, const int *__restrict__ ci,
                                 const T *__restrict__ val, const T *__restrict__ x,
                                 const T *__restrict__ z, T *__restrict__ y) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= nr) return;
   T s = 0;
   for (int a = rp[i]; a < rp[i + 1]; ++a) s += val[a] * x[ci[a]];
@@ -131,7 +131,7 @@ static void precondition(bamg_handle *h, const double *b, double *x, hipStream_t
 __global__ void k_spmv_dual(int nr, const int *__restrict__ rp, const int *__restrict__ ci,
                             const double *__restrict__ val, const double *__restrict__ x,
                             double *__restrict__ y1, double *__restrict__ y2) {
-  const int gid = blockIdx.x * 256 + threadIdx.x;
+  const int gid = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   const int row = gid / 8, lane = gid % 8;
   if (row >= nr) return;
   double sum = 0.0;
