@@ -44,6 +44,38 @@ WORKLOADS = {
 }
 
 
+# Sources of the dominant kernel (the finest-level Jacobi sweep). The HBM
+# traffic measured by hardware counters is kept in profiles/ together with
+# the digest of these files; after any change to them it no longer applies.
+KERNEL_SOURCES = ("paper_1402_4005_amd/csrc/k_sparse.hip",
+                  "paper_1402_4005_amd/csrc/device_common.h")
+
+
+def kernel_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per launch of the dominant kernel from the committed
+    FETCH_SIZE / WRITE_SIZE summary, or None if there is none for this
+    workload or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"k_jacobi_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic-json: "):
+                d = json.loads(line[len("traffic-json: "):])
+                if d.get("source_digest") == kernel_digest() and d.get("precision") == precision:
+                    return d
+    return None
+
+
 def make_chain(kind, size, seed):
     import chaingen
     if kind == "delaunay":
@@ -205,6 +237,7 @@ def main():
         mh.close()
     last.close()
 
+    traffic = measured_traffic(args.workload, args.precision)
     achieved = (kbytes / launches) / (kms / launches * 1e-3) / 1e9 if launches else None
     roofline = {
         "kernel": "k_jacobi (finest-level weighted-Jacobi sweep, CSR, 8 lanes/row)",
@@ -213,7 +246,9 @@ def main():
         "peak": HBM_PEAK_GBPS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBPS, 4) if achieved else None,
-        "traffic": None,
+        "traffic": traffic["bytes_per_launch"] if traffic else None,
+        "traffic_vs_algorithmic": (round(traffic["bytes_per_launch"] / (kbytes / launches), 3)
+                                   if traffic and launches else None),
         "launches": launches,
         "avg_us": round(kms / launches * 1e3, 3) if launches else None,
         "bytes_per_launch": kbytes / launches if launches else None,

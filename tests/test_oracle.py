@@ -296,6 +296,37 @@ def test_smoother_fixed_point(tandem14):
         assert np.allclose(x1, 0.7 * b / B.diagonal(), atol=1e-15)
 
 
+def test_kaczmarz_sweep_is_a_sequence_of_projections():
+    # Section 3 lists Kaczmarz relaxation: each row update is the orthogonal
+    # projection onto {x : B_i x = b_i}. On a consistent system this makes
+    # ||x - x*|| non-increasing for every solution x*, leaves the rows of the
+    # last colour exactly satisfied (later rows of that colour touch other
+    # columns only), and repeated sweeps converge to a solution.
+    ch = chaingen.tandem(12, 11 / 31, 10 / 31, 10 / 31)
+    h = oracle.Hierarchy(ch, oracle.options_for(ch, r=6, max_levels=2, coarse_max=1,
+                                                smoother="kaczmarz"))
+    B = sp.csr_matrix(sp.eye(ch.n) - ch.to_scipy())
+    B.sort_indices()
+    Bt = B.T.tocsr()
+    Bt.sort_indices()
+    col = oracle.row_colouring(B.indptr, B.indices, Bt.indptr, Bt.indices)
+    last = col == col.max()
+    rng = np.random.default_rng(3)
+    xs = rng.standard_normal(ch.n)
+    b = B @ xs
+    x = rng.standard_normal(ch.n)
+    err = [np.linalg.norm(x - xs)]
+    for _ in range(400):
+        x = h.smooth(0, b, x)
+        err.append(np.linalg.norm(x - xs))
+        r = b - B @ x
+        assert np.abs(r[last]).max() < 1e-12 * max(1.0, np.abs(b).max())
+    err = np.array(err)
+    assert np.all(np.diff(err) <= 1e-12 * err[0])
+    # approaching the solution set {xs + t x_null} (Kaczmarz converges slowly)
+    assert np.linalg.norm(b - B @ x) < 1e-3 * np.linalg.norm(b)
+
+
 def test_two_grid_propagator_formula():
     """V-cycle with two levels and an exact coarse solve: I - C B equals
     S^nu2 (I - P B_c^+ Q B) S^nu1 (eq. error_propagator_twogrid; pre-smoothing
