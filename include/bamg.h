@@ -97,7 +97,19 @@ typedef struct {
   int32_t interp_rule;  /* 0 = plain LS over J_i, 1 = LS with negative weights removed */
   int32_t validate;     /* 1 = check stochasticity and strong connectivity */
   int32_t use_graph;    /* 1 = GMRES replays the V-cycle from a captured HIP graph */
+  int32_t learned;      /* BAMG_LEARNED_*: interpolation weights from an MLP (see below) */
+  const struct bamg_mlp *mlp; /* network for BAMG_LEARNED_USE, else ignored */
 } bamg_options;
+
+/* Learned interpolation weights. Not part of the paper: an addition whose
+ * aim is to replace the second bootstrap cycle (BAMG^2, Section 7). In
+ * BAMG_LEARNED_USE mode, setup cycle 1 takes each F row of P from the MLP
+ * instead of from the least-squares fit of eq. ls_interpolation. The exact
+ * LS fit is kept for a row whenever the MLP weights give an LS objective
+ * above twice the exact fit's value. BAMG_LEARNED_RECORD keeps the MLP
+ * input features of cycle 1 so that bamg_harvest can return them together
+ * with the final P rows (training data). */
+enum { BAMG_LEARNED_OFF = 0, BAMG_LEARNED_USE = 1, BAMG_LEARNED_RECORD = 2 };
 
 /* Device allocator used for every library allocation (NULL = hipMalloc /
  * hipFree). alloc returns NULL on failure. */
@@ -118,6 +130,29 @@ typedef struct {
 } bamg_solve_info;
 
 typedef struct bamg_handle bamg_handle;
+
+/* ---------------------------------------------------------------------
+ * Interpolation-weight MLP: 96 inputs -> 64 -> 64 (ReLU) -> 8 outputs.
+ * Parameters, FP32, in this order (row-major, out x in):
+ *   W1[64][96], b1[64], W2[64][64], b2[64], W3[8][64], b3[8]
+ * (BAMG_MLP_NPARAMS values). Inference runs on MFMA in BF16 (weights and
+ * activations rounded to nearest-even BF16, FP32 accumulation); training
+ * runs in FP32.
+ *
+ * Features of an F point i with interpolation set J_i = (j_1..j_m), m <= 8,
+ * and r = 8 normalised test vectors v^(k) with LS weights w_k (eq.
+ * ls_weights, divided by their maximum):
+ *   f[9k]         = sqrt(w_k) v^(k)_i / S          k = 0..7
+ *   f[9k + 1 + t] = sqrt(w_k) v^(k)_{j_t} / S      t < m, else 0
+ *   f[72 + t] = B_{i j_t} / B_ii,  f[80 + t] = B_{j_t i} / B_ii  (t < m, else 0)
+ *   f[88 + t] = 1 if t < m else 0
+ * with S the largest |sqrt(w_k) v^(k)| among the gathered values (1 if 0).
+ * Outputs: the weights p_{i j_t}, t < m (entries t >= m are ignored). */
+#define BAMG_MLP_IN 96
+#define BAMG_MLP_HIDDEN 64
+#define BAMG_MLP_OUT 8
+#define BAMG_MLP_NPARAMS 10888
+typedef struct bamg_mlp bamg_mlp;
 
 /* Fill *out with the defaults above. */
 bamg_status bamg_default_options(bamg_options *out);
@@ -193,6 +228,43 @@ bamg_status bamg_kernel_profile_end(bamg_handle *h, int64_t *launches, double *m
 
 /* Free every resource of h (NULL is ignored). */
 void bamg_destroy(bamg_handle *h);
+
+/* Create a network from BAMG_MLP_NPARAMS FP32 parameters (host memory,
+ * copied) on the current device. Adam moments start at zero. */
+bamg_status bamg_mlp_create(const float *params, bamg_mlp **out);
+/* Copy the current FP32 parameters to host memory (BAMG_MLP_NPARAMS). */
+bamg_status bamg_mlp_get_params(const bamg_mlp *m, float *params);
+void bamg_mlp_destroy(bamg_mlp *m);
+/* Y = MLP(X) for npts points: X device FP32 npts x 96, Y device FP32
+ * npts x 8. mode 0 = FP32 (the training arithmetic), 1 = BF16 MFMA (the
+ * inference path used by the setup). */
+bamg_status bamg_mlp_forward(const bamg_mlp *m, const float *X, int64_t npts, float *Y,
+                             int32_t mode, void *hip_stream);
+/* Loss and gradient over npts points (device FP32 X npts x 96, targets T
+ * and mask M npts x 8):
+ *   loss = 1/(2 npts) sum_p sum_t M_pt (MLP(X_p)_t - T_pt)^2
+ * *loss (host) in FP64; grad (device FP32, BAMG_MLP_NPARAMS, same order
+ * as the parameters). FP32 arithmetic, fixed summation order. */
+bamg_status bamg_mlp_loss_grad(const bamg_mlp *m, const float *X, const float *T,
+                               const float *M, int64_t npts, double *loss, float *grad,
+                               void *hip_stream);
+/* Adam training (beta1 0.9, beta2 0.999, eps 1e-8) on the loss above with
+ * mini-batches of `batch` consecutive points, `epochs` passes in the given
+ * order. loss_per_epoch (host, epochs entries, nullable) receives the mean
+ * batch loss of each epoch. */
+bamg_status bamg_mlp_train(bamg_mlp *m, const float *X, const float *T, const float *M,
+                           int64_t npts, int32_t batch, int32_t epochs, float lr,
+                           double *loss_per_epoch, void *hip_stream);
+/* Training data of a handle set up with learned = BAMG_LEARNED_RECORD:
+ * for level l (< levels - 1), the cycle-1 features of its F points
+ * (ascending state index) and their final P rows (weights in J_i order,
+ * zero-padded to 8) with a mask of the valid entries. X, T, M are device
+ * FP32 buffers of nF x 96, nF x 8, nF x 8, or all NULL to query *nF. */
+bamg_status bamg_harvest(const bamg_handle *h, int32_t level, float *X, float *T, float *M,
+                         int64_t *nF, void *hip_stream);
+/* Points whose P row the MLP supplied and rows that fell back to the exact
+ * LS fit, summed over levels (learned = BAMG_LEARNED_USE). */
+bamg_status bamg_learned_stats(const bamg_handle *h, int64_t *mlp_rows, int64_t *fallback_rows);
 
 /* Static description of a status code. */
 const char *bamg_status_string(bamg_status s);

@@ -44,7 +44,7 @@ class Options(C.Structure):
                 ("max_interp", C.c_int32), ("max_levels", C.c_int32), ("coarse_max", C.c_int32),
                 ("coarsening", C.c_int32), ("geom_kind", C.c_int32), ("nx", C.c_int32),
                 ("ny", C.c_int32), ("seed", C.c_uint64), ("smoother", C.c_int32),
-                ("interp_rule", C.c_int32)]
+                ("interp_rule", C.c_int32), ("record_features", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -84,6 +84,8 @@ def lib():
         _lib.orc_mis.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_uint64, C.c_int, C.c_void_p]
         _lib.orc_row_colouring.argtypes = [C.c_int] + [C.c_void_p] * 5
         _lib.orc_default_options.argtypes = [P(Options)]
+        _lib.orc_harvest.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]
     return _lib
 
 
@@ -193,6 +195,19 @@ class Hierarchy:
         x = np.zeros(self.n)
         lib().orc_x0(self.h, _p(x))
         return x
+
+    def harvest(self, l):
+        """Cycle-1 MLP features of level l's F points (needs
+        record_features=1) and the final P rows: X (nF x 96), T, M (nF x 8)."""
+        nf = C.c_int64()
+        st = lib().orc_harvest(self.h, l, C.byref(nf), None, None, None)
+        if st:
+            raise OracleError(st)
+        X = np.zeros((nf.value, 96))
+        T = np.zeros((nf.value, 8))
+        M = np.zeros((nf.value, 8))
+        lib().orc_harvest(self.h, l, C.byref(nf), _p(X), _p(T), _p(M))
+        return X, T, M
 
     def coarse_pinv(self):
         nL = int(self.dims(self.levels - 1)[0])

@@ -579,6 +579,8 @@ typedef struct {
   csr G;            /* symmetrised graph of B without diagonal */
   int32_t *colB, *colBt, ncolB, ncolBt; /* Kaczmarz row colourings */
   double *U, *V;
+  int nF;       /* recorded F points (learned interpolation), -1 = none */
+  double *feat; /* nF x 96 */
 } level;
 
 struct orc_ctx {
@@ -732,6 +734,8 @@ static void build_P_pattern(orc_ctx *c, int l) {
 }
 
 static void level_free(level *L) {
+  free(L->feat);
+  L->feat = NULL;
   csr_free(&L->B);
   csr_free(&L->Bt);
   csr_free(&L->M);
@@ -960,7 +964,76 @@ static void fit_point(int rule, int r, int m, const double *G, const double *g, 
 
 /* LS fits of all P rows and Q columns of level l (eq. ls_interpolation,
  * eq. ls_weights, Section 5 constraint). */
-static void fit_transfer(orc_ctx *c, level *L) {
+/* Value of B at (i, j) from the rows of A (A = B for B_ij, A = B^T for B_ji). */
+static double csr_at(const csr *A, int i, int j) {
+  for (int k = A->rp[i]; k < A->rp[i + 1]; ++k)
+    if (A->ci[k] == j) return A->v[k];
+  return 0.0;
+}
+
+/* Features of the F points for the learned interpolation weights (not part
+ * of the paper). For F point i with interpolation points j_1..j_m (m <= 8)
+ * and the normalised LS weights w_k of the first min(r, 8) right vectors:
+ * 8 groups of 9 values sqrt(w_k) v_k at (i, j_1..j_8), divided by their
+ * largest magnitude; B_{i j_t}/B_ii; B_{j_t i}/B_ii; and the mask t < m. */
+static void record_features(orc_ctx *c, level *L, const double *wv) {
+  int n = L->n, r = c->o.r, kr = r < 8 ? r : 8;
+  int nF = 0;
+  for (int i = 0; i < n; ++i) nF += L->cf[i] ? 0 : 1;
+  free(L->feat);
+  L->feat = NEW(double, (size_t)nF * 96);
+  L->nF = nF;
+  int f = 0;
+  for (int i = 0; i < n; ++i) {
+    if (L->cf[i]) continue;
+    double *o = L->feat + (size_t)f * 96;
+    int a = L->P.rp[i], m = L->P.rp[i + 1] - a;
+    if (m > 8) m = 8;
+    int J[8];
+    for (int t = 0; t < m; ++t) J[t] = L->cpts[L->P.ci[a + t]];
+    double S = 0.0;
+    for (int k = 0; k < kr; ++k) {
+      double sw = sqrt(wv[k]);
+      S = fmax(S, fabs(sw * L->V[(size_t)i * r + k]));
+      for (int t = 0; t < m; ++t) S = fmax(S, fabs(sw * L->V[(size_t)J[t] * r + k]));
+    }
+    if (!(S > 0.0)) S = 1.0;
+    for (int k = 0; k < kr; ++k) {
+      double sw = sqrt(wv[k]);
+      o[9 * k] = sw * L->V[(size_t)i * r + k] / S;
+      for (int t = 0; t < m; ++t) o[9 * k + 1 + t] = sw * L->V[(size_t)J[t] * r + k] / S;
+    }
+    double bii = csr_at(&L->B, i, i);
+    if (bii == 0.0) bii = 1.0;
+    for (int t = 0; t < m; ++t) {
+      o[72 + t] = csr_at(&L->B, i, J[t]) / bii;
+      o[80 + t] = csr_at(&L->Bt, i, J[t]) / bii;
+      o[88 + t] = 1.0;
+    }
+    ++f;
+  }
+}
+
+int orc_harvest(const orc_ctx *c, int l, int64_t *nF, double *X, double *T, double *M) {
+  if (!c || !nF || l < 0 || l >= c->L - 1) return ORC_E_ARG;
+  const level *L = &c->lv[l];
+  if (L->nF < 0 || !L->feat) return ORC_E_ARG;
+  *nF = L->nF;
+  if (X) memcpy(X, L->feat, sizeof(double) * (size_t)L->nF * 96);
+  int f = 0;
+  for (int i = 0; i < L->n; ++i) {
+    if (L->cf[i]) continue;
+    int a = L->P.rp[i], m = L->P.rp[i + 1] - a;
+    for (int t = 0; t < 8; ++t) {
+      if (T) T[(size_t)f * 8 + t] = t < m ? L->P.v[a + t] : 0.0;
+      if (M) M[(size_t)f * 8 + t] = t < m ? 1.0 : 0.0;
+    }
+    ++f;
+  }
+  return ORC_OK;
+}
+
+static void fit_transfer(orc_ctx *c, level *L, int record) {
   int n = L->n, r = c->o.r;
   double *wv = NEW(double, r), *wu = NEW(double, r);
   double *x = NEW(double, n), *t = NEW(double, n);
@@ -1002,6 +1075,7 @@ static void fit_transfer(orc_ctx *c, level *L) {
     fit_point(c->o.interp_rule, r, m, G, g, wu, 1, p);
     for (int tt = 0; tt < m; ++tt) L->Qt.v[a + tt] = p[tt];
   }
+  if (record) record_features(c, L, wv);
   free(wv);
   free(wu);
   free(x);
@@ -1052,7 +1126,7 @@ static int mle(orc_ctx *c, int l, int cycle) {
   if (l == c->L - 1) return coarsest_triplets(c, L);
   relax_pairs(c, L, cycle > 1);
   normalize_pairs(c, L);
-  fit_transfer(c, L);
+  fit_transfer(c, L, c->o.record_features && cycle == 1);
   galerkin(c, l);
   level *C = &c->lv[l + 1];
   for (int a = 0; a < C->n; ++a)

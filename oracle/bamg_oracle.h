@@ -54,6 +54,7 @@ typedef struct {
   uint64_t seed;
   int32_t smoother;     /* ORC_SMOOTH_JACOBI or ORC_SMOOTH_KACZMARZ */
   int32_t interp_rule;  /* 0 plain LS, 1 active set (no negative weights) */
+  int32_t record_features; /* keep cycle-1 MLP features of the F points */
 } orc_options;
 
 typedef struct {
@@ -92,6 +93,12 @@ int orc_smooth(const orc_ctx *c, int l, const double *b, double *x);
  * ||Bx||_2/||x||_2 < tol; x is returned scaled to 1^T x = 1. */
 int orc_gmres(const orc_ctx *c, double *x, int32_t m, double tol, int32_t maxit,
               int32_t use_x0, int32_t precondition, orc_info *info);
+
+/* Learned interpolation (an addition to the paper): the 96 features of each
+ * F point of level l as recorded in setup cycle 1 (record_features = 1), and
+ * the final P rows (zero-padded to 8) with their mask. nF receives the
+ * number of F points; X, T, M (nF x 96, nF x 8, nF x 8) may be NULL. */
+int orc_harvest(const orc_ctx *c, int l, int64_t *nF, double *X, double *T, double *M);
 
 /* Building blocks exposed for the pins. */
 void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);

@@ -24,6 +24,8 @@ SMOOTH_JACOBI, SMOOTH_KACZMARZ = 0, 1
 PRECISION_FP64, PRECISION_MIXED = 0, 1
 DTYPE_F64, DTYPE_F32 = 0, 1
 GEOM_NONE, GEOM_LINE, GEOM_GRID2D = 0, 1, 2
+LEARNED_OFF, LEARNED_USE, LEARNED_RECORD = 0, 1, 2
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_NPARAMS = 96, 64, 8, 10888
 WHAT = {"B": 0, "Bt": 1, "M": 2, "N": 3, "P": 4, "Q": 5, "Qt": 6}
 
 
@@ -48,7 +50,7 @@ class Options(C.Structure):
                 ("max_interp", C.c_int32), ("max_levels", C.c_int32), ("coarse_max", C.c_int32),
                 ("coarsening", C.c_int32), ("seed", C.c_uint64), ("smoother", C.c_int32),
                 ("precision", C.c_int32), ("interp_rule", C.c_int32), ("validate", C.c_int32),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("learned", C.c_int32), ("mlp", C.c_void_p)]
 
 
 class SolveInfo(C.Structure):
@@ -97,6 +99,16 @@ def lib():
         L.bamg_status_string.restype = C.c_char_p
         L.bamg_last_error.argtypes = []
         L.bamg_last_error.restype = C.c_char_p
+        L.bamg_mlp_create.argtypes = [V, P(V)]
+        L.bamg_mlp_get_params.argtypes = [V, V]
+        L.bamg_mlp_destroy.argtypes = [V]
+        L.bamg_mlp_destroy.restype = None
+        L.bamg_mlp_forward.argtypes = [V, V, C.c_int64, V, C.c_int32, V]
+        L.bamg_mlp_loss_grad.argtypes = [V, V, V, V, C.c_int64, P(C.c_double), V, V]
+        L.bamg_mlp_train.argtypes = [V, V, V, V, C.c_int64, C.c_int32, C.c_int32, C.c_float,
+                                     V, V]
+        L.bamg_harvest.argtypes = [V, C.c_int32, V, V, V, P(C.c_int64), V]
+        L.bamg_learned_stats.argtypes = [V, P(C.c_int64), P(C.c_int64)]
         _lib = L
     return _lib
 
@@ -121,10 +133,13 @@ def default_options(**kw) -> Options:
         "coarsening": {"geom": COARSEN_GEOMETRIC, "geometric": COARSEN_GEOMETRIC, "mis": COARSEN_MIS},
         "smoother": {"jacobi": SMOOTH_JACOBI, "kaczmarz": SMOOTH_KACZMARZ},
         "precision": {"fp64": PRECISION_FP64, "mixed": PRECISION_MIXED},
+        "learned": {"off": LEARNED_OFF, "use": LEARNED_USE, "record": LEARNED_RECORD},
     }
     for k, v in kw.items():
         if k in names and isinstance(v, str):
             v = names[k][v]
+        if k == "mlp" and isinstance(v, MLP):
+            v = v.h.value
         if not hasattr(o, k):
             raise KeyError(k)
         setattr(o, k, v)
@@ -298,12 +313,100 @@ class Hierarchy:
         _check(lib().bamg_kernel_profile_end(self.h, C.byref(n), C.byref(ms), C.byref(by)))
         return n.value, ms.value, by.value
 
+    def harvest(self, level):
+        """Cycle-1 features and final P rows of level `level`'s F points
+        (handle set up with learned="record"): CUDA float32 tensors
+        X (nF x 96), T (nF x 8), M (nF x 8)."""
+        torch = _torch()
+        nf = C.c_int64()
+        _check(lib().bamg_harvest(self.h, level, None, None, None, C.byref(nf), None))
+        n = nf.value
+        X = torch.empty((n, MLP_IN), dtype=torch.float32, device="cuda")
+        T = torch.empty((n, MLP_OUT), dtype=torch.float32, device="cuda")
+        M = torch.empty((n, MLP_OUT), dtype=torch.float32, device="cuda")
+        if n:
+            _check(lib().bamg_harvest(self.h, level, C.c_void_p(X.data_ptr()),
+                                      C.c_void_p(T.data_ptr()), C.c_void_p(M.data_ptr()),
+                                      C.byref(nf), _stream(None)))
+        return X, T, M
+
+    def learned_stats(self):
+        """(rows taken from the MLP, rows that fell back to the exact LS fit)."""
+        a, b = C.c_int64(), C.c_int64()
+        _check(lib().bamg_learned_stats(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
     def coarse_pinv(self):
         info = self.info()
         nL = info["n"][-1]
         B = np.zeros((nL, nL))
         _check(lib().bamg_coarse_pinv(self.h, B.ctypes.data))
         return B
+
+
+class MLP:
+    """Interpolation-weight network on the device (bamg_mlp_*). Parameters
+    are FP32 in the order W1, b1, W2, b2, W3, b3 (include/bamg.h)."""
+
+    def __init__(self, params):
+        p = np.ascontiguousarray(params, np.float32)
+        if p.shape != (MLP_NPARAMS,):
+            raise ValueError(f"expected {MLP_NPARAMS} parameters")
+        self.h = C.c_void_p()
+        _check(lib().bamg_mlp_create(p.ctypes.data_as(C.c_void_p), C.byref(self.h)))
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().bamg_mlp_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(MLP_NPARAMS, np.float32)
+        _check(lib().bamg_mlp_get_params(self.h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def forward(self, X, mode=1, stream=None):
+        """Y = MLP(X); X CUDA float32 (n x 96). mode 1 = BF16 MFMA, 0 = FP32."""
+        torch = _torch()
+        X = X.contiguous()
+        Y = torch.empty((X.shape[0], MLP_OUT), dtype=torch.float32, device=X.device)
+        _check(lib().bamg_mlp_forward(self.h, C.c_void_p(X.data_ptr()), X.shape[0],
+                                      C.c_void_p(Y.data_ptr()), mode, _stream(stream)))
+        return Y
+
+    def loss_grad(self, X, T, M, stream=None):
+        torch = _torch()
+        g = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=X.device)
+        loss = C.c_double()
+        _check(lib().bamg_mlp_loss_grad(self.h, C.c_void_p(X.data_ptr()),
+                                        C.c_void_p(T.data_ptr()), C.c_void_p(M.data_ptr()),
+                                        X.shape[0], C.byref(loss), C.c_void_p(g.data_ptr()),
+                                        _stream(stream)))
+        return loss.value, g
+
+    def train(self, X, T, M, batch=1024, epochs=10, lr=1e-3, stream=None):
+        """Adam on the masked squared error; returns the mean loss per epoch."""
+        losses = np.zeros(max(epochs, 1), np.float64)
+        _check(lib().bamg_mlp_train(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+                                    C.c_void_p(M.data_ptr()), X.shape[0], batch, epochs, lr,
+                                    losses.ctypes.data_as(C.c_void_p), _stream(stream)))
+        return losses[:epochs]
+
+
+def mlp_init_params(seed):
+    """He-normal weights and zero biases, seeded (float32, MLP_NPARAMS)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for (o, i) in ((MLP_HIDDEN, MLP_IN), (MLP_HIDDEN, MLP_HIDDEN), (MLP_OUT, MLP_HIDDEN)):
+        parts.append(rng.standard_normal(o * i) * np.sqrt(2.0 / i))
+        parts.append(np.zeros(o))
+    return np.concatenate(parts).astype(np.float32)
 
 
 def options_for(chain, **kw) -> Options:

@@ -198,6 +198,8 @@ static bamg_status check_options(const bamg_options *o) {
   if (o->smoother != BAMG_SMOOTH_JACOBI && o->smoother != BAMG_SMOOTH_KACZMARZ) return BAMG_E_ARG;
   if (o->precision != BAMG_PRECISION_FP64 && o->precision != BAMG_PRECISION_MIXED) return BAMG_E_ARG;
   if (o->interp_rule != 0 && o->interp_rule != 1) return BAMG_E_ARG;
+  if (o->learned < BAMG_LEARNED_OFF || o->learned > BAMG_LEARNED_RECORD) return BAMG_E_ARG;
+  if (o->learned == BAMG_LEARNED_USE && !o->mlp) return BAMG_E_ARG;
   return BAMG_OK;
 }
 
@@ -460,6 +462,114 @@ bamg_status bamg_kernel_profile_end(bamg_handle *h, int64_t *launches, double *m
   if (bytes_total) *bytes_total = h->prof_bytes;
   h->prof_kernel = -1;
   h->prof_used = 0;
+  return BAMG_OK;
+  BAMG_CATCH
+}
+
+bamg_status bamg_mlp_create(const float *params, bamg_mlp **out) {
+  if (!params || !out) return BAMG_E_ARG;
+  bamg_mlp *m = new (std::nothrow) bamg_mlp();
+  if (!m) return BAMG_E_NOMEM;
+  const size_t pb = sizeof(float) * BAMG_MLP_NPARAMS;
+  try {
+    HIPCHK(hipMalloc(&m->p, pb));
+    HIPCHK(hipMalloc(&m->m, pb));
+    HIPCHK(hipMalloc(&m->v, pb));
+    HIPCHK(hipMalloc(&m->wb, sizeof(__bf16) * (BAMG_MLP_HIDDEN * BAMG_MLP_IN +
+                                               BAMG_MLP_HIDDEN * BAMG_MLP_HIDDEN +
+                                               16 * BAMG_MLP_HIDDEN)));
+    HIPCHK(hipMemcpy(m->p, params, pb, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(m->m, 0, pb));
+    HIPCHK(hipMemset(m->v, 0, pb));
+    mlp_refresh_bf16(m, nullptr);
+    HIPCHK(hipDeviceSynchronize());
+  } catch (const Error &e) {
+    bamg_mlp_destroy(m);
+    return translate(e);
+  }
+  *out = m;
+  return BAMG_OK;
+}
+
+bamg_status bamg_mlp_get_params(const bamg_mlp *m, float *params) {
+  if (!m || !params) return BAMG_E_ARG;
+  BAMG_TRY
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(params, m->p, sizeof(float) * BAMG_MLP_NPARAMS, hipMemcpyDeviceToHost));
+  return BAMG_OK;
+  BAMG_CATCH
+}
+
+void bamg_mlp_destroy(bamg_mlp *m) {
+  if (!m) return;
+  void *ps[] = {m->p, m->m, m->v, m->wb};
+  for (void *p : ps)
+    if (p) (void)hipFree(p);
+  delete m;
+}
+
+bamg_status bamg_mlp_forward(const bamg_mlp *m, const float *X, int64_t npts, float *Y,
+                             int32_t mode, void *hip_stream) {
+  if (!m || npts < 0 || (npts > 0 && (!X || !Y)) || (mode != 0 && mode != 1)) return BAMG_E_ARG;
+  BAMG_TRY
+  mlp_forward(m, X, (long)npts, Y, mode, (hipStream_t)hip_stream);
+  return BAMG_OK;
+  BAMG_CATCH
+}
+
+bamg_status bamg_mlp_loss_grad(const bamg_mlp *m, const float *X, const float *T,
+                               const float *M, int64_t npts, double *loss, float *grad,
+                               void *hip_stream) {
+  if (!m || !X || !T || !M || npts < 1 || !loss || !grad) return BAMG_E_ARG;
+  BAMG_TRY
+  *loss = mlp_loss_grad(m, X, T, M, (long)npts, grad, (hipStream_t)hip_stream);
+  return BAMG_OK;
+  BAMG_CATCH
+}
+
+bamg_status bamg_mlp_train(bamg_mlp *m, const float *X, const float *T, const float *M,
+                           int64_t npts, int32_t batch, int32_t epochs, float lr,
+                           double *loss_per_epoch, void *hip_stream) {
+  if (!m || !X || !T || !M || npts < 1 || batch < 1 || epochs < 0 || !(lr > 0.f))
+    return BAMG_E_ARG;
+  BAMG_TRY
+  mlp_train(m, X, T, M, (long)npts, batch, epochs, lr, loss_per_epoch, (hipStream_t)hip_stream);
+  return BAMG_OK;
+  BAMG_CATCH
+}
+
+bamg_status bamg_harvest(const bamg_handle *h, int32_t level, float *X, float *T, float *M,
+                         int64_t *nF, void *hip_stream) {
+  if (!h || !nF || level < 0 || level >= h->L - 1) return BAMG_E_ARG;
+  const Level &L = h->lv[level];
+  if (h->opt.learned != BAMG_LEARNED_RECORD || L.nF < 0) return BAMG_E_ARG;
+  *nF = L.nF;
+  if (!X && !T && !M) return BAMG_OK;
+  if (!X || !T || !M) return BAMG_E_ARG;
+  BAMG_TRY
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (L.nF > 0) {
+    HIPCHK(hipMemcpyAsync(X, L.feat, sizeof(float) * (size_t)L.nF * BAMG_MLP_IN,
+                          hipMemcpyDeviceToDevice, s));
+    if (h->prec == 0)
+      mlp_targets<double>(L, (const double *)L.Pv, T, M, s);
+    else
+      mlp_targets<float>(L, (const float *)L.Pv, T, M, s);
+  }
+  return BAMG_OK;
+  BAMG_CATCH
+}
+
+bamg_status bamg_learned_stats(const bamg_handle *h, int64_t *mlp_rows, int64_t *fallback_rows) {
+  if (!h || !mlp_rows || !fallback_rows) return BAMG_E_ARG;
+  int c[2] = {0, 0};
+  BAMG_TRY
+  if (h->lcount) {
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(c, h->lcount, sizeof(c), hipMemcpyDeviceToHost));
+  }
+  *mlp_rows = c[0];
+  *fallback_rows = c[1];
   return BAMG_OK;
   BAMG_CATCH
 }

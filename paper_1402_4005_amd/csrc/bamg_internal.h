@@ -80,9 +80,19 @@ struct Level {
   std::vector<int> offB, offBt;                 // host: colour segment offsets
   void *rowinvB = nullptr, *rowinvBt = nullptr; // 1/||row||^2
   int lanes = 0;                                // lanes per CSR row (0 = from nnz/row)
+  // learned interpolation: F points (ascending) and recorded cycle-1 features
+  int *fpts = nullptr;
+  int nF = -1;
+  float *feat = nullptr;  // nF x BAMG_MLP_IN (learned = record)
 };
 
 }  // namespace bamg
+
+struct bamg_mlp {
+  float *p = nullptr, *m = nullptr, *v = nullptr;  // FP32 parameters, Adam moments
+  __bf16 *wb = nullptr;                            // BF16 weights for MFMA inference
+  int step = 0;                                    // Adam steps taken
+};
 
 struct bamg_handle {
   bamg_options opt{};
@@ -117,6 +127,7 @@ struct bamg_handle {
   // input validation running beside the setup on an auxiliary stream
   hipStream_t aux = nullptr;
   hipEvent_t aux_ready = nullptr, aux_done = nullptr;
+  int *lcount = nullptr;  // device: [MLP rows, LS fallback rows]
   int *vflag = nullptr;  // device: [colsum bits, reached forward, reached backward, -]
   void join_validation(bool wait_main);
   int validation_result();
@@ -254,5 +265,21 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
 constexpr int kRedBlocks = 1024;  // partial-sum blocks of the reductions
 
 inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+// learned interpolation weights (k_mlp.hip)
+void mlp_refresh_bf16(bamg_mlp *m, hipStream_t s);
+void mlp_forward(const bamg_mlp *m, const float *X, long npts, float *Y, int mode, hipStream_t s);
+double mlp_loss_grad(const bamg_mlp *m, const float *X, const float *T, const float *M, long npts,
+                     float *grad, hipStream_t s);
+void mlp_train(bamg_mlp *m, const float *X, const float *T, const float *M, long npts, int batch,
+               int epochs, float lr, double *loss_per_epoch, hipStream_t s);
+void level_fpoints(bamg_handle *h, Level &L, hipStream_t s);
+template <class T>
+void mlp_features(const Level &L, int r, const T *V, const double *wv, float *F, hipStream_t s);
+template <class T>
+void mlp_select(const Level &L, int r, const T *V, const double *wv, const float *Y, T *Pv,
+                int *counts, hipStream_t s);
+template <class T>
+void mlp_targets(const Level &L, const T *Pv, float *Tg, float *Mk, hipStream_t s);
 
 }  // namespace bamg

@@ -130,6 +130,27 @@ struct Setup {
     }
   }
 
+  // Learned interpolation (cycle 1): the MLP's weights replace the exact LS
+  // row where their LS objective is within twice the optimum; in record mode
+  // the features are kept for bamg_harvest.
+  void learned_rows(Level &L) {
+    level_fpoints(h, L, s);
+    if (L.nF <= 0) return;
+    const size_t nf = (size_t)L.nF;
+    if (h->opt.learned == BAMG_LEARNED_RECORD) {
+      if (!L.feat) L.feat = pool().template get<float>(nf * BAMG_MLP_IN);
+      mlp_features<T>(L, r, (const T *)L.V, wv, L.feat, s);
+      return;
+    }
+    float *F = pool().template get<float>(nf * BAMG_MLP_IN);
+    float *Y = pool().template get<float>(nf * BAMG_MLP_OUT);
+    mlp_features<T>(L, r, (const T *)L.V, wv, F, s);
+    mlp_forward(h->opt.mlp, F, L.nF, Y, 1, s);
+    mlp_select<T>(L, r, (const T *)L.V, wv, Y, (T *)L.Pv, h->lcount, s);
+    pool().release(Y);
+    pool().release(F);
+  }
+
   // Algorithm 1 (bamg_mle) from level l
   void mle(int l, int cycle) {
     if (l == h->L - 1) {
@@ -142,6 +163,7 @@ struct Setup {
     weights(L);
     ls_fit<T>(L, r, (const T *)L.U, (const T *)L.V, wv, wu, h->opt.interp_rule, (T *)L.Pv,
               (T *)L.Qtv, s);
+    if (h->opt.learned != BAMG_LEARNED_OFF && cycle == 1) learned_rows(L);
     galerkin(l);
     Level &C = h->lv[l + 1];
     inject<T>(L.cpts, C.n, r, (const T *)L.U, (T *)C.U, s);
@@ -426,6 +448,11 @@ void setup_all(bamg_handle *h, const bamg_csr *A, const bamg_geometry *geom) {
   S.scales = pool.get<double>(32);
   S.flag = flag;
   S.alloc_dense(nL);
+
+  if (o.learned != BAMG_LEARNED_OFF) {
+    h->lcount = pool.get<int>(2);
+    fill_i32(h->lcount, 0, 2, s);
+  }
 
   // ---- bootstrap cycles
   philox_testvecs(h->lv[0].U, h->lv[0].V, h->prec, n, r, o.seed, s);
