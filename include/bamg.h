@@ -99,6 +99,8 @@ typedef struct {
   int32_t use_graph;    /* 1 = GMRES replays the V-cycle from a captured HIP graph */
   int32_t learned;      /* BAMG_LEARNED_*: interpolation weights from an MLP (see below) */
   const struct bamg_mlp *mlp; /* network for BAMG_LEARNED_USE, else ignored */
+  int32_t autotune;     /* 1 = time the lanes-per-row choices of each level's
+                           sweeps once per matrix shape (cached per process) */
 } bamg_options;
 
 /* Learned interpolation weights. Not part of the paper: an addition whose
@@ -144,10 +146,12 @@ typedef struct bamg_handle bamg_handle;
  * ls_weights, divided by their maximum):
  *   f[9k]         = sqrt(w_k) v^(k)_i / S          k = 0..7
  *   f[9k + 1 + t] = sqrt(w_k) v^(k)_{j_t} / S      t < m, else 0
- *   f[72 + t] = B_{i j_t} / B_ii,  f[80 + t] = B_{j_t i} / B_ii  (t < m, else 0)
+ *   f[72 + t] = B_{i j_t} / B_ii                    (t < m, else 0)
+ *   f[80 + t] = p^LS_{i j_t}, the exact cycle-1 fit of the row
  *   f[88 + t] = 1 if t < m else 0
  * with S the largest |sqrt(w_k) v^(k)| among the gathered values (1 if 0).
- * Outputs: the weights p_{i j_t}, t < m (entries t >= m are ignored). */
+ * Outputs y_t are corrections: the network's row is p^LS_{i j_t} + y_t,
+ * t < m (entries t >= m are ignored). */
 #define BAMG_MLP_IN 96
 #define BAMG_MLP_HIDDEN 64
 #define BAMG_MLP_OUT 8
@@ -229,6 +233,32 @@ bamg_status bamg_kernel_profile_end(bamg_handle *h, int64_t *launches, double *m
 /* Free every resource of h (NULL is ignored). */
 void bamg_destroy(bamg_handle *h);
 
+/* ---------------------------------------------------------------------
+ * Many independent chains. bamg_setup_batched sets up chain i from A[i],
+ * geom[i] (geom may be NULL: no geometry for any chain) and opt[i]. The
+ * chains run concurrently on nstreams library streams (0 = 4), largest
+ * first, each stream served by its own host thread; the caller's stream
+ * is joined to them on entry and on return, so work enqueued on it
+ * afterwards sees every result. A failing chain does not fail the batch:
+ * its status is kept (bamg_batch_status) and it is skipped by the solve.
+ * Returns BAMG_OK when the batch object was created. */
+typedef struct bamg_batch bamg_batch;
+bamg_status bamg_setup_batched(int32_t nchains, const bamg_csr *A, const bamg_geometry *geom,
+                               const bamg_options *opt, const bamg_allocator *alloc,
+                               int32_t nstreams, void *hip_stream, bamg_batch **out);
+/* Setup status of chain i and its handle (NULL if the setup failed); the
+ * handle stays owned by the batch. */
+bamg_status bamg_batch_status(const bamg_batch *b, int32_t i, bamg_status *setup_status,
+                              bamg_handle **handle);
+/* bamg_gmres_solve for every chain that was set up: x[i] device FP64 of
+ * chain i's length; infos and statuses (host, nchains entries each;
+ * statuses nullable) receive each chain's result. Returns BAMG_OK if all
+ * chains converged, BAMG_NOT_CONVERGED if any did not or failed. */
+bamg_status bamg_gmres_solve_batched(bamg_batch *b, double *const *x, int32_t restart,
+                                     double tol, int32_t max_iters, bamg_solve_info *infos,
+                                     bamg_status *statuses, void *hip_stream);
+void bamg_batch_destroy(bamg_batch *b);
+
 /* Create a network from BAMG_MLP_NPARAMS FP32 parameters (host memory,
  * copied) on the current device. Adam moments start at zero. */
 bamg_status bamg_mlp_create(const float *params, bamg_mlp **out);
@@ -258,7 +288,8 @@ bamg_status bamg_mlp_train(bamg_mlp *m, const float *X, const float *T, const fl
 /* Training data of a handle set up with learned = BAMG_LEARNED_RECORD:
  * for level l (< levels - 1), the cycle-1 features of its F points
  * (ascending state index) and their final P rows (weights in J_i order,
- * zero-padded to 8) with a mask of the valid entries. X, T, M are device
+ * zero-padded to 8) with a mask of the valid entries. Training targets for
+ * the corrections are T - X[:, 80:88]. X, T, M are device
  * FP32 buffers of nF x 96, nF x 8, nF x 8, or all NULL to query *nF. */
 bamg_status bamg_harvest(const bamg_handle *h, int32_t level, float *X, float *T, float *M,
                          int64_t *nF, void *hip_stream);

@@ -975,7 +975,8 @@ static double csr_at(const csr *A, int i, int j) {
  * of the paper). For F point i with interpolation points j_1..j_m (m <= 8)
  * and the normalised LS weights w_k of the first min(r, 8) right vectors:
  * 8 groups of 9 values sqrt(w_k) v_k at (i, j_1..j_8), divided by their
- * largest magnitude; B_{i j_t}/B_ii; B_{j_t i}/B_ii; and the mask t < m. */
+ * largest magnitude; B_{i j_t}/B_ii; the row's exact LS weights p_t just
+ * fitted; and the mask t < m. */
 static void record_features(orc_ctx *c, level *L, const double *wv) {
   int n = L->n, r = c->o.r, kr = r < 8 ? r : 8;
   int nF = 0;
@@ -1007,7 +1008,7 @@ static void record_features(orc_ctx *c, level *L, const double *wv) {
     if (bii == 0.0) bii = 1.0;
     for (int t = 0; t < m; ++t) {
       o[72 + t] = csr_at(&L->B, i, J[t]) / bii;
-      o[80 + t] = csr_at(&L->Bt, i, J[t]) / bii;
+      o[80 + t] = L->P.v[a + t];
       o[88 + t] = 1.0;
     }
     ++f;

@@ -50,7 +50,8 @@ class Options(C.Structure):
                 ("max_interp", C.c_int32), ("max_levels", C.c_int32), ("coarse_max", C.c_int32),
                 ("coarsening", C.c_int32), ("seed", C.c_uint64), ("smoother", C.c_int32),
                 ("precision", C.c_int32), ("interp_rule", C.c_int32), ("validate", C.c_int32),
-                ("use_graph", C.c_int32), ("learned", C.c_int32), ("mlp", C.c_void_p)]
+                ("use_graph", C.c_int32), ("learned", C.c_int32), ("mlp", C.c_void_p),
+                ("autotune", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -108,6 +109,11 @@ def lib():
         L.bamg_mlp_train.argtypes = [V, V, V, V, C.c_int64, C.c_int32, C.c_int32, C.c_float,
                                      V, V]
         L.bamg_harvest.argtypes = [V, C.c_int32, V, V, V, P(C.c_int64), V]
+        L.bamg_setup_batched.argtypes = [C.c_int32, V, V, V, V, C.c_int32, V, P(V)]
+        L.bamg_batch_status.argtypes = [V, C.c_int32, P(C.c_int32), P(V)]
+        L.bamg_gmres_solve_batched.argtypes = [V, V, C.c_int32, C.c_double, C.c_int32, V, V, V]
+        L.bamg_batch_destroy.argtypes = [V]
+        L.bamg_batch_destroy.restype = None
         L.bamg_learned_stats.argtypes = [V, P(C.c_int64), P(C.c_int64)]
         _lib = L
     return _lib
@@ -342,6 +348,61 @@ class Hierarchy:
         B = np.zeros((nL, nL))
         _check(lib().bamg_coarse_pinv(self.h, B.ctypes.data))
         return B
+
+
+class Batch:
+    """Many chains set up and solved together (bamg_setup_batched): chains
+    is a list of chaingen.Chain, opts a list of Options (one per chain)."""
+
+    def __init__(self, chains, opts, nstreams=0, stream=None):
+        torch = _torch()
+        self.n = len(chains)
+        self._keep = []
+        A = (Csr * self.n)()
+        G = (Geometry * self.n)()
+        O = (Options * self.n)()
+        for i, (ch, o) in enumerate(zip(chains, opts)):
+            rp = torch.from_numpy(ch.indptr).cuda()
+            ci = torch.from_numpy(ch.indices).cuda()
+            va = torch.from_numpy(ch.data).cuda()
+            self._keep += [rp, ci, va]
+            A[i] = Csr(ch.n, ch.nnz, rp.data_ptr(), ci.data_ptr(), va.data_ptr(), 1)
+            G[i] = Geometry(*ch.geom)
+            O[i] = o
+        self.sizes = [ch.n for ch in chains]
+        self.h = C.c_void_p()
+        _check(lib().bamg_setup_batched(self.n, C.byref(A), C.byref(G), C.byref(O), None,
+                                        nstreams, _stream(stream), C.byref(self.h)))
+        self._keep = None
+
+    def status(self, i):
+        st = C.c_int32()
+        hh = C.c_void_p()
+        _check(lib().bamg_batch_status(self.h, i, C.byref(st), C.byref(hh)))
+        return st.value
+
+    def gmres(self, restart=20, tol=1e-10, maxit=500, stream=None):
+        """Solve every chain; returns (list of x tensors or None, infos, statuses)."""
+        torch = _torch()
+        xs = [torch.empty(n, dtype=torch.float64, device="cuda") for n in self.sizes]
+        ptrs = (C.c_void_p * self.n)(*[x.data_ptr() for x in xs])
+        infos = (SolveInfo * self.n)()
+        sts = (C.c_int32 * self.n)()
+        _check(lib().bamg_gmres_solve_batched(self.h, ptrs, restart, tol, maxit, infos, sts,
+                                              _stream(stream)))
+        out = [x if sts[i] >= 0 else None for i, x in enumerate(xs)]
+        return out, list(infos), list(sts)
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().bamg_batch_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class MLP:

@@ -266,6 +266,10 @@ constexpr int kRedBlocks = 1024;  // partial-sum blocks of the reductions
 
 inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
+// lanes per CSR row for a level's sweeps, by timing (tune.hip)
+template <class T>
+int tune_lanes(Pool &pool, const Level &L, hipStream_t s);
+
 // learned interpolation weights (k_mlp.hip)
 void mlp_refresh_bf16(bamg_mlp *m, hipStream_t s);
 void mlp_forward(const bamg_mlp *m, const float *X, long npts, float *Y, int mode, hipStream_t s);
@@ -275,7 +279,8 @@ void mlp_train(bamg_mlp *m, const float *X, const float *T, const float *M, long
                int epochs, float lr, double *loss_per_epoch, hipStream_t s);
 void level_fpoints(bamg_handle *h, Level &L, hipStream_t s);
 template <class T>
-void mlp_features(const Level &L, int r, const T *V, const double *wv, float *F, hipStream_t s);
+void mlp_features(const Level &L, int r, const T *V, const double *wv, const T *Pv, float *F,
+                  hipStream_t s);
 template <class T>
 void mlp_select(const Level &L, int r, const T *V, const double *wv, const float *Y, T *Pv,
                 int *counts, hipStream_t s);

@@ -1,0 +1,140 @@
+// Many independent chains: setup and solve spread over a few library
+// streams, one host thread per stream, chains taken largest first from a
+// shared counter. Each chain's hierarchy is an ordinary handle.
+#include <algorithm>
+#include <atomic>
+#include <numeric>
+#include <thread>
+#include <vector>
+
+#include "bamg_internal.h"
+
+struct bamg_batch {
+  int n = 0;
+  int dev = 0;
+  std::vector<bamg_handle *> h;
+  std::vector<bamg_status> st;
+  std::vector<hipStream_t> streams;
+  std::vector<int> order;  // chains by decreasing nonzeros
+};
+
+namespace {
+
+void join_into(hipStream_t from, hipStream_t to) {
+  hipEvent_t e;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+    bamg::fail(BAMG_E_DEVICE, "event create failed");
+  (void)hipEventRecord(e, from);
+  (void)hipStreamWaitEvent(to, e, 0);
+  (void)hipEventDestroy(e);
+}
+
+// run f(chain, stream) over the batch with one thread per stream
+template <class F>
+void for_each_chain(bamg_batch *b, F f) {
+  std::atomic<int> next{0};
+  auto work = [&](int w) {
+    (void)hipSetDevice(b->dev);
+    for (;;) {
+      const int k = next.fetch_add(1);
+      if (k >= b->n) break;
+      f(b->order[k], b->streams[w]);
+    }
+  };
+  std::vector<std::thread> th;
+  for (int w = 1; w < (int)b->streams.size(); ++w) th.emplace_back(work, w);
+  work(0);
+  for (auto &t : th) t.join();
+}
+
+}  // namespace
+
+extern "C" {
+
+bamg_status bamg_setup_batched(int32_t nchains, const bamg_csr *A, const bamg_geometry *geom,
+                               const bamg_options *opt, const bamg_allocator *alloc,
+                               int32_t nstreams, void *hip_stream, bamg_batch **out) {
+  if (nchains < 1 || !A || !opt || !out || nstreams < 0 || nstreams > 32) return BAMG_E_ARG;
+  bamg_batch *b = new (std::nothrow) bamg_batch();
+  if (!b) return BAMG_E_NOMEM;
+  b->n = nchains;
+  b->h.assign(nchains, nullptr);
+  b->st.assign(nchains, BAMG_E_ARG);
+  b->order.resize(nchains);
+  std::iota(b->order.begin(), b->order.end(), 0);
+  std::stable_sort(b->order.begin(), b->order.end(),
+                   [&](int x, int y) { return A[x].nnz > A[y].nnz; });
+  hipStream_t caller = (hipStream_t)hip_stream;
+  const int ns = std::min<int>(nstreams ? nstreams : 4, nchains);
+  if (hipGetDevice(&b->dev) != hipSuccess) {
+    delete b;
+    return BAMG_E_DEVICE;
+  }
+  for (int w = 0; w < ns; ++w) {
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      bamg_batch_destroy(b);
+      return BAMG_E_DEVICE;
+    }
+    b->streams.push_back(s);
+  }
+  try {
+    for (hipStream_t s : b->streams) join_into(caller, s);  // inputs are ready
+    for_each_chain(b, [&](int i, hipStream_t s) {
+      b->st[i] = bamg_setup(&A[i], geom ? &geom[i] : nullptr, &opt[i], alloc, s, &b->h[i]);
+    });
+    for (hipStream_t s : b->streams) join_into(s, caller);
+  } catch (const bamg::Error &e) {
+    bamg_batch_destroy(b);
+    return e.code;
+  }
+  *out = b;
+  return BAMG_OK;
+}
+
+bamg_status bamg_batch_status(const bamg_batch *b, int32_t i, bamg_status *setup_status,
+                              bamg_handle **handle) {
+  if (!b || i < 0 || i >= b->n) return BAMG_E_ARG;
+  if (setup_status) *setup_status = b->st[i];
+  if (handle) *handle = b->h[i];
+  return BAMG_OK;
+}
+
+bamg_status bamg_gmres_solve_batched(bamg_batch *b, double *const *x, int32_t restart,
+                                     double tol, int32_t max_iters, bamg_solve_info *infos,
+                                     bamg_status *statuses, void *hip_stream) {
+  if (!b || !x || !infos) return BAMG_E_ARG;
+  for (int i = 0; i < b->n; ++i)
+    if (b->h[i] && !x[i]) return BAMG_E_ARG;
+  std::vector<bamg_status> st(b->n, BAMG_E_ARG);
+  hipStream_t caller = (hipStream_t)hip_stream;
+  try {
+    for (hipStream_t s : b->streams) join_into(caller, s);
+    for_each_chain(b, [&](int i, hipStream_t s) {
+      infos[i] = bamg_solve_info{};
+      if (!b->h[i]) {
+        st[i] = b->st[i];
+        return;
+      }
+      st[i] = bamg_gmres_solve(b->h[i], x[i], restart, tol, max_iters, 0, &infos[i], s);
+    });
+    for (hipStream_t s : b->streams) join_into(s, caller);
+  } catch (const bamg::Error &e) {
+    return e.code;
+  }
+  bool all = true;
+  for (int i = 0; i < b->n; ++i) {
+    if (statuses) statuses[i] = st[i];
+    all = all && st[i] == BAMG_OK;
+  }
+  return all ? BAMG_OK : BAMG_NOT_CONVERGED;
+}
+
+void bamg_batch_destroy(bamg_batch *b) {
+  if (!b) return;
+  for (bamg_handle *h : b->h) bamg_destroy(h);
+  for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+  delete b;
+}
+
+}  // extern "C"

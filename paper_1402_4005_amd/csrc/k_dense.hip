@@ -675,16 +675,15 @@ __global__ void __launch_bounds__(kSmallThreads)
 size_t coarse_small_lds(int n) { return sizeof(double) * ((size_t)2 * n * (n + 1) + n); }
 
 int coarse_small_max(void) {
-  static int nmax = -1;
-  if (nmax < 0) {
+  static const int nmax = [] {  // thread-safe one-time initialisation
     int dev = 0, lds = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
       lds = 65536;
     int n = 2;
     while (coarse_small_lds(n + 1) + 1024 <= (size_t)lds && n < 128) ++n;
-    nmax = n;
-  }
+    return n;
+  }();
   return nmax;
 }
 

@@ -4,6 +4,9 @@
 // fit of eq. ls_interpolation, keeping the exact fit for any row where the
 // network's weights give an LS objective above twice the optimum.
 //
+// The network's outputs are corrections added to the exact LS row, which is
+// also one of its inputs.
+//
 // Kernels:
 //  * k_mlp_infer      inference on MFMA (v_mfma_f32_16x16x32_bf16): one wave
 //                     per 16 points, weights in LDS as BF16, FP32 accumulate;
@@ -235,8 +238,7 @@ __global__ void k_mlp_features(int nF, const int *__restrict__ fpts, int r,
                                const int *__restrict__ cpts, const T *__restrict__ V,
                                const double *__restrict__ wv, const int *__restrict__ brp,
                                const int *__restrict__ bci, const T *__restrict__ bv,
-                               const int *__restrict__ btrp, const int *__restrict__ btci,
-                               const T *__restrict__ btv, float *__restrict__ F) {
+                               const T *__restrict__ Pv, float *__restrict__ F) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= nF) return;
   const int i = fpts[f];
@@ -264,21 +266,19 @@ __global__ void k_mlp_features(int nF, const int *__restrict__ fpts, int r,
     if (bci[a] == i) bii = (double)bv[a];
   if (bii == 0.0) bii = 1.0;
   for (int t = 0; t < kOut; ++t) {
-    double bij = 0.0, bji = 0.0;
-    if (t < m) {
+    double bij = 0.0;
+    if (t < m)
       for (int a = brp[i]; a < brp[i + 1]; ++a)
         if (bci[a] == J[t]) bij = (double)bv[a];
-      for (int a = btrp[i]; a < btrp[i + 1]; ++a)
-        if (btci[a] == J[t]) bji = (double)btv[a];
-    }
     o[72 + t] = (float)(bij / bii);
-    o[80 + t] = (float)(bji / bii);
+    o[80 + t] = t < m ? (float)Pv[a0 + t] : 0.f;
     o[88 + t] = t < m ? 1.f : 0.f;
   }
 }
 
-// LS objective sum_k w_k (v_i - sum_t p_t v_{j_t})^2 of the MLP row against
-// the exact row already in Pv; the MLP row replaces it if within 2x.
+// LS objective sum_k w_k (v_i - sum_t p_t v_{j_t})^2 of the MLP row (the
+// exact row in Pv plus the network's correction) against the exact row; the
+// MLP row replaces it if within 2x.
 template <class T>
 __global__ void k_mlp_select(int nF, const int *__restrict__ fpts, int r,
                              const int *__restrict__ prp, const int *__restrict__ pci,
@@ -294,14 +294,14 @@ __global__ void k_mlp_select(int nF, const int *__restrict__ fpts, int r,
     double em = (double)V[(size_t)i * r + k], el = em;
     for (int t = 0; t < m; ++t) {
       const double vj = (double)V[(size_t)cpts[pci[a0 + t]] * r + k];
-      em -= (double)Y[(size_t)f * kOut + t] * vj;
+      em -= ((double)Pv[a0 + t] + (double)Y[(size_t)f * kOut + t]) * vj;
       el -= (double)Pv[a0 + t] * vj;
     }
     jm += wv[k] * em * em;
     jl += wv[k] * el * el;
   }
   if (jm <= 2.0 * jl) {
-    for (int t = 0; t < m; ++t) Pv[a0 + t] = (T)Y[(size_t)f * kOut + t];
+    for (int t = 0; t < m; ++t) Pv[a0 + t] = (T)((double)Pv[a0 + t] + (double)Y[(size_t)f * kOut + t]);
     atomicAdd(&counts[0], 1);
   } else {
     atomicAdd(&counts[1], 1);
@@ -460,11 +460,12 @@ void level_fpoints(bamg_handle *h, Level &L, hipStream_t s) {
 }
 
 template <class T>
-void mlp_features(const Level &L, int r, const T *V, const double *wv, float *F, hipStream_t s) {
+void mlp_features(const Level &L, int r, const T *V, const double *wv, const T *Pv, float *F,
+                  hipStream_t s) {
   if (L.nF <= 0) return;
-  k_mlp_features<T><<<ceil_div(L.nF, 128), 128, 0, s>>>(
-      L.nF, L.fpts, r, L.P.rp, L.P.ci, L.cpts, V, wv, L.B.rp, L.B.ci, (const T *)L.Bv, L.Bt.rp,
-      L.Bt.ci, (const T *)L.Btv, F);
+  k_mlp_features<T><<<ceil_div(L.nF, 128), 128, 0, s>>>(L.nF, L.fpts, r, L.P.rp, L.P.ci, L.cpts,
+                                                        V, wv, L.B.rp, L.B.ci, (const T *)L.Bv,
+                                                        Pv, F);
   LAUNCHCHK();
 }
 
@@ -485,8 +486,8 @@ void mlp_targets(const Level &L, const T *Pv, float *Tg, float *Mk, hipStream_t 
 }
 
 #define INST(T)                                                                              \
-  template void mlp_features<T>(const Level &, int, const T *, const double *, float *,     \
-                                hipStream_t);                                                \
+  template void mlp_features<T>(const Level &, int, const T *, const double *, const T *,  \
+                                float *, hipStream_t);                                       \
   template void mlp_select<T>(const Level &, int, const T *, const double *, const float *, \
                               T *, int *, hipStream_t);                                      \
   template void mlp_targets<T>(const Level &, const T *, float *, float *, hipStream_t);

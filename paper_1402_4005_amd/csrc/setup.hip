@@ -130,21 +130,21 @@ struct Setup {
     }
   }
 
-  // Learned interpolation (cycle 1): the MLP's weights replace the exact LS
-  // row where their LS objective is within twice the optimum; in record mode
-  // the features are kept for bamg_harvest.
+  // Learned interpolation (cycle 1): the exact LS row plus the MLP's
+  // correction replaces the exact row where its LS objective is within twice
+  // the optimum; in record mode the features are kept for bamg_harvest.
   void learned_rows(Level &L) {
     level_fpoints(h, L, s);
     if (L.nF <= 0) return;
     const size_t nf = (size_t)L.nF;
     if (h->opt.learned == BAMG_LEARNED_RECORD) {
       if (!L.feat) L.feat = pool().template get<float>(nf * BAMG_MLP_IN);
-      mlp_features<T>(L, r, (const T *)L.V, wv, L.feat, s);
+      mlp_features<T>(L, r, (const T *)L.V, wv, (const T *)L.Pv, L.feat, s);
       return;
     }
     float *F = pool().template get<float>(nf * BAMG_MLP_IN);
     float *Y = pool().template get<float>(nf * BAMG_MLP_OUT);
-    mlp_features<T>(L, r, (const T *)L.V, wv, F, s);
+    mlp_features<T>(L, r, (const T *)L.V, wv, (const T *)L.Pv, F, s);
     mlp_forward(h->opt.mlp, F, L.nF, Y, 1, s);
     mlp_select<T>(L, r, (const T *)L.V, wv, Y, (T *)L.Pv, h->lcount, s);
     pool().release(Y);
@@ -475,6 +475,8 @@ void setup_all(bamg_handle *h, const bamg_csr *A, const bamg_geometry *geom) {
   normalize_sum(h->x0, n, part, nb, fl, s);
   pool.release(part);
   pool.release(fl);
+  if (o.autotune)
+    for (int l = 0; l + 1 < h->L; ++l) h->lv[l].lanes = tune_lanes<T>(pool, h->lv[l], s);
   h->join_validation(true);
   st = h->validation_result();
   if (st != BAMG_OK) fail(st, "transition matrix rejected");

@@ -116,19 +116,24 @@ def test_harvest_matches_oracle(name, make, kw):
 def test_learned_rows_follow_the_objective_rule():
     # Level 0's cycle-1 features and LS rows are the same with and without
     # the network (nothing before the first fit depends on it). Every F row
-    # of P in learned mode must be the MFMA output when its LS objective,
-    # computable from the features, is within twice the exact fit's, and
-    # the exact row otherwise; x must still be the stationary vector.
+    # of P in learned mode must be the LS row plus the MFMA correction when
+    # its LS objective, computable from the features, is within twice the
+    # exact fit's, and the exact row otherwise; x must still be the
+    # stationary vector.
     import torch
     ch = chaingen.tandem(33, 11 / 31, 10 / 31, 10 / 31)
     kw = dict(r=8, coarse_max=300, nu_setup=3)
     rec = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, learned="record", **kw))
     X, T_ls, M = (a.cpu().numpy() for a in rec.harvest(0))
-    # a network trained briefly on these LS rows: close to them, not equal
+    # a network trained towards small random corrections of the LS rows, so
+    # that some rows pass the objective test and some do not
+    assert np.array_equal(X[:, 80:88], T_ls)
+    rng = np.random.default_rng(13)
+    Tc = (0.05 * rng.standard_normal(T_ls.shape) * M).astype(np.float32)
     net = bamg.MLP(bamg.mlp_init_params(12))
-    Xd, Td, Md = (torch.from_numpy(a).cuda() for a in (X, T_ls, M))
-    net.train(Xd, Td, Md, batch=256, epochs=40, lr=2e-3)
-    Y = net.forward(Xd, mode=1).cpu().numpy()
+    Xd, Td, Md = (torch.from_numpy(a).cuda() for a in (X, Tc, M))
+    net.train(Xd, Td, Md, batch=256, epochs=20, lr=2e-3)
+    Y = T_ls + net.forward(Xd, mode=1).cpu().numpy() * M
     use = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, learned="use", mlp=net, **kw))
     Pm = use.scipy(0, "P")
     cf, _ = use.cf(0)
@@ -145,7 +150,7 @@ def test_learned_rows_follow_the_objective_rule():
             continue  # too close to the threshold to decide in FP32 features
         info = (f, i, m, row, Y[f, :m], T_ls[f, :m], jm, jl)
         if jm <= 2 * jl:
-            assert np.allclose(row, Y[f, :m], rtol=0, atol=1e-6), info
+            assert np.allclose(row, Y[f, :m], rtol=0, atol=2e-6), info
             n_mlp += 1
         else:
             assert np.allclose(row, T_ls[f, :m], rtol=1e-6, atol=1e-7), info  # FP32 harvest
