@@ -85,12 +85,115 @@ def make_chain(kind, size, seed):
     return chaingen.tandem(size, 11 / 31, 10 / 31, 10 / 31)
 
 
+# training chains of the learned form, per family: (kind, size, seed)
+LEARN_TRAIN = {
+    "delaunay": [("delaunay", n, 100 + i) for i, n in enumerate([4096, 8192, 16384, 32768,
+                                                                  65536])],
+    "tandem": [("tandem", n, 0) for n in (33, 65, 129, 257)],
+}
+
+
+def batch_members(count, master_seed):
+    """The batched workload: chain k uses numpy's generator seeded with
+    (master_seed, k). Even k: tandem queue on an N x N grid, N uniform in
+    17..257, rates uniform in [0.2, 0.5] normalised; odd k: Delaunay random
+    walk on 2^U[10, 16] uniform points. Options per family as in Section 7
+    (tandem: r = 8, c = 4, 3 + 3 sweeps, 7+ levels to 17 x 17; planar: c = 3,
+    5 + 5 sweeps, coarsest < 100), FP32 cycles with FP64 Krylov."""
+    import numpy as np
+    import chaingen
+    out = []
+    for k in range(count):
+        rng = np.random.default_rng([master_seed, k])
+        if k % 2 == 0:
+            N = int(rng.integers(17, 258))
+            r = rng.uniform(0.2, 0.5, 3)
+            r = r / r.sum()
+            ch = chaingen.tandem(N, *r)
+            kw = dict(r=8, max_interp=4, coarse_max=300 if N >= 65 else 99, nu_setup=8)
+        else:
+            n = int(round(2 ** rng.uniform(10, 16)))
+            ch = chaingen.delaunay_walk(n, int(rng.integers(1 << 31)))
+            kw = dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99)
+        out.append((ch, kw))
+    return out
+
+
+def run_batch(args):
+    """Many chains per step: bamg_setup_batched + bamg_gmres_solve_batched."""
+    import numpy as np
+    import torch
+    import paper_1402_4005_amd as bamg
+    tg = time.perf_counter()
+    mem = batch_members(args.batch, 14024004)
+    gen_s = time.perf_counter() - tg
+    chains = [c for c, _ in mem]
+    opts = [bamg.options_for(c, precision=args.precision if args.precision != "fp64" else "mixed",
+                             **kw) for c, kw in mem]
+
+    def step():
+        b = bamg.Batch(chains, opts, nstreams=args.streams)
+        xs, infos, sts = b.gmres(restart=args.restart, tol=args.tol, maxit=args.maxit)
+        return b, infos, sts
+
+    for _ in range(args.warmup):
+        step()[0].close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b, infos, sts = step()
+        b.close()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    nconv = sum(1 for s in sts if s == 0)
+    states = sum(c.n for c in chains)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        tc = time.perf_counter()
+        done, done_nnz = 0, 0
+        for c, kw in mem:
+            if time.perf_counter() - tc > 15.0:
+                break
+            try:
+                ho = oracle.Hierarchy(c, oracle.options_for(c, **kw))
+                ho.gmres(m=args.restart, tol=args.tol, maxit=args.maxit)
+            except Exception:
+                pass
+            done += 1
+            done_nnz += c.nnz
+        el = time.perf_counter() - tc
+        tot_nnz = sum(c.nnz for c in chains)
+        cpu = {"value": round(el * 1e3 * tot_nnz / max(done_nnz, 1), 1), "unit": "ms",
+               "cores": 1, "kind": "oracle",
+               "sample": f"oracle setup+GMRES of the first {done} chains ({done_nnz} nnz of "
+                         f"{tot_nnz}) in {el:.1f} s, scaled by nonzeros to the whole batch"}
+    line = {
+        "metric": METRIC, "value": round(ms, 3), "unit": "ms", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"batch{args.batch}", "chains": args.batch, "states": states,
+                   "nnz_A": sum(c.nnz for c in chains), "streams": args.streams or 4,
+                   "tol": args.tol, "restart": args.restart},
+        "chains_per_s": round(args.batch / (ms * 1e-3), 1),
+        "converged": nconv,
+        "failed": {str(s): sum(1 for x in sts if x == s) for s in set(sts) if s != 0},
+        "iterations_median": float(np.median([i.iterations for i, s in zip(infos, sts) if s == 0]))
+        if nconv else None,
+        "host_generation_s": round(gen_s, 1),
+        "roofline": None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="delaunay262144", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="delaunay262144", choices=sorted(WORKLOADS) + ["batch"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--setup-cycles", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-10)
@@ -100,6 +203,11 @@ def main():
     ap.add_argument("--maxit", type=int, default=1000)
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision comparison run")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-interpolation comparison run")
+    ap.add_argument("--batch", type=int, default=512,
+                    help="chains of the batched workload (--workload batch)")
+    ap.add_argument("--streams", type=int, default=0, help="library streams of a batch")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device-to-device copies of MIB MiB (the known "
                          "byte count that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -126,6 +234,9 @@ def main():
 
     import paper_1402_4005_amd as bamg
 
+    if args.workload == "batch":
+        run_batch(args)
+        return
     kind, size, wopts = WORKLOADS[args.workload]
     ch = make_chain(kind, size, wopts["seed"])
     dev = torch.device("cuda:0")
@@ -219,6 +330,38 @@ def main():
     hs.close()
     vcycle = vcycle_rate(opts)
 
+    # the learned form: a network trained (untimed) on BAMG^2 corrections of
+    # smaller chains of the same family, then one-cycle setups with it
+    learned_line = None
+    if args.precision == "fp64" and not args.no_learned and kind in LEARN_TRAIN:
+        from paper_1402_4005_amd import learned as lmod
+        tl = time.perf_counter()
+        tchains = [make_chain(k2, s2, sd2) for k2, s2, sd2 in LEARN_TRAIN[kind]]
+        LX, LT, LM = lmod.harvest(tchains, **{k: v for k, v in wopts.items() if k != "seed"})
+        net, losses = lmod.train(LX, LT, LM, epochs=120)
+        train_s = time.perf_counter() - tl
+        lopts = options(args.precision)
+        lopts.learned = bamg.LEARNED_USE
+        lopts.mlp = net.h.value
+        lms, lh, lx, linfos = timed(lopts)
+        lxs = lx.cpu().numpy()
+        nm, nl = lh.learned_stats()
+        learned_line = {
+            "ms_per_step": round(lms, 3),
+            "speedup_vs_fp64": round(ms_per_step / lms, 3),
+            "iterations": [i.iterations for i in linfos],
+            "converged": [bool(i.converged) for i in linfos],
+            "x_rel_l1_vs_fp64": float(np.abs(lxs - xs).sum() / np.abs(xs).sum()),
+            "mlp_rows": nm, "ls_fallback_rows": nl,
+            "training": {"chains": [f"{k2}{s2}" for k2, s2, _ in LEARN_TRAIN[kind]],
+                         "samples": int(LX.shape[0]), "epochs": 240,
+                         "loss_first_last": [round(float(losses[0]), 5),
+                                             round(float(losses[-1]), 5)],
+                         "seconds": round(train_s, 1)},
+        }
+        lh.close()
+        net.close()
+
     # the mixed-precision form on the same workload: FP32 setup and V-cycles,
     # FP64 Krylov, residual, normalisation and coarsest solve
     mixed = None
@@ -295,6 +438,7 @@ def main():
         "setup_ms": round(setup_ms, 3),
         "vcycle": vcycle,
         "mixed": mixed,
+        "learned": learned_line,
         "roofline": roofline,
         "cpu_baseline": cpu,
         **extra,
