@@ -286,25 +286,38 @@ __global__ void k_mlp_select(int nF, const int *__restrict__ fpts, int r,
                              const double *__restrict__ wv, const float *__restrict__ Y,
                              T *__restrict__ Pv, int *__restrict__ counts) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= nF) return;
-  const int i = fpts[f];
-  const int a0 = prp[i], m = min(prp[i + 1] - a0, kOut);
-  double jm = 0.0, jl = 0.0;
-  for (int k = 0; k < r; ++k) {
-    double em = (double)V[(size_t)i * r + k], el = em;
+  bool take = false;
+  const bool active = f < nF;
+  if (active) {
+    const int i = fpts[f];
+    const int a0 = prp[i], m = min(prp[i + 1] - a0, kOut);
+    int J[kOut];
+    double pl[kOut], pm[kOut];
     for (int t = 0; t < m; ++t) {
-      const double vj = (double)V[(size_t)cpts[pci[a0 + t]] * r + k];
-      em -= ((double)Pv[a0 + t] + (double)Y[(size_t)f * kOut + t]) * vj;
-      el -= (double)Pv[a0 + t] * vj;
+      J[t] = cpts[pci[a0 + t]];
+      pl[t] = (double)Pv[a0 + t];
+      pm[t] = pl[t] + (double)Y[(size_t)f * kOut + t];
     }
-    jm += wv[k] * em * em;
-    jl += wv[k] * el * el;
+    double jm = 0.0, jl = 0.0;
+    for (int k = 0; k < r; ++k) {
+      double em = (double)V[(size_t)i * r + k], el = em;
+      for (int t = 0; t < m; ++t) {
+        const double vj = (double)V[(size_t)J[t] * r + k];
+        em -= pm[t] * vj;
+        el -= pl[t] * vj;
+      }
+      jm += wv[k] * em * em;
+      jl += wv[k] * el * el;
+    }
+    take = jm <= 2.0 * jl;
+    if (take)
+      for (int t = 0; t < m; ++t) Pv[a0 + t] = (T)pm[t];
   }
-  if (jm <= 2.0 * jl) {
-    for (int t = 0; t < m; ++t) Pv[a0 + t] = (T)((double)Pv[a0 + t] + (double)Y[(size_t)f * kOut + t]);
-    atomicAdd(&counts[0], 1);
-  } else {
-    atomicAdd(&counts[1], 1);
+  // one counter update per wave
+  const unsigned long long bt = __ballot(active && take), bf = __ballot(active && !take);
+  if ((threadIdx.x % kWave) == 0) {
+    if (bt) atomicAdd(&counts[0], (int)__popcll(bt));
+    if (bf) atomicAdd(&counts[1], (int)__popcll(bf));
   }
 }
 

@@ -309,18 +309,22 @@ __global__ void k_mis_select(int n, const int *__restrict__ rp, const int *__res
 __global__ void k_mis_update(int n, const int *__restrict__ rp, const int *__restrict__ ci,
                              const int *__restrict__ sel, int *__restrict__ state, int round,
                              int *__restrict__ undecided) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n || state[v] != -1) return;
-  if (sel[v] == round) {
-    state[v] = 1;
-    return;
-  }
-  for (int k = rp[v]; k < rp[v + 1]; ++k)
-    if (sel[ci[k]] == round) {
-      state[v] = 0;
-      return;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  bool und = false;
+  if (v < n && state[v] == -1) {
+    if (sel[v] == round) {
+      state[v] = 1;
+    } else {
+      bool beaten = false;
+      for (int k = rp[v]; k < rp[v + 1] && !beaten; ++k) beaten = sel[ci[k]] == round;
+      if (beaten)
+        state[v] = 0;
+      else
+        und = true;
     }
-  atomicAdd(undecided, 1);
+  }
+  const unsigned long long b = __ballot(und);  // one counter update per wave
+  if ((threadIdx.x % kWave) == 0 && b) atomicAdd(undecided, (int)__popcll(b));
 }
 
 void mis_cf(Pool &pool, const Csr &G, uint64_t seed, int level, int *cf, hipStream_t s) {
