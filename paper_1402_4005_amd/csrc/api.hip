@@ -581,6 +581,8 @@ void bamg_destroy(bamg_handle *h) {
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   h->pool.release_all();
   if (h->hred) (void)hipHostFree(h->hred);
+  for (hipEvent_t e : h->gm_ev)
+    if (e) (void)hipEventDestroy(e);
   delete h;
 }
 

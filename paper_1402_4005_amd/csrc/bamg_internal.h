@@ -107,7 +107,8 @@ struct bamg_handle {
   double *x0 = nullptr;     // device, n (FP64)
   double *red = nullptr;    // device reduction scratch
   size_t red_cap = 0;
-  double *hred = nullptr;   // pinned host mirror
+  double *hred = nullptr;   // pinned host mirror: 2 x 16 flag slots
+  hipEvent_t gm_ev[2] = {nullptr, nullptr};  // flag copies of alternate iterations
   // GMRES storage, allocated on first use
   int gm_m = 0;
   double *gV = nullptr, *gBV = nullptr, *gw = nullptr, *gx0 = nullptr, *gbx0 = nullptr;

@@ -487,22 +487,23 @@ void interp_pattern(Pool &pool, const Level &L, int cap, int geometric, Csr &P, 
 }
 
 // ============================================================ SpGEMM symbolic
-// One wave (block of 64) per row of C = A * B: every product term appends
-// its column to an LDS buffer, the buffer is bitonic-sorted and the distinct
-// columns counted (pass 1) or written (pass 2). The result is the sorted
-// structural product, independent of thread timing.
+// Rows of C = A * B with many product terms: one wave (block of 64) per
+// listed row, every term appends its column to an LDS buffer, the buffer is
+// bitonic-sorted and the distinct columns counted (pass 1) or written
+// (pass 2). The result is the sorted structural product, independent of
+// thread timing.
 constexpr int kSymCap = 4096;
 
 template <bool FILL>
 __global__ void __launch_bounds__(64)
-    k_spgemm_sym(int nr, const int *__restrict__ arp, const int *__restrict__ aci,
-                 const int *__restrict__ brp, const int *__restrict__ bci, int force_diag,
-                 int *__restrict__ cnt, const int *__restrict__ crp, int *__restrict__ cci,
-                 int *__restrict__ overflow) {
+    k_spgemm_sym_list(const int *__restrict__ rows, const int *__restrict__ arp,
+                      const int *__restrict__ aci, const int *__restrict__ brp,
+                      const int *__restrict__ bci, int force_diag, int *__restrict__ cnt,
+                      const int *__restrict__ crp, int *__restrict__ cci,
+                      int *__restrict__ overflow) {
   __shared__ int buf[kSymCap];
   __shared__ int nbuf;
-  const int row = blockIdx.x, lane = threadIdx.x;
-  if (row >= nr) return;
+  const int row = rows[blockIdx.x], lane = threadIdx.x;
   if (lane == 0) nbuf = 0;
   __syncthreads();
   if (force_diag && lane == 0) {
@@ -558,15 +559,81 @@ __global__ void __launch_bounds__(64)
   if (!FILL && lane == 0) cnt[row] = base;
 }
 
+// Short rows (at most kSymShort candidate terms, the common case of the
+// Galerkin products): one thread per row sorts its candidates in a private
+// LDS slice (position-major) and counts or writes the distinct columns.
+// Longer rows are listed for the wave-per-row kernel above (rowlist).
+constexpr int kSymShort = 32, kSymThreads = 128;
+
+template <bool FILL>
+__global__ void __launch_bounds__(kSymThreads)
+    k_spgemm_sym_short(int nr, const int *__restrict__ arp, const int *__restrict__ aci,
+                       const int *__restrict__ brp, const int *__restrict__ bci, int force_diag,
+                       int *__restrict__ cnt, const int *__restrict__ crp, int *__restrict__ cci,
+                       int *__restrict__ longrows, int *__restrict__ nlong) {
+  __shared__ int buf[kSymShort * kSymThreads];
+  const int t = threadIdx.x;
+  const int row = blockIdx.x * kSymThreads + t;
+  bool is_long = false;
+  if (row < nr) {
+    int total = force_diag ? 1 : 0;
+    for (int a = arp[row]; a < arp[row + 1]; ++a) total += brp[aci[a] + 1] - brp[aci[a]];
+    if (total > kSymShort) {
+      is_long = true;
+    } else {
+      int m = 0;
+      if (force_diag) buf[(m++) * kSymThreads + t] = row;
+      for (int a = arp[row]; a < arp[row + 1]; ++a) {
+        const int k = aci[a];
+        for (int b = brp[k]; b < brp[k + 1]; ++b) {
+          // insertion into the sorted slice
+          const int v = bci[b];
+          int q = m++;
+          while (q > 0 && buf[(q - 1) * kSymThreads + t] > v) {
+            buf[q * kSymThreads + t] = buf[(q - 1) * kSymThreads + t];
+            --q;
+          }
+          buf[q * kSymThreads + t] = v;
+        }
+      }
+      int d = 0;
+      const int out0 = FILL ? crp[row] : 0;
+      for (int q = 0; q < m; ++q) {
+        const int v = buf[q * kSymThreads + t];
+        if (q == 0 || v != buf[(q - 1) * kSymThreads + t]) {
+          if (FILL) cci[out0 + d] = v;
+          ++d;
+        }
+      }
+      if (!FILL) cnt[row] = d;
+    }
+  }
+  const unsigned long long bl = __ballot(is_long);
+  if (bl) {
+    int base = 0;
+    if ((t % kWave) == 0) base = atomicAdd(nlong, (int)__popcll(bl));
+    base = __shfl(base, 0, kWave);
+    const int lane = t % kWave;
+    if (is_long) longrows[base + __popcll(bl & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))))] = row;
+  }
+}
+
 void spgemm_symbolic(Pool &pool, const Csr &A, const Csr &B, int force_diag, Csr &C,
                      hipStream_t s) {
   const int nr = A.nr;
   int *cnt = pool.get<int>(nr);
-  int *ovf = pool.get<int>(1);
-  fill_i32(ovf, 0, 1, s);
+  int *ovf = pool.get<int>(2);  // [overflow, long rows]
+  int *longrows = pool.get<int>(nr);
+  fill_i32(ovf, 0, 2, s);
   if (nr) {
-    k_spgemm_sym<false><<<nr, 64, 0, s>>>(nr, A.rp, A.ci, B.rp, B.ci, force_diag, cnt, nullptr,
-                                          nullptr, ovf);
+    k_spgemm_sym_short<false><<<ceil_div(nr, kSymThreads), kSymThreads, 0, s>>>(
+        nr, A.rp, A.ci, B.rp, B.ci, force_diag, cnt, nullptr, nullptr, longrows, ovf + 1);
+    LAUNCHCHK();
+  }
+  const int nlong = read_int(ovf + 1, s);
+  if (nlong > 0) {
+    k_spgemm_sym_list<false><<<nlong, 64, 0, s>>>(longrows, A.rp, A.ci, B.rp, B.ci, force_diag,
+                                                  cnt, nullptr, nullptr, ovf);
     LAUNCHCHK();
   }
   if (read_int(ovf, s)) fail(BAMG_E_ARG, "Galerkin row wider than the symbolic buffer");
@@ -577,47 +644,27 @@ void spgemm_symbolic(Pool &pool, const Csr &A, const Csr &B, int force_diag, Csr
   C.nnz = read_int(C.rp + nr, s);
   C.ci = pool.get<int>(C.nnz);
   if (nr) {
-    k_spgemm_sym<true><<<nr, 64, 0, s>>>(nr, A.rp, A.ci, B.rp, B.ci, force_diag, nullptr, C.rp,
-                                         C.ci, ovf);
+    fill_i32(ovf + 1, 0, 1, s);
+    k_spgemm_sym_short<true><<<ceil_div(nr, kSymThreads), kSymThreads, 0, s>>>(
+        nr, A.rp, A.ci, B.rp, B.ci, force_diag, nullptr, C.rp, C.ci, longrows, ovf + 1);
+    LAUNCHCHK();
+  }
+  if (nlong > 0) {
+    k_spgemm_sym_list<true><<<nlong, 64, 0, s>>>(longrows, A.rp, A.ci, B.rp, B.ci, force_diag,
+                                                 nullptr, C.rp, C.ci, ovf);
     LAUNCHCHK();
   }
   pool.release(cnt);
   pool.release(ovf);
+  pool.release(longrows);
 }
 
 // ============================================================ SpGEMM numeric
 // One thread per row of C: terms are added in the order (A column, B column)
 // ascending, each at the position of its column in the sorted row of C.
-template <class T>
-__global__ void k_spgemm_num(int nr, const int *__restrict__ arp, const int *__restrict__ aci,
-                             const T *__restrict__ av, const int *__restrict__ brp,
-                             const int *__restrict__ bci, const T *__restrict__ bv,
-                             const int *__restrict__ crp, const int *__restrict__ cci,
-                             T *__restrict__ cv) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nr) return;
-  const int c0 = crp[i], c1 = crp[i + 1];
-  for (int p = c0; p < c1; ++p) cv[p] = (T)0;
-  for (int a = arp[i]; a < arp[i + 1]; ++a) {
-    const int k = aci[a];
-    const T x = av[a];
-    for (int b = brp[k]; b < brp[k + 1]; ++b) {
-      const int j = bci[b];
-      int lo = c0, hi = c1 - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (cci[mid] < j)
-          lo = mid + 1;
-        else
-          hi = mid;
-      }
-      cv[lo] += x * bv[b];
-    }
-  }
-}
-
 // Same products and term order; rows of C with at most kNumAcc entries
-// accumulate in the thread's private LDS slice (laid out position-major so
+// accumulate in the thread's private LDS slice, next to the row's column
+// indices that the binary search reads (both laid out position-major so
 // the threads of a wave hit distinct banks) and are written once.
 constexpr int kNumThreads = 128, kNumAcc = 32;
 
@@ -629,6 +676,7 @@ __global__ void __launch_bounds__(kNumThreads)
                      const int *__restrict__ crp, const int *__restrict__ cci,
                      T *__restrict__ cv) {
   __shared__ T acc[kNumAcc * kNumThreads];
+  __shared__ int cols[kNumAcc * kNumThreads];  // the output row's columns
   const int t = threadIdx.x;
   const int i = blockIdx.x * kNumThreads + t;
   if (i >= nr) return;
@@ -653,21 +701,25 @@ __global__ void __launch_bounds__(kNumThreads)
     }
     return;
   }
-  for (int q = 0; q < c1 - c0; ++q) acc[q * kNumThreads + t] = (T)0;
+  const int m = c1 - c0;
+  for (int q = 0; q < m; ++q) {
+    acc[q * kNumThreads + t] = (T)0;
+    cols[q * kNumThreads + t] = cci[c0 + q];
+  }
   for (int a = arp[i]; a < arp[i + 1]; ++a) {
     const int k = aci[a];
     const T x = av[a];
     for (int b = brp[k]; b < brp[k + 1]; ++b) {
       const int j = bci[b];
-      int lo = c0, hi = c1 - 1;
+      int lo = 0, hi = m - 1;
       while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (cci[mid] < j)
+        if (cols[mid * kNumThreads + t] < j)
           lo = mid + 1;
         else
           hi = mid;
       }
-      acc[(lo - c0) * kNumThreads + t] += x * bv[b];
+      acc[lo * kNumThreads + t] += x * bv[b];
     }
   }
   for (int q = 0; q < c1 - c0; ++q) cv[c0 + q] = acc[q * kNumThreads + t];

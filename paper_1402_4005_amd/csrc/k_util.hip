@@ -1,5 +1,7 @@
 // Integer utilities (prefix sums, CSR transposition), value permutations and
 // the counter-based generator of the random test vectors.
+#include <climits>
+
 #include "bamg_internal.h"
 #include "device_common.h"
 
@@ -180,55 +182,134 @@ __global__ void k_scatter_rows(const int *__restrict__ rp, const int *__restrict
   }
 }
 
-__global__ void k_sort_segments(const int *__restrict__ rp, int nr, int *__restrict__ key,
-                                int *__restrict__ val) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nr) return;
-  int a = rp[j], b = rp[j + 1];
-  constexpr int kReg = 32;
-  if (b - a <= kReg) {
-    // short segment: sort in registers, one read and one write per entry
-    int kk[kReg], vv[kReg];
-    const int m = b - a;
+// Bitonic sorting network over N registers (static indices only, so the
+// arrays stay in registers); entries past the segment hold INT_MAX.
+template <int N>
+__device__ __forceinline__ void bitonic_regs(int (&k)[N], int (&v)[N]) {
 #pragma unroll
-    for (int p = 0; p < kReg; ++p)
-      if (p < m) {
-        kk[p] = key[a + p];
-        vv[p] = val[a + p];
-      }
+  for (int size = 2; size <= N; size <<= 1)
 #pragma unroll
-    for (int p = 1; p < kReg; ++p) {
-      if (p >= m) break;
-      // insertion of element p, expressed with compile-time indices
+    for (int stride = size >> 1; stride > 0; stride >>= 1)
 #pragma unroll
-      for (int q = p; q > 0; --q) {
-        if (kk[q - 1] > kk[q]) {
-          const int t0 = kk[q - 1], t1 = vv[q - 1];
-          kk[q - 1] = kk[q];
-          vv[q - 1] = vv[q];
-          kk[q] = t0;
-          vv[q] = t1;
+      for (int i = 0; i < N; ++i) {
+        const int l = i ^ stride;
+        if (l > i) {
+          const bool up = (i & size) == 0;
+          if ((k[i] > k[l]) == up) {
+            const int t0 = k[i], t1 = v[i];
+            k[i] = k[l];
+            v[i] = v[l];
+            k[l] = t0;
+            v[l] = t1;
+          }
         }
       }
-    }
+}
+
+template <int N>
+__device__ __forceinline__ void sort_short(int *__restrict__ key, int *__restrict__ val, int a,
+                                           int m) {
+  int kk[N], vv[N];
 #pragma unroll
-    for (int p = 0; p < kReg; ++p)
-      if (p < m) {
-        key[a + p] = kk[p];
-        val[a + p] = vv[p];
-      }
-    return;
+  for (int p = 0; p < N; ++p) {
+    kk[p] = p < m ? key[a + p] : INT_MAX;
+    vv[p] = p < m ? val[a + p] : 0;
   }
-  for (int p = a + 1; p < b; ++p) {
-    int kk = key[p], vv = val[p];
-    int q = p - 1;
-    while (q >= a && key[q] > kk) {
-      key[q + 1] = key[q];
-      val[q + 1] = val[q];
-      --q;
+  bitonic_regs<N>(kk, vv);
+#pragma unroll
+  for (int p = 0; p < N; ++p)
+    if (p < m) {
+      key[a + p] = kk[p];
+      val[a + p] = vv[p];
     }
-    key[q + 1] = kk;
-    val[q + 1] = vv;
+}
+
+// Sort each CSR segment by key (keys within a segment are distinct), with
+// the values permuted alongside. Segments of up to 32 entries are sorted by
+// their own thread in registers; longer ones are appended to a list for
+// k_sort_long (one counter update per wave).
+__global__ void k_sort_segments(const int *__restrict__ rp, int nr, int *__restrict__ key,
+                                int *__restrict__ val, int *__restrict__ longseg,
+                                int *__restrict__ nlong) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  bool is_long = false;
+  if (j < nr) {
+    const int a = rp[j], m = rp[j + 1] - a;
+    if (m > 32)
+      is_long = true;
+    else if (m > 16)
+      sort_short<32>(key, val, a, m);
+    else if (m > 8)
+      sort_short<16>(key, val, a, m);
+    else if (m > 1)
+      sort_short<8>(key, val, a, m);
+  }
+  const unsigned long long bl = __ballot(is_long);
+  if (bl) {
+    const int lane = threadIdx.x % kWave;
+    int base = 0;
+    if (lane == 0) base = atomicAdd(nlong, (int)__popcll(bl));
+    base = __shfl(base, 0, kWave);
+    if (is_long) longseg[base + __popcll(bl & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))))] = j;
+  }
+}
+
+// Long segments: one 64-thread workgroup per listed segment (grid-stride over
+// the device-side count), bitonic sort in LDS of up to kLongCap entries;
+// beyond that, an insertion sort by one thread.
+constexpr int kLongCap = 2048;
+
+__global__ void __launch_bounds__(64)
+    k_sort_long(const int *__restrict__ rp, const int *__restrict__ longseg,
+                const int *__restrict__ nlong, int *__restrict__ key, int *__restrict__ val) {
+  __shared__ int ks[kLongCap], vs[kLongCap];
+  const int nl = *nlong, t = threadIdx.x;
+  for (int w = blockIdx.x; w < nl; w += gridDim.x) {
+    const int j = longseg[w];
+    const int a = rp[j], m = rp[j + 1] - a;
+    if (m > kLongCap) {
+      if (t == 0)
+        for (int p = a + 1; p < a + m; ++p) {
+          const int kk = key[p], vv = val[p];
+          int q = p - 1;
+          while (q >= a && key[q] > kk) {
+            key[q + 1] = key[q];
+            val[q + 1] = val[q];
+            --q;
+          }
+          key[q + 1] = kk;
+          val[q + 1] = vv;
+        }
+      __syncthreads();
+      continue;
+    }
+    int P2 = 1;
+    while (P2 < m) P2 <<= 1;
+    for (int p = t; p < P2; p += 64) {
+      ks[p] = p < m ? key[a + p] : INT_MAX;
+      vs[p] = p < m ? val[a + p] : 0;
+    }
+    __syncthreads();
+    for (int size = 2; size <= P2; size <<= 1)
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int i = t; i < (P2 >> 1); i += 64) {
+          const int lo = 2 * i - (i & (stride - 1)), hi = lo + stride;
+          const bool up = (lo & size) == 0;
+          if ((ks[lo] > ks[hi]) == up) {
+            const int k0 = ks[lo], v0 = vs[lo];
+            ks[lo] = ks[hi];
+            vs[lo] = vs[hi];
+            ks[hi] = k0;
+            vs[hi] = v0;
+          }
+        }
+        __syncthreads();
+      }
+    for (int p = t; p < m; p += 64) {
+      key[a + p] = ks[p];
+      val[a + p] = vs[p];
+    }
+    __syncthreads();
   }
 }
 
@@ -252,8 +333,14 @@ void transpose_pattern(Pool &pool, const Csr &A, Csr &At, int *&perm, hipStream_
     LAUNCHCHK();
   }
   if (At.nr) {
-    k_sort_segments<<<ceil_div(At.nr, 256), 256, 0, s>>>(At.rp, At.nr, At.ci, perm);
+    int *longseg = pool.get<int>(At.nr + 1);  // [count, segments...]
+    fill_i32(longseg, 0, 1, s);
+    k_sort_segments<<<ceil_div(At.nr, 256), 256, 0, s>>>(At.rp, At.nr, At.ci, perm, longseg + 1,
+                                                         longseg);
     LAUNCHCHK();
+    k_sort_long<<<std::min(1024, At.nr), 64, 0, s>>>(At.rp, longseg + 1, longseg, At.ci, perm);
+    LAUNCHCHK();
+    pool.release(longseg);
   }
   pool.release(cnt);
 }

@@ -204,7 +204,9 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
       h->vb = pool.get<float>(n);
       h->vx = pool.get<float>(n);
     }
-    if (!h->hred) HIPCHK(hipHostMalloc((void **)&h->hred, sizeof(double) * 16, 0));
+    if (!h->hred) HIPCHK(hipHostMalloc((void **)&h->hred, sizeof(double) * 32, 0));
+    for (hipEvent_t &e : h->gm_ev)
+      if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     if (!h->vcin) h->vcin = pool.get<double>(n);
     if (h->vc_exec) {
       (void)hipGraphExecDestroy(h->vc_exec);  // it wrote into the old gw
@@ -218,8 +220,9 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
   double *part = h->gsc;                          // (m+2) * nblk: multi-dot partials
   double *part2 = part + (size_t)(m + 2) * nblk;  // nblk: |w|^2 partials
   double *part3 = part2 + nblk;                   // 2 nblk: residual-check partials
-  double *coef = pool.get<double>(2 * (size_t)(m + 2));
+  double *coef = pool.get<double>(4 * (size_t)(m + 2));
   double *c1 = coef, *c2 = coef + (m + 2);  // the two Gram-Schmidt passes
+  double *yring = coef + 2 * (m + 2);       // y of the last two iterations
 
   if (use_x0)
     HIPCHK(hipMemcpyAsync(h->gx0, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
@@ -253,7 +256,12 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
     scale_vec(h->gw, flags + 3, h->gV, n, s);  // v_0 = z / beta
     int used = 0;
     bool broke = false;
-    for (int j = 0; j < m && it < maxit; ++j) {
+    // Iteration j is enqueued, then its status flags are copied to a pinned
+    // slot and its y saved; the host reads them only after iteration j + 1
+    // is enqueued, so the device never waits for the host between
+    // iterations. Stopping at j discards the work of j + 1 (it writes only
+    // basis vector j + 2, the Hessenberg column j + 1 and the other y slot).
+    auto enqueue = [&](int j) {
       double *vj = h->gV + (size_t)j * n, *bvj = h->gBV + (size_t)j * n;
       k_spmv_dual<<<ceil_div((long)n * 8, 256), 256, 0, s>>>(n, B.rp, B.ci, h->B64, vj, bvj,
                                                              h->vcin);  // B v_j
@@ -270,24 +278,42 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
       scale_vec(h->gw, flags + 3, h->gV + (size_t)(j + 1) * n, n, s);
       residual_check_partials(h->gx0, h->gbx0, h->gV, h->gBV, y, n, j + 1, part3, nblk, s);
       residual_check_finalize(part3, nblk, tol, flags, s);
-      read_flags();
+      double *ys = yring + (size_t)(j & 1) * (m + 2);
+      HIPCHK(hipMemcpyAsync(ys, y, sizeof(double) * (j + 1), hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(hf + 16 * (j & 1), flags, sizeof(double) * 16,
+                            hipMemcpyDeviceToHost, s));
+      HIPCHK(hipEventRecord(h->gm_ev[j & 1], s));
+    };
+    auto finished = [&](int j) {  // true: stop after iteration j
+      HIPCHK(hipEventSynchronize(h->gm_ev[j & 1]));
+      const double *f = hf + 16 * (j & 1);
       ++it;
       used = j + 1;
-      rel = hf[2];
+      rel = f[2];
       if (!std::isfinite(rel)) {
         st = BAMG_E_NONFINITE;
-        break;
+        return true;
       }
-      if (hf[0] != 0.0) {
+      if (f[0] != 0.0) {
         conv = 1;
-        break;
+        return true;
       }
-      if (hf[1] != 0.0) {
+      if (f[1] != 0.0) {
         broke = true;
-        break;
+        return true;
+      }
+      return false;
+    };
+    if (it < maxit) {
+      enqueue(0);
+      for (int j = 0;; ++j) {
+        const bool more = j + 1 < m && it + 1 < maxit;
+        if (more) enqueue(j + 1);
+        if (finished(j) || !more) break;
       }
     }
-    if (used > 0) update_iterate(h->gx0, h->gV, y, n, used, s);
+    if (used > 0)
+      update_iterate(h->gx0, h->gV, yring + (size_t)((used - 1) & 1) * (m + 2), n, used, s);
     if (st != BAMG_OK) break;
     if (broke && !conv && ++breakdowns >= 2) {
       st = BAMG_E_BREAKDOWN;
