@@ -205,6 +205,8 @@ def main():
                     help="skip the mixed-precision comparison run")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-interpolation comparison run")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1 = time the lanes per CSR row of every level's sweeps at setup")
     ap.add_argument("--batch", type=int, default=512,
                     help="chains of the batched workload (--workload batch)")
     ap.add_argument("--streams", type=int, default=0, help="library streams of a batch")
@@ -247,7 +249,7 @@ def main():
 
     def options(precision):
         return bamg.options_for(ch, precision=precision, setup_cycles=args.setup_cycles,
-                                **wopts)
+                                autotune=args.autotune, **wopts)
 
     def step(opts, profile=False):
         h = bamg.Hierarchy(rp, ci, va, ch.geom, opts, stream=stream)

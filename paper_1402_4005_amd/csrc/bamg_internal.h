@@ -158,6 +158,9 @@ void spmv(const Csr &A, const T *val, const T *x, T *y, const T *b, int mode, in
 template <class T>
 void jacobi(const Csr &A, const T *val, const T *dinv, T omega, const T *b, const T *xin, T *xout,
             int lanes, hipStream_t s);
+template <class T>
+void jacobi2_from_zero(const Csr &A, const T *val, const T *dinv, T omega, const T *b, T *xout,
+                       int lanes, hipStream_t s);  // two sweeps from x = 0
 // Kaczmarz sweep over one colour segment (in place)
 template <class T>
 void kaczmarz_colour(const Csr &A, const T *val, const T *rowinv, const int *rows, int nrows,
@@ -226,7 +229,9 @@ int cholesky(double *A, int n, hipStream_t s);            // in place, lower, ro
 void trsm_lower_cols(const double *L, double *X, int n, int ncols, int ldx,
                      hipStream_t s);  // X <- L^-1 X, column by column
 void transpose_dense(const double *A, double *At, int n, hipStream_t s);
-int jacobi_svd(Pool &pool, double *W, double *J, int n, hipStream_t s);  // W, J col-major
+int jacobi_svd(Pool &pool, double *W, double *J, int n, hipStream_t s);
+int jacobi_svd2(Pool &pool, double *W, double *J, double *W2, double *J2, int n,
+                hipStream_t s);  // both SVDs in one cooperative launch (W2 nullable)  // W, J col-major
 void column_norms(const double *W, int n, double *sv, hipStream_t s);
 void coarse_triplets_out(const double *LM, const double *LN, const double *W, const double *J,
                          const double *sv, int n, int r, void *U, void *V, int prec,

@@ -167,7 +167,8 @@ __device__ __forceinline__ int rr_index(int j, int round, int m) {
 // of sweep s; ctrl[kSvdMaxSweeps] receives the number of sweeps run.
 // blockDim.x = 64 * bs; dynamic LDS = (2 bs n + 4 bs^2) doubles.
 __global__ void __launch_bounds__(1024)
-    k_block_jacobi_svd(double *__restrict__ W, double *__restrict__ J, int n, int bs, int nbp,
+    k_block_jacobi_svd(double *__restrict__ W, double *__restrict__ J, double *__restrict__ W2,
+                       double *__restrict__ J2, int nmat, int n, int bs, int nbp,
                        int *__restrict__ ctrl) {
   cg::grid_group grid = cg::this_grid();
   extern __shared__ double lds[];
@@ -181,13 +182,17 @@ __global__ void __launch_bounds__(1024)
   int sweep = 0;
   for (; sweep < kSvdMaxSweeps; ++sweep) {
     for (int round = 0; round < nbp - 1; ++round) {
-      for (int pr = blockIdx.x; pr < nbp / 2; pr += gridDim.x) {
+      for (int pm = blockIdx.x; pm < nmat * (nbp / 2); pm += gridDim.x) {
+        // pair pr of matrix pm / (nbp / 2): (W, J) or (W2, J2)
+        const int pr = pm % (nbp / 2);
+        double *__restrict__ Wm = pm < nbp / 2 ? W : W2;
+        double *__restrict__ Jm = pm < nbp / 2 ? J : J2;
         const int ba = rr_index(pr, round, nbp), bb = rr_index(nbp - 1 - pr, round, nbp);
         // local column c -> global column
         auto gcol = [&](int c) { return c < bs ? ba * bs + c : bb * bs + (c - bs); };
         for (int e = threadIdx.x; e < cols * n; e += nt) {
           const int c = e / n, i = e % n, g = gcol(c);
-          Ws[e] = g < n ? W[(size_t)g * n + i] : 0.0;
+          Ws[e] = g < n ? Wm[(size_t)g * n + i] : 0.0;
         }
         for (int e = threadIdx.x; e < cols * cols; e += nt) R[e] = (e / cols) == (e % cols);
         if (threadIdx.x == 0) nrot = 0;
@@ -231,14 +236,14 @@ __global__ void __launch_bounds__(1024)
         }
         for (int e = threadIdx.x; e < cols * n; e += nt) {
           const int c = e / n, i = e % n, g = gcol(c);
-          if (g < n) W[(size_t)g * n + i] = Ws[e];
+          if (g < n) Wm[(size_t)g * n + i] = Ws[e];
         }
         __syncthreads();
         if (nrot > 0) {
           // J[:, pair] = J[:, pair] R, staged through the (now free) W slice
           for (int e = threadIdx.x; e < cols * n; e += nt) {
             const int c = e / n, i = e % n, g = gcol(c);
-            Ws[e] = g < n ? J[(size_t)g * n + i] : 0.0;
+            Ws[e] = g < n ? Jm[(size_t)g * n + i] : 0.0;
           }
           __syncthreads();
           for (int e = threadIdx.x; e < cols * n; e += nt) {
@@ -246,7 +251,7 @@ __global__ void __launch_bounds__(1024)
             if (g >= n) continue;
             double acc = 0.0;
             for (int d = 0; d < cols; ++d) acc += Ws[(size_t)d * n + i] * R[(size_t)c * cols + d];
-            J[(size_t)g * n + i] = acc;
+            Jm[(size_t)g * n + i] = acc;
           }
           if (threadIdx.x == 0) atomicAdd(&ctrl[sweep], nrot);
         }
@@ -272,6 +277,12 @@ static size_t block_jacobi_lds(int n, int bs) {
 }
 
 int jacobi_svd(Pool &pool, double *W, double *J, int n, hipStream_t s) {
+  return jacobi_svd2(pool, W, J, nullptr, nullptr, n, s);
+}
+
+// One cooperative launch for the SVDs of W (and of W2 when given): the two
+// matrices share the grid barriers and stop when neither rotates.
+int jacobi_svd2(Pool &pool, double *W, double *J, double *W2, double *J2, int n, hipStream_t s) {
   int dev = 0, maxlds = 0, ncu = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -287,18 +298,24 @@ int jacobi_svd(Pool &pool, double *W, double *J, int n, hipStream_t s) {
   if (nbp < 2) nbp = 2;
   int *ctrl = pool.get<int>(kSvdMaxSweeps + 1);
   fill_i32(ctrl, 0, kSvdMaxSweeps + 1, s);
+  const int nmat = W2 ? 2 : 1;
   k_identity_dense<<<ceil_div((long)n * n, 256), 256, 0, s>>>(J, n);  // J = I
   LAUNCHCHK();
+  if (W2) {
+    k_identity_dense<<<ceil_div((long)n * n, 256), 256, 0, s>>>(J2, n);
+    LAUNCHCHK();
+  }
   HIPCHK(hipFuncSetAttribute((const void *)k_block_jacobi_svd,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
   int per = 0;
   HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_block_jacobi_svd,
                                                       threads, shm));
-  int grid = nbp / 2;
+  int grid = nmat * (nbp / 2);
   const int cap = ncu * (per > 0 ? per : 1);
   if (grid > cap) grid = cap;
   if (grid < 1) grid = 1;
-  void *args[] = {(void *)&W, (void *)&J, (void *)&n, (void *)&bs, (void *)&nbp, (void *)&ctrl};
+  void *args[] = {(void *)&W,  (void *)&J,  (void *)&W2,  (void *)&J2,  (void *)&nmat,
+                  (void *)&n,  (void *)&bs, (void *)&nbp, (void *)&ctrl};
   HIPCHK(hipLaunchCooperativeKernel((const void *)k_block_jacobi_svd, dim3(grid), dim3(threads),
                                     args, shm, s));
   int sweeps = 0;
@@ -476,7 +493,7 @@ __device__ void chol_block(double *A, int n, int *flag) {
   for (int j = 0; j < n; ++j) {
     if (t == 0) {
       const double d = A[j * n + j];
-      if (!(d > 0.0)) *flag |= 1;
+      if (!(d > 0.0)) atomicOr(flag, 1);
       piv = d > 0.0 ? sqrt(d) : 1.0;
       A[j * n + j] = piv;
     }
@@ -512,6 +529,9 @@ __global__ void __launch_bounds__(kSmallThreads)
   __shared__ int rotated;
   __shared__ int kmin;
   const int t = threadIdx.x, w = t / kWave, lane = t % kWave, nw = kSmallThreads / kWave;
+  // mode 2: both at once, workgroup 0 the triplets and workgroup 1 the
+  // pseudo-inverse (they share only the read-only B)
+  if (mode == 2) mode = (int)blockIdx.x;
   if (mode == 0) {
     chol_block(Md, n, flag);
     chol_block(Nd, n, flag);
@@ -590,7 +610,7 @@ __global__ void __launch_bounds__(kSmallThreads)
     const int any = rotated;
     __syncthreads();
     if (!any) break;
-    if (sweep == 79 && t == 0) *flag |= 2;
+    if (sweep == 79 && t == 0) atomicOr(flag, 2);
   }
   // singular values
   for (int k = w; k < n; k += nw) {
@@ -611,7 +631,7 @@ __global__ void __launch_bounds__(kSmallThreads)
       double s2 = 1e300;
       for (int k = 0; k < n; ++k)
         if (k != km) s2 = fmin(s2, sv[k]);
-      if (!(sv[km] <= 1e-10 * smax) || !(s2 > 1e-13 * smax)) *flag |= 4;
+      if (!(sv[km] <= 1e-10 * smax) || !(s2 > 1e-13 * smax)) atomicOr(flag, 4);
       kmin = km;
     }
     __syncthreads();
@@ -694,13 +714,13 @@ int coarse_small(int mode, int n, int r, const double *Bd, double *Md, double *N
   if (prec == 0) {
     HIPCHK(hipFuncSetAttribute((const void *)k_coarse_small<double>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-    k_coarse_small<double><<<1, kSmallThreads, shm, s>>>(mode, n, r, Bd, Md, Nd, (double *)U,
-                                                         (double *)V, sigma, bdag, flag);
+    k_coarse_small<double><<<mode == 2 ? 2 : 1, kSmallThreads, shm, s>>>(
+        mode, n, r, Bd, Md, Nd, (double *)U, (double *)V, sigma, bdag, flag);
   } else {
     HIPCHK(hipFuncSetAttribute((const void *)k_coarse_small<float>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-    k_coarse_small<float><<<1, kSmallThreads, shm, s>>>(mode, n, r, Bd, Md, Nd, (float *)U,
-                                                        (float *)V, sigma, bdag, flag);
+    k_coarse_small<float><<<mode == 2 ? 2 : 1, kSmallThreads, shm, s>>>(
+        mode, n, r, Bd, Md, Nd, (float *)U, (float *)V, sigma, bdag, flag);
   }
   LAUNCHCHK();
   const int f = read_int(flag, s);

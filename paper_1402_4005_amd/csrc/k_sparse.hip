@@ -54,6 +54,31 @@ __global__ void __launch_bounds__(kSpThreads)
   if (lane == 0) xout[row] = xin[row] + omega * dinv[row] * (b[row] - sum);
 }
 
+// Two sweeps from x = 0 in one pass: x1 = omega dinv b is formed on the fly
+// wherever it is needed (same expression as the zero-start sweep, so the
+// result equals two separate sweeps bit for bit), then
+// x2 = x1 + omega dinv (b - A x1).
+template <class T, int LPR>
+__global__ void __launch_bounds__(kSpThreads)
+    k_jacobi2(int nr, const int *__restrict__ rp, const int *__restrict__ ci,
+              const T *__restrict__ val, const T *__restrict__ dinv, T omega,
+              const T *__restrict__ b, T *__restrict__ xout) {
+  const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * kSpThreads + threadIdx.x;
+  const int row = (int)(gid / LPR), lane = (int)(gid % LPR);
+  if (row >= nr) return;
+  T sum = 0;
+  const int e = rp[row + 1];
+  for (int k = rp[row] + lane; k < e; k += LPR) {
+    const int c = ci[k];
+    sum += val[k] * (omega * dinv[c] * b[c]);
+  }
+  sum = group_sum(sum, LPR);
+  if (lane == 0) {
+    const T x1 = omega * dinv[row] * b[row];
+    xout[row] = x1 + omega * dinv[row] * (b[row] - sum);
+  }
+}
+
 static int pick_lanes(int nr, int nnz) {
   int avg = nr ? (nnz + nr - 1) / nr : 1;
   int l = 1;
@@ -93,6 +118,14 @@ void jacobi(const Csr &A, const T *val, const T *dinv, T omega, const T *b, cons
   if (lanes <= 0) lanes = pick_lanes(A.nr, A.nnz);
   if (xin == nullptr) lanes = 1;
   BAMG_LPR_SWITCH(lanes, k_jacobi, A.nr, A.nr, A.rp, A.ci, val, dinv, omega, b, xin, xout);
+}
+
+template <class T>
+void jacobi2_from_zero(const Csr &A, const T *val, const T *dinv, T omega, const T *b, T *xout,
+                       int lanes, hipStream_t s) {
+  if (A.nr <= 0) return;
+  if (lanes <= 0) lanes = pick_lanes(A.nr, A.nnz);
+  BAMG_LPR_SWITCH(lanes, k_jacobi2, A.nr, A.nr, A.rp, A.ci, val, dinv, omega, b, xout);
 }
 
 // Kaczmarz row projections x <- x + (b_i - A_i x) / ||A_i||^2 A_i^T for the
@@ -162,6 +195,8 @@ void dot_partials(const double *x, const double *y, int n, double *part, int nbl
                         hipStream_t);                                                        \
   template void jacobi<T>(const Csr &, const T *, const T *, T, const T *, const T *, T *,   \
                           int, hipStream_t);                                                 \
+  template void jacobi2_from_zero<T>(const Csr &, const T *, const T *, T, const T *, T *,   \
+                                     int, hipStream_t);                                      \
   template void kaczmarz_colour<T>(const Csr &, const T *, const T *, const int *, int,      \
                                    const T *, T *, hipStream_t);                             \
   template void coarse_gemv<T>(const double *, int, const T *, T *, hipStream_t);

@@ -26,6 +26,8 @@ struct Setup {
   int nL = 0;
   double *Bd = nullptr, *Md = nullptr, *Nd = nullptr, *X = nullptr, *W = nullptr, *J = nullptr;
   double *sv = nullptr, *work = nullptr;
+  double *W2 = nullptr, *J2 = nullptr, *sv2 = nullptr;  // SVD of B_L for the pseudo-inverse
+  bool pinv_done = false;
 
   Pool &pool() { return h->pool; }
 
@@ -161,7 +163,7 @@ struct Setup {
   // Algorithm 1 (bamg_mle) from level l
   void mle(int l, int cycle) {
     if (l == h->L - 1) {
-      coarsest();
+      coarsest(cycle == h->opt.setup_cycles);
       return;
     }
     Level &L = h->lv[l];
@@ -194,39 +196,60 @@ struct Setup {
     J = pool().template get<double>(nn);
     sv = pool().template get<double>(n);
     work = pool().template get<double>(n + 64);
+    if (n > coarse_small_max()) {
+      W2 = pool().template get<double>(nn);
+      J2 = pool().template get<double>(nn);
+      sv2 = pool().template get<double>(n);
+    }
   }
 
-  // r smallest generalized singular triplets on the coarsest level
-  void coarsest() {
+  // r smallest generalized singular triplets on the coarsest level. In the
+  // last setup cycle B_L is final, so its pseudo-inverse (the coarse solve
+  // of the V-cycle) is computed in the same launches.
+  void coarsest(bool last) {
     Level &C = h->lv[h->L - 1];
     const int n = C.n;
     csr_to_dense(C.B, C.Bv, h->prec, Bd, s);
     if (h->prec) zero_colsums(Bd, n, s);
     csr_to_dense(C.M, C.Mv, h->prec, Md, s);
     csr_to_dense(C.M, C.Nv, h->prec, Nd, s);
+    if (last && !h->bdag) h->bdag = pool().template get<double>((size_t)n * n);
     if (n <= coarse_small_max()) {
-      if (coarse_small(0, n, r, Bd, Md, Nd, C.U, C.V, h->prec, h->sigma, nullptr, flag, s) !=
-          BAMG_OK)
-        fail(BAMG_E_COARSE, "coarsest generalized SVD failed (M_L, N_L not SPD or no convergence)");
+      const int st = coarse_small(last ? 2 : 0, n, r, Bd, Md, Nd, C.U, C.V, h->prec, h->sigma,
+                                  last ? h->bdag : nullptr, flag, s);
+      if (st != BAMG_OK)
+        fail(BAMG_E_COARSE,
+             last ? "coarsest generalized SVD failed or coarsest operator not of rank n_L - 1"
+                  : "coarsest generalized SVD failed (M_L, N_L not SPD or no convergence)");
+      pinv_done = last;
       return;
     }
+    if (last) transpose_dense(Bd, W2, n, s);  // B_L column-major, for its own SVD
     if (cholesky(Md, n, s) != BAMG_OK || cholesky(Nd, n, s) != BAMG_OK)
       fail(BAMG_E_COARSE, "coarsest M_L or N_L not positive definite");
     HIPCHK(hipMemcpyAsync(X, Bd, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToDevice, s));
     trsm_lower_cols(Md, X, n, n, n, s);  // X = L_M^-1 B
     transpose_dense(X, W, n, s);
     trsm_lower_cols(Nd, W, n, n, n, s);  // W = L_N^-1 X^T, i.e. Bt column-major
-    if (jacobi_svd(pool(), W, J, n, s) != BAMG_OK) fail(BAMG_E_COARSE, "Jacobi SVD did not converge");
+    if (jacobi_svd2(pool(), W, J, last ? W2 : nullptr, last ? J2 : nullptr, n, s) != BAMG_OK)
+      fail(BAMG_E_COARSE, "Jacobi SVD did not converge");
     column_norms(W, n, sv, s);
     coarse_triplets_out(Md, Nd, W, J, sv, n, r, C.U, C.V, h->prec, h->sigma, work, s);
+    if (last) {
+      column_norms(W2, n, sv2, s);
+      if (build_pinv(pool(), W2, J2, sv2, n, h->bdag, s) != BAMG_OK)
+        fail(BAMG_E_COARSE, "coarsest operator is not of rank n_L - 1");
+      pinv_done = true;
+    }
   }
 
   void pinv() {
+    if (pinv_done) return;
     Level &C = h->lv[h->L - 1];
     const int n = C.n;
     csr_to_dense(C.B, C.Bv, h->prec, Bd, s);
     if (h->prec) zero_colsums(Bd, n, s);
-    h->bdag = pool().template get<double>((size_t)n * n);
+    if (!h->bdag) h->bdag = pool().template get<double>((size_t)n * n);
     if (n <= coarse_small_max()) {
       if (coarse_small(1, n, r, Bd, nullptr, nullptr, nullptr, nullptr, h->prec, nullptr, h->bdag,
                        flag, s) != BAMG_OK)

@@ -56,11 +56,16 @@ void smooth_steps(bamg_handle *h, Level &L, const T *b, T *x, int steps, bool fr
   T *spare = (T *)L.tb;
   T *cur = x, *oth = spare;
   if (from_zero) {
-    T *first = (steps % 2 == 1) ? x : spare;
-    jacobi<T>(L.B, (const T *)L.Bv, (const T *)L.dinv, om, b, nullptr, first, L.lanes, s);
+    // the first two sweeps in one kernel (one if only one is asked for)
+    const int done = steps >= 2 ? 2 : 1;
+    T *first = ((steps - done) % 2 == 0) ? x : spare;
+    if (done == 2)
+      jacobi2_from_zero<T>(L.B, (const T *)L.Bv, (const T *)L.dinv, om, b, first, L.lanes, s);
+    else
+      jacobi<T>(L.B, (const T *)L.Bv, (const T *)L.dinv, om, b, nullptr, first, L.lanes, s);
     cur = first;
     oth = first == x ? spare : x;
-    --steps;
+    steps -= done;
   } else if (steps % 2 == 1) {
     // odd count from x: the caller provided x in the spare buffer instead
     cur = spare;
