@@ -318,6 +318,7 @@ def main():
 
     # untimed: accuracy and split of the last step, V-cycle bandwidth
     hinfo = last.info()
+    hinfo_lanes = last.lanes(0)
     xs = x.cpu().numpy()
     extra = {}
     if kind == "delaunay":
@@ -383,9 +384,10 @@ def main():
     last.close()
 
     traffic = measured_traffic(args.workload, args.precision)
+    lanes0 = hinfo_lanes
     achieved = (kbytes / launches) / (kms / launches * 1e-3) / 1e9 if launches else None
     roofline = {
-        "kernel": "k_jacobi (finest-level weighted-Jacobi sweep, CSR, 8 lanes/row)",
+        "kernel": f"k_jacobi (finest-level weighted-Jacobi sweep, CSR, {lanes0} lanes/row)",
         "bound": "hbm",
         "achieved": round(achieved, 1) if achieved else None,
         "peak": HBM_PEAK_GBPS,

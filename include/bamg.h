@@ -219,6 +219,9 @@ bamg_status bamg_coarse_pinv(const bamg_handle *h, double *bdag);
  * and index read once, every vector read or written once per kernel that
  * touches it, the dense coarsest solve; FP64 or FP32 values as stored. */
 bamg_status bamg_vcycle_bytes(const bamg_handle *h, double *bytes);
+/* Lanes of a 64-wide wave that share one CSR row in the sweeps and
+ * residual of level l (after autotuning, if it was requested). */
+bamg_status bamg_level_lanes(const bamg_handle *h, int32_t l, int32_t *lanes);
 
 /* Kernel timing with HIP events on the launch stream. kernel 0 = the
  * weighted-Jacobi sweep on the finest level (the V-cycle smoother that

@@ -92,6 +92,7 @@ def lib():
         L.bamg_x0.argtypes = [V, V, V]
         L.bamg_coarse_pinv.argtypes = [V, V]
         L.bamg_vcycle_bytes.argtypes = [V, V]
+        L.bamg_level_lanes.argtypes = [V, C.c_int32, P(C.c_int32)]
         L.bamg_kernel_profile_begin.argtypes = [V, C.c_int32]
         L.bamg_kernel_profile_end.argtypes = [V, V, V, V]
         L.bamg_destroy.argtypes = [V]
@@ -310,6 +311,12 @@ class Hierarchy:
         b = C.c_double()
         _check(lib().bamg_vcycle_bytes(self.h, C.byref(b)))
         return b.value
+
+    def lanes(self, l):
+        """Lanes per CSR row used by level l's sweeps."""
+        v = C.c_int32()
+        _check(lib().bamg_level_lanes(self.h, l, C.byref(v)))
+        return v.value
 
     def profile_begin(self, kernel=0):
         _check(lib().bamg_kernel_profile_begin(self.h, kernel))

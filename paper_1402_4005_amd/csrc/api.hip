@@ -437,6 +437,13 @@ bamg_status bamg_vcycle_bytes(const bamg_handle *h, double *bytes) {
   return BAMG_OK;
 }
 
+bamg_status bamg_level_lanes(const bamg_handle *h, int32_t l, int32_t *lanes) {
+  if (!h || !lanes || l < 0 || l >= h->L) return BAMG_E_ARG;
+  const Level &L = h->lv[l];
+  *lanes = L.lanes > 0 ? L.lanes : lanes_for(L.n, L.B.nnz);
+  return BAMG_OK;
+}
+
 bamg_status bamg_kernel_profile_begin(bamg_handle *h, int32_t kernel) {
   if (!h || kernel != 0) return BAMG_E_ARG;
   h->prof_kernel = kernel;

@@ -272,6 +272,9 @@ constexpr int kRedBlocks = 1024;  // partial-sum blocks of the reductions
 
 inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
+// default lanes per CSR row: the average row length rounded up to a power of two
+int lanes_for(int nr, int nnz);
+
 // lanes per CSR row for a level's sweeps, by timing (tune.hip)
 template <class T>
 int tune_lanes(Pool &pool, const Level &L, hipStream_t s);

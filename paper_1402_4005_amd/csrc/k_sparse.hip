@@ -79,12 +79,13 @@ __global__ void __launch_bounds__(kSpThreads)
   }
 }
 
-static int pick_lanes(int nr, int nnz) {
+int lanes_for(int nr, int nnz) {
   int avg = nr ? (nnz + nr - 1) / nr : 1;
   int l = 1;
   while (l < avg && l < 64) l <<= 1;
   return l;
 }
+static int pick_lanes(int nr, int nnz) { return lanes_for(nr, nnz); }
 
 #define BAMG_LPR_SWITCH(LANES, KERNEL, GRIDROWS, ...)                                        \
   do {                                                                                       \
