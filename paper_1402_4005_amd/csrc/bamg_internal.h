@@ -189,12 +189,12 @@ void spgemm_symbolic(Pool &pool, const Csr &A, const Csr &B, int force_diag, Csr
                      hipStream_t s);
 template <class T>
 void spgemm_numeric(const Csr &A, const T *av, const Csr &B, const T *bv, const Csr &C, T *cv,
-                    hipStream_t s);
+                    int *scratch, hipStream_t s);  // scratch: A.nr + 1 ints
 template <class T>
 void fill_transfer_identity(const Level &L, T *Pv, T *Qtv, hipStream_t s);
 template <class T>
-void ls_fit(const Level &L, int r, const T *U, const T *V, const double *wv, const double *wu,
-            int rule, T *Pv, T *Qtv, hipStream_t s);
+void ls_fit(const Level &L, int r, int mmax, const T *U, const T *V, const double *wv,
+            const double *wu, int rule, T *Pv, T *Qtv, hipStream_t s);
 template <class T>
 void dinv_from_diag(const Level &L, const T *bv, T *dinv, int *flag, hipStream_t s);
 template <class T>

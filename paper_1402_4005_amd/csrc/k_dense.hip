@@ -12,6 +12,8 @@
 // grid-wide barrier between rounds (cooperative launch).
 #include <hip/hip_cooperative_groups.h>
 
+#include <mutex>
+
 #include "bamg_internal.h"
 #include "device_common.h"
 
@@ -316,11 +318,19 @@ int jacobi_svd2(Pool &pool, double *W, double *J, double *W2, double *J2, int n,
   if (grid < 1) grid = 1;
   void *args[] = {(void *)&W,  (void *)&J,  (void *)&W2,  (void *)&J2,  (void *)&nmat,
                   (void *)&n,  (void *)&bs, (void *)&nbp, (void *)&ctrl};
-  HIPCHK(hipLaunchCooperativeKernel((const void *)k_block_jacobi_svd, dim3(grid), dim3(threads),
-                                    args, shm, s));
   int sweeps = 0;
-  HIPCHK(hipMemcpyAsync(&sweeps, ctrl + kSvdMaxSweeps, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  {
+    // A cooperative grid is sized to be co-resident on an otherwise idle
+    // device; two of them at once (chains set up on concurrent streams)
+    // could not both be resident and their grid barriers could wait
+    // forever. One in flight per process, held until it has finished.
+    static std::mutex coop_mu;
+    std::lock_guard<std::mutex> lock(coop_mu);
+    HIPCHK(hipLaunchCooperativeKernel((const void *)k_block_jacobi_svd, dim3(grid),
+                                      dim3(threads), args, shm, s));
+    HIPCHK(hipMemcpyAsync(&sweeps, ctrl + kSvdMaxSweeps, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
   pool.release(ctrl);
   return sweeps < kSvdMaxSweeps ? BAMG_OK : BAMG_E_COARSE;
 }

@@ -395,12 +395,12 @@ __device__ int common_neighbours(const int *__restrict__ rp, const int *__restri
   return c;
 }
 
-template <bool FILL>
+// Row i's set is counted into cnt[i] and kept in tmp[i * cap ...]; a copy
+// kernel then packs it into P once the row pointers are known.
 __global__ void k_interp_pattern(int n, int nx, int ny, int gkind, int geometric, int cap,
                                  const int *__restrict__ cf, const int *__restrict__ cidx,
                                  const int *__restrict__ grp, const int *__restrict__ gci,
-                                 int *__restrict__ cnt, const int *__restrict__ prp,
-                                 int *__restrict__ pci, int *__restrict__ overflow) {
+                                 int *__restrict__ cnt, int *__restrict__ tmp) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int out[16];
@@ -454,23 +454,25 @@ __global__ void k_interp_pattern(int n, int nx, int ny, int gkind, int geometric
       out[q + 1] = v;
     }
   }
-  if (FILL) {
-    const int p0 = prp[i];
-    for (int q = 0; q < m; ++q) pci[p0 + q] = out[q];
-  } else {
-    cnt[i] = m;
-  }
+  cnt[i] = m;
+  for (int q = 0; q < m; ++q) tmp[(size_t)i * cap + q] = out[q];
+}
+
+__global__ void k_pack_rows(int n, int cap, const int *__restrict__ tmp,
+                            const int *__restrict__ prp, int *__restrict__ pci) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int p0 = prp[i], m = prp[i + 1] - p0;
+  for (int q = 0; q < m; ++q) pci[p0 + q] = tmp[(size_t)i * cap + q];
 }
 
 void interp_pattern(Pool &pool, const Level &L, int cap, int geometric, Csr &P, hipStream_t s) {
   const int n = L.n;
   if (cap > 16) fail(BAMG_E_ARG, "max_interp above 16");
   int *cnt = pool.get<int>(n);
-  int *ovf = pool.get<int>(1);
-  fill_i32(ovf, 0, 1, s);
-  k_interp_pattern<false><<<ceil_div(n, 128), 128, 0, s>>>(
-      n, L.nx, L.ny, L.gkind, geometric, cap, L.cf, L.cidx, L.G.rp, L.G.ci, cnt, nullptr, nullptr,
-      ovf);
+  int *tmp = pool.get<int>((size_t)n * cap);
+  k_interp_pattern<<<ceil_div(n, 128), 128, 0, s>>>(n, L.nx, L.ny, L.gkind, geometric, cap, L.cf,
+                                                     L.cidx, L.G.rp, L.G.ci, cnt, tmp);
   LAUNCHCHK();
   P.nr = n;
   P.nc = L.nc;
@@ -478,12 +480,10 @@ void interp_pattern(Pool &pool, const Level &L, int cap, int geometric, Csr &P, 
   scan_counts(pool, cnt, P.rp, n, s);
   P.nnz = read_int(P.rp + n, s);
   P.ci = pool.get<int>(P.nnz);
-  k_interp_pattern<true><<<ceil_div(n, 128), 128, 0, s>>>(
-      n, L.nx, L.ny, L.gkind, geometric, cap, L.cf, L.cidx, L.G.rp, L.G.ci, nullptr, P.rp, P.ci,
-      ovf);
+  k_pack_rows<<<ceil_div(n, 256), 256, 0, s>>>(n, cap, tmp, P.rp, P.ci);
   LAUNCHCHK();
   pool.release(cnt);
-  pool.release(ovf);
+  pool.release(tmp);
 }
 
 // ============================================================ SpGEMM symbolic
@@ -662,11 +662,11 @@ void spgemm_symbolic(Pool &pool, const Csr &A, const Csr &B, int force_diag, Csr
 // ============================================================ SpGEMM numeric
 // One thread per row of C: terms are added in the order (A column, B column)
 // ascending, each at the position of its column in the sorted row of C.
-// Same products and term order; rows of C with at most kNumAcc entries
+// Rows of C with at most kNumAcc entries and kNumTerms product terms
 // accumulate in the thread's private LDS slice, next to the row's column
 // indices that the binary search reads (both laid out position-major so
 // the threads of a wave hit distinct banks) and are written once.
-constexpr int kNumThreads = 128, kNumAcc = 32;
+constexpr int kNumThreads = 128, kNumAcc = 32, kNumTerms = 64;
 
 template <class T>
 __global__ void __launch_bounds__(kNumThreads)
@@ -674,78 +674,174 @@ __global__ void __launch_bounds__(kNumThreads)
                      const T *__restrict__ av, const int *__restrict__ brp,
                      const int *__restrict__ bci, const T *__restrict__ bv,
                      const int *__restrict__ crp, const int *__restrict__ cci,
-                     T *__restrict__ cv) {
+                     T *__restrict__ cv, int *__restrict__ longrows, int *__restrict__ nlong) {
   __shared__ T acc[kNumAcc * kNumThreads];
   __shared__ int cols[kNumAcc * kNumThreads];  // the output row's columns
   const int t = threadIdx.x;
   const int i = blockIdx.x * kNumThreads + t;
-  if (i >= nr) return;
-  const int c0 = crp[i], c1 = crp[i + 1];
-  if (c1 - c0 > kNumAcc) {
-    for (int p = c0; p < c1; ++p) cv[p] = (T)0;
-    for (int a = arp[i]; a < arp[i + 1]; ++a) {
-      const int k = aci[a];
-      const T x = av[a];
-      for (int b = brp[k]; b < brp[k + 1]; ++b) {
-        const int j = bci[b];
-        int lo = c0, hi = c1 - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (cci[mid] < j)
-            lo = mid + 1;
-          else
-            hi = mid;
+  bool is_long = false;
+  if (i < nr) {
+    const int c0 = crp[i], c1 = crp[i + 1];
+    const int m = c1 - c0;
+    int terms = 0;
+    for (int a = arp[i]; a < arp[i + 1] && terms <= kNumTerms; ++a)
+      terms += brp[aci[a] + 1] - brp[aci[a]];
+    if (m > kNumAcc || terms > kNumTerms) {
+      is_long = true;
+    } else {
+      for (int q = 0; q < m; ++q) {
+        acc[q * kNumThreads + t] = (T)0;
+        cols[q * kNumThreads + t] = cci[c0 + q];
+      }
+      for (int a = arp[i]; a < arp[i + 1]; ++a) {
+        const int k = aci[a];
+        const T x = av[a];
+        for (int b = brp[k]; b < brp[k + 1]; ++b) {
+          const int j = bci[b];
+          int lo = 0, hi = m - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (cols[mid * kNumThreads + t] < j)
+              lo = mid + 1;
+            else
+              hi = mid;
+          }
+          acc[lo * kNumThreads + t] += x * bv[b];
         }
-        cv[lo] += x * bv[b];
       }
-    }
-    return;
-  }
-  const int m = c1 - c0;
-  for (int q = 0; q < m; ++q) {
-    acc[q * kNumThreads + t] = (T)0;
-    cols[q * kNumThreads + t] = cci[c0 + q];
-  }
-  for (int a = arp[i]; a < arp[i + 1]; ++a) {
-    const int k = aci[a];
-    const T x = av[a];
-    for (int b = brp[k]; b < brp[k + 1]; ++b) {
-      const int j = bci[b];
-      int lo = 0, hi = m - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (cols[mid * kNumThreads + t] < j)
-          lo = mid + 1;
-        else
-          hi = mid;
-      }
-      acc[lo * kNumThreads + t] += x * bv[b];
+      for (int q = 0; q < m; ++q) cv[c0 + q] = acc[q * kNumThreads + t];
     }
   }
-  for (int q = 0; q < c1 - c0; ++q) cv[c0 + q] = acc[q * kNumThreads + t];
+  // rows with more than kNumAcc entries or kNumTerms product terms go to
+  // k_spgemm_num_long (one counter update per wave)
+  const unsigned long long bl = __ballot(is_long);
+  if (bl) {
+    const int lane = t % kWave;
+    int base = 0;
+    if (lane == 0) base = atomicAdd(nlong, (int)__popcll(bl));
+    base = __shfl(base, 0, kWave);
+    if (is_long) longrows[base + __popcll(bl & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))))] = i;
+  }
+}
+
+// Long rows of C: a group of kLongLanes lanes per row. Lane l takes a
+// contiguous chunk of the row of A and accumulates its terms into its own
+// LDS slice; the slices are then summed in lane order, so the result does
+// not depend on timing. Rows wider than kLongAcc are summed by one lane in
+// global memory.
+constexpr int kLongLanes = 16, kLongGroups = 4, kLongAcc = 96, kNumFewRows = 32768;
+
+template <class T>
+__global__ void __launch_bounds__(kLongLanes * kLongGroups)
+    k_spgemm_num_long(const int *__restrict__ rows, const int *__restrict__ nlong, int nall,
+                      const int *__restrict__ arp, const int *__restrict__ aci,
+                      const T *__restrict__ av, const int *__restrict__ brp,
+                      const int *__restrict__ bci, const T *__restrict__ bv,
+                      const int *__restrict__ crp, const int *__restrict__ cci,
+                      T *__restrict__ cv) {
+  __shared__ T acc[kLongGroups][kLongAcc * kLongLanes];
+  __shared__ int cols[kLongGroups][kLongAcc];
+  const int g = threadIdx.x / kLongLanes, lane = threadIdx.x % kLongLanes;
+  const int nl = rows ? *nlong : nall;  // rows == nullptr: every row of C
+  for (int base = blockIdx.x * kLongGroups; base < nl; base += gridDim.x * kLongGroups) {
+    const int w = base + g;
+    const int i = w < nl ? (rows ? rows[w] : w) : -1;
+    const int c0 = i >= 0 ? crp[i] : 0, m = i >= 0 ? crp[i + 1] - c0 : 0;
+    const bool lds = m <= kLongAcc;
+    if (i >= 0 && lds) {
+      for (int q = lane; q < m; q += kLongLanes) cols[g][q] = cci[c0 + q];
+      for (int q = 0; q < m; ++q) acc[g][q * kLongLanes + lane] = (T)0;
+    }
+    __syncthreads();
+    if (i >= 0 && lds) {
+      const int ab = arp[i], ae = arp[i + 1];
+      const int chunk = (ae - ab + kLongLanes - 1) / kLongLanes;
+      const int a1 = ab + lane * chunk, a2 = min(ae, a1 + chunk);
+      for (int a = a1; a < a2; ++a) {
+        const int k = aci[a];
+        const T x = av[a];
+        for (int b = brp[k]; b < brp[k + 1]; ++b) {
+          const int j = bci[b];
+          int lo = 0, hi = m - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (cols[g][mid] < j)
+              lo = mid + 1;
+            else
+              hi = mid;
+          }
+          acc[g][lo * kLongLanes + lane] += x * bv[b];
+        }
+      }
+    } else if (i >= 0 && lane == 0) {
+      for (int p = c0; p < c0 + m; ++p) cv[p] = (T)0;
+      for (int a = arp[i]; a < arp[i + 1]; ++a) {
+        const int k = aci[a];
+        const T x = av[a];
+        for (int b = brp[k]; b < brp[k + 1]; ++b) {
+          const int j = bci[b];
+          int lo = c0, hi = c0 + m - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (cci[mid] < j)
+              lo = mid + 1;
+            else
+              hi = mid;
+          }
+          cv[lo] += x * bv[b];
+        }
+      }
+    }
+    __syncthreads();
+    if (i >= 0 && lds)
+      for (int q = lane; q < m; q += kLongLanes) {
+        T sum = (T)0;
+        for (int l = 0; l < kLongLanes; ++l) sum += acc[g][q * kLongLanes + l];
+        cv[c0 + q] = sum;
+      }
+    __syncthreads();
+  }
 }
 
 template <class T>
 void spgemm_numeric(const Csr &A, const T *av, const Csr &B, const T *bv, const Csr &C, T *cv,
-                    hipStream_t s) {
+                    int *scratch, hipStream_t s) {
   if (!A.nr) return;
+  const int grid = std::min(1024, ceil_div(A.nr, kLongGroups));
+  if (A.nr < kNumFewRows) {
+    // few rows: a thread per row cannot hide its chain of dependent loads,
+    // so every row goes to the lane groups
+    k_spgemm_num_long<T><<<grid, kLongLanes * kLongGroups, 0, s>>>(
+        nullptr, nullptr, A.nr, A.rp, A.ci, av, B.rp, B.ci, bv, C.rp, C.ci, cv);
+    LAUNCHCHK();
+    return;
+  }
+  int *nlong = scratch, *longrows = scratch + 1;  // scratch holds A.nr + 1 ints
+  fill_i32(nlong, 0, 1, s);
   k_spgemm_num_lds<T><<<ceil_div(A.nr, kNumThreads), kNumThreads, 0, s>>>(
-      A.nr, A.rp, A.ci, av, B.rp, B.ci, bv, C.rp, C.ci, cv);
+      A.nr, A.rp, A.ci, av, B.rp, B.ci, bv, C.rp, C.ci, cv, longrows, nlong);
+  LAUNCHCHK();
+  k_spgemm_num_long<T><<<grid, kLongLanes * kLongGroups, 0, s>>>(
+      longrows, nlong, 0, A.rp, A.ci, av, B.rp, B.ci, bv, C.rp, C.ci, cv);
   LAUNCHCHK();
 }
 
 // ============================================================ LS fits
+// Array bounds of one fit: RM test vectors, MM interpolation points. The
+// small instance (RM = 8, MM = 4, the paper's r = 8 with c <= 4) keeps its
+// arrays in registers; the large one (16, 8) covers the remaining options.
 constexpr int kRMax = 16, kMMax = 8;
 
 // Householder least squares on the columns listed in idx[0..na): minimise
 // || G[:, idx] p - g || over rows [row0, rows). A column whose |R_tt| falls
 // to 1e-12 max|R_ss| or below is removed from idx and the fit redone.
 // Returns the number of columns kept; p[t] for t < na afterwards.
-__device__ int ls_qr(double (&G)[kRMax][kMMax], const double (&g)[kRMax], int row0, int rows,
-                     int (&idx)[kMMax], int na, double (&p)[kMMax]) {
+template <int RM, int MM>
+__device__ int ls_qr(double (&G)[RM][MM], const double (&g)[RM], int row0, int rows,
+                     int (&idx)[MM], int na, double (&p)[MM]) {
   for (;;) {
     if (na == 0) return 0;
-    double W[kRMax][kMMax], h[kRMax], R[kMMax];
+    double W[RM][MM], h[RM], R[MM];
     const int nrow = rows - row0;
     for (int k = 0; k < nrow; ++k) {
       for (int a = 0; a < na; ++a) W[k][a] = G[row0 + k][idx[a]];
@@ -805,26 +901,27 @@ __device__ int ls_qr(double (&G)[kRMax][kMMax], const double (&g)[kRMax], int ro
 // One weighted fit over the active points act[]: plain (sum1 = false, rows
 // k = 0..r-1) or with sum-to-one (rows k = 1..r-1, last active point
 // eliminated). Writes coef[0..m) (0 for inactive points).
-__device__ void fit_active(const double (&Gr)[kRMax][kMMax], const double (&gr)[kRMax],
+template <int RM, int MM>
+__device__ void fit_active(const double (&Gr)[RM][MM], const double (&gr)[RM],
                            const double *__restrict__ w, int r, int m, bool sum1,
-                           const bool (&act)[kMMax], double (&coef)[kMMax]) {
-  int ids[kMMax];
+                           const bool (&act)[MM], double (&coef)[MM]) {
+  int ids[MM];
   int na = 0;
   for (int t = 0; t < m; ++t) {
     coef[t] = 0.0;
     if (act[t]) ids[na++] = t;
   }
   if (na == 0) return;
-  double G[kRMax][kMMax], g[kRMax], p[kMMax];
+  double G[RM][MM], g[RM], p[MM];
   if (!sum1) {
     for (int k = 0; k < r; ++k) {
       const double sw = sqrt(w[k]);
       for (int a = 0; a < na; ++a) G[k][a] = sw * Gr[k][ids[a]];
       g[k] = sw * gr[k];
     }
-    int cols[kMMax];
+    int cols[MM];
     for (int a = 0; a < na; ++a) cols[a] = a;
-    const int kept = ls_qr(G, g, 0, r, cols, na, p);
+    const int kept = ls_qr<RM, MM>(G, g, 0, r, cols, na, p);
     for (int a = 0; a < kept; ++a) coef[ids[cols[a]]] = p[a];
     return;
   }
@@ -839,10 +936,10 @@ __device__ void fit_active(const double (&Gr)[kRMax][kMMax], const double (&gr)[
     for (int a = 0; a < mm; ++a) G[k][a] = sw * (Gr[k][ids[a]] - lv);
     g[k] = sw * (gr[k] - lv);
   }
-  int cols[kMMax];
+  int cols[MM];
   for (int a = 0; a < mm; ++a) cols[a] = a;
   for (int a = 0; a < mm; ++a) p[a] = 0.0;
-  const int kept = ls_qr(G, g, 1, r, cols, mm, p);
+  const int kept = ls_qr<RM, MM>(G, g, 1, r, cols, mm, p);
   double sum = 0.0;
   for (int a = 0; a < kept; ++a) {
     coef[ids[cols[a]]] = p[a];
@@ -853,14 +950,15 @@ __device__ void fit_active(const double (&Gr)[kRMax][kMMax], const double (&gr)[
 
 // rule 1: while a weight is negative, remove the most negative point and
 // refit (at least one point stays).
-__device__ void fit_point(const double (&G)[kRMax][kMMax], const double (&g)[kRMax],
+template <int RM, int MM>
+__device__ void fit_point(const double (&G)[RM][MM], const double (&g)[RM],
                           const double *__restrict__ w, int r, int m, bool sum1, int rule,
-                          double (&coef)[kMMax]) {
-  bool act[kMMax];
-  for (int t = 0; t < kMMax; ++t) act[t] = t < m;
+                          double (&coef)[MM]) {
+  bool act[MM];
+  for (int t = 0; t < MM; ++t) act[t] = t < m;
   int na = m;
   for (;;) {
-    fit_active(G, g, w, r, m, sum1, act, coef);
+    fit_active<RM, MM>(G, g, w, r, m, sum1, act, coef);
     if (rule == 0 || na == 1) return;
     int worst = -1;
     for (int t = 0; t < m; ++t)
@@ -871,7 +969,7 @@ __device__ void fit_point(const double (&G)[kRMax][kMMax], const double (&g)[kRM
   }
 }
 
-template <class T>
+template <class T, int RM, int MM>
 __global__ void __launch_bounds__(64)
     k_ls_fit(int n, int r, const int *__restrict__ cf, const int *__restrict__ prp,
              const int *__restrict__ pci, const int *__restrict__ cpts, const T *__restrict__ U,
@@ -886,29 +984,34 @@ __global__ void __launch_bounds__(64)
     return;
   }
   const int m = prp[i + 1] - a0;
-  int jf[kMMax];
+  int jf[MM];
   for (int t = 0; t < m; ++t) jf[t] = cpts[pci[a0 + t]];
-  double G[kRMax][kMMax], g[kRMax], coef[kMMax];
+  double G[RM][MM], g[RM], coef[MM];
   for (int k = 0; k < r; ++k) {
     for (int t = 0; t < m; ++t) G[k][t] = (double)V[(size_t)jf[t] * r + k];
     g[k] = (double)V[(size_t)i * r + k];
   }
-  fit_point(G, g, wv, r, m, false, rule, coef);
+  fit_point<RM, MM>(G, g, wv, r, m, false, rule, coef);
   for (int t = 0; t < m; ++t) Pv[a0 + t] = (T)coef[t];
   for (int k = 0; k < r; ++k) {
     for (int t = 0; t < m; ++t) G[k][t] = (double)U[(size_t)jf[t] * r + k];
     g[k] = (double)U[(size_t)i * r + k];
   }
-  fit_point(G, g, wu, r, m, true, rule, coef);
+  fit_point<RM, MM>(G, g, wu, r, m, true, rule, coef);
   for (int t = 0; t < m; ++t) Qtv[a0 + t] = (T)coef[t];
 }
 
 template <class T>
-void ls_fit(const Level &L, int r, const T *U, const T *V, const double *wv, const double *wu,
-            int rule, T *Pv, T *Qtv, hipStream_t s) {
+void ls_fit(const Level &L, int r, int mmax, const T *U, const T *V, const double *wv,
+            const double *wu, int rule, T *Pv, T *Qtv, hipStream_t s) {
   if (r > kRMax) fail(BAMG_E_ARG, "r above 16");
-  k_ls_fit<T><<<ceil_div(L.n, 64), 64, 0, s>>>(L.n, r, L.cf, L.P.rp, L.P.ci, L.cpts, U, V, wv, wu,
-                                               rule, Pv, Qtv);
+  if (mmax > kMMax) fail(BAMG_E_ARG, "more than 8 interpolation points");
+  if (r <= 8 && mmax <= 4)
+    k_ls_fit<T, 8, 4><<<ceil_div(L.n, 64), 64, 0, s>>>(L.n, r, L.cf, L.P.rp, L.P.ci, L.cpts, U, V,
+                                                      wv, wu, rule, Pv, Qtv);
+  else
+    k_ls_fit<T, kRMax, kMMax><<<ceil_div(L.n, 64), 64, 0, s>>>(L.n, r, L.cf, L.P.rp, L.P.ci, L.cpts,
+                                                              U, V, wv, wu, rule, Pv, Qtv);
   LAUNCHCHK();
 }
 
@@ -1353,9 +1456,9 @@ void row_inv_norms(const Csr &A, const T *val, T *out, hipStream_t s) {
 
 #define INST(T)                                                                              \
   template void spgemm_numeric<T>(const Csr &, const T *, const Csr &, const T *, const Csr &, \
-                                  T *, hipStream_t);                                         \
+                                  T *, int *, hipStream_t);                                  \
   template void fill_transfer_identity<T>(const Level &, T *, T *, hipStream_t);             \
-  template void ls_fit<T>(const Level &, int, const T *, const T *, const double *,          \
+  template void ls_fit<T>(const Level &, int, int, const T *, const T *, const double *,     \
                           const double *, int, T *, T *, hipStream_t);                       \
   template void dinv_from_diag<T>(const Level &, const T *, T *, int *, hipStream_t);               \
   template void inject<T>(const int *, int, int, const T *, T *, hipStream_t);               \

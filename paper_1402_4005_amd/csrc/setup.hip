@@ -116,12 +116,14 @@ struct Setup {
     Level &C = h->lv[l + 1];
     copy_permuted<T>((T *)L.Ptv, (const T *)L.Pv, L.pcperm, L.P.nnz, s);
     copy_permuted<T>((T *)L.Qv, (const T *)L.Qtv, L.pcperm, L.P.nnz, s);
-    spgemm_numeric<T>(L.B, (const T *)L.Bv, L.P, (const T *)L.Pv, L.T1, (T *)L.T1v, s);
-    spgemm_numeric<T>(L.Pc, (const T *)L.Qv, L.T1, (const T *)L.T1v, C.B, (T *)C.Bv, s);
-    spgemm_numeric<T>(L.M, (const T *)L.Mv, L.P, (const T *)L.Qtv, L.T2, (T *)L.T2v, s);
-    spgemm_numeric<T>(L.Pc, (const T *)L.Qv, L.T2, (const T *)L.T2v, C.M, (T *)C.Mv, s);
-    spgemm_numeric<T>(L.M, (const T *)L.Nv, L.P, (const T *)L.Pv, L.T2, (T *)L.T3v, s);
-    spgemm_numeric<T>(L.Pc, (const T *)L.Ptv, L.T2, (const T *)L.T3v, C.M, (T *)C.Nv, s);
+    int *sc = pool().template get<int>((size_t)L.n + 1);  // long-row lists (n >= nc)
+    spgemm_numeric<T>(L.B, (const T *)L.Bv, L.P, (const T *)L.Pv, L.T1, (T *)L.T1v, sc, s);
+    spgemm_numeric<T>(L.Pc, (const T *)L.Qv, L.T1, (const T *)L.T1v, C.B, (T *)C.Bv, sc, s);
+    spgemm_numeric<T>(L.M, (const T *)L.Mv, L.P, (const T *)L.Qtv, L.T2, (T *)L.T2v, sc, s);
+    spgemm_numeric<T>(L.Pc, (const T *)L.Qv, L.T2, (const T *)L.T2v, C.M, (T *)C.Mv, sc, s);
+    spgemm_numeric<T>(L.M, (const T *)L.Nv, L.P, (const T *)L.Pv, L.T2, (T *)L.T3v, sc, s);
+    spgemm_numeric<T>(L.Pc, (const T *)L.Ptv, L.T2, (const T *)L.T3v, C.M, (T *)C.Nv, sc, s);
+    pool().release(sc);
     copy_permuted<T>((T *)C.Btv, (const T *)C.Bv, C.btperm, C.B.nnz, s);
     dinv_from_diag<T>(C, (const T *)C.Bv, (T *)C.dinv, flag, s);
     // Kaczmarz row norms exist only where the smoother runs (not on the
@@ -170,8 +172,8 @@ struct Setup {
     relax(L, cycle > 1);
     normalize(L);
     weights(L);
-    ls_fit<T>(L, r, (const T *)L.U, (const T *)L.V, wv, wu, h->opt.interp_rule, (T *)L.Pv,
-              (T *)L.Qtv, s);
+    ls_fit<T>(L, r, h->opt.max_interp, (const T *)L.U, (const T *)L.V, wv, wu,
+              h->opt.interp_rule, (T *)L.Pv, (T *)L.Qtv, s);
     if (h->opt.learned != BAMG_LEARNED_OFF && cycle == 1) learned_rows(L);
     galerkin(l);
     Level &C = h->lv[l + 1];
