@@ -207,15 +207,18 @@ template <class T>
 void relax_pairs(const Level &L, int r, T omega, int with_rhs, const double *sigma, const T *U,
                  const T *V, T *Uo, T *Vo, hipStream_t s);
 // per-block partial sums of u.Bv, u.Mu, v.Nv, |Bv|^2, |B^T u|^2 per column
+// over at most nmax blocks; returns the number of blocks used
 template <class T>
-void pair_products(const Level &L, int r, const T *U, const T *V, int which, double *part,
-                   int nblk, hipStream_t s);
+int pair_products(const Level &L, int r, const T *U, const T *V, int which, double *part,
+                  int nmax, hipStream_t s);
 template <class T>
 void scale_columns(T *X, int n, int r, const double *scale, int skip0, hipStream_t s);
-// finalize kernels on the reduction buffer
-void finalize_products(const double *part, int nblk, int r, double *out, hipStream_t s);
-void sigma_from_products(const double *prod, int r, double *sigma, hipStream_t s);
-void norm_scales(const double *prod, int r, double *scales, hipStream_t s);
+// sums of the product partials into out[16 t + k]; epi 1 also writes
+// sigma_k to aux[k], epi 2 the normalisation scales (aux[k] for v_k,
+// aux[16 + k] for u_k)
+constexpr int kProdBlocks = 2048;
+void finalize_products(const double *part, int nblk, int r, int which, int epi, double *out,
+                       double *aux, hipStream_t s);
 void ls_weights(const double *prod, int r, double *wv, double *wu, hipStream_t s);
 // Kaczmarz colouring of the rows of A (columns listed by At)
 void row_colouring(Pool &pool, const Csr &A, const Csr &At, int *colour, int &ncol,

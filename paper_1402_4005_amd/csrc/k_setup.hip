@@ -565,12 +565,14 @@ __global__ void __launch_bounds__(64)
 // Longer rows are listed for the wave-per-row kernel above (rowlist).
 constexpr int kSymShort = 32, kSymThreads = 128;
 
-template <bool FILL>
+// The distinct columns of each short row are kept in tmp[row * kSymShort ..]
+// (counted into cnt) and packed into C by k_sym_pack once C's row pointers
+// are known; a long row has tmp[row * kSymShort] = -1.
 __global__ void __launch_bounds__(kSymThreads)
     k_spgemm_sym_short(int nr, const int *__restrict__ arp, const int *__restrict__ aci,
                        const int *__restrict__ brp, const int *__restrict__ bci, int force_diag,
-                       int *__restrict__ cnt, const int *__restrict__ crp, int *__restrict__ cci,
-                       int *__restrict__ longrows, int *__restrict__ nlong) {
+                       int *__restrict__ cnt, int *__restrict__ tmp, int *__restrict__ longrows,
+                       int *__restrict__ nlong) {
   __shared__ int buf[kSymShort * kSymThreads];
   const int t = threadIdx.x;
   const int row = blockIdx.x * kSymThreads + t;
@@ -580,6 +582,7 @@ __global__ void __launch_bounds__(kSymThreads)
     for (int a = arp[row]; a < arp[row + 1]; ++a) total += brp[aci[a] + 1] - brp[aci[a]];
     if (total > kSymShort) {
       is_long = true;
+      tmp[(size_t)row * kSymShort] = -1;  // written by the list kernel instead
     } else {
       int m = 0;
       if (force_diag) buf[(m++) * kSymThreads + t] = row;
@@ -597,15 +600,11 @@ __global__ void __launch_bounds__(kSymThreads)
         }
       }
       int d = 0;
-      const int out0 = FILL ? crp[row] : 0;
       for (int q = 0; q < m; ++q) {
         const int v = buf[q * kSymThreads + t];
-        if (q == 0 || v != buf[(q - 1) * kSymThreads + t]) {
-          if (FILL) cci[out0 + d] = v;
-          ++d;
-        }
+        if (q == 0 || v != buf[(q - 1) * kSymThreads + t]) tmp[(size_t)row * kSymShort + d++] = v;
       }
-      if (!FILL) cnt[row] = d;
+      cnt[row] = d;
     }
   }
   const unsigned long long bl = __ballot(is_long);
@@ -618,16 +617,26 @@ __global__ void __launch_bounds__(kSymThreads)
   }
 }
 
+__global__ void k_sym_pack(int nr, const int *__restrict__ tmp,
+                           const int *__restrict__ crp, int *__restrict__ cci) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nr) return;
+  const int p0 = crp[i], m = crp[i + 1] - p0;
+  if (m == 0 || tmp[(size_t)i * kSymShort] < 0) return;  // long rows: the list kernel
+  for (int q = 0; q < m; ++q) cci[p0 + q] = tmp[(size_t)i * kSymShort + q];
+}
+
 void spgemm_symbolic(Pool &pool, const Csr &A, const Csr &B, int force_diag, Csr &C,
                      hipStream_t s) {
   const int nr = A.nr;
   int *cnt = pool.get<int>(nr);
+  int *tmp = pool.get<int>((size_t)nr * kSymShort);
   int *ovf = pool.get<int>(2);  // [overflow, long rows]
   int *longrows = pool.get<int>(nr);
   fill_i32(ovf, 0, 2, s);
   if (nr) {
-    k_spgemm_sym_short<false><<<ceil_div(nr, kSymThreads), kSymThreads, 0, s>>>(
-        nr, A.rp, A.ci, B.rp, B.ci, force_diag, cnt, nullptr, nullptr, longrows, ovf + 1);
+    k_spgemm_sym_short<<<ceil_div(nr, kSymThreads), kSymThreads, 0, s>>>(
+        nr, A.rp, A.ci, B.rp, B.ci, force_diag, cnt, tmp, longrows, ovf + 1);
     LAUNCHCHK();
   }
   const int nlong = read_int(ovf + 1, s);
@@ -644,9 +653,7 @@ void spgemm_symbolic(Pool &pool, const Csr &A, const Csr &B, int force_diag, Csr
   C.nnz = read_int(C.rp + nr, s);
   C.ci = pool.get<int>(C.nnz);
   if (nr) {
-    fill_i32(ovf + 1, 0, 1, s);
-    k_spgemm_sym_short<true><<<ceil_div(nr, kSymThreads), kSymThreads, 0, s>>>(
-        nr, A.rp, A.ci, B.rp, B.ci, force_diag, nullptr, C.rp, C.ci, longrows, ovf + 1);
+    k_sym_pack<<<ceil_div(nr, 256), 256, 0, s>>>(nr, tmp, C.rp, C.ci);
     LAUNCHCHK();
   }
   if (nlong > 0) {
@@ -655,6 +662,7 @@ void spgemm_symbolic(Pool &pool, const Csr &A, const Csr &B, int force_diag, Csr
     LAUNCHCHK();
   }
   pool.release(cnt);
+  pool.release(tmp);
   pool.release(ovf);
   pool.release(longrows);
 }
@@ -1101,52 +1109,97 @@ void spmm(const Csr &A, const T *av, int r, const T *X, T *Y, int reset0, hipStr
 }
 
 // ============================================================ relaxation
+// sum over a in [a0, a1) of val[a] * X[ci[a] * r + k], in index order,
+// accumulated in A. Four entries at a time: their indices, values and
+// gathered vector entries are loaded before any product, so a thread keeps
+// four independent loads in flight instead of one dependent chain.
+template <class A, class T>
+__device__ __forceinline__ A row_dot(int a0, int a1, const int *__restrict__ ci,
+                                     const T *__restrict__ val, const T *__restrict__ X, int r,
+                                     int k) {
+  A acc = 0;
+  int a = a0;
+  for (; a + 4 <= a1; a += 4) {
+    int c[4];
+    T w[4], x[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      c[j] = ci[a + j];
+      w[j] = val[a + j];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[j] = X[(size_t)c[j] * r + k];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc += (A)w[j] * (A)x[j];
+  }
+  for (; a < a1; ++a) acc += (A)val[a] * (A)X[(size_t)ci[a] * r + k];
+  return acc;
+}
+
+// The same for two value arrays on one pattern: (mv . U, nv . V) on row i
+// of M (whose pattern N shares).
+template <class A, class T>
+__device__ __forceinline__ void row_dot2(int a0, int a1, const int *__restrict__ ci,
+                                         const T *__restrict__ mv, const T *__restrict__ nv,
+                                         const T *__restrict__ U, const T *__restrict__ V, int r,
+                                         int k, A &mu, A &nvv) {
+  mu = 0;
+  nvv = 0;
+  int a = a0;
+  for (; a + 2 <= a1; a += 2) {
+    const size_t j0 = (size_t)ci[a] * r + k, j1 = (size_t)ci[a + 1] * r + k;
+    const T m0 = mv[a], m1 = mv[a + 1], n0 = nv[a], n1 = nv[a + 1];
+    const T u0 = U[j0], u1 = U[j1], v0 = V[j0], v1 = V[j1];
+    mu += (A)m0 * (A)u0;
+    nvv += (A)n0 * (A)v0;
+    mu += (A)m1 * (A)u1;
+    nvv += (A)n1 * (A)v1;
+  }
+  if (a < a1) {
+    const size_t j = (size_t)ci[a] * r + k;
+    mu += (A)mv[a] * (A)U[j];
+    nvv += (A)nv[a] * (A)V[j];
+  }
+}
+
 // One simultaneous weighted-Jacobi step on all test vectors (Algorithm 1):
 //   v_k <- v_k + omega D^-1 (sigma_k M u_k - B v_k)
 //   u_k <- u_k + omega D^-1 (sigma_k N v_k - B^T u_k)     (k >= 1)
 // with the sigma terms dropped for the homogeneous first pass. Both
-// right-hand sides use the old vectors. Thread per (row, column).
+// right-hand sides use the old vectors. Thread per (row, column), the r
+// threads of a row adjacent; blocks renumbered XCD-contiguous.
 template <class T>
-__global__ void k_relax_pairs(int n, int r, const int *__restrict__ brp,
-                              const int *__restrict__ bci, const T *__restrict__ bv,
-                              const int *__restrict__ trp, const int *__restrict__ tci,
-                              const T *__restrict__ tv, const int *__restrict__ mrp,
-                              const int *__restrict__ mci, const T *__restrict__ mv,
-                              const T *__restrict__ nv, int identity_mn,
-                              const T *__restrict__ dinv, T omega, int with_rhs,
-                              const double *__restrict__ sigma, const T *__restrict__ U,
-                              const T *__restrict__ V, T *__restrict__ Uo, T *__restrict__ Vo) {
-  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256)
+    k_relax_pairs(int n, int r, const int *__restrict__ brp, const int *__restrict__ bci,
+                  const T *__restrict__ bv, const int *__restrict__ trp,
+                  const int *__restrict__ tci, const T *__restrict__ tv,
+                  const int *__restrict__ mrp, const int *__restrict__ mci,
+                  const T *__restrict__ mv, const T *__restrict__ nv, int identity_mn,
+                  const T *__restrict__ dinv, T omega, int with_rhs,
+                  const double *__restrict__ sigma, const T *__restrict__ U,
+                  const T *__restrict__ V, T *__restrict__ Uo, T *__restrict__ Vo) {
+  const long idx = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (idx >= (long)n * r) return;
   const int i = (int)(idx / r), k = (int)(idx % r);
   const T di = dinv[i];
-  T bvk = 0;
-  for (int a = brp[i]; a < brp[i + 1]; ++a) bvk += bv[a] * V[(size_t)bci[a] * r + k];
+  const T bvk = row_dot<T>(brp[i], brp[i + 1], bci, bv, V, r, k);
+  T btu = 0;
+  if (k > 0) btu = row_dot<T>(trp[i], trp[i + 1], tci, tv, U, r, k);
   T rhs_v = 0, rhs_u = 0;
   if (with_rhs) {
     const T sg = (T)sigma[k];
-    T mu = 0, nvv = 0;
+    T mu, nvv;
     if (identity_mn) {
       mu = U[idx];
       nvv = V[idx];
     } else {
-      for (int a = mrp[i]; a < mrp[i + 1]; ++a) {
-        const size_t j = (size_t)mci[a] * r + k;
-        mu += mv[a] * U[j];
-        nvv += nv[a] * V[j];
-      }
+      row_dot2<T>(mrp[i], mrp[i + 1], mci, mv, nv, U, V, r, k, mu, nvv);
     }
     rhs_v = sg * mu;
     rhs_u = sg * nvv;
   }
   Vo[idx] = V[idx] + omega * di * (rhs_v - bvk);
-  if (k == 0) {
-    Uo[idx] = U[idx];
-    return;
-  }
-  T btu = 0;
-  for (int a = trp[i]; a < trp[i + 1]; ++a) btu += tv[a] * U[(size_t)tci[a] * r + k];
-  Uo[idx] = U[idx] + omega * di * (rhs_u - btu);
+  Uo[idx] = k == 0 ? U[idx] : U[idx] + omega * di * (rhs_u - btu);
 }
 
 template <class T>
@@ -1162,11 +1215,14 @@ void relax_pairs(const Level &L, int r, T omega, int with_rhs, const double *sig
 
 // Per-block partial sums, FP64, deterministic order. For each column k:
 //   q0 = u.B v, q1 = u.M u, q2 = v.N v, q3 = |B v|^2, q4 = |B^T u|^2
-// `which` bit 0: q0..q2, bit 1: q3, q4. Lanes of a 16-lane group are the
-// columns; a block of 256 threads covers 16 rows per step.
+// `which` bit 0: q0..q2, bit 1: q3, q4. A group of G lanes (G = 8 when
+// r <= 8, else 16) holds the columns of one row; a block of 256 threads
+// covers 256 / G rows per step. Partial t of column k from block b goes to
+// part[(16 t + k) * nblk + b], so the finalisation reads each output's
+// partials contiguously.
 constexpr int kPPThreads = 256, kPPLanes = 16;
 
-template <class T>
+template <class T, int G>
 __global__ void __launch_bounds__(kPPThreads)
     k_pair_products(int n, int r, const int *__restrict__ brp, const int *__restrict__ bci,
                     const T *__restrict__ bv, const int *__restrict__ trp,
@@ -1175,110 +1231,113 @@ __global__ void __launch_bounds__(kPPThreads)
                     const T *__restrict__ mv, const T *__restrict__ nv, int identity_mn,
                     const T *__restrict__ U, const T *__restrict__ V, int which,
                     double *__restrict__ part) {
-  __shared__ double sh[kPPThreads / kWave][5][kPPLanes];
-  const int k = threadIdx.x % kPPLanes;
-  const int rowoff = threadIdx.x / kPPLanes;  // 0..15
+  constexpr int kRows = kPPThreads / G;
+  __shared__ double sh[kPPThreads / kWave][5][G];
+  const int nblk = gridDim.x, vb = xcd_block(blockIdx.x, nblk);
+  const int k = threadIdx.x % G;
+  const int rowoff = threadIdx.x / G;
   double q[5] = {0, 0, 0, 0, 0};
   if (k < r) {
-    for (long i = (long)blockIdx.x * (kPPThreads / kPPLanes) + rowoff; i < n;
-         i += (long)gridDim.x * (kPPThreads / kPPLanes)) {
+    for (long i = (long)vb * kRows + rowoff; i < n; i += (long)nblk * kRows) {
       const size_t ik = (size_t)i * r + k;
       const double u = (double)U[ik], v = (double)V[ik];
-      double b = 0.0;
-      for (int a = brp[i]; a < brp[i + 1]; ++a) b += (double)bv[a] * (double)V[(size_t)bci[a] * r + k];
+      const double b = row_dot<double>(brp[i], brp[i + 1], bci, bv, V, r, k);
       if (which & 1) {
-        double mu = 0.0, nvv = 0.0;
+        double mu, nvv;
         if (identity_mn) {
           mu = u;
           nvv = v;
         } else {
-          for (int a = mrp[i]; a < mrp[i + 1]; ++a) {
-            const size_t j = (size_t)mci[a] * r + k;
-            mu += (double)mv[a] * (double)U[j];
-            nvv += (double)nv[a] * (double)V[j];
-          }
+          row_dot2<double>(mrp[i], mrp[i + 1], mci, mv, nv, U, V, r, k, mu, nvv);
         }
         q[0] += u * b;
         q[1] += u * mu;
         q[2] += v * nvv;
       }
       if (which & 2) {
-        double bt = 0.0;
-        for (int a = trp[i]; a < trp[i + 1]; ++a)
-          bt += (double)tv[a] * (double)U[(size_t)tci[a] * r + k];
+        const double bt = row_dot<double>(trp[i], trp[i + 1], tci, tv, U, r, k);
         q[3] += b * b;
         q[4] += bt * bt;
       }
     }
   }
-  // lanes l, l^16, l^32, l^48 of a wave share the column k
+  // lanes l, l ^ G, l ^ 2G, ... of a wave share the column k
 #pragma unroll
   for (int t = 0; t < 5; ++t) {
     double x = q[t];
-    x += __shfl_xor(x, 16, kWave);
-    x += __shfl_xor(x, 32, kWave);
+#pragma unroll
+    for (int off = G; off < kWave; off <<= 1) x += __shfl_xor(x, off, kWave);
     q[t] = x;
   }
   const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
-  if (l < kPPLanes)
+  if (l < G)
     for (int t = 0; t < 5; ++t) sh[w][t][l] = q[t];
   __syncthreads();
-  if (threadIdx.x < 5 * kPPLanes) {
-    const int t = threadIdx.x / kPPLanes, kk = threadIdx.x % kPPLanes;
-    double s = 0.0;
-    for (int ww = 0; ww < kPPThreads / kWave; ++ww) s += sh[ww][t][kk];
-    part[(size_t)blockIdx.x * 5 * kPPLanes + t * kPPLanes + kk] = s;
+  if (threadIdx.x < 5 * G) {
+    const int t = threadIdx.x / G, kk = threadIdx.x % G;
+    if (kk < r && ((t < 3) ? (which & 1) : (which & 2))) {
+      double s = 0.0;
+      for (int ww = 0; ww < kPPThreads / kWave; ++ww) s += sh[ww][t][kk];
+      part[(size_t)(t * kPPLanes + kk) * nblk + vb] = s;
+    }
   }
 }
 
+// Blocks for the products on a level of n rows: one row per thread while
+// that fits in nmax blocks.
+int product_blocks(int n, int r, int nmax) {
+  const int rows = kPPThreads / (r <= 8 ? 8 : 16);
+  return std::max(1, std::min(nmax, ceil_div(n, rows)));
+}
+
 template <class T>
-void pair_products(const Level &L, int r, const T *U, const T *V, int which, double *part,
-                   int nblk, hipStream_t s) {
+int pair_products(const Level &L, int r, const T *U, const T *V, int which, double *part,
+                  int nmax, hipStream_t s) {
   if (r > kPPLanes) fail(BAMG_E_ARG, "r above 16");
-  k_pair_products<T><<<nblk, kPPThreads, 0, s>>>(
-      L.n, r, L.B.rp, L.B.ci, (const T *)L.Bv, L.Bt.rp, L.Bt.ci, (const T *)L.Btv, L.M.rp, L.M.ci,
-      (const T *)L.Mv, (const T *)L.Nv, L.identity_mn ? 1 : 0, U, V, which, part);
+  const int nblk = product_blocks(L.n, r, nmax);
+  if (r <= 8)
+    k_pair_products<T, 8><<<nblk, kPPThreads, 0, s>>>(
+        L.n, r, L.B.rp, L.B.ci, (const T *)L.Bv, L.Bt.rp, L.Bt.ci, (const T *)L.Btv, L.M.rp,
+        L.M.ci, (const T *)L.Mv, (const T *)L.Nv, L.identity_mn ? 1 : 0, U, V, which, part);
+  else
+    k_pair_products<T, 16><<<nblk, kPPThreads, 0, s>>>(
+        L.n, r, L.B.rp, L.B.ci, (const T *)L.Bv, L.Bt.rp, L.Bt.ci, (const T *)L.Btv, L.M.rp,
+        L.M.ci, (const T *)L.Mv, (const T *)L.Nv, L.identity_mn ? 1 : 0, U, V, which, part);
   LAUNCHCHK();
+  return nblk;
 }
 
-// out[t*16 + k] = sum over blocks; one block per output, fixed reduction tree
-__global__ void __launch_bounds__(256) k_finalize_products(const double *__restrict__ part,
-                                                           int nblk, double *__restrict__ out) {
+// out[16 t + k] = sum over the nblk partials, block k per column, fixed
+// reduction tree; then, in the same block, the column's scalar that the
+// products feed (epi 1: sigma_k, Algorithm 1; epi 2: the normalisation
+// scales of v_k and u_k).
+__global__ void __launch_bounds__(256)
+    k_finalize_products(const double *__restrict__ part, int nblk, int which, int epi,
+                        double *__restrict__ out, double *__restrict__ aux) {
   __shared__ double sh[4];
-  const int o = blockIdx.x;  // 0..79
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += 256) s += part[(size_t)b * 5 * kPPLanes + o];
-  s = block_sum<256>(s, sh);
-  if (threadIdx.x == 0) out[o] = s;
+  const int k = blockIdx.x;
+  double q[5] = {0, 0, 0, 0, 0};
+  for (int t = 0; t < 5; ++t) {
+    if (!((t < 3) ? (which & 1) : (which & 2))) continue;
+    const double *p = part + (size_t)(t * kPPLanes + k) * nblk;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) s += p[b];
+    q[t] = block_sum<256>(s, sh);
+    if (threadIdx.x == 0) out[t * kPPLanes + k] = q[t];
+  }
+  if (threadIdx.x != 0) return;
+  if (epi == 1) {
+    const double den = sqrt(q[1] * q[2]);
+    aux[k] = den > 0.0 ? q[0] / den : 0.0;
+  } else if (epi == 2) {
+    aux[k] = q[2] > 0.0 ? 1.0 / sqrt(q[2]) : 1.0;
+    aux[kPPLanes + k] = (k > 0 && q[1] > 0.0) ? 1.0 / sqrt(q[1]) : 1.0;
+  }
 }
 
-void finalize_products(const double *part, int nblk, int r, double *out, hipStream_t s) {
-  (void)r;
-  k_finalize_products<<<5 * kPPLanes, 256, 0, s>>>(part, nblk, out);
-  LAUNCHCHK();
-}
-
-__global__ void k_sigma(const double *__restrict__ q, int r, double *__restrict__ sigma) {
-  const int k = threadIdx.x;
-  if (k >= r) return;
-  const double den = sqrt(q[1 * kPPLanes + k] * q[2 * kPPLanes + k]);
-  sigma[k] = den > 0.0 ? q[k] / den : 0.0;
-}
-void sigma_from_products(const double *prod, int r, double *sigma, hipStream_t s) {
-  k_sigma<<<1, 64, 0, s>>>(prod, r, sigma);
-  LAUNCHCHK();
-}
-
-// scales[k] for V (from v.N v), scales[16 + k] for U (from u.M u, k >= 1)
-__global__ void k_norm_scales(const double *__restrict__ q, int r, double *__restrict__ sc) {
-  const int k = threadIdx.x;
-  if (k >= r) return;
-  const double vv = q[2 * kPPLanes + k], uu = q[1 * kPPLanes + k];
-  sc[k] = vv > 0.0 ? 1.0 / sqrt(vv) : 1.0;
-  sc[kPPLanes + k] = (k > 0 && uu > 0.0) ? 1.0 / sqrt(uu) : 1.0;
-}
-void norm_scales(const double *prod, int r, double *scales, hipStream_t s) {
-  k_norm_scales<<<1, 64, 0, s>>>(prod, r, scales);
+void finalize_products(const double *part, int nblk, int r, int which, int epi, double *out,
+                       double *aux, hipStream_t s) {
+  k_finalize_products<<<r, 256, 0, s>>>(part, nblk, which, epi, out, aux);
   LAUNCHCHK();
 }
 
@@ -1465,7 +1524,7 @@ void row_inv_norms(const Csr &A, const T *val, T *out, hipStream_t s) {
   template void spmm<T>(const Csr &, const T *, int, const T *, T *, int, hipStream_t);      \
   template void relax_pairs<T>(const Level &, int, T, int, const double *, const T *,        \
                                const T *, T *, T *, hipStream_t);                            \
-  template void pair_products<T>(const Level &, int, const T *, const T *, int, double *,    \
+  template int pair_products<T>(const Level &, int, const T *, const T *, int, double *,    \
                                  int, hipStream_t);                                          \
   template void scale_columns<T>(T *, int, int, const double *, int, hipStream_t);           \
   template void row_inv_norms<T>(const Csr &, const T *, T *, hipStream_t);

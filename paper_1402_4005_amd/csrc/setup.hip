@@ -36,9 +36,9 @@ struct Setup {
     std::swap(L.V, L.V2);
   }
 
-  void products(Level &L, int which) {
-    pair_products<T>(L, r, (const T *)L.U, (const T *)L.V, which, part, nblk, s);
-    finalize_products(part, nblk, r, prod, s);
+  void products(Level &L, int which, int epi = 0, double *aux = nullptr) {
+    const int nb = pair_products<T>(L, r, (const T *)L.U, (const T *)L.V, which, part, nblk, s);
+    finalize_products(part, nb, r, which, epi, prod, aux, s);
   }
 
   // nu_setup smoothing steps of Algorithm 1 on the test-vector pairs
@@ -52,10 +52,7 @@ struct Setup {
                        (T *)L.V2, s);
         swap_uv(L);
       }
-      if (with_rhs) {
-        products(L, 1);
-        sigma_from_products(prod, r, h->sigma, s);
-      }
+      if (with_rhs) products(L, 1, 1, h->sigma);
     }
   }
 
@@ -100,8 +97,7 @@ struct Setup {
   void column_set(T *X, int n, int r_, int k, const T *in);
 
   void normalize(Level &L) {
-    products(L, 1);
-    norm_scales(prod, r, scales, s);
+    products(L, 1, 2, scales);
     scale_columns<T>((T *)L.V, L.n, r, scales, 0, s);
     scale_columns<T>((T *)L.U, L.n, r, scales + 16, 1, s);
   }
@@ -472,7 +468,7 @@ void setup_all(bamg_handle *h, const bamg_csr *A, const bamg_geometry *geom) {
   S.h = h;
   S.s = s;
   S.r = r;
-  S.nblk = std::min(kRedBlocks, std::max(1, ceil_div(n, 16 * 16)));
+  S.nblk = kProdBlocks;
   S.part = pool.get<double>((size_t)S.nblk * 5 * 16);
   S.prod = pool.get<double>(5 * 16);
   S.wv = pool.get<double>(16);
