@@ -11,6 +11,32 @@ namespace bamg {
 
 constexpr int kSpThreads = 256;
 
+// A lane's share of a CSR row, sum over k = k0, k0 + LPR, ... < e of
+// val[k] * g(ci[k]), added in that order. Four entries per round: their
+// indices and values are loaded first, then the four gathers, so a short
+// row costs one dependent round trip instead of a chain of them.
+template <class T, int LPR, class G>
+__device__ __forceinline__ T lane_dot(int k0, int e, const int *__restrict__ ci,
+                                      const T *__restrict__ val, G g) {
+  T sum = 0;
+  for (int k = k0; k < e; k += 4 * LPR) {
+    int c[4];
+    T v[4], xv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int kk = k + j * LPR;
+      c[j] = kk < e ? ci[kk] : 0;
+      v[j] = kk < e ? val[kk] : (T)0;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) xv[j] = k + j * LPR < e ? g(c[j]) : (T)0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (k + j * LPR < e) sum += v[j] * xv[j];
+  }
+  return sum;
+}
+
 // y = A x (mode 0), y = b - A x (mode 1), y = y + A x (mode 2)
 template <class T, int LPR>
 __global__ void __launch_bounds__(kSpThreads)
@@ -20,9 +46,7 @@ __global__ void __launch_bounds__(kSpThreads)
   const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * kSpThreads + threadIdx.x;
   const int row = (int)(gid / LPR), lane = (int)(gid % LPR);
   if (row >= nr) return;  // whole groups leave together
-  T sum = 0;
-  const int e = rp[row + 1];
-  for (int k = rp[row] + lane; k < e; k += LPR) sum += val[k] * x[ci[k]];
+  T sum = lane_dot<T, LPR>(rp[row] + lane, rp[row + 1], ci, val, [&](int c) { return x[c]; });
   sum = group_sum(sum, LPR);
   if (lane == 0) {
     if (mode == 0)
@@ -47,9 +71,8 @@ __global__ void __launch_bounds__(kSpThreads)
     if (lane == 0) xout[row] = omega * dinv[row] * b[row];
     return;
   }
-  T sum = 0;
-  const int e = rp[row + 1];
-  for (int k = rp[row] + lane; k < e; k += LPR) sum += val[k] * xin[ci[k]];
+  T sum =
+      lane_dot<T, LPR>(rp[row] + lane, rp[row + 1], ci, val, [&](int c) { return xin[c]; });
   sum = group_sum(sum, LPR);
   if (lane == 0) xout[row] = xin[row] + omega * dinv[row] * (b[row] - sum);
 }
@@ -66,12 +89,8 @@ __global__ void __launch_bounds__(kSpThreads)
   const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * kSpThreads + threadIdx.x;
   const int row = (int)(gid / LPR), lane = (int)(gid % LPR);
   if (row >= nr) return;
-  T sum = 0;
-  const int e = rp[row + 1];
-  for (int k = rp[row] + lane; k < e; k += LPR) {
-    const int c = ci[k];
-    sum += val[k] * (omega * dinv[c] * b[c]);
-  }
+  T sum = lane_dot<T, LPR>(rp[row] + lane, rp[row + 1], ci, val,
+                           [&](int c) { return omega * dinv[c] * b[c]; });
   sum = group_sum(sum, LPR);
   if (lane == 0) {
     const T x1 = omega * dinv[row] * b[row];
