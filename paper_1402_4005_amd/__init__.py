@@ -9,8 +9,10 @@ CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -166,6 +168,48 @@ def _stream(stream):
     return C.c_void_p(s.cuda_stream)
 
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("alloc", _ALLOC_FN), ("free", _FREE_FN)]
+
+
+def _torch_alloc(ctx, nbytes, stream):
+    try:
+        return _torch()._C._cuda_cudaCachingAllocator_raw_alloc(nbytes, stream or 0)
+    except RuntimeError:
+        return None  # the library reports BAMG_E_NOMEM
+
+
+def _torch_free(ctx, ptr, stream):
+    _torch()._C._cuda_cudaCachingAllocator_raw_delete(ptr)
+
+
+_TORCH_ALLOCATOR = Allocator(None, _ALLOC_FN(_torch_alloc), _FREE_FN(_torch_free))
+_LIVE = weakref.WeakSet()  # hierarchies whose memory may come from torch
+
+
+@atexit.register
+def _close_live():
+    # before torch's own teardown: a handle freed later would call into it
+    for h in list(_LIVE):
+        h.close()
+
+
+def _allocator(kind):
+    """bamg_allocator for `kind`: "torch" = torch's caching allocator (blocks
+    are stream-ordered on the handle's stream and reused by later handles
+    without a device synchronisation), "hip" = the library's own
+    hipMalloc / hipFree."""
+    if kind == "torch":
+        return C.byref(_TORCH_ALLOCATOR)
+    if kind == "hip":
+        return None
+    raise ValueError(f"allocator {kind!r}: 'torch' or 'hip'")
+
+
 class Hierarchy:
     """A BAMG hierarchy set up on the GPU (wraps ``bamg_handle``).
 
@@ -175,7 +219,7 @@ class Hierarchy:
     """
 
     def __init__(self, indptr, indices, data, geom=(0, 0, 0), opts: Options | None = None,
-                 stream=None):
+                 stream=None, allocator="torch"):
         torch = _torch()
         self.opts = opts if opts is not None else default_options()
         on_dev = isinstance(indptr, torch.Tensor)
@@ -197,18 +241,20 @@ class Hierarchy:
         g = Geometry(*geom)
         h = C.c_void_p()
         self._stream = _stream(stream)
-        _check(lib().bamg_setup(C.byref(A), C.byref(g), C.byref(self.opts), None, self._stream,
-                                C.byref(h)))
+        _check(lib().bamg_setup(C.byref(A), C.byref(g), C.byref(self.opts),
+                                _allocator(allocator), self._stream, C.byref(h)))
         self.h = h
+        _LIVE.add(self)
         self.mixed = self.opts.precision == PRECISION_MIXED
 
     @classmethod
-    def from_chain(cls, chain, opts: Options | None = None, on_device=False, stream=None):
+    def from_chain(cls, chain, opts: Options | None = None, on_device=False, stream=None,
+                   allocator="torch"):
         if on_device:
             torch = _torch()
             return cls(torch.from_numpy(chain.indptr).cuda(), torch.from_numpy(chain.indices).cuda(),
-                       torch.from_numpy(chain.data).cuda(), chain.geom, opts, stream)
-        return cls(chain.indptr, chain.indices, chain.data, chain.geom, opts, stream)
+                       torch.from_numpy(chain.data).cuda(), chain.geom, opts, stream, allocator)
+        return cls(chain.indptr, chain.indices, chain.data, chain.geom, opts, stream, allocator)
 
     def close(self):
         if getattr(self, "h", None):
