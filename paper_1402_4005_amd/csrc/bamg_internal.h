@@ -228,7 +228,8 @@ void row_inv_norms(const Csr &A, const T *val, T *out, hipStream_t s);
 
 // ---- launchers: coarsest level dense algebra (k_dense.hip)
 void csr_to_dense(const Csr &A, const void *val, int prec, double *D, hipStream_t s);
-int cholesky(double *A, int n, hipStream_t s);            // in place, lower, row-major
+// A0 = L L^T and A1 = L L^T (A1 may be null) in place, lower, row-major
+int cholesky2(double *A0, double *A1, int n, int *flag, hipStream_t s);
 void trsm_lower_cols(const double *L, double *X, int n, int ncols, int ldx,
                      hipStream_t s);  // X <- L^-1 X, column by column
 void transpose_dense(const double *A, double *At, int n, hipStream_t s);

@@ -39,38 +39,61 @@ void csr_to_dense(const Csr &A, const void *val, int prec, double *D, hipStream_
   LAUNCHCHK();
 }
 
-// Right-looking Cholesky in one workgroup, in place (lower triangle,
-// row-major); the strict upper triangle is zeroed. flag = 1 if not SPD.
-__global__ void __launch_bounds__(1024) k_cholesky(double *__restrict__ A, int n,
-                                                   int *__restrict__ flag) {
-  __shared__ double piv;
+// Cholesky factorisations A = L L^T in place (lower triangle, row-major;
+// the strict upper triangle is zeroed), one workgroup per matrix (blockIdx
+// 0: A0, 1: A1). Right-looking by panels of nb columns: the panel (rows
+// j0.., nb columns) is factored in LDS, written back, and the trailing lower
+// triangle is updated with the panel's columns. Every entry receives the
+// same updates in the same order as the column-by-column algorithm
+// (a -= l_ij l_kj for j ascending), so the factor equals it bit for bit.
+// flag[0] = 1 if a pivot is not positive (not SPD).
+__global__ void __launch_bounds__(1024) k_cholesky(double *__restrict__ A0, double *__restrict__ A1,
+                                                   int n, int nbmax, int *__restrict__ flag) {
+  extern __shared__ double pan[];  // (n - j0) x nb, row-major with stride nbmax
+  double *__restrict__ A = blockIdx.x == 0 ? A0 : A1;
   const int t = threadIdx.x, nt = blockDim.x;
-  for (int j = 0; j < n; ++j) {
-    if (t == 0) {
-      const double d = A[(size_t)j * n + j];
-      if (!(d > 0.0)) {
-        *flag = 1;
-        piv = 1.0;
-      } else {
-        piv = sqrt(d);
-      }
-      A[(size_t)j * n + j] = piv;
+  for (int j0 = 0; j0 < n; j0 += nbmax) {
+    const int nb = min(nbmax, n - j0), m = n - j0;
+    for (int e = t; e < m * nb; e += nt) {
+      const int i = e / nb, c = e % nb;
+      pan[i * nbmax + c] = A[(size_t)(j0 + i) * n + j0 + c];
     }
     __syncthreads();
-    const double inv = 1.0 / piv;
-    for (int i = j + 1 + t; i < n; i += nt) A[(size_t)i * n + j] *= inv;
-    __syncthreads();
-    // trailing update of the lower triangle: rows i > j, columns j < k <= i
-    const int m = n - j - 1;
-    const long tot = (long)m * (m + 1) / 2;
-    for (long e = t; e < tot; e += nt) {
-      // e -> (ii, kk) with 0 <= kk <= ii < m, row-wise enumeration
-      int ii = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
-      while ((long)ii * (ii + 1) / 2 > e) --ii;
-      while ((long)(ii + 1) * (ii + 2) / 2 <= e) ++ii;
-      const int kk = (int)(e - (long)ii * (ii + 1) / 2);
-      const int i = j + 1 + ii, k = j + 1 + kk;
-      A[(size_t)i * n + k] -= A[(size_t)i * n + j] * A[(size_t)k * n + j];
+    for (int c = 0; c < nb; ++c) {
+      if (t == 0) {
+        const double d = pan[c * nbmax + c];
+        if (!(d > 0.0)) {
+          flag[0] = 1;
+          pan[c * nbmax + c] = 1.0;
+        } else {
+          pan[c * nbmax + c] = sqrt(d);
+        }
+      }
+      __syncthreads();
+      const double inv = 1.0 / pan[c * nbmax + c];
+      for (int i = c + 1 + t; i < m; i += nt) pan[i * nbmax + c] *= inv;
+      __syncthreads();
+      // remaining panel columns cc > c, rows i >= cc
+      const int w = nb - c - 1;
+      for (int e = t; e < (m - c - 1) * w; e += nt) {
+        const int i = c + 1 + e / w, cc = c + 1 + e % w;
+        if (cc <= i) pan[i * nbmax + cc] -= pan[i * nbmax + c] * pan[cc * nbmax + c];
+      }
+      __syncthreads();
+    }
+    for (int e = t; e < m * nb; e += nt) {
+      const int i = e / nb, c = e % nb;
+      A[(size_t)(j0 + i) * n + j0 + c] = pan[i * nbmax + c];
+    }
+    // trailing lower triangle: rows i, columns k with j0 + nb <= k <= i
+    const int mt = m - nb;
+    for (long e = t; e < (long)mt * mt; e += nt) {
+      const int ii = (int)(e / mt), kk = (int)(e % mt);
+      if (kk > ii) continue;
+      const double *li = pan + (size_t)(nb + ii) * nbmax, *lk = pan + (size_t)(nb + kk) * nbmax;
+      double a = A[(size_t)(j0 + nb + ii) * n + j0 + nb + kk];
+      for (int c = 0; c < nb; ++c) a -= li[c] * lk[c];
+      A[(size_t)(j0 + nb + ii) * n + j0 + nb + kk] = a;
     }
     __syncthreads();
   }
@@ -80,15 +103,22 @@ __global__ void __launch_bounds__(1024) k_cholesky(double *__restrict__ A, int n
   }
 }
 
-int cholesky(double *A, int n, hipStream_t s) {
-  int *flag;
-  HIPCHK(hipMalloc(&flag, sizeof(int)));
+// Factor A0 and (when not null) A1, both n x n; flag is a device int the
+// caller owns. Returns BAMG_E_COARSE if either is not positive definite.
+int cholesky2(double *A0, double *A1, int n, int *flag, hipStream_t s) {
+  int dev = 0, maxlds = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  int nb = 32;
+  while (nb > 1 && sizeof(double) * (size_t)n * nb > (size_t)maxlds) nb >>= 1;
+  const size_t shm = sizeof(double) * (size_t)n * nb;
+  if (shm > (size_t)maxlds) fail(BAMG_E_ARG, "cholesky: matrix too large for an LDS panel");
+  HIPCHK(hipFuncSetAttribute((const void *)k_cholesky, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)shm));
   fill_i32(flag, 0, 1, s);
-  k_cholesky<<<1, 1024, 0, s>>>(A, n, flag);
+  k_cholesky<<<A1 ? 2 : 1, 1024, shm, s>>>(A0, A1, n, nb, flag);
   LAUNCHCHK();
-  const int f = read_int(flag, s);
-  HIPCHK(hipFree(flag));
-  return f ? BAMG_E_COARSE : BAMG_OK;
+  return read_int(flag, s) ? BAMG_E_COARSE : BAMG_OK;
 }
 
 // Forward substitution L Y = X for the columns of X (n x ncols, row-major,
@@ -353,19 +383,19 @@ void column_norms(const double *W, int n, double *sv, hipStream_t s) {
 }
 
 // The r smallest singular values in ascending order (ties: lower index).
+// Thread per value: its rank among all n is the count of smaller values
+// plus equal ones at lower index; ranks below r give the order.
 __global__ void k_select_smallest(const double *__restrict__ sv, int n, int r,
                                   int *__restrict__ order) {
-  if (threadIdx.x != 0) return;
-  for (int t = 0; t < r; ++t) {
-    int best = -1;
-    for (int k = 0; k < n; ++k) {
-      bool taken = false;
-      for (int q = 0; q < t; ++q) taken |= (order[q] == k);
-      if (taken) continue;
-      if (best < 0 || sv[k] < sv[best]) best = k;
-    }
-    order[t] = best;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double v = sv[k];
+  int rank = 0;
+  for (int j = 0; j < n; ++j) {
+    const double u = sv[j];
+    rank += (u < v || (u == v && j < k)) ? 1 : 0;
   }
+  if (rank < r) order[rank] = k;
 }
 
 // One block per requested triplet t: x = L^-T (column of W / sigma or of J),
@@ -419,7 +449,7 @@ void coarse_triplets_out(const double *LM, const double *LN, const double *W, co
                          const double *sv, int n, int r, void *U, void *V, int prec,
                          double *sigma, double *work, hipStream_t s) {
   int *order = reinterpret_cast<int *>(work);
-  k_select_smallest<<<1, 64, 0, s>>>(sv, n, r, order);
+  k_select_smallest<<<ceil_div(n, 256), 256, 0, s>>>(sv, n, r, order);
   LAUNCHCHK();
   const size_t shm = sizeof(double) * 2 * (size_t)n;
   if (prec == 0)

@@ -840,140 +840,217 @@ void spgemm_numeric(const Csr &A, const T *av, const Csr &B, const T *bv, const 
 // arrays in registers; the large one (16, 8) covers the remaining options.
 constexpr int kRMax = 16, kMMax = 8;
 
-// Householder least squares on the columns listed in idx[0..na): minimise
-// || G[:, idx] p - g || over rows [row0, rows). A column whose |R_tt| falls
-// to 1e-12 max|R_ss| or below is removed from idx and the fit redone.
-// Returns the number of columns kept; p[t] for t < na afterwards.
-template <int RM, int MM>
-__device__ int ls_qr(double (&G)[RM][MM], const double (&g)[RM], int row0, int rows,
-                     int (&idx)[MM], int na, double (&p)[MM]) {
+// Every array below is indexed only by loop counters of fully unrolled
+// loops over the compile-time bounds RM, MM (rows and points beyond the
+// live counts are masked off), so the compiler keeps the arrays in
+// registers. Point sets are bitmasks over the MM positions; a column's
+// place in the factorisation is its rank among the set bits.
+
+// Householder least squares over the point set `mask`: minimise
+// || W[:, mask] p - h || over rows [0, nrow), W and h produced by
+// build(W, h) (rows >= nrow zero). Columns enter in increasing position;
+// column t eliminates at pivot row rank(t). Only the first nrow columns can
+// be determined (the rest are dropped), and a column whose |R_tt| falls to
+// 1e-12 max |R_ss| or below is dropped; after a drop the fit is redone from
+// build(). Returns the set kept, with p[t] for its positions.
+template <int RM, int MM, class Build>
+__device__ unsigned ls_qr(Build build, int nrow, unsigned mask, double (&p)[MM]) {
   for (;;) {
-    if (na == 0) return 0;
+    if (mask == 0) return 0;
     double W[RM][MM], h[RM], R[MM];
-    const int nrow = rows - row0;
-    for (int k = 0; k < nrow; ++k) {
-      for (int a = 0; a < na; ++a) W[k][a] = G[row0 + k][idx[a]];
-      h[k] = g[row0 + k];
-    }
-    const int nq = na < nrow ? na : nrow;
-    for (int a = 0; a < nq; ++a) {
-      double nrm = 0.0;
-      for (int k = a; k < nrow; ++k) nrm += W[k][a] * W[k][a];
+    build(W, h);
+    const int na = __popc(mask);
+    int a = 0;  // pivot row of the next column
+#pragma unroll
+    for (int t = 0; t < MM; ++t) {
+      R[t] = 0.0;
+      if (!((mask >> t) & 1u) || a >= nrow) continue;
+      double nrm = 0.0, x0 = 0.0;
+#pragma unroll
+      for (int k = 0; k < RM; ++k)
+        if (k >= a && k < nrow) nrm += W[k][t] * W[k][t];
       nrm = sqrt(nrm);
-      const double x0 = W[a][a];
+#pragma unroll
+      for (int k = 0; k < RM; ++k)
+        if (k == a) x0 = W[k][t];
       const double alpha = x0 >= 0 ? -nrm : nrm;
-      R[a] = alpha;
-      if (nrm == 0.0) continue;
-      W[a][a] = x0 - alpha;
-      double vtv = 0.0;
-      for (int k = a; k < nrow; ++k) vtv += W[k][a] * W[k][a];
-      if (vtv == 0.0) continue;
-      for (int b = a + 1; b < na; ++b) {
-        double s = 0.0;
-        for (int k = a; k < nrow; ++k) s += W[k][a] * W[k][b];
-        s = 2.0 * s / vtv;
-        for (int k = a; k < nrow; ++k) W[k][b] -= s * W[k][a];
+      R[t] = alpha;
+      if (nrm != 0.0) {
+#pragma unroll
+        for (int k = 0; k < RM; ++k)
+          if (k == a) W[k][t] = x0 - alpha;
+        double vtv = 0.0;
+#pragma unroll
+        for (int k = 0; k < RM; ++k)
+          if (k >= a && k < nrow) vtv += W[k][t] * W[k][t];
+        if (vtv != 0.0) {
+#pragma unroll
+          for (int b = t + 1; b < MM; ++b) {
+            if (!((mask >> b) & 1u)) continue;
+            double sb = 0.0;
+#pragma unroll
+            for (int k = 0; k < RM; ++k)
+              if (k >= a && k < nrow) sb += W[k][t] * W[k][b];
+            sb = 2.0 * sb / vtv;
+#pragma unroll
+            for (int k = 0; k < RM; ++k)
+              if (k >= a && k < nrow) W[k][b] -= sb * W[k][t];
+          }
+          double sh = 0.0;
+#pragma unroll
+          for (int k = 0; k < RM; ++k)
+            if (k >= a && k < nrow) sh += W[k][t] * h[k];
+          sh = 2.0 * sh / vtv;
+#pragma unroll
+          for (int k = 0; k < RM; ++k)
+            if (k >= a && k < nrow) h[k] -= sh * W[k][t];
+        }
       }
-      double s = 0.0;
-      for (int k = a; k < nrow; ++k) s += W[k][a] * h[k];
-      s = 2.0 * s / vtv;
-      for (int k = a; k < nrow; ++k) h[k] -= s * W[k][a];
+      ++a;
     }
-    // columns beyond the number of rows cannot be determined: drop them
     if (na > nrow) {
-      na = nrow;
+      // keep the first nrow columns
+      unsigned keep = 0;
+      int cnt = 0;
+#pragma unroll
+      for (int t = 0; t < MM; ++t)
+        if ((mask >> t) & 1u) {
+          if (cnt < nrow) keep |= 1u << t;
+          ++cnt;
+        }
+      mask = keep;
       continue;
     }
     double rmax = 0.0;
-    for (int a = 0; a < na; ++a) rmax = fmax(rmax, fabs(R[a]));
+#pragma unroll
+    for (int t = 0; t < MM; ++t)
+      if ((mask >> t) & 1u) rmax = fmax(rmax, fabs(R[t]));
     int drop = -1;
-    for (int a = 0; a < na; ++a)
-      if (!(fabs(R[a]) > 1e-12 * rmax)) {
-        drop = a;
-        break;
-      }
+#pragma unroll
+    for (int t = 0; t < MM; ++t)
+      if (drop < 0 && ((mask >> t) & 1u) && !(fabs(R[t]) > 1e-12 * rmax)) drop = t;
     if (drop >= 0) {
-      for (int a = drop; a + 1 < na; ++a) idx[a] = idx[a + 1];
-      --na;
+      mask &= ~(1u << drop);
       continue;
     }
-    for (int a = na - 1; a >= 0; --a) {
-      double s = h[a];
-      for (int b = a + 1; b < na; ++b) s -= W[a][b] * p[b];
-      p[a] = s / R[a];
+    // back substitution, last column first; column t's pivot row is rank(t)
+#pragma unroll
+    for (int t = MM - 1; t >= 0; --t) {
+      if (!((mask >> t) & 1u)) continue;
+      const int at = __popc(mask & ((1u << t) - 1u));
+      double sum = 0.0;
+#pragma unroll
+      for (int k = 0; k < RM; ++k)
+        if (k == at) sum = h[k];
+#pragma unroll
+      for (int b = t + 1; b < MM; ++b) {
+        if (!((mask >> b) & 1u)) continue;
+        double wab = 0.0;
+#pragma unroll
+        for (int k = 0; k < RM; ++k)
+          if (k == at) wab = W[k][b];
+        sum -= wab * p[b];
+      }
+      p[t] = sum / R[t];
     }
-    return na;
+    return mask;
   }
 }
 
-// One weighted fit over the active points act[]: plain (sum1 = false, rows
-// k = 0..r-1) or with sum-to-one (rows k = 1..r-1, last active point
-// eliminated). Writes coef[0..m) (0 for inactive points).
+// One weighted fit over the point set act (bits < m): plain (sum1 = false,
+// rows k = 0..r-1) or with sum-to-one (rows k = 1..r-1, the highest active
+// point eliminated). Writes coef[0..MM) (0 for points outside the set).
 template <int RM, int MM>
 __device__ void fit_active(const double (&Gr)[RM][MM], const double (&gr)[RM],
-                           const double *__restrict__ w, int r, int m, bool sum1,
-                           const bool (&act)[MM], double (&coef)[MM]) {
-  int ids[MM];
-  int na = 0;
-  for (int t = 0; t < m; ++t) {
+                           const double *__restrict__ w, int r, bool sum1, unsigned act,
+                           double (&coef)[MM]) {
+  double p[MM];
+#pragma unroll
+  for (int t = 0; t < MM; ++t) {
     coef[t] = 0.0;
-    if (act[t]) ids[na++] = t;
+    p[t] = 0.0;
   }
-  if (na == 0) return;
-  double G[RM][MM], g[RM], p[MM];
+  if (act == 0) return;
   if (!sum1) {
-    for (int k = 0; k < r; ++k) {
-      const double sw = sqrt(w[k]);
-      for (int a = 0; a < na; ++a) G[k][a] = sw * Gr[k][ids[a]];
-      g[k] = sw * gr[k];
+    auto build = [&](double (&W)[RM][MM], double (&h)[RM]) {
+#pragma unroll
+      for (int k = 0; k < RM; ++k) {
+        const double sw = k < r ? sqrt(w[k]) : 0.0;
+#pragma unroll
+        for (int t = 0; t < MM; ++t) W[k][t] = sw * Gr[k][t];
+        h[k] = sw * gr[k];
+      }
+    };
+    const unsigned kept = ls_qr<RM, MM>(build, r, act, p);
+#pragma unroll
+    for (int t = 0; t < MM; ++t)
+      if ((kept >> t) & 1u) coef[t] = p[t];
+    return;
+  }
+  const int last = 31 - __clz(act);
+  if (act == (1u << last)) {
+    coef[last] = 1.0;
+    return;
+  }
+  double glast[RM];
+#pragma unroll
+  for (int k = 0; k < RM; ++k) {
+    glast[k] = 0.0;
+#pragma unroll
+    for (int t = 0; t < MM; ++t)
+      if (t == last) glast[k] = Gr[k][t];
+  }
+  // row k' of the fit is row k' + 1 of the test vectors
+  auto build = [&](double (&W)[RM][MM], double (&h)[RM]) {
+#pragma unroll
+    for (int kk = 0; kk < RM; ++kk) {
+      const int k = kk + 1;
+      if (k < RM && k < r) {
+        const double sw = sqrt(w[k]);
+        const double lv = glast[k < RM ? k : 0];
+#pragma unroll
+        for (int t = 0; t < MM; ++t) W[kk][t] = sw * (Gr[k < RM ? k : 0][t] - lv);
+        h[kk] = sw * (gr[k < RM ? k : 0] - lv);
+      } else {
+#pragma unroll
+        for (int t = 0; t < MM; ++t) W[kk][t] = 0.0;
+        h[kk] = 0.0;
+      }
     }
-    int cols[MM];
-    for (int a = 0; a < na; ++a) cols[a] = a;
-    const int kept = ls_qr<RM, MM>(G, g, 0, r, cols, na, p);
-    for (int a = 0; a < kept; ++a) coef[ids[cols[a]]] = p[a];
-    return;
-  }
-  if (na == 1) {
-    coef[ids[0]] = 1.0;
-    return;
-  }
-  const int last = ids[na - 1], mm = na - 1;
-  for (int k = 1; k < r; ++k) {
-    const double sw = sqrt(w[k]);
-    const double lv = Gr[k][last];
-    for (int a = 0; a < mm; ++a) G[k][a] = sw * (Gr[k][ids[a]] - lv);
-    g[k] = sw * (gr[k] - lv);
-  }
-  int cols[MM];
-  for (int a = 0; a < mm; ++a) cols[a] = a;
-  for (int a = 0; a < mm; ++a) p[a] = 0.0;
-  const int kept = ls_qr<RM, MM>(G, g, 1, r, cols, mm, p);
+  };
+  const unsigned kept = ls_qr<RM, MM>(build, r - 1, act & ~(1u << last), p);
   double sum = 0.0;
-  for (int a = 0; a < kept; ++a) {
-    coef[ids[cols[a]]] = p[a];
-    sum += p[a];
-  }
-  coef[last] = 1.0 - sum;
+#pragma unroll
+  for (int t = 0; t < MM; ++t)
+    if ((kept >> t) & 1u) {
+      coef[t] = p[t];
+      sum += p[t];
+    }
+#pragma unroll
+  for (int t = 0; t < MM; ++t)
+    if (t == last) coef[t] = 1.0 - sum;
 }
 
-// rule 1: while a weight is negative, remove the most negative point and
-// refit (at least one point stays).
+// rule 1: while a weight is negative, remove the most negative point (the
+// lowest position among equals) and refit (at least one point stays).
 template <int RM, int MM>
 __device__ void fit_point(const double (&G)[RM][MM], const double (&g)[RM],
                           const double *__restrict__ w, int r, int m, bool sum1, int rule,
                           double (&coef)[MM]) {
-  bool act[MM];
-  for (int t = 0; t < MM; ++t) act[t] = t < m;
-  int na = m;
+  unsigned act = (m >= 32) ? ~0u : ((1u << m) - 1u);
   for (;;) {
-    fit_active<RM, MM>(G, g, w, r, m, sum1, act, coef);
-    if (rule == 0 || na == 1) return;
+    fit_active<RM, MM>(G, g, w, r, sum1, act, coef);
+    if (rule == 0 || __popc(act) == 1) return;
     int worst = -1;
-    for (int t = 0; t < m; ++t)
-      if (act[t] && coef[t] < 0.0 && (worst < 0 || coef[t] < coef[worst])) worst = t;
+    double cw = 0.0;
+#pragma unroll
+    for (int t = 0; t < MM; ++t)
+      if (((act >> t) & 1u) && coef[t] < 0.0 && (worst < 0 || coef[t] < cw)) {
+        worst = t;
+        cw = coef[t];
+      }
     if (worst < 0) return;
-    act[worst] = false;
-    --na;
+    act &= ~(1u << worst);
   }
 }
 
@@ -993,20 +1070,29 @@ __global__ void __launch_bounds__(64)
   }
   const int m = prp[i + 1] - a0;
   int jf[MM];
-  for (int t = 0; t < m; ++t) jf[t] = cpts[pci[a0 + t]];
+#pragma unroll
+  for (int t = 0; t < MM; ++t) jf[t] = t < m ? cpts[pci[a0 + t]] : 0;
   double G[RM][MM], g[RM], coef[MM];
-  for (int k = 0; k < r; ++k) {
-    for (int t = 0; t < m; ++t) G[k][t] = (double)V[(size_t)jf[t] * r + k];
-    g[k] = (double)V[(size_t)i * r + k];
+#pragma unroll
+  for (int k = 0; k < RM; ++k) {
+#pragma unroll
+    for (int t = 0; t < MM; ++t) G[k][t] = (k < r && t < m) ? (double)V[(size_t)jf[t] * r + k] : 0.0;
+    g[k] = k < r ? (double)V[(size_t)i * r + k] : 0.0;
   }
   fit_point<RM, MM>(G, g, wv, r, m, false, rule, coef);
-  for (int t = 0; t < m; ++t) Pv[a0 + t] = (T)coef[t];
-  for (int k = 0; k < r; ++k) {
-    for (int t = 0; t < m; ++t) G[k][t] = (double)U[(size_t)jf[t] * r + k];
-    g[k] = (double)U[(size_t)i * r + k];
+#pragma unroll
+  for (int t = 0; t < MM; ++t)
+    if (t < m) Pv[a0 + t] = (T)coef[t];
+#pragma unroll
+  for (int k = 0; k < RM; ++k) {
+#pragma unroll
+    for (int t = 0; t < MM; ++t) G[k][t] = (k < r && t < m) ? (double)U[(size_t)jf[t] * r + k] : 0.0;
+    g[k] = k < r ? (double)U[(size_t)i * r + k] : 0.0;
   }
   fit_point<RM, MM>(G, g, wu, r, m, true, rule, coef);
-  for (int t = 0; t < m; ++t) Qtv[a0 + t] = (T)coef[t];
+#pragma unroll
+  for (int t = 0; t < MM; ++t)
+    if (t < m) Qtv[a0 + t] = (T)coef[t];
 }
 
 template <class T>

@@ -223,7 +223,7 @@ struct Setup {
       return;
     }
     if (last) transpose_dense(Bd, W2, n, s);  // B_L column-major, for its own SVD
-    if (cholesky(Md, n, s) != BAMG_OK || cholesky(Nd, n, s) != BAMG_OK)
+    if (cholesky2(Md, Nd, n, flag, s) != BAMG_OK)
       fail(BAMG_E_COARSE, "coarsest M_L or N_L not positive definite");
     HIPCHK(hipMemcpyAsync(X, Bd, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToDevice, s));
     trsm_lower_cols(Md, X, n, n, n, s);  // X = L_M^-1 B
