@@ -49,48 +49,49 @@ void csr_to_dense(const Csr &A, const void *val, int prec, double *D, hipStream_
 // flag[0] = 1 if a pivot is not positive (not SPD).
 __global__ void __launch_bounds__(1024) k_cholesky(double *__restrict__ A0, double *__restrict__ A1,
                                                    int n, int nbmax, int *__restrict__ flag) {
-  extern __shared__ double pan[];  // (n - j0) x nb, row-major with stride nbmax
+  extern __shared__ double pan[];  // (n - j0) x nb, row-major, stride nbmax + 1 (odd: no
+                                   // bank conflicts down a column)
   double *__restrict__ A = blockIdx.x == 0 ? A0 : A1;
-  const int t = threadIdx.x, nt = blockDim.x;
+  const int t = threadIdx.x, nt = blockDim.x, ld = nbmax + 1;
   for (int j0 = 0; j0 < n; j0 += nbmax) {
     const int nb = min(nbmax, n - j0), m = n - j0;
     for (int e = t; e < m * nb; e += nt) {
       const int i = e / nb, c = e % nb;
-      pan[i * nbmax + c] = A[(size_t)(j0 + i) * n + j0 + c];
+      pan[i * ld + c] = A[(size_t)(j0 + i) * n + j0 + c];
     }
     __syncthreads();
     for (int c = 0; c < nb; ++c) {
       if (t == 0) {
-        const double d = pan[c * nbmax + c];
+        const double d = pan[c * ld + c];
         if (!(d > 0.0)) {
           flag[0] = 1;
-          pan[c * nbmax + c] = 1.0;
+          pan[c * ld + c] = 1.0;
         } else {
-          pan[c * nbmax + c] = sqrt(d);
+          pan[c * ld + c] = sqrt(d);
         }
       }
       __syncthreads();
-      const double inv = 1.0 / pan[c * nbmax + c];
-      for (int i = c + 1 + t; i < m; i += nt) pan[i * nbmax + c] *= inv;
+      const double inv = 1.0 / pan[c * ld + c];
+      for (int i = c + 1 + t; i < m; i += nt) pan[i * ld + c] *= inv;
       __syncthreads();
       // remaining panel columns cc > c, rows i >= cc
       const int w = nb - c - 1;
       for (int e = t; e < (m - c - 1) * w; e += nt) {
         const int i = c + 1 + e / w, cc = c + 1 + e % w;
-        if (cc <= i) pan[i * nbmax + cc] -= pan[i * nbmax + c] * pan[cc * nbmax + c];
+        if (cc <= i) pan[i * ld + cc] -= pan[i * ld + c] * pan[cc * ld + c];
       }
       __syncthreads();
     }
     for (int e = t; e < m * nb; e += nt) {
       const int i = e / nb, c = e % nb;
-      A[(size_t)(j0 + i) * n + j0 + c] = pan[i * nbmax + c];
+      A[(size_t)(j0 + i) * n + j0 + c] = pan[i * ld + c];
     }
     // trailing lower triangle: rows i, columns k with j0 + nb <= k <= i
     const int mt = m - nb;
     for (long e = t; e < (long)mt * mt; e += nt) {
       const int ii = (int)(e / mt), kk = (int)(e % mt);
       if (kk > ii) continue;
-      const double *li = pan + (size_t)(nb + ii) * nbmax, *lk = pan + (size_t)(nb + kk) * nbmax;
+      const double *li = pan + (size_t)(nb + ii) * ld, *lk = pan + (size_t)(nb + kk) * ld;
       double a = A[(size_t)(j0 + nb + ii) * n + j0 + nb + kk];
       for (int c = 0; c < nb; ++c) a -= li[c] * lk[c];
       A[(size_t)(j0 + nb + ii) * n + j0 + nb + kk] = a;
@@ -110,8 +111,8 @@ int cholesky2(double *A0, double *A1, int n, int *flag, hipStream_t s) {
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   int nb = 32;
-  while (nb > 1 && sizeof(double) * (size_t)n * nb > (size_t)maxlds) nb >>= 1;
-  const size_t shm = sizeof(double) * (size_t)n * nb;
+  while (nb > 1 && sizeof(double) * (size_t)n * (nb + 1) > (size_t)maxlds) nb >>= 1;
+  const size_t shm = sizeof(double) * (size_t)n * (nb + 1);
   if (shm > (size_t)maxlds) fail(BAMG_E_ARG, "cholesky: matrix too large for an LDS panel");
   HIPCHK(hipFuncSetAttribute((const void *)k_cholesky, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)shm));
