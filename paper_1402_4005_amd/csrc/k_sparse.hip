@@ -12,26 +12,31 @@ namespace bamg {
 constexpr int kSpThreads = 256;
 
 // A lane's share of a CSR row, sum over k = k0, k0 + LPR, ... < e of
-// val[k] * g(ci[k]), added in that order. Four entries per round: their
+// val[k] * g(ci[k]), added in that order. U = 4 entries per round: their
 // indices and values are loaded first, then the four gathers, so a short
-// row costs one dependent round trip instead of a chain of them.
+// row costs one dependent round trip instead of a chain of them (8 per
+// round raises the register count past what full occupancy allows, and is
+// slower). Positions past the row end load the row's last entry again (no
+// branches around the loads, so all of them are in flight together) and
+// are not added.
 template <class T, int LPR, class G>
 __device__ __forceinline__ T lane_dot(int k0, int e, const int *__restrict__ ci,
                                       const T *__restrict__ val, G g) {
+  constexpr int U = 4;
   T sum = 0;
-  for (int k = k0; k < e; k += 4 * LPR) {
-    int c[4];
-    T v[4], xv[4];
+  for (int k = k0; k < e; k += U * LPR) {
+    int c[U];
+    T v[U], xv[U];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int kk = k + j * LPR;
-      c[j] = kk < e ? ci[kk] : 0;
-      v[j] = kk < e ? val[kk] : (T)0;
+    for (int j = 0; j < U; ++j) {
+      const int kk = min(k + j * LPR, e - 1);
+      c[j] = ci[kk];
+      v[j] = val[kk];
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) xv[j] = k + j * LPR < e ? g(c[j]) : (T)0;
+    for (int j = 0; j < U; ++j) xv[j] = g(c[j]);
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < U; ++j)
       if (k + j * LPR < e) sum += v[j] * xv[j];
   }
   return sum;
@@ -46,15 +51,18 @@ __global__ void __launch_bounds__(kSpThreads)
   const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * kSpThreads + threadIdx.x;
   const int row = (int)(gid / LPR), lane = (int)(gid % LPR);
   if (row >= nr) return;  // whole groups leave together
+  // row-wise operands are loaded first, beside the row pointers, so their
+  // latency overlaps the row's gathers instead of following the reduction
+  const T br = mode == 1 ? b[row] : mode == 2 ? y[row] : (T)0;
   T sum = lane_dot<T, LPR>(rp[row] + lane, rp[row + 1], ci, val, [&](int c) { return x[c]; });
   sum = group_sum(sum, LPR);
   if (lane == 0) {
     if (mode == 0)
       y[row] = sum;
     else if (mode == 1)
-      y[row] = b[row] - sum;
+      y[row] = br - sum;
     else
-      y[row] += sum;
+      y[row] = br + sum;
   }
 }
 
@@ -71,10 +79,11 @@ __global__ void __launch_bounds__(kSpThreads)
     if (lane == 0) xout[row] = omega * dinv[row] * b[row];
     return;
   }
+  const T xr = xin[row], dr = dinv[row], br = b[row];  // issued beside the row pointers
   T sum =
       lane_dot<T, LPR>(rp[row] + lane, rp[row + 1], ci, val, [&](int c) { return xin[c]; });
   sum = group_sum(sum, LPR);
-  if (lane == 0) xout[row] = xin[row] + omega * dinv[row] * (b[row] - sum);
+  if (lane == 0) xout[row] = xr + omega * dr * (br - sum);
 }
 
 // Two sweeps from x = 0 in one pass: x1 = omega dinv b is formed on the fly
@@ -89,12 +98,13 @@ __global__ void __launch_bounds__(kSpThreads)
   const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * kSpThreads + threadIdx.x;
   const int row = (int)(gid / LPR), lane = (int)(gid % LPR);
   if (row >= nr) return;
+  const T dr = dinv[row], br = b[row];  // issued beside the row pointers
   T sum = lane_dot<T, LPR>(rp[row] + lane, rp[row + 1], ci, val,
                            [&](int c) { return omega * dinv[c] * b[c]; });
   sum = group_sum(sum, LPR);
   if (lane == 0) {
-    const T x1 = omega * dinv[row] * b[row];
-    xout[row] = x1 + omega * dinv[row] * (b[row] - sum);
+    const T x1 = omega * dr * br;
+    xout[row] = x1 + omega * dr * (br - sum);
   }
 }
 
