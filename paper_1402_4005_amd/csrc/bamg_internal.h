@@ -196,7 +196,7 @@ template <class T>
 void ls_fit(const Level &L, int r, int mmax, const T *U, const T *V, const double *wv,
             const double *wu, int rule, T *Pv, T *Qtv, hipStream_t s);
 template <class T>
-void dinv_from_diag(const Level &L, const T *bv, T *dinv, int *flag, hipStream_t s);
+void dinv_from_diag(const Level &L, const T *bv, T *dinv, int *flag, bool check, hipStream_t s);
 template <class T>
 void inject(const int *cpts, int nc, int r, const T *X, T *Xc, hipStream_t s);
 // Y = A X for r columns (row-major); if reset0, column 0 of Y is set to 1

@@ -335,13 +335,18 @@ void mis_cf(Pool &pool, const Csr &G, uint64_t seed, int level, int *cf, hipStre
   fill_i32(sel, 0, n, s);
   k_mis_keys<<<ceil_div(n, 256), 256, 0, s>>>(n, seed, level, key, cf);
   LAUNCHCHK();
-  for (int round = 1;; ++round) {
+  // Two rounds per host check of the undecided count: a round after the
+  // last decision changes nothing, so the set is the same, with half the
+  // host round trips.
+  for (int round = 1;; round += 2) {
     if (round > n + 1) fail(BAMG_E_DEVICE, "MIS did not terminate");
-    fill_i32(und, 0, 1, s);
-    k_mis_select<<<ceil_div(n, 256), 256, 0, s>>>(n, G.rp, G.ci, key, cf, sel, round);
-    LAUNCHCHK();
-    k_mis_update<<<ceil_div(n, 256), 256, 0, s>>>(n, G.rp, G.ci, sel, cf, round, und);
-    LAUNCHCHK();
+    for (int q = 0; q < 2; ++q) {
+      fill_i32(und, 0, 1, s);
+      k_mis_select<<<ceil_div(n, 256), 256, 0, s>>>(n, G.rp, G.ci, key, cf, sel, round + q);
+      LAUNCHCHK();
+      k_mis_update<<<ceil_div(n, 256), 256, 0, s>>>(n, G.rp, G.ci, sel, cf, round + q, und);
+      LAUNCHCHK();
+    }
     if (read_int(und, s) == 0) break;
   }
   pool.release(key);
@@ -488,75 +493,81 @@ void interp_pattern(Pool &pool, const Level &L, int cap, int geometric, Csr &P, 
 
 // ============================================================ SpGEMM symbolic
 // Rows of C = A * B with many product terms: one wave (block of 64) per
-// listed row, every term appends its column to an LDS buffer, the buffer is
+// listed row at a time, every term appends its column to an LDS buffer, the buffer is
 // bitonic-sorted and the distinct columns counted (pass 1) or written
 // (pass 2). The result is the sorted structural product, independent of
 // thread timing.
-constexpr int kSymCap = 4096;
+constexpr int kSymCap = 4096, kSymListBlocks = 4096;
 
+// The number of listed rows is read on the device (nlist), so the host does
+// not wait for it: the grid strides over the list.
 template <bool FILL>
 __global__ void __launch_bounds__(64)
-    k_spgemm_sym_list(const int *__restrict__ rows, const int *__restrict__ arp,
-                      const int *__restrict__ aci, const int *__restrict__ brp,
-                      const int *__restrict__ bci, int force_diag, int *__restrict__ cnt,
-                      const int *__restrict__ crp, int *__restrict__ cci,
+    k_spgemm_sym_list(const int *__restrict__ rows, const int *__restrict__ nlist,
+                      const int *__restrict__ arp, const int *__restrict__ aci,
+                      const int *__restrict__ brp, const int *__restrict__ bci, int force_diag,
+                      int *__restrict__ cnt, const int *__restrict__ crp, int *__restrict__ cci,
                       int *__restrict__ overflow) {
   __shared__ int buf[kSymCap];
   __shared__ int nbuf;
-  const int row = rows[blockIdx.x], lane = threadIdx.x;
-  if (lane == 0) nbuf = 0;
-  __syncthreads();
-  if (force_diag && lane == 0) {
-    buf[0] = row;
-    nbuf = 1;
-  }
-  __syncthreads();
-  const int ab = arp[row], ae = arp[row + 1];
-  for (int a = ab + lane; a < ae; a += 64) {
-    const int k = aci[a];
-    for (int b = brp[k]; b < brp[k + 1]; ++b) {
-      const int pos = atomicAdd(&nbuf, 1);
-      if (pos < kSymCap) buf[pos] = bci[b];
+  const int nl = *nlist, lane = threadIdx.x;
+  for (int li = blockIdx.x; li < nl; li += gridDim.x) {
+    const int row = rows[li];
+    if (lane == 0) nbuf = 0;
+    __syncthreads();
+    if (force_diag && lane == 0) {
+      buf[0] = row;
+      nbuf = 1;
     }
-  }
-  __syncthreads();
-  int cntv = nbuf;
-  if (cntv > kSymCap) {
-    if (lane == 0) atomicOr(overflow, 1);
-    cntv = kSymCap;
-  }
-  int P2 = 1;
-  while (P2 < cntv) P2 <<= 1;
-  for (int i = cntv + lane; i < P2; i += 64) buf[i] = 0x7fffffff;
-  __syncthreads();
-  // bitonic sort of buf[0..P2)
-  for (int size = 2; size <= P2; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = lane; i < (P2 >> 1); i += 64) {
-        const int lo = 2 * i - (i & (stride - 1));
-        const int hi = lo + stride;
-        const bool up = (lo & size) == 0;
-        const int x = buf[lo], y = buf[hi];
-        if ((x > y) == up) {
-          buf[lo] = y;
-          buf[hi] = x;
-        }
+    __syncthreads();
+    const int ab = arp[row], ae = arp[row + 1];
+    for (int a = ab + lane; a < ae; a += 64) {
+      const int k = aci[a];
+      for (int b = brp[k]; b < brp[k + 1]; ++b) {
+        const int pos = atomicAdd(&nbuf, 1);
+        if (pos < kSymCap) buf[pos] = bci[b];
       }
-      __syncthreads();
     }
+    __syncthreads();
+    int cntv = nbuf;
+    if (cntv > kSymCap) {
+      if (lane == 0) atomicOr(overflow, 1);
+      cntv = kSymCap;
+    }
+    int P2 = 1;
+    while (P2 < cntv) P2 <<= 1;
+    for (int i = cntv + lane; i < P2; i += 64) buf[i] = 0x7fffffff;
+    __syncthreads();
+    // bitonic sort of buf[0..P2)
+    for (int size = 2; size <= P2; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int i = lane; i < (P2 >> 1); i += 64) {
+          const int lo = 2 * i - (i & (stride - 1));
+          const int hi = lo + stride;
+          const bool up = (lo & size) == 0;
+          const int x = buf[lo], y = buf[hi];
+          if ((x > y) == up) {
+            buf[lo] = y;
+            buf[hi] = x;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // distinct values, written in order with a running count per 64-chunk
+    int base = 0;
+    const int out0 = FILL ? crp[row] : 0;
+    for (int c0 = 0; c0 < cntv; c0 += 64) {
+      const int i = c0 + lane;
+      const bool isnew = i < cntv && (i == 0 || buf[i] != buf[i - 1]);
+      const uint64_t mask = __ballot(isnew);
+      const int before = __popcll(mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+      if (FILL && isnew) cci[out0 + base + before] = buf[i];
+      base += __popcll(mask);
+    }
+    if (!FILL && lane == 0) cnt[row] = base;
+    __syncthreads();  // buf and nbuf are reused by the next listed row
   }
-  // distinct values, written in order with a running count per 64-chunk
-  int base = 0;
-  const int out0 = FILL ? crp[row] : 0;
-  for (int c0 = 0; c0 < cntv; c0 += 64) {
-    const int i = c0 + lane;
-    const bool isnew = i < cntv && (i == 0 || buf[i] != buf[i - 1]);
-    const uint64_t mask = __ballot(isnew);
-    const int before = __popcll(mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
-    if (FILL && isnew) cci[out0 + base + before] = buf[i];
-    base += __popcll(mask);
-  }
-  if (!FILL && lane == 0) cnt[row] = base;
 }
 
 // Short rows (at most kSymShort candidate terms, the common case of the
@@ -639,26 +650,32 @@ void spgemm_symbolic(Pool &pool, const Csr &A, const Csr &B, int force_diag, Csr
         nr, A.rp, A.ci, B.rp, B.ci, force_diag, cnt, tmp, longrows, ovf + 1);
     LAUNCHCHK();
   }
-  const int nlong = read_int(ovf + 1, s);
-  if (nlong > 0) {
-    k_spgemm_sym_list<false><<<nlong, 64, 0, s>>>(longrows, A.rp, A.ci, B.rp, B.ci, force_diag,
-                                                  cnt, nullptr, nullptr, ovf);
+  // long rows: a strided grid about as wide as the LDS lets stay resident
+  const int lgrid = std::min(nr, kSymListBlocks);
+  if (lgrid > 0) {
+    k_spgemm_sym_list<false><<<lgrid, 64, 0, s>>>(longrows, ovf + 1, A.rp, A.ci, B.rp, B.ci,
+                                                  force_diag, cnt, nullptr, nullptr, ovf);
     LAUNCHCHK();
   }
-  if (read_int(ovf, s)) fail(BAMG_E_ARG, "Galerkin row wider than the symbolic buffer");
   C.nr = nr;
   C.nc = B.nc;
   C.rp = pool.get<int>(nr + 1);
   scan_counts(pool, cnt, C.rp, nr, s);
-  C.nnz = read_int(C.rp + nr, s);
+  // one host round trip for the size and the overflow flag
+  int hv[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(&hv[0], C.rp + nr, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&hv[1], ovf, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hv[1]) fail(BAMG_E_ARG, "Galerkin row wider than the symbolic buffer");
+  C.nnz = hv[0];
   C.ci = pool.get<int>(C.nnz);
   if (nr) {
     k_sym_pack<<<ceil_div(nr, 256), 256, 0, s>>>(nr, tmp, C.rp, C.ci);
     LAUNCHCHK();
   }
-  if (nlong > 0) {
-    k_spgemm_sym_list<true><<<nlong, 64, 0, s>>>(longrows, A.rp, A.ci, B.rp, B.ci, force_diag,
-                                                 nullptr, C.rp, C.ci, ovf);
+  if (lgrid > 0) {
+    k_spgemm_sym_list<true><<<lgrid, 64, 0, s>>>(longrows, ovf + 1, A.rp, A.ci, B.rp, B.ci,
+                                                 force_diag, nullptr, C.rp, C.ci, ovf);
     LAUNCHCHK();
   }
   pool.release(cnt);
@@ -1144,12 +1161,15 @@ __global__ void k_dinv(int n, const int *__restrict__ dpos, const T *__restrict_
   }
 }
 
+// check = false: the flag only accumulates (the caller zeroed it and reads
+// it later, sparing a host round trip per level).
 template <class T>
-void dinv_from_diag(const Level &L, const T *bv, T *dinv, int *flag, hipStream_t s) {
-  fill_i32(flag, 0, 1, s);
+void dinv_from_diag(const Level &L, const T *bv, T *dinv, int *flag, bool check, hipStream_t s) {
+  if (check) fill_i32(flag, 0, 1, s);
   k_dinv<T><<<ceil_div(L.n, 256), 256, 0, s>>>(L.n, L.dpos, bv, dinv, flag);
   LAUNCHCHK();
-  if (read_int(flag, s)) fail(BAMG_E_BAD_DIAG, "zero or non-finite diagonal in some B_l");
+  if (check && read_int(flag, s))
+    fail(BAMG_E_BAD_DIAG, "zero or non-finite diagonal in some B_l");
 }
 
 template <class T>
@@ -1605,7 +1625,7 @@ void row_inv_norms(const Csr &A, const T *val, T *out, hipStream_t s) {
   template void fill_transfer_identity<T>(const Level &, T *, T *, hipStream_t);             \
   template void ls_fit<T>(const Level &, int, int, const T *, const T *, const double *,     \
                           const double *, int, T *, T *, hipStream_t);                       \
-  template void dinv_from_diag<T>(const Level &, const T *, T *, int *, hipStream_t);               \
+  template void dinv_from_diag<T>(const Level &, const T *, T *, int *, bool, hipStream_t);               \
   template void inject<T>(const int *, int, int, const T *, T *, hipStream_t);               \
   template void spmm<T>(const Csr &, const T *, int, const T *, T *, int, hipStream_t);      \
   template void relax_pairs<T>(const Level &, int, T, int, const double *, const T *,        \

@@ -121,7 +121,7 @@ struct Setup {
     spgemm_numeric<T>(L.Pc, (const T *)L.Ptv, L.T2, (const T *)L.T3v, C.M, (T *)C.Nv, sc, s);
     pool().release(sc);
     copy_permuted<T>((T *)C.Btv, (const T *)C.Bv, C.btperm, C.B.nnz, s);
-    dinv_from_diag<T>(C, (const T *)C.Bv, (T *)C.dinv, flag, s);
+    dinv_from_diag<T>(C, (const T *)C.Bv, (T *)C.dinv, flag + 3, false, s);
     // Kaczmarz row norms exist only where the smoother runs (not on the
     // coarsest level, which is solved directly)
     if (h->opt.smoother == BAMG_SMOOTH_KACZMARZ && l + 1 < h->L - 1) {
@@ -205,6 +205,9 @@ struct Setup {
   // last setup cycle B_L is final, so its pseudo-inverse (the coarse solve
   // of the V-cycle) is computed in the same launches.
   void coarsest(bool last) {
+    // every coarse diagonal of this cycle exists now: report a bad one
+    // before anything the coarsest solve might say about it
+    if (read_int(flag + 3, s)) fail(BAMG_E_BAD_DIAG, "zero or non-finite diagonal in some B_l");
     Level &C = h->lv[h->L - 1];
     const int n = C.n;
     csr_to_dense(C.B, C.Bv, h->prec, Bd, s);
@@ -381,8 +384,9 @@ void setup_all(bamg_handle *h, const bamg_csr *A, const bamg_geometry *geom) {
     L0.identity_mn = true;
     L0.dinv = pool.get<T>(n);
   }
-  int *flag = pool.get<int>(4);
-  dinv_from_diag<T>(h->lv[0], (const T *)h->lv[0].Bv, (T *)h->lv[0].dinv, flag, s);
+  int *flag = pool.get<int>(4);  // [3]: coarse-level diagonal failures, read per cycle
+  fill_i32(flag, 0, 4, s);
+  dinv_from_diag<T>(h->lv[0], (const T *)h->lv[0].Bv, (T *)h->lv[0].dinv, flag, true, s);
 
   // ---- integer structure of the hierarchy
   for (int l = 0;; ++l) {
