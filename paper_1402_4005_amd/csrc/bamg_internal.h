@@ -108,6 +108,7 @@ struct bamg_handle {
   double *red = nullptr;    // device reduction scratch
   size_t red_cap = 0;
   double *hred = nullptr;   // pinned host mirror: 2 x 16 flag slots
+  double *hred_dev = nullptr;  // the same memory as the device addresses it
   hipEvent_t gm_ev[2] = {nullptr, nullptr};  // flag copies of alternate iterations
   // GMRES storage, allocated on first use
   int gm_m = 0;
@@ -261,7 +262,11 @@ void residual_check_partials(const double *x0, const double *bx0, const double *
                              const double *BVb, const double *y, int n, int k, double *part,
                              int nblk, hipStream_t s);
 void residual_check_finalize(const double *part, int nblk, double tol, double *flags,
-                             hipStream_t s);
+                             double *host_out, hipStream_t s);
+// w <- w - sum_t h[t] V_t with the partials of V_t . w (t < k) in one pass;
+// false (nothing launched) when k is above the fused kernel's bound
+bool multi_axpy_dot(const double *Vb, int n, int k, const double *h, double *w, double *part,
+                    int nblk, hipStream_t s);
 void update_iterate(double *x0, const double *Vb, const double *y, int n, int k, hipStream_t s);
 void negate_copy(const double *in, double *out, int n, hipStream_t s);
 void normalize_sum(double *x, int n, double *part, int nblk, double *flags, hipStream_t s);

@@ -74,6 +74,68 @@ void multi_axpy_norm(const double *Vb, int n, int k, const double *h, double *w,
   LAUNCHCHK();
 }
 
+// The first Gram-Schmidt update fused with the second pass's dots:
+// w <- w - sum_t h[t] V_t, then part[t * nblk + b] = block b's partial of
+// V_t . w (t < k). Each row's V entries are loaded once for both. Rows are
+// distributed over the blocks and reduced exactly as in k_multi_dot and
+// k_multi_axpy_norm, so w and the partials equal the two separate kernels'
+// bit for bit. KF >= k is the compile-time bound of the register arrays
+// (loads past column k - 1 re-read that column and are not used).
+constexpr int kFusedK = 24;
+
+template <int KF>
+__global__ void __launch_bounds__(kKT)
+    k_multi_axpy_dot(const double *__restrict__ Vb, int n, int k, const double *__restrict__ h,
+                     double *__restrict__ w, double *__restrict__ part) {
+  __shared__ double sh[kKT / kWave][KF];
+  __shared__ double hs[KF];
+  if (threadIdx.x < KF) hs[threadIdx.x] = threadIdx.x < k ? h[threadIdx.x] : 0.0;
+  __syncthreads();
+  double acc[KF];
+#pragma unroll
+  for (int t = 0; t < KF; ++t) acc[t] = 0.0;
+  for (long i = (long)blockIdx.x * kKT + threadIdx.x; i < n; i += (long)gridDim.x * kKT) {
+    double v[KF];
+#pragma unroll
+    for (int t = 0; t < KF; ++t) v[t] = Vb[(size_t)min(t, k - 1) * n + i];
+    double x = w[i];
+#pragma unroll
+    for (int t = 0; t < KF; ++t)
+      if (t < k) x -= hs[t] * v[t];
+    w[i] = x;
+#pragma unroll
+    for (int t = 0; t < KF; ++t)
+      if (t < k) acc[t] += v[t] * x;
+  }
+  const int wv = threadIdx.x / kWave, l = threadIdx.x % kWave;
+#pragma unroll
+  for (int t = 0; t < KF; ++t) {
+    const double r = group_sum(acc[t], kWave);
+    if (l == 0) sh[wv][t] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < k) {
+    double r = 0.0;
+    for (int q = 0; q < kKT / kWave; ++q) r += sh[q][threadIdx.x];
+    part[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = r;
+  }
+}
+
+bool multi_axpy_dot(const double *Vb, int n, int k, const double *h, double *w, double *part,
+                    int nblk, hipStream_t s) {
+  if (k < 1 || k > kFusedK) return false;
+  switch ((k + 3) / 4) {
+    case 1: k_multi_axpy_dot<4><<<nblk, kKT, 0, s>>>(Vb, n, k, h, w, part); break;
+    case 2: k_multi_axpy_dot<8><<<nblk, kKT, 0, s>>>(Vb, n, k, h, w, part); break;
+    case 3: k_multi_axpy_dot<12><<<nblk, kKT, 0, s>>>(Vb, n, k, h, w, part); break;
+    case 4: k_multi_axpy_dot<16><<<nblk, kKT, 0, s>>>(Vb, n, k, h, w, part); break;
+    case 5: k_multi_axpy_dot<20><<<nblk, kKT, 0, s>>>(Vb, n, k, h, w, part); break;
+    default: k_multi_axpy_dot<24><<<nblk, kKT, 0, s>>>(Vb, n, k, h, w, part); break;
+  }
+  LAUNCHCHK();
+  return true;
+}
+
 // Arnoldi step j of the Hessenberg matrix H ((m+1) x m, row-major), Givens
 // rotations cs/sn, right-hand side g, solution y of the leading j+1 system.
 // h1, h2: the two Gram-Schmidt coefficient passes (j+1 values each, plus the
@@ -171,9 +233,11 @@ void residual_check_partials(const double *x0, const double *bx0, const double *
   LAUNCHCHK();
 }
 
-// flags[0] = converged, flags[2] = ||Bx||/||x||
+// flags[0] = converged, flags[2] = ||Bx||/||x||; then all 16 flags are
+// copied to host_out (mapped pinned memory) when it is not null.
 __global__ void __launch_bounds__(kKT) k_resid_final(const double *__restrict__ part, int nblk,
-                                                     double tol, double *__restrict__ flags) {
+                                                     double tol, double *__restrict__ flags,
+                                                     double *__restrict__ host_out) {
   __shared__ double sh[kKT / kWave];
   double a = 0.0, b = 0.0;
   for (int q = threadIdx.x; q < nblk; q += kKT) {
@@ -186,12 +250,14 @@ __global__ void __launch_bounds__(kKT) k_resid_final(const double *__restrict__ 
     const double rel = b > 0.0 ? sqrt(a) / sqrt(b) : INFINITY;
     flags[2] = rel;
     flags[0] = rel < tol ? 1.0 : 0.0;
+    if (host_out)
+      for (int q = 0; q < 16; ++q) host_out[q] = flags[q];
   }
 }
 
 void residual_check_finalize(const double *part, int nblk, double tol, double *flags,
-                             hipStream_t s) {
-  k_resid_final<<<1, kKT, 0, s>>>(part, nblk, tol, flags);
+                             double *host_out, hipStream_t s) {
+  k_resid_final<<<1, kKT, 0, s>>>(part, nblk, tol, flags, host_out);
   LAUNCHCHK();
 }
 

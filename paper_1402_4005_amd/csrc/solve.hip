@@ -148,6 +148,27 @@ __global__ void k_spmv_dual(int nr, const int *__restrict__ rp, const int *__res
   }
 }
 
+// v = w * scal[0] (the next Arnoldi basis vector), y1 = y2 = A v: the
+// scaling of the previous iteration done where the product reads it (the
+// same expressions as scale_vec followed by k_spmv_dual, bit for bit).
+__global__ void k_spmv_dual_scaled(int nr, const int *__restrict__ rp, const int *__restrict__ ci,
+                                   const double *__restrict__ val, const double *__restrict__ w,
+                                   const double *__restrict__ scal, double *__restrict__ v,
+                                   double *__restrict__ y1, double *__restrict__ y2) {
+  const int gid = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  const int row = gid / 8, lane = gid % 8;
+  if (row >= nr) return;
+  const double sc = scal[0];
+  double sum = 0.0;
+  for (int k = rp[row] + lane; k < rp[row + 1]; k += 8) sum += val[k] * (w[ci[k]] * sc);
+  sum = group_sum(sum, 8);
+  if (lane == 0) {
+    v[row] = w[row] * sc;
+    y1[row] = sum;
+    y2[row] = sum;
+  }
+}
+
 // C applied to the fixed input buffer h->vcin, result in h->gw. The launch
 // sequence of one V-cycle (about ten kernels per level) is captured once
 // into a HIP graph and replayed, which removes per-launch host overhead.
@@ -209,7 +230,13 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
       h->vb = pool.get<float>(n);
       h->vx = pool.get<float>(n);
     }
-    if (!h->hred) HIPCHK(hipHostMalloc((void **)&h->hred, sizeof(double) * 32, 0));
+    if (!h->hred) {
+      // mapped and coherent: the residual kernel writes each iteration's
+      // flags here directly, the host reads them after that iteration's event
+      HIPCHK(hipHostMalloc((void **)&h->hred, sizeof(double) * 32,
+                           hipHostMallocMapped | hipHostMallocCoherent));
+      HIPCHK(hipHostGetDevicePointer((void **)&h->hred_dev, h->hred, 0));
+    }
     for (hipEvent_t &e : h->gm_ev)
       if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     if (!h->vcin) h->vcin = pool.get<double>(n);
@@ -245,7 +272,7 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
   // initial test on x0
   spmv<double>(B, h->B64, h->gx0, h->gbx0, nullptr, 0, lanes, s);
   residual_check_partials(h->gx0, h->gbx0, h->gV, h->gBV, c1, n, 0, part3, nblk, s);
-  residual_check_finalize(part3, nblk, tol, flags, s);
+  residual_check_finalize(part3, nblk, tol, flags, nullptr, s);
   read_flags();
   int it = 0, restarts = 0, breakdowns = 0, conv = hf[0] != 0.0;
   double rel = hf[2];
@@ -261,32 +288,37 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
     scale_vec(h->gw, flags + 3, h->gV, n, s);  // v_0 = z / beta
     int used = 0;
     bool broke = false;
-    // Iteration j is enqueued, then its status flags are copied to a pinned
-    // slot and its y saved; the host reads them only after iteration j + 1
-    // is enqueued, so the device never waits for the host between
-    // iterations. Stopping at j discards the work of j + 1 (it writes only
+    // Iteration j is enqueued with its status flags written by the residual
+    // kernel into a mapped pinned slot and its y into a ring slot; the host
+    // reads them only after iteration j + 1 is enqueued, so the device never
+    // waits for the host between iterations. Stopping at j discards the work of j + 1 (it writes only
     // basis vector j + 2, the Hessenberg column j + 1 and the other y slot).
+    // v_{j+1} = w / h_{j+1,j} is written by iteration j + 1's product
+    // kernel, which is the first to read it.
     auto enqueue = [&](int j) {
       double *vj = h->gV + (size_t)j * n, *bvj = h->gBV + (size_t)j * n;
-      k_spmv_dual<<<ceil_div((long)n * 8, 256), 256, 0, s>>>(n, B.rp, B.ci, h->B64, vj, bvj,
-                                                             h->vcin);  // B v_j
+      if (j == 0)
+        k_spmv_dual<<<ceil_div((long)n * 8, 256), 256, 0, s>>>(n, B.rp, B.ci, h->B64, vj, bvj,
+                                                               h->vcin);  // B v_0
+      else
+        k_spmv_dual_scaled<<<ceil_div((long)n * 8, 256), 256, 0, s>>>(
+            n, B.rp, B.ci, h->B64, h->gw, flags + 3, vj, bvj, h->vcin);  // v_j, B v_j
       LAUNCHCHK();
       precondition_fixed(h, s);  // w = C B v_j
-      // Gram-Schmidt, twice
+      // Gram-Schmidt, twice; the first update and the second pass's dots in one kernel
       multi_dot(h->gV, n, j + 1, h->gw, part, nblk, s);
       finalize_multi(part, nblk, j + 2, c1, s);  // c1[0..j], c1[j+1] = |w|^2
-      multi_axpy_norm(h->gV, n, j + 1, c1, h->gw, part2, nblk, s);
-      multi_dot(h->gV, n, j + 1, h->gw, part, nblk, s);
+      if (!multi_axpy_dot(h->gV, n, j + 1, c1, h->gw, part, nblk, s)) {
+        multi_axpy_norm(h->gV, n, j + 1, c1, h->gw, part2, nblk, s);
+        multi_dot(h->gV, n, j + 1, h->gw, part, nblk, s);
+      }
       finalize_multi(part, nblk, j + 1, c2, s);
       multi_axpy_norm(h->gV, n, j + 1, c2, h->gw, part2, nblk, s);
-      gmres_arnoldi_update(H, cs, sn, g, y, c1, c2, part2, nblk, nullptr, j, m, flags, s);
-      scale_vec(h->gw, flags + 3, h->gV + (size_t)(j + 1) * n, n, s);
-      residual_check_partials(h->gx0, h->gbx0, h->gV, h->gBV, y, n, j + 1, part3, nblk, s);
-      residual_check_finalize(part3, nblk, tol, flags, s);
+      // y goes straight to this iteration's ring slot
       double *ys = yring + (size_t)(j & 1) * (m + 2);
-      HIPCHK(hipMemcpyAsync(ys, y, sizeof(double) * (j + 1), hipMemcpyDeviceToDevice, s));
-      HIPCHK(hipMemcpyAsync(hf + 16 * (j & 1), flags, sizeof(double) * 16,
-                            hipMemcpyDeviceToHost, s));
+      gmres_arnoldi_update(H, cs, sn, g, ys, c1, c2, part2, nblk, nullptr, j, m, flags, s);
+      residual_check_partials(h->gx0, h->gbx0, h->gV, h->gBV, ys, n, j + 1, part3, nblk, s);
+      residual_check_finalize(part3, nblk, tol, flags, h->hred_dev + 16 * (j & 1), s);
       HIPCHK(hipEventRecord(h->gm_ev[j & 1], s));
     };
     auto finished = [&](int j) {  // true: stop after iteration j
