@@ -47,6 +47,20 @@ __device__ __forceinline__ X group_sum(X v, int width) {
   return v;
 }
 
+// Three group sums at once: the same butterfly as group_sum for each value
+// (bit-identical results), with the three shuffle chains interleaved so
+// their latencies overlap.
+template <class X>
+__device__ __forceinline__ void group_sum3(X &a, X &b, X &c, int width) {
+  for (int off = width >> 1; off > 0; off >>= 1) {
+    const X ta = __shfl_xor(a, off, width), tb = __shfl_xor(b, off, width),
+            tc = __shfl_xor(c, off, width);
+    a += ta;
+    b += tb;
+    c += tc;
+  }
+}
+
 // The dispatcher hands workgroup b to XCD b % 8. Renumbering so that XCD x
 // owns one contiguous range of logical blocks keeps neighbouring rows (and
 // the vector entries they gather) in one XCD's L2 instead of all eight.

@@ -183,12 +183,14 @@ void transpose_dense(const double *A, double *At, int n, hipStream_t s) {
 // ------------------------------------------------------------ Jacobi SVD
 // Block one-sided Jacobi. The columns of W are split into blocks of bs
 // columns; the blocks are paired by the round-robin schedule, one workgroup
-// per block pair. A workgroup holds its 2 bs columns in LDS and runs one
-// cyclic sweep over all their pairs (again round-robin, bs disjoint pairs at
-// a time, one wave per pair), accumulating the rotations in a 2bs x 2bs
-// matrix R; the matching columns of J are then multiplied by R once. Only
-// the block rounds need a grid-wide barrier, so a sweep costs about 2n
-// workgroup barriers and n/bs grid barriers.
+// per block pair. A workgroup holds its 2 bs columns in LDS and rotates
+// their pairs (bs disjoint pairs at a time, one wave per pair): in the first
+// round of a sweep all pairs of the 2 bs columns, afterwards only the pairs
+// across the two blocks, so each column pair of W is visited once per
+// sweep. The rotations accumulate in a 2bs x 2bs matrix R, and the matching
+// columns of J are multiplied by R once. Only the block rounds need a
+// grid-wide barrier: a sweep costs about n workgroup barriers and n/bs grid
+// barriers.
 constexpr int kSvdMaxSweeps = 80;
 
 __device__ __forceinline__ int rr_index(int j, int round, int m) {
@@ -230,12 +232,25 @@ __global__ void __launch_bounds__(1024)
         for (int e = threadIdx.x; e < cols * cols; e += nt) R[e] = (e / cols) == (e % cols);
         if (threadIdx.x == 0) nrot = 0;
         __syncthreads();
-        for (int ir = 0; ir < cols - 1; ++ir) {
-          int p = rr_index(wv, ir, cols), q = rr_index(cols - 1 - wv, ir, cols);
-          if (p > q) {
-            const int x = p;
-            p = q;
-            q = x;
+        // Round 0 of a sweep: every pair of the 2 bs columns (round-robin,
+        // bs disjoint pairs at a time), which covers each block's own pairs
+        // once per sweep. Later rounds: only the bs x bs cross pairs of the
+        // two blocks, column wv of block a with column (wv + ir) mod bs of
+        // block b. Every column pair of W is rotated once per sweep.
+        const int ninner = round == 0 ? cols - 1 : bs;
+        for (int ir = 0; ir < ninner; ++ir) {
+          int p, q;
+          if (round == 0) {
+            p = rr_index(wv, ir, cols);
+            q = rr_index(cols - 1 - wv, ir, cols);
+            if (p > q) {
+              const int x = p;
+              p = q;
+              q = x;
+            }
+          } else {
+            p = wv;
+            q = bs + (wv + ir) % bs;
           }
           double *wp = Ws + (size_t)p * n, *wq = Ws + (size_t)q * n;
           double al = 0.0, be = 0.0, ga = 0.0;
@@ -245,9 +260,7 @@ __global__ void __launch_bounds__(1024)
             be += y * y;
             ga += x * y;
           }
-          al = group_sum(al, kWave);
-          be = group_sum(be, kWave);
-          ga = group_sum(ga, kWave);
+          group_sum3(al, be, ga, kWave);
           if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
             const double zeta = (be - al) / (2.0 * ga);
             const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
@@ -631,9 +644,7 @@ __global__ void __launch_bounds__(kSmallThreads)
           be += b * b;
           ga += a * b;
         }
-        al = group_sum(al, kPairLanes);
-        be = group_sum(be, kPairLanes);
-        ga = group_sum(ga, kPairLanes);
+        group_sum3(al, be, ga, kPairLanes);
         if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
           const double zeta = (be - al) / (2.0 * ga);
           const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
