@@ -335,8 +335,8 @@ int jacobi_svd2(Pool &pool, double *W, double *J, double *W2, double *J2, int n,
   HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   // Column blocks of bs: 16 when that still gives 32 or more blocks, else 8.
   // Fewer, wider blocks leave most compute units idle in a round; narrower
-  // ones than 8 add rounds faster than they shorten them (n = 289: 55.4 ms
-  // setup with bs 16, 49.9 with 8, 55.5 with 4, 11 sweeps each).
+  // ones than 8 add rounds faster than they shorten them (n = 289, tandem
+  // 1025^2 setup: 47.9 ms with bs 16, 45.3 with 8, 57.7 with 4).
   int bs = ceil_div(n, 16) >= 32 ? 16 : 8;
   while (bs > 1 && block_jacobi_lds(n, bs) + 256 > (size_t)maxlds) bs >>= 1;
   if (block_jacobi_lds(n, bs) + 256 > (size_t)maxlds)
