@@ -162,6 +162,11 @@ void jacobi(const Csr &A, const T *val, const T *dinv, T omega, const T *b, cons
 template <class T>
 void jacobi2_from_zero(const Csr &A, const T *val, const T *dinv, T omega, const T *b, T *xout,
                        int lanes, hipStream_t s);  // two sweeps from x = 0
+// GMRES products (FP64): y1 = y2 = A x; and v = w scal[0], y1 = y2 = A v
+void spmv_dual(const Csr &A, const double *val, const double *x, double *y1, double *y2,
+               int lanes, hipStream_t s);
+void spmv_dual_scaled(const Csr &A, const double *val, const double *w, const double *scal,
+                      double *v, double *y1, double *y2, int lanes, hipStream_t s);
 // Kaczmarz sweep over one colour segment (in place)
 template <class T>
 void kaczmarz_colour(const Csr &A, const T *val, const T *rowinv, const int *rows, int nrows,

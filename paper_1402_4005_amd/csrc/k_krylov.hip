@@ -11,6 +11,7 @@
 namespace bamg {
 
 constexpr int kKT = 256;
+constexpr int kArnoldiLds = 32;  // restart lengths below this stage H in LDS
 
 // part[t * nblk + b] = sum over block b's rows of V_t . w  (t < k); t == k: w . w
 __global__ void __launch_bounds__(kKT) k_multi_dot(const double *__restrict__ Vb, int n, int k,
@@ -147,37 +148,77 @@ __global__ void __launch_bounds__(kKT)
                      const double *__restrict__ h1, const double *__restrict__ h2,
                      const double *__restrict__ wpart, int nblk, int j, int m,
                      double *__restrict__ flags) {
+  // The serial part (rotations, back substitution) runs in one thread; the
+  // rows 0..j of columns 0..j of H, the rotations and g are first staged in
+  // LDS by the whole block so that thread never waits on global memory.
+  constexpr int kS = kArnoldiLds;  // j < kS uses the LDS copy
   __shared__ double sh[kKT / kWave];
+  __shared__ double Hs[kS * kS], css[kS], sns[kS], gs[kS + 1], ys[kS], col[kS + 1];
   double s = 0.0;
   for (int b = threadIdx.x; b < nblk; b += kKT) s += wpart[b];
   s = block_sum<kKT>(s, sh);
+  const bool lds = j < kS;
+  if (lds) {
+    for (int e = threadIdx.x; e < (j + 1) * (j + 1); e += kKT) {
+      const int i = e / (j + 1), q = e % (j + 1);
+      if (q >= i && q < j) Hs[i * kS + q] = H[(size_t)i * m + q];
+    }
+    for (int i = threadIdx.x; i <= j; i += kKT) {
+      css[i] = i < j ? cs[i] : 0.0;
+      sns[i] = i < j ? sn[i] : 0.0;
+      gs[i] = g[i];
+    }
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
+  // Hr(i, q): the LDS copy when it exists, else H itself
+  double *const Hb = lds ? Hs : H;
+  const int ld = lds ? kS : m;
+  double *const cb = lds ? css : cs, *const sb = lds ? sns : sn, *const gb = lds ? gs : g;
+  double *const yb = lds ? ys : y;
   const double hn = sqrt(s);
   const double w0 = sqrt(h1[j + 1]);
-  for (int i = 0; i <= j; ++i) H[i * m + j] = h1[i] + h2[i];
-  H[(j + 1) * m + j] = hn;
+  // col: column j of H, rows 0..j+1 (used when staged)
+  auto cget = [&](int i) -> double { return lds ? col[i] : H[(size_t)i * m + j]; };
+  auto cset = [&](int i, double v) {
+    if (lds)
+      col[i] = v;
+    else
+      H[(size_t)i * m + j] = v;
+  };
+  for (int i = 0; i <= j; ++i) cset(i, h1[i] + h2[i]);
+  cset(j + 1, hn);
   const bool broke = !(hn > 1e-14 * w0);
   for (int i = 0; i < j; ++i) {
-    const double a = H[i * m + j], b = H[(i + 1) * m + j];
-    H[i * m + j] = cs[i] * a + sn[i] * b;
-    H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+    const double a = cget(i), b = cget(i + 1);
+    cset(i, cb[i] * a + sb[i] * b);
+    cset(i + 1, -sb[i] * a + cb[i] * b);
   }
-  const double a = H[j * m + j], b = H[(j + 1) * m + j];
+  const double a = cget(j), b = cget(j + 1);
   const double den = sqrt(a * a + b * b);
-  cs[j] = den > 0 ? a / den : 1.0;
-  sn[j] = den > 0 ? b / den : 0.0;
-  H[j * m + j] = den;
-  H[(j + 1) * m + j] = 0.0;
-  g[j + 1] = -sn[j] * g[j];
-  g[j] = cs[j] * g[j];
+  const double cj = den > 0 ? a / den : 1.0, sj = den > 0 ? b / den : 0.0;
+  cs[j] = cj;
+  sn[j] = sj;
+  cset(j, den);
+  cset(j + 1, 0.0);
+  const double gj = gb[j];
+  g[j + 1] = -sj * gj;
+  g[j] = cj * gj;
+  if (lds) gs[j] = cj * gj;
+  if (lds)
+    for (int i = 0; i <= j; ++i) Hs[i * kS + j] = col[i];
   for (int i = j; i >= 0; --i) {
-    double t = g[i];
-    for (int q = i + 1; q <= j; ++q) t -= H[i * m + q] * y[q];
-    y[i] = t / H[i * m + i];
+    double t = gb[i];
+    for (int q = i + 1; q <= j; ++q) t -= Hb[(size_t)i * ld + q] * yb[q];
+    yb[i] = t / Hb[(size_t)i * ld + i];
+  }
+  if (lds) {
+    for (int i = 0; i <= j + 1; ++i) H[(size_t)i * m + j] = col[i];
+    for (int i = 0; i <= j; ++i) y[i] = ys[i];
   }
   flags[1] = broke ? 1.0 : 0.0;
   flags[3] = broke ? 0.0 : 1.0 / hn;
-  flags[4] = fabs(g[j + 1]);
+  flags[4] = fabs(-sj * gj);
 }
 
 void gmres_arnoldi_update(double *H, double *cs, double *sn, double *g, double *y, double *h1,

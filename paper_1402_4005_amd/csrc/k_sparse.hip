@@ -158,6 +158,62 @@ void jacobi2_from_zero(const Csr &A, const T *val, const T *dinv, T omega, const
   BAMG_LPR_SWITCH(lanes, k_jacobi2, A.nr, A.nr, A.rp, A.ci, val, dinv, omega, b, xout);
 }
 
+// GMRES products on the finest level (FP64), with the level's lanes per row:
+// y1 = y2 = A x (the second copy is the V-cycle's fixed input), and the
+// same with x = w * scal[0] formed where it is gathered and stored as v
+// (the next Arnoldi basis vector).
+template <class T, int LPR>
+__global__ void __launch_bounds__(kSpThreads)
+    k_spmv_dual(int nr, const int *__restrict__ rp, const int *__restrict__ ci,
+                const T *__restrict__ val, const T *__restrict__ x, T *__restrict__ y1,
+                T *__restrict__ y2) {
+  const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * kSpThreads + threadIdx.x;
+  const int row = (int)(gid / LPR), lane = (int)(gid % LPR);
+  if (row >= nr) return;
+  T sum = lane_dot<T, LPR>(rp[row] + lane, rp[row + 1], ci, val, [&](int c) { return x[c]; });
+  sum = group_sum(sum, LPR);
+  if (lane == 0) {
+    y1[row] = sum;
+    y2[row] = sum;
+  }
+}
+
+template <class T, int LPR>
+__global__ void __launch_bounds__(kSpThreads)
+    k_spmv_dual_scaled(int nr, const int *__restrict__ rp, const int *__restrict__ ci,
+                       const T *__restrict__ val, const T *__restrict__ w,
+                       const T *__restrict__ scal, T *__restrict__ v, T *__restrict__ y1,
+                       T *__restrict__ y2) {
+  const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * kSpThreads + threadIdx.x;
+  const int row = (int)(gid / LPR), lane = (int)(gid % LPR);
+  if (row >= nr) return;
+  const T sc = scal[0], wr = w[row];
+  T sum = lane_dot<T, LPR>(rp[row] + lane, rp[row + 1], ci, val,
+                           [&](int c) { return w[c] * sc; });
+  sum = group_sum(sum, LPR);
+  if (lane == 0) {
+    v[row] = wr * sc;
+    y1[row] = sum;
+    y2[row] = sum;
+  }
+}
+
+void spmv_dual(const Csr &A, const double *val, const double *x, double *y1, double *y2,
+               int lanes, hipStream_t s) {
+  using T = double;
+  if (A.nr <= 0) return;
+  if (lanes <= 0) lanes = pick_lanes(A.nr, A.nnz);
+  BAMG_LPR_SWITCH(lanes, k_spmv_dual, A.nr, A.nr, A.rp, A.ci, val, x, y1, y2);
+}
+
+void spmv_dual_scaled(const Csr &A, const double *val, const double *w, const double *scal,
+                      double *v, double *y1, double *y2, int lanes, hipStream_t s) {
+  using T = double;
+  if (A.nr <= 0) return;
+  if (lanes <= 0) lanes = pick_lanes(A.nr, A.nnz);
+  BAMG_LPR_SWITCH(lanes, k_spmv_dual_scaled, A.nr, A.nr, A.rp, A.ci, val, w, scal, v, y1, y2);
+}
+
 // Kaczmarz row projections x <- x + (b_i - A_i x) / ||A_i||^2 A_i^T for the
 // rows of one colour; rows of one colour share no column, so their updates
 // touch disjoint entries of x and may run in any order.

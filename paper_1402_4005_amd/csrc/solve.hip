@@ -132,43 +132,6 @@ static void precondition(bamg_handle *h, const double *b, double *x, hipStream_t
   convert<float, double>(x, (const float *)h->vx, n, s);
 }
 
-// y1 = y2 = A x (the second copy feeds the captured V-cycle)
-__global__ void k_spmv_dual(int nr, const int *__restrict__ rp, const int *__restrict__ ci,
-                            const double *__restrict__ val, const double *__restrict__ x,
-                            double *__restrict__ y1, double *__restrict__ y2) {
-  const int gid = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-  const int row = gid / 8, lane = gid % 8;
-  if (row >= nr) return;
-  double sum = 0.0;
-  for (int k = rp[row] + lane; k < rp[row + 1]; k += 8) sum += val[k] * x[ci[k]];
-  sum = group_sum(sum, 8);
-  if (lane == 0) {
-    y1[row] = sum;
-    y2[row] = sum;
-  }
-}
-
-// v = w * scal[0] (the next Arnoldi basis vector), y1 = y2 = A v: the
-// scaling of the previous iteration done where the product reads it (the
-// same expressions as scale_vec followed by k_spmv_dual, bit for bit).
-__global__ void k_spmv_dual_scaled(int nr, const int *__restrict__ rp, const int *__restrict__ ci,
-                                   const double *__restrict__ val, const double *__restrict__ w,
-                                   const double *__restrict__ scal, double *__restrict__ v,
-                                   double *__restrict__ y1, double *__restrict__ y2) {
-  const int gid = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-  const int row = gid / 8, lane = gid % 8;
-  if (row >= nr) return;
-  const double sc = scal[0];
-  double sum = 0.0;
-  for (int k = rp[row] + lane; k < rp[row + 1]; k += 8) sum += val[k] * (w[ci[k]] * sc);
-  sum = group_sum(sum, 8);
-  if (lane == 0) {
-    v[row] = w[row] * sc;
-    y1[row] = sum;
-    y2[row] = sum;
-  }
-}
-
 // C applied to the fixed input buffer h->vcin, result in h->gw. The launch
 // sequence of one V-cycle (about ten kernels per level) is captured once
 // into a HIP graph and replayed, which removes per-launch host overhead.
@@ -298,12 +261,9 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
     auto enqueue = [&](int j) {
       double *vj = h->gV + (size_t)j * n, *bvj = h->gBV + (size_t)j * n;
       if (j == 0)
-        k_spmv_dual<<<ceil_div((long)n * 8, 256), 256, 0, s>>>(n, B.rp, B.ci, h->B64, vj, bvj,
-                                                               h->vcin);  // B v_0
+        spmv_dual(B, h->B64, vj, bvj, h->vcin, lanes, s);  // B v_0
       else
-        k_spmv_dual_scaled<<<ceil_div((long)n * 8, 256), 256, 0, s>>>(
-            n, B.rp, B.ci, h->B64, h->gw, flags + 3, vj, bvj, h->vcin);  // v_j, B v_j
-      LAUNCHCHK();
+        spmv_dual_scaled(B, h->B64, h->gw, flags + 3, vj, bvj, h->vcin, lanes, s);  // v_j, B v_j
       precondition_fixed(h, s);  // w = C B v_j
       // Gram-Schmidt, twice; the first update and the second pass's dots in one kernel
       multi_dot(h->gV, n, j + 1, h->gw, part, nblk, s);
