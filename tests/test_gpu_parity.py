@@ -172,3 +172,21 @@ def test_setup_deterministic():
         for what in ("B", "M", "N"):
             assert np.array_equal(h1.csr(l, what)[2], h2.csr(l, what)[2])
     assert np.array_equal(h1.sigma(), h2.sigma())
+
+
+def test_long_restart_matches_oracle():
+    """GMRES(40) on a weakly preconditioned chain (1 + 0 sweeps): the
+    restart cycle reaches Arnoldi step 39, past the fused Gram-Schmidt
+    kernel's 24 columns and the LDS-staged Hessenberg update's 32, so the
+    general paths of both run; x and the iteration count match the oracle."""
+    import torch
+    ch = chaingen.tandem(65, 11 / 31, 10 / 31, 10 / 31)
+    kw = dict(r=8, coarse_max=30, nu_pre=1, nu_post=0)
+    ho, hg = both(ch, **kw)
+    xo, io = ho.gmres(m=40, tol=1e-12, maxit=600)
+    xg, ig = hg.gmres(restart=40, tol=1e-12, maxit=600)
+    torch.cuda.synchronize()
+    assert io.converged and ig.converged
+    assert io.iterations > 33
+    assert abs(ig.iterations - io.iterations) <= 1, (ig.iterations, io.iterations)
+    assert rel_l1(xg.cpu().numpy(), xo) < 1e-10
