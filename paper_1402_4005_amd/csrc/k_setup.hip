@@ -463,6 +463,124 @@ __global__ void k_interp_pattern(int n, int nx, int ny, int gkind, int geometric
   for (int q = 0; q < m; ++q) tmp[(size_t)i * cap + q] = out[q];
 }
 
+// Algebraic J_i with a group of W lanes per row (same result as the
+// thread-per-row code above). Row i's neighbour list is staged in LDS; each
+// lane scores its share of the coarse neighbours j (ascending j within the
+// lane) by looking every entry of row j up in the staged row (binary
+// search), and keeps its own best kJCap by (score desc, j asc). The group's
+// lists then go to LDS, where each entry's rank in the group's order is
+// counted: entries ranked below cap are J_i, and since the coarse index
+// increases with j, the position of an entry in row i of P is the number of
+// selected entries with smaller j. Rows longer than kJRow score by the
+// sorted merge instead of the LDS lookup.
+constexpr int kJCap = 8, kJRow = 128, kJThreads = 256;
+
+__device__ __forceinline__ bool jbeats(int s2, int j2, int s1, int j1) {
+  return s2 > s1 || (s2 == s1 && j2 < j1);
+}
+
+template <int W>
+__global__ void __launch_bounds__(kJThreads)
+    k_interp_alg(int n, int cap, const int *__restrict__ cf, const int *__restrict__ cidx,
+                 const int *__restrict__ grp, const int *__restrict__ gci, int *__restrict__ cnt,
+                 int *__restrict__ tmp) {
+  constexpr int G = kJThreads / W;
+  __shared__ int rowbuf[G][kJRow];
+  __shared__ int ls[G][W * kJCap], lj[G][W * kJCap], lr[G][W * kJCap];
+  const int g = threadIdx.x / W, lane = threadIdx.x % W;
+  const int row = blockIdx.x * G + g;
+  const bool live = row < n && !cf[row];
+  const int r0 = row < n ? grp[row] : 0, rlen = row < n ? grp[row + 1] - r0 : 0;
+  const bool staged = rlen <= kJRow;
+  if (live && staged)
+    for (int q = lane; q < rlen; q += W) rowbuf[g][q] = gci[r0 + q];
+  __syncthreads();
+  // this lane's best kJCap candidates, (score desc, j asc)
+  int bs[kJCap], bj[kJCap], nb = 0;
+#pragma unroll
+  for (int q = 0; q < kJCap; ++q) bs[q] = bj[q] = 0;
+  if (live) {
+    for (int k = lane; k < rlen; k += W) {
+      const int j = gci[r0 + k];
+      if (!cf[j]) continue;
+      int sc = 0;
+      if (staged) {
+        for (int b = grp[j]; b < grp[j + 1]; ++b) {
+          const int v = gci[b];
+          int lo = 0, hi = rlen;  // first position with rowbuf >= v
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (rowbuf[g][mid] < v)
+              lo = mid + 1;
+            else
+              hi = mid;
+          }
+          sc += (lo < rlen && rowbuf[g][lo] == v) ? 1 : 0;
+        }
+      } else {
+        sc = common_neighbours(grp, gci, row, j);
+      }
+      int pos = 0;  // entries ahead of (sc, j); j is the largest so far, so ties stay ahead
+#pragma unroll
+      for (int q = 0; q < kJCap; ++q) pos += (q < nb && bs[q] >= sc) ? 1 : 0;
+      if (pos >= cap) continue;
+#pragma unroll
+      for (int q = kJCap - 1; q > 0; --q)
+        if (q > pos && q < cap) {
+          bs[q] = bs[q - 1];
+          bj[q] = bj[q - 1];
+        }
+#pragma unroll
+      for (int q = 0; q < kJCap; ++q)
+        if (q == pos) {
+          bs[q] = sc;
+          bj[q] = j;
+        }
+      if (nb < cap) ++nb;
+    }
+  }
+  // publish the lane's list (score -1 marks an empty slot)
+#pragma unroll
+  for (int q = 0; q < kJCap; ++q) {
+    ls[g][lane * kJCap + q] = q < nb ? bs[q] : -1;
+    lj[g][lane * kJCap + q] = bj[q];
+  }
+  __syncthreads();
+  // rank of each own entry among the group's entries
+  int rk[kJCap];
+#pragma unroll
+  for (int q = 0; q < kJCap; ++q) {
+    rk[q] = 0;
+    if (q >= nb) continue;
+    for (int e = 0; e < W * kJCap; ++e) {
+      const int s2 = ls[g][e];
+      if (s2 >= 0 && jbeats(s2, lj[g][e], bs[q], bj[q])) ++rk[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kJCap; ++q) lr[g][lane * kJCap + q] = q < nb ? rk[q] : 0x7fffffff;
+  __syncthreads();
+  if (row >= n) return;
+  if (cf[row]) {
+    if (lane == 0) {
+      cnt[row] = 1;
+      tmp[(size_t)row * cap] = cidx[row];
+    }
+    return;
+  }
+  int total = 0;  // group entries, computed by every lane alike
+  for (int e = 0; e < W * kJCap; ++e) total += ls[g][e] >= 0 ? 1 : 0;
+  if (lane == 0) cnt[row] = total < cap ? total : cap;
+#pragma unroll
+  for (int q = 0; q < kJCap; ++q) {
+    if (q >= nb || rk[q] >= cap) continue;
+    int p = 0;
+    for (int e = 0; e < W * kJCap; ++e)
+      if (lr[g][e] < cap && lj[g][e] < bj[q]) ++p;
+    tmp[(size_t)row * cap + p] = cidx[bj[q]];
+  }
+}
+
 __global__ void k_pack_rows(int n, int cap, const int *__restrict__ tmp,
                             const int *__restrict__ prp, int *__restrict__ pci) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -476,8 +594,32 @@ void interp_pattern(Pool &pool, const Level &L, int cap, int geometric, Csr &P, 
   if (cap > 16) fail(BAMG_E_ARG, "max_interp above 16");
   int *cnt = pool.get<int>(n);
   int *tmp = pool.get<int>((size_t)n * cap);
-  k_interp_pattern<<<ceil_div(n, 128), 128, 0, s>>>(n, L.nx, L.ny, L.gkind, geometric, cap, L.cf,
-                                                     L.cidx, L.G.rp, L.G.ci, cnt, tmp);
+  if (!geometric && cap <= kJCap) {
+    // lanes per row: the average row length of G, 8 to 64
+    const int w = std::max(8, std::min(64, lanes_for(L.G.nr, L.G.nnz)));
+    const int groups = kJThreads / w;
+    switch (w) {
+      case 8:
+        k_interp_alg<8><<<ceil_div(n, groups), kJThreads, 0, s>>>(n, cap, L.cf, L.cidx, L.G.rp,
+                                                                  L.G.ci, cnt, tmp);
+        break;
+      case 16:
+        k_interp_alg<16><<<ceil_div(n, groups), kJThreads, 0, s>>>(n, cap, L.cf, L.cidx, L.G.rp,
+                                                                   L.G.ci, cnt, tmp);
+        break;
+      case 32:
+        k_interp_alg<32><<<ceil_div(n, groups), kJThreads, 0, s>>>(n, cap, L.cf, L.cidx, L.G.rp,
+                                                                   L.G.ci, cnt, tmp);
+        break;
+      default:
+        k_interp_alg<64><<<ceil_div(n, groups), kJThreads, 0, s>>>(n, cap, L.cf, L.cidx, L.G.rp,
+                                                                   L.G.ci, cnt, tmp);
+        break;
+    }
+  } else {
+    k_interp_pattern<<<ceil_div(n, 128), 128, 0, s>>>(n, L.nx, L.ny, L.gkind, geometric, cap,
+                                                       L.cf, L.cidx, L.G.rp, L.G.ci, cnt, tmp);
+  }
   LAUNCHCHK();
   P.nr = n;
   P.nc = L.nc;
