@@ -145,6 +145,28 @@ def grid2d(nx: int, ny: int) -> Chain:
                        {"deg": deg})
 
 
+def hub_walk(n: int, hubs: int, links: int, seed: int) -> Chain:
+    """Random walk on a ring of ``n`` states (each joined to the states one
+    and two steps away) plus ``hubs`` extra states, each joined to ``links``
+    distinct ring states drawn with numpy's PCG64 seeded by ``seed``.
+    ``a_ij = 1/deg(j)`` for every edge, so pi_i is proportional to deg(i).
+    The hubs give rows far longer than the rest (a stress case for per-row
+    work)."""
+    rng = np.random.default_rng(seed)
+    i = np.arange(n)
+    e = [np.stack([i, (i + 1) % n], 1), np.stack([i, (i + 2) % n], 1)]
+    for h in range(hubs):
+        tgt = rng.choice(n, size=links, replace=False)
+        e.append(np.stack([np.full(links, n + h), tgt], 1))
+    e = np.concatenate(e)
+    src = np.concatenate([e[:, 0], e[:, 1]])
+    dst = np.concatenate([e[:, 1], e[:, 0]])
+    N = n + hubs
+    deg = np.bincount(src, minlength=N).astype(np.float64)
+    return _from_moves(N, src, dst, 1.0 / deg[src], (0, 0, 0), f"hub{n}x{hubs}",
+                       {"deg": deg})
+
+
 def _morton_order(pts: np.ndarray) -> np.ndarray:
     """Permutation that sorts points in [0,1)^2 along a Z-order curve."""
     q = np.minimum((pts * 65536.0).astype(np.uint64), 65535)

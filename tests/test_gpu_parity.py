@@ -66,6 +66,10 @@ CASES = [
     # coarsest 17 x 17 = 289 states: the block Jacobi SVD rather than the LDS solver
     ("tandem65_c289", lambda: chaingen.tandem(65, 11 / 31, 10 / 31, 10 / 31),
      dict(r=8, max_interp=4, coarse_max=300, nu_setup=5)),
+    # eight hubs of degree 200 (F points at level 0): rows longer than the
+    # LDS-staged J_i selection takes, and coarse rows of up to ~400 entries
+    ("hub4000", lambda: chaingen.hub_walk(4000, 8, 200, 7),
+     dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99)),
 ]
 
 
@@ -190,3 +194,15 @@ def test_long_restart_matches_oracle():
     assert io.iterations > 33
     assert abs(ig.iterations - io.iterations) <= 1, (ig.iterations, io.iterations)
     assert rel_l1(xg.cpu().numpy(), xo) < 1e-10
+
+
+def test_hub_rows_are_f_points():
+    """The hub case really takes the long-row path of the J_i selection: its
+    hubs are F points on the finest level (the oracle's splitting, which the
+    structure test matches bit for bit)."""
+    ch = chaingen.hub_walk(4000, 8, 200, 7)
+    ho = oracle.Hierarchy(ch, oracle.options_for(ch, r=8, max_interp=3, nu_pre=5, nu_post=5,
+                                                 nu_setup=5, coarse_max=99))
+    cf = ho.cf(0)[0]
+    assert (cf[4000:] == 0).any()
+    assert ch.indptr[4001] - ch.indptr[4000] > 128

@@ -383,6 +383,18 @@ def test_delaunay_closed_form():
     assert info.iterations < 40
 
 
+def test_hub_walk_closed_form():
+    """A random walk with a few high-degree hubs (long rows on every level):
+    the method still reaches pi proportional to the degree."""
+    ch = chaingen.hub_walk(600, 3, 80, 5)
+    h = oracle.Hierarchy(ch, oracle.options_for(ch, r=8, max_interp=3, nu_pre=5, nu_post=5,
+                                                nu_setup=5, coarse_max=60))
+    x, info = h.gmres(m=20, tol=1e-14, maxit=300)
+    deg = ch.extra["deg"]
+    assert info.converged
+    assert rel_l1(x, deg / deg.sum()) < 1e-10
+
+
 def test_birth_death_closed_form_method():
     n = 257
     ch = chaingen.birth_death(n, 0.96)
