@@ -101,6 +101,11 @@ typedef struct {
   const struct bamg_mlp *mlp; /* network for BAMG_LEARNED_USE, else ignored */
   int32_t autotune;     /* 1 = time the lanes-per-row choices of each level's
                            sweeps once per matrix shape (cached per process) */
+  int32_t fuse_last_level; /* 1 = when the level above the coarsest (not the
+                           finest) fits in one workgroup's LDS, its part of the
+                           V-cycle and the coarsest solve run as one launch
+                           (the same steps, Jacobi smoother only); 0 = one
+                           kernel per step */
 } bamg_options;
 
 /* Learned interpolation weights. Not part of the paper: an addition whose

@@ -53,7 +53,7 @@ class Options(C.Structure):
                 ("coarsening", C.c_int32), ("seed", C.c_uint64), ("smoother", C.c_int32),
                 ("precision", C.c_int32), ("interp_rule", C.c_int32), ("validate", C.c_int32),
                 ("use_graph", C.c_int32), ("learned", C.c_int32), ("mlp", C.c_void_p),
-                ("autotune", C.c_int32)]
+                ("autotune", C.c_int32), ("fuse_last_level", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

@@ -163,6 +163,7 @@ bamg_status bamg_default_options(bamg_options *o) {
   o->interp_rule = 1;
   o->validate = 1;
   o->use_graph = 1;
+  o->fuse_last_level = 1;
   return BAMG_OK;
 }
 
@@ -220,6 +221,7 @@ bamg_status bamg_setup(const bamg_csr *A, const bamg_geometry *geom, const bamg_
   h->opt = *opt;
   h->prec = opt->precision == BAMG_PRECISION_MIXED ? 1 : 0;
   h->use_graph = opt->use_graph ? 1 : 0;
+  h->last_fused = opt->fuse_last_level ? 1 : 0;
   h->pool.s = (hipStream_t)hip_stream;
   if (alloc) {
     h->pool.a = *alloc;

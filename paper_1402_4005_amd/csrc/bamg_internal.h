@@ -119,6 +119,7 @@ struct bamg_handle {
   hipGraphExec_t vc_exec = nullptr;   // captured V-cycle: vcin -> gw
   hipStream_t cap_stream = nullptr;   // stream the V-cycle is captured on
   int use_graph = 1;
+  int last_fused = 1;  // one-workgroup cycle on a small last level (option fuse_last_level)
   // event timing of one kernel (bamg_kernel_profile_*)
   int prof_kernel = -1;
   std::vector<hipEvent_t> prof_ev;  // pairs (start, stop)
@@ -288,6 +289,12 @@ inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
 // default lanes per CSR row: the average row length rounded up to a power of two
 int lanes_for(int nr, int nnz);
+
+// the V-cycle of the level above the coarsest and the coarsest solve in one
+// workgroup (k_lastlevel.hip); false when the level does not fit (nothing
+// launched)
+template <class T>
+bool vcycle_last_level(bamg_handle *h, int l, const T *b, T *x, hipStream_t s);
 
 // lanes per CSR row for a level's sweeps, by timing (tune.hip)
 template <class T>

@@ -93,6 +93,7 @@ void vcycle_level(bamg_handle *h, int l, const T *b, T *x, hipStream_t s) {
     coarse_gemv<T>(h->bdag, L.n, b, x, s);
     return;
   }
+  if (h->last_fused && vcycle_last_level<T>(h, l, b, x, s)) return;
   Level &C = h->lv[l + 1];
   const int nu1 = h->opt.nu_pre, nu2 = h->opt.nu_post;
   smooth_steps<T>(h, L, b, x, nu1, true, s);

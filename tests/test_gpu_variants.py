@@ -90,3 +90,46 @@ def test_kaczmarz_matches_oracle(name, make, kw):
     torch.cuda.synchronize()
     assert ig.converged and io.converged
     assert rel_l1(xg.cpu().numpy(), xo) < 1e-10
+
+
+LAST = [
+    ("delaunay20000", lambda: chaingen.delaunay_walk(20000, 5),
+     dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99)),
+    ("tandem65_nu33", lambda: chaingen.tandem(65, 11 / 31, 10 / 31, 10 / 31),
+     dict(r=8, coarse_max=30)),
+    ("tandem65_nu21", lambda: chaingen.tandem(65, 11 / 31, 10 / 31, 10 / 31),
+     dict(r=8, coarse_max=30, nu_pre=2, nu_post=1)),
+    ("tandem65_nu04", lambda: chaingen.tandem(65, 11 / 31, 10 / 31, 10 / 31),
+     dict(r=8, coarse_max=30, nu_pre=0, nu_post=4)),
+    ("delaunay20000_mixed", lambda: chaingen.delaunay_walk(20000, 5),
+     dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99, precision="mixed")),
+]
+
+
+@pytest.mark.parametrize("name,make,kw", LAST, ids=[c[0] for c in LAST])
+def test_fused_last_level_matches_separate_steps(name, make, kw):
+    """The one-workgroup cycle of the level above the coarsest (LDS-resident
+    operator, transfers and pseudo-inverse) against one kernel per step: the
+    same cycle up to the order of partial sums."""
+    import torch
+    ch = make()
+    h0 = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, fuse_last_level=0, **kw))
+    h1 = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, fuse_last_level=1, **kw))
+    assert h1.info()["n"][-2] <= 1024  # the fused path applies
+    mixed = kw.get("precision") == "mixed"
+    dt = torch.float32 if mixed else torch.float64
+    b = torch.from_numpy(np.random.default_rng(11).standard_normal(ch.n)).cuda().to(dt)
+    y0, y1 = h0.vcycle(b).double().cpu().numpy(), h1.vcycle(b).double().cpu().numpy()
+    assert rel_l1(y1, y0) < (1e-5 if mixed else 1e-12), rel_l1(y1, y0)
+    x0, i0 = h0.gmres(restart=20, tol=1e-12, maxit=600)
+    x1, i1 = h1.gmres(restart=20, tol=1e-12, maxit=600)
+    torch.cuda.synchronize()
+    assert i0.converged and i1.converged
+    assert abs(i1.iterations - i0.iterations) <= 1, (i0.iterations, i1.iterations)
+    assert rel_l1(x1.cpu().numpy(), x0.cpu().numpy()) < 1e-10
+    if not mixed:
+        xo, _ = oracle.Hierarchy(ch, oracle.options_for(ch, **kw)).gmres(m=20, tol=1e-12,
+                                                                          maxit=600)
+        assert rel_l1(x1.cpu().numpy(), xo) < 1e-10
+    h0.close()
+    h1.close()
