@@ -207,6 +207,9 @@ def main():
                     help="skip the learned-interpolation comparison run")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1 = time the lanes per CSR row of every level's sweeps at setup")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the V-cycle inside GMRES from a captured HIP graph instead "
+                         "of launching its kernels one by one")
     ap.add_argument("--batch", type=int, default=512,
                     help="chains of the batched workload (--workload batch)")
     ap.add_argument("--streams", type=int, default=0, help="library streams of a batch")
@@ -249,7 +252,8 @@ def main():
 
     def options(precision):
         return bamg.options_for(ch, precision=precision, setup_cycles=args.setup_cycles,
-                                autotune=args.autotune, **wopts)
+                                autotune=args.autotune, use_graph=1 if args.graph else 0,
+                                **wopts)
 
     def step(opts, profile=False):
         h = bamg.Hierarchy(rp, ci, va, ch.geom, opts, stream=stream)

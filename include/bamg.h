@@ -96,7 +96,10 @@ typedef struct {
   int32_t precision;    /* BAMG_PRECISION_FP64 or BAMG_PRECISION_MIXED */
   int32_t interp_rule;  /* 0 = plain LS over J_i, 1 = LS with negative weights removed */
   int32_t validate;     /* 1 = check stochasticity and strong connectivity */
-  int32_t use_graph;    /* 1 = GMRES replays the V-cycle from a captured HIP graph */
+  int32_t use_graph;    /* 1 = GMRES replays the V-cycle from a captured HIP graph;
+                           0 (default) = its kernels are launched one by one (the
+                           host enqueues an iteration ahead, and on MI355X a graph
+                           replay costs more than the launches it saves) */
   int32_t learned;      /* BAMG_LEARNED_*: interpolation weights from an MLP (see below) */
   const struct bamg_mlp *mlp; /* network for BAMG_LEARNED_USE, else ignored */
   int32_t autotune;     /* 1 = time the lanes-per-row choices of each level's

@@ -162,7 +162,7 @@ bamg_status bamg_default_options(bamg_options *o) {
   o->precision = BAMG_PRECISION_FP64;
   o->interp_rule = 1;
   o->validate = 1;
-  o->use_graph = 1;
+  o->use_graph = 0;
   o->fuse_last_level = 1;
   return BAMG_OK;
 }

@@ -133,3 +133,22 @@ def test_fused_last_level_matches_separate_steps(name, make, kw):
         assert rel_l1(x1.cpu().numpy(), xo) < 1e-10
     h0.close()
     h1.close()
+
+
+def test_graph_replay_equals_direct_launches():
+    """GMRES with the V-cycle replayed from a captured HIP graph (use_graph=1)
+    against launching its kernels one by one (the default): the same kernels
+    in the same order, so x and the iteration count are identical."""
+    import torch
+    ch = chaingen.delaunay_walk(20000, 5)
+    kw = dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99)
+    out = []
+    for g in (0, 1):
+        h = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, use_graph=g, **kw))
+        x, info = h.gmres(restart=20, tol=1e-12, maxit=600)
+        torch.cuda.synchronize()
+        assert info.converged
+        out.append((x.cpu().numpy(), info.iterations))
+        h.close()
+    assert out[0][1] == out[1][1]
+    assert np.array_equal(out[0][0], out[1][0])
