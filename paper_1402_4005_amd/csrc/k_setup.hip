@@ -639,7 +639,7 @@ void interp_pattern(Pool &pool, const Level &L, int cap, int geometric, Csr &P, 
 // bitonic-sorted and the distinct columns counted (pass 1) or written
 // (pass 2). The result is the sorted structural product, independent of
 // thread timing.
-constexpr int kSymCap = 4096, kSymListBlocks = 4096;
+constexpr int kSymCap = 4096, kSymListBlocks = 4096, kSymBitWords = 256;
 
 // The number of listed rows is read on the device (nlist), so the host does
 // not wait for it: the grid strides over the list.
@@ -651,6 +651,7 @@ __global__ void __launch_bounds__(64)
                       int *__restrict__ cnt, const int *__restrict__ crp, int *__restrict__ cci,
                       int *__restrict__ overflow) {
   __shared__ int buf[kSymCap];
+  __shared__ unsigned bits[kSymBitWords];
   __shared__ int nbuf;
   const int nl = *nlist, lane = threadIdx.x;
   for (int li = blockIdx.x; li < nl; li += gridDim.x) {
@@ -675,6 +676,52 @@ __global__ void __launch_bounds__(64)
     if (cntv > kSymCap) {
       if (lane == 0) atomicOr(overflow, 1);
       cntv = kSymCap;
+    }
+    // Narrow rows (all columns within kSymBitWords * 32 of the smallest):
+    // mark the columns in an LDS bitmap and read them back in order.
+    int lo = 0x7fffffff, hi = -1;
+    for (int i = lane; i < cntv; i += 64) {
+      lo = min(lo, buf[i]);
+      hi = max(hi, buf[i]);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      lo = min(lo, __shfl_xor(lo, off, 64));
+      hi = max(hi, __shfl_xor(hi, off, 64));
+    }
+    const int words = cntv > 0 ? ((hi - lo) >> 5) + 1 : 0;
+    if (words <= kSymBitWords) {
+      for (int q = lane; q < words; q += 64) bits[q] = 0u;
+      __syncthreads();
+      for (int i = lane; i < cntv; i += 64) {
+        const int d = buf[i] - lo;
+        atomicOr(&bits[d >> 5], 1u << (d & 31));
+      }
+      __syncthreads();
+      int base = 0;
+      const int out0 = FILL ? crp[row] : 0;
+      for (int q0 = 0; q0 < words; q0 += 64) {
+        const int q = q0 + lane;
+        const unsigned wbits = q < words ? bits[q] : 0u;
+        // exclusive prefix of the popcounts over the wave
+        int c = __popc(wbits), incl = c;
+        for (int off = 1; off < 64; off <<= 1) {
+          const int v = __shfl_up(incl, off, 64);
+          if (lane >= off) incl += v;
+        }
+        if (FILL) {
+          unsigned m = wbits;
+          int o = out0 + base + incl - c;
+          while (m) {
+            const int b = __ffs(m) - 1;
+            cci[o++] = lo + (q << 5) + b;
+            m &= m - 1;
+          }
+        }
+        base += __shfl(incl, 63, 64);
+      }
+      if (!FILL && lane == 0) cnt[row] = base;
+      __syncthreads();  // bits, buf and nbuf are reused by the next listed row
+      continue;
     }
     int P2 = 1;
     while (P2 < cntv) P2 <<= 1;
