@@ -635,8 +635,11 @@ void interp_pattern(Pool &pool, const Level &L, int cap, int geometric, Csr &P, 
 
 // ============================================================ SpGEMM symbolic
 // Rows of C = A * B with many product terms: one wave (block of 64) per
-// listed row at a time, every term appends its column to an LDS buffer, the buffer is
-// bitonic-sorted and the distinct columns counted (pass 1) or written
+// listed row at a time. When the row's columns lie within kSymBitWords * 32
+// of each other (the usual case for Galerkin rows), every term sets its
+// column's bit in an LDS bitmap and the set bits are read back in order;
+// otherwise every term appends its column to an LDS buffer, which is
+// bitonic-sorted. The distinct columns are counted (pass 1) or written
 // (pass 2). The result is the sorted structural product, independent of
 // thread timing.
 constexpr int kSymCap = 4096, kSymListBlocks = 4096, kSymBitWords = 256;
@@ -656,45 +659,34 @@ __global__ void __launch_bounds__(64)
   const int nl = *nlist, lane = threadIdx.x;
   for (int li = blockIdx.x; li < nl; li += gridDim.x) {
     const int row = rows[li];
-    if (lane == 0) nbuf = 0;
-    __syncthreads();
-    if (force_diag && lane == 0) {
-      buf[0] = row;
-      nbuf = 1;
-    }
-    __syncthreads();
     const int ab = arp[row], ae = arp[row + 1];
+    // column span of the row's terms: rows of B are sorted, so each term
+    // block contributes its first and last column
+    int lo = force_diag ? row : 0x7fffffff, hi = force_diag ? row : -1;
     for (int a = ab + lane; a < ae; a += 64) {
-      const int k = aci[a];
-      for (int b = brp[k]; b < brp[k + 1]; ++b) {
-        const int pos = atomicAdd(&nbuf, 1);
-        if (pos < kSymCap) buf[pos] = bci[b];
+      const int k = aci[a], b0 = brp[k], b1 = brp[k + 1];
+      if (b1 > b0) {
+        lo = min(lo, bci[b0]);
+        hi = max(hi, bci[b1 - 1]);
       }
-    }
-    __syncthreads();
-    int cntv = nbuf;
-    if (cntv > kSymCap) {
-      if (lane == 0) atomicOr(overflow, 1);
-      cntv = kSymCap;
-    }
-    // Narrow rows (all columns within kSymBitWords * 32 of the smallest):
-    // mark the columns in an LDS bitmap and read them back in order.
-    int lo = 0x7fffffff, hi = -1;
-    for (int i = lane; i < cntv; i += 64) {
-      lo = min(lo, buf[i]);
-      hi = max(hi, buf[i]);
     }
     for (int off = 32; off > 0; off >>= 1) {
       lo = min(lo, __shfl_xor(lo, off, 64));
       hi = max(hi, __shfl_xor(hi, off, 64));
     }
-    const int words = cntv > 0 ? ((hi - lo) >> 5) + 1 : 0;
+    const int words = hi >= lo ? ((hi - lo) >> 5) + 1 : 0;
     if (words <= kSymBitWords) {
+      // Narrow row (all columns within kSymBitWords * 32 of the smallest):
+      // mark every term's column in an LDS bitmap, read them back in order.
       for (int q = lane; q < words; q += 64) bits[q] = 0u;
       __syncthreads();
-      for (int i = lane; i < cntv; i += 64) {
-        const int d = buf[i] - lo;
-        atomicOr(&bits[d >> 5], 1u << (d & 31));
+      if (force_diag && lane == 0) atomicOr(&bits[(row - lo) >> 5], 1u << ((row - lo) & 31));
+      for (int a = ab + lane; a < ae; a += 64) {
+        const int k = aci[a];
+        for (int b = brp[k]; b < brp[k + 1]; ++b) {
+          const int d = bci[b] - lo;
+          atomicOr(&bits[d >> 5], 1u << (d & 31));
+        }
       }
       __syncthreads();
       int base = 0;
@@ -712,16 +704,37 @@ __global__ void __launch_bounds__(64)
           unsigned m = wbits;
           int o = out0 + base + incl - c;
           while (m) {
-            const int b = __ffs(m) - 1;
-            cci[o++] = lo + (q << 5) + b;
+            const int bb = __ffs(m) - 1;
+            cci[o++] = lo + (q << 5) + bb;
             m &= m - 1;
           }
         }
         base += __shfl(incl, 63, 64);
       }
       if (!FILL && lane == 0) cnt[row] = base;
-      __syncthreads();  // bits, buf and nbuf are reused by the next listed row
+      __syncthreads();  // bits is reused by the next listed row
       continue;
+    }
+    // wide row: gather the terms and sort them
+    if (lane == 0) nbuf = 0;
+    __syncthreads();
+    if (force_diag && lane == 0) {
+      buf[0] = row;
+      nbuf = 1;
+    }
+    __syncthreads();
+    for (int a = ab + lane; a < ae; a += 64) {
+      const int k = aci[a];
+      for (int b = brp[k]; b < brp[k + 1]; ++b) {
+        const int pos = atomicAdd(&nbuf, 1);
+        if (pos < kSymCap) buf[pos] = bci[b];
+      }
+    }
+    __syncthreads();
+    int cntv = nbuf;
+    if (cntv > kSymCap) {
+      if (lane == 0) atomicOr(overflow, 1);
+      cntv = kSymCap;
     }
     int P2 = 1;
     while (P2 < cntv) P2 <<= 1;
