@@ -7,9 +7,10 @@
 //    correction (eq. coarse_grid_correction), from the SVD of B_L with the
 //    one zero singular value (1^T B_L = 0, Section 5) dropped.
 // The SVD is one-sided Jacobi (Hestenes): column pairs of W are rotated until
-// orthogonal. Pairs follow the round-robin (circle) schedule, so one round
-// rotates n/2 disjoint pairs in parallel, one workgroup per pair, with a
-// grid-wide barrier between rounds (cooperative launch).
+// orthogonal. Blocks of columns are paired by the round-robin (circle)
+// schedule, so one round treats disjoint block pairs in parallel, one
+// workgroup per block pair, with a grid-wide barrier between rounds
+// (cooperative launch).
 #include <hip/hip_cooperative_groups.h>
 
 #include <mutex>
@@ -182,38 +183,103 @@ void transpose_dense(const double *A, double *At, int n, hipStream_t s) {
 
 // ------------------------------------------------------------ Jacobi SVD
 // Block one-sided Jacobi. The columns of W are split into blocks of bs
-// columns; the blocks are paired by the round-robin schedule, one workgroup
-// per block pair. A workgroup holds its 2 bs columns in LDS and rotates
-// their pairs (bs disjoint pairs at a time, one wave per pair): in the first
-// round of a sweep all pairs of the 2 bs columns, afterwards only the pairs
-// across the two blocks, so each column pair of W is visited once per
-// sweep. The rotations accumulate in a 2bs x 2bs matrix R, and the matching
-// columns of J are multiplied by R once. Only the block rounds need a
-// grid-wide barrier: a sweep costs about n workgroup barriers and n/bs grid
-// barriers.
+// columns (bs = 8 or 16); the blocks are paired by the round-robin schedule,
+// one workgroup per block pair. A workgroup loads its 2 bs columns Wc into
+// LDS and forms their Gram matrix G = Wcᵀ Wc once (FP64 MFMA). The pair's
+// rotations are then found and applied on G (G <- Jᵀ G J, bs disjoint pairs
+// at a time): in the first round of a sweep all pairs of the 2 bs columns,
+// afterwards only the pairs across the two blocks, so each column pair of W
+// is visited once per sweep. They accumulate in a 2bs x 2bs matrix R, and
+// the columns of W and J are multiplied by R once (FP64 MFMA), from the LDS
+// copy straight to memory. The rotation test and angle are those of
+// one-sided Jacobi: the inner products of the rotated columns are the
+// entries of the rotated G. A sweep ends the iteration when it finds nothing
+// to rotate; its tests are made on Gram matrices formed afresh from W. Only
+// the block rounds need a grid-wide barrier.
 constexpr int kSvdMaxSweeps = 80;
+constexpr int kSvdPref = 12;  // rows of J per thread fetched ahead (n <= 384 entirely)
+
+typedef double svd_d4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int rr_index(int j, int round, int m) {
   return j == 0 ? 0 : 1 + (j - 1 + round) % (m - 1);
 }
 
+// Columns (p, q), p < q, rotated as pair k (0 <= k < bs) in inner round ir
+// (0 <= ir < 2 bs - 1) of a block pair of 2 bs columns, bs a power of two:
+// all pairs by the round-robin schedule (all = true), else column k of the
+// first block with column bs + (k + ir) mod bs. The schedule's remainders
+// are taken by one conditional subtraction, not an integer division.
+__device__ __forceinline__ void svd_pair(int k, int ir, int bs, bool all, int &p, int &q) {
+  if (!all) {
+    p = k;
+    q = bs + ((k + ir) & (bs - 1));
+    return;
+  }
+  const int m1 = 2 * bs - 1;
+  int a = 0;
+  if (k != 0) {
+    a = k - 1 + ir;
+    if (a >= m1) a -= m1;
+    ++a;
+  }
+  int b = m1 - 1 - k + ir;  // position 2 bs - 1 - k >= 1
+  if (b >= m1) b -= m1;
+  ++b;
+  p = a < b ? a : b;
+  q = a < b ? b : a;
+}
+
+// One-sided Jacobi rotation of columns p < q with inner products
+// al = |w_p|^2, be = |w_q|^2, ga = w_p . w_q: (c, s) with w_p <- c w_p - s w_q,
+// w_q <- s w_p + c w_q, zeroing the new inner product; none when the pair is
+// orthogonal to the tolerance (|ga| <= tol sqrt(al be)).
+__device__ __forceinline__ bool svd_rotation(double al, double be, double ga, double &c,
+                                             double &sn) {
+  const double tol = 1e-15;
+  c = 1.0;
+  sn = 0.0;
+  if (ga == 0.0 || ga * ga <= tol * tol * (al * be)) return false;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  c = rsqrt(1.0 + t * t);
+  sn = c * t;
+  return true;
+}
+
+// D (16 x 16 tile) += A B over k = 4 k0 .. 4 k1 - 1 with A[i][k] = a(i, k),
+// B[k][j] = b(k, j); lane l supplies A[l % 16][k] and B[k][l % 16] for
+// k = 4 kk + l / 16 and receives D[l / 16 + 4 r][l % 16] in acc[r].
+template <class FA, class FB>
+__device__ __forceinline__ svd_d4 mfma_tile(int k0, int k1, FA a, FB b, svd_d4 acc) {
+  const int l = threadIdx.x % kWave;
+#pragma unroll 4
+  for (int kk = k0; kk < k1; ++kk) {
+    const int k = 4 * kk + l / 16;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a(l % 16, k), b(k, l % 16), acc, 0, 0, 0);
+  }
+  return acc;
+}
+
 // W and J column-major n x n; nbp = number of column blocks rounded up to
 // even (columns >= n are zero and never written). ctrl[s] counts rotations
 // of sweep s; ctrl[kSvdMaxSweeps] receives the number of sweeps run.
-// blockDim.x = 64 * bs; dynamic LDS = (2 bs n + 4 bs^2) doubles.
+// blockDim.x = 64 bs with bs = 8 or 16; dynamic LDS = block_jacobi_lds().
 __global__ void __launch_bounds__(1024)
     k_block_jacobi_svd(double *__restrict__ W, double *__restrict__ J, double *__restrict__ W2,
                        double *__restrict__ J2, int nmat, int n, int bs, int nbp,
                        int *__restrict__ ctrl) {
   cg::grid_group grid = cg::this_grid();
   extern __shared__ double lds[];
-  const int cols = 2 * bs;
-  double *Ws = lds;                         // column c at Ws + c * n
-  double *R = lds + (size_t)cols * n;       // cols x cols, column-major
-  __shared__ int nrot;
-  const int nt = blockDim.x;
+  const int cols = 2 * bs, cc = cols * cols, nt = blockDim.x, nw = nt / kWave;
   const int wv = threadIdx.x / kWave, ln = threadIdx.x % kWave;
-  const double tol = 1e-15;
+  const int ct = cols / 16;        // 16-column tiles per block pair
+  const int nsl = nw / (ct * ct);  // K-slices of the Gram product
+  double *Ws = lds;                // column c at Ws + c * n
+  double *Ga = Ws + (size_t)cols * n, *Ra = Ga + cc;  // G and R, row-major cols x cols
+  double *part = Ra + cc;                              // nw 16 x 16 partial tiles of G
+  double *rc = part + (size_t)nw * 256, *rs = rc + bs;  // rotation of each pair
+  __shared__ int nrot, need;
   int sweep = 0;
   for (; sweep < kSvdMaxSweeps; ++sweep) {
     for (int round = 0; round < nbp - 1; ++round) {
@@ -225,83 +291,150 @@ __global__ void __launch_bounds__(1024)
         const int ba = rr_index(pr, round, nbp), bb = rr_index(nbp - 1 - pr, round, nbp);
         // local column c -> global column
         auto gcol = [&](int c) { return c < bs ? ba * bs + c : bb * bs + (c - bs); };
-        for (int e = threadIdx.x; e < cols * n; e += nt) {
-          const int c = e / n, i = e % n, g = gcol(c);
-          Ws[e] = g < n ? Wm[(size_t)g * n + i] : 0.0;
+        // 32 threads per column (blockDim.x = 32 cols)
+        const int lc = threadIdx.x / 32, li = threadIdx.x % 32, lg = gcol(lc);
+        {
+          double *dst = Ws + (size_t)lc * n;
+          const double *src = Wm + (size_t)lg * n;
+#pragma unroll 4
+          for (int i = li; i < n; i += 32) dst[i] = lg < n ? src[i] : 0.0;
         }
-        for (int e = threadIdx.x; e < cols * cols; e += nt) R[e] = (e / cols) == (e % cols);
-        if (threadIdx.x == 0) nrot = 0;
-        __syncthreads();
-        // Round 0 of a sweep: every pair of the 2 bs columns (round-robin,
-        // bs disjoint pairs at a time), which covers each block's own pairs
-        // once per sweep. Later rounds: only the bs x bs cross pairs of the
-        // two blocks, column wv of block a with column (wv + ir) mod bs of
-        // block b. Every column pair of W is rotated once per sweep.
-        const int ninner = round == 0 ? cols - 1 : bs;
-        for (int ir = 0; ir < ninner; ++ir) {
-          int p, q;
-          if (round == 0) {
-            p = rr_index(wv, ir, cols);
-            q = rr_index(cols - 1 - wv, ir, cols);
-            if (p > q) {
-              const int x = p;
-              p = q;
-              q = x;
-            }
-          } else {
-            p = wv;
-            q = bs + (wv + ir) % bs;
-          }
-          double *wp = Ws + (size_t)p * n, *wq = Ws + (size_t)q * n;
-          double al = 0.0, be = 0.0, ga = 0.0;
-          for (int i = ln; i < n; i += kWave) {
-            const double x = wp[i], y = wq[i];
-            al += x * x;
-            be += y * y;
-            ga += x * y;
-          }
-          group_sum3(al, be, ga, kWave);
-          if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
-            const double zeta = (be - al) / (2.0 * ga);
-            const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-            for (int i = ln; i < n; i += kWave) {
-              const double x = wp[i], y = wq[i];
-              wp[i] = c * x - sn * y;
-              wq[i] = sn * x + c * y;
-            }
-            double *rp = R + (size_t)p * cols, *rq = R + (size_t)q * cols;
-            for (int i = ln; i < cols; i += kWave) {
-              const double x = rp[i], y = rq[i];
-              rp[i] = c * x - sn * y;
-              rq[i] = sn * x + c * y;
-            }
-            if (ln == 0) atomicAdd(&nrot, 1);
-          }
-          __syncthreads();
-        }
-        for (int e = threadIdx.x; e < cols * n; e += nt) {
-          const int c = e / n, i = e % n, g = gcol(c);
-          if (g < n) Wm[(size_t)g * n + i] = Ws[e];
+        if (threadIdx.x == 0) {
+          nrot = 0;
+          need = 0;
         }
         __syncthreads();
+        // Gram matrix: wave wv forms tile (wv % (ct ct)) over K-slice
+        // wv / (ct ct); the slices are added in order below
+        {
+          const int tile = wv % (ct * ct), sl = wv / (ct * ct);
+          const int ta = tile / ct, tb = tile % ct, ks = (n + 3) / 4;
+          const int k0 = sl * ks / nsl, k1 = (sl + 1) * ks / nsl;
+          svd_d4 acc = {0.0, 0.0, 0.0, 0.0};
+          acc = mfma_tile(
+              k0, k1, [&](int i, int k) { return k < n ? Ws[(size_t)(16 * ta + i) * n + k] : 0.0; },
+              [&](int k, int j) { return k < n ? Ws[(size_t)(16 * tb + j) * n + k] : 0.0; }, acc);
+          for (int r = 0; r < 4; ++r) part[(size_t)wv * 256 + (ln / 16 + 4 * r) * 16 + ln % 16] = acc[r];
+        }
+        __syncthreads();
+        // G[a][b] from the upper-triangle tiles only, so G is exactly
+        // symmetric; R = I; does any pair this visit rotates need it?
+        for (int e = threadIdx.x; e < cc; e += nt) {
+          int a = e / cols, b = e % cols;
+          if (a > b) {
+            const int x = a;
+            a = b;
+            b = x;
+          }
+          const int tile = (a / 16) * ct + b / 16, off = (a % 16) * 16 + b % 16;
+          double g = 0.0;
+          for (int sl = 0; sl < nsl; ++sl) g += part[(size_t)(sl * ct * ct + tile) * 256 + off];
+          Ga[e] = g;
+          Ra[e] = (e / cols) == (e % cols);
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < cc; e += nt) {
+          const int a = e / cols, b = e % cols;
+          if (a < b && (round == 0 || (a < bs && b >= bs))) {
+            double c, sn;
+            if (svd_rotation(Ga[a * cols + a], Ga[b * cols + b], Ga[e], c, sn)) need = 1;
+          }
+        }
+        __syncthreads();
+        // Inner rounds. Wave 0 finds the rotations (lane k: pair k); then
+        // thread (k1, k2) < (bs, bs) rewrites the 2 x 2 block of G at rows
+        // of pair k1 and columns of pair k2 to that of Jᵀ G J, and thread
+        // (r, k2) the two entries of row r of R at pair k2 to those of R J.
+        // The blocks are disjoint, so both updates are made in place.
+        if (need) {
+          const bool all0 = round == 0;
+          const int ninner = all0 ? cols - 1 : bs;
+          for (int ir = 0; ir < ninner; ++ir) {
+            if (wv == 0) {
+              bool did = false;
+              if (ln < bs) {
+                int p, q;
+                svd_pair(ln, ir, bs, all0, p, q);
+                double c, sn;
+                did = svd_rotation(Ga[p * cols + p], Ga[q * cols + q], Ga[p * cols + q], c, sn);
+                rc[ln] = c;
+                rs[ln] = sn;
+              }
+              const unsigned long long m = __ballot(did);
+              if (ln == 0) nrot += __popcll(m);
+            }
+            __syncthreads();
+            const int e = threadIdx.x;
+            if (e < bs * bs) {
+              const int k1 = e / bs, k2 = e % bs;
+              int p1, q1, p2, q2;
+              svd_pair(k1, ir, bs, all0, p1, q1);
+              svd_pair(k2, ir, bs, all0, p2, q2);
+              const double c1 = rc[k1], s1 = rs[k1], c2 = rc[k2], s2 = rs[k2];
+              double *g1 = Ga + p1 * cols, *g2 = Ga + q1 * cols;
+              const double gpp = g1[p2], gpq = g1[q2], gqp = g2[p2], gqq = g2[q2];
+              const double hpp = c1 * gpp - s1 * gqp, hpq = c1 * gpq - s1 * gqq;
+              const double hqp = s1 * gpp + c1 * gqp, hqq = s1 * gpq + c1 * gqq;
+              g1[p2] = c2 * hpp - s2 * hpq;
+              g1[q2] = s2 * hpp + c2 * hpq;
+              g2[p2] = c2 * hqp - s2 * hqq;
+              g2[q2] = s2 * hqp + c2 * hqq;
+            } else if (e < bs * bs + cols * bs) {
+              const int r = (e - bs * bs) / bs, k2 = (e - bs * bs) % bs;
+              int p2, q2;
+              svd_pair(k2, ir, bs, all0, p2, q2);
+              const double c2 = rc[k2], s2 = rs[k2];
+              double *rr = Ra + r * cols;
+              const double x = rr[p2], y = rr[q2];
+              rr[p2] = c2 * x - s2 * y;
+              rr[q2] = s2 * x + c2 * y;
+            }
+            __syncthreads();
+          }
+        }
+        const double *R = Ra;
         if (nrot > 0) {
-          // J[:, pair] = J[:, pair] R, staged through the (now free) W slice
-          for (int e = threadIdx.x; e < cols * n; e += nt) {
-            const int c = e / n, i = e % n, g = gcol(c);
-            Ws[e] = g < n ? Jm[(size_t)g * n + i] : 0.0;
+          // X[:, pair] <- X[:, pair] R for X = W (from Ws), then X = J (loaded
+          // into Ws): output tiles of 16 rows x 16 columns, round-robin over
+          // the waves
+          // J's first kSvdPref * 32 rows are fetched into registers before
+          // the product with W, so their latency overlaps it
+          const int rt = (n + 15) / 16;
+          const double *jsrc = Jm + (size_t)lg * n;
+          double jr[kSvdPref];
+#pragma unroll
+          for (int j = 0; j < kSvdPref; ++j) {
+            const int i = li + 32 * j;
+            jr[j] = lg < n && i < n ? jsrc[i] : 0.0;
           }
-          __syncthreads();
-          for (int e = threadIdx.x; e < cols * n; e += nt) {
-            const int c = e / n, i = e % n, g = gcol(c);
-            if (g >= n) continue;
-            double acc = 0.0;
-            for (int d = 0; d < cols; ++d) acc += Ws[(size_t)d * n + i] * R[(size_t)c * cols + d];
-            Jm[(size_t)g * n + i] = acc;
+          for (int pass = 0; pass < 2; ++pass) {
+            double *__restrict__ Xm = pass == 0 ? Wm : Jm;
+            if (pass == 1) {
+              double *dst = Ws + (size_t)lc * n;
+#pragma unroll
+              for (int j = 0; j < kSvdPref; ++j)
+                if (li + 32 * j < n) dst[li + 32 * j] = jr[j];
+              for (int i = li + 32 * kSvdPref; i < n; i += 32) dst[i] = lg < n ? jsrc[i] : 0.0;
+              __syncthreads();
+            }
+            for (int tl = wv; tl < rt * ct; tl += nw) {
+              const int it = tl / ct, cj = tl % ct;
+              svd_d4 acc = {0.0, 0.0, 0.0, 0.0};
+              acc = mfma_tile(
+                  0, cols / 4,
+                  [&](int i, int k) { return Ws[(size_t)k * n + min(16 * it + i, n - 1)]; },
+                  [&](int k, int j) { return R[k * cols + 16 * cj + j]; }, acc);
+              const int c = 16 * cj + ln % 16, g = gcol(c);
+              for (int r = 0; r < 4; ++r) {
+                const int i = 16 * it + ln / 16 + 4 * r;
+                if (i < n && g < n) Xm[(size_t)g * n + i] = acc[r];
+              }
+            }
+            __syncthreads();
           }
           if (threadIdx.x == 0) atomicAdd(&ctrl[sweep], nrot);
         }
-        __syncthreads();
+        __syncthreads();  // before the next pair resets nrot and need
       }
       grid.sync();
     }
@@ -318,8 +451,11 @@ __global__ void k_identity_dense(double *__restrict__ J, int n) {
   J[e] = (e / n) == (e % n) ? 1.0 : 0.0;
 }
 
+// Ws (2 bs columns), G, R, one 16 x 16 partial tile per wave, and the
+// rotation (c, s) of each of the bs pairs of an inner round
 static size_t block_jacobi_lds(int n, int bs) {
-  return sizeof(double) * ((size_t)2 * bs * n + (size_t)4 * bs * bs);
+  const size_t cols = 2 * (size_t)bs;
+  return sizeof(double) * (cols * n + 2 * cols * cols + (size_t)bs * 256 + 2 * (size_t)bs);
 }
 
 int jacobi_svd(Pool &pool, double *W, double *J, int n, hipStream_t s) {
@@ -333,12 +469,12 @@ int jacobi_svd2(Pool &pool, double *W, double *J, double *W2, double *J2, int n,
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  // Column blocks of bs: 16 when that still gives 32 or more blocks, else 8.
-  // Fewer, wider blocks leave most compute units idle in a round; narrower
-  // ones than 8 add rounds faster than they shorten them (n = 289, tandem
-  // 1025^2 setup: 47.9 ms with bs 16, 45.3 with 8, 57.7 with 4).
-  int bs = ceil_div(n, 16) >= 32 ? 16 : 8;
-  while (bs > 1 && block_jacobi_lds(n, bs) + 256 > (size_t)maxlds) bs >>= 1;
+  // Column blocks of 16 where they fit in LDS (n <= 375), else of 8: with
+  // the rotations made on the Gram matrix a wider block costs little more
+  // per round and halves the rounds (n = 289, tandem 1025^2 setup: 10.4 ms
+  // for both SVDs with 16, 10.5 with 8, before the later tuning).
+  int bs = 16;
+  if (block_jacobi_lds(n, bs) + 256 > (size_t)maxlds) bs = 8;
   if (block_jacobi_lds(n, bs) + 256 > (size_t)maxlds)
     fail(BAMG_E_ARG, "coarsest level too large for the LDS-staged Jacobi SVD");
   const size_t shm = block_jacobi_lds(n, bs);
@@ -544,7 +680,7 @@ __device__ __forceinline__ double wave_sum_all(double v) {
   return v;
 }
 
-// right-looking Cholesky in place (lower, row-major, global memory)
+// right-looking Cholesky in place (lower, row-major), by the whole workgroup
 __device__ void chol_block(double *A, int n, int *flag) {
   __shared__ double piv;
   const int t = threadIdx.x;
@@ -590,17 +726,25 @@ __global__ void __launch_bounds__(kSmallThreads)
   // mode 2: both at once, workgroup 0 the triplets and workgroup 1 the
   // pseudo-inverse (they share only the read-only B)
   if (mode == 2) mode = (int)blockIdx.x;
-  if (mode == 0) {
-    chol_block(Md, n, flag);
-    chol_block(Nd, n, flag);
-  }
+  // Until J^T is set up its LDS rows hold one n x n factor at a time: each
+  // Cholesky runs there (workgroup barriers, no global round trips), is
+  // copied back for the final back-substitutions and used in place for its
+  // triangular solve.
+  double *S = Jt;
+  auto factor = [&](double *A) {
+    for (int e = t; e < n * n; e += blockDim.x) S[e] = A[e];
+    __syncthreads();
+    chol_block(S, n, flag);
+    for (int e = t; e < n * n; e += blockDim.x) A[e] = S[e];
+  };
+  if (mode == 0) factor(Nd);
   // Y = L_N^-1 B^T (column j per thread), stored in C
   for (int j = t; j < n; j += blockDim.x) {
     for (int i = 0; i < n; ++i) {
       double s = Bd[j * n + i];
       if (mode == 0) {
-        for (int k = 0; k < i; ++k) s -= Nd[i * n + k] * C[k * ld + j];
-        s /= Nd[i * n + i];
+        for (int k = 0; k < i; ++k) s -= S[i * n + k] * C[k * ld + j];
+        s /= S[i * n + i];
       }
       C[i * ld + j] = s;
     }
@@ -608,13 +752,15 @@ __global__ void __launch_bounds__(kSmallThreads)
   __syncthreads();
   // C = Y L_M^-T (row i per thread, in place)
   if (mode == 0) {
+    factor(Md);
     for (int i = t; i < n; i += blockDim.x) {
       for (int k = 0; k < n; ++k) {
         double s = C[i * ld + k];
-        for (int j = 0; j < k; ++j) s -= Md[k * n + j] * C[i * ld + j];
-        C[i * ld + k] = s / Md[k * n + k];
+        for (int j = 0; j < k; ++j) s -= S[k * n + j] * C[i * ld + j];
+        C[i * ld + k] = s / S[k * n + k];
       }
     }
+    __syncthreads();
   }
   for (int e = t; e < n * ld; e += blockDim.x) Jt[e] = (e / ld == e % ld) ? 1.0 : 0.0;
   __syncthreads();
