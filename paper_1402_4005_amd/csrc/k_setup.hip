@@ -99,9 +99,10 @@ __global__ void k_colsum_check(const int *__restrict__ trp, const int *__restric
 // Reachability from state 0, forward (block 0, rows of B) and backward
 // (block 1, rows of B^T) in one launch, level-synchronous breadth-first
 // search with the frontier queues in global memory. With LDSMAP the visited
-// set is a bitmap in LDS (n <= kReachLdsStates), so the per-level chain of
-// dependent accesses avoids global atomics.
-constexpr int kReachLdsStates = 1 << 20;
+// set is a bitmap in LDS (whenever it fits: n up to about 1.3 M states), so
+// the per-level chain of dependent accesses avoids global atomics. The
+// global-atomic form is slower and, running beside the setup, slows the
+// setup's own kernels (tandem 1025^2: products 26 -> 172 us while it ran).
 
 template <bool LDSMAP>
 __global__ void __launch_bounds__(1024)
@@ -130,16 +131,26 @@ __global__ void __launch_bounds__(1024)
     const int cn = cur_n;
     for (int idx = t; idx < cn; idx += blockDim.x) {
       const int v = cur[idx];
-      for (int k = rp[v]; k < rp[v + 1]; ++k) {
-        const int u = ci[k];
-        bool fresh;
-        if (LDSMAP) {
-          const unsigned m = 1u << (u & 31);
-          fresh = (atomicOr(&bits[u >> 5], m) & m) == 0;
-        } else {
-          fresh = atomicCAS(&vis[u], 0, 1) == 0;
+      const int e = rp[v + 1];
+      // four neighbours per round: their indices are loaded together
+      // (positions past the row end reload its last entry and are skipped)
+      for (int k = rp[v]; k < e; k += 4) {
+        int us[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) us[j] = ci[min(k + j, e - 1)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (k + j >= e) break;
+          const int u = us[j];
+          bool fresh;
+          if (LDSMAP) {
+            const unsigned m = 1u << (u & 31);
+            fresh = (atomicOr(&bits[u >> 5], m) & m) == 0;
+          } else {
+            fresh = atomicCAS(&vis[u], 0, 1) == 0;
+          }
+          if (fresh) nxt[atomicAdd(&nxt_n, 1)] = u;
         }
-        if (fresh) nxt[atomicAdd(&nxt_n, 1)] = u;
       }
     }
     __syncthreads();
@@ -165,7 +176,7 @@ void reach_launch(const Csr &B, const Csr &Bt, int *visited, int *queues, int *f
   int dev = 0, maxlds = 65536;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  if (n <= kReachLdsStates && shm + 256 <= (size_t)maxlds) {
+  if (shm + 256 <= (size_t)maxlds) {
     HIPCHK(hipFuncSetAttribute((const void *)k_reach2<true>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     k_reach2<true><<<2, 1024, shm, s>>>(B.rp, B.ci, Bt.rp, Bt.ci, n, visited, queues, flag + 1);
