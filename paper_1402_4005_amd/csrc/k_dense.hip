@@ -126,11 +126,14 @@ int cholesky2(double *A0, double *A1, int n, int *flag, hipStream_t s) {
 // Forward substitution L Y = X for the columns of X (n x ncols, row-major,
 // leading dimension ldx), in place. Each workgroup holds a slab of sw
 // columns in LDS and eliminates row by row (right-looking): once row k is
-// final, every later row subtracts L[i][k] times it.
+// final, every later row subtracts L[i][k] times it. The columns of L are
+// staged in LDS pw at a time (rows k0..n-1 of columns k0..k0+pw-1, row
+// stride pw + 1), so a step waits on LDS and a workgroup barrier only.
 __global__ void __launch_bounds__(1024) k_trsm_slab(const double *__restrict__ L,
                                                     double *__restrict__ X, int n, int ncols,
-                                                    int ldx, int sw) {
-  extern __shared__ double xs[];  // n x sw
+                                                    int ldx, int sw, int pw) {
+  extern __shared__ double xs[];  // n x sw, then the panel of L
+  double *lp = xs + (size_t)n * sw;
   const int t = threadIdx.x, nt = blockDim.x;
   const int c = t % sw, ro = t / sw, nro = nt / sw;
   const int col = blockIdx.x * sw + c;
@@ -138,12 +141,21 @@ __global__ void __launch_bounds__(1024) k_trsm_slab(const double *__restrict__ L
     const int i = e / sw, cc = e % sw, g = blockIdx.x * sw + cc;
     xs[e] = g < ncols ? X[(size_t)i * ldx + g] : 0.0;
   }
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    const double xk = xs[k * sw + c] / L[(size_t)k * n + k];
-    if (ro == 0 && col < ncols) X[(size_t)k * ldx + col] = xk;
-    for (int i = k + 1 + ro; i < n; i += nro) xs[i * sw + c] -= L[(size_t)i * n + k] * xk;
+  for (int k0 = 0; k0 < n; k0 += pw) {
+    const int w = min(pw, n - k0);
+    __syncthreads();  // the previous panel is no longer read
+    for (int e = t; e < (n - k0) * w; e += nt) {
+      const int i = e / w, j = e % w;
+      lp[(size_t)i * (pw + 1) + j] = L[(size_t)(k0 + i) * n + k0 + j];
+    }
     __syncthreads();
+    for (int k = k0; k < k0 + w; ++k) {
+      const double *lk = lp + (k - k0);  // column k: lk[(i - k0) * (pw + 1)]
+      const double xk = xs[k * sw + c] / lk[(size_t)(k - k0) * (pw + 1)];
+      if (ro == 0 && col < ncols) X[(size_t)k * ldx + col] = xk;
+      for (int i = k + 1 + ro; i < n; i += nro) xs[i * sw + c] -= lk[(size_t)(i - k0) * (pw + 1)] * xk;
+      __syncthreads();
+    }
   }
 }
 
@@ -151,13 +163,19 @@ void trsm_lower_cols(const double *L, double *X, int n, int ncols, int ldx, hipS
   int dev = 0, maxlds = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  int sw = 32;
-  while (sw > 1 && sizeof(double) * (size_t)n * sw > (size_t)maxlds) sw >>= 1;
-  const size_t shm = sizeof(double) * (size_t)n * sw;
+  // slab of sw columns of X and a panel of pw columns of L (rows padded to
+  // pw + 1): the widest that fit, the panel shrinking first
+  auto bytes = [&](int sw, int pw) {
+    return sizeof(double) * ((size_t)n * sw + (size_t)n * (pw + 1));
+  };
+  int sw = 32, pw = 32;
+  while (pw > 1 && bytes(sw, pw) > (size_t)maxlds) pw >>= 1;
+  while (sw > 1 && bytes(sw, pw) > (size_t)maxlds) sw >>= 1;
+  const size_t shm = bytes(sw, pw);
   if (shm > (size_t)maxlds) fail(BAMG_E_ARG, "trsm: matrix too large for an LDS slab");
   HIPCHK(hipFuncSetAttribute((const void *)k_trsm_slab,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-  k_trsm_slab<<<ceil_div(ncols, sw), 1024, shm, s>>>(L, X, n, ncols, ldx, sw);
+  k_trsm_slab<<<ceil_div(ncols, sw), 1024, shm, s>>>(L, X, n, ncols, ldx, sw, pw);
   LAUNCHCHK();
 }
 
