@@ -192,8 +192,9 @@ void geom_cf(int n, int nx, int gkind, int *cf, hipStream_t s);
 void mis_cf(Pool &pool, const Csr &G, uint64_t seed, int level, int *cf, hipStream_t s);
 int coarse_numbering(Pool &pool, const int *cf, int n, int *cidx, int *&cpts, hipStream_t s);
 void interp_pattern(Pool &pool, const Level &L, int cap, int geometric, Csr &P, hipStream_t s);
-void spgemm_symbolic(Pool &pool, const Csr &A, const Csr &B, int force_diag, Csr &C,
-                     hipStream_t s);
+// C1 = A1 B1 and C2 = A2 B2 (patterns) with one host round trip for both
+void spgemm_symbolic2(Pool &pool, const Csr &A1, const Csr &B1, const Csr &A2, const Csr &B2,
+                      int force_diag, Csr &C1, Csr &C2, hipStream_t s);
 template <class T>
 void spgemm_numeric(const Csr &A, const T *av, const Csr &B, const T *bv, const Csr &C, T *cv,
                     int *scratch, hipStream_t s);  // scratch: A.nr + 1 ints

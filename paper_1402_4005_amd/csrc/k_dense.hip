@@ -271,7 +271,6 @@ __device__ __forceinline__ bool svd_rotation(double al, double be, double ga, do
 template <class FA, class FB>
 __device__ __forceinline__ svd_d4 mfma_tile(int k0, int k1, FA a, FB b, svd_d4 acc) {
   const int l = threadIdx.x % kWave;
-#pragma unroll 4
   for (int kk = k0; kk < k1; ++kk) {
     const int k = 4 * kk + l / 16;
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a(l % 16, k), b(k, l % 16), acc, 0, 0, 0);

@@ -850,51 +850,82 @@ __global__ void k_sym_pack(int nr, const int *__restrict__ tmp,
   for (int q = 0; q < m; ++q) cci[p0 + q] = tmp[(size_t)i * kSymShort + q];
 }
 
-void spgemm_symbolic(Pool &pool, const Csr &A, const Csr &B, int force_diag, Csr &C,
-                     hipStream_t s) {
+// Symbolic product in two halves, so that two independent products share
+// one host round trip: the count half enqueues the row counts, the scan and
+// the copies of the size and the overflow flag to the host; the finish half
+// (after the caller has synchronised s) allocates the column indices and
+// enqueues the packing.
+struct SymJob {
+  const Csr *A = nullptr, *B = nullptr;
+  int force_diag = 0, lgrid = 0;
+  Csr *C = nullptr;
+  int *cnt = nullptr, *tmp = nullptr, *ovf = nullptr, *longrows = nullptr;
+  int hv[2] = {0, 0};  // C's size and the overflow flag, copied by the count half
+};
+
+static void sym_count(Pool &pool, const Csr &A, const Csr &B, int force_diag, Csr &C, SymJob &j,
+                      hipStream_t s) {
   const int nr = A.nr;
-  int *cnt = pool.get<int>(nr);
-  int *tmp = pool.get<int>((size_t)nr * kSymShort);
-  int *ovf = pool.get<int>(2);  // [overflow, long rows]
-  int *longrows = pool.get<int>(nr);
-  fill_i32(ovf, 0, 2, s);
+  j.A = &A;
+  j.B = &B;
+  j.force_diag = force_diag;
+  j.C = &C;
+  j.cnt = pool.get<int>(nr);
+  j.tmp = pool.get<int>((size_t)nr * kSymShort);
+  j.ovf = pool.get<int>(2);  // [overflow, long rows]
+  j.longrows = pool.get<int>(nr);
+  fill_i32(j.ovf, 0, 2, s);
   if (nr) {
     k_spgemm_sym_short<<<ceil_div(nr, kSymThreads), kSymThreads, 0, s>>>(
-        nr, A.rp, A.ci, B.rp, B.ci, force_diag, cnt, tmp, longrows, ovf + 1);
+        nr, A.rp, A.ci, B.rp, B.ci, force_diag, j.cnt, j.tmp, j.longrows, j.ovf + 1);
     LAUNCHCHK();
   }
   // long rows: a strided grid about as wide as the LDS lets stay resident
-  const int lgrid = std::min(nr, kSymListBlocks);
-  if (lgrid > 0) {
-    k_spgemm_sym_list<false><<<lgrid, 64, 0, s>>>(longrows, ovf + 1, A.rp, A.ci, B.rp, B.ci,
-                                                  force_diag, cnt, nullptr, nullptr, ovf);
+  j.lgrid = std::min(nr, kSymListBlocks);
+  if (j.lgrid > 0) {
+    k_spgemm_sym_list<false><<<j.lgrid, 64, 0, s>>>(j.longrows, j.ovf + 1, A.rp, A.ci, B.rp,
+                                                    B.ci, force_diag, j.cnt, nullptr, nullptr,
+                                                    j.ovf);
     LAUNCHCHK();
   }
   C.nr = nr;
   C.nc = B.nc;
   C.rp = pool.get<int>(nr + 1);
-  scan_counts(pool, cnt, C.rp, nr, s);
-  // one host round trip for the size and the overflow flag
-  int hv[2] = {0, 0};
-  HIPCHK(hipMemcpyAsync(&hv[0], C.rp + nr, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&hv[1], ovf, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  if (hv[1]) fail(BAMG_E_ARG, "Galerkin row wider than the symbolic buffer");
-  C.nnz = hv[0];
+  scan_counts(pool, j.cnt, C.rp, nr, s);
+  HIPCHK(hipMemcpyAsync(&j.hv[0], C.rp + nr, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&j.hv[1], j.ovf, sizeof(int), hipMemcpyDeviceToHost, s));
+}
+
+static void sym_finish(Pool &pool, SymJob &j, hipStream_t s) {
+  const Csr &A = *j.A, &B = *j.B;
+  Csr &C = *j.C;
+  const int nr = A.nr;
+  if (j.hv[1]) fail(BAMG_E_ARG, "Galerkin row wider than the symbolic buffer");
+  C.nnz = j.hv[0];
   C.ci = pool.get<int>(C.nnz);
   if (nr) {
-    k_sym_pack<<<ceil_div(nr, 256), 256, 0, s>>>(nr, tmp, C.rp, C.ci);
+    k_sym_pack<<<ceil_div(nr, 256), 256, 0, s>>>(nr, j.tmp, C.rp, C.ci);
     LAUNCHCHK();
   }
-  if (lgrid > 0) {
-    k_spgemm_sym_list<true><<<lgrid, 64, 0, s>>>(longrows, ovf + 1, A.rp, A.ci, B.rp, B.ci,
-                                                 force_diag, nullptr, C.rp, C.ci, ovf);
+  if (j.lgrid > 0) {
+    k_spgemm_sym_list<true><<<j.lgrid, 64, 0, s>>>(j.longrows, j.ovf + 1, A.rp, A.ci, B.rp, B.ci,
+                                                   j.force_diag, nullptr, C.rp, C.ci, j.ovf);
     LAUNCHCHK();
   }
-  pool.release(cnt);
-  pool.release(tmp);
-  pool.release(ovf);
-  pool.release(longrows);
+  pool.release(j.cnt);
+  pool.release(j.tmp);
+  pool.release(j.ovf);
+  pool.release(j.longrows);
+}
+
+void spgemm_symbolic2(Pool &pool, const Csr &A1, const Csr &B1, const Csr &A2, const Csr &B2,
+                      int force_diag, Csr &C1, Csr &C2, hipStream_t s) {
+  SymJob j1, j2;
+  sym_count(pool, A1, B1, force_diag, C1, j1, s);
+  sym_count(pool, A2, B2, force_diag, C2, j2, s);
+  HIPCHK(hipStreamSynchronize(s));
+  sym_finish(pool, j1, s);
+  sym_finish(pool, j2, s);
 }
 
 // ============================================================ SpGEMM numeric

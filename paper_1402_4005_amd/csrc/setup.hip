@@ -404,8 +404,7 @@ void setup_all(bamg_handle *h, const bamg_csr *A, const bamg_geometry *geom) {
       if (L.nc == 0 || L.nc >= L.n) break;
       interp_pattern(pool, L, o.max_interp, geometric ? 1 : 0, L.P, s);
       transpose_pattern(pool, L.P, L.Pc, L.pcperm, s);
-      spgemm_symbolic(pool, L.B, L.P, 0, L.T1, s);
-      spgemm_symbolic(pool, L.M, L.P, 0, L.T2, s);
+      spgemm_symbolic2(pool, L.B, L.P, L.M, L.P, 0, L.T1, L.T2, s);
     }
     Level C;
     {
@@ -414,8 +413,7 @@ void setup_all(bamg_handle *h, const bamg_csr *A, const bamg_geometry *geom) {
       C.gkind = L.gkind;
       C.nx = (L.nx + 1) / 2;
       C.ny = L.gkind == 2 ? (L.ny + 1) / 2 : 1;
-      spgemm_symbolic(pool, L.Pc, L.T1, 1, C.B, s);
-      spgemm_symbolic(pool, L.Pc, L.T2, 1, C.M, s);
+      spgemm_symbolic2(pool, L.Pc, L.T1, L.Pc, L.T2, 1, C.B, C.M, s);
       L.Pv = pool.get<T>(L.P.nnz);
       L.Qtv = pool.get<T>(L.P.nnz);
       L.Ptv = pool.get<T>(L.P.nnz);
