@@ -1,7 +1,9 @@
 // C ABI of the library (include/bamg.h): argument checks, error translation
 // (no exception crosses the boundary), device memory ownership.
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "bamg_internal.h"
 
@@ -82,8 +84,33 @@ void Pool::flush() {
   deferred.clear();
 }
 
+// Pinned blocks are recycled through a process-wide free list rather than
+// freed, so a handle made per solve does not pay for pinning memory (nor a
+// free that may synchronise the device); they last until the process ends.
+namespace {
+std::mutex g_pin_mu;
+std::vector<int *> g_pin_free;
+}  // namespace
+
+int *Pool::pinned() {
+  if (!hpin) {
+    std::lock_guard<std::mutex> g(g_pin_mu);
+    if (!g_pin_free.empty()) {
+      hpin = g_pin_free.back();
+      g_pin_free.pop_back();
+    }
+  }
+  if (!hpin) HIPCHK(hipHostMalloc((void **)&hpin, sizeof(int) * kPinnedInts, hipHostMallocDefault));
+  return hpin;
+}
+
 void Pool::release_all() {
   (void)hipStreamSynchronize(s);
+  if (hpin) {
+    std::lock_guard<std::mutex> g(g_pin_mu);
+    g_pin_free.push_back(hpin);
+    hpin = nullptr;
+  }
   for (void *p : live) free_one(*this, p);
   live.clear();
   deferred.clear();

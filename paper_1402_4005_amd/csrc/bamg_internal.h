@@ -53,6 +53,12 @@ struct Pool {
   void release(void *p);          // defer the free of a temporary
   void flush();                   // synchronise s, then free the deferred
   void release_all();
+  // kPinnedInts ints of pinned host memory for device-to-host copies of
+  // sizes and flags: copies into it are queued without staging, so several
+  // of them need one synchronisation only
+  static constexpr int kPinnedInts = 64;
+  int *hpin = nullptr;
+  int *pinned();
 };
 
 struct Csr {

@@ -191,7 +191,7 @@ void reach_launch(const Csr &B, const Csr &Bt, int *visited, int *queues, int *f
 // values finite and non-negative) before anything indexes through it.
 int check_input(Pool &pool, const int *arp, const int *aci, const double *aval, int n, int nnz,
                 hipStream_t s) {
-  int ends[2];
+  int *ends = pool.pinned();
   HIPCHK(hipMemcpyAsync(&ends[0], arp, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&ends[1], arp + n, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -860,12 +860,13 @@ struct SymJob {
   int force_diag = 0, lgrid = 0;
   Csr *C = nullptr;
   int *cnt = nullptr, *tmp = nullptr, *ovf = nullptr, *longrows = nullptr;
-  int hv[2] = {0, 0};  // C's size and the overflow flag, copied by the count half
+  int *hv = nullptr;  // pinned: C's size and the overflow flag, copied by the count half
 };
 
 static void sym_count(Pool &pool, const Csr &A, const Csr &B, int force_diag, Csr &C, SymJob &j,
-                      hipStream_t s) {
+                      int *hv, hipStream_t s) {
   const int nr = A.nr;
+  j.hv = hv;
   j.A = &A;
   j.B = &B;
   j.force_diag = force_diag;
@@ -921,8 +922,9 @@ static void sym_finish(Pool &pool, SymJob &j, hipStream_t s) {
 void spgemm_symbolic2(Pool &pool, const Csr &A1, const Csr &B1, const Csr &A2, const Csr &B2,
                       int force_diag, Csr &C1, Csr &C2, hipStream_t s) {
   SymJob j1, j2;
-  sym_count(pool, A1, B1, force_diag, C1, j1, s);
-  sym_count(pool, A2, B2, force_diag, C2, j2, s);
+  int *hv = pool.pinned();
+  sym_count(pool, A1, B1, force_diag, C1, j1, hv, s);
+  sym_count(pool, A2, B2, force_diag, C2, j2, hv + 2, s);
   HIPCHK(hipStreamSynchronize(s));
   sym_finish(pool, j1, s);
   sym_finish(pool, j2, s);
