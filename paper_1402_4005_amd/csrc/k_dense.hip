@@ -730,7 +730,8 @@ template <class T>
 __global__ void __launch_bounds__(kSmallThreads)
     k_coarse_small(int mode, int n, int r, const double *__restrict__ Bd, double *__restrict__ Md,
                    double *__restrict__ Nd, T *__restrict__ U, T *__restrict__ V,
-                   double *__restrict__ sigma, double *__restrict__ bdag, int *__restrict__ flag) {
+                   double *__restrict__ sigma, double *__restrict__ bdag, int *__restrict__ flag,
+                   int gram) {
   extern __shared__ double lds[];
   const int ld = n + 1;
   double *C = lds;                 // n x ld
@@ -755,10 +756,13 @@ __global__ void __launch_bounds__(kSmallThreads)
     for (int e = t; e < n * n; e += blockDim.x) A[e] = S[e];
   };
   if (mode == 0) factor(Nd);
-  // Y = L_N^-1 B^T (column j per thread), stored in C
+  // Y = L_N^-1 B^T (column j per thread), stored in C; B^T is copied into C
+  // first by the whole workgroup
+  for (int e = t; e < n * n; e += blockDim.x) C[(e % n) * ld + e / n] = Bd[e];
+  __syncthreads();
   for (int j = t; j < n; j += blockDim.x) {
     for (int i = 0; i < n; ++i) {
-      double s = Bd[j * n + i];
+      double s = C[i * ld + j];
       if (mode == 0) {
         for (int k = 0; k < i; ++k) s -= S[i * n + k] * C[k * ld + j];
         s /= S[i * n + i];
@@ -787,7 +791,113 @@ __global__ void __launch_bounds__(kSmallThreads)
   const int grp = t / kPairLanes, gl = t % kPairLanes, ngrp = kSmallThreads / kPairLanes;
   const int m = n + (n & 1);
   const double tol = 1e-15;
-  for (int sweep = 0; sweep < 80; ++sweep) {
+  if (gram) {
+    // The same sweeps with the inner products taken from the Gram matrix
+    // G = C Cᵀ, formed afresh at the start of each sweep (so a sweep that
+    // rotates nothing has tested fresh inner products). Per round, lane k of
+    // wave 0 finds pair k's rotation from G; then the rows of C and Jᵀ are
+    // rotated and G's 2 x 2 blocks rewritten to Jᵀ G J, in place.
+    const int gld = m + 1, np = m / 2;
+    double *G = sv + n;                 // m x gld
+    double *rc = G + (size_t)m * gld;   // per pair: c, s
+    double *rs = rc + np;
+    int *pp = reinterpret_cast<int *>(rs + np), *qq = pp + np;
+    // this thread's tasks, the same every round (at most kTasks of each kind)
+    constexpr int kTasks = 4;
+    int rk[kTasks], ri[kTasks], g1k[kTasks], g2k[kTasks];
+#pragma unroll
+    for (int u = 0; u < kTasks; ++u) {
+      const int e = t + u * (int)blockDim.x;
+      rk[u] = e < np * n ? e / n : -1;
+      ri[u] = e < np * n ? e % n : 0;
+      g1k[u] = e < np * np ? e / np : -1;
+      g2k[u] = e < np * np ? e % np : 0;
+    }
+    for (int sweep = 0; sweep < 80; ++sweep) {
+      if (t == 0) rotated = 0;
+      for (int e = t; e < m * m; e += blockDim.x) {
+        const int a = e / m, b = e % m;
+        if (a > b) continue;
+        double g = 0.0;
+        if (b < n)
+          for (int i = 0; i < n; ++i) g += C[a * ld + i] * C[b * ld + i];
+        G[a * gld + b] = g;
+        G[b * gld + a] = g;
+      }
+      __syncthreads();
+      for (int round = 0; round < m - 1; ++round) {
+        if (w == 0 && lane < np) {
+          // round-robin positions lane and m - 1 - lane, remainders mod m - 1
+          // by one conditional subtraction
+          int p = 0, q = m - 1 - lane + round - 1;
+          if (lane != 0) {
+            p = lane - 1 + round;
+            if (p >= m - 1) p -= m - 1;
+            ++p;
+          }
+          if (q >= m - 1) q -= m - 1;
+          ++q;
+          if (p > q) {
+            const int x = p;
+            p = q;
+            q = x;
+          }
+          double c = 1.0, sn = 0.0;
+          const double al = G[p * gld + p], be = G[q * gld + q], ga = G[p * gld + q];
+          if (q < n && ga != 0.0 && ga * ga > tol * tol * (al * be)) {
+            // tan of the smaller rotation angle, with one division
+            const double d = be - al;
+            const double tt = (d >= 0 ? 2.0 : -2.0) * ga / (fabs(d) + sqrt(d * d + 4.0 * ga * ga));
+            c = rsqrt(1.0 + tt * tt);
+            sn = c * tt;
+            rotated = 1;
+          }
+          rc[lane] = c;
+          rs[lane] = sn;
+          pp[lane] = p;
+          qq[lane] = q;
+        }
+        __syncthreads();
+        // rows of C and Jᵀ: task (k, i), i < n
+#pragma unroll
+        for (int u = 0; u < kTasks; ++u) {
+          const int k = rk[u], i = ri[u];
+          if (k < 0) continue;
+          const int p = pp[k], q = qq[k];
+          const double c = rc[k], sn = rs[k];
+          if (sn == 0.0) continue;
+          const double a = C[p * ld + i], b = C[q * ld + i];
+          C[p * ld + i] = c * a - sn * b;
+          C[q * ld + i] = sn * a + c * b;
+          const double x = Jt[p * ld + i], y = Jt[q * ld + i];
+          Jt[p * ld + i] = c * x - sn * y;
+          Jt[q * ld + i] = sn * x + c * y;
+        }
+        // G: the 2 x 2 block of pairs (k1, k2)
+#pragma unroll
+        for (int u = 0; u < kTasks; ++u) {
+          const int k1 = g1k[u], k2 = g2k[u];
+          if (k1 < 0) continue;
+          const int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
+          const double c1 = rc[k1], s1 = rs[k1], c2 = rc[k2], s2 = rs[k2];
+          double *g1 = G + p1 * gld, *g2 = G + q1 * gld;
+          const double gpp = g1[p2], gpq = g1[q2], gqp = g2[p2], gqq = g2[q2];
+          const double hpp = c1 * gpp - s1 * gqp, hpq = c1 * gpq - s1 * gqq;
+          const double hqp = s1 * gpp + c1 * gqp, hqq = s1 * gpq + c1 * gqq;
+          g1[p2] = c2 * hpp - s2 * hpq;
+          g1[q2] = s2 * hpp + c2 * hpq;
+          g2[p2] = c2 * hqp - s2 * hqq;
+          g2[q2] = s2 * hqp + c2 * hqq;
+        }
+        __syncthreads();
+      }
+      const int any = rotated;
+      __syncthreads();
+      if (!any) break;
+      if (sweep == 79 && t == 0) atomicOr(flag, 2);
+    }
+  }
+  for (int sweep = 0; sweep < 80 && !gram; ++sweep) {
     if (t == 0) rotated = 0;
     __syncthreads();
     for (int round = 0; round < m - 1; ++round) {
@@ -863,16 +973,16 @@ __global__ void __launch_bounds__(kSmallThreads)
     }
     return;
   }
-  if (t == 0) {
-    for (int q = 0; q < r; ++q) {
-      int best = -1;
-      for (int k = 0; k < n; ++k) {
-        bool taken = false;
-        for (int z = 0; z < q; ++z) taken |= (order[z] == k);
-        if (!taken && (best < 0 || sv[k] < sv[best])) best = k;
-      }
-      order[q] = best;
-    }
+  // the r smallest singular values in ascending order, ties by index: the
+  // value of rank q (strictly smaller ones, or equal ones of lower index).
+  // Every slot first holds a valid row, in case non-finite values leave a
+  // rank unassigned.
+  if (t < r) order[t] = t < n ? t : n - 1;
+  __syncthreads();
+  for (int k = t; k < n; k += blockDim.x) {
+    int rank = 0;
+    for (int j = 0; j < n; ++j) rank += sv[j] < sv[k] || (sv[j] == sv[k] && j < k);
+    if (rank < r) order[rank] = k;
   }
   __syncthreads();
   // back-substitutions: wave 2q solves L_M^T u = C_k / sigma_k, wave 2q+1
@@ -912,6 +1022,12 @@ __global__ void __launch_bounds__(kSmallThreads)
 }
 
 size_t coarse_small_lds(int n) { return sizeof(double) * ((size_t)2 * n * (n + 1) + n); }
+// with the Gram matrix (m = n rounded up to even, row stride m + 1), the
+// rotations (c, s) and the pairs (p, q) of a round
+static size_t coarse_small_gram_lds(int n) {
+  const size_t m = n + (n & 1);
+  return coarse_small_lds(n) + sizeof(double) * (m * (m + 1) + m) + sizeof(int) * m;
+}
 
 int coarse_small_max(void) {
   static const int nmax = [] {  // thread-safe one-time initialisation
@@ -928,18 +1044,28 @@ int coarse_small_max(void) {
 
 int coarse_small(int mode, int n, int r, const double *Bd, double *Md, double *Nd, void *U,
                  void *V, int prec, double *sigma, double *bdag, int *flag, hipStream_t s) {
-  const size_t shm = coarse_small_lds(n);
+  int dev = 0, maxlds = 65536;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  // the Gram form where it fits in LDS and each thread has at most 4 row
+  // tasks and 4 block tasks per round (n <= 80 on 160 KB of LDS)
+  const int np = (n + (n & 1)) / 2;
+  const int gram = coarse_small_gram_lds(n) + 1024 <= (size_t)maxlds &&
+                           np * n <= 4 * kSmallThreads && np * np <= 4 * kSmallThreads
+                       ? 1
+                       : 0;
+  const size_t shm = gram ? coarse_small_gram_lds(n) : coarse_small_lds(n);
   fill_i32(flag, 0, 1, s);
   if (prec == 0) {
     HIPCHK(hipFuncSetAttribute((const void *)k_coarse_small<double>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     k_coarse_small<double><<<mode == 2 ? 2 : 1, kSmallThreads, shm, s>>>(
-        mode, n, r, Bd, Md, Nd, (double *)U, (double *)V, sigma, bdag, flag);
+        mode, n, r, Bd, Md, Nd, (double *)U, (double *)V, sigma, bdag, flag, gram);
   } else {
     HIPCHK(hipFuncSetAttribute((const void *)k_coarse_small<float>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     k_coarse_small<float><<<mode == 2 ? 2 : 1, kSmallThreads, shm, s>>>(
-        mode, n, r, Bd, Md, Nd, (float *)U, (float *)V, sigma, bdag, flag);
+        mode, n, r, Bd, Md, Nd, (float *)U, (float *)V, sigma, bdag, flag, gram);
   }
   LAUNCHCHK();
   const int f = read_int(flag, s);
