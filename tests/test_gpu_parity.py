@@ -143,6 +143,29 @@ def test_coarse_pinv_block_jacobi_matches_numpy():
     assert rel_max(hg.coarse_pinv(), ref) < 1e-9
 
 
+def test_coarse_pinv_block_jacobi_narrow_blocks_matches_numpy():
+    """441-state coarsest level: too wide for 16-column blocks in LDS, so the
+    Jacobi SVD runs on 8-column blocks, and the triangular solves stage
+    narrower panels of the Cholesky factors. The pseudo-inverse matches
+    numpy's, and the stationary vector the oracle's."""
+    import torch
+    ch = chaingen.tandem(81, 11 / 31, 10 / 31, 10 / 31)
+    kw = dict(r=8, max_interp=4, coarse_max=450, nu_setup=5)
+    ho, hg = both(ch, **kw)
+    L = hg.levels - 1
+    BL = hg.scipy(L, "B").toarray()
+    assert BL.shape == (441, 441)
+    ref = np.linalg.pinv(BL, rcond=1e-10)
+    assert rel_max(hg.coarse_pinv(), ref) < 1e-9
+    so, sg = ho.sigma(), hg.sigma()
+    assert np.allclose(np.sort(np.abs(sg)), np.sort(np.abs(so)), rtol=1e-6, atol=1e-12)
+    xo, io = ho.gmres(m=20, tol=1e-14, maxit=400)
+    xg, ig = hg.gmres(restart=20, tol=1e-14, maxit=400)
+    torch.cuda.synchronize()
+    assert io.converged and ig.converged
+    assert rel_l1(xg.cpu().numpy(), xo) < 1e-10
+
+
 def test_error_codes():
     ch = chaingen.tandem(6, 11 / 31, 10 / 31, 10 / 31)
     bad = chaingen.Chain(ch.to_scipy() * 1.01, ch.geom)
