@@ -164,13 +164,18 @@ void trsm_lower_cols(const double *L, double *X, int n, int ncols, int ldx, hipS
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   // slab of sw columns of X and a panel of pw columns of L (rows padded to
-  // pw + 1): the widest that fit, the panel shrinking first
+  // pw + 1): the widest that fit, the panel shrinking to 8 first, then the
+  // slab to 8, then either further
   auto bytes = [&](int sw, int pw) {
     return sizeof(double) * ((size_t)n * sw + (size_t)n * (pw + 1));
   };
   int sw = 32, pw = 32;
-  while (pw > 1 && bytes(sw, pw) > (size_t)maxlds) pw >>= 1;
-  while (sw > 1 && bytes(sw, pw) > (size_t)maxlds) sw >>= 1;
+  while (bytes(sw, pw) > (size_t)maxlds && (sw > 1 || pw > 1)) {
+    if (pw > 8 || (sw <= 8 && pw > 1))
+      pw >>= 1;
+    else
+      sw >>= 1;
+  }
   const size_t shm = bytes(sw, pw);
   if (shm > (size_t)maxlds) fail(BAMG_E_ARG, "trsm: matrix too large for an LDS slab");
   HIPCHK(hipFuncSetAttribute((const void *)k_trsm_slab,
@@ -486,10 +491,11 @@ int jacobi_svd2(Pool &pool, double *W, double *J, double *W2, double *J2, int n,
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  // Column blocks of 16 where they fit in LDS (n <= 375), else of 8: with
-  // the rotations made on the Gram matrix a wider block costs little more
-  // per round and halves the rounds (n = 289, tandem 1025^2 setup: 10.4 ms
-  // for both SVDs with 16, 10.5 with 8, before the later tuning).
+  // Column blocks of 16 where they fit in LDS (n <= 446 on 160 KB), else of
+  // 8 (n <= 1117): with the rotations made on the Gram matrix a wider block
+  // costs little more per round and halves the rounds (n = 289, tandem
+  // 1025^2 setup: 10.4 ms for both SVDs with 16, 10.5 with 8, before the
+  // later tuning).
   int bs = 16;
   if (block_jacobi_lds(n, bs) + 256 > (size_t)maxlds) bs = 8;
   if (block_jacobi_lds(n, bs) + 256 > (size_t)maxlds)

@@ -143,18 +143,20 @@ def test_coarse_pinv_block_jacobi_matches_numpy():
     assert rel_max(hg.coarse_pinv(), ref) < 1e-9
 
 
-def test_coarse_pinv_block_jacobi_narrow_blocks_matches_numpy():
-    """441-state coarsest level: too wide for 16-column blocks in LDS, so the
-    Jacobi SVD runs on 8-column blocks, and the triangular solves stage
-    narrower panels of the Cholesky factors. The pseudo-inverse matches
-    numpy's, and the stationary vector the oracle's."""
+@pytest.mark.parametrize("N,coarse_max,nc", [(81, 450, 441), (97, 700, 625)],
+                         ids=["c441", "c625"])
+def test_coarse_pinv_block_jacobi_wide_levels_match_numpy(N, coarse_max, nc):
+    """Wider coarsest levels. 441 states: the widest that 16-column blocks
+    fit in LDS. 625 states: 8-column blocks, J fetched ahead only in part,
+    and the triangular solves on narrower slabs and panels. The
+    pseudo-inverse matches numpy's, and the stationary vector the oracle's."""
     import torch
-    ch = chaingen.tandem(81, 11 / 31, 10 / 31, 10 / 31)
-    kw = dict(r=8, max_interp=4, coarse_max=450, nu_setup=5)
+    ch = chaingen.tandem(N, 11 / 31, 10 / 31, 10 / 31)
+    kw = dict(r=8, max_interp=4, coarse_max=coarse_max, nu_setup=5)
     ho, hg = both(ch, **kw)
     L = hg.levels - 1
     BL = hg.scipy(L, "B").toarray()
-    assert BL.shape == (441, 441)
+    assert BL.shape == (nc, nc)
     ref = np.linalg.pinv(BL, rcond=1e-10)
     assert rel_max(hg.coarse_pinv(), ref) < 1e-9
     so, sg = ho.sigma(), hg.sigma()
