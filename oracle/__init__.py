@@ -79,6 +79,9 @@ def lib():
         _lib.orc_uniform_pm1.restype = C.c_double
         for name in ("orc_ls_row", "orc_ls_row_sum1"):
             getattr(_lib, name).argtypes = [C.c_int, C.c_int] + [C.c_void_p] * 4
+        _lib.orc_fit_point.argtypes = [C.c_int, C.c_int, C.c_int] + [C.c_void_p] * 3 + \
+            [C.c_int, C.c_void_p]
+        _lib.orc_rayleigh_sigma.argtypes = [C.c_int] + [C.c_void_p] * 12
         _lib.orc_gsvd.argtypes = [C.c_int] + [C.c_void_p] * 6
         _lib.orc_svd_jacobi.argtypes = [C.c_int] + [C.c_void_p] * 4
         _lib.orc_mis.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_uint64, C.c_int, C.c_void_p]
@@ -276,6 +279,37 @@ def ls_row_sum1(G, g, w):
     if st:
         raise OracleError(st)
     return q
+
+
+def fit_point(G, g, w, rule=1, sum1=False):
+    """One F point's weights as the setup fits them (rule 0 plain LS, rule 1
+    with negative weights removed; sum1 for the constrained Q fit)."""
+    G = np.ascontiguousarray(G, np.float64)
+    r, m = G.shape
+    p = np.zeros(m)
+    st = lib().orc_fit_point(rule, r, m, _p(G), _p(np.ascontiguousarray(g, np.float64)),
+                             _p(np.ascontiguousarray(w, np.float64)), 1 if sum1 else 0, _p(p))
+    if st:
+        raise OracleError(st)
+    return p
+
+
+def rayleigh_sigma(B, M, N, u, v):
+    """eq. singular_value for one pair (u, v); B, M, N scipy sparse."""
+    import scipy.sparse as sp
+    mats = []
+    for X in (B, M, N):
+        X = sp.csr_matrix(X)
+        X.sort_indices()
+        mats += [np.ascontiguousarray(X.indptr, np.int32), np.ascontiguousarray(X.indices, np.int32),
+                 np.ascontiguousarray(X.data, np.float64)]
+    u = np.ascontiguousarray(u, np.float64)
+    v = np.ascontiguousarray(v, np.float64)
+    out = np.zeros(1)
+    st = lib().orc_rayleigh_sigma(B.shape[0], *[_p(a) for a in mats], _p(u), _p(v), _p(out))
+    if st:
+        raise OracleError(st)
+    return float(out[0])
 
 
 def gsvd(B, M, N):

@@ -826,7 +826,39 @@ int orc_smooth(const orc_ctx *c, int l, const double *b, double *x) {
   return ORC_OK;
 }
 
-/* sigma_k by the generalized Rayleigh quotient (eq. singular_value). */
+/* The generalized Rayleigh quotient of eq. singular_value for one pair:
+ * u^T B v / ((u^T M u)^(1/2) (v^T N v)^(1/2)); t is n scratch values. A
+ * zero denominator gives 0. */
+static double rayleigh_sigma(const csr *B, const csr *M, const csr *N, const double *u,
+                             const double *v, double *t) {
+  int n = B->nr;
+  csr_spmv(B, v, t);
+  double ubv = dot(n, u, t);
+  csr_spmv(M, u, t);
+  double umu = dot(n, u, t);
+  csr_spmv(N, v, t);
+  double vnv = dot(n, v, t);
+  double den = sqrt(umu * vnv);
+  return den > 0 ? ubv / den : 0.0;
+}
+
+int orc_rayleigh_sigma(int n, const int32_t *brp, const int32_t *bci, const double *bv,
+                       const int32_t *mrp, const int32_t *mci, const double *mv,
+                       const int32_t *nrp, const int32_t *nci, const double *nv,
+                       const double *u, const double *v, double *sigma) {
+  if (n < 1 || !brp || !bci || !bv || !mrp || !mci || !mv || !nrp || !nci || !nv || !u || !v ||
+      !sigma)
+    return ORC_E_ARG;
+  csr B = {n, n, brp[n], (int32_t *)brp, (int32_t *)bci, (double *)bv};
+  csr M = {n, n, mrp[n], (int32_t *)mrp, (int32_t *)mci, (double *)mv};
+  csr N = {n, n, nrp[n], (int32_t *)nrp, (int32_t *)nci, (double *)nv};
+  double *t = NEW(double, n);
+  *sigma = rayleigh_sigma(&B, &M, &N, u, v, t);
+  free(t);
+  return ORC_OK;
+}
+
+/* sigma_k of every pair of level l by eq. singular_value. */
 static void update_sigma(orc_ctx *c, level *L) {
   int n = L->n, r = c->o.r;
   double *u = NEW(double, n), *v = NEW(double, n), *t = NEW(double, n);
@@ -835,14 +867,7 @@ static void update_sigma(orc_ctx *c, level *L) {
       u[i] = L->U[(size_t)i * r + k];
       v[i] = L->V[(size_t)i * r + k];
     }
-    csr_spmv(&L->B, v, t);
-    double ubv = dot(n, u, t);
-    csr_spmv(&L->M, u, t);
-    double umu = dot(n, u, t);
-    csr_spmv(&L->N, v, t);
-    double vnv = dot(n, v, t);
-    double den = sqrt(umu * vnv);
-    c->sigma[k] = den > 0 ? ubv / den : 0.0;
+    c->sigma[k] = rayleigh_sigma(&L->B, &L->M, &L->N, u, v, t);
   }
   free(u);
   free(v);
@@ -962,8 +987,14 @@ static void fit_point(int rule, int r, int m, const double *G, const double *g, 
   }
 }
 
-/* LS fits of all P rows and Q columns of level l (eq. ls_interpolation,
- * eq. ls_weights, Section 5 constraint). */
+int orc_fit_point(int rule, int r, int m, const double *G, const double *g, const double *w,
+                  int sum1, double *p) {
+  if (r < 1 || r > 64 || m < 1 || m > 16 || !G || !g || !w || !p || (rule != 0 && rule != 1))
+    return ORC_E_ARG;
+  fit_point(rule, r, m, G, g, w, sum1 ? 1 : 0, p);
+  return ORC_OK;
+}
+
 /* Value of B at (i, j) from the rows of A (A = B for B_ij, A = B^T for B_ji). */
 static double csr_at(const csr *A, int i, int j) {
   for (int k = A->rp[i]; k < A->rp[i + 1]; ++k)

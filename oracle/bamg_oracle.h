@@ -109,6 +109,20 @@ double orc_uniform_pm1(uint64_t seed, uint64_t side, uint64_t k, uint64_t i);
 int orc_ls_row(int r, int m, const double *G, const double *g, const double *w, double *p);
 /* Same with the sum-to-one constraint of Section 5, rows k >= 1 only. */
 int orc_ls_row_sum1(int r, int m, const double *G, const double *g, const double *w, double *q);
+/* Interpolation weights of one F point as the setup fits them: rule 0 =
+ * plain weighted LS over all m points (eq. ls_interpolation), rule 1 =
+ * R-ACT (while a weight is negative, the point with the most negative
+ * weight is dropped and the fit redone, at least one point stays). sum1 = 1
+ * takes the constrained Q-column fit of Section 5 instead (rows k >= 1,
+ * weights sum to one). Same G, g, w layout as orc_ls_row. */
+int orc_fit_point(int rule, int r, int m, const double *G, const double *g, const double *w,
+                  int sum1, double *p);
+/* The generalized Rayleigh quotient of eq. singular_value for one pair
+ * (u, v) of length n, with B, M, N in CSR. */
+int orc_rayleigh_sigma(int n, const int32_t *brp, const int32_t *bci, const double *bv,
+                       const int32_t *mrp, const int32_t *mci, const double *mv,
+                       const int32_t *nrp, const int32_t *nci, const double *nv,
+                       const double *u, const double *v, double *sigma);
 /* Dense generalized singular triplets of (B, M, N), eq. generalized_eigenvalue:
  * all n values ascending, U, V n x n column-major. */
 int orc_gsvd(int n, const double *B, const double *M, const double *N,
