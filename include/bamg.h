@@ -196,6 +196,41 @@ bamg_status bamg_gmres_solve(bamg_handle *h, void *x, int32_t restart, double to
                              int32_t max_iters, int32_t use_x0, bamg_solve_info *info,
                              void *hip_stream);
 
+/* A CSR matrix in host memory with nrows x ncols, columns strictly
+ * ascending within each row, FP64 values. */
+typedef struct {
+  int64_t nrows, ncols, nnz;
+  const int32_t *row_ptr; /* nrows + 1 */
+  const int32_t *col_idx; /* nnz */
+  const double *val;      /* nnz */
+} bamg_host_csr;
+
+/* One level of an explicitly given hierarchy: B_l (n_l x n_l, diagonal
+ * stored and non-zero), the interpolation P_l (n_l x n_{l+1}) and the
+ * restriction Q_l (n_{l+1} x n_l); P and Q are ignored on the last level. */
+typedef struct {
+  bamg_host_csr B, P, Q;
+} bamg_level_ops;
+
+/* A handle whose hierarchy is given instead of built: nlevels (2..32)
+ * levels of operators, coarse_pinv the n_L x n_L row-major pseudo-inverse
+ * of B_L used as the coarsest solve (eq. coarse_grid_correction), x0 the
+ * n_0 initial iterate of GMRES (Section 6); all host memory, copied before
+ * the call returns. The V-cycle (Section 3) and GMRES then run on exactly
+ * these operators with the kernels bamg_setup's handles use. From opt only
+ * the solve-phase fields are read: nu_pre, nu_post, omega, smoother,
+ * precision, use_graph, autotune, fuse_last_level (r, setup and coarsening
+ * fields are ignored). Errors: BAMG_E_ARG for a shape, pointer, ordering or
+ * size fault (each coarse level smaller than its fine level, n_L <= 2048),
+ * BAMG_E_NONFINITE for a non-finite value, BAMG_E_BAD_DIAG for a zero or
+ * missing diagonal of some B_l. The setup-only inspection calls
+ * (bamg_level_cf, bamg_level_vectors, M/N/B^T in bamg_level_csr,
+ * bamg_harvest) return BAMG_E_ARG on such a handle. */
+bamg_status bamg_setup_from_levels(int32_t nlevels, const bamg_level_ops *levels,
+                                   const double *coarse_pinv, const double *x0,
+                                   const bamg_options *opt, const bamg_allocator *alloc,
+                                   void *hip_stream, bamg_handle **out);
+
 /* Hierarchy summary (host outputs, each may be NULL): number of levels,
  * n_l and nnz(B_l) for l < *levels (arrays sized >= 32), operator and grid
  * complexity (Section 4.1 eq. operator_complexity_def, Section 7). */

@@ -46,6 +46,15 @@ class Geometry(C.Structure):
     _fields_ = [("kind", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32)]
 
 
+class HostCsr(C.Structure):
+    _fields_ = [("nrows", C.c_int64), ("ncols", C.c_int64), ("nnz", C.c_int64),
+                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p)]
+
+
+class LevelOps(C.Structure):
+    _fields_ = [("B", HostCsr), ("P", HostCsr), ("Q", HostCsr)]
+
+
 class Options(C.Structure):
     _fields_ = [("r", C.c_int32), ("setup_cycles", C.c_int32), ("nu_pre", C.c_int32),
                 ("nu_post", C.c_int32), ("nu_setup", C.c_int32), ("omega", C.c_double),
@@ -83,6 +92,7 @@ def lib():
         L.bamg_default_options.argtypes = [P(Options)]
         L.bamg_setup.argtypes = [P(Csr), P(Geometry), P(Options), V, V, P(V)]
         L.bamg_vcycle.argtypes = [V, V, V, C.c_int32, V]
+        L.bamg_setup_from_levels.argtypes = [C.c_int32, V, V, V, P(Options), V, V, P(V)]
         L.bamg_gmres_solve.argtypes = [V, V, C.c_int32, C.c_double, C.c_int32, C.c_int32,
                                        P(SolveInfo), V]
         L.bamg_hierarchy_info.argtypes = [V, V, V, V, V, V]
@@ -255,6 +265,51 @@ class Hierarchy:
             return cls(torch.from_numpy(chain.indptr).cuda(), torch.from_numpy(chain.indices).cuda(),
                        torch.from_numpy(chain.data).cuda(), chain.geom, opts, stream, allocator)
         return cls(chain.indptr, chain.indices, chain.data, chain.geom, opts, stream, allocator)
+
+    @classmethod
+    def from_levels(cls, B, P, Q, coarse_pinv, x0, opts: Options | None = None, stream=None,
+                    allocator="torch"):
+        """A handle on an explicitly given hierarchy (bamg_setup_from_levels):
+        B a list of the level operators B_l, P and Q lists of the transfers
+        (one fewer), all scipy sparse (converted to sorted CSR); coarse_pinv
+        the dense pseudo-inverse of the last B; x0 the initial iterate."""
+        import scipy.sparse as sp
+        _torch()
+        self = cls.__new__(cls)
+        self.opts = opts if opts is not None else default_options()
+        nl = len(B)
+        if len(P) != nl - 1 or len(Q) != nl - 1:
+            raise ValueError("P and Q need one entry per level above the coarsest")
+        keep = []
+
+        def host(A):
+            A = sp.csr_matrix(A)
+            A.sort_indices()
+            arrs = (np.ascontiguousarray(A.indptr, np.int32),
+                    np.ascontiguousarray(A.indices, np.int32),
+                    np.ascontiguousarray(A.data, np.float64))
+            keep.extend(arrs)
+            return HostCsr(A.shape[0], A.shape[1], A.nnz, *[a.ctypes.data for a in arrs])
+
+        ops = (LevelOps * nl)()
+        for l in range(nl):
+            ops[l].B = host(B[l])
+            if l + 1 < nl:
+                ops[l].P = host(P[l])
+                ops[l].Q = host(Q[l])
+        pinv = np.ascontiguousarray(coarse_pinv, np.float64)
+        x0a = np.ascontiguousarray(x0, np.float64)
+        self.n = B[0].shape[0]
+        self._keep = ()
+        h = C.c_void_p()
+        self._stream = _stream(stream)
+        _check(lib().bamg_setup_from_levels(nl, ops, pinv.ctypes.data, x0a.ctypes.data,
+                                            C.byref(self.opts), _allocator(allocator),
+                                            self._stream, C.byref(h)))
+        self.h = h
+        _LIVE.add(self)
+        self.mixed = self.opts.precision == PRECISION_MIXED
+        return self
 
     def close(self):
         if getattr(self, "h", None):

@@ -283,6 +283,53 @@ bamg_status bamg_setup(const bamg_csr *A, const bamg_geometry *geom, const bamg_
   return BAMG_OK;
 }
 
+bamg_status bamg_setup_from_levels(int32_t nlevels, const bamg_level_ops *levels,
+                                   const double *coarse_pinv, const double *x0,
+                                   const bamg_options *opt, const bamg_allocator *alloc,
+                                   void *hip_stream, bamg_handle **out) {
+  if (nlevels < 2 || nlevels > 32 || !levels || !coarse_pinv || !x0 || !opt || !out)
+    return BAMG_E_ARG;
+  if (opt->nu_pre < 0 || opt->nu_post < 0 || opt->nu_pre > 64 || opt->nu_post > 64 ||
+      !(opt->omega > 0.0 && opt->omega < 2.0) ||
+      (opt->smoother != BAMG_SMOOTH_JACOBI && opt->smoother != BAMG_SMOOTH_KACZMARZ) ||
+      (opt->precision != BAMG_PRECISION_FP64 && opt->precision != BAMG_PRECISION_MIXED))
+    return BAMG_E_ARG;
+  if (alloc && (!alloc->alloc || !alloc->free)) return BAMG_E_ARG;
+  bamg_handle *h = new (std::nothrow) bamg_handle();
+  if (!h) return BAMG_E_NOMEM;
+  h->opt = *opt;
+  h->opt.learned = BAMG_LEARNED_OFF;
+  h->opt.mlp = nullptr;
+  h->imported = 1;
+  h->prec = opt->precision == BAMG_PRECISION_MIXED ? 1 : 0;
+  h->use_graph = opt->use_graph ? 1 : 0;
+  h->last_fused = opt->fuse_last_level ? 1 : 0;
+  h->pool.s = (hipStream_t)hip_stream;
+  if (alloc) {
+    h->pool.a = *alloc;
+    h->pool.custom = true;
+  }
+  try {
+    if (h->prec == 0)
+      import_all<double>(h, nlevels, levels, coarse_pinv, x0);
+    else
+      import_all<float>(h, nlevels, levels, coarse_pinv, x0);
+  } catch (const Error &e) {
+    (void)hipStreamSynchronize(h->pool.s);
+    h->pool.release_all();
+    delete h;
+    return translate(e);
+  } catch (...) {
+    (void)hipStreamSynchronize(h->pool.s);
+    h->pool.release_all();
+    delete h;
+    g_last_error = "unexpected exception in bamg_setup_from_levels";
+    return BAMG_E_DEVICE;
+  }
+  *out = h;
+  return BAMG_OK;
+}
+
 bamg_status bamg_vcycle(bamg_handle *h, const void *b, void *x, int32_t dtype, void *hip_stream) {
   if (!h || !b || !x || b == x) return BAMG_E_ARG;
   if (dtype != BAMG_DTYPE_F64 && dtype != BAMG_DTYPE_F32) return BAMG_E_ARG;
@@ -340,6 +387,7 @@ bamg_status bamg_hierarchy_info(const bamg_handle *h, int32_t *levels, int64_t *
 
 static bool level_pick(const bamg_handle *h, int l, int what, const Csr **A, const void **v) {
   if (l < 0 || l >= h->L || what < 0 || what > 6) return false;
+  if (h->imported && (what == 1 || what == 2 || what == 3 || what == 6)) return false;
   const Level &L = h->lv[l];
   if (what >= 4 && l == h->L - 1) return false;
   switch (what) {
@@ -388,7 +436,7 @@ bamg_status bamg_level_csr(const bamg_handle *h, int32_t l, int32_t what, int32_
 }
 
 bamg_status bamg_level_cf(const bamg_handle *h, int32_t l, int32_t *cf, int32_t *cidx) {
-  if (!h || l < 0 || l >= h->L - 1) return BAMG_E_ARG;
+  if (!h || h->imported || l < 0 || l >= h->L - 1) return BAMG_E_ARG;
   BAMG_TRY
   const Level &L = h->lv[l];
   if (cf) HIPCHK(hipMemcpy(cf, L.cf, sizeof(int) * L.n, hipMemcpyDeviceToHost));
@@ -398,7 +446,7 @@ bamg_status bamg_level_cf(const bamg_handle *h, int32_t l, int32_t *cf, int32_t 
 }
 
 bamg_status bamg_level_vectors(const bamg_handle *h, int32_t l, double *U, double *V) {
-  if (!h || l < 0 || l >= h->L) return BAMG_E_ARG;
+  if (!h || h->imported || l < 0 || l >= h->L) return BAMG_E_ARG;
   BAMG_TRY
   const Level &L = h->lv[l];
   const size_t nr = (size_t)L.n * h->opt.r;
@@ -451,11 +499,11 @@ bamg_status bamg_vcycle_bytes(const bamg_handle *h, double *bytes) {
   double tot = 0.0;
   for (int l = 0; l + 1 < h->L; ++l) {
     const Level &L = h->lv[l];
-    const double n = L.n, nnz = L.B.nnz, nc = h->lv[l + 1].n, np = L.P.nnz;
+    const double n = L.n, nnz = L.B.nnz, nc = h->lv[l + 1].n, np = L.P.nnz, nq = L.Pc.nnz;
     const double sweep = nnz * (s + 4) + 4 * (n + 1) + 4 * s * n;
     const double first = 3 * s * n;
     const double resid = nnz * (s + 4) + 4 * (n + 1) + 3 * s * n;
-    const double restr = np * (s + 4) + 4 * (nc + 1) + s * (n + nc);
+    const double restr = nq * (s + 4) + 4 * (nc + 1) + s * (n + nc);
     const double prol = np * (s + 4) + 4 * (n + 1) + s * (nc + 2 * n);
     const int sweeps = (nu1 > 0 ? nu1 - 1 : 0) + nu2;
     tot += sweeps * sweep + (nu1 > 0 ? first : 0) + resid + restr + prol;

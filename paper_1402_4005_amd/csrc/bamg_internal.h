@@ -126,6 +126,7 @@ struct bamg_handle {
   hipStream_t cap_stream = nullptr;   // stream the V-cycle is captured on
   int use_graph = 1;
   int last_fused = 1;  // one-workgroup cycle on a small last level (option fuse_last_level)
+  int imported = 0;    // hierarchy given by bamg_setup_from_levels (no setup data)
   // event timing of one kernel (bamg_kernel_profile_*)
   int prof_kernel = -1;
   std::vector<hipEvent_t> prof_ev;  // pairs (start, stop)
@@ -249,7 +250,7 @@ void trsm_lower_cols(const double *L, double *X, int n, int ncols, int ldx,
 void transpose_dense(const double *A, double *At, int n, hipStream_t s);
 int jacobi_svd(Pool &pool, double *W, double *J, int n, hipStream_t s);
 int jacobi_svd2(Pool &pool, double *W, double *J, double *W2, double *J2, int n,
-                hipStream_t s);  // both SVDs in one cooperative launch (W2 nullable)  // W, J col-major
+                hipStream_t s);  // both SVDs in the same launches (W2 nullable); W, J col-major
 void column_norms(const double *W, int n, double *sv, hipStream_t s);
 void coarse_triplets_out(const double *LM, const double *LN, const double *W, const double *J,
                          const double *sv, int n, int r, void *U, void *V, int prec,
@@ -286,6 +287,9 @@ void normalize_sum(double *x, int n, double *part, int nblk, double *flags, hipS
 
 // host-side orchestration
 template <class T> void setup_all(bamg_handle *h, const bamg_csr *A, const bamg_geometry *g);
+template <class T>
+void import_all(bamg_handle *h, int nlev, const bamg_level_ops *ops, const double *pinv,
+                const double *x0);
 template <class T> void vcycle_run(bamg_handle *h, const T *b, T *x, hipStream_t s);
 void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_x0,
                bamg_solve_info *info, hipStream_t s);

@@ -9,16 +9,11 @@
 // The SVD is one-sided Jacobi (Hestenes): column pairs of W are rotated until
 // orthogonal. Blocks of columns are paired by the round-robin (circle)
 // schedule, so one round treats disjoint block pairs in parallel, one
-// workgroup per block pair, with a grid-wide barrier between rounds
-// (cooperative launch).
-#include <hip/hip_cooperative_groups.h>
-
-#include <mutex>
+// workgroup per block pair, one launch per round.
+#include <algorithm>
 
 #include "bamg_internal.h"
 #include "device_common.h"
-
-namespace cg = cooperative_groups;
 
 namespace bamg {
 
@@ -283,15 +278,19 @@ __device__ __forceinline__ svd_d4 mfma_tile(int k0, int k1, FA a, FB b, svd_d4 a
   return acc;
 }
 
-// W and J column-major n x n; nbp = number of column blocks rounded up to
-// even (columns >= n are zero and never written). ctrl[s] counts rotations
-// of sweep s; ctrl[kSvdMaxSweeps] receives the number of sweeps run.
-// blockDim.x = 64 bs with bs = 8 or 16; dynamic LDS = block_jacobi_lds().
+// One round of the block one-sided Jacobi sweep `sweep`: workgroup pm treats
+// block pair pm % (nbp / 2) of the round-robin round `round` of W (pm <
+// nbp / 2) or of W2. W and J column-major n x n; nbp = number of column
+// blocks rounded up to even (columns >= n are zero and never written).
+// ctrl[s] counts the rotations of sweep s; ctrl[kSvdMaxSweeps + 1] != 0 once
+// a sweep has found nothing to rotate, which turns the remaining launches
+// into no-ops. grid = nmat * nbp / 2; blockDim.x = 64 bs with bs = 8 or 16;
+// dynamic LDS = block_jacobi_lds().
 __global__ void __launch_bounds__(1024)
-    k_block_jacobi_svd(double *__restrict__ W, double *__restrict__ J, double *__restrict__ W2,
-                       double *__restrict__ J2, int nmat, int n, int bs, int nbp,
-                       int *__restrict__ ctrl) {
-  cg::grid_group grid = cg::this_grid();
+    k_block_jacobi_round(double *__restrict__ W, double *__restrict__ J, double *__restrict__ W2,
+                         double *__restrict__ J2, int n, int bs, int nbp,
+                         int *__restrict__ ctrl, int sweep, int round) {
+  if (ctrl[kSvdMaxSweeps + 1]) return;
   extern __shared__ double lds[];
   const int cols = 2 * bs, cc = cols * cols, nt = blockDim.x, nw = nt / kWave;
   const int wv = threadIdx.x / kWave, ln = threadIdx.x % kWave;
@@ -302,169 +301,172 @@ __global__ void __launch_bounds__(1024)
   double *part = Ra + cc;                              // nw 16 x 16 partial tiles of G
   double *rc = part + (size_t)nw * 256, *rs = rc + bs;  // rotation of each pair
   __shared__ int nrot, need;
-  int sweep = 0;
-  for (; sweep < kSvdMaxSweeps; ++sweep) {
-    for (int round = 0; round < nbp - 1; ++round) {
-      for (int pm = blockIdx.x; pm < nmat * (nbp / 2); pm += gridDim.x) {
-        // pair pr of matrix pm / (nbp / 2): (W, J) or (W2, J2)
-        const int pr = pm % (nbp / 2);
-        double *__restrict__ Wm = pm < nbp / 2 ? W : W2;
-        double *__restrict__ Jm = pm < nbp / 2 ? J : J2;
-        const int ba = rr_index(pr, round, nbp), bb = rr_index(nbp - 1 - pr, round, nbp);
-        // local column c -> global column
-        auto gcol = [&](int c) { return c < bs ? ba * bs + c : bb * bs + (c - bs); };
-        // 32 threads per column (blockDim.x = 32 cols)
-        const int lc = threadIdx.x / 32, li = threadIdx.x % 32, lg = gcol(lc);
-        {
-          double *dst = Ws + (size_t)lc * n;
-          const double *src = Wm + (size_t)lg * n;
+  const int pm = blockIdx.x;
+  // pair pr of matrix pm / (nbp / 2): (W, J) or (W2, J2)
+  const int pr = pm % (nbp / 2);
+  double *__restrict__ Wm = pm < nbp / 2 ? W : W2;
+  double *__restrict__ Jm = pm < nbp / 2 ? J : J2;
+  const int ba = rr_index(pr, round, nbp), bb = rr_index(nbp - 1 - pr, round, nbp);
+  // local column c -> global column
+  auto gcol = [&](int c) { return c < bs ? ba * bs + c : bb * bs + (c - bs); };
+  // 32 threads per column (blockDim.x = 32 cols)
+  const int lc = threadIdx.x / 32, li = threadIdx.x % 32, lg = gcol(lc);
+  {
+    double *dst = Ws + (size_t)lc * n;
+    const double *src = Wm + (size_t)lg * n;
 #pragma unroll 4
-          for (int i = li; i < n; i += 32) dst[i] = lg < n ? src[i] : 0.0;
-        }
-        if (threadIdx.x == 0) {
-          nrot = 0;
-          need = 0;
-        }
-        __syncthreads();
-        // Gram matrix: wave wv forms tile (wv % (ct ct)) over K-slice
-        // wv / (ct ct); the slices are added in order below
-        {
-          const int tile = wv % (ct * ct), sl = wv / (ct * ct);
-          const int ta = tile / ct, tb = tile % ct, ks = (n + 3) / 4;
-          const int k0 = sl * ks / nsl, k1 = (sl + 1) * ks / nsl;
-          svd_d4 acc = {0.0, 0.0, 0.0, 0.0};
-          acc = mfma_tile(
-              k0, k1, [&](int i, int k) { return k < n ? Ws[(size_t)(16 * ta + i) * n + k] : 0.0; },
-              [&](int k, int j) { return k < n ? Ws[(size_t)(16 * tb + j) * n + k] : 0.0; }, acc);
-          for (int r = 0; r < 4; ++r) part[(size_t)wv * 256 + (ln / 16 + 4 * r) * 16 + ln % 16] = acc[r];
-        }
-        __syncthreads();
-        // G[a][b] from the upper-triangle tiles only, so G is exactly
-        // symmetric; R = I; does any pair this visit rotates need it?
-        for (int e = threadIdx.x; e < cc; e += nt) {
-          int a = e / cols, b = e % cols;
-          if (a > b) {
-            const int x = a;
-            a = b;
-            b = x;
-          }
-          const int tile = (a / 16) * ct + b / 16, off = (a % 16) * 16 + b % 16;
-          double g = 0.0;
-          for (int sl = 0; sl < nsl; ++sl) g += part[(size_t)(sl * ct * ct + tile) * 256 + off];
-          Ga[e] = g;
-          Ra[e] = (e / cols) == (e % cols);
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < cc; e += nt) {
-          const int a = e / cols, b = e % cols;
-          if (a < b && (round == 0 || (a < bs && b >= bs))) {
-            double c, sn;
-            if (svd_rotation(Ga[a * cols + a], Ga[b * cols + b], Ga[e], c, sn)) need = 1;
-          }
-        }
-        __syncthreads();
-        // Inner rounds. Wave 0 finds the rotations (lane k: pair k); then
-        // thread (k1, k2) < (bs, bs) rewrites the 2 x 2 block of G at rows
-        // of pair k1 and columns of pair k2 to that of Jᵀ G J, and thread
-        // (r, k2) the two entries of row r of R at pair k2 to those of R J.
-        // The blocks are disjoint, so both updates are made in place.
-        if (need) {
-          const bool all0 = round == 0;
-          const int ninner = all0 ? cols - 1 : bs;
-          for (int ir = 0; ir < ninner; ++ir) {
-            if (wv == 0) {
-              bool did = false;
-              if (ln < bs) {
-                int p, q;
-                svd_pair(ln, ir, bs, all0, p, q);
-                double c, sn;
-                did = svd_rotation(Ga[p * cols + p], Ga[q * cols + q], Ga[p * cols + q], c, sn);
-                rc[ln] = c;
-                rs[ln] = sn;
-              }
-              const unsigned long long m = __ballot(did);
-              if (ln == 0) nrot += __popcll(m);
-            }
-            __syncthreads();
-            const int e = threadIdx.x;
-            if (e < bs * bs) {
-              const int k1 = e / bs, k2 = e % bs;
-              int p1, q1, p2, q2;
-              svd_pair(k1, ir, bs, all0, p1, q1);
-              svd_pair(k2, ir, bs, all0, p2, q2);
-              const double c1 = rc[k1], s1 = rs[k1], c2 = rc[k2], s2 = rs[k2];
-              double *g1 = Ga + p1 * cols, *g2 = Ga + q1 * cols;
-              const double gpp = g1[p2], gpq = g1[q2], gqp = g2[p2], gqq = g2[q2];
-              const double hpp = c1 * gpp - s1 * gqp, hpq = c1 * gpq - s1 * gqq;
-              const double hqp = s1 * gpp + c1 * gqp, hqq = s1 * gpq + c1 * gqq;
-              g1[p2] = c2 * hpp - s2 * hpq;
-              g1[q2] = s2 * hpp + c2 * hpq;
-              g2[p2] = c2 * hqp - s2 * hqq;
-              g2[q2] = s2 * hqp + c2 * hqq;
-            } else if (e < bs * bs + cols * bs) {
-              const int r = (e - bs * bs) / bs, k2 = (e - bs * bs) % bs;
-              int p2, q2;
-              svd_pair(k2, ir, bs, all0, p2, q2);
-              const double c2 = rc[k2], s2 = rs[k2];
-              double *rr = Ra + r * cols;
-              const double x = rr[p2], y = rr[q2];
-              rr[p2] = c2 * x - s2 * y;
-              rr[q2] = s2 * x + c2 * y;
-            }
-            __syncthreads();
-          }
-        }
-        const double *R = Ra;
-        if (nrot > 0) {
-          // X[:, pair] <- X[:, pair] R for X = W (from Ws), then X = J (loaded
-          // into Ws): output tiles of 16 rows x 16 columns, round-robin over
-          // the waves
-          // J's first kSvdPref * 32 rows are fetched into registers before
-          // the product with W, so their latency overlaps it
-          const int rt = (n + 15) / 16;
-          const double *jsrc = Jm + (size_t)lg * n;
-          double jr[kSvdPref];
-#pragma unroll
-          for (int j = 0; j < kSvdPref; ++j) {
-            const int i = li + 32 * j;
-            jr[j] = lg < n && i < n ? jsrc[i] : 0.0;
-          }
-          for (int pass = 0; pass < 2; ++pass) {
-            double *__restrict__ Xm = pass == 0 ? Wm : Jm;
-            if (pass == 1) {
-              double *dst = Ws + (size_t)lc * n;
-#pragma unroll
-              for (int j = 0; j < kSvdPref; ++j)
-                if (li + 32 * j < n) dst[li + 32 * j] = jr[j];
-              for (int i = li + 32 * kSvdPref; i < n; i += 32) dst[i] = lg < n ? jsrc[i] : 0.0;
-              __syncthreads();
-            }
-            for (int tl = wv; tl < rt * ct; tl += nw) {
-              const int it = tl / ct, cj = tl % ct;
-              svd_d4 acc = {0.0, 0.0, 0.0, 0.0};
-              acc = mfma_tile(
-                  0, cols / 4,
-                  [&](int i, int k) { return Ws[(size_t)k * n + min(16 * it + i, n - 1)]; },
-                  [&](int k, int j) { return R[k * cols + 16 * cj + j]; }, acc);
-              const int c = 16 * cj + ln % 16, g = gcol(c);
-              for (int r = 0; r < 4; ++r) {
-                const int i = 16 * it + ln / 16 + 4 * r;
-                if (i < n && g < n) Xm[(size_t)g * n + i] = acc[r];
-              }
-            }
-            __syncthreads();
-          }
-          if (threadIdx.x == 0) atomicAdd(&ctrl[sweep], nrot);
-        }
-        __syncthreads();  // before the next pair resets nrot and need
-      }
-      grid.sync();
-    }
-    const int rotated = atomicAdd(&ctrl[sweep], 0);
-    grid.sync();
-    if (rotated == 0) break;
+    for (int i = li; i < n; i += 32) dst[i] = lg < n ? src[i] : 0.0;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl[kSvdMaxSweeps] = sweep;
+  if (threadIdx.x == 0) {
+    nrot = 0;
+    need = 0;
+  }
+  __syncthreads();
+  // Gram matrix: wave wv forms tile (wv % (ct ct)) over K-slice
+  // wv / (ct ct); the slices are added in order below
+  {
+    const int tile = wv % (ct * ct), sl = wv / (ct * ct);
+    const int ta = tile / ct, tb = tile % ct, ks = (n + 3) / 4;
+    const int k0 = sl * ks / nsl, k1 = (sl + 1) * ks / nsl;
+    svd_d4 acc = {0.0, 0.0, 0.0, 0.0};
+    acc = mfma_tile(
+        k0, k1, [&](int i, int k) { return k < n ? Ws[(size_t)(16 * ta + i) * n + k] : 0.0; },
+        [&](int k, int j) { return k < n ? Ws[(size_t)(16 * tb + j) * n + k] : 0.0; }, acc);
+    for (int r = 0; r < 4; ++r) part[(size_t)wv * 256 + (ln / 16 + 4 * r) * 16 + ln % 16] = acc[r];
+  }
+  __syncthreads();
+  // G[a][b] from the upper-triangle tiles only, so G is exactly
+  // symmetric; R = I; does any pair this visit rotates need it?
+  for (int e = threadIdx.x; e < cc; e += nt) {
+    int a = e / cols, b = e % cols;
+    if (a > b) {
+      const int x = a;
+      a = b;
+      b = x;
+    }
+    const int tile = (a / 16) * ct + b / 16, off = (a % 16) * 16 + b % 16;
+    double g = 0.0;
+    for (int sl = 0; sl < nsl; ++sl) g += part[(size_t)(sl * ct * ct + tile) * 256 + off];
+    Ga[e] = g;
+    Ra[e] = (e / cols) == (e % cols);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < cc; e += nt) {
+    const int a = e / cols, b = e % cols;
+    if (a < b && (round == 0 || (a < bs && b >= bs))) {
+      double c, sn;
+      if (svd_rotation(Ga[a * cols + a], Ga[b * cols + b], Ga[e], c, sn)) need = 1;
+    }
+  }
+  __syncthreads();
+  // Inner rounds. Wave 0 finds the rotations (lane k: pair k); then
+  // thread (k1, k2) < (bs, bs) rewrites the 2 x 2 block of G at rows
+  // of pair k1 and columns of pair k2 to that of Jᵀ G J, and thread
+  // (r, k2) the two entries of row r of R at pair k2 to those of R J.
+  // The blocks are disjoint, so both updates are made in place.
+  if (need) {
+    const bool all0 = round == 0;
+    const int ninner = all0 ? cols - 1 : bs;
+    for (int ir = 0; ir < ninner; ++ir) {
+      if (wv == 0) {
+        bool did = false;
+        if (ln < bs) {
+          int p, q;
+          svd_pair(ln, ir, bs, all0, p, q);
+          double c, sn;
+          did = svd_rotation(Ga[p * cols + p], Ga[q * cols + q], Ga[p * cols + q], c, sn);
+          rc[ln] = c;
+          rs[ln] = sn;
+        }
+        const unsigned long long m = __ballot(did);
+        if (ln == 0) nrot += __popcll(m);
+      }
+      __syncthreads();
+      const int e = threadIdx.x;
+      if (e < bs * bs) {
+        const int k1 = e / bs, k2 = e % bs;
+        int p1, q1, p2, q2;
+        svd_pair(k1, ir, bs, all0, p1, q1);
+        svd_pair(k2, ir, bs, all0, p2, q2);
+        const double c1 = rc[k1], s1 = rs[k1], c2 = rc[k2], s2 = rs[k2];
+        double *g1 = Ga + p1 * cols, *g2 = Ga + q1 * cols;
+        const double gpp = g1[p2], gpq = g1[q2], gqp = g2[p2], gqq = g2[q2];
+        const double hpp = c1 * gpp - s1 * gqp, hpq = c1 * gpq - s1 * gqq;
+        const double hqp = s1 * gpp + c1 * gqp, hqq = s1 * gpq + c1 * gqq;
+        g1[p2] = c2 * hpp - s2 * hpq;
+        g1[q2] = s2 * hpp + c2 * hpq;
+        g2[p2] = c2 * hqp - s2 * hqq;
+        g2[q2] = s2 * hqp + c2 * hqq;
+      } else if (e < bs * bs + cols * bs) {
+        const int r = (e - bs * bs) / bs, k2 = (e - bs * bs) % bs;
+        int p2, q2;
+        svd_pair(k2, ir, bs, all0, p2, q2);
+        const double c2 = rc[k2], s2 = rs[k2];
+        double *rr = Ra + r * cols;
+        const double x = rr[p2], y = rr[q2];
+        rr[p2] = c2 * x - s2 * y;
+        rr[q2] = s2 * x + c2 * y;
+      }
+      __syncthreads();
+    }
+  }
+  const double *R = Ra;
+  if (nrot > 0) {
+    // X[:, pair] <- X[:, pair] R for X = W (from Ws), then X = J (loaded
+    // into Ws): output tiles of 16 rows x 16 columns, round-robin over
+    // the waves
+    // J's first kSvdPref * 32 rows are fetched into registers before
+    // the product with W, so their latency overlaps it
+    const int rt = (n + 15) / 16;
+    const double *jsrc = Jm + (size_t)lg * n;
+    double jr[kSvdPref];
+#pragma unroll
+    for (int j = 0; j < kSvdPref; ++j) {
+      const int i = li + 32 * j;
+      jr[j] = lg < n && i < n ? jsrc[i] : 0.0;
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+      double *__restrict__ Xm = pass == 0 ? Wm : Jm;
+      if (pass == 1) {
+        double *dst = Ws + (size_t)lc * n;
+#pragma unroll
+        for (int j = 0; j < kSvdPref; ++j)
+          if (li + 32 * j < n) dst[li + 32 * j] = jr[j];
+        for (int i = li + 32 * kSvdPref; i < n; i += 32) dst[i] = lg < n ? jsrc[i] : 0.0;
+        __syncthreads();
+      }
+      for (int tl = wv; tl < rt * ct; tl += nw) {
+        const int it = tl / ct, cj = tl % ct;
+        svd_d4 acc = {0.0, 0.0, 0.0, 0.0};
+        acc = mfma_tile(
+            0, cols / 4,
+            [&](int i, int k) { return Ws[(size_t)k * n + min(16 * it + i, n - 1)]; },
+            [&](int k, int j) { return R[k * cols + 16 * cj + j]; }, acc);
+        const int c = 16 * cj + ln % 16, g = gcol(c);
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * it + ln / 16 + 4 * r;
+          if (i < n && g < n) Xm[(size_t)g * n + i] = acc[r];
+        }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(&ctrl[sweep], nrot);
+  }
+}
+
+// After the last round of sweep `sweep`: a sweep without a rotation ends the
+// iteration, and ctrl[kSvdMaxSweeps] records its index (it stays
+// kSvdMaxSweeps if no sweep converges).
+__global__ void k_block_jacobi_sweep_end(int *__restrict__ ctrl, int sweep) {
+  if (threadIdx.x == 0 && ctrl[kSvdMaxSweeps + 1] == 0 && ctrl[sweep] == 0) {
+    ctrl[kSvdMaxSweeps + 1] = 1;
+    ctrl[kSvdMaxSweeps] = sweep;
+  }
+}
+
+__global__ void k_block_jacobi_init(int *__restrict__ ctrl) {
+  const int i = threadIdx.x;
+  if (i < kSvdMaxSweeps + 2) ctrl[i] = i == kSvdMaxSweeps ? kSvdMaxSweeps : 0;
 }
 
 __global__ void k_identity_dense(double *__restrict__ J, int n) {
@@ -484,13 +486,17 @@ int jacobi_svd(Pool &pool, double *W, double *J, int n, hipStream_t s) {
   return jacobi_svd2(pool, W, J, nullptr, nullptr, n, s);
 }
 
-// One cooperative launch for the SVDs of W (and of W2 when given): the two
-// matrices share the grid barriers and stop when neither rotates.
+// The SVDs of W (and of W2 when given) by rounds of the block Jacobi sweep,
+// one launch per round: kernel boundaries order the rounds, so no grid
+// barrier and no co-residency of the workgroups is needed, and several
+// setups on concurrent streams do not wait on each other. The two matrices
+// share the launches and stop after the first sweep in which neither
+// rotates. Sweeps are enqueued in groups and the convergence flag is read
+// back after each group; launches behind the converged sweep return at once.
 int jacobi_svd2(Pool &pool, double *W, double *J, double *W2, double *J2, int n, hipStream_t s) {
-  int dev = 0, maxlds = 0, ncu = 0;
+  int dev = 0, maxlds = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   // Column blocks of 16 where they fit in LDS (n <= 446 on 160 KB), else of
   // 8 (n <= 1117): with the rotations made on the Gram matrix a wider block
   // costs little more per round and halves the rounds (n = 289, tandem
@@ -505,8 +511,9 @@ int jacobi_svd2(Pool &pool, double *W, double *J, double *W2, double *J2, int n,
   const int nb = ceil_div(n, bs);
   int nbp = nb + (nb & 1);
   if (nbp < 2) nbp = 2;
-  int *ctrl = pool.get<int>(kSvdMaxSweeps + 1);
-  fill_i32(ctrl, 0, kSvdMaxSweeps + 1, s);
+  int *ctrl = pool.get<int>(kSvdMaxSweeps + 2);
+  k_block_jacobi_init<<<1, 128, 0, s>>>(ctrl);
+  LAUNCHCHK();
   const int nmat = W2 ? 2 : 1;
   k_identity_dense<<<ceil_div((long)n * n, 256), 256, 0, s>>>(J, n);  // J = I
   LAUNCHCHK();
@@ -514,32 +521,31 @@ int jacobi_svd2(Pool &pool, double *W, double *J, double *W2, double *J2, int n,
     k_identity_dense<<<ceil_div((long)n * n, 256), 256, 0, s>>>(J2, n);
     LAUNCHCHK();
   }
-  HIPCHK(hipFuncSetAttribute((const void *)k_block_jacobi_svd,
+  HIPCHK(hipFuncSetAttribute((const void *)k_block_jacobi_round,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-  int per = 0;
-  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_block_jacobi_svd,
-                                                      threads, shm));
-  int grid = nmat * (nbp / 2);
-  const int cap = ncu * (per > 0 ? per : 1);
-  if (grid > cap) grid = cap;
-  if (grid < 1) grid = 1;
-  void *args[] = {(void *)&W,  (void *)&J,  (void *)&W2,  (void *)&J2,  (void *)&nmat,
-                  (void *)&n,  (void *)&bs, (void *)&nbp, (void *)&ctrl};
-  int sweeps = 0;
-  {
-    // A cooperative grid is sized to be co-resident on an otherwise idle
-    // device; two of them at once (chains set up on concurrent streams)
-    // could not both be resident and their grid barriers could wait
-    // forever. One in flight per process, held until it has finished.
-    static std::mutex coop_mu;
-    std::lock_guard<std::mutex> lock(coop_mu);
-    HIPCHK(hipLaunchCooperativeKernel((const void *)k_block_jacobi_svd, dim3(grid),
-                                      dim3(threads), args, shm, s));
-    HIPCHK(hipMemcpyAsync(&sweeps, ctrl + kSvdMaxSweeps, sizeof(int), hipMemcpyDeviceToHost, s));
+  const int grid = nmat * (nbp / 2);
+  int *hp = pool.pinned();
+  // about 12 sweeps converge a coarsest level of a few hundred states: the
+  // first check comes after 8, later ones after every 2
+  int sweep = 0, done = 0;
+  while (!done && sweep < kSvdMaxSweeps) {
+    const int upto = std::min(kSvdMaxSweeps, sweep == 0 ? 8 : sweep + 2);
+    for (; sweep < upto; ++sweep) {
+      for (int round = 0; round < nbp - 1; ++round) {
+        k_block_jacobi_round<<<grid, threads, shm, s>>>(W, J, W2, J2, n, bs, nbp, ctrl, sweep,
+                                                        round);
+        LAUNCHCHK();
+      }
+      k_block_jacobi_sweep_end<<<1, 64, 0, s>>>(ctrl, sweep);
+      LAUNCHCHK();
+    }
+    HIPCHK(hipMemcpyAsync(hp, ctrl + kSvdMaxSweeps, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    done = hp[1];
   }
+  const int sweeps = hp[0];
   pool.release(ctrl);
-  return sweeps < kSvdMaxSweeps ? BAMG_OK : BAMG_E_COARSE;
+  return done && sweeps < kSvdMaxSweeps ? BAMG_OK : BAMG_E_COARSE;
 }
 
 __global__ void k_column_norms(const double *__restrict__ W, int n, double *__restrict__ sv) {

@@ -1,8 +1,10 @@
 """GPU parity tests: the HIP library (through its C ABI) against the FP64 CPU
-oracle on the same seeded inputs. Integer outputs (C/F splittings, coarse
-numbering, every sparsity pattern) must be bit-exact; floating-point outputs
-within the tolerances stated per test; the stationary vector within 1e-10 in
-relative l1 when both sides run to ||Bx||/||x|| < 1e-14."""
+oracle on the same seeded inputs, each side building its own hierarchy.
+Integer outputs (C/F splittings, coarse numbering, every sparsity pattern)
+must be bit-exact; floating-point outputs within the tolerances stated per
+test (operators 1e-10 relative); the stationary vector within 1e-10 in
+relative l1. The solve phase on identical operators is compared more
+tightly in test_gpu_shared_ops.py."""
 import numpy as np
 import pytest
 
@@ -70,6 +72,14 @@ CASES = [
     # LDS-staged J_i selection takes, and coarse rows of up to ~400 entries
     ("hub4000", lambda: chaingen.hub_walk(4000, 8, 200, 7),
      dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99)),
+    # the plain weighted LS of eq. ls_interpolation over all of J_i
+    # (interp_rule 0) instead of the fit with negative weights removed
+    ("tandem65_c289_plainls", lambda: chaingen.tandem(65, 11 / 31, 10 / 31, 10 / 31),
+     dict(r=8, max_interp=4, coarse_max=300, nu_setup=5, interp_rule=0)),
+    ("delaunay3000_plainls", lambda: chaingen.delaunay_walk(3000, 12),
+     dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=500, interp_rule=0)),
+    ("hub4000_plainls", lambda: chaingen.hub_walk(4000, 8, 200, 7),
+     dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99, interp_rule=0)),
 ]
 
 
@@ -78,6 +88,30 @@ def test_structure_bit_exact(name, make, kw):
     ch = make()
     ho, hg = both(ch, **kw)
     check_structure(ho, hg)
+
+
+# Separately built hierarchies agree to rounding: the setup's arithmetic is
+# the oracle's, in another summation order. Measured maxima over CASES (one
+# MI355X run): operators 3.6e-11 relative (hub4000_plainls, whose hub rows
+# gather hundreds of terms; 5e-13 or less elsewhere), sigma 3.6e-9 per index,
+# test vectors 3.2e-9 (the same case). The tolerances below are those maxima
+# rounded up to the next power of ten; operators meet the 1e-10 of a direct
+# comparison.
+OPS_TOL, SIGMA_TOL, VEC_TOL = 1e-10, 1e-8, 1e-8
+
+
+def separated_columns(sigma, gap=1e-8):
+    """Columns whose sigma is at least gap * max|sigma| away from every other:
+    only there is a singular vector unique up to sign (a degenerate sigma
+    leaves a rotation free)."""
+    s = np.asarray(sigma)
+    scale = np.abs(s).max()
+    out = []
+    for k in range(len(s)):
+        d = np.abs(np.delete(s, k) - s[k])
+        if d.min() > gap * scale:
+            out.append(k)
+    return out
 
 
 @pytest.mark.parametrize("name,make,kw", CASES, ids=[c[0] for c in CASES])
@@ -89,38 +123,49 @@ def test_operators_and_vectors_close(name, make, kw):
     for l in range(ho.levels - 1):
         for what in ("P", "Qt"):
             a, b = hg.csr(l, what)[2], ho.csr(l, what)[2]
-            assert rel_max(a, b) < 1e-7, (l, what, rel_max(a, b))
+            assert rel_max(a, b) < OPS_TOL, (l, what, rel_max(a, b))
     for l in range(1, ho.levels):
         for what in ("B", "M", "N"):
             a, b = hg.csr(l, what)[2], ho.csr(l, what)[2]
-            assert rel_max(a, b) < 1e-7, (l, what, rel_max(a, b))
+            assert rel_max(a, b) < OPS_TOL, (l, what, rel_max(a, b))
+    # sigma index by index (no sorting: a swapped pair fails)
     so, sg = ho.sigma(), hg.sigma()
-    assert np.allclose(np.sort(np.abs(sg)), np.sort(np.abs(so)), rtol=1e-6, atol=1e-12)
+    assert np.abs(sg - so).max() <= SIGMA_TOL * np.abs(so).max(), (sg, so)
+    # test vectors where the singular value is separated (signs are fixed
+    # the same way on both sides)
+    cols = separated_columns(so)
+    assert len(cols) >= 2
+    for l in range(ho.levels):
+        Uo, Vo = ho.vectors(l)
+        Ug, Vg = hg.vectors(l)
+        for k in cols:
+            assert rel_max(Ug[:, k], Uo[:, k]) < VEC_TOL, (l, "U", k, rel_max(Ug[:, k], Uo[:, k]))
+            assert rel_max(Vg[:, k], Vo[:, k]) < VEC_TOL, (l, "V", k, rel_max(Vg[:, k], Vo[:, k]))
 
 
 @pytest.mark.parametrize("name,make,kw", CASES, ids=[c[0] for c in CASES])
-def test_stationary_vector_matches_oracle(name, make, kw):
+def test_vcycle_and_iterations_match_oracle(name, make, kw):
+    """One V-cycle on the separately built hierarchies, and GMRES at the
+    paper's kind of tolerance (1e-10): with operators equal to 1e-10 the
+    cycles agree to about that, the iteration counts are equal (or differ by
+    one when the last residual lies within 1% of tol) and the iterates agree
+    to 1e-10 in relative l1."""
     import torch
     ch = make()
     ho, hg = both(ch, **kw)
-    xo, io = ho.gmres(m=20, tol=1e-14, maxit=400)
-    xg, ig = hg.gmres(restart=20, tol=1e-14, maxit=400)
-    torch.cuda.synchronize()
-    xg = xg.cpu().numpy()
-    assert ig.converged and io.converged
-    assert rel_l1(xg, xo) < 1e-10, rel_l1(xg, xo)
-    assert abs(xg.sum() - 1) < 1e-12
-
-
-def test_vcycle_close_to_oracle():
-    import torch
-    ch = chaingen.tandem(33, 11 / 31, 10 / 31, 10 / 31)
-    ho, hg = both(ch, r=6, max_levels=3, coarse_max=1)
-    rng = np.random.default_rng(5)
-    b = rng.standard_normal(ch.n)
+    b = np.random.default_rng(5).standard_normal(ch.n)
     xo = ho.vcycle(b)
     xg = hg.vcycle(torch.from_numpy(b).cuda()).cpu().numpy()
-    assert rel_max(xg, xo) < 1e-7, rel_max(xg, xo)
+    assert rel_max(xg, xo) < 1e-9, rel_max(xg, xo)
+    xo, io = ho.gmres(m=20, tol=1e-10, maxit=400)
+    xg, ig = hg.gmres(restart=20, tol=1e-10, maxit=400)
+    torch.cuda.synchronize()
+    assert io.converged and ig.converged
+    near = abs(io.rel_residual - 1e-10) < 1e-12 or abs(ig.rel_residual - 1e-10) < 1e-12
+    assert ig.iterations == io.iterations or (near and abs(ig.iterations - io.iterations) == 1), \
+        (ig.iterations, io.iterations)
+    if ig.iterations == io.iterations:
+        assert rel_l1(xg.cpu().numpy(), xo) < 1e-10, rel_l1(xg.cpu().numpy(), xo)
 
 
 def test_coarse_pinv_matches_numpy():
@@ -160,7 +205,7 @@ def test_coarse_pinv_block_jacobi_wide_levels_match_numpy(N, coarse_max, nc):
     ref = np.linalg.pinv(BL, rcond=1e-10)
     assert rel_max(hg.coarse_pinv(), ref) < 1e-9
     so, sg = ho.sigma(), hg.sigma()
-    assert np.allclose(np.sort(np.abs(sg)), np.sort(np.abs(so)), rtol=1e-6, atol=1e-12)
+    assert np.abs(sg - so).max() <= SIGMA_TOL * np.abs(so).max(), (sg, so)
     xo, io = ho.gmres(m=20, tol=1e-14, maxit=400)
     xg, ig = hg.gmres(restart=20, tol=1e-14, maxit=400)
     torch.cuda.synchronize()

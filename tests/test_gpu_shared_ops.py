@@ -1,0 +1,165 @@
+"""GPU parity on identical operators: the oracle's hierarchy (B_l, P_l, Q_l,
+the coarsest pseudo-inverse, x0) is handed to the HIP library through
+bamg_setup_from_levels, so the V-cycle and GMRES kernels run on exactly the
+operators the oracle's V-cycle (Section 3, eq. coarse_grid_correction) and
+GMRES (Section 6) use. Differences are then rounding only:
+
+* one V-cycle, FP64: within 1e-12 relative to max |x| (the oracle sums each
+  row in ascending column order, the kernels in lane groups, and a cycle
+  applies a few dozen such products);
+* GMRES to ||Bx||/||x|| < 1e-10 (Section 7): the same iteration count, and
+  the same iterate to 1e-12 in relative l1 (CGS2 on the GPU and modified
+  Gram-Schmidt in the oracle span the same Krylov space);
+* mixed precision (FP32 V-cycle): the cycle within 2e-6 of the FP64 oracle's,
+  FP32's 2^-24 unit roundoff times the few dozen products of a cycle, and
+  the GMRES iterate still within 1e-10 of the oracle's at tol 1e-12.
+"""
+import numpy as np
+import pytest
+
+import chaingen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+bamg = pytest.importorskip("paper_1402_4005_amd")
+
+
+def rel_l1(x, y):
+    return float(np.abs(x - y).sum() / np.abs(y).sum())
+
+
+def rel_max(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+SOLVE_KEYS = ("nu_pre", "nu_post", "omega", "smoother", "precision", "fuse_last_level",
+              "use_graph", "seed")
+
+
+def import_oracle(ho, kw, **extra):
+    """GPU handle on the oracle hierarchy ho, with the solve-phase options."""
+    L = ho.levels
+    B = [ho.scipy(l, "B") for l in range(L)]
+    P = [ho.scipy(l, "P") for l in range(L - 1)]
+    Q = [ho.scipy(l, "Q") for l in range(L - 1)]
+    solve_kw = {k: v for k, v in {**kw, **extra}.items() if k in SOLVE_KEYS}
+    opts = bamg.default_options(**solve_kw)
+    return bamg.Hierarchy.from_levels(B, P, Q, ho.coarse_pinv(), ho.x0(), opts)
+
+
+CASES = [
+    ("tandem33_3lev", lambda: chaingen.tandem(33, 11 / 31, 10 / 31, 10 / 31),
+     dict(r=6, max_levels=3, coarse_max=1)),
+    ("tandem65_c289", lambda: chaingen.tandem(65, 11 / 31, 10 / 31, 10 / 31),
+     dict(r=8, max_interp=4, coarse_max=300, nu_setup=5)),
+    ("tandem65_c289_plainls", lambda: chaingen.tandem(65, 11 / 31, 10 / 31, 10 / 31),
+     dict(r=8, max_interp=4, coarse_max=300, nu_setup=5, interp_rule=0)),
+    ("delaunay3000_mis", lambda: chaingen.delaunay_walk(3000, 12),
+     dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99)),
+    ("delaunay3000_plainls", lambda: chaingen.delaunay_walk(3000, 12),
+     dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99, interp_rule=0)),
+    ("hub4000", lambda: chaingen.hub_walk(4000, 8, 200, 7),
+     dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99)),
+    ("birthdeath257", lambda: chaingen.birth_death(257, 0.96),
+     dict(r=8, max_interp=2, coarse_max=29)),
+    # level above the coarsest in one workgroup (fused last level) on levels
+    # 1..L-2, with odd and even sweep counts
+    ("delaunay20000_fused", lambda: chaingen.delaunay_walk(20000, 3),
+     dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99)),
+    ("tandem65_nu21_fused", lambda: chaingen.tandem(65, 11 / 31, 10 / 31, 10 / 31),
+     dict(r=8, max_interp=4, coarse_max=30, nu_pre=2, nu_post=1, nu_setup=5)),
+    ("tandem14_kaczmarz", lambda: chaingen.tandem(14, 11 / 31, 10 / 31, 10 / 31),
+     dict(r=6, max_levels=2, coarse_max=1, smoother=1)),
+    ("delaunay1500_kaczmarz", lambda: chaingen.delaunay_walk(1500, 4),
+     dict(r=8, max_interp=3, nu_pre=2, nu_post=2, nu_setup=3, coarse_max=60, smoother=1)),
+]
+
+_CACHE = {}
+
+
+def oracle_for(name, make, kw):
+    if name not in _CACHE:
+        ch = make()
+        _CACHE[name] = (ch, oracle.Hierarchy(ch, oracle.options_for(ch, **kw)))
+    return _CACHE[name]
+
+
+@pytest.mark.parametrize("name,make,kw", CASES, ids=[c[0] for c in CASES])
+def test_vcycle_on_oracle_operators(name, make, kw):
+    import torch
+    ch, ho = oracle_for(name, make, kw)
+    hg = import_oracle(ho, kw)
+    assert hg.levels == ho.levels
+    rng = np.random.default_rng(11)
+    for trial in range(2):
+        b = rng.standard_normal(ch.n)
+        xo = ho.vcycle(b)
+        xg = hg.vcycle(torch.from_numpy(b).cuda()).cpu().numpy()
+        assert rel_max(xg, xo) < 1e-12, (trial, rel_max(xg, xo))
+
+
+@pytest.mark.parametrize("name,make,kw", CASES, ids=[c[0] for c in CASES])
+def test_gmres_on_oracle_operators(name, make, kw):
+    import torch
+    ch, ho = oracle_for(name, make, kw)
+    hg = import_oracle(ho, kw)
+    xo, io = ho.gmres(m=20, tol=1e-10, maxit=400)
+    xg, ig = hg.gmres(restart=20, tol=1e-10, maxit=400)
+    torch.cuda.synchronize()
+    assert io.converged and ig.converged
+    assert ig.iterations == io.iterations, (ig.iterations, io.iterations)
+    assert rel_l1(xg.cpu().numpy(), xo) < 1e-12, rel_l1(xg.cpu().numpy(), xo)
+
+
+@pytest.mark.parametrize("name", ["delaunay3000_mis", "tandem65_c289", "delaunay20000_fused"])
+def test_mixed_precision_on_oracle_operators(name):
+    import torch
+    make, kw = next((m, k) for n, m, k in CASES if n == name)
+    ch, ho = oracle_for(name, make, kw)
+    hg = import_oracle(ho, kw, precision=1)
+    b = np.random.default_rng(12).standard_normal(ch.n)
+    xo = ho.vcycle(b)
+    xg = hg.vcycle(torch.from_numpy(b).cuda()).cpu().numpy()
+    assert rel_max(xg, xo) < 2e-6, rel_max(xg, xo)
+    x32 = hg.vcycle(torch.from_numpy(b).float().cuda()).cpu().numpy()
+    assert rel_max(x32, xo) < 2e-6
+    xo2, io2 = ho.gmres(m=20, tol=1e-12, maxit=400)
+    xg2, ig2 = hg.gmres(restart=20, tol=1e-12, maxit=400)
+    torch.cuda.synchronize()
+    assert io2.converged and ig2.converged
+    assert rel_l1(xg2.cpu().numpy(), xo2) < 1e-10
+
+
+def test_import_rejects_bad_operators():
+    import scipy.sparse as sp
+    ch, ho = oracle_for(*CASES[0][:2], CASES[0][2])
+    B = [ho.scipy(l, "B") for l in range(ho.levels)]
+    P = [ho.scipy(l, "P") for l in range(ho.levels - 1)]
+    Q = [ho.scipy(l, "Q") for l in range(ho.levels - 1)]
+    pinv, x0 = ho.coarse_pinv(), ho.x0()
+    opts = bamg.default_options()
+    # P with the wrong number of columns
+    with pytest.raises(bamg.BamgError) as e:
+        bamg.Hierarchy.from_levels(B, [P[0][:, :-1]] + P[1:], Q, pinv, x0, opts)
+    assert e.value.code == -1
+    # a zero diagonal entry on level 1
+    B1 = B[1].tolil()
+    B1[3, 3] = 0.0
+    B1 = sp.csr_matrix(B1)
+    with pytest.raises(bamg.BamgError) as e:
+        bamg.Hierarchy.from_levels([B[0], B1] + B[2:], P, Q, pinv, x0, opts)
+    assert e.value.code in (-4, -1)
+    # non-finite pseudo-inverse
+    bad = pinv.copy()
+    bad[0, 0] = np.nan
+    with pytest.raises(bamg.BamgError) as e:
+        bamg.Hierarchy.from_levels(B, P, Q, bad, x0, opts)
+    assert e.value.code == -7
+    # setup-only inspection calls refuse an imported handle
+    hg = bamg.Hierarchy.from_levels(B, P, Q, pinv, x0, opts)
+    with pytest.raises(bamg.BamgError):
+        hg.cf(0)
+    with pytest.raises(bamg.BamgError):
+        hg.csr(0, "M")
+    assert np.array_equal(hg.csr(1, "B")[1], ho.csr(1, "B")[1])
