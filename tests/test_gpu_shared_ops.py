@@ -61,6 +61,11 @@ CASES = [
      dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99, interp_rule=0)),
     ("hub4000", lambda: chaingen.hub_walk(4000, 8, 200, 7),
      dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99)),
+    # (hub4000 with the plain LS fit is left out: its hub rows get large
+    # weights of both signs, the V-cycle returns entries near 1e12 for a
+    # unit input, rounding is amplified accordingly (3e-11 measured) and
+    # GMRES needs several restart cycles; the separately built hierarchies
+    # are compared operator by operator in test_gpu_parity.py)
     ("birthdeath257", lambda: chaingen.birth_death(257, 0.96),
      dict(r=8, max_interp=2, coarse_max=29)),
     # level above the coarsest in one workgroup (fused last level) on levels
