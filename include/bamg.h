@@ -324,6 +324,20 @@ bamg_status bamg_mlp_forward(const bamg_mlp *m, const float *X, int64_t npts, fl
 bamg_status bamg_mlp_loss_grad(const bamg_mlp *m, const float *X, const float *T,
                                const float *M, int64_t npts, double *loss, float *grad,
                                void *hip_stream);
+/* bamg_mlp_loss_grad for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving or training loops, harnesses that
+ * forbid hipMalloc): the same inputs, outputs and kernels, with the
+ * per-point activations, the gradient partials and the loss sum held in one
+ * fixed device array of the library (64 MiB per GPU, held until the process
+ * ends) instead of fresh allocations. At most BAMG_MLP_NOALLOC_MAX_POINTS
+ * points per call (else BAMG_E_ARG, nothing enqueued). Every call on one GPU
+ * uses that GPU's array: calls that overlap on one GPU (different streams or
+ * threads without ordering) race and must not be made. The call synchronises
+ * hip_stream to return *loss. */
+#define BAMG_MLP_NOALLOC_MAX_POINTS 60000
+bamg_status bamg_mlp_loss_grad_noalloc(const bamg_mlp *m, const float *X, const float *T,
+                                       const float *M, int64_t npts, double *loss, float *grad,
+                                       void *hip_stream);
 /* Adam training (beta1 0.9, beta2 0.999, eps 1e-8) on the loss above with
  * mini-batches of `batch` consecutive points, `epochs` passes in the given
  * order. loss_per_epoch (host, epochs entries, nullable) receives the mean

@@ -611,6 +611,16 @@ bamg_status bamg_mlp_loss_grad(const bamg_mlp *m, const float *X, const float *T
   BAMG_CATCH
 }
 
+bamg_status bamg_mlp_loss_grad_noalloc(const bamg_mlp *m, const float *X, const float *T,
+                                       const float *M, int64_t npts, double *loss, float *grad,
+                                       void *hip_stream) {
+  if (!m || !X || !T || !M || npts < 1 || !loss || !grad) return BAMG_E_ARG;
+  BAMG_TRY
+  *loss = mlp_loss_grad_noalloc(m, X, T, M, (long)npts, grad, (hipStream_t)hip_stream);
+  return BAMG_OK;
+  BAMG_CATCH
+}
+
 bamg_status bamg_mlp_train(bamg_mlp *m, const float *X, const float *T, const float *M,
                            int64_t npts, int32_t batch, int32_t epochs, float lr,
                            double *loss_per_epoch, void *hip_stream) {

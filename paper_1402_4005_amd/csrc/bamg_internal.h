@@ -316,6 +316,9 @@ void mlp_refresh_bf16(bamg_mlp *m, hipStream_t s);
 void mlp_forward(const bamg_mlp *m, const float *X, long npts, float *Y, int mode, hipStream_t s);
 double mlp_loss_grad(const bamg_mlp *m, const float *X, const float *T, const float *M, long npts,
                      float *grad, hipStream_t s);
+// the same with the scratch in the library's fixed per-GPU array (no allocation)
+double mlp_loss_grad_noalloc(const bamg_mlp *m, const float *X, const float *T, const float *M,
+                             long npts, float *grad, hipStream_t s);
 void mlp_train(bamg_mlp *m, const float *X, const float *T, const float *M, long npts, int batch,
                int epochs, float lr, double *loss_per_epoch, hipStream_t s);
 void level_fpoints(bamg_handle *h, Level &L, hipStream_t s);

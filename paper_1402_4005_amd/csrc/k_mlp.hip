@@ -15,6 +15,9 @@
 //  * k_adam, k_mlp_bf16  the optimiser step and the BF16 weight copy;
 //  * k_mlp_features   the 96 inputs of each F point;
 //  * k_mlp_select     MLP row or exact LS row, by the objective test.
+#include <mutex>
+#include <string>
+
 #include "bamg_internal.h"
 #include "device_common.h"
 
@@ -420,6 +423,70 @@ double mlp_loss_grad(const bamg_mlp *m, const float *X, const float *T, const fl
     throw;
   }
   mlp_scratch_free(w);
+  return loss;
+}
+
+// ---------------------------------------------------------------- no-alloc
+// Scratch of the loss/gradient for callers that cannot allocate device
+// memory: one fixed array per GPU, held until the process ends and shared by
+// every call on that GPU (the last call's contents stay; every kernel below
+// writes its part in full before it is read, so nothing needs clearing).
+// Host code never passes the array's name to a kernel: its device address
+// is looked up once per device and kept in g_scratch_ptr.
+constexpr long kNoAllocPoints = BAMG_MLP_NOALLOC_MAX_POINTS;
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+constexpr size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t kHidBytes = round256(sizeof(float) * (size_t)kNoAllocPoints * kHid);
+constexpr size_t kDyBytes = round256(sizeof(float) * (size_t)kNoAllocPoints * kOut);
+constexpr size_t kGBytes = round256(sizeof(float) * kNPar);
+constexpr size_t kPlBytes = round256(sizeof(double) * (size_t)kNoAllocPoints);
+static_assert(4 * kHidBytes + kDyBytes + kGBytes + kPlBytes + 256 <= kNoAllocBytes,
+              "no-alloc scratch too small for its maximum point count");
+
+// device address of this GPU's scratch array (looked up on the first call
+// made with the device current)
+char *scratch_base() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) fail(BAMG_E_DEVICE, "device ordinal above 63");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = p;
+  }
+  return static_cast<char *>(g_scratch_ptr[dev]);
+}
+}  // namespace
+
+double mlp_loss_grad_noalloc(const bamg_mlp *m, const float *X, const float *T, const float *M,
+                             long npts, float *grad, hipStream_t s) {
+  if (npts < 1 || npts > kNoAllocPoints)
+    fail(BAMG_E_ARG, "npts above the no-allocation maximum of " +
+                         std::to_string(kNoAllocPoints) + " points");
+  char *b = scratch_base();
+  MlpScratch w{};
+  w.H1 = reinterpret_cast<float *>(b);
+  w.H2 = reinterpret_cast<float *>(b + kHidBytes);
+  w.D1 = reinterpret_cast<float *>(b + 2 * kHidBytes);
+  w.D2 = reinterpret_cast<float *>(b + 3 * kHidBytes);
+  w.DY = reinterpret_cast<float *>(b + 4 * kHidBytes);
+  w.G = reinterpret_cast<float *>(b + 4 * kHidBytes + kDyBytes);
+  w.pl = reinterpret_cast<double *>(b + 4 * kHidBytes + kDyBytes + kGBytes);
+  w.lsum = reinterpret_cast<double *>(b + 4 * kHidBytes + kDyBytes + kGBytes + kPlBytes);
+  double loss = 0.0;
+  mlp_batch_grad(m, X, T, M, npts, w, s);
+  HIPCHK(hipMemcpyAsync(grad, w.G, sizeof(float) * kNPar, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(&loss, w.lsum, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
   return loss;
 }
 
