@@ -263,8 +263,15 @@ bamg_status bamg_coarse_pinv(const bamg_handle *h, double *bdag);
  * touches it, the dense coarsest solve; FP64 or FP32 values as stored. */
 bamg_status bamg_vcycle_bytes(const bamg_handle *h, double *bytes);
 /* Lanes of a 64-wide wave that share one CSR row in the sweeps and
- * residual of level l (after autotuning, if it was requested). */
+ * residual of level l (after autotuning, if it was requested; otherwise the
+ * average row length rounded up to a power of two, at most 4). */
 bamg_status bamg_level_lanes(const bamg_handle *h, int32_t l, int32_t *lanes);
+/* Set the lanes per row (1, 2 or 4) of level l's sweeps and residual
+ * (l < levels - 1), e.g. to pin a launch shape for profiling. Each row is
+ * summed in one fixed order whatever the lane count, so results are bitwise
+ * the same for every choice. BAMG_E_ARG for another value, or once GMRES
+ * has captured the V-cycle into a graph (use_graph = 1). */
+bamg_status bamg_level_set_lanes(bamg_handle *h, int32_t l, int32_t lanes);
 
 /* Kernel timing with HIP events on the launch stream. kernel 0 = the
  * weighted-Jacobi sweep on the finest level (the V-cycle smoother that

@@ -105,6 +105,7 @@ def lib():
         L.bamg_coarse_pinv.argtypes = [V, V]
         L.bamg_vcycle_bytes.argtypes = [V, V]
         L.bamg_level_lanes.argtypes = [V, C.c_int32, P(C.c_int32)]
+        L.bamg_level_set_lanes.argtypes = [V, C.c_int32, C.c_int32]
         L.bamg_kernel_profile_begin.argtypes = [V, C.c_int32]
         L.bamg_kernel_profile_end.argtypes = [V, V, V, V]
         L.bamg_destroy.argtypes = [V]
@@ -418,6 +419,10 @@ class Hierarchy:
         v = C.c_int32()
         _check(lib().bamg_level_lanes(self.h, l, C.byref(v)))
         return v.value
+
+    def set_lanes(self, l, lanes):
+        """Pin the lanes per row (1, 2, 4) of level l's sweeps and residual."""
+        _check(lib().bamg_level_set_lanes(self.h, l, lanes))
 
     def profile_begin(self, kernel=0):
         _check(lib().bamg_kernel_profile_begin(self.h, kernel))

@@ -517,7 +517,15 @@ bamg_status bamg_vcycle_bytes(const bamg_handle *h, double *bytes) {
 bamg_status bamg_level_lanes(const bamg_handle *h, int32_t l, int32_t *lanes) {
   if (!h || !lanes || l < 0 || l >= h->L) return BAMG_E_ARG;
   const Level &L = h->lv[l];
-  *lanes = L.lanes > 0 ? L.lanes : lanes_for(L.n, L.B.nnz);
+  *lanes = L.lanes > 0 ? L.lanes : sweep_lanes_default(L.n, L.B.nnz);
+  return BAMG_OK;
+}
+
+bamg_status bamg_level_set_lanes(bamg_handle *h, int32_t l, int32_t lanes) {
+  if (!h || l < 0 || l >= h->L - 1) return BAMG_E_ARG;
+  if (lanes != 1 && lanes != 2 && lanes != 4) return BAMG_E_ARG;
+  if (h->vc_exec) return BAMG_E_ARG;  // a captured V-cycle keeps its launches
+  h->lv[l].lanes = lanes;
   return BAMG_OK;
 }
 

@@ -300,6 +300,14 @@ inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
 // default lanes per CSR row: the average row length rounded up to a power of two
 int lanes_for(int nr, int nnz);
+// lanes per row of the V-cycle sweeps and residuals: 1, 2 or 4, where the
+// row sums are formed in one order whatever the count (tuned, or else the
+// average row length rounded up to a power of two, at most 4)
+constexpr int kMaxTunedLanes = 4;
+inline int sweep_lanes_default(int nr, int nnz) {
+  const int l = lanes_for(nr, nnz);
+  return l < kMaxTunedLanes ? l : kMaxTunedLanes;
+}
 
 // the V-cycle of the level above the coarsest and the coarsest solve in one
 // workgroup (k_lastlevel.hip); false when the level does not fit (nothing

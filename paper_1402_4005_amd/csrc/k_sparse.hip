@@ -42,6 +42,77 @@ __device__ __forceinline__ T lane_dot(int k0, int e, const int *__restrict__ ci,
   return sum;
 }
 
+// The sum of a CSR row, sum over k in [rs, e) of val[k] * g(ci[k]), in one
+// fixed order whatever the number LPR <= 4 of lanes sharing the row, so
+// results do not depend on the lanes a tuner picks: entry k goes to partial
+// (k - rs) mod 4, each partial adds its entries in ascending order, and the
+// four partials are combined as (p0+p1)+(p2+p3). Lane `lane` of the group
+// holds the partials lane, lane + LPR, ...; a level of the combining tree is
+// a cross-lane shuffle when the two partials sit in different lanes and a
+// register add otherwise (both lanes of a shuffle form the same sum:
+// addition is commutative). Every lane of the group returns the row sum.
+// Loads as in lane_dot: U = 4 entries per round, indices and values first,
+// then the gathers. Four partials keep every sweep kernel at full occupancy
+// (eight took the one-lane sweep from 42 to 65 VGPRs).
+constexpr int kCanon = 4;
+
+template <class T, int LPR, class G>
+__device__ __forceinline__ T row_dot(int rs, int e, int lane, const int *__restrict__ ci,
+                                     const T *__restrict__ val, G g) {
+  static_assert(LPR >= 1 && LPR <= kCanon, "canonical row sums take at most 4 lanes");
+  constexpr int R = kCanon / LPR, U = 4, PH = R > U ? R / U : 1;
+  T acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0;
+  for (int k = rs + lane; k < e; k += PH * U * LPR) {
+#pragma unroll
+    for (int ph = 0; ph < PH; ++ph) {
+      const int kp = k + ph * U * LPR;
+      if (ph == 0 || kp < e) {
+        int c[U];
+        T v[U], xv[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+          const int kk = min(kp + j * LPR, e - 1);
+          c[j] = ci[kk];
+          v[j] = val[kk];
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) xv[j] = g(c[j]);
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+          if (kp + j * LPR < e) acc[(ph * U + j) % R] += v[j] * xv[j];
+      }
+    }
+  }
+#pragma unroll
+  for (int st = 1; st < kCanon; st <<= 1) {
+    if (st < LPR) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] = acc[r] + __shfl_xor(acc[r], st, LPR);
+    } else {
+      const int step = st / LPR;
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if ((r & step) == 0 && r + step < R) acc[r] = acc[r] + acc[r + step];
+    }
+  }
+  return acc[0];
+}
+
+// Row sum for any LPR: the canonical order up to 4 lanes; wider groups
+// (taken only by the transfers, whose lanes follow from the matrix shape)
+// add their lanes' shares by a butterfly.
+template <class T, int LPR, class G>
+__device__ __forceinline__ T row_sum(int rs, int e, int lane, const int *__restrict__ ci,
+                                     const T *__restrict__ val, G g) {
+  if constexpr (LPR <= kCanon) {
+    return row_dot<T, LPR>(rs, e, lane, ci, val, g);
+  } else {
+    return group_sum(lane_dot<T, LPR>(rs + lane, e, ci, val, g), LPR);
+  }
+}
+
 // y = A x (mode 0), y = b - A x (mode 1), y = y + A x (mode 2)
 template <class T, int LPR>
 __global__ void __launch_bounds__(kSpThreads)
@@ -54,8 +125,7 @@ __global__ void __launch_bounds__(kSpThreads)
   // row-wise operands are loaded first, beside the row pointers, so their
   // latency overlaps the row's gathers instead of following the reduction
   const T br = mode == 1 ? b[row] : mode == 2 ? y[row] : (T)0;
-  T sum = lane_dot<T, LPR>(rp[row] + lane, rp[row + 1], ci, val, [&](int c) { return x[c]; });
-  sum = group_sum(sum, LPR);
+  const T sum = row_sum<T, LPR>(rp[row], rp[row + 1], lane, ci, val, [&](int c) { return x[c]; });
   if (lane == 0) {
     if (mode == 0)
       y[row] = sum;
@@ -80,9 +150,8 @@ __global__ void __launch_bounds__(kSpThreads)
     return;
   }
   const T xr = xin[row], dr = dinv[row], br = b[row];  // issued beside the row pointers
-  T sum =
-      lane_dot<T, LPR>(rp[row] + lane, rp[row + 1], ci, val, [&](int c) { return xin[c]; });
-  sum = group_sum(sum, LPR);
+  const T sum =
+      row_sum<T, LPR>(rp[row], rp[row + 1], lane, ci, val, [&](int c) { return xin[c]; });
   if (lane == 0) xout[row] = xr + omega * dr * (br - sum);
 }
 
@@ -99,9 +168,8 @@ __global__ void __launch_bounds__(kSpThreads)
   const int row = (int)(gid / LPR), lane = (int)(gid % LPR);
   if (row >= nr) return;
   const T dr = dinv[row], br = b[row];  // issued beside the row pointers
-  T sum = lane_dot<T, LPR>(rp[row] + lane, rp[row + 1], ci, val,
-                           [&](int c) { return omega * dinv[c] * b[c]; });
-  sum = group_sum(sum, LPR);
+  const T sum = row_sum<T, LPR>(rp[row], rp[row + 1], lane, ci, val,
+                                [&](int c) { return omega * dinv[c] * b[c]; });
   if (lane == 0) {
     const T x1 = omega * dr * br;
     xout[row] = x1 + omega * dr * (br - sum);
@@ -170,8 +238,7 @@ __global__ void __launch_bounds__(kSpThreads)
   const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * kSpThreads + threadIdx.x;
   const int row = (int)(gid / LPR), lane = (int)(gid % LPR);
   if (row >= nr) return;
-  T sum = lane_dot<T, LPR>(rp[row] + lane, rp[row + 1], ci, val, [&](int c) { return x[c]; });
-  sum = group_sum(sum, LPR);
+  const T sum = row_sum<T, LPR>(rp[row], rp[row + 1], lane, ci, val, [&](int c) { return x[c]; });
   if (lane == 0) {
     y1[row] = sum;
     y2[row] = sum;
@@ -188,9 +255,8 @@ __global__ void __launch_bounds__(kSpThreads)
   const int row = (int)(gid / LPR), lane = (int)(gid % LPR);
   if (row >= nr) return;
   const T sc = scal[0], wr = w[row];
-  T sum = lane_dot<T, LPR>(rp[row] + lane, rp[row + 1], ci, val,
-                           [&](int c) { return w[c] * sc; });
-  sum = group_sum(sum, LPR);
+  const T sum = row_sum<T, LPR>(rp[row], rp[row + 1], lane, ci, val,
+                                [&](int c) { return w[c] * sc; });
   if (lane == 0) {
     v[row] = wr * sc;
     y1[row] = sum;

@@ -1,11 +1,13 @@
 // Autotuner for the row-parallel sweeps of the V-cycle: the number of lanes
-// that share one CSR row (1..64, a power of two) is chosen per level by
-// timing a few weighted-Jacobi sweeps of the level's own matrix with HIP
-// events, once per (device, rows, nonzeros, value type); the choice is
-// cached for the life of the process. Candidates are tried from the fewest
-// lanes up, and a wider one replaces the choice only when at least 3%
-// faster, so near-ties (within timing noise) resolve the same way in every
-// process.
+// that share one CSR row (1, 2 or 4) is chosen per level by timing a few
+// weighted-Jacobi sweeps of the level's own matrix with HIP events, once per
+// (device, rows, nonzeros, value type); the choice is cached for the life of
+// the process. The sweeps sum each row in one fixed order whatever the lane
+// count (k_sparse.hip, row_dot), so the choice changes the speed only, never
+// a bit of the result. Candidates are tried from the fewest lanes up, and a
+// wider one replaces the choice only when at least 3% faster, so near-ties
+// (within timing noise) usually resolve the same way in every process.
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -38,10 +40,11 @@ int tune_lanes(Pool &pool, const Level &L, hipStream_t s) {
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  int best = base;
+  int best = std::min(base, kMaxTunedLanes);
   float best_ms = 1e30f;
   const T om = (T)0.7;
-  for (int lanes = std::max(1, base / 8); lanes <= std::min(64, base * 2); lanes <<= 1) {
+  for (int lanes = std::max(1, base / 8); lanes <= std::min(kMaxTunedLanes, base * 2);
+       lanes <<= 1) {
     jacobi<T>(L.B, (const T *)L.Bv, (const T *)L.dinv, om, b, x, y, lanes, s);  // warm
     HIPCHK(hipEventRecord(e0, s));
     for (int it = 0; it < 4; ++it) {

@@ -152,3 +152,35 @@ def test_graph_replay_equals_direct_launches():
         h.close()
     assert out[0][1] == out[1][1]
     assert np.array_equal(out[0][0], out[1][0])
+
+
+@pytest.mark.parametrize("name", ["delaunay20000", "tandem65"])
+def test_results_bitwise_independent_of_lanes_per_row(name):
+    """The V-cycle sweeps and residuals sum every row in one fixed order
+    whatever the number of lanes sharing it, so the lanes an autotuner picks
+    (timing-dependent, per process) never change a bit: one V-cycle and a
+    whole GMRES solve are bitwise equal for 1, 2 and 4 lanes on every
+    level."""
+    import torch
+    if name == "delaunay20000":
+        ch = chaingen.delaunay_walk(20000, 3)
+        kw = dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99)
+    else:
+        ch = chaingen.tandem(65, 11 / 31, 10 / 31, 10 / 31)
+        kw = dict(r=8, max_interp=4, coarse_max=30, nu_setup=5)
+    h = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, autotune=0, fuse_last_level=0, **kw))
+    b = torch.from_numpy(np.random.default_rng(3).standard_normal(ch.n)).cuda()
+    ref_v, ref_x = None, None
+    for lanes in (1, 2, 4):
+        for l in range(h.levels - 1):
+            h.set_lanes(l, lanes)
+        v = h.vcycle(b).cpu().numpy()
+        x, info = h.gmres(restart=20, tol=1e-12, maxit=300)
+        x = x.cpu().numpy()
+        assert info.converged
+        if ref_v is None:
+            ref_v, ref_x, ref_it = v, x, info.iterations
+        else:
+            assert np.array_equal(v, ref_v), lanes
+            assert np.array_equal(x, ref_x), lanes
+            assert info.iterations == ref_it
