@@ -3,11 +3,16 @@
 One step = the whole hot path on one synthetic chain whose transition matrix
 is already resident in HBM: bamg_setup (validation, hierarchy structure, one
 bootstrap cycle, coarsest pseudo-inverse) followed by bamg_gmres_solve to the
-tolerance. Default workload: random walk on the Delaunay triangulation of
-262,144 uniform points (p_ij = 1/deg(j)), r = 8 test vectors, c = 3, 5 + 5
-Jacobi sweeps, coarsening until fewer than 100 states remain (Section 7:
-planar-graph level counts are to a coarsest level of < 100 variables),
-GMRES(20), FP64.
+tolerance. Default workload: the tandem queueing network of Section 7
+(Table 3's rates lam = 11/31, mu1 = mu2 = 10/31) on a 2049 x 2049 grid
+(4,198,401 states, the largest single-GPU size), r = 8 test vectors, c = 4,
+3 + 3 Jacobi sweeps, 8 setup sweeps, geometric coarsening down to 33 x 33
+(7 levels), GMRES(20), FP64; beside it the same steps in mixed precision and
+with the learned interpolation weights. Its finest operator and vectors
+(about 0.5 GB) exceed the 256 MB Infinity Cache, so the sweep's bandwidth is
+HBM bandwidth. The random-rate tandems of the same sizes (rates drawn
+U[0.2, 0.5] and normalised) are run too, untimed and capped at 100
+iterations, and reported with their convergence status.
 
 Prints one JSON line. `value` is the time to tolerance in ms (lower is
 better), over K timed steps. `roofline` covers the dominant kernel (the
@@ -30,18 +35,29 @@ METRIC = ("time to \u2016Bx\u2016/\u2016x\u2016<1e-10 + V-cycle HBM GB/s; "
 
 WORKLOADS = {
     # name: (kind, size, options)
+    # Table 3's rates on a 2049 x 2049 grid; coarsening stops at 33 x 33 (7
+    # levels): with a 17 x 17 coarsest level the two deepest Galerkin levels
+    # lose the sign structure Jacobi needs and GMRES stalls at this size
+    "tandem2049": ("tandem", 2049, dict(r=8, max_interp=4, coarse_max=1100, nu_setup=8,
+                                        seed=14024101)),
     "delaunay262144": ("delaunay", 262144, dict(r=8, max_interp=3, nu_pre=5, nu_post=5,
                                                  nu_setup=5, coarse_max=99, seed=14024002)),
-    # Table 3's rates (lam = 11/31, mu1 = mu2 = 10/31) on a 1025 x 1025 grid,
-    # 7 levels down to 17 x 17 as in Section 7; 8 test-vector sweeps
+    # Table 3's rates on a 1025 x 1025 grid, 7 levels down to 17 x 17 as in
+    # Section 7; 8 test-vector sweeps
     "tandem1025": ("tandem", 1025, dict(r=8, max_interp=4, coarse_max=300, nu_setup=8,
                                         seed=14024003)),
     # rates drawn U[0.2, 0.5] and normalised (seed 14024003: 0.302, 0.230, 0.468)
     "tandem1025_random": ("tandem_random", 1025, dict(r=8, max_interp=4, coarse_max=300,
                                                       nu_setup=8, seed=14024003)),
+    "tandem2049_random": ("tandem_random", 2049, dict(r=8, max_interp=4, coarse_max=1100,
+                                                      nu_setup=8, seed=14024101)),
     "tandem33": ("tandem", 33, dict(r=6, max_interp=4, max_levels=3, coarse_max=1,
                                     seed=14024001)),
 }
+
+# untimed convergence status of the random-rate tandems (rates from each seed)
+STATUS_RUNS = [("tandem1025_random", 1025, 14024003)] + \
+    [("tandem2049_random", 2049, s) for s in range(14024101, 14024106)]
 
 
 # Sources of the dominant kernel (the finest-level Jacobi sweep). The HBM
@@ -193,7 +209,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="delaunay262144", choices=sorted(WORKLOADS) + ["batch"])
+    ap.add_argument("--workload", default="tandem2049", choices=sorted(WORKLOADS) + ["batch"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--setup-cycles", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-10)
@@ -205,6 +221,8 @@ def main():
                     help="skip the mixed-precision comparison run")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-interpolation comparison run")
+    ap.add_argument("--no-status", action="store_true",
+                    help="skip the convergence status of the random-rate tandems")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1 = time the lanes per CSR row of every level's sweeps at setup")
     ap.add_argument("--graph", action="store_true",
@@ -344,7 +362,9 @@ def main():
         from paper_1402_4005_amd import learned as lmod
         tl = time.perf_counter()
         tchains = [make_chain(k2, s2, sd2) for k2, s2, sd2 in LEARN_TRAIN[kind]]
-        LX, LT, LM = lmod.harvest(tchains, **{k: v for k, v in wopts.items() if k != "seed"})
+        hkw = {k: v for k, v in wopts.items() if k != "seed"}
+        hkw["coarse_max"] = min(hkw.get("coarse_max", 300), 300)
+        LX, LT, LM = lmod.harvest(tchains, **hkw)
         net, losses = lmod.train(LX, LT, LM, epochs=120)
         train_s = time.perf_counter() - tl
         lopts = options(args.precision)
@@ -386,6 +406,28 @@ def main():
         }
         mh.close()
     last.close()
+
+    # random-rate tandems (configurations whose rates are drawn): setup and
+    # at most 100 GMRES iterations each, untimed, with the outcome
+    status = None
+    if args.workload == "tandem2049" and not args.no_status:
+        import chaingen
+        status = []
+        for name, N, sd in STATUS_RUNS:
+            rates = chaingen.tandem_random_rates(sd)
+            sch = chaingen.tandem(N, *rates)
+            sopts = bamg.options_for(sch, **dict(WORKLOADS[name][2], seed=sd))
+            entry = {"workload": name, "rate_seed": sd,
+                     "rates": [round(float(r), 4) for r in rates]}
+            try:
+                hst = bamg.Hierarchy.from_chain(sch, sopts, on_device=True, stream=stream)
+                _, sinfo = hst.gmres(restart=args.restart, tol=args.tol, maxit=100, stream=stream)
+                entry.update(converged=bool(sinfo.converged), iterations=sinfo.iterations,
+                             rel_residual=float(f"{sinfo.rel_residual:.3g}"))
+                hst.close()
+            except bamg.BamgError as e:
+                entry["error"] = str(e)
+            status.append(entry)
 
     traffic = measured_traffic(args.workload, args.precision)
     lanes0 = hinfo_lanes
@@ -449,6 +491,7 @@ def main():
         "learned": learned_line,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "random_rate_status": status,
         **extra,
     }
     print(json.dumps(line))

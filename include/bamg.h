@@ -95,7 +95,9 @@ typedef struct {
   int32_t smoother;     /* BAMG_SMOOTH_JACOBI or BAMG_SMOOTH_KACZMARZ (Section 3) */
   int32_t precision;    /* BAMG_PRECISION_FP64 or BAMG_PRECISION_MIXED */
   int32_t interp_rule;  /* 0 = plain LS over J_i, 1 = LS with negative weights removed */
-  int32_t validate;     /* 1 = check stochasticity and strong connectivity */
+  int32_t validate;     /* 1 = check stochasticity and strong connectivity; 2 = the
+                           same with the search's visited set in global memory
+                           whatever the size (the form large chains take) */
   int32_t use_graph;    /* 1 = GMRES replays the V-cycle from a captured HIP graph;
                            0 (default) = its kernels are launched one by one (the
                            host enqueues an iteration ahead, and on MI355X a graph

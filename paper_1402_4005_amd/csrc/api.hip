@@ -226,6 +226,7 @@ static bamg_status check_options(const bamg_options *o) {
   if (o->smoother != BAMG_SMOOTH_JACOBI && o->smoother != BAMG_SMOOTH_KACZMARZ) return BAMG_E_ARG;
   if (o->precision != BAMG_PRECISION_FP64 && o->precision != BAMG_PRECISION_MIXED) return BAMG_E_ARG;
   if (o->interp_rule != 0 && o->interp_rule != 1) return BAMG_E_ARG;
+  if (o->validate < 0 || o->validate > 2) return BAMG_E_ARG;
   if (o->learned < BAMG_LEARNED_OFF || o->learned > BAMG_LEARNED_RECORD) return BAMG_E_ARG;
   if (o->learned == BAMG_LEARNED_USE && !o->mlp) return BAMG_E_ARG;
   return BAMG_OK;

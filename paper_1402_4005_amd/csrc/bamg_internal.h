@@ -191,8 +191,10 @@ void build_B(const int *arp, const int *aci, const double *aval, int n, Pool &po
 int check_input(Pool &pool, const int *arp, const int *aci, const double *aval, int n, int nnz,
                 hipStream_t s);
 void colsum_launch(const Csr &Bt, const double *btv, int *flag, hipStream_t s);
-void reach_launch(const Csr &B, const Csr &Bt, int *visited, int *queues, int *flag,
-                  hipStream_t s);
+// visited: 2 ceil(n / 32) words of device scratch (bitmaps, used when they
+// do not fit in LDS or when force_global is set); queues: 4 n ints
+void reach_launch(const Csr &B, const Csr &Bt, unsigned *visited, int *queues, int *flag,
+                  bool force_global, hipStream_t s);
 int validation_status(const int *h, int n);
 void sym_graph(Pool &pool, const Csr &B, const Csr &Bt, Csr &G, hipStream_t s);
 void geom_cf(int n, int nx, int gkind, int *cf, hipStream_t s);

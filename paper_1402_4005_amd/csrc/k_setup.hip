@@ -98,28 +98,28 @@ __global__ void k_colsum_check(const int *__restrict__ trp, const int *__restric
 
 // Reachability from state 0, forward (block 0, rows of B) and backward
 // (block 1, rows of B^T) in one launch, level-synchronous breadth-first
-// search with the frontier queues in global memory. With LDSMAP the visited
-// set is a bitmap in LDS (whenever it fits: n up to about 1.3 M states), so
-// the per-level chain of dependent accesses avoids global atomics. The
-// global-atomic form is slower and, running beside the setup, slows the
-// setup's own kernels (tandem 1025^2: products 26 -> 172 us while it ran).
+// search with the frontier queues in global memory. The visited set is a
+// bitmap: in LDS whenever it fits (LDSMAP, n up to about 1.3 M states),
+// else in global memory (n / 8 bytes per direction, 525 KB at 4.2 M states,
+// small enough to stay in the L2 of the CU's XCD), so each level's chain of
+// dependent accesses is an atomic OR on a cached word. An int per state
+// updated by compare-and-swap (16.8 MB per direction at 4.2 M states) sent
+// every access to HBM: 122 ms per tandem 2049^2 setup.
 
 template <bool LDSMAP>
 __global__ void __launch_bounds__(1024)
     k_reach2(const int *__restrict__ rp0, const int *__restrict__ ci0,
              const int *__restrict__ rp1, const int *__restrict__ ci1, int n,
-             int *__restrict__ visited, int *__restrict__ queues, int *__restrict__ out) {
-  extern __shared__ unsigned bits[];
+             unsigned *__restrict__ visited, int *__restrict__ queues, int *__restrict__ out) {
+  extern __shared__ unsigned lbits[];
   __shared__ int cur_n, nxt_n, total;
   const int b = blockIdx.x, t = threadIdx.x;
   const int *rp = b ? rp1 : rp0, *ci = b ? ci1 : ci0;
-  int *vis = visited + (size_t)b * n;
-  int *qa = queues + (size_t)b * 2 * n, *qb = qa + n;
   const int words = (n + 31) >> 5;
-  if (LDSMAP)
-    for (int i = t; i < words; i += blockDim.x) bits[i] = i == 0 ? 1u : 0u;
+  unsigned *bits = LDSMAP ? lbits : visited + (size_t)b * words;
+  int *qa = queues + (size_t)b * 2 * n, *qb = qa + n;
+  for (int i = t; i < words; i += blockDim.x) bits[i] = i == 0 ? 1u : 0u;
   if (t == 0) {
-    if (!LDSMAP) vis[0] = 1;
     qa[0] = 0;
     cur_n = 1;
     nxt_n = 0;
@@ -142,13 +142,8 @@ __global__ void __launch_bounds__(1024)
         for (int j = 0; j < 4; ++j) {
           if (k + j >= e) break;
           const int u = us[j];
-          bool fresh;
-          if (LDSMAP) {
-            const unsigned m = 1u << (u & 31);
-            fresh = (atomicOr(&bits[u >> 5], m) & m) == 0;
-          } else {
-            fresh = atomicCAS(&vis[u], 0, 1) == 0;
-          }
+          const unsigned m = 1u << (u & 31);
+          const bool fresh = (atomicOr(&bits[u >> 5], m) & m) == 0;
           if (fresh) nxt[atomicAdd(&nxt_n, 1)] = u;
         }
       }
@@ -169,19 +164,18 @@ __global__ void __launch_bounds__(1024)
 
 // Launch the reachability search on stream s (the caller's auxiliary
 // stream); results land in flag[1], flag[2] (states reached each way).
-void reach_launch(const Csr &B, const Csr &Bt, int *visited, int *queues, int *flag,
-                  hipStream_t s) {
+void reach_launch(const Csr &B, const Csr &Bt, unsigned *visited, int *queues, int *flag,
+                  bool force_global, hipStream_t s) {
   const int n = B.nr;
   const size_t shm = sizeof(unsigned) * (size_t)((n + 31) / 32);
   int dev = 0, maxlds = 65536;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  if (shm + 256 <= (size_t)maxlds) {
+  if (!force_global && shm + 256 <= (size_t)maxlds) {
     HIPCHK(hipFuncSetAttribute((const void *)k_reach2<true>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     k_reach2<true><<<2, 1024, shm, s>>>(B.rp, B.ci, Bt.rp, Bt.ci, n, visited, queues, flag + 1);
   } else {
-    fill_i32(visited, 0, 2 * (size_t)n, s);
     k_reach2<false><<<2, 1024, 0, s>>>(B.rp, B.ci, Bt.rp, Bt.ci, n, visited, queues, flag + 1);
   }
   LAUNCHCHK();

@@ -282,3 +282,44 @@ def test_hub_rows_are_f_points():
     cf = ho.cf(0)[0]
     assert (cf[4000:] == 0).any()
     assert ch.indptr[4001] - ch.indptr[4000] > 128
+
+
+@pytest.mark.parametrize("validate", [1, 2])
+def test_reachability_search_both_forms(validate):
+    """The strong-connectivity check in both of its forms (visited bitmap in
+    LDS, and in global memory as chains above about 1.3 M states use it):
+    a reducible chain is rejected, an irreducible one gives the same
+    hierarchy and solution either way."""
+    import scipy.sparse as sp
+    import torch
+    A = sp.lil_matrix((6, 6))
+    for i in range(3):
+        A[(i + 1) % 3, i] = 0.5
+        A[i, i] = 0.5
+        A[3 + (i + 1) % 3, 3 + i] = 0.5
+        A[3 + i, 3 + i] = 0.5
+    bad = chaingen.Chain(A.tocsr())
+    with pytest.raises(bamg.BamgError) as e:
+        bamg.Hierarchy.from_chain(bad, bamg.default_options(r=2, coarsening="mis", coarse_max=1,
+                                                             max_levels=2, validate=validate))
+    assert e.value.code == -3
+    # one-way edge: every state reachable from 0, but 0 not from state 5
+    B = sp.lil_matrix((6, 6))
+    for i in range(5):
+        B[i + 1, i] = 0.5
+        B[i, i] = 0.5
+    B[0, 5] = 0.0
+    B[5, 5] = 1.0
+    with pytest.raises(bamg.BamgError) as e:
+        bamg.Hierarchy.from_chain(chaingen.Chain(B.tocsr()),
+                                  bamg.default_options(r=2, coarsening="mis", coarse_max=1,
+                                                       max_levels=2, validate=validate))
+    assert e.value.code == -3
+    ch = chaingen.delaunay_walk(3000, 12)
+    kw = dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99)
+    h1 = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, validate=1, **kw))
+    h2 = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, validate=validate, **kw))
+    x1, _ = h1.gmres(tol=1e-12, maxit=200)
+    x2, _ = h2.gmres(tol=1e-12, maxit=200)
+    torch.cuda.synchronize()
+    assert torch.equal(x1, x2)
