@@ -44,7 +44,8 @@ class Options(C.Structure):
                 ("max_interp", C.c_int32), ("max_levels", C.c_int32), ("coarse_max", C.c_int32),
                 ("coarsening", C.c_int32), ("geom_kind", C.c_int32), ("nx", C.c_int32),
                 ("ny", C.c_int32), ("seed", C.c_uint64), ("smoother", C.c_int32),
-                ("interp_rule", C.c_int32), ("record_features", C.c_int32)]
+                ("interp_rule", C.c_int32), ("record_features", C.c_int32),
+                ("cycle", C.c_int32), ("mu", C.c_int32), ("restriction", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -71,6 +72,7 @@ def lib():
             getattr(_lib, name).argtypes = [C.c_void_p, C.c_void_p]
         _lib.orc_complexity.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         _lib.orc_vcycle.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        _lib.orc_cycle.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
         _lib.orc_smooth.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         _lib.orc_gmres.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_int32,
                                    C.c_int32, C.c_int32, P(Info)]
@@ -104,6 +106,10 @@ def default_options(**kw) -> Options:
             v = {"geom": 0, "mis": 1}[v]
         if k == "smoother" and isinstance(v, str):
             v = {"jacobi": 0, "kaczmarz": 1}[v]
+        if k == "cycle" and isinstance(v, str):
+            v = {"V": 0, "W": 1, "F": 2}[v]
+        if k == "restriction" and isinstance(v, str):
+            v = {"ls": 0, "average": 1}[v]
         setattr(o, k, v)
     return o
 
@@ -227,6 +233,17 @@ class Hierarchy:
         b = np.ascontiguousarray(b, np.float64)
         x = np.zeros_like(b)
         lib().orc_vcycle(self.h, _p(b), _p(x))
+        return x
+
+    def cycle(self, b, kind="V", x=None):
+        """One cycle of type kind ('V', 'W', 'F') for B x = b on level 0, from
+        x = 0, or from the given x."""
+        b = np.ascontiguousarray(b, np.float64)
+        xz = x is None
+        x = np.zeros_like(b) if xz else np.array(x, np.float64, copy=True)
+        st = lib().orc_cycle(self.h, {"V": 0, "W": 1, "F": 2}[kind], _p(b), _p(x), 1 if xz else 0)
+        if st:
+            raise OracleError(st)
         return x
 
     def smooth(self, l, b, x):

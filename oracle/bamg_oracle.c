@@ -608,6 +608,9 @@ void orc_default_options(orc_options *o) {
   o->seed = 14024001ULL;
   o->smoother = ORC_SMOOTH_JACOBI;
   o->interp_rule = 1;
+  o->cycle = ORC_CYCLE_V;
+  o->mu = 1;
+  o->restriction = 0;
 }
 
 /* symmetrised pattern of B without the diagonal (for MIS and J_i) */
@@ -1104,6 +1107,12 @@ static void fit_transfer(orc_ctx *c, level *L, int record) {
       for (int tt = 0; tt < m; ++tt) G[k * m + tt] = L->U[(size_t)L->cpts[L->P.ci[a + tt]] * r + k];
       g[k] = L->U[(size_t)i * r + k];
     }
+    if (c->o.restriction == 1) {
+      /* simple averaging (Section 5, the alternative the constraint is
+       * compared with): every entry of column i of Q is 1 / |J_i| */
+      for (int tt = 0; tt < m; ++tt) L->Qt.v[a + tt] = 1.0 / m;
+      continue;
+    }
     fit_point(c->o.interp_rule, r, m, G, g, wu, 1, p);
     for (int tt = 0; tt < m; ++tt) L->Qt.v[a + tt] = p[tt];
   }
@@ -1151,27 +1160,32 @@ static int coarsest_triplets(orc_ctx *c, level *L) {
   return st;
 }
 
-/* bamg_mle (Algorithm 1) with R-MU, R-KV, R-NSET, R-NORM. */
+/* bamg_mle (Algorithm 1) with R-KV, R-NSET, R-NORM: smoothing, then mu
+ * passes of the inner loop (fits, Galerkin products, injection, recursion,
+ * interpolation back, smoothing with the sigma right-hand sides); mu = 1
+ * is R-MU. A later pass fits the vectors the previous pass left. */
 static int mle(orc_ctx *c, int l, int cycle) {
   level *L = &c->lv[l];
   int r = c->o.r;
   if (l == c->L - 1) return coarsest_triplets(c, L);
   relax_pairs(c, L, cycle > 1);
-  normalize_pairs(c, L);
-  fit_transfer(c, L, c->o.record_features && cycle == 1);
-  galerkin(c, l);
-  level *C = &c->lv[l + 1];
-  for (int a = 0; a < C->n; ++a)
-    for (int k = 0; k < r; ++k) {
-      C->U[(size_t)a * r + k] = L->U[(size_t)L->cpts[a] * r + k];
-      C->V[(size_t)a * r + k] = L->V[(size_t)L->cpts[a] * r + k];
-    }
-  int st = mle(c, l + 1, cycle);
-  if (st != ORC_OK) return st;
-  csr_spmm(&L->Qt, r, C->U, L->U);
-  csr_spmm(&L->P, r, C->V, L->V);
-  for (int i = 0; i < L->n; ++i) L->U[(size_t)i * r] = 1.0;
-  relax_pairs(c, L, 1);
+  for (int pass = 0; pass < c->o.mu; ++pass) {
+    normalize_pairs(c, L);
+    fit_transfer(c, L, c->o.record_features && cycle == 1 && pass == 0);
+    galerkin(c, l);
+    level *C = &c->lv[l + 1];
+    for (int a = 0; a < C->n; ++a)
+      for (int k = 0; k < r; ++k) {
+        C->U[(size_t)a * r + k] = L->U[(size_t)L->cpts[a] * r + k];
+        C->V[(size_t)a * r + k] = L->V[(size_t)L->cpts[a] * r + k];
+      }
+    int st = mle(c, l + 1, cycle);
+    if (st != ORC_OK) return st;
+    csr_spmm(&L->Qt, r, C->U, L->U);
+    csr_spmm(&L->P, r, C->V, L->V);
+    for (int i = 0; i < L->n; ++i) L->U[(size_t)i * r] = 1.0;
+    relax_pairs(c, L, 1);
+  }
   return ORC_OK;
 }
 
@@ -1222,6 +1236,9 @@ int orc_setup(int64_t n64, const int32_t *rp, const int32_t *ci, const double *a
               const orc_options *opt, orc_ctx **out) {
   if (!out || !rp || !ci || !a || !opt || n64 < 2 || n64 > 0x7fffffff) return ORC_E_ARG;
   if (opt->r < 2 || opt->r > 64 || opt->max_interp < 1 || opt->max_interp > 16) return ORC_E_ARG;
+  if (opt->cycle < ORC_CYCLE_V || opt->cycle > ORC_CYCLE_F || opt->mu < 1 || opt->mu > 8 ||
+      (opt->restriction != 0 && opt->restriction != 1))
+    return ORC_E_ARG;
   int n = (int)n64;
   /* O1: validate (Section 2) and form B = I - A with the diagonal stored */
   csr A = csr_new(n, n, rp[n]);
@@ -1493,23 +1510,37 @@ int orc_complexity(const orc_ctx *c, double *oc, double *og) {
   return ORC_OK;
 }
 
-/* ------------------------------------------------------------ V-cycle */
-/* Section 3 and Section 6: nu_pre smoothing steps from x = 0, residual,
- * restriction by Q, recursive coarse correction (pseudo-inverse on the
- * coarsest level, eq. coarse_grid_correction), interpolation by P,
- * nu_post smoothing steps. */
-static void vcycle_rec(const orc_ctx *c, int l, const double *b, double *x) {
+/* ------------------------------------------------------------ cycles */
+/* One multigrid cycle on level l for B_l x = b from the guess x (x = 0 when
+ * x_zero), Section 3: nu_pre smoothing steps, residual, restriction by Q,
+ * coarse-grid correction, interpolation by P, nu_post smoothing steps. The
+ * coarse correction (eq. coarse_grid_correction) solves B_{l+1} e = Q r
+ * approximately: a V-cycle takes one V-cycle on level l+1 from zero; a
+ * W-cycle two W-cycles there, the second from the first's result; an
+ * F-cycle one F-cycle and then one V-cycle from its result (the cycle
+ * shapes named at the end of the two-grid discussion). On the coarsest
+ * level the cycle is the correction x + B_L^dagger (b - B_L x). */
+static void cycle_rec(const orc_ctx *c, int l, int type, const double *b, double *x,
+                      int x_zero) {
   const level *L = &c->lv[l];
   int n = L->n;
   if (l == c->L - 1) {
+    double *res = NEW(double, n);
+    if (x_zero) {
+      memcpy(res, b, sizeof(double) * n);
+    } else {
+      csr_spmv(&L->B, x, res);
+      for (int i = 0; i < n; ++i) res[i] = b[i] - res[i];
+    }
     for (int i = 0; i < n; ++i) {
       double s = 0.0;
-      for (int j = 0; j < n; ++j) s += c->bdag[(size_t)i * n + j] * b[j];
-      x[i] = s;
+      for (int j = 0; j < n; ++j) s += c->bdag[(size_t)i * n + j] * res[j];
+      x[i] = x_zero ? s : x[i] + s;
     }
+    free(res);
     return;
   }
-  memset(x, 0, sizeof(double) * n);
+  if (x_zero) memset(x, 0, sizeof(double) * n);
   for (int s = 0; s < c->o.nu_pre; ++s) smooth_vec(c, L, 0, b, x);
   double *res = NEW(double, n);
   csr_spmv(&L->B, x, res);
@@ -1517,7 +1548,9 @@ static void vcycle_rec(const orc_ctx *c, int l, const double *b, double *x) {
   int nc = L->nc;
   double *bc = NEW(double, nc), *xc = NEW(double, nc);
   csr_spmv(&L->Q, res, bc);
-  vcycle_rec(c, l + 1, bc, xc);
+  cycle_rec(c, l + 1, type, bc, xc, 1);
+  if (type == ORC_CYCLE_W) cycle_rec(c, l + 1, ORC_CYCLE_W, bc, xc, 0);
+  if (type == ORC_CYCLE_F) cycle_rec(c, l + 1, ORC_CYCLE_V, bc, xc, 0);
   double *corr = NEW(double, n);
   csr_spmv(&L->P, xc, corr);
   for (int i = 0; i < n; ++i) x[i] += corr[i];
@@ -1529,7 +1562,13 @@ static void vcycle_rec(const orc_ctx *c, int l, const double *b, double *x) {
 }
 
 int orc_vcycle(const orc_ctx *c, const double *b, double *x) {
-  vcycle_rec(c, 0, b, x);
+  cycle_rec(c, 0, c->o.cycle, b, x, 1);
+  return ORC_OK;
+}
+
+int orc_cycle(const orc_ctx *c, int type, const double *b, double *x, int x_zero) {
+  if (type < ORC_CYCLE_V || type > ORC_CYCLE_F) return ORC_E_ARG;
+  cycle_rec(c, 0, type, b, x, x_zero);
   return ORC_OK;
 }
 
@@ -1563,7 +1602,7 @@ int orc_gmres(const orc_ctx *c, double *x, int32_t m, double tol, int32_t maxit,
     csr_spmv(&L0->B, x, t);
     for (int i = 0; i < n; ++i) t[i] = -t[i];
     if (precondition)
-      vcycle_rec(c, 0, t, w);
+      cycle_rec(c, 0, c->o.cycle, t, w, 1);
     else
       memcpy(w, t, sizeof(double) * n);
     double beta = sqrt(dot(n, w, w));
@@ -1576,7 +1615,7 @@ int orc_gmres(const orc_ctx *c, double *x, int32_t m, double tol, int32_t maxit,
       double *vj = Vk + (size_t)j * n;
       csr_spmv(&L0->B, vj, t);
       if (precondition)
-        vcycle_rec(c, 0, t, w);
+        cycle_rec(c, 0, c->o.cycle, t, w, 1);
       else
         memcpy(w, t, sizeof(double) * n);
       double wnorm0 = sqrt(dot(n, w, w));

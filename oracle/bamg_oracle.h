@@ -55,7 +55,12 @@ typedef struct {
   int32_t smoother;     /* ORC_SMOOTH_JACOBI or ORC_SMOOTH_KACZMARZ */
   int32_t interp_rule;  /* 0 plain LS, 1 active set (no negative weights) */
   int32_t record_features; /* keep cycle-1 MLP features of the F points */
+  int32_t cycle;        /* preconditioning cycle: ORC_CYCLE_V, _W or _F (Section 3) */
+  int32_t mu;           /* passes of the inner loop of Algorithm 1 per level visit */
+  int32_t restriction;  /* 0 = LS fit with 1^T Q = 1^T (Section 5), 1 = simple averaging */
 } orc_options;
+
+enum { ORC_CYCLE_V = 0, ORC_CYCLE_W = 1, ORC_CYCLE_F = 2 };
 
 typedef struct {
   int32_t iterations, restarts, converged;
@@ -85,8 +90,12 @@ int orc_x0(const orc_ctx *c, double *x0);
 int orc_coarse_pinv(const orc_ctx *c, double *bdag); /* n_L x n_L row-major */
 int orc_complexity(const orc_ctx *c, double *oc, double *og);
 
-/* One V-cycle from a zero initial guess: x = C b (Section 6). */
+/* One V-cycle from a zero initial guess: x = C b (Section 6); the cycle
+ * type of the options (V, W or F). */
 int orc_vcycle(const orc_ctx *c, const double *b, double *x);
+/* One cycle of the given type (ORC_CYCLE_*) on level 0 for B x = b: from
+ * x = 0 if x_zero, else from the x passed in. */
+int orc_cycle(const orc_ctx *c, int type, const double *b, double *x, int x_zero);
 /* Apply one smoothing sweep on level l: x <- S_l(x, b). */
 int orc_smooth(const orc_ctx *c, int l, const double *b, double *x);
 /* Left-preconditioned GMRES(m) on C B e = -C B x0 (Section 6); stops when
