@@ -111,7 +111,20 @@ typedef struct {
                            V-cycle and the coarsest solve run as one launch
                            (the same steps, Jacobi smoother only); 0 = one
                            kernel per step */
+  int32_t cycle;        /* preconditioner C of GMRES and bamg_vcycle: BAMG_CYCLE_V
+                           (default), _W, _F (Section 3), or _NONE (C = I: GMRES
+                           without preconditioner, the GMRES(m) rows of Section 7) */
+  int32_t mu;           /* passes of the inner loop of Algorithm 1 per level visit, 1..8
+                           (1 = default) */
+  int32_t restriction;  /* 0 = Q fitted with 1^T Q = 1^T (Section 5), 1 = simple
+                           averaging: column i of Q has 1 / |J_i| on J_i */
 } bamg_options;
+
+/* Cycle shapes. A W-cycle takes two cycles of its own shape on the next
+ * level, the second from the first's result; an F-cycle one F-cycle and
+ * then one V-cycle. On the coarsest level a cycle from a guess x is
+ * x + B_L^+ (b - B_L x). */
+enum { BAMG_CYCLE_V = 0, BAMG_CYCLE_W = 1, BAMG_CYCLE_F = 2, BAMG_CYCLE_NONE = 3 };
 
 /* Learned interpolation weights. Not part of the paper: an addition whose
  * aim is to replace the second bootstrap cycle (BAMG^2, Section 7). In
@@ -181,10 +194,12 @@ bamg_status bamg_default_options(bamg_options *out);
 bamg_status bamg_setup(const bamg_csr *A, const bamg_geometry *geom, const bamg_options *opt,
                        const bamg_allocator *alloc, void *hip_stream, bamg_handle **out);
 
-/* One V-cycle with zero initial guess, x = C b (Section 6, eq.
- * iterate_preconditioner). b and x are device arrays of n values of type
- * dtype (BAMG_DTYPE_F64 or, for a mixed-precision handle, BAMG_DTYPE_F32);
- * they must not overlap. Asynchronous on hip_stream. */
+/* One application of the preconditioner with zero initial guess, x = C b
+ * (Section 6, eq. iterate_preconditioner): a V-cycle by default, or the
+ * handle's cycle shape (bamg_options.cycle, bamg_set_cycle). b and x are
+ * device arrays of n values of type dtype (BAMG_DTYPE_F64 or, for a
+ * mixed-precision handle, BAMG_DTYPE_F32); they must not overlap.
+ * Asynchronous on hip_stream. */
 bamg_status bamg_vcycle(bamg_handle *h, const void *b, void *x, int32_t dtype, void *hip_stream);
 
 /* GMRES(restart) on the preconditioned residual equation C B e = -C B x0
@@ -232,6 +247,10 @@ bamg_status bamg_setup_from_levels(int32_t nlevels, const bamg_level_ops *levels
                                    const double *coarse_pinv, const double *x0,
                                    const bamg_options *opt, const bamg_allocator *alloc,
                                    void *hip_stream, bamg_handle **out);
+
+/* Change the preconditioner shape of h (BAMG_CYCLE_*) without a new
+ * setup; BAMG_E_ARG for another value. */
+bamg_status bamg_set_cycle(bamg_handle *h, int32_t cycle);
 
 /* Hierarchy summary (host outputs, each may be NULL): number of levels,
  * n_l and nnz(B_l) for l < *levels (arrays sized >= 32), operator and grid

@@ -27,6 +27,7 @@ PRECISION_FP64, PRECISION_MIXED = 0, 1
 DTYPE_F64, DTYPE_F32 = 0, 1
 GEOM_NONE, GEOM_LINE, GEOM_GRID2D = 0, 1, 2
 LEARNED_OFF, LEARNED_USE, LEARNED_RECORD = 0, 1, 2
+CYCLE_V, CYCLE_W, CYCLE_F, CYCLE_NONE = 0, 1, 2, 3
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_NPARAMS = 96, 64, 8, 10888
 WHAT = {"B": 0, "Bt": 1, "M": 2, "N": 3, "P": 4, "Q": 5, "Qt": 6}
 
@@ -62,7 +63,8 @@ class Options(C.Structure):
                 ("coarsening", C.c_int32), ("seed", C.c_uint64), ("smoother", C.c_int32),
                 ("precision", C.c_int32), ("interp_rule", C.c_int32), ("validate", C.c_int32),
                 ("use_graph", C.c_int32), ("learned", C.c_int32), ("mlp", C.c_void_p),
-                ("autotune", C.c_int32), ("fuse_last_level", C.c_int32)]
+                ("autotune", C.c_int32), ("fuse_last_level", C.c_int32),
+                ("cycle", C.c_int32), ("mu", C.c_int32), ("restriction", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -96,6 +98,7 @@ def lib():
         L.bamg_gmres_solve.argtypes = [V, V, C.c_int32, C.c_double, C.c_int32, C.c_int32,
                                        P(SolveInfo), V]
         L.bamg_hierarchy_info.argtypes = [V, V, V, V, V, V]
+        L.bamg_set_cycle.argtypes = [V, C.c_int32]
         L.bamg_level_nnz.argtypes = [V, C.c_int32, C.c_int32, V, V]
         L.bamg_level_csr.argtypes = [V, C.c_int32, C.c_int32, V, V, V]
         L.bamg_level_cf.argtypes = [V, C.c_int32, V, V]
@@ -154,6 +157,8 @@ def default_options(**kw) -> Options:
         "smoother": {"jacobi": SMOOTH_JACOBI, "kaczmarz": SMOOTH_KACZMARZ},
         "precision": {"fp64": PRECISION_FP64, "mixed": PRECISION_MIXED},
         "learned": {"off": LEARNED_OFF, "use": LEARNED_USE, "record": LEARNED_RECORD},
+        "cycle": {"V": CYCLE_V, "W": CYCLE_W, "F": CYCLE_F, "none": CYCLE_NONE},
+        "restriction": {"ls": 0, "average": 1},
     }
     for k, v in kw.items():
         if k in names and isinstance(v, str):
@@ -419,6 +424,11 @@ class Hierarchy:
         v = C.c_int32()
         _check(lib().bamg_level_lanes(self.h, l, C.byref(v)))
         return v.value
+
+    def set_cycle(self, cycle):
+        """Preconditioner shape: 'V', 'W', 'F' or 'none' (C = I)."""
+        code = {"V": CYCLE_V, "W": CYCLE_W, "F": CYCLE_F, "none": CYCLE_NONE}.get(cycle, cycle)
+        _check(lib().bamg_set_cycle(self.h, code))
 
     def set_lanes(self, l, lanes):
         """Pin the lanes per row (1, 2, 4) of level l's sweeps and residual."""

@@ -191,6 +191,9 @@ bamg_status bamg_default_options(bamg_options *o) {
   o->validate = 1;
   o->use_graph = 0;
   o->fuse_last_level = 1;
+  o->cycle = BAMG_CYCLE_V;
+  o->mu = 1;
+  o->restriction = 0;
   return BAMG_OK;
 }
 
@@ -227,6 +230,9 @@ static bamg_status check_options(const bamg_options *o) {
   if (o->precision != BAMG_PRECISION_FP64 && o->precision != BAMG_PRECISION_MIXED) return BAMG_E_ARG;
   if (o->interp_rule != 0 && o->interp_rule != 1) return BAMG_E_ARG;
   if (o->validate < 0 || o->validate > 2) return BAMG_E_ARG;
+  if (o->cycle < BAMG_CYCLE_V || o->cycle > BAMG_CYCLE_NONE) return BAMG_E_ARG;
+  if (o->mu < 1 || o->mu > 8) return BAMG_E_ARG;
+  if (o->restriction != 0 && o->restriction != 1) return BAMG_E_ARG;
   if (o->learned < BAMG_LEARNED_OFF || o->learned > BAMG_LEARNED_RECORD) return BAMG_E_ARG;
   if (o->learned == BAMG_LEARNED_USE && !o->mlp) return BAMG_E_ARG;
   return BAMG_OK;
@@ -293,7 +299,8 @@ bamg_status bamg_setup_from_levels(int32_t nlevels, const bamg_level_ops *levels
   if (opt->nu_pre < 0 || opt->nu_post < 0 || opt->nu_pre > 64 || opt->nu_post > 64 ||
       !(opt->omega > 0.0 && opt->omega < 2.0) ||
       (opt->smoother != BAMG_SMOOTH_JACOBI && opt->smoother != BAMG_SMOOTH_KACZMARZ) ||
-      (opt->precision != BAMG_PRECISION_FP64 && opt->precision != BAMG_PRECISION_MIXED))
+      (opt->precision != BAMG_PRECISION_FP64 && opt->precision != BAMG_PRECISION_MIXED) ||
+      opt->cycle < BAMG_CYCLE_V || opt->cycle > BAMG_CYCLE_NONE)
     return BAMG_E_ARG;
   if (alloc && (!alloc->alloc || !alloc->free)) return BAMG_E_ARG;
   bamg_handle *h = new (std::nothrow) bamg_handle();
@@ -368,6 +375,16 @@ bamg_status bamg_gmres_solve(bamg_handle *h, void *x, int32_t restart, double to
   h->pool.s = keep;
   return BAMG_OK;
   BAMG_CATCH
+}
+
+bamg_status bamg_set_cycle(bamg_handle *h, int32_t cycle) {
+  if (!h || cycle < BAMG_CYCLE_V || cycle > BAMG_CYCLE_NONE) return BAMG_E_ARG;
+  if (h->opt.cycle != cycle && h->vc_exec) {
+    (void)hipGraphExecDestroy(h->vc_exec);  // captured with the old shape
+    h->vc_exec = nullptr;
+  }
+  h->opt.cycle = cycle;
+  return BAMG_OK;
 }
 
 bamg_status bamg_hierarchy_info(const bamg_handle *h, int32_t *levels, int64_t *n_l,

@@ -179,9 +179,9 @@ void spmv_dual_scaled(const Csr &A, const double *val, const double *w, const do
 template <class T>
 void kaczmarz_colour(const Csr &A, const T *val, const T *rowinv, const int *rows, int nrows,
                      const T *b, T *x, hipStream_t s);
-// dense coarse solve x = Bdag b (Bdag FP64)
+// dense coarse solve x = Bdag b (Bdag FP64); add != 0: x += Bdag b
 template <class T>
-void coarse_gemv(const double *bdag, int n, const T *b, T *x, hipStream_t s);
+void coarse_gemv(const double *bdag, int n, const T *b, T *x, hipStream_t s, int add = 0);
 // partial sums for dot products: out[block] = sum x_i y_i (FP64)
 void dot_partials(const double *x, const double *y, int n, double *part, int nblk, hipStream_t s);
 
@@ -211,7 +211,7 @@ template <class T>
 void fill_transfer_identity(const Level &L, T *Pv, T *Qtv, hipStream_t s);
 template <class T>
 void ls_fit(const Level &L, int r, int mmax, const T *U, const T *V, const double *wv,
-            const double *wu, int rule, T *Pv, T *Qtv, hipStream_t s);
+            const double *wu, int rule, int average, T *Pv, T *Qtv, hipStream_t s);
 template <class T>
 void dinv_from_diag(const Level &L, const T *bv, T *dinv, int *flag, bool check, hipStream_t s);
 template <class T>

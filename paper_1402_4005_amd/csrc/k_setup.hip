@@ -1316,7 +1316,8 @@ __global__ void __launch_bounds__(64)
     k_ls_fit(int n, int r, const int *__restrict__ cf, const int *__restrict__ prp,
              const int *__restrict__ pci, const int *__restrict__ cpts, const T *__restrict__ U,
              const T *__restrict__ V, const double *__restrict__ wv,
-             const double *__restrict__ wu, int rule, T *__restrict__ Pv, T *__restrict__ Qtv) {
+             const double *__restrict__ wu, int rule, int average, T *__restrict__ Pv,
+             T *__restrict__ Qtv) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int a0 = prp[i];
@@ -1340,6 +1341,11 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
   for (int t = 0; t < MM; ++t)
     if (t < m) Pv[a0 + t] = (T)coef[t];
+  if (average) {
+    // simple averaging (Section 5): every entry of column i of Q is 1 / |J_i|
+    for (int t = 0; t < m; ++t) Qtv[a0 + t] = (T)(1.0 / m);
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < RM; ++k) {
 #pragma unroll
@@ -1354,15 +1360,16 @@ __global__ void __launch_bounds__(64)
 
 template <class T>
 void ls_fit(const Level &L, int r, int mmax, const T *U, const T *V, const double *wv,
-            const double *wu, int rule, T *Pv, T *Qtv, hipStream_t s) {
+            const double *wu, int rule, int average, T *Pv, T *Qtv, hipStream_t s) {
   if (r > kRMax) fail(BAMG_E_ARG, "r above 16");
   if (mmax > kMMax) fail(BAMG_E_ARG, "more than 8 interpolation points");
   if (r <= 8 && mmax <= 4)
     k_ls_fit<T, 8, 4><<<ceil_div(L.n, 64), 64, 0, s>>>(L.n, r, L.cf, L.P.rp, L.P.ci, L.cpts, U, V,
-                                                      wv, wu, rule, Pv, Qtv);
+                                                      wv, wu, rule, average, Pv, Qtv);
   else
     k_ls_fit<T, kRMax, kMMax><<<ceil_div(L.n, 64), 64, 0, s>>>(L.n, r, L.cf, L.P.rp, L.P.ci, L.cpts,
-                                                              U, V, wv, wu, rule, Pv, Qtv);
+                                                              U, V, wv, wu, rule, average, Pv,
+                                                              Qtv);
   LAUNCHCHK();
 }
 
@@ -1863,8 +1870,8 @@ void row_inv_norms(const Csr &A, const T *val, T *out, hipStream_t s) {
   template void spgemm_numeric<T>(const Csr &, const T *, const Csr &, const T *, const Csr &, \
                                   T *, int *, hipStream_t);                                  \
   template void fill_transfer_identity<T>(const Level &, T *, T *, hipStream_t);             \
-  template void ls_fit<T>(const Level &, int, int, const T *, const T *, const double *,     \
-                          const double *, int, T *, T *, hipStream_t);                       \
+  template void ls_fit<T>(const Level &, int, int, const T *, const T *, const double *,      \
+                          const double *, int, int, T *, T *, hipStream_t);                  \
   template void dinv_from_diag<T>(const Level &, const T *, T *, int *, bool, hipStream_t);               \
   template void inject<T>(const int *, int, int, const T *, T *, hipStream_t);               \
   template void spmm<T>(const Csr &, const T *, int, const T *, T *, int, hipStream_t);      \

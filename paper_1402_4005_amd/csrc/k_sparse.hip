@@ -306,23 +306,23 @@ void kaczmarz_colour(const Csr &A, const T *val, const T *rowinv, const int *row
   LAUNCHCHK();
 }
 
-// x = Bdag b with Bdag dense FP64 row-major; one wave per row.
+// x = Bdag b (add: x += Bdag b) with Bdag dense FP64 row-major; one wave per row.
 template <class T>
 __global__ void __launch_bounds__(256) k_coarse_gemv(const double *__restrict__ Bd, int n,
-                                                     const T *__restrict__ b,
-                                                     T *__restrict__ x) {
+                                                     const T *__restrict__ b, T *__restrict__ x,
+                                                     int add) {
   const int row = blockIdx.x * 4 + threadIdx.x / kWave, lane = threadIdx.x % kWave;
   if (row >= n) return;
   double s = 0.0;
   const double *r = Bd + (size_t)row * n;
   for (int j = lane; j < n; j += kWave) s += r[j] * (double)b[j];
   s = group_sum(s, kWave);
-  if (lane == 0) x[row] = (T)s;
+  if (lane == 0) x[row] = add ? (T)((double)x[row] + s) : (T)s;
 }
 
 template <class T>
-void coarse_gemv(const double *bdag, int n, const T *b, T *x, hipStream_t s) {
-  k_coarse_gemv<T><<<ceil_div(n, 4), 256, 0, s>>>(bdag, n, b, x);
+void coarse_gemv(const double *bdag, int n, const T *b, T *x, hipStream_t s, int add) {
+  k_coarse_gemv<T><<<ceil_div(n, 4), 256, 0, s>>>(bdag, n, b, x, add);
   LAUNCHCHK();
 }
 
@@ -351,7 +351,7 @@ void dot_partials(const double *x, const double *y, int n, double *part, int nbl
                                      int, hipStream_t);                                      \
   template void kaczmarz_colour<T>(const Csr &, const T *, const T *, const int *, int,      \
                                    const T *, T *, hipStream_t);                             \
-  template void coarse_gemv<T>(const double *, int, const T *, T *, hipStream_t);
+  template void coarse_gemv<T>(const double *, int, const T *, T *, hipStream_t, int);
 INST(double)
 INST(float)
 #undef INST

@@ -158,29 +158,33 @@ struct Setup {
   float *lF = nullptr, *lY = nullptr;  // learned-row scratch
   size_t lcap = 0;
 
-  // Algorithm 1 (bamg_mle) from level l
+  // Algorithm 1 (bamg_mle) from level l: smoothing, then mu passes of the
+  // inner loop (fits, Galerkin products, injection, recursion,
+  // interpolation back, smoothing with the sigma right-hand sides)
   void mle(int l, int cycle) {
     if (l == h->L - 1) {
       coarsest(cycle == h->opt.setup_cycles);
       return;
     }
-    Level &L = h->lv[l];
-    relax(L, cycle > 1);
-    normalize(L);
-    weights(L);
-    ls_fit<T>(L, r, h->opt.max_interp, (const T *)L.U, (const T *)L.V, wv, wu,
-              h->opt.interp_rule, (T *)L.Pv, (T *)L.Qtv, s);
-    if (h->opt.learned != BAMG_LEARNED_OFF && cycle == 1) learned_rows(L);
-    galerkin(l);
-    Level &C = h->lv[l + 1];
-    inject<T>(L.cpts, C.n, r, (const T *)L.U, (T *)C.U, s);
-    inject<T>(L.cpts, C.n, r, (const T *)L.V, (T *)C.V, s);
-    mle(l + 1, cycle);
-    Level &L2 = h->lv[l];
-    Level &C2 = h->lv[l + 1];
-    spmm<T>(L2.P, (const T *)L2.Qtv, r, (const T *)C2.U, (T *)L2.U, 1, s);
-    spmm<T>(L2.P, (const T *)L2.Pv, r, (const T *)C2.V, (T *)L2.V, 0, s);
-    relax(L2, 1);
+    relax(h->lv[l], cycle > 1);
+    for (int pass = 0; pass < h->opt.mu; ++pass) {
+      Level &L = h->lv[l];
+      normalize(L);
+      weights(L);
+      ls_fit<T>(L, r, h->opt.max_interp, (const T *)L.U, (const T *)L.V, wv, wu,
+                h->opt.interp_rule, h->opt.restriction, (T *)L.Pv, (T *)L.Qtv, s);
+      if (h->opt.learned != BAMG_LEARNED_OFF && cycle == 1 && pass == 0) learned_rows(L);
+      galerkin(l);
+      Level &C = h->lv[l + 1];
+      inject<T>(L.cpts, C.n, r, (const T *)L.U, (T *)C.U, s);
+      inject<T>(L.cpts, C.n, r, (const T *)L.V, (T *)C.V, s);
+      mle(l + 1, cycle);
+      Level &L2 = h->lv[l];
+      Level &C2 = h->lv[l + 1];
+      spmm<T>(L2.P, (const T *)L2.Qtv, r, (const T *)C2.U, (T *)L2.U, 1, s);
+      spmm<T>(L2.P, (const T *)L2.Pv, r, (const T *)C2.V, (T *)L2.V, 0, s);
+      relax(L2, 1);
+    }
   }
 
   void alloc_dense(int n) {

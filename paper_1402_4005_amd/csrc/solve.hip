@@ -86,21 +86,40 @@ void smooth_steps(bamg_handle *h, Level &L, const T *b, T *x, int steps, bool fr
   }
 }
 
+// One cycle of shape `type` on level l for B_l x = b (Section 3): from
+// x = 0 when x_zero, else from the x passed in. Pre-smoothing, residual,
+// restriction by Q, the coarse correction (one cycle of the same shape on
+// level l + 1 from zero; a W-cycle a second one from the first's result, an
+// F-cycle a V-cycle from it), interpolation by P, post-smoothing. On the
+// coarsest level: x = B_L^+ b, or x + B_L^+ (b - B_L x) from a guess.
 template <class T>
-void vcycle_level(bamg_handle *h, int l, const T *b, T *x, hipStream_t s) {
+void cycle_level(bamg_handle *h, int l, int type, const T *b, T *x, bool x_zero,
+                 hipStream_t s) {
   Level &L = h->lv[l];
   if (l == h->L - 1) {
-    coarse_gemv<T>(h->bdag, L.n, b, x, s);
+    if (x_zero) {
+      coarse_gemv<T>(h->bdag, L.n, b, x, s);
+    } else {
+      spmv<T>(L.B, (const T *)L.Bv, x, (T *)L.rb, b, 1, 0, s);  // r = b - B x
+      coarse_gemv<T>(h->bdag, L.n, (const T *)L.rb, x, s, 1);   // x += B^+ r
+    }
     return;
   }
-  if (h->last_fused && vcycle_last_level<T>(h, l, b, x, s)) return;
+  if (x_zero && type == BAMG_CYCLE_V && h->last_fused && vcycle_last_level<T>(h, l, b, x, s))
+    return;
   Level &C = h->lv[l + 1];
   const int nu1 = h->opt.nu_pre, nu2 = h->opt.nu_post;
-  smooth_steps<T>(h, L, b, x, nu1, true, s);
+  const bool jac = h->opt.smoother != BAMG_SMOOTH_KACZMARZ;
+  if (!x_zero && jac && nu1 % 2 == 1)  // an odd count from a guess starts in the spare buffer
+    HIPCHK(hipMemcpyAsync(L.tb, x, sizeof(T) * L.n, hipMemcpyDeviceToDevice, s));
+  smooth_steps<T>(h, L, b, x, nu1, x_zero, s);
   spmv<T>(L.B, (const T *)L.Bv, x, (T *)L.rb, b, 1, L.lanes, s);          // r = b - B x
   spmv<T>(L.Pc, (const T *)L.Qv, (const T *)L.rb, (T *)C.bb, nullptr, 0, 0, s);  // b_c = Q r
-  vcycle_level<T>(h, l + 1, (const T *)C.bb, (T *)C.xb, s);
-  const bool jac = h->opt.smoother != BAMG_SMOOTH_KACZMARZ;
+  cycle_level<T>(h, l + 1, type, (const T *)C.bb, (T *)C.xb, true, s);
+  if (type == BAMG_CYCLE_W)
+    cycle_level<T>(h, l + 1, BAMG_CYCLE_W, (const T *)C.bb, (T *)C.xb, false, s);
+  else if (type == BAMG_CYCLE_F)
+    cycle_level<T>(h, l + 1, BAMG_CYCLE_V, (const T *)C.bb, (T *)C.xb, false, s);
   if (jac && nu2 % 2 == 1) {
     // spare = x + P x_c, then an odd number of sweeps ends in x
     k_spmv_add_into<T><<<ceil_div(L.n, 256), 256, 0, s>>>(L.n, L.P.rp, L.P.ci, (const T *)L.Pv,
@@ -116,7 +135,11 @@ void vcycle_level(bamg_handle *h, int l, const T *b, T *x, hipStream_t s) {
 
 template <class T>
 void vcycle_run(bamg_handle *h, const T *b, T *x, hipStream_t s) {
-  vcycle_level<T>(h, 0, b, x, s);
+  if (h->opt.cycle == BAMG_CYCLE_NONE) {
+    HIPCHK(hipMemcpyAsync(x, b, sizeof(T) * h->lv[0].n, hipMemcpyDeviceToDevice, s));
+    return;
+  }
+  cycle_level<T>(h, 0, h->opt.cycle, b, x, true, s);
 }
 template void vcycle_run<double>(bamg_handle *, const double *, double *, hipStream_t);
 template void vcycle_run<float>(bamg_handle *, const float *, float *, hipStream_t);

@@ -34,7 +34,7 @@ def rel_max(a, b):
 
 
 SOLVE_KEYS = ("nu_pre", "nu_post", "omega", "smoother", "precision", "fuse_last_level",
-              "use_graph", "seed")
+              "use_graph", "seed", "cycle")
 
 
 def import_oracle(ho, kw, **extra):
@@ -168,3 +168,53 @@ def test_import_rejects_bad_operators():
     with pytest.raises(bamg.BamgError):
         hg.csr(0, "M")
     assert np.array_equal(hg.csr(1, "B")[1], ho.csr(1, "B")[1])
+
+
+CYCLE_CASES = ["tandem65_c289", "delaunay20000_fused", "tandem65_nu21_fused", "delaunay1500_kaczmarz"]
+
+
+@pytest.mark.parametrize("kind", ["W", "F"])
+@pytest.mark.parametrize("name", CYCLE_CASES)
+def test_w_and_f_cycles_on_oracle_operators(name, kind):
+    """W- and F-cycles (Section 3's cycle shapes): one cycle from zero within
+    1e-12 of the oracle's; GMRES with that preconditioner to 1e-10 in the
+    oracle's iteration count, iterate within 1e-12."""
+    import torch
+    make, kw = next((m, k) for n, m, k in CASES if n == name)
+    ch, ho = oracle_for(name, make, kw)
+    code = {"W": 1, "F": 2}[kind]
+    hg = import_oracle(ho, kw, cycle=code)
+    b = np.random.default_rng(21).standard_normal(ch.n)
+    xo = ho.cycle(b, kind)
+    xg = hg.vcycle(torch.from_numpy(b).cuda()).cpu().numpy()
+    assert rel_max(xg, xo) < 1e-12, rel_max(xg, xo)
+    ko = oracle.options_for(ch, cycle=code, **kw)
+    hoc = oracle.Hierarchy(ch, ko)
+    xo2, io = hoc.gmres(m=20, tol=1e-10, maxit=400)
+    xg2, ig = hg.gmres(restart=20, tol=1e-10, maxit=400)
+    torch.cuda.synchronize()
+    assert io.converged and ig.converged
+    assert ig.iterations == io.iterations, (ig.iterations, io.iterations)
+    assert rel_l1(xg2.cpu().numpy(), xo2) < 1e-12
+
+
+def test_unpreconditioned_gmres_matches_oracle():
+    """GMRES(50) without preconditioner (C = I), the baseline rows of
+    Section 7: iteration count within 2 of the oracle's (modified against
+    classical Gram-Schmidt over ~150 iterations) and the iterate within
+    1e-8 (both stop at ||Bx||/||x|| < 1e-7 as in Section 7)."""
+    import torch
+    name = "tandem33_3lev"
+    make, kw = next((m, k) for n, m, k in CASES if n == name)
+    ch, ho = oracle_for(name, make, kw)
+    hg = import_oracle(ho, kw, cycle=3)
+    x0 = np.full(ch.n, 1.0 / ch.n)
+    xo, io = ho.gmres(m=50, tol=1e-7, maxit=2000, x0=x0, precondition=False)
+    xg, ig = hg.gmres(x=torch.from_numpy(x0).cuda(), restart=50, tol=1e-7, maxit=2000)
+    torch.cuda.synchronize()
+    assert io.converged and ig.converged
+    assert abs(ig.iterations - io.iterations) <= 2, (ig.iterations, io.iterations)
+    assert rel_l1(xg.cpu().numpy(), xo) < 1e-6
+    # C = I: one "cycle" is the identity
+    b = np.random.default_rng(22).standard_normal(ch.n)
+    assert np.array_equal(hg.vcycle(torch.from_numpy(b).cuda()).cpu().numpy(), b)
