@@ -1,0 +1,109 @@
+"""Reproduction harness of the paper's iteration-count tables (Section 7,
+Tables 1-4) on the GPU: for each chain size, GMRES iterations after one
+setup cycle (BAMG) and after two (BAMG^2), and of GMRES(50) without a
+preconditioner, all to the paper's stopping test ||Bx||/||x|| < 1e-7 with
+its standard parameters (3 + 3 weighted-Jacobi sweeps, omega = 0.7, r = 8;
+5 + 5 sweeps and c = 3 on the planar graphs), plus the grid and operator
+complexities of the hierarchy. Every step runs in the library's kernels.
+
+Command line (prints one JSON object per chain):
+    python -m paper_1402_4005_amd.tables [table ...] [--max-n N]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+# table -> (chain kind, sizes, options); sizes as printed in Section 7.
+# Table 4's chains are random walks on Delaunay triangulations of uniform
+# points (seeded here); Section 7 coarsens them by compatible relaxation,
+# for which greedy MIS coarsening stands in (coarsest level below 500).
+TABLES = {
+    "table1_birth_death": ("birth_death", [1025, 2049, 4097, 8193, 16385, 32769, 65537],
+                           dict(r=8, max_interp=2, coarse_max=29)),
+    "table2_uniform2d": ("grid2d", [33, 65, 97, 129, 161, 257],
+                         dict(r=8, max_interp=4, coarse_max=289)),
+    "table3_tandem": ("tandem", [33, 65, 97, 129, 161, 257],
+                      dict(r=8, max_interp=4, coarse_max=289)),
+    "table4_planar": ("delaunay", [1024, 4096, 8192, 16384, 32768, 65536],
+                      dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5,
+                           coarse_max=499)),
+}
+
+TOL = 1e-7          # Section 7 stopping test
+GMRES_RESTART = 50  # GMRES(50) of Section 7; also the restart of the preconditioned runs
+SEED = 14024006     # test vectors and planar points
+
+
+def make_chain(kind, size):
+    import chaingen
+    if kind == "birth_death":
+        return chaingen.birth_death(size, 0.96)
+    if kind == "grid2d":
+        return chaingen.grid2d(size, size)
+    if kind == "tandem":
+        return chaingen.tandem(size, 11 / 31, 10 / 31, 10 / 31)
+    return chaingen.delaunay_walk(size, SEED + size)
+
+
+def run_chain(kind, size, kw, maxit=3000, unpreconditioned=True):
+    """Counts of one chain: {'n', 'bamg', 'bamg2', 'gmres50', 'levels', 'oc',
+    'og', ...}. Each solve starts from the setup's x0 (the preconditioned
+    ones) or from the uniform vector (GMRES(50))."""
+    import torch
+    from . import BamgError, Hierarchy, options_for
+    ch = make_chain(kind, size)
+    out = {"n": ch.n}
+    for cycles, key in ((1, "bamg"), (2, "bamg2")):
+        t0 = time.perf_counter()
+        try:
+            h = Hierarchy.from_chain(ch, options_for(ch, setup_cycles=cycles, seed=SEED, **kw),
+                                     on_device=True)
+        except BamgError as e:
+            out[key] = None
+            out[key + "_error"] = str(e)
+            continue
+        out[key] = _iterations(h, out, key, maxit)
+        out[key + "_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+        if cycles == 1:
+            inf = h.info()
+            out.update(levels=inf["levels"], oc=round(inf["oc"], 3), og=round(inf["og"], 3))
+            if unpreconditioned:
+                h.set_cycle("none")
+                x0 = torch.full((ch.n,), 1.0 / ch.n, dtype=torch.float64, device="cuda")
+                out["gmres50"] = _iterations(h, out, "gmres50", maxit, x0)
+        h.close()
+    return out
+
+
+def _iterations(h, out, key, maxit, x0=None):
+    """GMRES iterations to TOL, or None (not converged, or an error, which
+    is kept in out[key + '_error'])."""
+    from . import BamgError
+    try:
+        _, info = h.gmres(x=x0, restart=GMRES_RESTART, tol=TOL, maxit=maxit)
+    except BamgError as e:
+        out[key + "_error"] = str(e)
+        return None
+    return info.iterations if info.converged else None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("tables", nargs="*", default=sorted(TABLES))
+    ap.add_argument("--max-n", type=int, default=10 ** 9, help="skip chains above this size")
+    ap.add_argument("--maxit", type=int, default=3000)
+    args = ap.parse_args()
+    for name in args.tables:
+        kind, sizes, kw = TABLES[name]
+        for size in sizes:
+            ch_n = size * size if kind in ("grid2d", "tandem") else size
+            if ch_n > args.max_n:
+                continue
+            row = run_chain(kind, size, kw, maxit=args.maxit)
+            print(json.dumps({"table": name, **row}), flush=True)
+
+
+if __name__ == "__main__":
+    main()
