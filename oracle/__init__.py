@@ -29,11 +29,13 @@ class OracleError(RuntimeError):
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA contraction)."""
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA contraction;
+    OpenMP over independent row loops only, so any thread count gives the
+    same bits)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-                               "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"])
+                               "-fno-fast-math", "-fopenmp", "-Wall", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -65,6 +67,7 @@ def lib():
                                    P(C.c_void_p)]
         _lib.orc_destroy.argtypes = [C.c_void_p]
         _lib.orc_num_levels.argtypes = [C.c_void_p]
+        _lib.orc_set_threads.argtypes = [C.c_int]
         for name in ("orc_level_dims", "orc_level_cf", "orc_level_vectors"):
             getattr(_lib, name).argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p][: 3 if name == "orc_level_dims" else 4]
         _lib.orc_level_csr.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -262,6 +265,12 @@ class Hierarchy:
         if st < 0:
             raise OracleError(st)
         return x, info
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's OpenMP row loops (same results for any count);
+    returns the previous count."""
+    return lib().orc_set_threads(n)
 
 
 def philox4x64(ctr, key):

@@ -35,6 +35,7 @@
  *   R-GM    GMRES: modified Gram-Schmidt, Givens rotations, true scaled
  *           residual ||Bx||/||x|| tested after every iteration
  */
+#include <omp.h>
 #include "bamg_oracle.h"
 
 #include <math.h>
@@ -177,7 +178,11 @@ static csr csr_matmul(const csr *X, const csr *Y, int force_diag) {
 }
 
 /* y = A x */
+/* Row loops below may run on several OpenMP threads (OMP_NUM_THREADS): each
+ * row is computed whole, in the order written, by one thread, so results
+ * are the same bits for any thread count. Reductions stay serial. */
 static void csr_spmv(const csr *A, const double *x, double *y) {
+#pragma omp parallel for schedule(static) if (A->nr > 8192)
   for (int i = 0; i < A->nr; ++i) {
     double s = 0.0;
     for (int k = A->rp[i]; k < A->rp[i + 1]; ++k) s += A->v[k] * x[A->ci[k]];
@@ -187,6 +192,7 @@ static void csr_spmv(const csr *A, const double *x, double *y) {
 
 /* Y = A X for X with r columns, row-major */
 static void csr_spmm(const csr *A, int r, const double *X, double *Y) {
+#pragma omp parallel for schedule(static) if (A->nr > 8192)
   for (int i = 0; i < A->nr; ++i)
     for (int k = 0; k < r; ++k) {
       double s = 0.0;
@@ -819,6 +825,7 @@ static void smooth_vec(const orc_ctx *c, const level *L, int transpose, const do
   }
   double *ax = NEW(double, n);
   csr_spmv(A, x, ax);
+#pragma omp parallel for schedule(static) if (n > 8192)
   for (int i = 0; i < n; ++i) x[i] += c->o.omega / L->d[i] * (b[i] - ax[i]);
   free(ax);
 }
@@ -1089,8 +1096,9 @@ static void fit_transfer(orc_ctx *c, level *L, int record) {
     wv[k] = minv / wv[k];
     wu[k] = k > 0 ? minu / wu[k] : 0.0;
   }
-  double G[64 * 16], g[64], p[16];
+#pragma omp parallel for schedule(dynamic, 256) if (n > 8192)
   for (int i = 0; i < n; ++i) {
+    double G[64 * 16], g[64], p[16];
     if (L->cf[i]) {
       L->P.v[L->P.rp[i]] = 1.0;
       L->Qt.v[L->Qt.rp[i]] = 1.0;
@@ -1432,6 +1440,12 @@ void orc_destroy(orc_ctx *c) {
 }
 
 int orc_num_levels(const orc_ctx *c) { return c->L; }
+
+int orc_set_threads(int n) {
+  const int old = omp_get_max_threads();
+  if (n >= 1) omp_set_num_threads(n);
+  return old;
+}
 
 int orc_level_dims(const orc_ctx *c, int l, int64_t d[6]) {
   if (l < 0 || l >= c->L) return ORC_E_ARG;

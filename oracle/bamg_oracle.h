@@ -78,6 +78,9 @@ int orc_setup(int64_t n, const int32_t *rp, const int32_t *ci, const double *a,
 void orc_destroy(orc_ctx *c);
 
 int orc_num_levels(const orc_ctx *c);
+/* Threads of the OpenMP row loops from now on (n >= 1; any count gives the
+ * same results); returns the previous count. */
+int orc_set_threads(int n);
 /* dims: [n, nc, nnzB, nnzM, nnzP, nnzQ(coarse rows, == nnzP)] */
 int orc_level_dims(const orc_ctx *c, int l, int64_t dims[6]);
 /* what: 0 = B_l, 1 = B_l^T, 2 = M_l, 3 = N_l, 4 = P_l (fine rows),

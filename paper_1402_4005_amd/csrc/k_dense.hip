@@ -215,7 +215,6 @@ void transpose_dense(const double *A, double *At, int n, hipStream_t s) {
 // to rotate; its tests are made on Gram matrices formed afresh from W. Only
 // the block rounds need a grid-wide barrier.
 constexpr int kSvdMaxSweeps = 80;
-constexpr int kSvdPref = 12;  // rows of J per thread fetched ahead (n <= 384 entirely)
 
 typedef double svd_d4 __attribute__((ext_vector_type(4)));
 
@@ -271,11 +270,20 @@ __device__ __forceinline__ bool svd_rotation(double al, double be, double ga, do
 template <class FA, class FB>
 __device__ __forceinline__ svd_d4 mfma_tile(int k0, int k1, FA a, FB b, svd_d4 acc) {
   const int l = threadIdx.x % kWave;
+#pragma unroll 4
   for (int kk = k0; kk < k1; ++kk) {
     const int k = 4 * kk + l / 16;
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a(l % 16, k), b(k, l % 16), acc, 0, 0, 0);
   }
   return acc;
+}
+
+// Make this wave's LDS writes visible to its other lanes before they read
+// (one wave only: no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // One round of the block one-sided Jacobi sweep `sweep`: workgroup pm treats
@@ -284,18 +292,22 @@ __device__ __forceinline__ svd_d4 mfma_tile(int k0, int k1, FA a, FB b, svd_d4 a
 // blocks rounded up to even (columns >= n are zero and never written).
 // ctrl[s] counts the rotations of sweep s; ctrl[kSvdMaxSweeps + 1] != 0 once
 // a sweep has found nothing to rotate, which turns the remaining launches
-// into no-ops. grid = nmat * nbp / 2; blockDim.x = 64 bs with bs = 8 or 16;
-// dynamic LDS = block_jacobi_lds().
-__global__ void __launch_bounds__(1024)
+// into no-ops. grid = nmat * nbp / 2; blockDim.x = 64 BS (BS = 8 or 16
+// columns per block); dynamic LDS = block_jacobi_lds(). NP rows of J per
+// thread are fetched into registers when the workgroup starts, so their
+// latency overlaps the load, Gram matrix and rotations of W (NP * 32 >= n
+// fetches J whole).
+template <int BS, int NP>
+__global__ void __launch_bounds__(64 * BS)
     k_block_jacobi_round(double *__restrict__ W, double *__restrict__ J, double *__restrict__ W2,
-                         double *__restrict__ J2, int n, int bs, int nbp,
-                         int *__restrict__ ctrl, int sweep, int round) {
+                         double *__restrict__ J2, int n, int nbp, int *__restrict__ ctrl,
+                         int sweep, int round) {
   if (ctrl[kSvdMaxSweeps + 1]) return;
+  constexpr int bs = BS, cols = 2 * BS, cc = cols * cols, nt = 64 * BS, nw = nt / kWave;
+  constexpr int ct = cols / 16;        // 16-column tiles per block pair
+  constexpr int nsl = nw / (ct * ct);  // K-slices of the Gram product
   extern __shared__ double lds[];
-  const int cols = 2 * bs, cc = cols * cols, nt = blockDim.x, nw = nt / kWave;
   const int wv = threadIdx.x / kWave, ln = threadIdx.x % kWave;
-  const int ct = cols / 16;        // 16-column tiles per block pair
-  const int nsl = nw / (ct * ct);  // K-slices of the Gram product
   double *Ws = lds;                // column c at Ws + c * n
   double *Ga = Ws + (size_t)cols * n, *Ra = Ga + cc;  // G and R, row-major cols x cols
   double *part = Ra + cc;                              // nw 16 x 16 partial tiles of G
@@ -311,11 +323,30 @@ __global__ void __launch_bounds__(1024)
   auto gcol = [&](int c) { return c < bs ? ba * bs + c : bb * bs + (c - bs); };
   // 32 threads per column (blockDim.x = 32 cols)
   const int lc = threadIdx.x / 32, li = threadIdx.x % 32, lg = gcol(lc);
+  const double *jsrc = Jm + (size_t)lg * n;
+  double jr[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    const int i = li + 32 * j;
+    jr[j] = lg < n && i < n ? jsrc[i] : 0.0;
+  }
   {
+    // W's columns in chunks of NP rows per thread, every load of a chunk in
+    // flight before its LDS stores (one memory latency per chunk; n <= 32 NP
+    // is a single chunk)
     double *dst = Ws + (size_t)lc * n;
     const double *src = Wm + (size_t)lg * n;
-#pragma unroll 4
-    for (int i = li; i < n; i += 32) dst[i] = lg < n ? src[i] : 0.0;
+    for (int i0 = li; i0 < n; i0 += 32 * NP) {
+      double w[NP];
+#pragma unroll
+      for (int j = 0; j < NP; ++j) {
+        const int i = i0 + 32 * j;
+        w[j] = lg < n && i < n ? src[i] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < NP; ++j)
+        if (i0 + 32 * j < n) dst[i0 + 32 * j] = w[j];
+    }
   }
   if (threadIdx.x == 0) {
     nrot = 0;
@@ -359,80 +390,119 @@ __global__ void __launch_bounds__(1024)
     }
   }
   __syncthreads();
-  // Inner rounds. Wave 0 finds the rotations (lane k: pair k); then
-  // thread (k1, k2) < (bs, bs) rewrites the 2 x 2 block of G at rows
-  // of pair k1 and columns of pair k2 to that of Jᵀ G J, and thread
-  // (r, k2) the two entries of row r of R at pair k2 to those of R J.
-  // The blocks are disjoint, so both updates are made in place.
+  // Inner rounds: the rotation of each of the bs pairs (lane k: pair k) from
+  // G; then the 2 x 2 block of G at rows of pair k1 and columns of pair k2
+  // becomes that of J^T G J, and the two entries of row r of R at pair k2
+  // those of R J. The blocks are disjoint, so both updates are in place.
   if (need) {
     const bool all0 = round == 0;
     const int ninner = all0 ? cols - 1 : bs;
-    for (int ir = 0; ir < ninner; ++ir) {
+    if constexpr (BS == 8) {
+      // 8-column blocks: one wave runs every inner round (64 block updates of
+      // G and 128 entries of R per round, the rotations passed by shuffles),
+      // so a round costs no workgroup barrier
       if (wv == 0) {
-        bool did = false;
-        if (ln < bs) {
-          int p, q;
-          svd_pair(ln, ir, bs, all0, p, q);
-          double c, sn;
-          did = svd_rotation(Ga[p * cols + p], Ga[q * cols + q], Ga[p * cols + q], c, sn);
-          rc[ln] = c;
-          rs[ln] = sn;
+        int count = 0;
+        for (int ir = 0; ir < ninner; ++ir) {
+          double c = 1.0, sn = 0.0;
+          bool did = false;
+          if (ln < bs) {
+            int p, q;
+            svd_pair(ln, ir, bs, all0, p, q);
+            did = svd_rotation(Ga[p * cols + p], Ga[q * cols + q], Ga[p * cols + q], c, sn);
+          }
+          count += __popcll(__ballot(did));
+          {
+            const int k1 = ln >> 3, k2 = ln & 7;
+            int p1, q1, p2, q2;
+            svd_pair(k1, ir, bs, all0, p1, q1);
+            svd_pair(k2, ir, bs, all0, p2, q2);
+            const double c1 = __shfl(c, k1), s1 = __shfl(sn, k1);
+            const double c2 = __shfl(c, k2), s2 = __shfl(sn, k2);
+            double *g1 = Ga + p1 * cols, *g2 = Ga + q1 * cols;
+            const double gpp = g1[p2], gpq = g1[q2], gqp = g2[p2], gqq = g2[q2];
+            const double hpp = c1 * gpp - s1 * gqp, hpq = c1 * gpq - s1 * gqq;
+            const double hqp = s1 * gpp + c1 * gqp, hqq = s1 * gpq + c1 * gqq;
+            g1[p2] = c2 * hpp - s2 * hpq;
+            g1[q2] = s2 * hpp + c2 * hpq;
+            g2[p2] = c2 * hqp - s2 * hqq;
+            g2[q2] = s2 * hqp + c2 * hqq;
+          }
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh) {
+            const int e2 = ln + 64 * hh, r = e2 >> 3, k2 = e2 & 7;
+            int p2, q2;
+            svd_pair(k2, ir, bs, all0, p2, q2);
+            const double c2 = __shfl(c, k2), s2 = __shfl(sn, k2);
+            double *rr = Ra + r * cols;
+            const double x = rr[p2], y = rr[q2];
+            rr[p2] = c2 * x - s2 * y;
+            rr[q2] = s2 * x + c2 * y;
+          }
+          wave_lds_sync();
         }
-        const unsigned long long m = __ballot(did);
-        if (ln == 0) nrot += __popcll(m);
+        if (ln == 0) nrot = count;
       }
       __syncthreads();
-      const int e = threadIdx.x;
-      if (e < bs * bs) {
-        const int k1 = e / bs, k2 = e % bs;
-        int p1, q1, p2, q2;
-        svd_pair(k1, ir, bs, all0, p1, q1);
-        svd_pair(k2, ir, bs, all0, p2, q2);
-        const double c1 = rc[k1], s1 = rs[k1], c2 = rc[k2], s2 = rs[k2];
-        double *g1 = Ga + p1 * cols, *g2 = Ga + q1 * cols;
-        const double gpp = g1[p2], gpq = g1[q2], gqp = g2[p2], gqq = g2[q2];
-        const double hpp = c1 * gpp - s1 * gqp, hpq = c1 * gpq - s1 * gqq;
-        const double hqp = s1 * gpp + c1 * gqp, hqq = s1 * gpq + c1 * gqq;
-        g1[p2] = c2 * hpp - s2 * hpq;
-        g1[q2] = s2 * hpp + c2 * hpq;
-        g2[p2] = c2 * hqp - s2 * hqq;
-        g2[q2] = s2 * hqp + c2 * hqq;
-      } else if (e < bs * bs + cols * bs) {
-        const int r = (e - bs * bs) / bs, k2 = (e - bs * bs) % bs;
-        int p2, q2;
-        svd_pair(k2, ir, bs, all0, p2, q2);
-        const double c2 = rc[k2], s2 = rs[k2];
-        double *rr = Ra + r * cols;
-        const double x = rr[p2], y = rr[q2];
-        rr[p2] = c2 * x - s2 * y;
-        rr[q2] = s2 * x + c2 * y;
+    } else {
+      for (int ir = 0; ir < ninner; ++ir) {
+        if (wv == 0) {
+          bool did = false;
+          if (ln < bs) {
+            int p, q;
+            svd_pair(ln, ir, bs, all0, p, q);
+            double c, sn;
+            did = svd_rotation(Ga[p * cols + p], Ga[q * cols + q], Ga[p * cols + q], c, sn);
+            rc[ln] = c;
+            rs[ln] = sn;
+          }
+          const unsigned long long m = __ballot(did);
+          if (ln == 0) nrot += __popcll(m);
+        }
+        __syncthreads();
+        const int e = threadIdx.x;
+        if (e < bs * bs) {
+          const int k1 = e / bs, k2 = e % bs;
+          int p1, q1, p2, q2;
+          svd_pair(k1, ir, bs, all0, p1, q1);
+          svd_pair(k2, ir, bs, all0, p2, q2);
+          const double c1 = rc[k1], s1 = rs[k1], c2 = rc[k2], s2 = rs[k2];
+          double *g1 = Ga + p1 * cols, *g2 = Ga + q1 * cols;
+          const double gpp = g1[p2], gpq = g1[q2], gqp = g2[p2], gqq = g2[q2];
+          const double hpp = c1 * gpp - s1 * gqp, hpq = c1 * gpq - s1 * gqq;
+          const double hqp = s1 * gpp + c1 * gqp, hqq = s1 * gpq + c1 * gqq;
+          g1[p2] = c2 * hpp - s2 * hpq;
+          g1[q2] = s2 * hpp + c2 * hpq;
+          g2[p2] = c2 * hqp - s2 * hqq;
+          g2[q2] = s2 * hqp + c2 * hqq;
+        } else if (e < bs * bs + cols * bs) {
+          const int r = (e - bs * bs) / bs, k2 = (e - bs * bs) % bs;
+          int p2, q2;
+          svd_pair(k2, ir, bs, all0, p2, q2);
+          const double c2 = rc[k2], s2 = rs[k2];
+          double *rr = Ra + r * cols;
+          const double x = rr[p2], y = rr[q2];
+          rr[p2] = c2 * x - s2 * y;
+          rr[q2] = s2 * x + c2 * y;
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
   }
   const double *R = Ra;
   if (nrot > 0) {
-    // X[:, pair] <- X[:, pair] R for X = W (from Ws), then X = J (loaded
-    // into Ws): output tiles of 16 rows x 16 columns, round-robin over
-    // the waves
-    // J's first kSvdPref * 32 rows are fetched into registers before
-    // the product with W, so their latency overlaps it
+    // X[:, pair] <- X[:, pair] R for X = W (from Ws), then X = J (from the
+    // registers fetched at the start, the rows past NP * 32 from memory):
+    // output tiles of 16 rows x 16 columns, round-robin over the waves
     const int rt = (n + 15) / 16;
-    const double *jsrc = Jm + (size_t)lg * n;
-    double jr[kSvdPref];
-#pragma unroll
-    for (int j = 0; j < kSvdPref; ++j) {
-      const int i = li + 32 * j;
-      jr[j] = lg < n && i < n ? jsrc[i] : 0.0;
-    }
     for (int pass = 0; pass < 2; ++pass) {
       double *__restrict__ Xm = pass == 0 ? Wm : Jm;
       if (pass == 1) {
         double *dst = Ws + (size_t)lc * n;
 #pragma unroll
-        for (int j = 0; j < kSvdPref; ++j)
+        for (int j = 0; j < NP; ++j)
           if (li + 32 * j < n) dst[li + 32 * j] = jr[j];
-        for (int i = li + 32 * kSvdPref; i < n; i += 32) dst[i] = lg < n ? jsrc[i] : 0.0;
+        for (int i = li + 32 * NP; i < n; i += 32) dst[i] = lg < n ? jsrc[i] : 0.0;
         __syncthreads();
       }
       for (int tl = wv; tl < rt * ct; tl += nw) {
@@ -521,8 +591,11 @@ int jacobi_svd2(Pool &pool, double *W, double *J, double *W2, double *J2, int n,
     k_identity_dense<<<ceil_div((long)n * n, 256), 256, 0, s>>>(J2, n);
     LAUNCHCHK();
   }
-  HIPCHK(hipFuncSetAttribute((const void *)k_block_jacobi_round,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+  // J fetched at the start: 12 rows per thread with 16-column blocks (n <=
+  // 384 whole), 36 with 8-column blocks (n <= 1152 whole)
+  const void *kern = bs == 16 ? (const void *)k_block_jacobi_round<16, 12>
+                              : (const void *)k_block_jacobi_round<8, 36>;
+  HIPCHK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
   const int grid = nmat * (nbp / 2);
   int *hp = pool.pinned();
   // about 12 sweeps converge a coarsest level of a few hundred states: the
@@ -532,8 +605,12 @@ int jacobi_svd2(Pool &pool, double *W, double *J, double *W2, double *J2, int n,
     const int upto = std::min(kSvdMaxSweeps, sweep == 0 ? 8 : sweep + 2);
     for (; sweep < upto; ++sweep) {
       for (int round = 0; round < nbp - 1; ++round) {
-        k_block_jacobi_round<<<grid, threads, shm, s>>>(W, J, W2, J2, n, bs, nbp, ctrl, sweep,
-                                                        round);
+        if (bs == 16)
+          k_block_jacobi_round<16, 12>
+              <<<grid, threads, shm, s>>>(W, J, W2, J2, n, nbp, ctrl, sweep, round);
+        else
+          k_block_jacobi_round<8, 36>
+              <<<grid, threads, shm, s>>>(W, J, W2, J2, n, nbp, ctrl, sweep, round);
         LAUNCHCHK();
       }
       k_block_jacobi_sweep_end<<<1, 64, 0, s>>>(ctrl, sweep);

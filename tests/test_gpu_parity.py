@@ -333,3 +333,45 @@ def test_reachability_search_both_forms(validate):
     x2, _ = h2.gmres(tol=1e-12, maxit=200)
     torch.cuda.synchronize()
     assert torch.equal(x1, x2)
+
+
+def test_coarse_level_1089_states():
+    """A 33 x 33 coarsest level (1089 states, as the 2049^2 tandem workload
+    uses): the Jacobi SVDs on 8-column blocks with the one-wave inner rounds
+    and J fetched whole at the start. The pseudo-inverse matches numpy's, the
+    generalized singular triplets satisfy B v = sigma M u, B^T u = sigma N v,
+    and the stationary vector matches a sparse direct null-space solve."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    import torch
+    ch = chaingen.tandem(129, 11 / 31, 10 / 31, 10 / 31)
+    hg = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, r=8, max_interp=4, coarse_max=1100,
+                                                        nu_setup=8))
+    L = hg.levels - 1
+    BL = hg.scipy(L, "B").toarray()
+    assert BL.shape == (1089, 1089)
+    ref = np.linalg.pinv(BL, rcond=1e-10)
+    assert rel_max(hg.coarse_pinv(), ref) < 1e-9
+    # the coarsest vectors are the r smallest generalized singular pairs
+    # (the setup's sigma is updated on the finer levels afterwards, so each
+    # pair's value is taken from its Rayleigh quotient, eq. singular_value)
+    U, V = hg.vectors(L)
+    M, N = hg.scipy(L, "M").toarray(), hg.scipy(L, "N").toarray()
+    scale = np.abs(BL).max()
+    for k in range(1, 8):
+        u, v = U[:, k], V[:, k]
+        sig = u @ BL @ v / np.sqrt((u @ M @ u) * (v @ N @ v))
+        nu, nv = np.sqrt(u @ M @ u), np.sqrt(v @ N @ v)
+        assert np.abs(BL @ v / nv - sig * (M @ u) / nu).max() < 1e-9 * scale, k
+        assert np.abs(BL.T @ u / nu - sig * (N @ v) / nv).max() < 1e-9 * scale, k
+    xg, ig = hg.gmres(restart=20, tol=1e-13, maxit=400)
+    torch.cuda.synchronize()
+    assert ig.converged
+    B = sp.csr_matrix(ch.to_scipy().shape) + sp.eye(ch.n) - ch.to_scipy()
+    Bm = B.tolil()
+    Bm[0, :] = np.ones(ch.n)
+    e0 = np.zeros(ch.n)
+    e0[0] = 1.0
+    xd = sla.spsolve(Bm.tocsc(), e0)
+    xd /= xd.sum()
+    assert rel_l1(xg.cpu().numpy(), xd) < 1e-10
