@@ -60,34 +60,39 @@ STATUS_RUNS = [("tandem1025_random", 1025, 14024003)] + \
     [("tandem2049_random", 2049, s) for s in range(14024101, 14024106)]
 
 
-# Sources of the dominant kernel (the finest-level Jacobi sweep). The HBM
+# Sources of the two profiled kernels: the finest-level Jacobi sweep of the
+# V-cycle and the round kernel of the coarsest-level Jacobi SVD. The HBM
 # traffic measured by hardware counters is kept in profiles/ together with
 # the digest of these files; after any change to them it no longer applies.
-KERNEL_SOURCES = ("paper_1402_4005_amd/csrc/k_sparse.hip",
-                  "paper_1402_4005_amd/csrc/device_common.h")
+KERNEL_SOURCES = {
+    "k_jacobi": ("paper_1402_4005_amd/csrc/k_sparse.hip", "paper_1402_4005_amd/csrc/device_common.h"),
+    "k_block_jacobi_round": ("paper_1402_4005_amd/csrc/k_dense.hip",
+                             "paper_1402_4005_amd/csrc/device_common.h"),
+}
 
 
-def kernel_digest():
+def kernel_digest(kernel="k_jacobi"):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, precision):
-    """HBM bytes per launch of the dominant kernel from the committed
+def measured_traffic(workload, precision, kernel="k_jacobi"):
+    """HBM bytes per launch of a profiled kernel from the committed
     FETCH_SIZE / WRITE_SIZE summary, or None if there is none for this
     workload or the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"k_jacobi_{workload}.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         for line in fh:
             if line.startswith("traffic-json: "):
                 d = json.loads(line[len("traffic-json: "):])
-                if d.get("source_digest") == kernel_digest() and d.get("precision") == precision:
+                if (d.get("source_digest") == kernel_digest(kernel)
+                        and d.get("precision") == precision):
                     return d
     return None
 
@@ -364,7 +369,8 @@ def main():
         return
 
     # kernel timing: the same K steps again with HIP events around every run of
-    # finest-level Jacobi sweeps (event recording bypasses the V-cycle graph)
+    # finest-level Jacobi sweeps (event recording bypasses the V-cycle graph),
+    # and K setups with events around the coarsest Jacobi SVD's round launches
     launches = 0
     kms = 0.0
     kbytes = 0.0
@@ -374,6 +380,14 @@ def main():
         kms += prof[1]
         kbytes += prof[2]
         hp.close()
+    svd = [0, 0.0, 0.0]
+    popts = options(args.precision)
+    popts.profile_setup = 1
+    for _ in range(args.steps):
+        hq = bamg.Hierarchy(rp, ci, va, ch.geom, popts, stream=stream)
+        for i, v in enumerate(hq.profile_end()):
+            svd[i] += v
+        hq.close()
 
     # untimed: accuracy and split of the last step, V-cycle bandwidth
     hinfo = last.info()
@@ -466,23 +480,30 @@ def main():
                 entry["error"] = str(e)
             status.append(entry)
 
-    traffic = measured_traffic(args.workload, args.precision)
-    lanes0 = hinfo_lanes
-    achieved = (kbytes / launches) / (kms / launches * 1e-3) / 1e9 if launches else None
-    roofline = {
-        "kernel": f"k_jacobi (finest-level weighted-Jacobi sweep, CSR, {lanes0} lanes/row)",
-        "bound": "hbm",
-        "achieved": round(achieved, 1) if achieved else None,
-        "peak": HBM_PEAK_GBPS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBPS, 4) if achieved else None,
-        "traffic": traffic["bytes_per_launch"] if traffic else None,
-        "traffic_vs_algorithmic": (round(traffic["bytes_per_launch"] / (kbytes / launches), 3)
-                                   if traffic and launches else None),
-        "launches": launches,
-        "avg_us": round(kms / launches * 1e3, 3) if launches else None,
-        "bytes_per_launch": kbytes / launches if launches else None,
-    }
+    def roofline_of(name, kernel, n_launch, ms_tot, bytes_tot):
+        if not n_launch:
+            return None
+        traffic = measured_traffic(args.workload, args.precision, kernel)
+        achieved = (bytes_tot / n_launch) / (ms_tot / n_launch * 1e-3) / 1e9
+        return {
+            "kernel": name, "bound": "hbm", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": traffic["bytes_per_launch"] if traffic else None,
+            "traffic_vs_algorithmic": (round(traffic["bytes_per_launch"] / (bytes_tot / n_launch),
+                                             3) if traffic else None),
+            "launches": n_launch, "avg_us": round(ms_tot / n_launch * 1e3, 3),
+            "bytes_per_launch": bytes_tot / n_launch,
+            "ms_per_step": round(ms_tot / args.steps, 3),
+        }
+
+    sweep_roof = roofline_of(f"k_jacobi (finest-level weighted-Jacobi sweep, CSR, {hinfo_lanes} "
+                             "lanes/row)", "k_jacobi", launches, kms, kbytes)
+    svd_roof = roofline_of("k_block_jacobi_round (coarsest-level block Jacobi SVD, one launch "
+                           "per round)", "k_block_jacobi_round", int(svd[0]), svd[1], svd[2])
+    # the roofline object covers whichever of the two takes more time per step
+    roofline = sweep_roof
+    if svd_roof and (not sweep_roof or svd_roof["ms_per_step"] > sweep_roof["ms_per_step"]):
+        roofline = svd_roof
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -517,6 +538,8 @@ def main():
         "mixed": mixed,
         "learned": learned_line,
         "roofline": roofline,
+        "roofline_finest_sweep": sweep_roof,
+        "roofline_coarsest_svd": svd_roof,
         "cpu_baseline": cpu,
         "random_rate_status": status,
         **extra,

@@ -118,6 +118,9 @@ typedef struct {
                            (1 = default) */
   int32_t restriction;  /* 0 = Q fitted with 1^T Q = 1^T (Section 5), 1 = simple
                            averaging: column i of Q has 1 / |J_i| on J_i */
+  int32_t profile_setup; /* 1 = time the round launches of the coarsest-level
+                           Jacobi SVD during bamg_setup with HIP events (read them
+                           with bamg_kernel_profile_end); 0 = off */
 } bamg_options;
 
 /* Cycle shapes. A W-cycle takes two cycles of its own shape on the next
@@ -294,12 +297,17 @@ bamg_status bamg_level_lanes(const bamg_handle *h, int32_t l, int32_t *lanes);
  * has captured the V-cycle into a graph (use_graph = 1). */
 bamg_status bamg_level_set_lanes(bamg_handle *h, int32_t l, int32_t lanes);
 
-/* Kernel timing with HIP events on the launch stream. kernel 0 = the
- * weighted-Jacobi sweep on the finest level (the V-cycle smoother that
- * starts from a nonzero iterate). After begin, every run of back-to-back
- * launches of that kernel on h is bracketed by two events; end synchronises
- * h's last stream and returns the number of launches, their summed duration
- * (ms) and their summed algorithmic bytes. */
+/* Kernel timing with HIP events on the launch stream. Kernel
+ * BAMG_PROFILE_FINEST_SWEEP: the weighted-Jacobi sweep on the finest level
+ * (the V-cycle smoother that starts from a nonzero iterate); after begin,
+ * every run of back-to-back launches of that kernel on h is bracketed by two
+ * events. Kernel BAMG_PROFILE_COARSEST_SVD: the round launches of the
+ * coarsest-level Jacobi SVD, recorded during bamg_setup when
+ * bamg_options.profile_setup = 1 (each group of sweeps bracketed; bytes:
+ * every W and J column block read, written where the block rotated). end
+ * synchronises h's last stream and returns the number of launches, their
+ * summed duration (ms) and their summed algorithmic bytes. */
+enum { BAMG_PROFILE_FINEST_SWEEP = 0, BAMG_PROFILE_COARSEST_SVD = 1 };
 bamg_status bamg_kernel_profile_begin(bamg_handle *h, int32_t kernel);
 bamg_status bamg_kernel_profile_end(bamg_handle *h, int64_t *launches, double *ms_total,
                                     double *bytes_total);

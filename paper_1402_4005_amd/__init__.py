@@ -64,7 +64,8 @@ class Options(C.Structure):
                 ("precision", C.c_int32), ("interp_rule", C.c_int32), ("validate", C.c_int32),
                 ("use_graph", C.c_int32), ("learned", C.c_int32), ("mlp", C.c_void_p),
                 ("autotune", C.c_int32), ("fuse_last_level", C.c_int32),
-                ("cycle", C.c_int32), ("mu", C.c_int32), ("restriction", C.c_int32)]
+                ("cycle", C.c_int32), ("mu", C.c_int32), ("restriction", C.c_int32),
+                ("profile_setup", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

@@ -119,6 +119,17 @@ void Pool::release_all() {
   chunk_left = 0;
 }
 
+// record one profiling event (start or stop of a bracketed run of launches)
+void profile_mark(bamg_handle *h, hipStream_t s, bool start) {
+  if (start && h->prof_used + 2 > h->prof_ev.size()) {
+    const size_t old = h->prof_ev.size(), grow = old ? old : 1024;
+    h->prof_ev.resize(old + grow);
+    for (size_t i = old; i < h->prof_ev.size(); ++i) HIPCHK(hipEventCreate(&h->prof_ev[i]));
+  }
+  HIPCHK(hipEventRecord(h->prof_ev[h->prof_used++], s));
+  h->prof_stream = s;
+}
+
 }  // namespace bamg
 
 // Wait for the validation work on the auxiliary stream and release it.
@@ -233,6 +244,7 @@ static bamg_status check_options(const bamg_options *o) {
   if (o->cycle < BAMG_CYCLE_V || o->cycle > BAMG_CYCLE_NONE) return BAMG_E_ARG;
   if (o->mu < 1 || o->mu > 8) return BAMG_E_ARG;
   if (o->restriction != 0 && o->restriction != 1) return BAMG_E_ARG;
+  if (o->profile_setup != 0 && o->profile_setup != 1) return BAMG_E_ARG;
   if (o->learned < BAMG_LEARNED_OFF || o->learned > BAMG_LEARNED_RECORD) return BAMG_E_ARG;
   if (o->learned == BAMG_LEARNED_USE && !o->mlp) return BAMG_E_ARG;
   return BAMG_OK;
@@ -257,6 +269,7 @@ bamg_status bamg_setup(const bamg_csr *A, const bamg_geometry *geom, const bamg_
   h->use_graph = opt->use_graph ? 1 : 0;
   h->last_fused = opt->fuse_last_level ? 1 : 0;
   h->pool.s = (hipStream_t)hip_stream;
+  if (opt->profile_setup) h->prof_kernel = BAMG_PROFILE_COARSEST_SVD;
   if (alloc) {
     h->pool.a = *alloc;
     h->pool.custom = true;
@@ -548,7 +561,7 @@ bamg_status bamg_level_set_lanes(bamg_handle *h, int32_t l, int32_t lanes) {
 }
 
 bamg_status bamg_kernel_profile_begin(bamg_handle *h, int32_t kernel) {
-  if (!h || kernel != 0) return BAMG_E_ARG;
+  if (!h || kernel != BAMG_PROFILE_FINEST_SWEEP) return BAMG_E_ARG;
   h->prof_kernel = kernel;
   h->prof_used = 0;
   h->prof_bytes = 0.0;

@@ -251,8 +251,11 @@ void trsm_lower_cols(const double *L, double *X, int n, int ncols, int ldx,
                      hipStream_t s);  // X <- L^-1 X, column by column
 void transpose_dense(const double *A, double *At, int n, hipStream_t s);
 int jacobi_svd(Pool &pool, double *W, double *J, int n, hipStream_t s);
-int jacobi_svd2(Pool &pool, double *W, double *J, double *W2, double *J2, int n,
-                hipStream_t s);  // both SVDs in the same launches (W2 nullable); W, J col-major
+// both SVDs in the same launches (W2 nullable); W, J col-major. prof: a
+// handle whose profiled kernel is the coarsest SVD (its round launches are
+// bracketed by events and their algorithmic bytes summed), else nullptr
+int jacobi_svd2(Pool &pool, double *W, double *J, double *W2, double *J2, int n, hipStream_t s,
+                bamg_handle *prof = nullptr);
 void column_norms(const double *W, int n, double *sv, hipStream_t s);
 void coarse_triplets_out(const double *LM, const double *LN, const double *W, const double *J,
                          const double *sv, int n, int r, void *U, void *V, int prec,
@@ -286,6 +289,9 @@ bool multi_axpy_dot(const double *Vb, int n, int k, const double *h, double *w, 
 void update_iterate(double *x0, const double *Vb, const double *y, int n, int k, hipStream_t s);
 void negate_copy(const double *in, double *out, int n, hipStream_t s);
 void normalize_sum(double *x, int n, double *part, int nblk, double *flags, hipStream_t s);
+
+// one event of a bracketed run of launches of the profiled kernel
+void profile_mark(bamg_handle *h, hipStream_t s, bool start);
 
 // host-side orchestration
 template <class T> void setup_all(bamg_handle *h, const bamg_csr *A, const bamg_geometry *g);

@@ -102,7 +102,18 @@ __global__ void __launch_bounds__(1024) k_cholesky(double *__restrict__ A0, doub
 
 // Factor A0 and (when not null) A1, both n x n; flag is a device int the
 // caller owns. Returns BAMG_E_COARSE if either is not positive definite.
+static void cholesky_blocked(double *A0, double *A1, int n, int *flag, hipStream_t s);
+
+// Above this order the factorisation runs blocked over many workgroups
+// (cholesky_blocked); one workgroup per matrix at or below it.
+constexpr int kCholOneWorkgroupMax = 384;
+
 int cholesky2(double *A0, double *A1, int n, int *flag, hipStream_t s) {
+  if (n > kCholOneWorkgroupMax) {
+    fill_i32(flag, 0, 1, s);
+    cholesky_blocked(A0, A1, n, flag, s);
+    return read_int(flag, s) ? BAMG_E_COARSE : BAMG_OK;
+  }
   int dev = 0, maxlds = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -270,7 +281,6 @@ __device__ __forceinline__ bool svd_rotation(double al, double be, double ga, do
 template <class FA, class FB>
 __device__ __forceinline__ svd_d4 mfma_tile(int k0, int k1, FA a, FB b, svd_d4 acc) {
   const int l = threadIdx.x % kWave;
-#pragma unroll 4
   for (int kk = k0; kk < k1; ++kk) {
     const int k = 4 * kk + l / 16;
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a(l % 16, k), b(k, l % 16), acc, 0, 0, 0);
@@ -284,6 +294,127 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------- blocked Cholesky
+// A = L L^T by kCb-column block steps, each three launches over both
+// matrices (A0 and A1 by grid index): the diagonal block factored in LDS by
+// the column algorithm; the block column below it solved against that
+// factor (a row per lane); the trailing lower triangle updated tile by tile,
+// C_IJ -= A_Ik A_Jk^T, on FP64 MFMA. Lower triangle row-major in place; the
+// strict upper triangle is zeroed; flag[0] |= 1 if a pivot is not positive.
+constexpr int kCb = 32;
+
+__global__ void __launch_bounds__(256) k_chol_diag(double *__restrict__ A0,
+                                                   double *__restrict__ A1, int n, int k0,
+                                                   int *__restrict__ flag) {
+  __shared__ double D[kCb][kCb + 1];
+  double *__restrict__ A = blockIdx.x == 0 ? A0 : A1;
+  const int b = min(kCb, n - k0), t = threadIdx.x;
+  for (int e = t; e < b * b; e += 256) D[e / b][e % b] = A[(size_t)(k0 + e / b) * n + k0 + e % b];
+  __syncthreads();
+  for (int c = 0; c < b; ++c) {
+    if (t == 0) {
+      double d = D[c][c];
+      if (!(d > 0.0)) {
+        atomicOr(flag, 1);
+        d = 1.0;
+      }
+      D[c][c] = sqrt(d);
+    }
+    __syncthreads();
+    const double inv = 1.0 / D[c][c];
+    for (int i = c + 1 + t; i < b; i += 256) D[i][c] *= inv;
+    __syncthreads();
+    const int w = b - c - 1;
+    for (int e = t; e < w * w; e += 256) {
+      const int i = c + 1 + e / w, j = c + 1 + e % w;
+      if (j <= i) D[i][j] -= D[i][c] * D[j][c];
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < b * b; e += 256) {
+    const int i = e / b, j = e % b;
+    A[(size_t)(k0 + i) * n + k0 + j] = j <= i ? D[i][j] : 0.0;
+  }
+}
+
+// rows below the diagonal block: x L_kk^T = a by forward substitution, one
+// row per lane; the mirrored strict-upper entries are zeroed
+__global__ void __launch_bounds__(64) k_chol_panel(double *__restrict__ A0,
+                                                   double *__restrict__ A1, int n, int k0) {
+  __shared__ double L[kCb][kCb + 1];
+  double *__restrict__ A = blockIdx.y == 0 ? A0 : A1;
+  const int b = min(kCb, n - k0), t = threadIdx.x;
+  for (int e = t; e < b * b; e += 64) L[e / b][e % b] = A[(size_t)(k0 + e / b) * n + k0 + e % b];
+  __syncthreads();
+  const int row = k0 + b + blockIdx.x * 64 + t;
+  if (row >= n) return;
+  double *__restrict__ ar = A + (size_t)row * n + k0;
+  double x[kCb];
+#pragma unroll
+  for (int j = 0; j < kCb; ++j) x[j] = j < b ? ar[j] : 0.0;
+#pragma unroll
+  for (int j = 0; j < kCb; ++j) {
+    if (j < b) {
+      double sum = x[j];
+#pragma unroll
+      for (int q = 0; q < j; ++q) sum -= x[q] * L[j][q];
+      x[j] = sum / L[j][j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kCb; ++j)
+    if (j < b) {
+      ar[j] = x[j];
+      A[(size_t)(k0 + j) * n + row] = 0.0;
+    }
+}
+
+// trailing tile (I, J), I >= J >= kb1 (tile index blockIdx.x in row order):
+// C_IJ -= A_Ik A_Jk^T over the kCb columns of block step k0; four waves, one
+// 16 x 16 quarter each; on a diagonal tile only the lower triangle
+__global__ void __launch_bounds__(256) k_chol_update(double *__restrict__ A0,
+                                                     double *__restrict__ A1, int n, int k0,
+                                                     int kb1) {
+  __shared__ double LA[kCb][kCb + 1], LB[kCb][kCb + 1];
+  double *__restrict__ A = blockIdx.y == 0 ? A0 : A1;
+  int I = 0;
+  const int tix = blockIdx.x;
+  while ((I + 1) * (I + 2) / 2 <= tix) ++I;
+  const int J = tix - I * (I + 1) / 2 + kb1;
+  I += kb1;
+  const int b = min(kCb, n - k0), r0 = I * kCb, c0 = J * kCb;
+  for (int e = threadIdx.x; e < kCb * kCb; e += 256) {
+    const int i = e / kCb, k = e % kCb;
+    LA[i][k] = r0 + i < n && k < b ? A[(size_t)(r0 + i) * n + k0 + k] : 0.0;
+    LB[i][k] = c0 + i < n && k < b ? A[(size_t)(c0 + i) * n + k0 + k] : 0.0;
+  }
+  __syncthreads();
+  const int wv = threadIdx.x / kWave, ln = threadIdx.x % kWave, si = wv >> 1, sj = wv & 1;
+  svd_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  acc = mfma_tile(
+      0, kCb / 4, [&](int i, int k) { return LA[16 * si + i][k]; },
+      [&](int k, int j) { return LB[16 * sj + j][k]; }, acc);
+  for (int r = 0; r < 4; ++r) {
+    const int i = r0 + 16 * si + ln / 16 + 4 * r, j = c0 + 16 * sj + ln % 16;
+    if (i < n && j <= i) A[(size_t)i * n + j] -= acc[r];
+  }
+}
+
+static void cholesky_blocked(double *A0, double *A1, int n, int *flag, hipStream_t s) {
+  const int nmat = A1 ? 2 : 1, nbk = ceil_div(n, kCb);
+  for (int kb = 0; kb < nbk; ++kb) {
+    const int k0 = kb * kCb, below = n - std::min(n, k0 + kCb);
+    k_chol_diag<<<nmat, 256, 0, s>>>(A0, A1, n, k0, flag);
+    LAUNCHCHK();
+    if (below <= 0) continue;
+    k_chol_panel<<<dim3(ceil_div(below, 64), nmat), 64, 0, s>>>(A0, A1, n, k0);
+    LAUNCHCHK();
+    const int m = nbk - kb - 1;
+    k_chol_update<<<dim3(m * (m + 1) / 2, nmat), 256, 0, s>>>(A0, A1, n, k0, kb + 1);
+    LAUNCHCHK();
+  }
 }
 
 // One round of the block one-sided Jacobi sweep `sweep`: workgroup pm treats
@@ -520,7 +651,10 @@ __global__ void __launch_bounds__(64 * BS)
       }
       __syncthreads();
     }
-    if (threadIdx.x == 0) atomicAdd(&ctrl[sweep], nrot);
+    if (threadIdx.x == 0) {
+      atomicAdd(&ctrl[sweep], nrot);
+      atomicAdd(&ctrl[kSvdMaxSweeps + 2], 1);  // blocks that rotated (written back)
+    }
   }
 }
 
@@ -536,7 +670,7 @@ __global__ void k_block_jacobi_sweep_end(int *__restrict__ ctrl, int sweep) {
 
 __global__ void k_block_jacobi_init(int *__restrict__ ctrl) {
   const int i = threadIdx.x;
-  if (i < kSvdMaxSweeps + 2) ctrl[i] = i == kSvdMaxSweeps ? kSvdMaxSweeps : 0;
+  if (i < kSvdMaxSweeps + 3) ctrl[i] = i == kSvdMaxSweeps ? kSvdMaxSweeps : 0;
 }
 
 __global__ void k_identity_dense(double *__restrict__ J, int n) {
@@ -563,7 +697,8 @@ int jacobi_svd(Pool &pool, double *W, double *J, int n, hipStream_t s) {
 // share the launches and stop after the first sweep in which neither
 // rotates. Sweeps are enqueued in groups and the convergence flag is read
 // back after each group; launches behind the converged sweep return at once.
-int jacobi_svd2(Pool &pool, double *W, double *J, double *W2, double *J2, int n, hipStream_t s) {
+int jacobi_svd2(Pool &pool, double *W, double *J, double *W2, double *J2, int n, hipStream_t s,
+                bamg_handle *prof) {
   int dev = 0, maxlds = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -581,7 +716,7 @@ int jacobi_svd2(Pool &pool, double *W, double *J, double *W2, double *J2, int n,
   const int nb = ceil_div(n, bs);
   int nbp = nb + (nb & 1);
   if (nbp < 2) nbp = 2;
-  int *ctrl = pool.get<int>(kSvdMaxSweeps + 2);
+  int *ctrl = pool.get<int>(kSvdMaxSweeps + 3);
   k_block_jacobi_init<<<1, 128, 0, s>>>(ctrl);
   LAUNCHCHK();
   const int nmat = W2 ? 2 : 1;
@@ -603,6 +738,7 @@ int jacobi_svd2(Pool &pool, double *W, double *J, double *W2, double *J2, int n,
   int sweep = 0, done = 0;
   while (!done && sweep < kSvdMaxSweeps) {
     const int upto = std::min(kSvdMaxSweeps, sweep == 0 ? 8 : sweep + 2);
+    if (prof) profile_mark(prof, s, true);
     for (; sweep < upto; ++sweep) {
       for (int round = 0; round < nbp - 1; ++round) {
         if (bs == 16)
@@ -616,11 +752,21 @@ int jacobi_svd2(Pool &pool, double *W, double *J, double *W2, double *J2, int n,
       k_block_jacobi_sweep_end<<<1, 64, 0, s>>>(ctrl, sweep);
       LAUNCHCHK();
     }
-    HIPCHK(hipMemcpyAsync(hp, ctrl + kSvdMaxSweeps, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    if (prof) profile_mark(prof, s, false);
+    HIPCHK(hipMemcpyAsync(hp, ctrl + kSvdMaxSweeps, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     done = hp[1];
   }
   const int sweeps = hp[0];
+  if (prof) {
+    // launches that did work: the sweeps up to the one that found nothing
+    // to rotate; each block reads its W and J columns, a rotating block
+    // writes both back
+    const double colbytes = 2.0 * bs * n * sizeof(double);
+    const long active = (long)std::min(sweeps + 1, sweep) * (nbp - 1);
+    prof->prof_launches += active;
+    prof->prof_bytes += (double)active * grid * 2.0 * colbytes + (double)hp[2] * 2.0 * colbytes;
+  }
   pool.release(ctrl);
   return done && sweeps < kSvdMaxSweeps ? BAMG_OK : BAMG_E_COARSE;
 }

@@ -236,7 +236,9 @@ struct Setup {
     trsm_lower_cols(Md, X, n, n, n, s);  // X = L_M^-1 B
     transpose_dense(X, W, n, s);
     trsm_lower_cols(Nd, W, n, n, n, s);  // W = L_N^-1 X^T, i.e. Bt column-major
-    if (jacobi_svd2(pool(), W, J, last ? W2 : nullptr, last ? J2 : nullptr, n, s) != BAMG_OK)
+    bamg_handle *prof = h->prof_kernel == BAMG_PROFILE_COARSEST_SVD ? h : nullptr;
+    if (jacobi_svd2(pool(), W, J, last ? W2 : nullptr, last ? J2 : nullptr, n, s, prof) !=
+        BAMG_OK)
       fail(BAMG_E_COARSE, "Jacobi SVD did not converge");
     column_norms(W, n, sv, s);
     coarse_triplets_out(Md, Nd, W, J, sv, n, r, C.U, C.V, h->prec, h->sigma, work, s);

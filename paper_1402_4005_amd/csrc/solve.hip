@@ -24,17 +24,6 @@ __global__ void k_spmv_add_into(int nr, const int *__restrict__ rp, const int *_
   y[i] = z[i] + s;
 }
 
-// record one profiling event (start or stop of a bracketed run of launches)
-void profile_mark(bamg_handle *h, hipStream_t s, bool start) {
-  if (start && h->prof_used + 2 > h->prof_ev.size()) {
-    const size_t old = h->prof_ev.size(), grow = old ? old : 1024;
-    h->prof_ev.resize(old + grow);
-    for (size_t i = old; i < h->prof_ev.size(); ++i) HIPCHK(hipEventCreate(&h->prof_ev[i]));
-  }
-  HIPCHK(hipEventRecord(h->prof_ev[h->prof_used++], s));
-  h->prof_stream = s;
-}
-
 template <class T>
 void smooth_steps(bamg_handle *h, Level &L, const T *b, T *x, int steps, bool from_zero,
                   hipStream_t s) {
@@ -72,7 +61,7 @@ void smooth_steps(bamg_handle *h, Level &L, const T *b, T *x, int steps, bool fr
     oth = x;
   }
   // profiled: one event pair around the run of back-to-back sweeps
-  const bool prof = h->prof_kernel == 0 && &L == &h->lv[0] && steps > 0;
+  const bool prof = h->prof_kernel == BAMG_PROFILE_FINEST_SWEEP && &L == &h->lv[0] && steps > 0;
   if (prof) profile_mark(h, s, true);
   for (int it = 0; it < steps; ++it) {
     jacobi<T>(L.B, (const T *)L.Bv, (const T *)L.dinv, om, b, cur, oth, L.lanes, s);
