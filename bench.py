@@ -421,6 +421,9 @@ def main():
         lopts = options(args.precision)
         lopts.learned = bamg.LEARNED_USE
         lopts.mlp = net.h.value
+        # iteration fallback: past plain BAMG's count plus two, the hierarchy
+        # is rebuilt with the exact fits and GMRES continues
+        lopts.learned_max_iters = max(i.iterations for i in infos) + 2
         lms, lh, lx, linfos = timed(lopts)
         lxs = lx.cpu().numpy()
         nm, nl = lh.learned_stats()
@@ -431,6 +434,8 @@ def main():
             "converged": [bool(i.converged) for i in linfos],
             "x_rel_l1_vs_fp64": float(np.abs(lxs - xs).sum() / np.abs(xs).sum()),
             "mlp_rows": nm, "ls_fallback_rows": nl,
+            "iteration_fallbacks": sum(i.mlp_fallback for i in linfos),
+            "fallback_after_iterations": lopts.learned_max_iters,
             "training": {"chains": [f"{k2}{s2}" for k2, s2, _ in LEARN_TRAIN[kind]],
                          "samples": int(LX.shape[0]), "epochs": 240,
                          "loss_first_last": [round(float(losses[0]), 5),
@@ -439,6 +444,20 @@ def main():
         }
         lh.close()
         net.close()
+
+    # BAMG^2 (two setup cycles, Section 7), whose second cycle the learned
+    # weights stand in for
+    bamg2 = None
+    if args.precision == "fp64" and not args.no_learned:
+        b2opts = options(args.precision)
+        b2opts.setup_cycles = 2
+        b2ms, b2h, _, b2infos = timed(b2opts)
+        b2h.close()
+        bamg2 = {"ms_per_step": round(b2ms, 3), "speedup_vs_fp64": round(ms_per_step / b2ms, 3),
+                 "iterations": [i.iterations for i in b2infos],
+                 "converged": [bool(i.converged) for i in b2infos]}
+        if learned_line:
+            learned_line["speedup_vs_bamg2"] = round(b2ms / learned_line["ms_per_step"], 3)
 
     # the mixed-precision form on the same workload: FP32 setup and V-cycles,
     # FP64 Krylov, residual, normalisation and coarsest solve
@@ -537,6 +556,7 @@ def main():
         "vcycle": vcycle,
         "mixed": mixed,
         "learned": learned_line,
+        "bamg2": bamg2,
         "roofline": roofline,
         "roofline_finest_sweep": sweep_roof,
         "roofline_coarsest_svd": svd_roof,

@@ -121,6 +121,10 @@ typedef struct {
   int32_t profile_setup; /* 1 = time the round launches of the coarsest-level
                            Jacobi SVD during bamg_setup with HIP events (read them
                            with bamg_kernel_profile_end); 0 = off */
+  int32_t learned_max_iters; /* BAMG_LEARNED_USE only: when GMRES has not converged
+                           after this many iterations, the hierarchy is rebuilt with
+                           the exact LS fits (same options, learned off) and GMRES
+                           continues from its iterate; 0 = never */
 } bamg_options;
 
 /* Cycle shapes. A W-cycle takes two cycles of its own shape on the next
@@ -155,6 +159,10 @@ typedef struct {
   double rel_residual;   /* final ||Bx||_2 / ||x||_2, FP64 */
   double x_min;          /* min_i x_i after scaling to 1^T x = 1 */
   double t_solve_ms;     /* host wall time of the call */
+  int32_t setup_cycles;  /* bootstrap cycles of the hierarchy used at the end */
+  int32_t mlp_fallback;  /* 1 if a learned hierarchy was replaced by the exact-LS one
+                            during this solve (bamg_options.learned_max_iters) */
+  double t_setup_ms;     /* host wall time of the setup(s) behind the final hierarchy */
 } bamg_solve_info;
 
 typedef struct bamg_handle bamg_handle;
@@ -211,7 +219,10 @@ bamg_status bamg_vcycle(bamg_handle *h, const void *b, void *x, int32_t dtype, v
  * after every iteration (Section 7). x: device, n FP64; on entry the
  * initial iterate if use_x0 != 0 (else the setup's x0 is used); on exit the
  * iterate scaled to 1^T x = 1. info (host, may be NULL) is filled after a
- * stream synchronisation. */
+ * stream synchronisation. For a learned hierarchy with learned_max_iters >
+ * 0 the iteration fallback may replace h's hierarchy by the exact-LS one
+ * (the handle stays valid; info->mlp_fallback says so; iterations count
+ * both parts). */
 bamg_status bamg_gmres_solve(bamg_handle *h, void *x, int32_t restart, double tol,
                              int32_t max_iters, int32_t use_x0, bamg_solve_info *info,
                              void *hip_stream);

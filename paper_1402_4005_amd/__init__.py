@@ -65,13 +65,14 @@ class Options(C.Structure):
                 ("use_graph", C.c_int32), ("learned", C.c_int32), ("mlp", C.c_void_p),
                 ("autotune", C.c_int32), ("fuse_last_level", C.c_int32),
                 ("cycle", C.c_int32), ("mu", C.c_int32), ("restriction", C.c_int32),
-                ("profile_setup", C.c_int32)]
+                ("profile_setup", C.c_int32), ("learned_max_iters", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
                 ("breakdowns", C.c_int32), ("rel_residual", C.c_double), ("x_min", C.c_double),
-                ("t_solve_ms", C.c_double)]
+                ("t_solve_ms", C.c_double), ("setup_cycles", C.c_int32),
+                ("mlp_fallback", C.c_int32), ("t_setup_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -1,5 +1,6 @@
 // C ABI of the library (include/bamg.h): argument checks, error translation
 // (no exception crosses the boundary), device memory ownership.
+#include <chrono>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -245,6 +246,7 @@ static bamg_status check_options(const bamg_options *o) {
   if (o->mu < 1 || o->mu > 8) return BAMG_E_ARG;
   if (o->restriction != 0 && o->restriction != 1) return BAMG_E_ARG;
   if (o->profile_setup != 0 && o->profile_setup != 1) return BAMG_E_ARG;
+  if (o->learned_max_iters < 0) return BAMG_E_ARG;
   if (o->learned < BAMG_LEARNED_OFF || o->learned > BAMG_LEARNED_RECORD) return BAMG_E_ARG;
   if (o->learned == BAMG_LEARNED_USE && !o->mlp) return BAMG_E_ARG;
   return BAMG_OK;
@@ -274,6 +276,7 @@ bamg_status bamg_setup(const bamg_csr *A, const bamg_geometry *geom, const bamg_
     h->pool.a = *alloc;
     h->pool.custom = true;
   }
+  const auto t0 = std::chrono::steady_clock::now();
   try {
     if (h->prec == 0)
       setup_all<double>(h, A, geom);
@@ -299,6 +302,8 @@ bamg_status bamg_setup(const bamg_csr *A, const bamg_geometry *geom, const bamg_
     g_last_error = "unexpected exception in setup";
     return BAMG_E_DEVICE;
   }
+  h->t_setup_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = h;
   return BAMG_OK;
 }
@@ -371,21 +376,93 @@ bamg_status bamg_vcycle(bamg_handle *h, const void *b, void *x, int32_t dtype, v
   BAMG_CATCH
 }
 
+namespace {
+
+__global__ void k_identity_minus(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                 const double *__restrict__ bv, double *__restrict__ av) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) av[k] = (ci[k] == i ? 1.0 : 0.0) - bv[k];
+}
+
+// The iteration fallback of the learned form: a hierarchy set up from the
+// same chain (A = I - B, B's pattern and FP64 values) with the same options
+// but exact LS fits replaces h's; the old one is freed.
+void rebuild_exact(bamg_handle *h, hipStream_t s) {
+  Level &L0 = h->lv[0];
+  const int n = L0.n, nnz = L0.B.nnz;
+  double *av = h->pool.get<double>(nnz);
+  k_identity_minus<<<ceil_div(n, 256), 256, 0, s>>>(n, L0.B.rp, L0.B.ci, h->B64, av);
+  LAUNCHCHK();
+  bamg_csr A{n, nnz, L0.B.rp, L0.B.ci, av, 1};
+  bamg_geometry g{L0.gkind, L0.nx, L0.gkind == BAMG_GEOM_GRID2D ? L0.ny : 0};
+  if (g.kind == BAMG_GEOM_LINE) g.nx = n;
+  bamg_options o = h->opt;
+  o.learned = BAMG_LEARNED_OFF;
+  o.mlp = nullptr;
+  o.validate = 0;  // the chain was validated by the first setup
+  o.profile_setup = 0;
+  bamg_handle *h2 = nullptr;
+  const bamg_status st = bamg_setup(&A, g.kind ? &g : nullptr, &o,
+                                    h->pool.custom ? &h->pool.a : nullptr, s, &h2);
+  if (st != BAMG_OK) fail(st, "rebuilding the hierarchy with exact LS fits failed");
+  h2->t_setup_ms += h->t_setup_ms;
+  std::swap(*h, *h2);
+  bamg_destroy(h2);  // the learned hierarchy (and B's arrays A borrowed)
+}
+
+}  // namespace
+
 bamg_status bamg_gmres_solve(bamg_handle *h, void *x, int32_t restart, double tol,
                              int32_t max_iters, int32_t use_x0, bamg_solve_info *info,
                              void *hip_stream) {
   if (!h || !x || restart < 1 || restart > 255 || max_iters < 0 || !(tol > 0.0)) return BAMG_E_ARG;
   BAMG_TRY
   hipStream_t s = (hipStream_t)hip_stream;
-  hipStream_t keep = h->pool.s;
-  h->pool.s = s;
-  try {
-    gmres_run(h, (double *)x, restart, tol, max_iters, use_x0, info, s);
-  } catch (...) {
+  bamg_solve_info local{};
+  bamg_solve_info *inf = info ? info : &local;
+  const bool fb = h->opt.learned == BAMG_LEARNED_USE && h->opt.learned_max_iters > 0 &&
+                  !h->imported && h->opt.learned_max_iters < max_iters;
+  const int first = fb ? h->opt.learned_max_iters : max_iters;
+  bool fell_back = false;
+  for (int part = 0; part < 2; ++part) {
+    hipStream_t keep = h->pool.s;
+    h->pool.s = s;
+    bool more = false;
+    bamg_solve_info cur{};
+    try {
+      gmres_run(h, (double *)x, restart, tol, part == 0 ? first : max_iters - first,
+                part == 0 ? use_x0 : 1, &cur, s);
+    } catch (const Error &e) {
+      h->pool.s = keep;
+      if (e.code != BAMG_NOT_CONVERGED || !fb || part == 1) {
+        if (part == 1) {  // report the whole solve with the status of its second part
+          cur.iterations += inf->iterations;
+          cur.restarts += inf->restarts;
+          cur.t_solve_ms += inf->t_solve_ms;
+        }
+        cur.setup_cycles = h->opt.setup_cycles;
+        cur.mlp_fallback = fell_back ? 1 : 0;
+        cur.t_setup_ms = h->t_setup_ms;
+        *inf = cur;
+        throw;
+      }
+      more = true;
+    }
     h->pool.s = keep;
-    throw;
+    if (part == 1) {
+      cur.iterations += inf->iterations;
+      cur.restarts += inf->restarts;
+      cur.t_solve_ms += inf->t_solve_ms;
+    }
+    *inf = cur;
+    if (!more) break;
+    rebuild_exact(h, s);
+    fell_back = true;
   }
-  h->pool.s = keep;
+  inf->setup_cycles = h->opt.setup_cycles;
+  inf->mlp_fallback = fell_back ? 1 : 0;
+  inf->t_setup_ms = h->t_setup_ms;
   return BAMG_OK;
   BAMG_CATCH
 }

@@ -127,6 +127,7 @@ struct bamg_handle {
   int use_graph = 1;
   int last_fused = 1;  // one-workgroup cycle on a small last level (option fuse_last_level)
   int imported = 0;    // hierarchy given by bamg_setup_from_levels (no setup data)
+  double t_setup_ms = 0.0;  // host wall time of the setup(s) behind this hierarchy
   // event timing of one kernel (bamg_kernel_profile_*)
   int prof_kernel = -1;
   std::vector<hipEvent_t> prof_ev;  // pairs (start, stop)

@@ -163,3 +163,33 @@ def test_learned_rows_follow_the_objective_rule():
     assert info.converged
     xs = x.cpu().numpy()
     assert np.abs(xs - xo).sum() / np.abs(xo).sum() < 1e-10
+
+
+def test_learned_iteration_fallback():
+    """The learned form's GMRES-iteration fallback: with learned_max_iters = 1
+    a learned hierarchy that has not converged after one iteration is
+    replaced by the exact-LS one (same options, learned off) and GMRES goes on
+    from its iterate. The solve converges, reports the fallback, counts both
+    parts, and ends at the plain BAMG solution (1e-10)."""
+    import torch
+    ch = chaingen.tandem(65, 11 / 31, 10 / 31, 10 / 31)
+    kw = dict(r=8, max_interp=4, coarse_max=300, nu_setup=8)
+    net = bamg.MLP(bamg.mlp_init_params(3))  # untrained: poor corrections
+    hl = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, learned="use", mlp=net,
+                                                        learned_max_iters=1, **kw))
+    xl, il = hl.gmres(restart=20, tol=1e-12, maxit=300)
+    hp = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, **kw))
+    xp, ip = hp.gmres(restart=20, tol=1e-12, maxit=300)
+    torch.cuda.synchronize()
+    assert il.converged and ip.converged
+    assert il.mlp_fallback == 1
+    assert il.iterations >= 2
+    assert il.t_setup_ms > 0
+    assert hl.learned_stats() == (0, 0)  # the hierarchy now is the exact-LS one
+    xl, xp = xl.cpu().numpy(), xp.cpu().numpy()
+    assert np.abs(xl - xp).sum() / np.abs(xp).sum() < 1e-10
+    # without the cap there is no fallback
+    hn = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, learned="use", mlp=net, **kw))
+    _, inn = hn.gmres(restart=20, tol=1e-12, maxit=300)
+    assert inn.mlp_fallback == 0
+    net.close()
