@@ -10,8 +10,8 @@
 // Kernels:
 //  * k_mlp_infer      inference on MFMA (v_mfma_f32_16x16x32_bf16): one wave
 //                     per 16 points, weights in LDS as BF16, FP32 accumulate;
-//  * k_mlp_point      FP32 forward and backward of one point per thread;
-//  * k_mlp_wgrad      weight gradients as fixed-order sums over the batch;
+//  * k_mlp_tile       FP32 forward and backward of 64 points on FP32 MFMA;
+//  * k_mlp_wgrad_mfma weight gradients as batch products on FP32 MFMA;
 //  * k_adam, k_mlp_bf16  the optimiser step and the BF16 weight copy;
 //  * k_mlp_features   the 96 inputs of each F point;
 //  * k_mlp_select     MLP row or exact LS row, by the objective test.
@@ -108,97 +108,206 @@ __global__ void __launch_bounds__(kInferWaves * kWave)
     }
 }
 
-// ------------------------------------------------------------ training
-// One point per thread: forward in FP32; with targets, the backward pass to
-// the hidden layers. Stores h1, h2 (post-ReLU), dh1, dh2 (pre-activation
-// gradients) and dy for the weight gradients, and the scaled point loss.
-constexpr int kPointThreads = 128;
+// ------------------------------------------------------------ training on MFMA
+// FP32 matrix-core products (v_mfma_f32_16x16x4f32: FP32 operands, FP32
+// accumulation) for the forward and backward passes and the weight
+// gradients. D (16 x 16) += A B over k in [0, K), K a multiple of 4: lane l
+// supplies A[l % 16][k + l / 16] and B[k + l / 16][l % 16] and holds
+// D[4 (l / 16) + r][l % 16] in acc[r].
+template <class FA, class FB>
+__device__ __forceinline__ f32x4 mfma32(int K, FA a, FB b, f32x4 acc, int k0 = 0, int kstep = 4) {
+  const int l = threadIdx.x % kWave;
+  for (int k = k0; k < K; k += kstep)
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a(l % 16, k + l / 16), b(k + l / 16, l % 16), acc,
+                                               0, 0, 0);
+  return acc;
+}
 
-__global__ void __launch_bounds__(kPointThreads)
-    k_mlp_point(const float *__restrict__ par, const float *__restrict__ X,
-                const float *__restrict__ T, const float *__restrict__ M, long npts, float scale,
-                float *__restrict__ H1, float *__restrict__ H2, float *__restrict__ D1,
-                float *__restrict__ D2, float *__restrict__ DY, float *__restrict__ Y,
-                double *__restrict__ ploss) {
-  __shared__ float w[kNPar];
-  for (int e = threadIdx.x; e < kNPar; e += blockDim.x) w[e] = par[e];
+// 64 points per workgroup (4 waves, wave w owns points 16 w .. 16 w + 15):
+// a1 = x W1^T + b1, a2 = relu(a1) W2^T + b2, y = relu(a2) W3^T + b3; with
+// targets dy = m (y - t) scale, d2 = (dy W3) [a2 > 0], d1 = (d2 W2) [a1 > 0].
+// Stores what k_mlp_wgrad_mfma needs (h1, h2 post-ReLU, d1, d2, dy) and the
+// scaled point losses. Dynamic LDS: mlp_tile_lds().
+constexpr int kTileP = 64, kXs = kIn + 1, kHs = kHid + 1, kYs = kOut + 1;
+static size_t mlp_tile_lds() {
+  return sizeof(float) * ((size_t)kNPar + kTileP * kXs + 3 * kTileP * kHs + kTileP * kYs);
+}
+
+__global__ void __launch_bounds__(256)
+    k_mlp_tile(const float *__restrict__ par, const float *__restrict__ X,
+               const float *__restrict__ T, const float *__restrict__ M, long npts, float scale,
+               float *__restrict__ H1, float *__restrict__ H2, float *__restrict__ D1,
+               float *__restrict__ D2, float *__restrict__ DY, float *__restrict__ Y,
+               double *__restrict__ ploss) {
+  extern __shared__ float sm[];
+  float *w = sm;                        // parameters, as in memory
+  float *xs = w + kNPar;                // 64 x 96 inputs
+  float *a1 = xs + kTileP * kXs;        // 64 x 64 pre-activations of layer 1
+  float *a2 = a1 + kTileP * kHs;        // layer 2
+  float *d2 = a2 + kTileP * kHs;        // 64 x 64 gradient of a2
+  float *yv = d2 + kTileP * kHs;        // 64 x 8 outputs, then dy
+  const long p0 = (long)blockIdx.x * kTileP;
+  const int t = threadIdx.x, wv = t / kWave, ln = t % kWave;
+  for (int e = t; e < kNPar; e += 256) w[e] = par[e];
+  for (int e = t; e < kTileP * kIn; e += 256) {
+    const int r = e / kIn, i = e % kIn;
+    xs[r * kXs + i] = p0 + r < npts ? X[(p0 + r) * kIn + i] : 0.f;
+  }
   __syncthreads();
-  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= npts) return;
-  float x[kIn], a1[kHid], a2[kHid], y[kOut];
-  for (int i = 0; i < kIn; ++i) x[i] = X[p * kIn + i];
-  for (int o = 0; o < kHid; ++o) {
-    float s = w[oB1 + o];
-    for (int i = 0; i < kIn; ++i) s += w[oW1 + o * kIn + i] * x[i];
-    a1[o] = s;
+  const int pr = 16 * wv;  // this wave's point rows
+  auto store = [&](float *dst, int ld, int cj, f32x4 acc, auto f) {
+    for (int r = 0; r < 4; ++r) {
+      const int row = pr + 4 * (ln / 16) + r, col = 16 * cj + ln % 16;
+      dst[row * ld + col] = f(acc[r], col);
+    }
+  };
+  // layer 1
+  for (int cj = 0; cj < kHid / 16; ++cj) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma32(kIn, [&](int i, int k) { return xs[(pr + i) * kXs + k]; },
+                 [&](int k, int j) { return w[oW1 + (16 * cj + j) * kIn + k]; }, acc);
+    store(a1, kHs, cj, acc, [&](float v, int c) { return v + w[oB1 + c]; });
   }
-  for (int o = 0; o < kHid; ++o) {
-    float s = w[oB2 + o];
-    for (int q = 0; q < kHid; ++q) s += w[oW2 + o * kHid + q] * fmaxf(a1[q], 0.f);
-    a2[o] = s;
+  __syncthreads();
+  // layer 2
+  for (int cj = 0; cj < kHid / 16; ++cj) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma32(kHid, [&](int i, int k) { return fmaxf(a1[(pr + i) * kHs + k], 0.f); },
+                 [&](int k, int j) { return w[oW2 + (16 * cj + j) * kHid + k]; }, acc);
+    store(a2, kHs, cj, acc, [&](float v, int c) { return v + w[oB2 + c]; });
   }
-  for (int t = 0; t < kOut; ++t) {
-    float s = w[oB3 + t];
-    for (int o = 0; o < kHid; ++o) s += w[oW3 + t * kHid + o] * fmaxf(a2[o], 0.f);
-    y[t] = s;
+  __syncthreads();
+  // output layer (columns 8..15 of the tile are zero)
+  {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma32(kHid, [&](int i, int k) { return fmaxf(a2[(pr + i) * kHs + k], 0.f); },
+                 [&](int k, int j) { return j < kOut ? w[oW3 + j * kHid + k] : 0.f; }, acc);
+    for (int r = 0; r < 4; ++r) {
+      const int row = pr + 4 * (ln / 16) + r, col = ln % 16;
+      if (col < kOut) yv[row * kYs + col] = acc[r] + w[oB3 + col];
+    }
   }
+  __syncthreads();
   if (Y)
-    for (int t = 0; t < kOut; ++t) Y[p * kOut + t] = y[t];
+    for (int e = t; e < kTileP * kOut; e += 256) {
+      const int r = e / kOut, c = e % kOut;
+      if (p0 + r < npts) Y[(p0 + r) * kOut + c] = yv[r * kYs + c];
+    }
   if (!T) return;
-  float dy[kOut];
-  double lp = 0.0;
-  for (int t = 0; t < kOut; ++t) {
-    const float m = M[p * kOut + t], d = y[t] - T[p * kOut + t];
-    dy[t] = m * d * scale;
-    lp += 0.5 * (double)m * (double)d * (double)d;
-    DY[p * kOut + t] = dy[t];
+  if (t < kTileP) {
+    const long p = p0 + t;
+    double lp = 0.0;
+    for (int c = 0; c < kOut; ++c) {
+      float dy = 0.f;
+      if (p < npts) {
+        const float m = M[p * kOut + c], d = yv[t * kYs + c] - T[p * kOut + c];
+        dy = m * d * scale;
+        lp += 0.5 * (double)m * (double)d * (double)d;
+        DY[p * kOut + c] = dy;
+      }
+      yv[t * kYs + c] = dy;
+    }
+    if (p < npts) ploss[p] = lp * (double)scale;
   }
-  ploss[p] = lp * (double)scale;
-  float d2[kHid];
-  for (int o = 0; o < kHid; ++o) {
-    float s = 0.f;
-    for (int t = 0; t < kOut; ++t) s += w[oW3 + t * kHid + o] * dy[t];
-    d2[o] = a2[o] > 0.f ? s : 0.f;
-    D2[p * kHid + o] = d2[o];
-    H2[p * kHid + o] = fmaxf(a2[o], 0.f);
+  __syncthreads();
+  // d2 = (dy W3) [a2 > 0]: K = 8
+  for (int cj = 0; cj < kHid / 16; ++cj) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma32(kOut, [&](int i, int k) { return yv[(pr + i) * kYs + k]; },
+                 [&](int k, int j) { return w[oW3 + k * kHid + 16 * cj + j]; }, acc);
+    for (int r = 0; r < 4; ++r) {
+      const int row = pr + 4 * (ln / 16) + r, col = 16 * cj + ln % 16;
+      const float av = a2[row * kHs + col], dv = av > 0.f ? acc[r] : 0.f;
+      d2[row * kHs + col] = dv;
+      if (p0 + row < npts) {
+        D2[(p0 + row) * kHid + col] = dv;
+        H2[(p0 + row) * kHid + col] = fmaxf(av, 0.f);
+      }
+    }
   }
-  for (int q = 0; q < kHid; ++q) {
-    float s = 0.f;
-    for (int o = 0; o < kHid; ++o) s += w[oW2 + o * kHid + q] * d2[o];
-    D1[p * kHid + q] = a1[q] > 0.f ? s : 0.f;
-    H1[p * kHid + q] = fmaxf(a1[q], 0.f);
+  __syncthreads();
+  // d1 = (d2 W2) [a1 > 0]
+  for (int cj = 0; cj < kHid / 16; ++cj) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma32(kHid, [&](int i, int k) { return d2[(pr + i) * kHs + k]; },
+                 [&](int k, int j) { return w[oW2 + k * kHid + 16 * cj + j]; }, acc);
+    for (int r = 0; r < 4; ++r) {
+      const int row = pr + 4 * (ln / 16) + r, col = 16 * cj + ln % 16;
+      const float av = a1[row * kHs + col];
+      if (p0 + row < npts) {
+        D1[(p0 + row) * kHid + col] = av > 0.f ? acc[r] : 0.f;
+        H1[(p0 + row) * kHid + col] = fmaxf(av, 0.f);
+      }
+    }
   }
 }
 
-// gradient entry e = sum over the batch, in point order
-__global__ void __launch_bounds__(256)
-    k_mlp_wgrad(const float *__restrict__ X, const float *__restrict__ H1,
-                const float *__restrict__ H2, const float *__restrict__ D1,
-                const float *__restrict__ D2, const float *__restrict__ DY, long npts,
-                float *__restrict__ G) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= kNPar) return;
-  float g = 0.f;
-  if (e < oB1) {
-    const int o = e / kIn, i = e % kIn;
-    for (long p = 0; p < npts; ++p) g += D1[p * kHid + o] * X[p * kIn + i];
-  } else if (e < oW2) {
-    const int o = e - oB1;
-    for (long p = 0; p < npts; ++p) g += D1[p * kHid + o];
-  } else if (e < oB2) {
-    const int o = (e - oW2) / kHid, q = (e - oW2) % kHid;
-    for (long p = 0; p < npts; ++p) g += D2[p * kHid + o] * H1[p * kHid + q];
-  } else if (e < oW3) {
-    const int o = e - oB2;
-    for (long p = 0; p < npts; ++p) g += D2[p * kHid + o];
-  } else if (e < oB3) {
-    const int t = (e - oW3) / kHid, o = (e - oW3) % kHid;
-    for (long p = 0; p < npts; ++p) g += DY[p * kOut + t] * H2[p * kHid + o];
+// Weight gradients as products over the batch, one workgroup per 16 x 16
+// tile of a gradient matrix; wave w takes the groups of four points 4 w,
+// 4 w + 16, ... and the four partial tiles are added in wave order, so the
+// result does not depend on timing:
+// G_W1 = D1^T X (24 tiles), G_W2 = D2^T H1 (16), G_W3 = DY^T H2 (4, rows 8..15
+// padding), and the bias gradients as products with a ones column (4 + 4 +
+// 1 tiles, column 0 kept).
+constexpr int kGradTiles = 24 + 16 + 4 + 9;
+
+constexpr int kGradWaves = 4;
+
+__global__ void __launch_bounds__(kGradWaves * kWave)
+    k_mlp_wgrad_mfma(const float *__restrict__ X, const float *__restrict__ H1,
+                     const float *__restrict__ H2, const float *__restrict__ D1,
+                     const float *__restrict__ D2, const float *__restrict__ DY, long npts,
+                     float *__restrict__ G) {
+  __shared__ f32x4 part[kGradWaves][kWave];
+  const int tile = blockIdx.x, wv = threadIdx.x / kWave, ln = threadIdx.x % kWave;
+  const int K = (int)((npts + 3) / 4) * 4, k0 = 4 * wv, ks = 4 * kGradWaves;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  auto pt = [&](int k) { return (long)k < npts; };
+  int kind, ti, tj;
+  if (tile < 24) {
+    kind = 0, ti = tile / 6, tj = tile % 6;
+    acc = mfma32(K, [&](int i, int k) { return pt(k) ? D1[(long)k * kHid + 16 * ti + i] : 0.f; },
+                 [&](int k, int j) { return pt(k) ? X[(long)k * kIn + 16 * tj + j] : 0.f; }, acc, k0, ks);
+  } else if (tile < 40) {
+    kind = 1, ti = (tile - 24) / 4, tj = (tile - 24) % 4;
+    acc = mfma32(K, [&](int i, int k) { return pt(k) ? D2[(long)k * kHid + 16 * ti + i] : 0.f; },
+                 [&](int k, int j) { return pt(k) ? H1[(long)k * kHid + 16 * tj + j] : 0.f; },
+                 acc, k0, ks);
+  } else if (tile < 44) {
+    kind = 2, ti = 0, tj = tile - 40;
+    acc = mfma32(
+        K, [&](int i, int k) { return pt(k) && i < kOut ? DY[(long)k * kOut + i] : 0.f; },
+        [&](int k, int j) { return pt(k) ? H2[(long)k * kHid + 16 * tj + j] : 0.f; }, acc, k0, ks);
   } else {
-    const int t = e - oB3;
-    for (long p = 0; p < npts; ++p) g += DY[p * kOut + t];
+    // bias tiles: 44..47 -> b1 rows, 48..51 -> b2 rows, 52 -> b3
+    kind = 3 + (tile - 44) / 4;
+    ti = (tile - 44) % 4;
+    tj = 0;
+    const float *Dm = tile < 48 ? D1 : tile < 52 ? D2 : DY;
+    const int ld = tile < 52 ? kHid : kOut, nr = tile < 52 ? 16 : kOut;
+    const int r0 = tile < 52 ? 16 * ti : 0;
+    acc = mfma32(K, [&](int i, int k) { return pt(k) && i < nr ? Dm[(long)k * ld + r0 + i] : 0.f; },
+                 [&](int k, int j) { return pt(k) && j == 0 ? 1.f : 0.f; }, acc, k0, ks);
   }
-  G[e] = g;
+  part[wv][ln] = acc;
+  __syncthreads();
+  if (wv != 0) return;
+  for (int q = 1; q < kGradWaves; ++q) acc += part[q][ln];
+  for (int r = 0; r < 4; ++r) {
+    const int i = 4 * (ln / 16) + r, j = ln % 16;
+    const float v = acc[r];
+    if (kind == 0)
+      G[oW1 + (16 * ti + i) * kIn + 16 * tj + j] = v;
+    else if (kind == 1)
+      G[oW2 + (16 * ti + i) * kHid + 16 * tj + j] = v;
+    else if (kind == 2) {
+      if (i < kOut) G[oW3 + i * kHid + 16 * tj + j] = v;
+    } else if (j == 0) {
+      if (kind == 3) G[oB1 + 16 * ti + i] = v;
+      else if (kind == 4) G[oB2 + 16 * ti + i] = v;
+      else if (i < kOut) G[oB3 + i] = v;
+    }
+  }
 }
 
 __global__ void k_adam(float *__restrict__ par, float *__restrict__ m, float *__restrict__ v,
@@ -356,6 +465,15 @@ void mlp_refresh_bf16(bamg_mlp *m, hipStream_t s) {
   LAUNCHCHK();
 }
 
+static void mlp_tile_attr() {
+  static const bool done = [] {
+    return hipFuncSetAttribute((const void *)k_mlp_tile,
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)mlp_tile_lds()) == hipSuccess;
+  }();
+  if (!done) fail(BAMG_E_DEVICE, "k_mlp_tile: dynamic LDS size not accepted");
+}
+
 void mlp_forward(const bamg_mlp *m, const float *X, long npts, float *Y, int mode, hipStream_t s) {
   if (npts <= 0) return;
   if (mode == 1) {
@@ -363,7 +481,8 @@ void mlp_forward(const bamg_mlp *m, const float *X, long npts, float *Y, int mod
     k_mlp_infer<<<ceil_div(waves, kInferWaves), kInferWaves * kWave, 0, s>>>(m->wb, m->p, X,
                                                                             npts, Y);
   } else {
-    k_mlp_point<<<ceil_div(npts, kPointThreads), kPointThreads, 0, s>>>(
+    mlp_tile_attr();
+    k_mlp_tile<<<ceil_div(npts, kTileP), 256, mlp_tile_lds(), s>>>(
         m->p, X, nullptr, nullptr, npts, 1.f, nullptr, nullptr, nullptr, nullptr, nullptr, Y,
         nullptr);
   }
@@ -400,10 +519,11 @@ static void mlp_scratch_free(MlpScratch &w) {
 static void mlp_batch_grad(const bamg_mlp *m, const float *X, const float *T, const float *M,
                            long npts, MlpScratch &w, hipStream_t s) {
   const float scale = 1.f / (float)npts;
-  k_mlp_point<<<ceil_div(npts, kPointThreads), kPointThreads, 0, s>>>(
+  mlp_tile_attr();
+  k_mlp_tile<<<ceil_div(npts, kTileP), 256, mlp_tile_lds(), s>>>(
       m->p, X, T, M, npts, scale, w.H1, w.H2, w.D1, w.D2, w.DY, nullptr, w.pl);
   LAUNCHCHK();
-  k_mlp_wgrad<<<ceil_div(kNPar, 256), 256, 0, s>>>(X, w.H1, w.H2, w.D1, w.D2, w.DY, npts, w.G);
+  k_mlp_wgrad_mfma<<<kGradTiles, kGradWaves * kWave, 0, s>>>(X, w.H1, w.H2, w.D1, w.D2, w.DY, npts, w.G);
   LAUNCHCHK();
   k_sum_double<<<1, 256, 0, s>>>(w.pl, npts, w.lsum);
   LAUNCHCHK();
