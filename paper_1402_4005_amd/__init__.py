@@ -131,6 +131,7 @@ def lib():
         L.bamg_setup_batched.argtypes = [C.c_int32, V, V, V, V, C.c_int32, V, P(V)]
         L.bamg_batch_status.argtypes = [V, C.c_int32, P(C.c_int32), P(V)]
         L.bamg_gmres_solve_batched.argtypes = [V, V, C.c_int32, C.c_double, C.c_int32, V, V, V]
+        L.bamg_batch_set_solver.argtypes = [V, C.c_int32]
         L.bamg_batch_destroy.argtypes = [V]
         L.bamg_batch_destroy.restype = None
         L.bamg_learned_stats.argtypes = [V, P(C.c_int64), P(C.c_int64)]
@@ -479,18 +480,22 @@ class Batch:
     """Many chains set up and solved together (bamg_setup_batched): chains
     is a list of chaingen.Chain, opts a list of Options (one per chain)."""
 
-    def __init__(self, chains, opts, nstreams=0, stream=None):
+    @staticmethod
+    def upload(chains):
+        """Device copies (row_ptr, col_idx, val) of the chains' matrices, to
+        pass as `arrays` when the inputs should already sit in device memory."""
         torch = _torch()
+        return [tuple(torch.from_numpy(a).cuda() for a in (ch.indptr, ch.indices, ch.data))
+                for ch in chains]
+
+    def __init__(self, chains, opts, nstreams=0, stream=None, arrays=None):
         self.n = len(chains)
-        self._keep = []
+        self._keep = arrays if arrays is not None else Batch.upload(chains)
         A = (Csr * self.n)()
         G = (Geometry * self.n)()
         O = (Options * self.n)()
         for i, (ch, o) in enumerate(zip(chains, opts)):
-            rp = torch.from_numpy(ch.indptr).cuda()
-            ci = torch.from_numpy(ch.indices).cuda()
-            va = torch.from_numpy(ch.data).cuda()
-            self._keep += [rp, ci, va]
+            rp, ci, va = self._keep[i]
             A[i] = Csr(ch.n, ch.nnz, rp.data_ptr(), ci.data_ptr(), va.data_ptr(), 1)
             G[i] = Geometry(*ch.geom)
             O[i] = o
@@ -505,6 +510,13 @@ class Batch:
         hh = C.c_void_p()
         _check(lib().bamg_batch_status(self.h, i, C.byref(st), C.byref(hh)))
         return st.value
+
+    SOLVERS = {"persistent": 0, "streams": 1}
+
+    def set_solver(self, solver):
+        """'persistent' (default: one launch, a workgroup per chain) or
+        'streams' (bamg_gmres_solve per chain on the library streams)."""
+        _check(lib().bamg_batch_set_solver(self.h, Batch.SOLVERS[solver]))
 
     def gmres(self, restart=20, tol=1e-10, maxit=500, stream=None):
         """Solve every chain; returns (list of x tensors or None, infos, statuses)."""

@@ -302,6 +302,18 @@ void import_all(bamg_handle *h, int nlev, const bamg_level_ops *ops, const doubl
 template <class T> void vcycle_run(bamg_handle *h, const T *b, T *x, hipStream_t s);
 void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_x0,
                bamg_solve_info *info, hipStream_t s);
+// partial-sum blocks of GMRES's reductions for n rows, and the Krylov
+// storage of restart length m (allocated when m changes)
+int gmres_blocks(int n);
+void gmres_buffers(bamg_handle *h, int m);
+
+// batched solve in one persistent launch (k_batch.hip): chains it can take,
+// and the solve of hs[i] into x[i] (order: chains largest first)
+constexpr int kBatchMaxRestart = 32;
+bool batch_persistent_eligible(const bamg_handle *h, int restart);
+void batch_persistent_solve(const std::vector<bamg_handle *> &hs, const std::vector<int> &order,
+                            double *const *x, int restart, double tol, int maxit,
+                            bamg_solve_info *infos, bamg_status *st, hipStream_t s);
 
 constexpr int kRedBlocks = 1024;  // partial-sum blocks of the reductions
 
@@ -323,6 +335,8 @@ inline int sweep_lanes_default(int nr, int nnz) {
 // launched)
 template <class T>
 bool vcycle_last_level(bamg_handle *h, int l, const T *b, T *x, hipStream_t s);
+template <class T>
+int last_level_lanes(const bamg_handle *h, int l);
 
 // lanes per CSR row for a level's sweeps, by timing (tune.hip)
 template <class T>

@@ -1,6 +1,10 @@
-// Many independent chains: setup and solve spread over a few library
+// Many independent chains. The setups are spread over a few library
 // streams, one host thread per stream, chains taken largest first from a
-// shared counter. Each chain's hierarchy is an ordinary handle.
+// shared counter; each chain's hierarchy is an ordinary handle. The solves
+// run in one persistent launch (k_batch.hip), chains the launch cannot take
+// (other cycle shapes, a learned iteration fallback, restart lengths above
+// its limit) and every chain when asked for, on the library streams as the
+// setups do.
 #include <algorithm>
 #include <atomic>
 #include <numeric>
@@ -16,6 +20,7 @@ struct bamg_batch {
   std::vector<bamg_status> st;
   std::vector<hipStream_t> streams;
   std::vector<int> order;  // chains by decreasing nonzeros
+  int solver = BAMG_BATCH_PERSISTENT;
 };
 
 namespace {
@@ -106,19 +111,50 @@ bamg_status bamg_gmres_solve_batched(bamg_batch *b, double *const *x, int32_t re
   if (!b || !x || !infos) return BAMG_E_ARG;
   for (int i = 0; i < b->n; ++i)
     if (b->h[i] && !x[i]) return BAMG_E_ARG;
+  if (restart < 1 || restart > 255 || max_iters < 0 || !(tol > 0.0)) return BAMG_E_ARG;
   std::vector<bamg_status> st(b->n, BAMG_E_ARG);
   hipStream_t caller = (hipStream_t)hip_stream;
-  try {
-    for (hipStream_t s : b->streams) join_into(caller, s);
-    for_each_chain(b, [&](int i, hipStream_t s) {
-      infos[i] = bamg_solve_info{};
-      if (!b->h[i]) {
-        st[i] = b->st[i];
-        return;
+  // the persistent launch's chains, largest first
+  std::vector<char> done(b->n, 0);
+  std::vector<bamg_handle *> ph;
+  std::vector<int> pidx;
+  std::vector<double *> px;
+  if (b->solver == BAMG_BATCH_PERSISTENT)
+    for (int k = 0; k < b->n; ++k) {
+      const int i = b->order[k];
+      if (b->h[i] && bamg::batch_persistent_eligible(b->h[i], restart)) {
+        pidx.push_back(i);
+        ph.push_back(b->h[i]);
+        px.push_back(x[i]);
+        done[i] = 1;
       }
-      st[i] = bamg_gmres_solve(b->h[i], x[i], restart, tol, max_iters, 0, &infos[i], s);
-    });
-    for (hipStream_t s : b->streams) join_into(s, caller);
+    }
+  try {
+    if (!ph.empty()) {
+      std::vector<int> ord(ph.size());
+      std::iota(ord.begin(), ord.end(), 0);
+      std::vector<bamg_solve_info> pinf(ph.size());
+      std::vector<bamg_status> pst(ph.size());
+      bamg::batch_persistent_solve(ph, ord, px.data(), restart, tol, max_iters, pinf.data(),
+                                   pst.data(), caller);
+      for (size_t k = 0; k < ph.size(); ++k) {
+        infos[pidx[k]] = pinf[k];
+        st[pidx[k]] = pst[k];
+      }
+    }
+    if ((int)ph.size() < b->n) {
+      for (hipStream_t s : b->streams) join_into(caller, s);
+      for_each_chain(b, [&](int i, hipStream_t s) {
+        if (done[i]) return;
+        infos[i] = bamg_solve_info{};
+        if (!b->h[i]) {
+          st[i] = b->st[i];
+          return;
+        }
+        st[i] = bamg_gmres_solve(b->h[i], x[i], restart, tol, max_iters, 0, &infos[i], s);
+      });
+      for (hipStream_t s : b->streams) join_into(s, caller);
+    }
   } catch (const bamg::Error &e) {
     return e.code;
   }
@@ -128,6 +164,12 @@ bamg_status bamg_gmres_solve_batched(bamg_batch *b, double *const *x, int32_t re
     all = all && st[i] == BAMG_OK;
   }
   return all ? BAMG_OK : BAMG_NOT_CONVERGED;
+}
+
+bamg_status bamg_batch_set_solver(bamg_batch *b, int32_t solver) {
+  if (!b || (solver != BAMG_BATCH_PERSISTENT && solver != BAMG_BATCH_STREAMS)) return BAMG_E_ARG;
+  b->solver = solver;
+  return BAMG_OK;
 }
 
 void bamg_batch_destroy(bamg_batch *b) {

@@ -7,6 +7,7 @@
 // on scheduling.
 #include "bamg_internal.h"
 #include "device_common.h"
+#include "givens.h"
 
 namespace bamg {
 
@@ -190,12 +191,13 @@ __global__ void __launch_bounds__(kKT)
   cset(j + 1, hn);
   const bool broke = !(hn > 1e-14 * w0);
   for (int i = 0; i < j; ++i) {
-    const double a = cget(i), b = cget(i + 1);
-    cset(i, cb[i] * a + sb[i] * b);
-    cset(i + 1, -sb[i] * a + cb[i] * b);
+    double a = cget(i), b = cget(i + 1);
+    givens_apply(cb[i], sb[i], a, b);
+    cset(i, a);
+    cset(i + 1, b);
   }
   const double a = cget(j), b = cget(j + 1);
-  const double den = sqrt(a * a + b * b);
+  const double den = givens_norm(a, b);
   const double cj = den > 0 ? a / den : 1.0, sj = den > 0 ? b / den : 0.0;
   cs[j] = cj;
   sn[j] = sj;

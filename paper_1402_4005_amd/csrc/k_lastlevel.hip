@@ -138,16 +138,17 @@ __global__ void __launch_bounds__(kLastThreads)
 
 }  // namespace
 
-// Launches the fused last level for level l (the one above the coarsest) if
-// it fits; returns false (nothing launched) otherwise.
+// Lanes per row of the fused last level for level l (the one above the
+// coarsest), or 0 when level l's V-cycle does not take that form.
 template <class T>
-bool vcycle_last_level(bamg_handle *h, int l, const T *b, T *x, hipStream_t s) {
-  if (l != h->L - 2 || l < 1 || h->opt.smoother != BAMG_SMOOTH_JACOBI) return false;
+int last_level_lanes(const bamg_handle *h, int l) {
+  if (!h->last_fused || l != h->L - 2 || l < 1 || h->opt.smoother != BAMG_SMOOTH_JACOBI)
+    return 0;
   const Level &L = h->lv[l], &C = h->lv[l + 1];
   // lanes per row: the largest power of two up to 16 with one pass over the rows
   int w = 16;
   while (w > 1 && (long)L.n * w > kLastThreads) w >>= 1;
-  if ((long)L.n * w > kLastThreads || C.n > kLastThreads) return false;
+  if ((long)L.n * w > kLastThreads || C.n > kLastThreads) return 0;
   static const int maxlds = [] {
     int dev = 0, v = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -156,7 +157,17 @@ bool vcycle_last_level(bamg_handle *h, int l, const T *b, T *x, hipStream_t s) {
     return v;
   }();
   const size_t shm = last_level_lds<T>(L.n, L.B.nnz, L.P.nnz, C.n, L.Pc.nnz);
-  if (shm + 64 > (size_t)maxlds) return false;
+  return shm + 64 > (size_t)maxlds ? 0 : w;
+}
+
+// Launches the fused last level for level l (the one above the coarsest) if
+// it fits; returns false (nothing launched) otherwise.
+template <class T>
+bool vcycle_last_level(bamg_handle *h, int l, const T *b, T *x, hipStream_t s) {
+  const int w = last_level_lanes<T>(h, l);
+  if (w == 0) return false;
+  const Level &L = h->lv[l], &C = h->lv[l + 1];
+  const size_t shm = last_level_lds<T>(L.n, L.B.nnz, L.P.nnz, C.n, L.Pc.nnz);
   LastLevel<T> a{};
   a.n = L.n;
   a.nnz = L.B.nnz;
@@ -185,6 +196,8 @@ bool vcycle_last_level(bamg_handle *h, int l, const T *b, T *x, hipStream_t s) {
   return true;
 }
 
+template int last_level_lanes<double>(const bamg_handle *, int);
+template int last_level_lanes<float>(const bamg_handle *, int);
 template bool vcycle_last_level<double>(bamg_handle *, int, const double *, double *,
                                         hipStream_t);
 template bool vcycle_last_level<float>(bamg_handle *, int, const float *, float *, hipStream_t);

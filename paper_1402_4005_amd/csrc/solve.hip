@@ -94,7 +94,7 @@ void cycle_level(bamg_handle *h, int l, int type, const T *b, T *x, bool x_zero,
     }
     return;
   }
-  if (x_zero && type == BAMG_CYCLE_V && h->last_fused && vcycle_last_level<T>(h, l, b, x, s))
+  if (x_zero && type == BAMG_CYCLE_V && vcycle_last_level<T>(h, l, b, x, s))
     return;
   Level &C = h->lv[l + 1];
   const int nu1 = h->opt.nu_pre, nu2 = h->opt.nu_post;
@@ -186,13 +186,12 @@ __global__ void k_krylov_start(const double *__restrict__ h1, double *__restrict
   flags[8] = beta;
 }
 
-void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_x0,
-               bamg_solve_info *info, hipStream_t s) {
-  const auto t0 = std::chrono::steady_clock::now();
+int gmres_blocks(int n) { return std::min(kRedBlocks, std::max(1, ceil_div(n, 256))); }
+
+void gmres_buffers(bamg_handle *h, int m) {
   Pool &pool = h->pool;
-  Level &L0 = h->lv[0];
-  const int n = L0.n;
-  const int nblk = std::min(kRedBlocks, std::max(1, ceil_div(n, 256)));
+  const int n = h->lv[0].n;
+  const int nblk = gmres_blocks(n);
   if (h->gm_m != m) {
     // (re)allocate Krylov storage; old buffers stay with the pool until destroy
     h->gV = pool.get<double>((size_t)(m + 1) * n);
@@ -222,6 +221,16 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
     }
     h->gm_m = m;
   }
+}
+
+void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_x0,
+               bamg_solve_info *info, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  Pool &pool = h->pool;
+  Level &L0 = h->lv[0];
+  const int n = L0.n;
+  const int nblk = gmres_blocks(n);
+  gmres_buffers(h, m);
   double *H = h->gH;
   double *cs = H + (size_t)(m + 1) * m, *sn = cs + (m + 2), *g = sn + (m + 2), *y = g + (m + 2);
   double *flags = y + (m + 2);  // 16 values
