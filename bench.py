@@ -158,6 +158,7 @@ def run_batch(args):
     def step():
         ta = time.perf_counter()
         b = bamg.Batch(chains, opts, nstreams=args.streams, arrays=arrays)
+        b.set_solver(args.batch_solver)
         torch.cuda.synchronize()
         tb = time.perf_counter()
         xs, infos, sts = b.gmres(restart=args.restart, tol=args.tol, maxit=args.maxit)
@@ -206,6 +207,7 @@ def run_batch(args):
         "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"batch{args.batch}", "chains": args.batch, "states": states,
                    "nnz_A": sum(c.nnz for c in chains), "streams": args.streams or 4,
+                   "solver": args.batch_solver,
                    "tol": args.tol, "restart": args.restart},
         "chains_per_s": round(args.batch / (ms * 1e-3), 1),
         "setup_ms": round(split[0] / args.steps, 1), "solve_ms": round(split[1] / args.steps, 1),
@@ -284,6 +286,9 @@ def main():
     ap.add_argument("--batch", type=int, default=512,
                     help="chains of the batched workload (--workload batch)")
     ap.add_argument("--streams", type=int, default=0, help="library streams of a batch")
+    ap.add_argument("--batch-solver", default="auto", choices=["auto", "persistent", "streams"],
+                    help="batched solve: small chains in one persistent launch and the others "
+                         "per chain on the streams (auto), all in the launch, or all on streams")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device-to-device copies of MIB MiB (the known "
                          "byte count that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")

@@ -348,22 +348,24 @@ bamg_status bamg_batch_status(const bamg_batch *b, int32_t i, bamg_status *setup
  * statuses nullable) receive each chain's result. Returns BAMG_OK if all
  * chains converged, BAMG_NOT_CONVERGED if any did not or failed.
  *
- * With the default solver (BAMG_BATCH_PERSISTENT) the chains run in one
- * persistent launch on the caller's stream: each workgroup takes the next
- * chain (largest first) and runs its GMRES(m) (Section 6) with V-cycle
- * preconditioning (Section 3) to the stopping test of Section 7 with
- * workgroup barriers only. Its arithmetic and summation orders are those
- * of bamg_gmres_solve on the same handle, so every chain's x, iteration
- * count and residual equal that call's bit for bit. It takes chains with a
- * V-cycle (or no preconditioner), restart <= 32 and no learned iteration
- * fallback; other chains, and all chains under BAMG_BATCH_STREAMS, are
- * solved by bamg_gmres_solve on the library streams. The call returns when
- * every result is written. infos[i].t_solve_ms is the chain's own time
- * inside the launch. */
+ * Chains run in one persistent launch on the caller's stream, or by
+ * bamg_gmres_solve on the library streams, both at once. In the launch each
+ * workgroup takes the next chain (largest first) and runs its GMRES(m)
+ * (Section 6) with V-cycle preconditioning (Section 3) to the stopping
+ * test of Section 7 with workgroup barriers only; its arithmetic and
+ * summation orders are those of bamg_gmres_solve on the same handle, so
+ * every chain's x, iteration count and residual equal that call's bit for
+ * bit, whichever way it ran. The launch takes chains with a V-cycle (or no
+ * preconditioner), restart <= 32 and no learned iteration fallback, and
+ * under the default BAMG_BATCH_AUTO only those of at most 4096 states
+ * (larger ones are faster per chain on the streams); BAMG_BATCH_PERSISTENT
+ * gives it every chain it can take, BAMG_BATCH_STREAMS none. The call
+ * returns when every result is written. infos[i].t_solve_ms is the chain's
+ * own time (inside the launch, or its call's). */
 bamg_status bamg_gmres_solve_batched(bamg_batch *b, double *const *x, int32_t restart,
                                      double tol, int32_t max_iters, bamg_solve_info *infos,
                                      bamg_status *statuses, void *hip_stream);
-enum { BAMG_BATCH_PERSISTENT = 0, BAMG_BATCH_STREAMS = 1 };
+enum { BAMG_BATCH_AUTO = 0, BAMG_BATCH_PERSISTENT = 1, BAMG_BATCH_STREAMS = 2 };
 /* Choose how bamg_gmres_solve_batched runs (BAMG_BATCH_*). BAMG_E_ARG for
  * an unknown value. */
 bamg_status bamg_batch_set_solver(bamg_batch *b, int32_t solver);

@@ -511,11 +511,13 @@ class Batch:
         _check(lib().bamg_batch_status(self.h, i, C.byref(st), C.byref(hh)))
         return st.value
 
-    SOLVERS = {"persistent": 0, "streams": 1}
+    SOLVERS = {"auto": 0, "persistent": 1, "streams": 2}
 
     def set_solver(self, solver):
-        """'persistent' (default: one launch, a workgroup per chain) or
-        'streams' (bamg_gmres_solve per chain on the library streams)."""
+        """'auto' (default: chains up to 4096 states in one persistent launch,
+        a workgroup per chain, the others per chain on the library streams,
+        both at once), 'persistent' (every chain the launch can take) or
+        'streams' (none)."""
         _check(lib().bamg_batch_set_solver(self.h, Batch.SOLVERS[solver]))
 
     def gmres(self, restart=20, tol=1e-10, maxit=500, stream=None):

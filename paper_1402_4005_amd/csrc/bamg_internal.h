@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -308,12 +309,15 @@ int gmres_blocks(int n);
 void gmres_buffers(bamg_handle *h, int m);
 
 // batched solve in one persistent launch (k_batch.hip): chains it can take,
-// and the solve of hs[i] into x[i] (order: chains largest first)
+// and the solve of hs[i] into x[i] (order: chains largest first); meanwhile
+// runs on the host after the launch is queued and before its results are
+// read back
 constexpr int kBatchMaxRestart = 32;
 bool batch_persistent_eligible(const bamg_handle *h, int restart);
 void batch_persistent_solve(const std::vector<bamg_handle *> &hs, const std::vector<int> &order,
                             double *const *x, int restart, double tol, int maxit,
-                            bamg_solve_info *infos, bamg_status *st, hipStream_t s);
+                            bamg_solve_info *infos, bamg_status *st, hipStream_t s,
+                            const std::function<void()> &meanwhile);
 
 constexpr int kRedBlocks = 1024;  // partial-sum blocks of the reductions
 

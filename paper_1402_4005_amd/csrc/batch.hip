@@ -1,10 +1,13 @@
 // Many independent chains. The setups are spread over a few library
 // streams, one host thread per stream, chains taken largest first from a
 // shared counter; each chain's hierarchy is an ordinary handle. The solves
-// run in one persistent launch (k_batch.hip), chains the launch cannot take
-// (other cycle shapes, a learned iteration fallback, restart lengths above
-// its limit) and every chain when asked for, on the library streams as the
-// setups do.
+// run in one persistent launch (k_batch.hip, a workgroup per chain) and on
+// the library streams (bamg_gmres_solve per chain) at the same time: by
+// default the launch takes the chains of at most kBatchAutoMaxStates
+// states, where one workgroup per chain beats a chain's launch-bound
+// per-step solve, and the streams the larger ones and every chain the
+// launch cannot take (other cycle shapes, a learned iteration fallback,
+// restart lengths above its limit).
 #include <algorithm>
 #include <atomic>
 #include <numeric>
@@ -13,6 +16,12 @@
 
 #include "bamg_internal.h"
 
+// Largest chain the default (automatic) split sends to the persistent
+// launch. Measured per GMRES iteration on the 512-chain batched workload
+// (mixed precision, MI355X): one workgroup per chain 0.26 ms below 2k
+// states and 0.71 ms at 2k-5k, the per-step solve 0.40 and 0.56 ms.
+constexpr int kBatchAutoMaxStates = 4096;
+
 struct bamg_batch {
   int n = 0;
   int dev = 0;
@@ -20,7 +29,7 @@ struct bamg_batch {
   std::vector<bamg_status> st;
   std::vector<hipStream_t> streams;
   std::vector<int> order;  // chains by decreasing nonzeros
-  int solver = BAMG_BATCH_PERSISTENT;
+  int solver = BAMG_BATCH_AUTO;
 };
 
 namespace {
@@ -119,10 +128,11 @@ bamg_status bamg_gmres_solve_batched(bamg_batch *b, double *const *x, int32_t re
   std::vector<bamg_handle *> ph;
   std::vector<int> pidx;
   std::vector<double *> px;
-  if (b->solver == BAMG_BATCH_PERSISTENT)
+  if (b->solver != BAMG_BATCH_STREAMS)
     for (int k = 0; k < b->n; ++k) {
       const int i = b->order[k];
-      if (b->h[i] && bamg::batch_persistent_eligible(b->h[i], restart)) {
+      if (b->h[i] && bamg::batch_persistent_eligible(b->h[i], restart) &&
+          (b->solver == BAMG_BATCH_PERSISTENT || b->h[i]->lv[0].n <= kBatchAutoMaxStates)) {
         pidx.push_back(i);
         ph.push_back(b->h[i]);
         px.push_back(x[i]);
@@ -130,20 +140,10 @@ bamg_status bamg_gmres_solve_batched(bamg_batch *b, double *const *x, int32_t re
       }
     }
   try {
-    if (!ph.empty()) {
-      std::vector<int> ord(ph.size());
-      std::iota(ord.begin(), ord.end(), 0);
-      std::vector<bamg_solve_info> pinf(ph.size());
-      std::vector<bamg_status> pst(ph.size());
-      bamg::batch_persistent_solve(ph, ord, px.data(), restart, tol, max_iters, pinf.data(),
-                                   pst.data(), caller);
-      for (size_t k = 0; k < ph.size(); ++k) {
-        infos[pidx[k]] = pinf[k];
-        st[pidx[k]] = pst[k];
-      }
-    }
-    if ((int)ph.size() < b->n) {
-      for (hipStream_t s : b->streams) join_into(caller, s);
+    // the streams start after what the caller queued, not after the launch
+    for (hipStream_t s : b->streams) join_into(caller, s);
+    auto per_chain = [&]() {
+      if ((int)ph.size() == b->n) return;
       for_each_chain(b, [&](int i, hipStream_t s) {
         if (done[i]) return;
         infos[i] = bamg_solve_info{};
@@ -153,8 +153,18 @@ bamg_status bamg_gmres_solve_batched(bamg_batch *b, double *const *x, int32_t re
         }
         st[i] = bamg_gmres_solve(b->h[i], x[i], restart, tol, max_iters, 0, &infos[i], s);
       });
-      for (hipStream_t s : b->streams) join_into(s, caller);
+    };
+    std::vector<int> ord(ph.size());
+    std::iota(ord.begin(), ord.end(), 0);
+    std::vector<bamg_solve_info> pinf(ph.size());
+    std::vector<bamg_status> pst(ph.size());
+    bamg::batch_persistent_solve(ph, ord, px.data(), restart, tol, max_iters, pinf.data(),
+                                 pst.data(), caller, per_chain);
+    for (size_t k = 0; k < ph.size(); ++k) {
+      infos[pidx[k]] = pinf[k];
+      st[pidx[k]] = pst[k];
     }
+    for (hipStream_t s : b->streams) join_into(s, caller);
   } catch (const bamg::Error &e) {
     return e.code;
   }
@@ -167,7 +177,7 @@ bamg_status bamg_gmres_solve_batched(bamg_batch *b, double *const *x, int32_t re
 }
 
 bamg_status bamg_batch_set_solver(bamg_batch *b, int32_t solver) {
-  if (!b || (solver != BAMG_BATCH_PERSISTENT && solver != BAMG_BATCH_STREAMS)) return BAMG_E_ARG;
+  if (!b || solver < BAMG_BATCH_AUTO || solver > BAMG_BATCH_STREAMS) return BAMG_E_ARG;
   b->solver = solver;
   return BAMG_OK;
 }

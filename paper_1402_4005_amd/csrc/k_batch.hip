@@ -22,6 +22,7 @@
 //    final sums follow the same pattern over the partials.
 #include <algorithm>
 #include <cstring>
+#include <functional>
 #include <vector>
 
 #include "bamg_internal.h"
@@ -752,9 +753,13 @@ bool batch_persistent_eligible(const bamg_handle *h, int restart) {
 
 void batch_persistent_solve(const std::vector<bamg_handle *> &hs, const std::vector<int> &order,
                             double *const *x, int restart, double tol, int maxit,
-                            bamg_solve_info *infos, bamg_status *st, hipStream_t s) {
+                            bamg_solve_info *infos, bamg_status *st, hipStream_t s,
+                            const std::function<void()> &meanwhile) {
   const int nc = (int)hs.size();
-  if (nc == 0) return;
+  if (nc == 0) {
+    if (meanwhile) meanwhile();
+    return;
+  }
   std::vector<BatchChain> ch(nc);
   std::vector<BatchLevel> lv;
   std::vector<size_t> lv_at(nc);
@@ -855,6 +860,7 @@ void batch_persistent_solve(const std::vector<bamg_handle *> &hs, const std::vec
                                                 (int *)(dev + off_ct),
                                                 (BatchResult *)(dev + off_rs));
   LAUNCHCHK();
+  if (meanwhile) meanwhile();  // host work while the launch runs
   std::vector<BatchResult> res(nc);
   HIPCHK(hipMemcpyAsync(res.data(), dev + off_rs, sizeof(BatchResult) * nc,
                         hipMemcpyDeviceToHost, s));

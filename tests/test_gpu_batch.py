@@ -113,9 +113,12 @@ def solve_batch(ms, solver, restart=20, tol=1e-12):
     return sorted(outs, key=lambda t: t[0])
 
 
-def test_persistent_solve_equals_per_chain_solve():
+@pytest.mark.parametrize("solver", ["persistent", "auto"])
+def test_persistent_solve_equals_per_chain_solve(solver):
+    """'persistent': every form in the launch; 'auto': the chains above 4096
+    states (Delaunay 5000) on the streams while the others run in the launch."""
     ms = forms()
-    per = solve_batch(ms, "persistent")
+    per = solve_batch(ms, solver)
     ref = solve_batch(ms, "streams")
     for (i, x, inf, st), (_, xr, infr, str_) in zip(per, ref):
         assert st == str_, (i, st, str_)
