@@ -47,7 +47,9 @@ class Options(C.Structure):
                 ("coarsening", C.c_int32), ("geom_kind", C.c_int32), ("nx", C.c_int32),
                 ("ny", C.c_int32), ("seed", C.c_uint64), ("smoother", C.c_int32),
                 ("interp_rule", C.c_int32), ("record_features", C.c_int32),
-                ("cycle", C.c_int32), ("mu", C.c_int32), ("restriction", C.c_int32)]
+                ("cycle", C.c_int32), ("mu", C.c_int32), ("restriction", C.c_int32),
+                ("cr_theta", C.c_double), ("cr_beta", C.c_double), ("cr_sweeps", C.c_int32),
+                ("cr_rounds", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -90,6 +92,9 @@ def lib():
         _lib.orc_gsvd.argtypes = [C.c_int] + [C.c_void_p] * 6
         _lib.orc_svd_jacobi.argtypes = [C.c_int] + [C.c_void_p] * 4
         _lib.orc_mis.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_uint64, C.c_int, C.c_void_p]
+        _lib.orc_cr.argtypes = [C.c_int] + [C.c_void_p] * 5 + [
+            C.c_uint64, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double,
+            C.c_void_p, C.c_void_p, C.c_void_p]
         _lib.orc_row_colouring.argtypes = [C.c_int] + [C.c_void_p] * 5
         _lib.orc_default_options.argtypes = [P(Options)]
         _lib.orc_harvest.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -106,7 +111,7 @@ def default_options(**kw) -> Options:
     lib().orc_default_options(C.byref(o))
     for k, v in kw.items():
         if k == "coarsening" and isinstance(v, str):
-            v = {"geom": 0, "mis": 1}[v]
+            v = {"geom": 0, "mis": 1, "cr": 2}[v]
         if k == "smoother" and isinstance(v, str):
             v = {"jacobi": 0, "kaczmarz": 1}[v]
         if k == "cycle" and isinstance(v, str):
@@ -369,6 +374,24 @@ def mis(indptr, indices, seed, level):
     lib().orc_mis(n, _p(np.ascontiguousarray(indptr, np.int32)),
                   _p(np.ascontiguousarray(indices, np.int32)), seed, level, _p(cf))
     return cf
+
+
+def cr(B, G, seed, level, theta=0.8, beta=0.7, sweeps=5, rounds=10, omega=0.7):
+    """Compatible-relaxation C/F split (R-CR) of the scipy CSR operator B on
+    the CSR pattern G (symmetrised, no diagonal): (cf, per-round rates)."""
+    n = B.shape[0]
+    cf = np.zeros(n, np.int32)
+    rates = np.zeros(max(rounds, 1), np.float64)
+    nr = C.c_int32()
+    st = lib().orc_cr(n, _p(np.ascontiguousarray(B.indptr, np.int32)),
+                      _p(np.ascontiguousarray(B.indices, np.int32)),
+                      _p(np.ascontiguousarray(B.data, np.float64)),
+                      _p(np.ascontiguousarray(G.indptr, np.int32)),
+                      _p(np.ascontiguousarray(G.indices, np.int32)), seed, level, theta, beta,
+                      sweeps, rounds, omega, _p(cf), _p(rates), C.byref(nr))
+    if st:
+        raise OracleError(st)
+    return cf, rates[:nr.value]
 
 
 def row_colouring(indptr, indices, cindptr, cindices):

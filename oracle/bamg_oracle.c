@@ -27,6 +27,19 @@
  *   R-MIS   algebraic C/F splitting = greedy maximal independent set of the
  *           symmetrised graph in decreasing pseudo-random priority (stand-in
  *           for compatible relaxation, whose algorithm the paper cites only)
+ *   R-CR    compatible-relaxation C/F splitting (the paper's algebraic
+ *           coarsening, algorithm cited only): rounds of weighted-Jacobi
+ *           F-relaxation on B_ff e_f = 0 from a fixed start (C entries 0); a
+ *           round whose last-sweep rate ||e^k|| / ||e^(k-1)|| is at most
+ *           theta ends the search; otherwise the F points with
+ *           |e_i| >= beta max |e| are candidates, and the greedy independent
+ *           set of the candidates' graph in decreasing (number of candidate
+ *           neighbours, priority) order joins C. Afterwards, F points with no
+ *           C neighbour take a greedy independent set of their own graph (so
+ *           every F point has a coarse neighbour for J_i). On levels below
+ *           the first the operator is the Galerkin product with the
+ *           averaging transfers of the structure pass (Section 5's simple
+ *           averaging); the bootstrap refits them afterwards.
  *   R-GAL   Galerkin patterns are structural products; no value dropping;
  *           the diagonal is always stored
  *   R-PINV  B_L^+ drops exactly the smallest singular value of B_L
@@ -542,6 +555,114 @@ int orc_mis(int n, const int32_t *rp, const int32_t *ci, uint64_t seed, int leve
   return ORC_OK;
 }
 
+/* Greedy independent set of the vertices with part[v] != 0, visited in
+ * decreasing (key, index) order: a vertex still undecided joins (cf = 1)
+ * and its undecided neighbours leave. Vertices with part[v] == 0 are not
+ * touched. */
+static void greedy_subset(int n, const int32_t *rp, const int32_t *ci, const uint64_t *key,
+                          const int32_t *part, int32_t *cf) {
+  int m = 0;
+  for (int i = 0; i < n; ++i) m += part[i] != 0;
+  prio *ord = NEW(prio, m);
+  int32_t *state = NEW(int32_t, n); /* 0 undecided, 1 taken, 2 out */
+  m = 0;
+  for (int i = 0; i < n; ++i)
+    if (part[i]) {
+      ord[m].key = key[i];
+      ord[m].i = i;
+      m++;
+    }
+  qsort(ord, m, sizeof(prio), cmp_prio_desc);
+  for (int t = 0; t < m; ++t) {
+    int v = ord[t].i;
+    if (state[v] != 0) continue;
+    state[v] = 1;
+    cf[v] = 1;
+    for (int k = rp[v]; k < rp[v + 1]; ++k)
+      if (part[ci[k]] && state[ci[k]] == 0) state[ci[k]] = 2;
+  }
+  free(ord);
+  free(state);
+}
+
+/* R-CR (see the file header). The start error of F point i is
+ * 0.5 + (priority >> 11) 2^-53, in [0.5, 1.5), exact in FP64; a sweep is
+ * e_i <- e_i - omega (sum_j b_ij e_j) / b_ii on F points, C entries 0. The
+ * candidates' ordering key is (number of candidate neighbours) * 2^48 +
+ * (priority >> 16), then the index. */
+int orc_cr(int n, const int32_t *brp, const int32_t *bci, const double *bv, const int32_t *grp,
+           const int32_t *gci, uint64_t seed, int level, double theta, double beta, int sweeps,
+           int rounds, double omega, int32_t *cf, double *rates, int32_t *nrounds) {
+  if (n < 1 || sweeps < 1 || rounds < 0) return ORC_E_ARG;
+  double *d = NEW(double, n), *e = NEW(double, n), *f = NEW(double, n), *e0 = NEW(double, n);
+  uint64_t *pr = NEW(uint64_t, n), *key = NEW(uint64_t, n);
+  int32_t *part = NEW(int32_t, n);
+  for (int i = 0; i < n; ++i) {
+    cf[i] = 0;
+    for (int k = brp[i]; k < brp[i + 1]; ++k)
+      if (bci[k] == i) d[i] = bv[k];
+    if (!(d[i] != 0.0)) {
+      free(d), free(e), free(f), free(e0), free(pr), free(key), free(part);
+      return ORC_E_BAD_DIAG;
+    }
+    pr[i] = priority_word(seed, 2, level, i);
+    e0[i] = 0.5 + (double)(pr[i] >> 11) * 0x1p-53;
+  }
+  int done = 0;
+  for (int round = 0; round < rounds; ++round) {
+    for (int i = 0; i < n; ++i) e[i] = cf[i] ? 0.0 : e0[i];
+    double prev2 = 0.0, now2 = 0.0;
+    for (int sw = 0; sw < sweeps; ++sw) {
+      for (int i = 0; i < n; ++i) {
+        if (cf[i]) {
+          f[i] = 0.0;
+          continue;
+        }
+        double acc = 0.0;
+        for (int k = brp[i]; k < brp[i + 1]; ++k) acc += bv[k] * e[bci[k]];
+        f[i] = e[i] - omega * (acc / d[i]);
+      }
+      if (sw == sweeps - 1) {
+        prev2 = now2 = 0.0;
+        for (int i = 0; i < n; ++i) {
+          prev2 += e[i] * e[i];
+          now2 += f[i] * f[i];
+        }
+      }
+      double *t = e;
+      e = f;
+      f = t;
+    }
+    const double rate = prev2 > 0.0 ? sqrt(now2) / sqrt(prev2) : 0.0;
+    if (rates) rates[round] = rate;
+    done = round + 1;
+    if (rate <= theta) break;
+    double emax = 0.0;
+    for (int i = 0; i < n; ++i)
+      if (!cf[i]) emax = fmax(emax, fabs(e[i]));
+    for (int i = 0; i < n; ++i) part[i] = !cf[i] && fabs(e[i]) >= beta * emax;
+    for (int i = 0; i < n; ++i) {
+      if (!part[i]) continue;
+      uint64_t w = 0;
+      for (int k = grp[i]; k < grp[i + 1]; ++k) w += part[gci[k]] != 0;
+      key[i] = (w << 48) + (pr[i] >> 16);
+    }
+    greedy_subset(n, grp, gci, key, part, cf);
+  }
+  /* every F point gets a coarse neighbour */
+  for (int i = 0; i < n; ++i) {
+    part[i] = 0;
+    if (cf[i]) continue;
+    int has = 0;
+    for (int k = grp[i]; k < grp[i + 1]; ++k) has |= cf[gci[k]] == 1;
+    part[i] = !has;
+  }
+  greedy_subset(n, grp, gci, pr, part, cf);
+  if (nrounds) *nrounds = done;
+  free(d), free(e), free(f), free(e0), free(pr), free(key), free(part);
+  return ORC_OK;
+}
+
 /* Greedy distance-2 colouring of the rows of a matrix in decreasing
  * pseudo-random priority: rows that share a column get different colours,
  * each row takes the smallest colour not used by earlier rows it conflicts
@@ -617,6 +738,10 @@ void orc_default_options(orc_options *o) {
   o->cycle = ORC_CYCLE_V;
   o->mu = 1;
   o->restriction = 0;
+  o->cr_theta = 0.8;
+  o->cr_beta = 0.7;
+  o->cr_sweeps = 5;
+  o->cr_rounds = 10;
 }
 
 /* symmetrised pattern of B without the diagonal (for MIS and J_i) */
@@ -664,6 +789,9 @@ static void coarsen(orc_ctx *c, int l) {
     }
   } else if (c->o.coarsening == ORC_COARSEN_GEOM && L->gkind == 1) {
     for (int s = 0; s < n; ++s) L->cf[s] = (s % 2 == 0);
+  } else if (c->o.coarsening == ORC_COARSEN_CR) {
+    orc_cr(n, L->B.rp, L->B.ci, L->B.v, L->G.rp, L->G.ci, c->o.seed, l, c->o.cr_theta,
+           c->o.cr_beta, c->o.cr_sweeps, c->o.cr_rounds, c->o.omega, L->cf, NULL, NULL);
   } else {
     orc_mis(n, L->G.rp, L->G.ci, c->o.seed, l, L->cf);
   }

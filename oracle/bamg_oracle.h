@@ -37,7 +37,7 @@ enum {
   ORC_E_NOMEM = -9
 };
 
-enum { ORC_COARSEN_GEOM = 0, ORC_COARSEN_MIS = 1 };
+enum { ORC_COARSEN_GEOM = 0, ORC_COARSEN_MIS = 1, ORC_COARSEN_CR = 2 };
 enum { ORC_SMOOTH_JACOBI = 0, ORC_SMOOTH_KACZMARZ = 1 };
 
 typedef struct {
@@ -48,7 +48,7 @@ typedef struct {
   int32_t max_interp;   /* c: cap on |J_i| (Section 4.1) */
   int32_t max_levels;
   int32_t coarse_max;   /* stop coarsening once n_l <= coarse_max */
-  int32_t coarsening;   /* ORC_COARSEN_GEOM or ORC_COARSEN_MIS */
+  int32_t coarsening;   /* ORC_COARSEN_GEOM, ORC_COARSEN_MIS or ORC_COARSEN_CR */
   int32_t geom_kind;    /* 1 = 1-D line, 2 = 2-D grid (index iy*nx+ix) */
   int32_t nx, ny;
   uint64_t seed;
@@ -58,6 +58,11 @@ typedef struct {
   int32_t cycle;        /* preconditioning cycle: ORC_CYCLE_V, _W or _F (Section 3) */
   int32_t mu;           /* passes of the inner loop of Algorithm 1 per level visit */
   int32_t restriction;  /* 0 = LS fit with 1^T Q = 1^T (Section 5), 1 = simple averaging */
+  /* compatible relaxation (coarsening = ORC_COARSEN_CR, reading R-CR) */
+  double cr_theta;      /* target F-relaxation rate: stop once a round's rate is at most this */
+  double cr_beta;       /* candidates: F points with |e_i| >= cr_beta * max |e| */
+  int32_t cr_sweeps;    /* F-relaxation sweeps per round */
+  int32_t cr_rounds;    /* at most this many rounds */
 } orc_options;
 
 enum { ORC_CYCLE_V = 0, ORC_CYCLE_W = 1, ORC_CYCLE_F = 2 };
@@ -78,6 +83,14 @@ int orc_setup(int64_t n, const int32_t *rp, const int32_t *ci, const double *a,
 void orc_destroy(orc_ctx *c);
 
 int orc_num_levels(const orc_ctx *c);
+
+/* Compatible-relaxation C/F splitting (reading R-CR) of the operator B
+ * (CSR with values, diagonal stored) on the symmetrised graph G (no
+ * diagonal): cf[i] = 1 for C, 0 for F. rates (rounds entries, nullable)
+ * receives each round's F-relaxation rate; *nrounds the rounds run. */
+int orc_cr(int n, const int32_t *brp, const int32_t *bci, const double *bv, const int32_t *grp,
+           const int32_t *gci, uint64_t seed, int level, double theta, double beta, int sweeps,
+           int rounds, double omega, int32_t *cf, double *rates, int32_t *nrounds);
 /* Threads of the OpenMP row loops from now on (n >= 1; any count gives the
  * same results); returns the previous count. */
 int orc_set_threads(int n);
