@@ -53,7 +53,7 @@ enum {
   BAMG_E_NOMEM = -9            /* device allocation failed */
 };
 
-enum { BAMG_COARSEN_GEOMETRIC = 0, BAMG_COARSEN_MIS = 1 };
+enum { BAMG_COARSEN_GEOMETRIC = 0, BAMG_COARSEN_MIS = 1, BAMG_COARSEN_CR = 2 };
 enum { BAMG_SMOOTH_JACOBI = 0, BAMG_SMOOTH_KACZMARZ = 1 };
 enum { BAMG_PRECISION_FP64 = 0, BAMG_PRECISION_MIXED = 1 };
 enum { BAMG_DTYPE_F64 = 0, BAMG_DTYPE_F32 = 1 };
@@ -90,7 +90,8 @@ typedef struct {
   int32_t max_interp;   /* c: at most c interpolation points per F point, 1..8 */
   int32_t max_levels;   /* cap on the number of levels, >= 2 */
   int32_t coarse_max;   /* stop coarsening once n_l <= coarse_max (<= 2048) */
-  int32_t coarsening;   /* BAMG_COARSEN_GEOMETRIC (needs geometry) or BAMG_COARSEN_MIS */
+  int32_t coarsening;   /* BAMG_COARSEN_GEOMETRIC (needs geometry), BAMG_COARSEN_MIS, or
+                           BAMG_COARSEN_CR (compatible relaxation, the cr_* fields) */
   uint64_t seed;        /* test vectors and MIS priorities (Philox-4x64-10) */
   int32_t smoother;     /* BAMG_SMOOTH_JACOBI or BAMG_SMOOTH_KACZMARZ (Section 3) */
   int32_t precision;    /* BAMG_PRECISION_FP64 or BAMG_PRECISION_MIXED */
@@ -125,6 +126,21 @@ typedef struct {
                            after this many iterations, the hierarchy is rebuilt with
                            the exact LS fits (same options, learned off) and GMRES
                            continues from its iterate; 0 = never */
+  /* Compatible-relaxation coarsening (BAMG_COARSEN_CR; Section 7 names the
+   * method, whose algorithm it cites): per level, rounds of cr_sweeps
+   * weighted-Jacobi sweeps (weight omega) on B_ff e_f = 0 from a fixed
+   * pseudo-random start with the C entries zero; a round whose last-sweep
+   * rate ||e^k|| / ||e^(k-1)|| is at most cr_theta ends the search, else the
+   * F points with |e_i| >= cr_beta max |e| are candidates and the greedy
+   * independent set of their graph, by decreasing (number of candidate
+   * neighbours, priority), joins C; at most cr_rounds rounds. Then F points
+   * without a coarse neighbour take a greedy independent set of their own.
+   * Levels below the first use the Galerkin product with averaging
+   * transfers (the bootstrap refits P and Q afterwards). */
+  double cr_theta;      /* 0.8 */
+  double cr_beta;       /* 0.7, in [0, 1] */
+  int32_t cr_sweeps;    /* 5, 1..64 */
+  int32_t cr_rounds;    /* 10, 0..64 */
 } bamg_options;
 
 /* Cycle shapes. A W-cycle takes two cycles of its own shape on the next

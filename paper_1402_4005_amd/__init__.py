@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libbamg.so")
 
 OK = 0
 NOT_CONVERGED = 1
-COARSEN_GEOMETRIC, COARSEN_MIS = 0, 1
+COARSEN_GEOMETRIC, COARSEN_MIS, COARSEN_CR = 0, 1, 2
 SMOOTH_JACOBI, SMOOTH_KACZMARZ = 0, 1
 PRECISION_FP64, PRECISION_MIXED = 0, 1
 DTYPE_F64, DTYPE_F32 = 0, 1
@@ -65,7 +65,9 @@ class Options(C.Structure):
                 ("use_graph", C.c_int32), ("learned", C.c_int32), ("mlp", C.c_void_p),
                 ("autotune", C.c_int32), ("fuse_last_level", C.c_int32),
                 ("cycle", C.c_int32), ("mu", C.c_int32), ("restriction", C.c_int32),
-                ("profile_setup", C.c_int32), ("learned_max_iters", C.c_int32)]
+                ("profile_setup", C.c_int32), ("learned_max_iters", C.c_int32),
+                ("cr_theta", C.c_double), ("cr_beta", C.c_double), ("cr_sweeps", C.c_int32),
+                ("cr_rounds", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -156,7 +158,8 @@ def default_options(**kw) -> Options:
     o = Options()
     _check(lib().bamg_default_options(C.byref(o)))
     names = {
-        "coarsening": {"geom": COARSEN_GEOMETRIC, "geometric": COARSEN_GEOMETRIC, "mis": COARSEN_MIS},
+        "coarsening": {"geom": COARSEN_GEOMETRIC, "geometric": COARSEN_GEOMETRIC, "mis": COARSEN_MIS,
+                       "cr": COARSEN_CR},
         "smoother": {"jacobi": SMOOTH_JACOBI, "kaczmarz": SMOOTH_KACZMARZ},
         "precision": {"fp64": PRECISION_FP64, "mixed": PRECISION_MIXED},
         "learned": {"off": LEARNED_OFF, "use": LEARNED_USE, "record": LEARNED_RECORD},

@@ -6,6 +6,8 @@
 #include <string>
 #include <vector>
 
+#include <cmath>
+
 #include "bamg_internal.h"
 
 namespace bamg {
@@ -206,6 +208,10 @@ bamg_status bamg_default_options(bamg_options *o) {
   o->cycle = BAMG_CYCLE_V;
   o->mu = 1;
   o->restriction = 0;
+  o->cr_theta = 0.8;
+  o->cr_beta = 0.7;
+  o->cr_sweeps = 5;
+  o->cr_rounds = 10;
   return BAMG_OK;
 }
 
@@ -237,7 +243,6 @@ static bamg_status check_options(const bamg_options *o) {
   if (o->max_interp < 1 || o->max_interp > 8) return BAMG_E_ARG;
   if (o->max_levels < 2 || o->max_levels > 32) return BAMG_E_ARG;
   if (o->coarse_max < 1 || o->coarse_max > 2048) return BAMG_E_ARG;
-  if (o->coarsening != BAMG_COARSEN_GEOMETRIC && o->coarsening != BAMG_COARSEN_MIS) return BAMG_E_ARG;
   if (o->smoother != BAMG_SMOOTH_JACOBI && o->smoother != BAMG_SMOOTH_KACZMARZ) return BAMG_E_ARG;
   if (o->precision != BAMG_PRECISION_FP64 && o->precision != BAMG_PRECISION_MIXED) return BAMG_E_ARG;
   if (o->interp_rule != 0 && o->interp_rule != 1) return BAMG_E_ARG;
@@ -247,6 +252,10 @@ static bamg_status check_options(const bamg_options *o) {
   if (o->restriction != 0 && o->restriction != 1) return BAMG_E_ARG;
   if (o->profile_setup != 0 && o->profile_setup != 1) return BAMG_E_ARG;
   if (o->learned_max_iters < 0) return BAMG_E_ARG;
+  if (o->coarsening < BAMG_COARSEN_GEOMETRIC || o->coarsening > BAMG_COARSEN_CR) return BAMG_E_ARG;
+  if (!std::isfinite(o->cr_theta) || !(o->cr_beta >= 0.0 && o->cr_beta <= 1.0) ||
+      o->cr_sweeps < 1 || o->cr_sweeps > 64 || o->cr_rounds < 0 || o->cr_rounds > 64)
+    return BAMG_E_ARG;
   if (o->learned < BAMG_LEARNED_OFF || o->learned > BAMG_LEARNED_RECORD) return BAMG_E_ARG;
   if (o->learned == BAMG_LEARNED_USE && !o->mlp) return BAMG_E_ARG;
   return BAMG_OK;

@@ -201,6 +201,11 @@ int validation_status(const int *h, int n);
 void sym_graph(Pool &pool, const Csr &B, const Csr &Bt, Csr &G, hipStream_t s);
 void geom_cf(int n, int nx, int gkind, int *cf, hipStream_t s);
 void mis_cf(Pool &pool, const Csr &G, uint64_t seed, int level, int *cf, hipStream_t s);
+void mis_rounds(Pool &pool, const Csr &G, const uint64_t *key, int *state, hipStream_t s);
+// compatible-relaxation C/F splitting of the operator (B, bv FP64, diagonal
+// positions dpos) on the graph G (k_cr.hip)
+void cr_cf(Pool &pool, const Csr &B, const double *bv, const int *dpos, const Csr &G,
+           uint64_t seed, int level, const bamg_options &o, int *cf, hipStream_t s);
 int coarse_numbering(Pool &pool, const int *cf, int n, int *cidx, int *&cpts, hipStream_t s);
 void interp_pattern(Pool &pool, const Level &L, int cap, int geometric, Csr &P, hipStream_t s);
 // C1 = A1 B1 and C2 = A2 B2 (patterns) with one host round trip for both

@@ -332,14 +332,14 @@ __global__ void k_mis_update(int n, const int *__restrict__ rp, const int *__res
   if ((threadIdx.x % kWave) == 0 && b) atomicAdd(undecided, (int)__popcll(b));
 }
 
-void mis_cf(Pool &pool, const Csr &G, uint64_t seed, int level, int *cf, hipStream_t s) {
+// Rounds of k_mis_select / k_mis_update until no vertex with state -1 is
+// left: the greedy independent set, in decreasing (key, index) order, of
+// the vertices that start undecided (-1); other states are left alone.
+void mis_rounds(Pool &pool, const Csr &G, const uint64_t *key, int *state, hipStream_t s) {
   const int n = G.nr;
-  uint64_t *key = pool.get<uint64_t>(n);
   int *sel = pool.get<int>(n);
   int *und = pool.get<int>(1);
   fill_i32(sel, 0, n, s);
-  k_mis_keys<<<ceil_div(n, 256), 256, 0, s>>>(n, seed, level, key, cf);
-  LAUNCHCHK();
   // Two rounds per host check of the undecided count: a round after the
   // last decision changes nothing, so the set is the same, with half the
   // host round trips.
@@ -347,16 +347,24 @@ void mis_cf(Pool &pool, const Csr &G, uint64_t seed, int level, int *cf, hipStre
     if (round > n + 1) fail(BAMG_E_DEVICE, "MIS did not terminate");
     for (int q = 0; q < 2; ++q) {
       fill_i32(und, 0, 1, s);
-      k_mis_select<<<ceil_div(n, 256), 256, 0, s>>>(n, G.rp, G.ci, key, cf, sel, round + q);
+      k_mis_select<<<ceil_div(n, 256), 256, 0, s>>>(n, G.rp, G.ci, key, state, sel, round + q);
       LAUNCHCHK();
-      k_mis_update<<<ceil_div(n, 256), 256, 0, s>>>(n, G.rp, G.ci, sel, cf, round + q, und);
+      k_mis_update<<<ceil_div(n, 256), 256, 0, s>>>(n, G.rp, G.ci, sel, state, round + q, und);
       LAUNCHCHK();
     }
     if (read_int(und, s) == 0) break;
   }
-  pool.release(key);
   pool.release(sel);
   pool.release(und);
+}
+
+void mis_cf(Pool &pool, const Csr &G, uint64_t seed, int level, int *cf, hipStream_t s) {
+  const int n = G.nr;
+  uint64_t *key = pool.get<uint64_t>(n);
+  k_mis_keys<<<ceil_div(n, 256), 256, 0, s>>>(n, seed, level, key, cf);
+  LAUNCHCHK();
+  mis_rounds(pool, G, key, cf, s);
+  pool.release(key);
 }
 
 __global__ void k_cidx(const int *__restrict__ cf, const int *__restrict__ scan, int n,

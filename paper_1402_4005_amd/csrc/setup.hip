@@ -402,10 +402,23 @@ void setup_all(bamg_handle *h, const bamg_csr *A, const bamg_geometry *geom) {
       sym_graph(pool, L.B, L.Bt, L.G, s);
       L.cf = pool.get<int>(L.n);
       L.cidx = pool.get<int>(L.n);
-      if (geometric)
+      if (geometric) {
         geom_cf(L.n, L.nx, L.gkind, L.cf, s);
-      else
+      } else if (o.coarsening == BAMG_COARSEN_CR) {
+        // FP64 operator values: the input's on the first level, the
+        // averaging Galerkin product below (formed when the level was made)
+        const double *bv = l == 0 ? h->B64 : (const double *)L.Bv;
+        double *tmp = nullptr;
+        if (l > 0 && sizeof(T) != sizeof(double)) {
+          tmp = pool.get<double>(L.B.nnz);
+          convert<T, double>(tmp, (const T *)L.Bv, L.B.nnz, s);
+          bv = tmp;
+        }
+        cr_cf(pool, L.B, bv, L.dpos, L.G, o.seed, l, o, L.cf, s);
+        if (tmp) pool.release(tmp);
+      } else {
         mis_cf(pool, L.G, o.seed, l, L.cf, s);
+      }
       L.nc = coarse_numbering(pool, L.cf, L.n, L.cidx, L.cpts, s);
       if (L.nc == 0 || L.nc >= L.n) break;
       interp_pattern(pool, L, o.max_interp, geometric ? 1 : 0, L.P, s);
@@ -437,6 +450,18 @@ void setup_all(bamg_handle *h, const bamg_csr *A, const bamg_geometry *geom) {
     C.Nv = pool.get<T>(C.M.nnz);
     C.dinv = pool.get<T>(C.n);
     h->lv.push_back(C);
+    if (o.coarsening == BAMG_COARSEN_CR && !geometric) {
+      // the next level's compatible relaxation runs on Q B P with the
+      // averaging transfers (1 / |J_i| on J_i); the bootstrap cycles refit P
+      // and Q and form the operator again
+      Level &L = h->lv[l], &N = h->lv[l + 1];
+      fill_transfer_identity<T>(L, (T *)L.Pv, (T *)L.Qtv, s);
+      copy_permuted<T>((T *)L.Qv, (const T *)L.Qtv, L.pcperm, L.P.nnz, s);
+      int *sc = pool.get<int>((size_t)L.n + 1);
+      spgemm_numeric<T>(L.B, (const T *)L.Bv, L.P, (const T *)L.Pv, L.T1, (T *)L.T1v, sc, s);
+      spgemm_numeric<T>(L.Pc, (const T *)L.Qv, L.T1, (const T *)L.T1v, N.B, (T *)N.Bv, sc, s);
+      pool.release(sc);
+    }
   }
   h->L = (int)h->lv.size();
   if (h->L < 2) fail(BAMG_E_ARG, "no coarsening happened (check coarse_max and max_levels)");

@@ -90,6 +90,15 @@ CASES = [
      dict(r=6, max_levels=3, coarse_max=1, restriction=1)),
     ("delaunay3000_average", lambda: chaingen.delaunay_walk(3000, 12),
      dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99, restriction=1)),
+    # compatible-relaxation coarsening (R-CR): its relaxation decides
+    # integers from FP64 values, so the C/F splits must still be bit-exact
+    ("delaunay3000_cr", lambda: chaingen.delaunay_walk(3000, 12),
+     dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99, coarsening="cr")),
+    ("hub4000_cr", lambda: chaingen.hub_walk(4000, 8, 200, 7),
+     dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99, coarsening="cr")),
+    ("delaunay6000_cr_more_rounds", lambda: chaingen.delaunay_walk(6000, 13),
+     dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99, coarsening="cr",
+          cr_theta=0.7, cr_beta=0.5, cr_sweeps=3)),
 ]
 
 
@@ -375,3 +384,26 @@ def test_coarse_level_1089_states():
     xd = sla.spsolve(Bm.tocsc(), e0)
     xd /= xd.sum()
     assert rel_l1(xg.cpu().numpy(), xd) < 1e-10
+
+
+def test_cr_without_rounds_is_mis_and_mixed_cr_solves():
+    """cr_rounds = 0 leaves only the completion step: the MIS split, bit for
+    bit, on every level. Mixed precision with CR runs the relaxation on the
+    FP32 coarse operators (converted to FP64), so its splits may differ
+    from the oracle's; its x must still reach the FP64 oracle's to 1e-10."""
+    import torch
+    ch = chaingen.delaunay_walk(3000, 14)
+    kw = dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99)
+    hm = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, coarsening="mis", **kw))
+    hc = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, coarsening="cr", cr_rounds=0, **kw))
+    assert hm.levels == hc.levels
+    for l in range(hm.levels - 1):
+        assert np.array_equal(hm.cf(l)[0], hc.cf(l)[0]), l
+    hx = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, coarsening="cr", precision="mixed",
+                                                        **kw))
+    x, info = hx.gmres(restart=20, tol=1e-12, maxit=300)
+    torch.cuda.synchronize()
+    xo, _ = oracle.Hierarchy(ch, oracle.options_for(ch, coarsening="cr", **kw)).gmres(
+        m=20, tol=1e-14, maxit=300)
+    assert info.converged
+    assert rel_l1(x.cpu().numpy(), xo) < 1e-10
