@@ -65,7 +65,8 @@ STATUS_RUNS = [("tandem1025_random", 1025, 14024003)] + \
 # traffic measured by hardware counters is kept in profiles/ together with
 # the digest of these files; after any change to them it no longer applies.
 KERNEL_SOURCES = {
-    "k_jacobi": ("paper_1402_4005_amd/csrc/k_sparse.hip", "paper_1402_4005_amd/csrc/device_common.h"),
+    "k_jacobi": ("paper_1402_4005_amd/csrc/k_sparse.hip", "paper_1402_4005_amd/csrc/sparse_row.h",
+                 "paper_1402_4005_amd/csrc/device_common.h"),
     "k_block_jacobi_round": ("paper_1402_4005_amd/csrc/k_dense.hip",
                              "paper_1402_4005_amd/csrc/device_common.h"),
 }
@@ -265,6 +266,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="tandem2049", choices=sorted(WORKLOADS) + ["batch"])
+    ap.add_argument("--coarsening", default=None, choices=["mis", "cr"],
+                    help="algebraic C/F splitting of a workload without geometry "
+                         "(default: the workload's own)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--setup-cycles", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-10)
@@ -319,6 +323,8 @@ def main():
         run_batch(args)
         return
     kind, size, wopts = WORKLOADS[args.workload]
+    if args.coarsening:
+        wopts = dict(wopts, coarsening=args.coarsening)
     ch = make_chain(kind, size, wopts["seed"])
     dev = torch.device("cuda:0")
     rp = torch.from_numpy(ch.indptr).to(dev)
@@ -565,6 +571,7 @@ def main():
             "r": opts.r, "c": opts.max_interp, "sweeps": f"{opts.nu_pre}+{opts.nu_post}",
             "setup_cycles": opts.setup_cycles, "restart": args.restart, "tol": args.tol,
             "precision": args.precision,
+            "coarsening": {0: "geometric", 1: "mis", 2: "cr"}[opts.coarsening],
         },
         "iterations": it,
         "converged": [bool(i.converged) for i in infos],
