@@ -485,15 +485,42 @@ __global__ void __launch_bounds__(64 * BS)
   }
   __syncthreads();
   // Gram matrix: wave wv forms tile (wv % (ct ct)) over K-slice
-  // wv / (ct ct); the slices are added in order below
+  // wv / (ct ct); the slices are added in order below. A diagonal tile
+  // (one 16-column tile per pair when bs = 8) multiplies a matrix by its own
+  // transpose, so one LDS load feeds both operands; four accumulators over
+  // interleaved K steps keep four MFMA chains in flight.
   {
     const int tile = wv % (ct * ct), sl = wv / (ct * ct);
     const int ta = tile / ct, tb = tile % ct, ks = (n + 3) / 4;
     const int k0 = sl * ks / nsl, k1 = (sl + 1) * ks / nsl;
     svd_d4 acc = {0.0, 0.0, 0.0, 0.0};
-    acc = mfma_tile(
-        k0, k1, [&](int i, int k) { return k < n ? Ws[(size_t)(16 * ta + i) * n + k] : 0.0; },
-        [&](int k, int j) { return k < n ? Ws[(size_t)(16 * tb + j) * n + k] : 0.0; }, acc);
+    if (ta == tb) {
+      const double *cw = Ws + (size_t)(16 * ta + ln % 16) * n + ln / 16;
+      svd_d4 a1 = acc, a2 = acc, a3 = acc;
+      int kk = k0;
+      for (; kk + 3 < k1; kk += 4) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = 4 * (kk + u) + ln / 16;
+          v[u] = k < n ? cw[4 * (kk + u)] : 0.0;
+        }
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v[0], v[0], acc, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(v[1], v[1], a1, 0, 0, 0);
+        a2 = __builtin_amdgcn_mfma_f64_16x16x4f64(v[2], v[2], a2, 0, 0, 0);
+        a3 = __builtin_amdgcn_mfma_f64_16x16x4f64(v[3], v[3], a3, 0, 0, 0);
+      }
+      for (; kk < k1; ++kk) {
+        const int k = 4 * kk + ln / 16;
+        const double v = k < n ? cw[4 * kk] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
+      }
+      acc = (acc + a1) + (a2 + a3);
+    } else {
+      acc = mfma_tile(
+          k0, k1, [&](int i, int k) { return k < n ? Ws[(size_t)(16 * ta + i) * n + k] : 0.0; },
+          [&](int k, int j) { return k < n ? Ws[(size_t)(16 * tb + j) * n + k] : 0.0; }, acc);
+    }
     for (int r = 0; r < 4; ++r) part[(size_t)wv * 256 + (ln / 16 + 4 * r) * 16 + ln % 16] = acc[r];
   }
   __syncthreads();
@@ -623,9 +650,13 @@ __global__ void __launch_bounds__(64 * BS)
   const double *R = Ra;
   if (nrot > 0) {
     // X[:, pair] <- X[:, pair] R for X = W (from Ws), then X = J (from the
-    // registers fetched at the start, the rows past NP * 32 from memory):
-    // output tiles of 16 rows x 16 columns, round-robin over the waves
-    const int rt = (n + 15) / 16;
+    // registers fetched at the start, the rows past NP * 32 from memory).
+    // Each tile is formed transposed, (R^T X^T) for 16 pair columns x 16
+    // rows: the FP64 MFMA leaves entry (l / 16 + 4 r, l % 16) of its output
+    // tile in lane l, register r, so lane l holds row 16 it + l % 16 and a
+    // store instruction writes 16 consecutive rows of each of 4 columns (X
+    // is column-major); two tiles per step, round-robin over the waves
+    const int rt = (n + 15) / 16, ntl = rt * ct;
     for (int pass = 0; pass < 2; ++pass) {
       double *__restrict__ Xm = pass == 0 ? Wm : Jm;
       if (pass == 1) {
@@ -636,18 +667,31 @@ __global__ void __launch_bounds__(64 * BS)
         for (int i = li + 32 * NP; i < n; i += 32) dst[i] = lg < n ? jsrc[i] : 0.0;
         __syncthreads();
       }
-      for (int tl = wv; tl < rt * ct; tl += nw) {
-        const int it = tl / ct, cj = tl % ct;
-        svd_d4 acc = {0.0, 0.0, 0.0, 0.0};
-        acc = mfma_tile(
-            0, cols / 4,
-            [&](int i, int k) { return Ws[(size_t)k * n + min(16 * it + i, n - 1)]; },
-            [&](int k, int j) { return R[k * cols + 16 * cj + j]; }, acc);
-        const int c = 16 * cj + ln % 16, g = gcol(c);
+      auto tile_ops = [&](int tl, int kk, double &a, double &b) {
+        const int it = tl / ct, cj = tl % ct, k = 4 * kk + ln / 16;
+        a = R[k * cols + 16 * cj + ln % 16];                      // (R^T)[j][k]
+        b = Ws[(size_t)k * n + min(16 * it + ln % 16, n - 1)];    // (X^T)[k][i]
+      };
+      auto tile_store = [&](int tl, const svd_d4 &acc) {
+        const int it = tl / ct, cj = tl % ct, i = 16 * it + ln % 16;
         for (int r = 0; r < 4; ++r) {
-          const int i = 16 * it + ln / 16 + 4 * r;
+          const int g = gcol(16 * cj + ln / 16 + 4 * r);
           if (i < n && g < n) Xm[(size_t)g * n + i] = acc[r];
         }
+      };
+      for (int tl = wv; tl < ntl; tl += 2 * nw) {
+        const int t2 = tl + nw;
+        svd_d4 a0 = {0.0, 0.0, 0.0, 0.0}, a1 = a0;
+#pragma unroll
+        for (int kk = 0; kk < cols / 4; ++kk) {
+          double x0, y0, x1 = 0.0, y1 = 0.0;
+          tile_ops(tl, kk, x0, y0);
+          if (t2 < ntl) tile_ops(t2, kk, x1, y1);
+          a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, a0, 0, 0, 0);
+          a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, a1, 0, 0, 0);
+        }
+        tile_store(tl, a0);
+        if (t2 < ntl) tile_store(t2, a1);
       }
       __syncthreads();
     }
