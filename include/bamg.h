@@ -373,7 +373,7 @@ bamg_status bamg_batch_status(const bamg_batch *b, int32_t i, bamg_status *setup
  * every chain's x, iteration count and residual equal that call's bit for
  * bit, whichever way it ran. The launch takes chains with a V-cycle (or no
  * preconditioner), restart <= 32 and no learned iteration fallback, and
- * under the default BAMG_BATCH_AUTO only those of at most 4096 states
+ * under the default BAMG_BATCH_AUTO only those of at most 5000 states
  * (larger ones are faster per chain on the streams); BAMG_BATCH_PERSISTENT
  * gives it every chain it can take, BAMG_BATCH_STREAMS none. The call
  * returns when every result is written. infos[i].t_solve_ms is the chain's

@@ -517,7 +517,7 @@ class Batch:
     SOLVERS = {"auto": 0, "persistent": 1, "streams": 2}
 
     def set_solver(self, solver):
-        """'auto' (default: chains up to 4096 states in one persistent launch,
+        """'auto' (default: chains up to 5000 states in one persistent launch,
         a workgroup per chain, the others per chain on the library streams,
         both at once), 'persistent' (every chain the launch can take) or
         'streams' (none)."""

@@ -18,9 +18,10 @@
 
 // Largest chain the default (automatic) split sends to the persistent
 // launch. Measured per GMRES iteration on the 512-chain batched workload
-// (mixed precision, MI355X): one workgroup per chain 0.26 ms below 2k
-// states and 0.71 ms at 2k-5k, the per-step solve 0.40 and 0.56 ms.
-constexpr int kBatchAutoMaxStates = 4096;
+// (mixed precision, MI355X, 1024-thread workgroups): one workgroup per
+// chain 0.23 ms below 2k states, 0.47 ms at 2k-5k and 0.95 ms at 5k-10k;
+// the per-step solve 0.43, 0.55 and 0.59 ms.
+constexpr int kBatchAutoMaxStates = 5000;
 
 struct bamg_batch {
   int n = 0;

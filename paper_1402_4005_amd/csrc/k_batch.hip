@@ -32,7 +32,7 @@
 
 namespace bamg {
 
-constexpr int kBatchThreads = 512;
+constexpr int kBatchThreads = 1024;
 constexpr int kBatchWaves = kBatchThreads / kWave;
 constexpr int kRedThreads = 256;  // block size of the per-step reductions
 constexpr int kRedWaves = kRedThreads / kWave;
@@ -355,6 +355,27 @@ __device__ __forceinline__ double block_partial(int b, int nblk, int n, Acc acc)
   return r;
 }
 
+// The same partial when every thread of the 256-thread block holds at most
+// one row (nblk * 256 >= n, so the stride passes the end): the lane holds
+// row 256 b + 64 q + ln of each sub-wave q, rows[q] < 0 past the end, and
+// the four sub-waves' loads and butterflies are independent of each other.
+__device__ __forceinline__ void block_rows(int b, int n, long rows[kRedWaves]) {
+  const int ln = threadIdx.x % kWave;
+#pragma unroll
+  for (int q = 0; q < kRedWaves; ++q) {
+    const long i = (long)b * kRedThreads + q * kWave + ln;
+    rows[q] = i < n ? i : -1;
+  }
+}
+__device__ __forceinline__ double block_combine(double s[kRedWaves]) {
+#pragma unroll
+  for (int q = 0; q < kRedWaves; ++q) s[q] = group_sum(s[q], kWave);
+  double r = 0.0;
+#pragma unroll
+  for (int q = 0; q < kRedWaves; ++q) r += s[q];
+  return r;
+}
+
 // the final stage: thread tt adds partials tt, tt + 256, ... in order, then
 // the block sum as above; one wave
 __device__ __forceinline__ double final_sum(const double *part, int nblk) {
@@ -373,6 +394,39 @@ __device__ void multi_dot(const BatchChain &c, int k, bool with_ww) {
   const int nb = c.nblk, n = c.n, wv = threadIdx.x / kWave, ln = threadIdx.x % kWave;
   const int nt = with_ww ? k + 1 : k;
   const double *w = c.w;
+  if ((long)nb * kRedThreads >= n) {
+    // a wave per block, every vector of it: w loaded once, two vectors'
+    // loads in flight at a time
+    for (int b = wv; b < nb; b += kBatchWaves) {
+      long rows[kRedWaves];
+      double wq[kRedWaves];
+      block_rows(b, n, rows);
+#pragma unroll
+      for (int q = 0; q < kRedWaves; ++q) wq[q] = rows[q] >= 0 ? w[rows[q]] : 0.0;
+      for (int t = 0; t < nt; t += 2) {
+        const double *v0 = t < k ? c.V + (size_t)t * n : w;
+        const double *v1 = t + 1 < k ? c.V + (size_t)(t + 1) * n : w;
+        double s0[kRedWaves], s1[kRedWaves];
+#pragma unroll
+        for (int q = 0; q < kRedWaves; ++q) {
+          s0[q] = 0.0;
+          s1[q] = 0.0;
+          if (rows[q] >= 0) {
+            s0[q] += v0[rows[q]] * wq[q];
+            if (t + 1 < nt) s1[q] += v1[rows[q]] * wq[q];
+          }
+        }
+        const double r0 = block_combine(s0);
+        if (ln == 0) c.part[(size_t)t * nb + b] = r0;
+        if (t + 1 < nt) {
+          const double r1 = block_combine(s1);
+          if (ln == 0) c.part[(size_t)(t + 1) * nb + b] = r1;
+        }
+      }
+    }
+    wg_sync();
+    return;
+  }
   for (int idx = wv; idx < nt * nb; idx += kBatchWaves) {
     const int t = idx / nb, b = idx % nb;
     const double *v = t < k ? c.V + (size_t)t * n : w;
@@ -397,6 +451,34 @@ __device__ void multi_axpy(const BatchChain &c, int k, const double *h, double *
   const int nb = c.nblk, n = c.n, wv = threadIdx.x / kWave, ln = threadIdx.x % kWave;
   double *w = c.w;
   const double *V = c.V;
+  if ((long)nb * kRedThreads >= n) {
+    for (int b = wv; b < nb; b += kBatchWaves) {
+      long rows[kRedWaves];
+      double x[kRedWaves], sq[kRedWaves];
+      block_rows(b, n, rows);
+#pragma unroll
+      for (int q = 0; q < kRedWaves; ++q) x[q] = rows[q] >= 0 ? w[rows[q]] : 0.0;
+      for (int t = 0; t < k; ++t) {
+        const double ht = h[t];
+        const double *vt = V + (size_t)t * n;
+#pragma unroll
+        for (int q = 0; q < kRedWaves; ++q)
+          if (rows[q] >= 0) x[q] -= ht * vt[rows[q]];
+      }
+#pragma unroll
+      for (int q = 0; q < kRedWaves; ++q) {
+        sq[q] = 0.0;
+        if (rows[q] >= 0) {
+          w[rows[q]] = x[q];
+          sq[q] += x[q] * x[q];
+        }
+      }
+      const double r = block_combine(sq);
+      if (part2 && ln == 0) part2[b] = r;
+    }
+    wg_sync();
+    return;
+  }
   for (int b = wv; b < nb; b += kBatchWaves) {
     const double r = block_partial(b, nb, n, [&](double &s, long i) {
       double x = w[i];
@@ -460,6 +542,42 @@ __device__ void residual_check(const BatchChain &c, int k, const double *y,
   const int n = c.n, nb = c.nblk, wv = threadIdx.x / kWave, ln = threadIdx.x % kWave;
   double *part3 = c.part + (size_t)(c.m + 3) * nb;
   const double *x0 = c.x0, *bx0 = c.bx0, *V = c.V, *BV = c.BV;
+  if ((long)nb * kRedThreads >= n) {
+    for (int b = wv; b < nb; b += kBatchWaves) {
+      long rows[kRedWaves];
+      double bx[kRedWaves], xx[kRedWaves], sb[kRedWaves], sx[kRedWaves];
+      block_rows(b, n, rows);
+#pragma unroll
+      for (int q = 0; q < kRedWaves; ++q) {
+        bx[q] = rows[q] >= 0 ? bx0[rows[q]] : 0.0;
+        xx[q] = rows[q] >= 0 ? x0[rows[q]] : 0.0;
+      }
+      for (int t = 0; t < k; ++t) {
+        const double yt = y[t];
+        const double *bvt = BV + (size_t)t * n, *vt = V + (size_t)t * n;
+#pragma unroll
+        for (int q = 0; q < kRedWaves; ++q)
+          if (rows[q] >= 0) {
+            bx[q] += yt * bvt[rows[q]];
+            xx[q] += yt * vt[rows[q]];
+          }
+      }
+#pragma unroll
+      for (int q = 0; q < kRedWaves; ++q) {
+        sb[q] = 0.0;
+        sx[q] = 0.0;
+        if (rows[q] >= 0) {
+          sb[q] += bx[q] * bx[q];
+          sx[q] += xx[q] * xx[q];
+        }
+      }
+      const double ra = block_combine(sb), rb = block_combine(sx);
+      if (ln == 0) {
+        part3[b] = ra;
+        part3[nb + b] = rb;
+      }
+    }
+  } else
   for (int b = wv; b < nb; b += kBatchWaves) {
     double ra = 0.0, rb = 0.0;
     for (int q = 0; q < kRedWaves; ++q) {

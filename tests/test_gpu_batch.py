@@ -89,7 +89,7 @@ def forms():
         (chaingen.tandem(33, 0.34, 0.33, 0.33), dict(r=8, coarse_max=30, nu_setup=5,
                                                      fuse_last_level=0), 300),
         (chaingen.tandem(33, 0.34, 0.33, 0.33), dict(r=8, coarse_max=30, nu_setup=5), 300),
-        (chaingen.delaunay_walk(5000, 23), dict(PLANAR, nu_pre=4, nu_post=3), 300),
+        (chaingen.delaunay_walk(6000, 23), dict(PLANAR, nu_pre=4, nu_post=3), 300),
         (chaingen.birth_death(257, 0.96), dict(r=8, max_interp=2, coarse_max=29), 300),
         (chaingen.tandem(65, *PAPER), dict(r=8, max_interp=4, coarse_max=300, nu_setup=8), 3),
         (chaingen.delaunay_walk(2000, 24), dict(PLANAR, cycle="none"), 40),
@@ -115,8 +115,8 @@ def solve_batch(ms, solver, restart=20, tol=1e-12):
 
 @pytest.mark.parametrize("solver", ["persistent", "auto"])
 def test_persistent_solve_equals_per_chain_solve(solver):
-    """'persistent': every form in the launch; 'auto': the chains above 4096
-    states (Delaunay 5000) on the streams while the others run in the launch."""
+    """'persistent': every form in the launch; 'auto': the chains above 5000
+    states (Delaunay 6000) on the streams while the others run in the launch."""
     ms = forms()
     per = solve_batch(ms, solver)
     ref = solve_batch(ms, "streams")
