@@ -414,6 +414,7 @@ def main():
     # untimed: accuracy and split of the last step, V-cycle bandwidth
     hinfo = last.info()
     hinfo_lanes = last.lanes(0)
+    hinfo_threads = last.threads(0)
     xs = x.cpu().numpy()
     extra = {}
     if kind == "delaunay":
@@ -538,7 +539,8 @@ def main():
         }
 
     sweep_roof = roofline_of(f"k_jacobi (finest-level weighted-Jacobi sweep, CSR, {hinfo_lanes} "
-                             "lanes/row)", "k_jacobi", launches, kms, kbytes)
+                             f"lanes/row, {hinfo_threads} threads/workgroup)", "k_jacobi",
+                             launches, kms, kbytes)
     svd_roof = roofline_of("k_block_jacobi_round (coarsest-level block Jacobi SVD, one launch "
                            "per round)", "k_block_jacobi_round", int(svd[0]), svd[1], svd[2])
     # the roofline object covers whichever of the two takes more time per step

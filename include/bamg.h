@@ -323,6 +323,15 @@ bamg_status bamg_level_lanes(const bamg_handle *h, int32_t l, int32_t *lanes);
  * the same for every choice. BAMG_E_ARG for another value, or once GMRES
  * has captured the V-cycle into a graph (use_graph = 1). */
 bamg_status bamg_level_set_lanes(bamg_handle *h, int32_t l, int32_t lanes);
+/* Workgroup size (threads) of level l's sweeps and residual, and on level 0
+ * of GMRES's products with B: 256 unless autotuning picked 128, 512 or 1024
+ * (l < levels - 1). */
+bamg_status bamg_level_threads(const bamg_handle *h, int32_t l, int32_t *threads);
+/* Set it (64, 128, 256, 512 or 1024), e.g. to pin a launch shape. A row's
+ * sum does not depend on the workgroup it falls in, so results are bitwise
+ * the same for every choice. BAMG_E_ARG for another value, or once GMRES has
+ * captured the V-cycle into a graph (use_graph = 1). */
+bamg_status bamg_level_set_threads(bamg_handle *h, int32_t l, int32_t threads);
 
 /* Kernel timing with HIP events on the launch stream. Kernel
  * BAMG_PROFILE_FINEST_SWEEP: the weighted-Jacobi sweep on the finest level

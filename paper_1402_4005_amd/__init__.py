@@ -113,6 +113,8 @@ def lib():
         L.bamg_vcycle_bytes.argtypes = [V, V]
         L.bamg_level_lanes.argtypes = [V, C.c_int32, P(C.c_int32)]
         L.bamg_level_set_lanes.argtypes = [V, C.c_int32, C.c_int32]
+        L.bamg_level_threads.argtypes = [V, C.c_int32, P(C.c_int32)]
+        L.bamg_level_set_threads.argtypes = [V, C.c_int32, C.c_int32]
         L.bamg_kernel_profile_begin.argtypes = [V, C.c_int32]
         L.bamg_kernel_profile_end.argtypes = [V, V, V, V]
         L.bamg_destroy.argtypes = [V]
@@ -439,6 +441,16 @@ class Hierarchy:
     def set_lanes(self, l, lanes):
         """Pin the lanes per row (1, 2, 4) of level l's sweeps and residual."""
         _check(lib().bamg_level_set_lanes(self.h, l, lanes))
+
+    def threads(self, l):
+        """Workgroup size of level l's sweeps and residual."""
+        v = C.c_int32()
+        _check(lib().bamg_level_threads(self.h, l, C.byref(v)))
+        return v.value
+
+    def set_threads(self, l, threads):
+        """Pin the workgroup size (64 ... 1024) of level l's sweeps and residual."""
+        _check(lib().bamg_level_set_threads(self.h, l, threads))
 
     def profile_begin(self, kernel=0):
         _check(lib().bamg_kernel_profile_begin(self.h, kernel))

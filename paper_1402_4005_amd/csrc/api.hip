@@ -646,6 +646,21 @@ bamg_status bamg_level_set_lanes(bamg_handle *h, int32_t l, int32_t lanes) {
   return BAMG_OK;
 }
 
+bamg_status bamg_level_threads(const bamg_handle *h, int32_t l, int32_t *threads) {
+  if (!h || !threads || l < 0 || l >= h->L - 1) return BAMG_E_ARG;
+  *threads = h->lv[l].threads > 0 ? h->lv[l].threads : 256;
+  return BAMG_OK;
+}
+
+bamg_status bamg_level_set_threads(bamg_handle *h, int32_t l, int32_t threads) {
+  if (!h || l < 0 || l >= h->L - 1) return BAMG_E_ARG;
+  if (threads != 64 && threads != 128 && threads != 256 && threads != 512 && threads != 1024)
+    return BAMG_E_ARG;
+  if (h->vc_exec) return BAMG_E_ARG;  // a captured V-cycle keeps its launches
+  h->lv[l].threads = threads;
+  return BAMG_OK;
+}
+
 bamg_status bamg_kernel_profile_begin(bamg_handle *h, int32_t kernel) {
   if (!h || kernel != BAMG_PROFILE_FINEST_SWEEP) return BAMG_E_ARG;
   h->prof_kernel = kernel;

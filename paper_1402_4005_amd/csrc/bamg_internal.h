@@ -87,6 +87,7 @@ struct Level {
   std::vector<int> offB, offBt;                 // host: colour segment offsets
   void *rowinvB = nullptr, *rowinvBt = nullptr; // 1/||row||^2
   int lanes = 0;                                // lanes per CSR row (0 = from nnz/row)
+  int threads = 0;                              // sweep workgroup size (0 = 256)
   // learned interpolation: F points (ascending) and recorded cycle-1 features
   int *fpts = nullptr;
   int nF = -1;
@@ -160,23 +161,26 @@ void transpose_pattern(Pool &pool, const Csr &A, Csr &At, int *&perm, hipStream_
 void diag_positions(const Csr &A, int *dpos, hipStream_t s);  // -1 if absent
 void philox_testvecs(void *U, void *V, int prec, int n, int r, uint64_t seed, hipStream_t s);
 
-// ---- launchers: sparse kernels on vectors (k_sparse.hip)
+// ---- launchers: sparse kernels on vectors (k_sparse.hip); lanes per CSR row
+// (0: from the average row length) and threads per workgroup (0: 256; the
+// tuner's choice for a level's sweeps), neither of which changes a result
 // y = A x (mode 0), y = b - A x (mode 1), y = y + A x (mode 2)
 template <class T>
 void spmv(const Csr &A, const T *val, const T *x, T *y, const T *b, int mode, int lanes,
-          hipStream_t s);
+          hipStream_t s, int threads = 0);
 // x_out = x_in + omega dinv (b - A x_in); x_in == nullptr means x_in = 0
 template <class T>
 void jacobi(const Csr &A, const T *val, const T *dinv, T omega, const T *b, const T *xin, T *xout,
-            int lanes, hipStream_t s);
+            int lanes, hipStream_t s, int threads = 0);
 template <class T>
 void jacobi2_from_zero(const Csr &A, const T *val, const T *dinv, T omega, const T *b, T *xout,
-                       int lanes, hipStream_t s);  // two sweeps from x = 0
+                       int lanes, hipStream_t s, int threads = 0);  // two sweeps from x = 0
 // GMRES products (FP64): y1 = y2 = A x; and v = w scal[0], y1 = y2 = A v
 void spmv_dual(const Csr &A, const double *val, const double *x, double *y1, double *y2,
-               int lanes, hipStream_t s);
+               int lanes, hipStream_t s, int threads = 0);
 void spmv_dual_scaled(const Csr &A, const double *val, const double *w, const double *scal,
-                      double *v, double *y1, double *y2, int lanes, hipStream_t s);
+                      double *v, double *y1, double *y2, int lanes, hipStream_t s,
+                      int threads = 0);
 // Kaczmarz sweep over one colour segment (in place)
 template <class T>
 void kaczmarz_colour(const Csr &A, const T *val, const T *rowinv, const int *rows, int nrows,
@@ -347,9 +351,10 @@ bool vcycle_last_level(bamg_handle *h, int l, const T *b, T *x, hipStream_t s);
 template <class T>
 int last_level_lanes(const bamg_handle *h, int l);
 
-// lanes per CSR row for a level's sweeps, by timing (tune.hip)
+// lanes per CSR row and workgroup size of a level's sweeps, by timing
+// (tune.hip); sets L.lanes and L.threads
 template <class T>
-int tune_lanes(Pool &pool, const Level &L, hipStream_t s);
+void tune_sweeps(Pool &pool, Level &L, hipStream_t s);
 
 // learned interpolation weights (k_mlp.hip)
 void mlp_refresh_bf16(bamg_mlp *m, hipStream_t s);

@@ -123,9 +123,12 @@ void import_all(bamg_handle *h, int nlev, const bamg_level_ops *ops, const doubl
     h->vb = pool.get<float>(n);
     h->vx = pool.get<float>(n);
   }
-  for (int l = 0; l + 1 < h->L; ++l)
-    h->lv[l].lanes = o.autotune ? tune_lanes<T>(pool, h->lv[l], s)
-                                : sweep_lanes_default(h->lv[l].n, h->lv[l].B.nnz);
+  for (int l = 0; l + 1 < h->L; ++l) {
+    if (o.autotune)
+      tune_sweeps<T>(pool, h->lv[l], s);
+    else
+      h->lv[l].lanes = sweep_lanes_default(h->lv[l].n, h->lv[l].B.nnz);
+  }
   // the host arrays are the caller's: every copy ends before the return
   HIPCHK(hipStreamSynchronize(s));
   pool.flush();

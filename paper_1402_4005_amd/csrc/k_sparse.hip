@@ -10,15 +10,16 @@
 
 namespace bamg {
 
-constexpr int kSpThreads = 256;
+constexpr int kSpThreads = 256;      // default workgroup size of the row kernels
+constexpr int kSpMaxThreads = 1024;  // largest the tuner may pick
 
 // y = A x (mode 0), y = b - A x (mode 1), y = y + A x (mode 2)
 template <class T, int LPR>
-__global__ void __launch_bounds__(kSpThreads)
+__global__ void __launch_bounds__(kSpMaxThreads)
     k_spmv(int nr, const int *__restrict__ rp, const int *__restrict__ ci,
            const T *__restrict__ val, const T *__restrict__ x, T *__restrict__ y,
            const T *__restrict__ b, int mode) {
-  const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * kSpThreads + threadIdx.x;
+  const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int row = (int)(gid / LPR), lane = (int)(gid % LPR);
   if (row >= nr) return;  // whole groups leave together
   // row-wise operands are loaded first, beside the row pointers, so their
@@ -37,11 +38,11 @@ __global__ void __launch_bounds__(kSpThreads)
 
 // x_out = x_in + omega dinv (b - A x_in); x_in == nullptr: x_in = 0.
 template <class T, int LPR>
-__global__ void __launch_bounds__(kSpThreads)
+__global__ void __launch_bounds__(kSpMaxThreads)
     k_jacobi(int nr, const int *__restrict__ rp, const int *__restrict__ ci,
              const T *__restrict__ val, const T *__restrict__ dinv, T omega,
              const T *__restrict__ b, const T *__restrict__ xin, T *__restrict__ xout) {
-  const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * kSpThreads + threadIdx.x;
+  const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int row = (int)(gid / LPR), lane = (int)(gid % LPR);
   if (row >= nr) return;
   if (xin == nullptr) {
@@ -59,11 +60,11 @@ __global__ void __launch_bounds__(kSpThreads)
 // result equals two separate sweeps bit for bit), then
 // x2 = x1 + omega dinv (b - A x1).
 template <class T, int LPR>
-__global__ void __launch_bounds__(kSpThreads)
+__global__ void __launch_bounds__(kSpMaxThreads)
     k_jacobi2(int nr, const int *__restrict__ rp, const int *__restrict__ ci,
               const T *__restrict__ val, const T *__restrict__ dinv, T omega,
               const T *__restrict__ b, T *__restrict__ xout) {
-  const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * kSpThreads + threadIdx.x;
+  const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int row = (int)(gid / LPR), lane = (int)(gid % LPR);
   if (row >= nr) return;
   const T dr = dinv[row], br = b[row];  // issued beside the row pointers
@@ -80,46 +81,46 @@ int lanes_for(int nr, int nnz) {
 }
 static int pick_lanes(int nr, int nnz) { return lanes_for(nr, nnz); }
 
-#define BAMG_LPR_SWITCH(LANES, KERNEL, GRIDROWS, ...)                                        \
+#define BAMG_LPR_SWITCH(LANES, THREADS, KERNEL, GRIDROWS, ...)                               \
   do {                                                                                       \
-    const int lpr_ = (LANES);                                                                \
+    const int lpr_ = (LANES), nt_ = (THREADS) > 0 ? (THREADS) : kSpThreads;                  \
     const long thr_ = (long)(GRIDROWS) * lpr_;                                               \
-    const int nb_ = ceil_div(thr_, kSpThreads);                                              \
+    const int nb_ = ceil_div(thr_, nt_);                                                     \
     switch (lpr_) {                                                                          \
-      case 1: KERNEL<T, 1><<<nb_, kSpThreads, 0, s>>>(__VA_ARGS__); break;                   \
-      case 2: KERNEL<T, 2><<<nb_, kSpThreads, 0, s>>>(__VA_ARGS__); break;                   \
-      case 4: KERNEL<T, 4><<<nb_, kSpThreads, 0, s>>>(__VA_ARGS__); break;                   \
-      case 8: KERNEL<T, 8><<<nb_, kSpThreads, 0, s>>>(__VA_ARGS__); break;                   \
-      case 16: KERNEL<T, 16><<<nb_, kSpThreads, 0, s>>>(__VA_ARGS__); break;                 \
-      case 32: KERNEL<T, 32><<<nb_, kSpThreads, 0, s>>>(__VA_ARGS__); break;                 \
-      default: KERNEL<T, 64><<<nb_, kSpThreads, 0, s>>>(__VA_ARGS__); break;                 \
+      case 1: KERNEL<T, 1><<<nb_, nt_, 0, s>>>(__VA_ARGS__); break;                          \
+      case 2: KERNEL<T, 2><<<nb_, nt_, 0, s>>>(__VA_ARGS__); break;                          \
+      case 4: KERNEL<T, 4><<<nb_, nt_, 0, s>>>(__VA_ARGS__); break;                          \
+      case 8: KERNEL<T, 8><<<nb_, nt_, 0, s>>>(__VA_ARGS__); break;                          \
+      case 16: KERNEL<T, 16><<<nb_, nt_, 0, s>>>(__VA_ARGS__); break;                        \
+      case 32: KERNEL<T, 32><<<nb_, nt_, 0, s>>>(__VA_ARGS__); break;                        \
+      default: KERNEL<T, 64><<<nb_, nt_, 0, s>>>(__VA_ARGS__); break;                        \
     }                                                                                        \
     LAUNCHCHK();                                                                             \
   } while (0)
 
 template <class T>
 void spmv(const Csr &A, const T *val, const T *x, T *y, const T *b, int mode, int lanes,
-          hipStream_t s) {
+          hipStream_t s, int threads) {
   if (A.nr <= 0) return;
   if (lanes <= 0) lanes = pick_lanes(A.nr, A.nnz);
-  BAMG_LPR_SWITCH(lanes, k_spmv, A.nr, A.nr, A.rp, A.ci, val, x, y, b, mode);
+  BAMG_LPR_SWITCH(lanes, threads, k_spmv, A.nr, A.nr, A.rp, A.ci, val, x, y, b, mode);
 }
 
 template <class T>
 void jacobi(const Csr &A, const T *val, const T *dinv, T omega, const T *b, const T *xin, T *xout,
-            int lanes, hipStream_t s) {
+            int lanes, hipStream_t s, int threads) {
   if (A.nr <= 0) return;
   if (lanes <= 0) lanes = pick_lanes(A.nr, A.nnz);
   if (xin == nullptr) lanes = 1;
-  BAMG_LPR_SWITCH(lanes, k_jacobi, A.nr, A.nr, A.rp, A.ci, val, dinv, omega, b, xin, xout);
+  BAMG_LPR_SWITCH(lanes, threads, k_jacobi, A.nr, A.nr, A.rp, A.ci, val, dinv, omega, b, xin, xout);
 }
 
 template <class T>
 void jacobi2_from_zero(const Csr &A, const T *val, const T *dinv, T omega, const T *b, T *xout,
-                       int lanes, hipStream_t s) {
+                       int lanes, hipStream_t s, int threads) {
   if (A.nr <= 0) return;
   if (lanes <= 0) lanes = pick_lanes(A.nr, A.nnz);
-  BAMG_LPR_SWITCH(lanes, k_jacobi2, A.nr, A.nr, A.rp, A.ci, val, dinv, omega, b, xout);
+  BAMG_LPR_SWITCH(lanes, threads, k_jacobi2, A.nr, A.nr, A.rp, A.ci, val, dinv, omega, b, xout);
 }
 
 // GMRES products on the finest level (FP64), with the level's lanes per row:
@@ -127,11 +128,11 @@ void jacobi2_from_zero(const Csr &A, const T *val, const T *dinv, T omega, const
 // same with x = w * scal[0] formed where it is gathered and stored as v
 // (the next Arnoldi basis vector).
 template <class T, int LPR>
-__global__ void __launch_bounds__(kSpThreads)
+__global__ void __launch_bounds__(kSpMaxThreads)
     k_spmv_dual(int nr, const int *__restrict__ rp, const int *__restrict__ ci,
                 const T *__restrict__ val, const T *__restrict__ x, T *__restrict__ y1,
                 T *__restrict__ y2) {
-  const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * kSpThreads + threadIdx.x;
+  const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int row = (int)(gid / LPR), lane = (int)(gid % LPR);
   if (row >= nr) return;
   const T sum = row_sum<T, LPR>(rp[row], rp[row + 1], lane, ci, val, [&](int c) { return x[c]; });
@@ -142,12 +143,12 @@ __global__ void __launch_bounds__(kSpThreads)
 }
 
 template <class T, int LPR>
-__global__ void __launch_bounds__(kSpThreads)
+__global__ void __launch_bounds__(kSpMaxThreads)
     k_spmv_dual_scaled(int nr, const int *__restrict__ rp, const int *__restrict__ ci,
                        const T *__restrict__ val, const T *__restrict__ w,
                        const T *__restrict__ scal, T *__restrict__ v, T *__restrict__ y1,
                        T *__restrict__ y2) {
-  const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * kSpThreads + threadIdx.x;
+  const long gid = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int row = (int)(gid / LPR), lane = (int)(gid % LPR);
   if (row >= nr) return;
   const T sc = scal[0], wr = w[row];
@@ -161,19 +162,19 @@ __global__ void __launch_bounds__(kSpThreads)
 }
 
 void spmv_dual(const Csr &A, const double *val, const double *x, double *y1, double *y2,
-               int lanes, hipStream_t s) {
+               int lanes, hipStream_t s, int threads) {
   using T = double;
   if (A.nr <= 0) return;
   if (lanes <= 0) lanes = pick_lanes(A.nr, A.nnz);
-  BAMG_LPR_SWITCH(lanes, k_spmv_dual, A.nr, A.nr, A.rp, A.ci, val, x, y1, y2);
+  BAMG_LPR_SWITCH(lanes, threads, k_spmv_dual, A.nr, A.nr, A.rp, A.ci, val, x, y1, y2);
 }
 
 void spmv_dual_scaled(const Csr &A, const double *val, const double *w, const double *scal,
-                      double *v, double *y1, double *y2, int lanes, hipStream_t s) {
+                      double *v, double *y1, double *y2, int lanes, hipStream_t s, int threads) {
   using T = double;
   if (A.nr <= 0) return;
   if (lanes <= 0) lanes = pick_lanes(A.nr, A.nnz);
-  BAMG_LPR_SWITCH(lanes, k_spmv_dual_scaled, A.nr, A.nr, A.rp, A.ci, val, w, scal, v, y1, y2);
+  BAMG_LPR_SWITCH(lanes, threads, k_spmv_dual_scaled, A.nr, A.nr, A.rp, A.ci, val, w, scal, v, y1, y2);
 }
 
 // Kaczmarz row projections x <- x + (b_i - A_i x) / ||A_i||^2 A_i^T for the
@@ -240,11 +241,11 @@ void dot_partials(const double *x, const double *y, int n, double *part, int nbl
 
 #define INST(T)                                                                              \
   template void spmv<T>(const Csr &, const T *, const T *, T *, const T *, int, int,         \
-                        hipStream_t);                                                        \
+                        hipStream_t, int);                                                   \
   template void jacobi<T>(const Csr &, const T *, const T *, T, const T *, const T *, T *,   \
-                          int, hipStream_t);                                                 \
+                          int, hipStream_t, int);                                            \
   template void jacobi2_from_zero<T>(const Csr &, const T *, const T *, T, const T *, T *,   \
-                                     int, hipStream_t);                                      \
+                                     int, hipStream_t, int);                                 \
   template void kaczmarz_colour<T>(const Csr &, const T *, const T *, const int *, int,      \
                                    const T *, T *, hipStream_t);                             \
   template void coarse_gemv<T>(const double *, int, const T *, T *, hipStream_t, int);

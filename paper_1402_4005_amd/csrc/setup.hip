@@ -539,9 +539,12 @@ void setup_all(bamg_handle *h, const bamg_csr *A, const bamg_geometry *geom) {
   normalize_sum(h->x0, n, part, nb, fl, s);
   pool.release(part);
   pool.release(fl);
-  for (int l = 0; l + 1 < h->L; ++l)
-    h->lv[l].lanes = o.autotune ? tune_lanes<T>(pool, h->lv[l], s)
-                                : sweep_lanes_default(h->lv[l].n, h->lv[l].B.nnz);
+  for (int l = 0; l + 1 < h->L; ++l) {
+    if (o.autotune)
+      tune_sweeps<T>(pool, h->lv[l], s);
+    else
+      h->lv[l].lanes = sweep_lanes_default(h->lv[l].n, h->lv[l].B.nnz);
+  }
   h->join_validation(true);
   st = h->validation_result();
   if (st != BAMG_OK) fail(st, "transition matrix rejected");

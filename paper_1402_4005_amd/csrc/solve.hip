@@ -49,9 +49,11 @@ void smooth_steps(bamg_handle *h, Level &L, const T *b, T *x, int steps, bool fr
     const int done = steps >= 2 ? 2 : 1;
     T *first = ((steps - done) % 2 == 0) ? x : spare;
     if (done == 2)
-      jacobi2_from_zero<T>(L.B, (const T *)L.Bv, (const T *)L.dinv, om, b, first, L.lanes, s);
+      jacobi2_from_zero<T>(L.B, (const T *)L.Bv, (const T *)L.dinv, om, b, first, L.lanes, s,
+                        L.threads);
     else
-      jacobi<T>(L.B, (const T *)L.Bv, (const T *)L.dinv, om, b, nullptr, first, L.lanes, s);
+      jacobi<T>(L.B, (const T *)L.Bv, (const T *)L.dinv, om, b, nullptr, first, L.lanes, s,
+                L.threads);
     cur = first;
     oth = first == x ? spare : x;
     steps -= done;
@@ -64,7 +66,7 @@ void smooth_steps(bamg_handle *h, Level &L, const T *b, T *x, int steps, bool fr
   const bool prof = h->prof_kernel == BAMG_PROFILE_FINEST_SWEEP && &L == &h->lv[0] && steps > 0;
   if (prof) profile_mark(h, s, true);
   for (int it = 0; it < steps; ++it) {
-    jacobi<T>(L.B, (const T *)L.Bv, (const T *)L.dinv, om, b, cur, oth, L.lanes, s);
+    jacobi<T>(L.B, (const T *)L.Bv, (const T *)L.dinv, om, b, cur, oth, L.lanes, s, L.threads);
     std::swap(cur, oth);
   }
   if (prof) {
@@ -102,7 +104,7 @@ void cycle_level(bamg_handle *h, int l, int type, const T *b, T *x, bool x_zero,
   if (!x_zero && jac && nu1 % 2 == 1)  // an odd count from a guess starts in the spare buffer
     HIPCHK(hipMemcpyAsync(L.tb, x, sizeof(T) * L.n, hipMemcpyDeviceToDevice, s));
   smooth_steps<T>(h, L, b, x, nu1, x_zero, s);
-  spmv<T>(L.B, (const T *)L.Bv, x, (T *)L.rb, b, 1, L.lanes, s);          // r = b - B x
+  spmv<T>(L.B, (const T *)L.Bv, x, (T *)L.rb, b, 1, L.lanes, s, L.threads);  // r = b - B x
   spmv<T>(L.Pc, (const T *)L.Qv, (const T *)L.rb, (T *)C.bb, nullptr, 0, 0, s);  // b_c = Q r
   cycle_level<T>(h, l + 1, type, (const T *)C.bb, (T *)C.xb, true, s);
   if (type == BAMG_CYCLE_W)
@@ -247,7 +249,7 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
     HIPCHK(hipMemcpyAsync(h->gx0, h->x0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
 
   const Csr &B = L0.B;
-  const int lanes = L0.lanes;
+  const int lanes = L0.lanes, threads = L0.threads;
   double *hf = h->hred;
   auto read_flags = [&]() {
     HIPCHK(hipMemcpyAsync(hf, flags, sizeof(double) * 16, hipMemcpyDeviceToHost, s));
@@ -255,7 +257,7 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
   };
 
   // initial test on x0
-  spmv<double>(B, h->B64, h->gx0, h->gbx0, nullptr, 0, lanes, s);
+  spmv<double>(B, h->B64, h->gx0, h->gbx0, nullptr, 0, lanes, s, threads);
   residual_check_partials(h->gx0, h->gbx0, h->gV, h->gBV, c1, n, 0, part3, nblk, s);
   residual_check_finalize(part3, nblk, tol, flags, nullptr, s);
   read_flags();
@@ -263,7 +265,7 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
   double rel = hf[2];
   bamg_status st = BAMG_OK;
   while (!conv && it < maxit) {
-    spmv<double>(B, h->B64, h->gx0, h->gbx0, nullptr, 0, lanes, s);  // B x0
+    spmv<double>(B, h->B64, h->gx0, h->gbx0, nullptr, 0, lanes, s, threads);  // B x0
     negate_copy(h->gbx0, h->vcin, n, s);                              // r0 = -B x0
     precondition_fixed(h, s);                                         // z = C r0
     multi_dot(h->gV, n, 0, h->gw, part, nblk, s);
@@ -283,9 +285,10 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
     auto enqueue = [&](int j) {
       double *vj = h->gV + (size_t)j * n, *bvj = h->gBV + (size_t)j * n;
       if (j == 0)
-        spmv_dual(B, h->B64, vj, bvj, h->vcin, lanes, s);  // B v_0
+        spmv_dual(B, h->B64, vj, bvj, h->vcin, lanes, s, threads);  // B v_0
       else
-        spmv_dual_scaled(B, h->B64, h->gw, flags + 3, vj, bvj, h->vcin, lanes, s);  // v_j, B v_j
+        spmv_dual_scaled(B, h->B64, h->gw, flags + 3, vj, bvj, h->vcin, lanes, s,
+                         threads);  // v_j, B v_j
       precondition_fixed(h, s);  // w = C B v_j
       // Gram-Schmidt, twice; the first update and the second pass's dots in one kernel
       multi_dot(h->gV, n, j + 1, h->gw, part, nblk, s);

@@ -1,16 +1,20 @@
-// Autotuner for the row-parallel sweeps of the V-cycle: the number of lanes
-// that share one CSR row (1, 2 or 4) is chosen per level by timing a few
-// weighted-Jacobi sweeps of the level's own matrix with HIP events, once per
-// (device, rows, nonzeros, value type); the choice is cached for the life of
-// the process. The sweeps sum each row in one fixed order whatever the lane
-// count (k_sparse.hip, row_dot), so the choice changes the speed only, never
-// a bit of the result. Candidates are tried from the fewest lanes up, and a
-// wider one replaces the choice only when at least 3% faster, so near-ties
+// Autotuner for the row-parallel sweeps of the V-cycle. Two choices per
+// level, found by timing a few weighted-Jacobi sweeps of the level's own
+// matrix with HIP events, once per (device, rows, nonzeros, value type) and
+// cached for the life of the process:
+//  * lanes per CSR row (1, 2 or 4): the sweeps sum each row in one fixed
+//    order whatever the lane count (sparse_row.h, row_dot);
+//  * workgroup size (128, 256, 512 or 1024 threads): a row's work does not
+//    depend on the workgroup it falls in;
+// so the choices change the speed only, never a bit of the result. The
+// candidates are tried in a fixed order (the defaults first), and a later
+// one replaces the choice only when at least 3% faster, so near-ties
 // (within timing noise) usually resolve the same way in every process.
 #include <algorithm>
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <utility>
 
 #include "bamg_internal.h"
 
@@ -18,18 +22,22 @@ namespace bamg {
 
 namespace {
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int>, int> g_tune;
+std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_tune;
 }  // namespace
 
 template <class T>
-int tune_lanes(Pool &pool, const Level &L, hipStream_t s) {
+void tune_sweeps(Pool &pool, Level &L, hipStream_t s) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   const auto key = std::make_tuple(dev, L.n, L.B.nnz, (int)sizeof(T));
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune.find(key);
-    if (it != g_tune.end()) return it->second;
+    if (it != g_tune.end()) {
+      L.lanes = it->second.first;
+      L.threads = it->second.second;
+      return;
+    }
   }
   const int avg = L.n ? (L.B.nnz + L.n - 1) / L.n : 1;
   int base = 1;
@@ -40,24 +48,36 @@ int tune_lanes(Pool &pool, const Level &L, hipStream_t s) {
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  int best = std::min(base, kMaxTunedLanes);
+  int best = std::min(base, kMaxTunedLanes), best_threads = 256;
   float best_ms = 1e30f;
   const T om = (T)0.7;
-  for (int lanes = std::max(1, base / 8); lanes <= std::min(kMaxTunedLanes, base * 2);
-       lanes <<= 1) {
-    jacobi<T>(L.B, (const T *)L.Bv, (const T *)L.dinv, om, b, x, y, lanes, s);  // warm
+  auto time_of = [&](int lanes, int threads) {
+    jacobi<T>(L.B, (const T *)L.Bv, (const T *)L.dinv, om, b, x, y, lanes, s, threads);  // warm
     HIPCHK(hipEventRecord(e0, s));
     for (int it = 0; it < 4; ++it) {
-      jacobi<T>(L.B, (const T *)L.Bv, (const T *)L.dinv, om, b, x, y, lanes, s);
-      jacobi<T>(L.B, (const T *)L.Bv, (const T *)L.dinv, om, b, y, x, lanes, s);
+      jacobi<T>(L.B, (const T *)L.Bv, (const T *)L.dinv, om, b, x, y, lanes, s, threads);
+      jacobi<T>(L.B, (const T *)L.Bv, (const T *)L.dinv, om, b, y, x, lanes, s, threads);
     }
     HIPCHK(hipEventRecord(e1, s));
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    return ms;
+  };
+  // lanes at the default workgroup size, then the workgroup size at those lanes
+  for (int lanes = std::max(1, base / 8); lanes <= std::min(kMaxTunedLanes, base * 2);
+       lanes <<= 1) {
+    const float ms = time_of(lanes, 256);
     if (ms < 0.97f * best_ms) {
       best_ms = ms;
       best = lanes;
+    }
+  }
+  for (int threads : {128, 512, 1024}) {
+    const float ms = time_of(best, threads);
+    if (ms < 0.97f * best_ms) {
+      best_ms = ms;
+      best_threads = threads;
     }
   }
   (void)hipEventDestroy(e0);
@@ -65,12 +85,13 @@ int tune_lanes(Pool &pool, const Level &L, hipStream_t s) {
   pool.release(b);
   pool.release(x);
   pool.release(y);
+  L.lanes = best;
+  L.threads = best_threads;
   std::lock_guard<std::mutex> g(g_tune_mu);
-  g_tune.emplace(key, best);
-  return best;
+  g_tune.emplace(key, std::make_pair(best, best_threads));
 }
 
-template int tune_lanes<double>(Pool &, const Level &, hipStream_t);
-template int tune_lanes<float>(Pool &, const Level &, hipStream_t);
+template void tune_sweeps<double>(Pool &, Level &, hipStream_t);
+template void tune_sweeps<float>(Pool &, Level &, hipStream_t);
 
 }  // namespace bamg

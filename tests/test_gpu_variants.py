@@ -157,9 +157,10 @@ def test_graph_replay_equals_direct_launches():
 @pytest.mark.parametrize("name", ["delaunay20000", "tandem65"])
 def test_results_bitwise_independent_of_lanes_per_row(name):
     """The V-cycle sweeps and residuals sum every row in one fixed order
-    whatever the number of lanes sharing it, so the lanes an autotuner picks
-    (timing-dependent, per process) never change a bit: one V-cycle and a
-    whole GMRES solve are bitwise equal for 1, 2 and 4 lanes on every
+    whatever the number of lanes sharing it and whatever workgroup it falls
+    in, so the lanes and workgroup sizes an autotuner picks (timing-dependent,
+    per process) never change a bit: one V-cycle and a whole GMRES solve are
+    bitwise equal for 1, 2 and 4 lanes and 64 to 1024 threads on every
     level."""
     import torch
     if name == "delaunay20000":
@@ -171,9 +172,12 @@ def test_results_bitwise_independent_of_lanes_per_row(name):
     h = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, autotune=0, fuse_last_level=0, **kw))
     b = torch.from_numpy(np.random.default_rng(3).standard_normal(ch.n)).cuda()
     ref_v, ref_x = None, None
-    for lanes in (1, 2, 4):
+    # lanes per row, then workgroup sizes (the tuner's two choices)
+    for lanes, threads in ((1, 256), (2, 256), (4, 256), (4, 64), (1, 1024), (2, 512)):
         for l in range(h.levels - 1):
             h.set_lanes(l, lanes)
+            h.set_threads(l, threads)
+            assert h.threads(l) == threads
         v = h.vcycle(b).cpu().numpy()
         x, info = h.gmres(restart=20, tol=1e-12, maxit=300)
         x = x.cpu().numpy()
