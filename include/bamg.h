@@ -98,7 +98,14 @@ typedef struct {
   int32_t interp_rule;  /* 0 = plain LS over J_i, 1 = LS with negative weights removed */
   int32_t validate;     /* 1 = check stochasticity and strong connectivity; 2 = the
                            same with the search's visited set in global memory
-                           whatever the size (the form large chains take) */
+                           whatever the size (the form large chains take); 3 = the
+                           check of 1, not waited for by bamg_setup: the
+                           strong-connectivity search keeps running beside the
+                           hierarchy and the first bamg_gmres_solve or bamg_vcycle
+                           waits for it at its end and returns BAMG_E_REDUCIBLE or
+                           BAMG_E_NOT_STOCHASTIC instead of its result when the
+                           chain fails (bamg_setup still reports them when it fails
+                           itself); 0 = no check */
   int32_t use_graph;    /* 1 = GMRES replays the V-cycle from a captured HIP graph;
                            0 (default) = its kernels are launched one by one (the
                            host enqueues an iteration ahead, and on MI355X a graph

@@ -147,6 +147,18 @@ void bamg_handle::join_validation(bool wait_main) {
   aux_ready = aux_done = nullptr;
 }
 
+int bamg_handle::finish_validation() {
+  if (!aux) return vstatus;
+  join_validation(true);
+  vstatus = validation_result();
+  if (vvisited) pool.release(vvisited);
+  if (vqueues) pool.release(vqueues);
+  vvisited = nullptr;
+  vqueues = nullptr;
+  pool.flush();
+  return vstatus;
+}
+
 // Outcome of the input validation (BAMG_OK when it was not requested).
 int bamg_handle::validation_result() {
   if (!vflag) return BAMG_OK;
@@ -246,7 +258,7 @@ static bamg_status check_options(const bamg_options *o) {
   if (o->smoother != BAMG_SMOOTH_JACOBI && o->smoother != BAMG_SMOOTH_KACZMARZ) return BAMG_E_ARG;
   if (o->precision != BAMG_PRECISION_FP64 && o->precision != BAMG_PRECISION_MIXED) return BAMG_E_ARG;
   if (o->interp_rule != 0 && o->interp_rule != 1) return BAMG_E_ARG;
-  if (o->validate < 0 || o->validate > 2) return BAMG_E_ARG;
+  if (o->validate < 0 || o->validate > 3) return BAMG_E_ARG;
   if (o->cycle < BAMG_CYCLE_V || o->cycle > BAMG_CYCLE_NONE) return BAMG_E_ARG;
   if (o->mu < 1 || o->mu > 8) return BAMG_E_ARG;
   if (o->restriction != 0 && o->restriction != 1) return BAMG_E_ARG;
@@ -365,10 +377,29 @@ bamg_status bamg_setup_from_levels(int32_t nlevels, const bamg_level_ops *levels
   return BAMG_OK;
 }
 
+// A validation still running beside the hierarchy (validate = 3) is joined
+// when a computation on it ends; its failure replaces that result.
+static bamg_status with_validation(bamg_handle *h, bamg_status st) {
+  const int vst = h->finish_validation();
+  if (vst != BAMG_OK) {
+    g_last_error = "transition matrix rejected";
+    return (bamg_status)vst;
+  }
+  return st;
+}
+
+static bamg_status vcycle_impl(bamg_handle *h, const void *b, void *x, int32_t dtype,
+                               void *hip_stream);
+
 bamg_status bamg_vcycle(bamg_handle *h, const void *b, void *x, int32_t dtype, void *hip_stream) {
   if (!h || !b || !x || b == x) return BAMG_E_ARG;
   if (dtype != BAMG_DTYPE_F64 && dtype != BAMG_DTYPE_F32) return BAMG_E_ARG;
   if (dtype == BAMG_DTYPE_F32 && h->prec == 0) return BAMG_E_ARG;
+  return with_validation(h, vcycle_impl(h, b, x, dtype, hip_stream));
+}
+
+static bamg_status vcycle_impl(bamg_handle *h, const void *b, void *x, int32_t dtype,
+                               void *hip_stream) {
   BAMG_TRY
   hipStream_t s = (hipStream_t)hip_stream;
   const int n = h->lv[0].n;
@@ -422,10 +453,20 @@ void rebuild_exact(bamg_handle *h, hipStream_t s) {
 
 }  // namespace
 
+static bamg_status gmres_impl(bamg_handle *h, void *x, int32_t restart, double tol,
+                              int32_t max_iters, int32_t use_x0, bamg_solve_info *info,
+                              void *hip_stream);
+
 bamg_status bamg_gmres_solve(bamg_handle *h, void *x, int32_t restart, double tol,
                              int32_t max_iters, int32_t use_x0, bamg_solve_info *info,
                              void *hip_stream) {
   if (!h || !x || restart < 1 || restart > 255 || max_iters < 0 || !(tol > 0.0)) return BAMG_E_ARG;
+  return with_validation(h, gmres_impl(h, x, restart, tol, max_iters, use_x0, info, hip_stream));
+}
+
+static bamg_status gmres_impl(bamg_handle *h, void *x, int32_t restart, double tol,
+                              int32_t max_iters, int32_t use_x0, bamg_solve_info *info,
+                              void *hip_stream) {
   BAMG_TRY
   hipStream_t s = (hipStream_t)hip_stream;
   bamg_solve_info local{};
@@ -466,6 +507,9 @@ bamg_status bamg_gmres_solve(bamg_handle *h, void *x, int32_t restart, double to
     }
     *inf = cur;
     if (!more) break;
+    // the rebuilt handle replaces this one: settle a validation still running
+    const int vst = h->finish_validation();
+    if (vst != BAMG_OK) fail(vst, "transition matrix rejected");
     rebuild_exact(h, s);
     fell_back = true;
   }
@@ -810,6 +854,7 @@ bamg_status bamg_learned_stats(const bamg_handle *h, int64_t *mlp_rows, int64_t 
 
 void bamg_destroy(bamg_handle *h) {
   if (!h) return;
+  h->join_validation(true);  // the search may still use the handle's memory
   for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
   if (h->vc_exec) (void)hipGraphExecDestroy(h->vc_exec);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);

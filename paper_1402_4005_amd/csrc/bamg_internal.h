@@ -142,8 +142,14 @@ struct bamg_handle {
   hipEvent_t aux_ready = nullptr, aux_done = nullptr;
   int *lcount = nullptr;  // device: [MLP rows, LS fallback rows]
   int *vflag = nullptr;  // device: [colsum bits, reached forward, reached backward, -]
+  unsigned *vvisited = nullptr;  // the search's buffers, released after the join
+  int *vqueues = nullptr;
+  int vstatus = BAMG_OK;         // outcome once joined
   void join_validation(bool wait_main);
   int validation_result();
+  // join a validation still running (validate = 3: after the setup), keep
+  // and return its outcome
+  int finish_validation();
 };
 
 namespace bamg {

@@ -106,6 +106,10 @@ __global__ void k_colsum_check(const int *__restrict__ trp, const int *__restric
 // updated by compare-and-swap (16.8 MB per direction at 4.2 M states) sent
 // every access to HBM: 122 ms per tandem 2049^2 setup.
 
+// global-bitmap form: hops per level and stack entries per thread; an entry
+// is the state (below 2^26) packed with its depth, and its row range
+constexpr int kReachDepth = 32, kReachStack = 10, kReachStateBits = 26;
+
 template <bool LDSMAP>
 __global__ void __launch_bounds__(1024)
     k_reach2(const int *__restrict__ rp0, const int *__restrict__ ci0,
@@ -127,30 +131,69 @@ __global__ void __launch_bounds__(1024)
   }
   __syncthreads();
   int *cur = qa, *nxt = qb;
+  // With the visited bits in global memory every hop costs dependent memory
+  // round trips, and a frontier level costs two barriers on top. The order
+  // of the search does not matter for the visited set, so there each thread
+  // follows the states it claims depth first, up to kReachDepth hops and
+  // kReachStack pending states (a per-thread stack in LDS), and hands the
+  // rest to the next frontier: far fewer levels. A neighbour's row pointers
+  // are loaded together with the atomic that claims it (used only if the
+  // claim succeeds), so a hop is two dependent round trips, not three.
+  // Every state is claimed once (the atomic bit), so every stack and every
+  // frontier is finite.
+  int *stk = reinterpret_cast<int *>(lbits) + (LDSMAP ? 0 : t * 3 * kReachStack);
+  __shared__ int found;
+  if (t == 0) found = 0;
+  __syncthreads();
   while (cur_n > 0) {
     const int cn = cur_n;
+    int mine = 0;
     for (int idx = t; idx < cn; idx += blockDim.x) {
-      const int v = cur[idx];
-      const int e = rp[v + 1];
-      // four neighbours per round: their indices are loaded together
-      // (positions past the row end reload its last entry and are skipped)
-      for (int k = rp[v]; k < e; k += 4) {
-        int us[4];
+      int sp = 0, d = 0;
+      const int v0 = cur[idx];
+      int kb = rp[v0], ke = rp[v0 + 1];
+      for (;;) {
+        // four neighbours per round: their indices are loaded together
+        // (positions past the row end reload its last entry and are skipped)
+        for (int k = kb; k < ke; k += 4) {
+          int us[4], r0[4], r1[4];
+          unsigned old[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) us[j] = ci[min(k + j, e - 1)];
+          for (int j = 0; j < 4; ++j) us[j] = ci[min(k + j, ke - 1)];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (k + j >= e) break;
-          const int u = us[j];
-          const unsigned m = 1u << (u & 31);
-          const bool fresh = (atomicOr(&bits[u >> 5], m) & m) == 0;
-          if (fresh) nxt[atomicAdd(&nxt_n, 1)] = u;
+          for (int j = 0; j < 4; ++j) {
+            const int u = us[j];
+            old[j] = k + j < ke ? atomicOr(&bits[u >> 5], 1u << (u & 31)) : ~0u;
+            if (!LDSMAP) {
+              r0[j] = rp[u];
+              r1[j] = rp[u + 1];
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int u = us[j];
+            if (k + j >= ke || (old[j] >> (u & 31)) & 1u) continue;
+            ++mine;
+            if (!LDSMAP && d + 1 < kReachDepth && sp < kReachStack) {
+              stk[3 * sp] = u | ((d + 1) << kReachStateBits);
+              stk[3 * sp + 1] = r0[j];
+              stk[3 * sp + 2] = r1[j];
+              ++sp;
+            } else {
+              nxt[atomicAdd(&nxt_n, 1)] = u;
+            }
+          }
         }
+        if (sp == 0) break;
+        --sp;
+        d = stk[3 * sp] >> kReachStateBits;
+        kb = stk[3 * sp + 1];
+        ke = stk[3 * sp + 2];
       }
     }
+    if (mine) atomicAdd(&found, mine);
     __syncthreads();
     if (t == 0) {
-      total += nxt_n;
       cur_n = nxt_n;
       nxt_n = 0;
     }
@@ -159,7 +202,7 @@ __global__ void __launch_bounds__(1024)
     cur = nxt;
     nxt = tmp;
   }
-  if (t == 0) out[b] = total;
+  if (t == 0) out[b] = total + found;
 }
 
 // Launch the reachability search on stream s (the caller's auxiliary
@@ -171,12 +214,16 @@ void reach_launch(const Csr &B, const Csr &Bt, unsigned *visited, int *queues, i
   int dev = 0, maxlds = 65536;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  if (n >= (1 << kReachStateBits)) fail(BAMG_E_ARG, "reachability search: more than 2^26 states");
   if (!force_global && shm + 256 <= (size_t)maxlds) {
     HIPCHK(hipFuncSetAttribute((const void *)k_reach2<true>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     k_reach2<true><<<2, 1024, shm, s>>>(B.rp, B.ci, Bt.rp, Bt.ci, n, visited, queues, flag + 1);
   } else {
-    k_reach2<false><<<2, 1024, 0, s>>>(B.rp, B.ci, Bt.rp, Bt.ci, n, visited, queues, flag + 1);
+    const size_t stk = sizeof(int) * 3 * kReachStack * 1024;  // per-thread stacks
+    HIPCHK(hipFuncSetAttribute((const void *)k_reach2<false>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)stk));
+    k_reach2<false><<<2, 1024, stk, s>>>(B.rp, B.ci, Bt.rp, Bt.ci, n, visited, queues, flag + 1);
   }
   LAUNCHCHK();
 }

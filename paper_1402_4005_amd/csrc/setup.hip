@@ -350,7 +350,8 @@ void setup_all(bamg_handle *h, const bamg_csr *A, const bamg_geometry *geom) {
     if (o.validate) {
       // column sums on the main stream; reachability (a long chain of small
       // dependent steps on two CUs) beside the setup on an auxiliary stream,
-      // joined before bamg_setup returns
+      // joined before bamg_setup returns (validate = 3: by the first
+      // computation on the hierarchy)
       h->vflag = pool.get<int>(4);
       fill_i32(h->vflag, 0, 4, s);
       colsum_launch(L0.Bt, bt64, h->vflag, s);
@@ -363,8 +364,8 @@ void setup_all(bamg_handle *h, const bamg_csr *A, const bamg_geometry *geom) {
       int *queues = pool.get<int>(4 * (size_t)n);
       reach_launch(L0.B, L0.Bt, visited, queues, h->vflag, o.validate == 2, h->aux);
       HIPCHK(hipEventRecord(h->aux_done, h->aux));
-      pool.release(visited);
-      pool.release(queues);
+      h->vvisited = visited;  // released after the join
+      h->vqueues = queues;
     }
     L0.dpos = pool.get<int>(n);
     diag_positions(L0.B, L0.dpos, s);
@@ -545,9 +546,10 @@ void setup_all(bamg_handle *h, const bamg_csr *A, const bamg_geometry *geom) {
     else
       h->lv[l].lanes = sweep_lanes_default(h->lv[l].n, h->lv[l].B.nnz);
   }
-  h->join_validation(true);
-  st = h->validation_result();
-  if (st != BAMG_OK) fail(st, "transition matrix rejected");
+  if (o.validate != 3) {
+    st = h->finish_validation();
+    if (st != BAMG_OK) fail(st, "transition matrix rejected");
+  }
   HIPCHK(hipStreamSynchronize(s));
   pool.flush();
 }

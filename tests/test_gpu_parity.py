@@ -246,6 +246,42 @@ def test_error_codes():
     assert e.value.code == -2
 
 
+def test_deferred_validation():
+    """validate = 3: the strong-connectivity search is joined by the first
+    solve instead of the setup. A valid chain gives bitwise the results of
+    validate = 1 (the V-cycle call joins it as well); the reducible chain of
+    test_reducible_chain_rejected is rejected with BAMG_E_REDUCIBLE, by the
+    setup if that fails first, else by the first solve."""
+    import scipy.sparse as sp
+    import torch
+    ch = chaingen.delaunay_walk(3000, 12)
+    kw = dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99)
+    out = []
+    for validate in (1, 3):
+        h = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, validate=validate, **kw))
+        b = torch.from_numpy(np.random.default_rng(4).standard_normal(ch.n)).cuda()
+        v = h.vcycle(b).cpu().numpy()
+        x, info = h.gmres(restart=20, tol=1e-12, maxit=300)
+        torch.cuda.synchronize()
+        out.append((v, x.cpu().numpy(), info.iterations))
+        h.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    assert out[0][2] == out[1][2]
+    A = sp.lil_matrix((6, 6))
+    for i in range(3):
+        A[(i + 1) % 3, i] = 0.5
+        A[i, i] = 0.5
+        A[3 + (i + 1) % 3, 3 + i] = 0.5
+        A[3 + i, 3 + i] = 0.5
+    bad = chaingen.Chain(A.tocsr())
+    with pytest.raises(bamg.BamgError) as e:
+        h = bamg.Hierarchy.from_chain(bad, bamg.default_options(r=2, coarsening="mis",
+                                                                coarse_max=1, max_levels=2,
+                                                                validate=3))
+        h.gmres(restart=5, tol=1e-10, maxit=20)
+    assert e.value.code == -3
+
+
 def test_reducible_chain_rejected():
     import scipy.sparse as sp
     # two disjoint 3-cycles with self-loops: column stochastic, not irreducible
