@@ -348,6 +348,11 @@ inline int sweep_lanes_default(int nr, int nnz) {
   const int l = lanes_for(nr, nnz);
   return l < kMaxTunedLanes ? l : kMaxTunedLanes;
 }
+// lanes per row of the V-cycle transfers (b_c = Q r, x += P x_c): the same
+// rule, so their row sums take the canonical order too (a row of Q on a
+// 2-D grid holds ~16 entries; 4 lanes of 4 entries each beat 16 lanes of
+// one and a butterfly)
+inline int transfer_lanes(int nr, int nnz) { return sweep_lanes_default(nr, nnz); }
 
 // the V-cycle of the level above the coarsest and the coarsest solve in one
 // workgroup (k_lastlevel.hip); false when the level does not fit (nothing

@@ -13,7 +13,7 @@
 // handle, step for step and in the same summation orders, so a chain's
 // result does not depend on which of the two ran it:
 //  * sweeps and residuals form their row sums canonically (sparse_row.h),
-//    the transfers with the lanes per row the per-step kernels take;
+//    the transfers too (at most 4 lanes per row on both paths);
 //  * the fused last level (one workgroup there too) keeps its W-lane sums;
 //  * GMRES's dot products are formed as the two-stage reductions of the
 //    per-step kernels: each wave here forms the partial of one of their
@@ -98,7 +98,8 @@ __device__ __forceinline__ void csr_rows_lpr(int nr, const int *rp, const int *c
   });
 }
 
-// B-operator rows: canonical sums, so 1, 2 or 4 lanes give the same bits
+// B-operator and transfer rows: canonical sums, so 1, 2 or 4 lanes give the
+// same bits
 template <class T, class G, class O>
 __device__ void csr_rows_canon(int lanes, int nr, const int *rp, const int *ci, const T *val, G g,
                                O out) {
@@ -108,21 +109,6 @@ __device__ void csr_rows_canon(int lanes, int nr, const int *rp, const int *ci, 
     csr_rows_lpr<T, 2>(nr, rp, ci, val, g, out);
   else
     csr_rows_lpr<T, 1>(nr, rp, ci, val, g, out);
-}
-
-// transfer rows: the lanes per row the per-step SpMV takes for the matrix
-template <class T, class G, class O>
-__device__ void csr_rows_any(int lpr, int nr, const int *rp, const int *ci, const T *val, G g,
-                             O out) {
-  switch (lpr) {
-    case 1: csr_rows_lpr<T, 1>(nr, rp, ci, val, g, out); break;
-    case 2: csr_rows_lpr<T, 2>(nr, rp, ci, val, g, out); break;
-    case 4: csr_rows_lpr<T, 4>(nr, rp, ci, val, g, out); break;
-    case 8: csr_rows_lpr<T, 8>(nr, rp, ci, val, g, out); break;
-    case 16: csr_rows_lpr<T, 16>(nr, rp, ci, val, g, out); break;
-    case 32: csr_rows_lpr<T, 32>(nr, rp, ci, val, g, out); break;
-    default: csr_rows_lpr<T, 64>(nr, rp, ci, val, g, out); break;
-  }
 }
 
 // ---------------------------------------------------------------- V-cycle
@@ -296,7 +282,7 @@ __device__ void vcycle(const BatchChain &c, const T *b0, T *x0) {
                       [&](int row, T s) { rb[row] = b[row] - s; });
     wg_sync();
     T *bbc = (T *)C.bb;
-    csr_rows_any<T>(L.qlpr, L.nc, L.qrp, L.qci, (const T *)L.qv,
+    csr_rows_canon<T>(L.qlpr, L.nc, L.qrp, L.qci, (const T *)L.qv,
                     [&](int col) { return rb[col]; }, [&](int row, T s) { bbc[row] = s; });
     wg_sync();
   }
@@ -329,7 +315,7 @@ __device__ void vcycle(const BatchChain &c, const T *b0, T *x0) {
         tb[i] = x[i] + s;
       }
     } else {
-      csr_rows_any<T>(L.plpr, L.n, L.prp, L.pci, pv, [&](int col) { return xcor[col]; },
+      csr_rows_canon<T>(L.plpr, L.n, L.prp, L.pci, pv, [&](int col) { return xcor[col]; },
                       [&](int row, T s) { x[row] = x[row] + s; });
     }
     wg_sync();
@@ -842,11 +828,11 @@ void describe_levels(bamg_handle *h, std::vector<BatchLevel> &out,
       d.prp = L.P.rp;
       d.pci = L.P.ci;
       d.pv = L.Pv;
-      d.plpr = lanes_for(L.P.nr, L.P.nnz);
+      d.plpr = transfer_lanes(L.P.nr, L.P.nnz);
       d.qrp = L.Pc.rp;
       d.qci = L.Pc.ci;
       d.qv = L.Qv;
-      d.qlpr = lanes_for(L.Pc.nr, L.Pc.nnz);
+      d.qlpr = transfer_lanes(L.Pc.nr, L.Pc.nnz);
       if (h->opt.smoother == BAMG_SMOOTH_KACZMARZ) {
         d.ncol = (int)L.offB.size() - 1;
         d.kord = L.ordB;

@@ -105,7 +105,8 @@ void cycle_level(bamg_handle *h, int l, int type, const T *b, T *x, bool x_zero,
     HIPCHK(hipMemcpyAsync(L.tb, x, sizeof(T) * L.n, hipMemcpyDeviceToDevice, s));
   smooth_steps<T>(h, L, b, x, nu1, x_zero, s);
   spmv<T>(L.B, (const T *)L.Bv, x, (T *)L.rb, b, 1, L.lanes, s, L.threads);  // r = b - B x
-  spmv<T>(L.Pc, (const T *)L.Qv, (const T *)L.rb, (T *)C.bb, nullptr, 0, 0, s);  // b_c = Q r
+  spmv<T>(L.Pc, (const T *)L.Qv, (const T *)L.rb, (T *)C.bb, nullptr, 0,
+          transfer_lanes(L.Pc.nr, L.Pc.nnz), s);  // b_c = Q r
   cycle_level<T>(h, l + 1, type, (const T *)C.bb, (T *)C.xb, true, s);
   if (type == BAMG_CYCLE_W)
     cycle_level<T>(h, l + 1, BAMG_CYCLE_W, (const T *)C.bb, (T *)C.xb, false, s);
@@ -117,7 +118,8 @@ void cycle_level(bamg_handle *h, int l, int type, const T *b, T *x, bool x_zero,
                                                           (const T *)C.xb, x, (T *)L.tb);
     LAUNCHCHK();
   } else {
-    spmv<T>(L.P, (const T *)L.Pv, (const T *)C.xb, x, nullptr, 2, 0, s);  // x += P x_c
+    spmv<T>(L.P, (const T *)L.Pv, (const T *)C.xb, x, nullptr, 2, transfer_lanes(L.P.nr, L.P.nnz),
+            s);  // x += P x_c
   }
   smooth_steps<T>(h, L, b, x, nu2, false, s);
 }

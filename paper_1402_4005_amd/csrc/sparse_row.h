@@ -96,9 +96,9 @@ __device__ __forceinline__ T row_dot(int rs, int e, int lane, const int *__restr
   return acc[0];
 }
 
-// Row sum for any LPR: the canonical order up to 4 lanes; wider groups
-// (taken only by the transfers, whose lanes follow from the matrix shape)
-// add their lanes' shares by a butterfly.
+// Row sum for any LPR: the canonical order up to 4 lanes; wider groups (an
+// SpMV whose lanes follow from the row length alone, such as the coarsest
+// level's residual in a W-cycle) add their lanes' shares by a butterfly.
 template <class T, int LPR, class G>
 __device__ __forceinline__ T row_sum(int rs, int e, int lane, const int *__restrict__ ci,
                                      const T *__restrict__ val, G g) {
