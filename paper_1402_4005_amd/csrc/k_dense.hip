@@ -135,6 +135,8 @@ int cholesky2(double *A0, double *A1, int n, int *flag, hipStream_t s) {
 // final, every later row subtracts L[i][k] times it. The columns of L are
 // staged in LDS pw at a time (rows k0..n-1 of columns k0..k0+pw-1, row
 // stride pw + 1), so a step waits on LDS and a workgroup barrier only.
+constexpr int kTrsmStep = 8;
+
 __global__ void __launch_bounds__(1024) k_trsm_slab(const double *__restrict__ L,
                                                     double *__restrict__ X, int n, int ncols,
                                                     int ldx, int sw, int pw) {
@@ -155,11 +157,33 @@ __global__ void __launch_bounds__(1024) k_trsm_slab(const double *__restrict__ L
       lp[(size_t)i * (pw + 1) + j] = L[(size_t)(k0 + i) * n + k0 + j];
     }
     __syncthreads();
-    for (int k = k0; k < k0 + w; ++k) {
-      const double *lk = lp + (k - k0);  // column k: lk[(i - k0) * (pw + 1)]
-      const double xk = xs[k * sw + c] / lk[(size_t)(k - k0) * (pw + 1)];
-      if (ro == 0 && col < ncols) X[(size_t)k * ldx + col] = xk;
-      for (int i = k + 1 + ro; i < n; i += nro) xs[i * sw + c] -= lk[(size_t)(i - k0) * (pw + 1)] * xk;
+    // kTrsmStep rows per step: every thread of column c solves the step's
+    // diagonal block itself (the same operations in the same order as one
+    // row at a time), then the rows below subtract the step's columns in
+    // order, so a workgroup barrier comes once per step
+    for (int k = k0; k < k0 + w; k += kTrsmStep) {
+      const int b = min(kTrsmStep, k0 + w - k);
+      double xb[kTrsmStep];
+#pragma unroll
+      for (int q = 0; q < kTrsmStep; ++q) {
+        if (q < b) {
+          const double *lr = lp + (size_t)(k + q - k0) * (pw + 1) + (k - k0);  // row k + q
+          double v = xs[(k + q) * sw + c];
+#pragma unroll
+          for (int p = 0; p < q; ++p) v -= lr[p] * xb[p];
+          xb[q] = v / lr[q];
+        }
+      }
+      if (ro == 0 && col < ncols)
+        for (int q = 0; q < b; ++q) X[(size_t)(k + q) * ldx + col] = xb[q];
+      for (int i = k + b + ro; i < n; i += nro) {
+        const double *lr = lp + (size_t)(i - k0) * (pw + 1) + (k - k0);
+        double v = xs[i * sw + c];
+#pragma unroll
+        for (int q = 0; q < kTrsmStep; ++q)
+          if (q < b) v -= lr[q] * xb[q];
+        xs[i * sw + c] = v;
+      }
       __syncthreads();
     }
   }
@@ -911,18 +935,55 @@ void coarse_triplets_out(const double *LM, const double *LN, const double *W, co
   LAUNCHCHK();
 }
 
-// Bdag = sum over kept k of J_k W_k^T / sigma_k^2 (W_k = sigma_k u_k).
-__global__ void k_pinv(const double *__restrict__ W, const double *__restrict__ J,
-                       const double *__restrict__ sv, int n, int kmin,
-                       double *__restrict__ bdag) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
-  if (j >= n) return;
-  double s = 0.0;
-  for (int k = 0; k < n; ++k) {
-    if (k == kmin) continue;
-    s += J[(size_t)k * n + i] * W[(size_t)k * n + j] / (sv[k] * sv[k]);
+// is2[k] = 1 / sigma_k^2, 0 for the dropped (null) direction kmin
+__global__ void k_inv_sq(const double *__restrict__ sv, int n, int kmin, double *__restrict__ is2) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) is2[k] = k == kmin ? 0.0 : 1.0 / (sv[k] * sv[k]);
+}
+
+// Bdag = sum over kept k of J_k W_k^T / sigma_k^2 (W_k = sigma_k u_k), row-
+// major: Bdag[i][j] = sum_k J[k n + i] (W[k n + j] is2[k]) on FP64 MFMA, a
+// 64 x 64 output tile per workgroup, 32 x 32 (2 x 2 MFMA tiles) per wave,
+// operands straight from memory (J's and W's columns are contiguous, so 16
+// lanes read 128 consecutive bytes).
+__global__ void __launch_bounds__(256) k_pinv(const double *__restrict__ W,
+                                              const double *__restrict__ J,
+                                              const double *__restrict__ is2, int n,
+                                              double *__restrict__ bdag) {
+  const int wv = threadIdx.x / kWave, ln = threadIdx.x % kWave;
+  const int i0 = blockIdx.y * 64 + (wv / 2) * 32, j0 = blockIdx.x * 64 + (wv % 2) * 32;
+  svd_d4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = svd_d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < n; k0 += 4) {
+    const int k = k0 + ln / 16;
+    const bool kok = k < n;
+    const double sc = kok ? is2[k] : 0.0;
+    double a[2], b[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int i = i0 + 16 * t + ln % 16, j = j0 + 16 * t + ln % 16;
+      a[t] = kok && i < n ? J[(size_t)k * n + i] : 0.0;
+      b[t] = kok && j < n ? W[(size_t)k * n + j] * sc : 0.0;
+    }
+#pragma unroll
+    for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+      for (int tb = 0; tb < 2; ++tb)
+        acc[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta], b[tb], acc[ta][tb], 0, 0, 0);
   }
-  bdag[(size_t)i * n + j] = s;
+  // lane ln, register r: row 16 ta + ln / 16 + 4 r, column 16 tb + ln % 16
+#pragma unroll
+  for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + 16 * ta + ln / 16 + 4 * r, j = j0 + 16 * tb + ln % 16;
+        if (i < n && j < n) bdag[(size_t)i * n + j] = acc[ta][tb][r];
+      }
 }
 
 int build_pinv(Pool &pool, const double *W, const double *J, const double *sv, int n,
@@ -940,10 +1001,12 @@ int build_pinv(Pool &pool, const double *W, const double *J, const double *sv, i
   for (int k = 0; k < n; ++k)
     if (k != kmin && h[k] < s2) s2 = h[k];
   if (!(h[kmin] <= 1e-10 * smax) || !(s2 > 1e-13 * smax)) return BAMG_E_COARSE;
-  dim3 g(ceil_div(n, 128), n);
-  k_pinv<<<g, 128, 0, s>>>(W, J, sv, n, kmin, bdag);
+  double *is2 = pool.get<double>(n);
+  k_inv_sq<<<ceil_div(n, 256), 256, 0, s>>>(sv, n, kmin, is2);
   LAUNCHCHK();
-  (void)pool;
+  k_pinv<<<dim3(ceil_div(n, 64), ceil_div(n, 64)), 256, 0, s>>>(W, J, is2, n, bdag);
+  LAUNCHCHK();
+  pool.release(is2);
   return BAMG_OK;
 }
 
