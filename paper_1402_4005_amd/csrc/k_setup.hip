@@ -697,25 +697,27 @@ void interp_pattern(Pool &pool, const Level &L, int cap, int geometric, Csr &P, 
 // Rows of C = A * B with many product terms: one wave (block of 64) per
 // listed row at a time. When the row's columns lie within kSymBitWords * 32
 // of each other (the usual case for Galerkin rows), every term sets its
-// column's bit in an LDS bitmap and the set bits are read back in order;
-// otherwise every term appends its column to an LDS buffer, which is
+// column's bit in an LDS bitmap and the set bits are read back in order
+// (k_spgemm_sym_narrow, which needs 1 KB of LDS, so many waves stay
+// resident per CU); the other rows are listed again for k_spgemm_sym_wide,
+// where every term appends its column to an LDS buffer, which is
 // bitonic-sorted. The distinct columns are counted (pass 1) or written
 // (pass 2). The result is the sorted structural product, independent of
 // thread timing.
-constexpr int kSymCap = 4096, kSymListBlocks = 4096, kSymBitWords = 256;
+constexpr int kSymCap = 4096, kSymListBlocks = 4096, kSymNarrowBlocks = 8192;
+constexpr int kSymBitWords = 256;
 
 // The number of listed rows is read on the device (nlist), so the host does
-// not wait for it: the grid strides over the list.
+// not wait for it: the grid strides over the list. Pass 1 appends the rows
+// too wide for the bitmap to wide / nwide; pass 2 skips them.
 template <bool FILL>
 __global__ void __launch_bounds__(64)
-    k_spgemm_sym_list(const int *__restrict__ rows, const int *__restrict__ nlist,
-                      const int *__restrict__ arp, const int *__restrict__ aci,
-                      const int *__restrict__ brp, const int *__restrict__ bci, int force_diag,
-                      int *__restrict__ cnt, const int *__restrict__ crp, int *__restrict__ cci,
-                      int *__restrict__ overflow) {
-  __shared__ int buf[kSymCap];
+    k_spgemm_sym_narrow(const int *__restrict__ rows, const int *__restrict__ nlist,
+                        const int *__restrict__ arp, const int *__restrict__ aci,
+                        const int *__restrict__ brp, const int *__restrict__ bci, int force_diag,
+                        int *__restrict__ cnt, const int *__restrict__ crp,
+                        int *__restrict__ cci, int *__restrict__ wide, int *__restrict__ nwide) {
   __shared__ unsigned bits[kSymBitWords];
-  __shared__ int nbuf;
   const int nl = *nlist, lane = threadIdx.x;
   for (int li = blockIdx.x; li < nl; li += gridDim.x) {
     const int row = rows[li];
@@ -735,47 +737,62 @@ __global__ void __launch_bounds__(64)
       hi = max(hi, __shfl_xor(hi, off, 64));
     }
     const int words = hi >= lo ? ((hi - lo) >> 5) + 1 : 0;
-    if (words <= kSymBitWords) {
-      // Narrow row (all columns within kSymBitWords * 32 of the smallest):
-      // mark every term's column in an LDS bitmap, read them back in order.
-      for (int q = lane; q < words; q += 64) bits[q] = 0u;
-      __syncthreads();
-      if (force_diag && lane == 0) atomicOr(&bits[(row - lo) >> 5], 1u << ((row - lo) & 31));
-      for (int a = ab + lane; a < ae; a += 64) {
-        const int k = aci[a];
-        for (int b = brp[k]; b < brp[k + 1]; ++b) {
-          const int d = bci[b] - lo;
-          atomicOr(&bits[d >> 5], 1u << (d & 31));
-        }
-      }
-      __syncthreads();
-      int base = 0;
-      const int out0 = FILL ? crp[row] : 0;
-      for (int q0 = 0; q0 < words; q0 += 64) {
-        const int q = q0 + lane;
-        const unsigned wbits = q < words ? bits[q] : 0u;
-        // exclusive prefix of the popcounts over the wave
-        int c = __popc(wbits), incl = c;
-        for (int off = 1; off < 64; off <<= 1) {
-          const int v = __shfl_up(incl, off, 64);
-          if (lane >= off) incl += v;
-        }
-        if (FILL) {
-          unsigned m = wbits;
-          int o = out0 + base + incl - c;
-          while (m) {
-            const int bb = __ffs(m) - 1;
-            cci[o++] = lo + (q << 5) + bb;
-            m &= m - 1;
-          }
-        }
-        base += __shfl(incl, 63, 64);
-      }
-      if (!FILL && lane == 0) cnt[row] = base;
-      __syncthreads();  // bits is reused by the next listed row
+    if (words > kSymBitWords) {  // the same decision in both passes
+      if (!FILL && lane == 0) wide[atomicAdd(nwide, 1)] = row;
       continue;
     }
-    // wide row: gather the terms and sort them
+    for (int q = lane; q < words; q += 64) bits[q] = 0u;
+    __syncthreads();
+    if (force_diag && lane == 0) atomicOr(&bits[(row - lo) >> 5], 1u << ((row - lo) & 31));
+    for (int a = ab + lane; a < ae; a += 64) {
+      const int k = aci[a];
+      for (int b = brp[k]; b < brp[k + 1]; ++b) {
+        const int d = bci[b] - lo;
+        atomicOr(&bits[d >> 5], 1u << (d & 31));
+      }
+    }
+    __syncthreads();
+    int base = 0;
+    const int out0 = FILL ? crp[row] : 0;
+    for (int q0 = 0; q0 < words; q0 += 64) {
+      const int q = q0 + lane;
+      const unsigned wbits = q < words ? bits[q] : 0u;
+      // exclusive prefix of the popcounts over the wave
+      int c = __popc(wbits), incl = c;
+      for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
+      }
+      if (FILL) {
+        unsigned m = wbits;
+        int o = out0 + base + incl - c;
+        while (m) {
+          const int bb = __ffs(m) - 1;
+          cci[o++] = lo + (q << 5) + bb;
+          m &= m - 1;
+        }
+      }
+      base += __shfl(incl, 63, 64);
+    }
+    if (!FILL && lane == 0) cnt[row] = base;
+    __syncthreads();  // bits is reused by the next listed row
+  }
+}
+
+template <bool FILL>
+__global__ void __launch_bounds__(64)
+    k_spgemm_sym_wide(const int *__restrict__ rows, const int *__restrict__ nlist,
+                      const int *__restrict__ arp, const int *__restrict__ aci,
+                      const int *__restrict__ brp, const int *__restrict__ bci, int force_diag,
+                      int *__restrict__ cnt, const int *__restrict__ crp, int *__restrict__ cci,
+                      int *__restrict__ overflow) {
+  __shared__ int buf[kSymCap];
+  __shared__ int nbuf;
+  const int nl = *nlist, lane = threadIdx.x;
+  for (int li = blockIdx.x; li < nl; li += gridDim.x) {
+    const int row = rows[li];
+    const int ab = arp[row], ae = arp[row + 1];
+    // gather the terms and sort them
     if (lane == 0) nbuf = 0;
     __syncthreads();
     if (force_diag && lane == 0) {
@@ -908,7 +925,7 @@ struct SymJob {
   const Csr *A = nullptr, *B = nullptr;
   int force_diag = 0, lgrid = 0;
   Csr *C = nullptr;
-  int *cnt = nullptr, *tmp = nullptr, *ovf = nullptr, *longrows = nullptr;
+  int *cnt = nullptr, *tmp = nullptr, *ovf = nullptr, *longrows = nullptr, *widerows = nullptr;
   int *hv = nullptr;  // pinned: C's size and the overflow flag, copied by the count half
 };
 
@@ -922,18 +939,23 @@ static void sym_count(Pool &pool, const Csr &A, const Csr &B, int force_diag, Cs
   j.C = &C;
   j.cnt = pool.get<int>(nr);
   j.tmp = pool.get<int>((size_t)nr * kSymShort);
-  j.ovf = pool.get<int>(2);  // [overflow, long rows]
+  j.ovf = pool.get<int>(3);  // [overflow, long rows, wide rows]
   j.longrows = pool.get<int>(nr);
-  fill_i32(j.ovf, 0, 2, s);
+  j.widerows = pool.get<int>(nr);
+  fill_i32(j.ovf, 0, 3, s);
   if (nr) {
     k_spgemm_sym_short<<<ceil_div(nr, kSymThreads), kSymThreads, 0, s>>>(
         nr, A.rp, A.ci, B.rp, B.ci, force_diag, j.cnt, j.tmp, j.longrows, j.ovf + 1);
     LAUNCHCHK();
   }
-  // long rows: a strided grid about as wide as the LDS lets stay resident
+  // long rows: strided grids about as wide as the LDS lets stay resident
   j.lgrid = std::min(nr, kSymListBlocks);
   if (j.lgrid > 0) {
-    k_spgemm_sym_list<false><<<j.lgrid, 64, 0, s>>>(j.longrows, j.ovf + 1, A.rp, A.ci, B.rp,
+    k_spgemm_sym_narrow<false><<<std::min(nr, kSymNarrowBlocks), 64, 0, s>>>(
+        j.longrows, j.ovf + 1, A.rp, A.ci, B.rp, B.ci, force_diag, j.cnt, nullptr, nullptr,
+        j.widerows, j.ovf + 2);
+    LAUNCHCHK();
+    k_spgemm_sym_wide<false><<<j.lgrid, 64, 0, s>>>(j.widerows, j.ovf + 2, A.rp, A.ci, B.rp,
                                                     B.ci, force_diag, j.cnt, nullptr, nullptr,
                                                     j.ovf);
     LAUNCHCHK();
@@ -958,7 +980,11 @@ static void sym_finish(Pool &pool, SymJob &j, hipStream_t s) {
     LAUNCHCHK();
   }
   if (j.lgrid > 0) {
-    k_spgemm_sym_list<true><<<j.lgrid, 64, 0, s>>>(j.longrows, j.ovf + 1, A.rp, A.ci, B.rp, B.ci,
+    k_spgemm_sym_narrow<true><<<std::min(nr, kSymNarrowBlocks), 64, 0, s>>>(
+        j.longrows, j.ovf + 1, A.rp, A.ci, B.rp, B.ci, j.force_diag, nullptr, C.rp, C.ci,
+        nullptr, nullptr);
+    LAUNCHCHK();
+    k_spgemm_sym_wide<true><<<j.lgrid, 64, 0, s>>>(j.widerows, j.ovf + 2, A.rp, A.ci, B.rp, B.ci,
                                                    j.force_diag, nullptr, C.rp, C.ci, j.ovf);
     LAUNCHCHK();
   }
@@ -966,6 +992,7 @@ static void sym_finish(Pool &pool, SymJob &j, hipStream_t s) {
   pool.release(j.tmp);
   pool.release(j.ovf);
   pool.release(j.longrows);
+  pool.release(j.widerows);
 }
 
 void spgemm_symbolic2(Pool &pool, const Csr &A1, const Csr &B1, const Csr &A2, const Csr &B2,

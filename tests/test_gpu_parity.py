@@ -109,6 +109,19 @@ def test_structure_bit_exact(name, make, kw):
     check_structure(ho, hg)
 
 
+def test_wide_galerkin_rows_bit_exact():
+    """Galerkin rows whose columns span 8192 or more (here the rows of the
+    four hubs on level 1 of a 60,000-state ring, about 20,000 coarse states
+    wide) leave the bitmap of the long-row symbolic kernel for the sorted
+    list; every pattern still equals the oracle's."""
+    ch = chaingen.hub_walk(60000, 4, 400, 9)
+    ho, hg = both(ch, r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99)
+    rp, ci, _ = hg.csr(1, "B")
+    spans = [ci[rp[i + 1] - 1] - ci[rp[i]] for i in range(len(rp) - 1) if rp[i + 1] > rp[i]]
+    assert max(spans) >= 8192, max(spans)
+    check_structure(ho, hg)
+
+
 # Separately built hierarchies agree to rounding: the setup's arithmetic is
 # the oracle's, in another summation order. Measured maxima over CASES (one
 # MI355X run): operators 3.6e-11 relative (hub4000_plainls, whose hub rows
