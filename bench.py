@@ -77,6 +77,12 @@ KERNEL_SOURCES = {
 }
 
 
+def progress(msg):
+    """One line on stderr when a phase of the run ends (the JSON result is
+    the only line on stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_digest(kernel="k_jacobi"):
     import hashlib
     h = hashlib.sha256()
@@ -384,6 +390,7 @@ def main():
         return {"ms": round(ms, 4), "bytes": nbytes, "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1)}
 
     opts = options(args.precision)
+    progress(f"{args.workload}: {ch.n} states built, {args.warmup} warm-up + {args.steps} timed steps")
     try:
         ms_per_step, last, x, infos = timed(opts)
     except bamg.BamgError as e:
@@ -396,6 +403,7 @@ def main():
                           "error": {"status": e.code, "message": str(e)}}))
         return
 
+    progress(f"timed steps done: {ms_per_step:.3f} ms per step")
     # kernel timing: the same K steps again with HIP events around every run of
     # finest-level Jacobi sweeps (event recording bypasses the V-cycle graph),
     # and K setups with events around the coarsest Jacobi SVD's round launches
@@ -431,6 +439,7 @@ def main():
     # return; with validation joined by the solve, the search is not in it)
     setup_ms = float(np.mean([i.t_setup_ms for i in infos]))
     vcycle = vcycle_rate(opts)
+    progress(f"kernel timing and V-cycle rate done ({vcycle['ms']} ms per V-cycle)")
 
     # the learned form: a network trained (untimed) on BAMG^2 corrections of
     # smaller chains of the same family, then one-cycle setups with it
@@ -470,6 +479,7 @@ def main():
         }
         lh.close()
         net.close()
+        progress(f"learned form done: {lms:.3f} ms per step")
 
     # BAMG^2 (two setup cycles, Section 7), whose second cycle the learned
     # weights stand in for
@@ -484,6 +494,7 @@ def main():
                  "converged": [bool(i.converged) for i in b2infos]}
         if learned_line:
             learned_line["speedup_vs_bamg2"] = round(b2ms / learned_line["ms_per_step"], 3)
+        progress(f"BAMG^2 done: {b2ms:.3f} ms per step")
 
     # the mixed-precision form on the same workload: FP32 setup and V-cycles,
     # FP64 Krylov, residual, normalisation and coarsest solve
@@ -501,6 +512,7 @@ def main():
             "vcycle": vcycle_rate(mopts),
         }
         mh.close()
+        progress(f"mixed precision done: {mms:.3f} ms per step")
     last.close()
 
     # random-rate tandems (configurations whose rates are drawn): setup and
@@ -524,6 +536,7 @@ def main():
             except bamg.BamgError as e:
                 entry["error"] = str(e)
             status.append(entry)
+            progress(f"status of {name} (rate seed {sd}) done")
 
     def roofline_of(name, kernel, n_launch, ms_tot, bytes_tot):
         if not n_launch:
@@ -554,6 +567,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, kind, size, wopts, ch, xs)
+        progress("oracle baseline done")
 
     it = [i.iterations for i in infos]
     line = {

@@ -10,6 +10,7 @@
 // candidates are tried in a fixed order (the defaults first), and a later
 // one replaces the choice only when at least 3% faster, so near-ties
 // (within timing noise) usually resolve the same way in every process.
+// Levels too small to fill the chip are not timed (see below).
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -42,6 +43,21 @@ void tune_sweeps(Pool &pool, Level &L, hipStream_t s) {
   const int avg = L.n ? (L.B.nnz + L.n - 1) / L.n : 1;
   int base = 1;
   while (base < avg && base < 64) base <<= 1;
+  const int dlanes = std::min(base, kMaxTunedLanes);
+  if ((long)L.n * dlanes < 256L * 256) {
+    // A level too small to fill the chip (under 256 workgroups of 256
+    // threads at the default lanes): its sweep is bound by the launch and
+    // one pass of dependent loads, so it takes the default lanes and the
+    // most workgroups (128 threads) untimed. Back-to-back timing of such
+    // short launches measures noise, and a choice of a few large
+    // workgroups made a sweep inside the cycle twice as long (Delaunay
+    // 262,144, level 3 of 1,814 rows: 7.0 against 3.5 us).
+    L.lanes = dlanes;
+    L.threads = 128;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune.emplace(key, std::make_pair(L.lanes, L.threads));
+    return;
+  }
   T *b = pool.get<T>(L.n), *x = pool.get<T>(L.n), *y = pool.get<T>(L.n);
   fill<T>(b, (T)1, L.n, s);
   fill<T>(x, (T)0, L.n, s);

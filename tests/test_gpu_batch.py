@@ -62,10 +62,20 @@ def test_batch_keeps_a_bad_chain_separate():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_autotuned_hierarchy_matches_oracle(precision):
-    ch = chaingen.delaunay_walk(3000, 12)
+@pytest.mark.parametrize("n", [3000, 20000])
+def test_autotuned_hierarchy_matches_oracle(precision, n):
+    """3,000 states: every level is too small to fill the chip, so none is
+    timed (default lanes, 128 threads); 20,000: the finest level's lanes and
+    workgroup size are timed. Either way x matches the oracle."""
+    ch = chaingen.delaunay_walk(n, 12)
     kw = dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99)
     h = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, autotune=1, precision=precision, **kw))
+    for l in range(h.levels - 1):
+        rp, _, _ = h.csr(l, "B")
+        avg = -(-int(rp[-1]) // (len(rp) - 1))
+        dl = min(4, 1 << max(0, (avg - 1).bit_length()))
+        if (len(rp) - 1) * dl < 256 * 256:
+            assert (h.lanes(l), h.threads(l)) == (dl, 128), l
     x, info = h.gmres(restart=20, tol=1e-13, maxit=400)
     xo, _ = oracle.Hierarchy(ch, oracle.options_for(ch, **kw)).gmres(m=20, tol=1e-14, maxit=400)
     assert info.converged
