@@ -382,8 +382,8 @@ template <class T>
 void mlp_features(const Level &L, int r, const T *V, const double *wv, const T *Pv, float *F,
                   hipStream_t s);
 template <class T>
-void mlp_select(const Level &L, int r, const T *V, const double *wv, const float *Y, T *Pv,
-                int *counts, hipStream_t s);
+void mlp_apply(const Level &L, int r, const T *V, const double *wv, const bamg_mlp *m, T *Pv,
+               int *counts, hipStream_t s);
 template <class T>
 void mlp_targets(const Level &L, const T *Pv, float *Tg, float *Mk, hipStream_t s);
 

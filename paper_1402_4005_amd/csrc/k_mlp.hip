@@ -13,8 +13,9 @@
 //  * k_mlp_tile       FP32 forward and backward of 64 points on FP32 MFMA;
 //  * k_mlp_wgrad_mfma weight gradients as batch products on FP32 MFMA;
 //  * k_adam, k_mlp_bf16  the optimiser step and the BF16 weight copy;
-//  * k_mlp_features   the 96 inputs of each F point;
-//  * k_mlp_select     MLP row or exact LS row, by the objective test.
+//  * k_mlp_features   the 96 inputs of each F point (recorded for training);
+//  * k_mlp_apply      features, inference and the objective test (MLP row or
+//                     exact LS row) of 16 F points per wave, in one launch.
 #include <mutex>
 #include <string>
 
@@ -344,20 +345,20 @@ __global__ void k_sum_double(const double *__restrict__ x, long n, double *__res
 }
 
 // ------------------------------------------------------------ features
+// The 96 inputs of F point f (state fpts[f]) into o[0 .. 95]: the weighted
+// test-vector values at the point and its coarse neighbours (scaled by
+// their largest magnitude), the stencil ratios b_ij / b_ii, the exact LS row
+// and the neighbour mask.
 template <class T>
-__global__ void k_mlp_features(int nF, const int *__restrict__ fpts, int r,
-                               const int *__restrict__ prp, const int *__restrict__ pci,
-                               const int *__restrict__ cpts, const T *__restrict__ V,
-                               const double *__restrict__ wv, const int *__restrict__ brp,
-                               const int *__restrict__ bci, const T *__restrict__ bv,
-                               const T *__restrict__ Pv, float *__restrict__ F) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= nF) return;
+__device__ __forceinline__ void mlp_point_features(
+    int f, const int *__restrict__ fpts, int r, const int *__restrict__ prp,
+    const int *__restrict__ pci, const int *__restrict__ cpts, const T *__restrict__ V,
+    const double *__restrict__ wv, const int *__restrict__ brp, const int *__restrict__ bci,
+    const T *__restrict__ bv, const T *__restrict__ Pv, float *__restrict__ o) {
   const int i = fpts[f];
   const int a0 = prp[i], m = min(prp[i + 1] - a0, kOut);
   int J[kOut];
   for (int t = 0; t < kOut; ++t) J[t] = t < m ? cpts[pci[a0 + t]] : -1;
-  float *o = F + (size_t)f * kIn;
   double S = 0.0;
   for (int k = 0; k < 8; ++k) {
     const double sw = k < r ? sqrt(wv[k]) : 0.0;
@@ -388,46 +389,272 @@ __global__ void k_mlp_features(int nF, const int *__restrict__ fpts, int r,
   }
 }
 
-// LS objective sum_k w_k (v_i - sum_t p_t v_{j_t})^2 of the MLP row (the
-// exact row in Pv plus the network's correction) against the exact row; the
-// MLP row replaces it if within 2x.
 template <class T>
-__global__ void k_mlp_select(int nF, const int *__restrict__ fpts, int r,
-                             const int *__restrict__ prp, const int *__restrict__ pci,
-                             const int *__restrict__ cpts, const T *__restrict__ V,
-                             const double *__restrict__ wv, const float *__restrict__ Y,
-                             T *__restrict__ Pv, int *__restrict__ counts) {
+__global__ void k_mlp_features(int nF, const int *__restrict__ fpts, int r,
+                               const int *__restrict__ prp, const int *__restrict__ pci,
+                               const int *__restrict__ cpts, const T *__restrict__ V,
+                               const double *__restrict__ wv, const int *__restrict__ brp,
+                               const int *__restrict__ bci, const T *__restrict__ bv,
+                               const T *__restrict__ Pv, float *__restrict__ F) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  bool take = false;
-  const bool active = f < nF;
-  if (active) {
-    const int i = fpts[f];
-    const int a0 = prp[i], m = min(prp[i + 1] - a0, kOut);
-    int J[kOut];
-    double pl[kOut], pm[kOut];
+  if (f >= nF) return;
+  mlp_point_features<T>(f, fpts, r, prp, pci, cpts, V, wv, brp, bci, bv, Pv, F + (size_t)f * kIn);
+}
+
+// LS objective sum_k w_k (v_i - sum_t p_t v_{j_t})^2 of the MLP row (the
+// exact row in Pv plus the network's correction y) against the exact row;
+// the MLP row replaces it if within 2x. Returns whether it did.
+template <class T>
+__device__ __forceinline__ bool mlp_point_select(int f, const int *__restrict__ fpts, int r,
+                                                 const int *__restrict__ prp,
+                                                 const int *__restrict__ pci,
+                                                 const int *__restrict__ cpts,
+                                                 const T *__restrict__ V,
+                                                 const double *__restrict__ wv,
+                                                 const float *__restrict__ y,
+                                                 T *__restrict__ Pv) {
+  const int i = fpts[f];
+  const int a0 = prp[i], m = min(prp[i + 1] - a0, kOut);
+  int J[kOut];
+  double pl[kOut], pm[kOut];
+  for (int t = 0; t < m; ++t) {
+    J[t] = cpts[pci[a0 + t]];
+    pl[t] = (double)Pv[a0 + t];
+    pm[t] = pl[t] + (double)y[t];
+  }
+  double jm = 0.0, jl = 0.0;
+  for (int k = 0; k < r; ++k) {
+    double em = (double)V[(size_t)i * r + k], el = em;
+    for (int t = 0; t < m; ++t) {
+      const double vj = (double)V[(size_t)J[t] * r + k];
+      em -= pm[t] * vj;
+      el -= pl[t] * vj;
+    }
+    jm += wv[k] * em * em;
+    jl += wv[k] * el * el;
+  }
+  const bool take = jm <= 2.0 * jl;
+  if (take)
+    for (int t = 0; t < m; ++t) Pv[a0 + t] = (T)pm[t];
+  return take;
+}
+
+// The features of one point by four lanes: part g (0..3) writes the entries
+// of test vectors k = 2g, 2g + 1 and of neighbours t = 2g, 2g + 1; every
+// entry is formed by the same operations as mlp_point_features (the scale
+// S is a maximum, combined across the four lanes exactly), so the row is
+// the same bit for bit. The four lanes of a point are l, l ^ 16, l ^ 32 and
+// l ^ 48 of one wave; `valid` is uniform across them.
+template <class T>
+__device__ __forceinline__ void mlp_point_features4(
+    int f, bool valid, int g, const int *__restrict__ fpts, int r, const int *__restrict__ prp,
+    const int *__restrict__ pci, const int *__restrict__ cpts, const T *__restrict__ V,
+    const double *__restrict__ wv, const int *__restrict__ brp, const int *__restrict__ bci,
+    const T *__restrict__ bv, const T *__restrict__ Pv, float *__restrict__ o) {
+  int i = 0, a0 = 0, m = 0;
+  int J[kOut];
+  double S = 0.0;
+  if (valid) {
+    i = fpts[f];
+    a0 = prp[i];
+    m = min(prp[i + 1] - a0, kOut);
+    for (int t = 0; t < kOut; ++t) J[t] = t < m ? cpts[pci[a0 + t]] : -1;
+    for (int k = 2 * g; k < 2 * g + 2; ++k) {
+      const double sw = k < r ? sqrt(wv[k]) : 0.0;
+      double a = k < r ? fabs(sw * (double)V[(size_t)i * r + k]) : 0.0;
+      S = fmax(S, a);
+      for (int t = 0; t < m; ++t)
+        if (k < r) S = fmax(S, fabs(sw * (double)V[(size_t)J[t] * r + k]));
+    }
+  }
+  S = fmax(S, __shfl_xor(S, 16, kWave));
+  S = fmax(S, __shfl_xor(S, 32, kWave));
+  if (!valid) return;
+  if (!(S > 0.0)) S = 1.0;
+  for (int k = 2 * g; k < 2 * g + 2; ++k) {
+    const double sw = k < r ? sqrt(wv[k]) : 0.0;
+    o[9 * k] = k < r ? (float)(sw * (double)V[(size_t)i * r + k] / S) : 0.f;
+    for (int t = 0; t < kOut; ++t)
+      o[9 * k + 1 + t] = (k < r && t < m) ? (float)(sw * (double)V[(size_t)J[t] * r + k] / S) : 0.f;
+  }
+  double bii = 1.0;
+  for (int a = brp[i]; a < brp[i + 1]; ++a)
+    if (bci[a] == i) bii = (double)bv[a];
+  if (bii == 0.0) bii = 1.0;
+  for (int t = 2 * g; t < 2 * g + 2; ++t) {
+    double bij = 0.0;
+    if (t < m)
+      for (int a = brp[i]; a < brp[i + 1]; ++a)
+        if (bci[a] == J[t]) bij = (double)bv[a];
+    o[72 + t] = (float)(bij / bii);
+    o[80 + t] = t < m ? (float)Pv[a0 + t] : 0.f;
+    o[88 + t] = t < m ? 1.f : 0.f;
+  }
+}
+
+// The objective test of one point by four lanes: part g forms the residuals
+// em, el of test vectors 2g, 2g + 1 as mlp_point_select does; part 0 then
+// adds the terms w_k e_k^2 in the order k = 0 .. r - 1 and writes the row.
+// Returns the decision in every lane of the point.
+template <class T>
+__device__ __forceinline__ bool mlp_point_select4(int f, bool valid, int g,
+                                                  const int *__restrict__ fpts, int r,
+                                                  const int *__restrict__ prp,
+                                                  const int *__restrict__ pci,
+                                                  const int *__restrict__ cpts,
+                                                  const T *__restrict__ V,
+                                                  const double *__restrict__ wv,
+                                                  const float *__restrict__ y,
+                                                  T *__restrict__ Pv) {
+  int i = 0, a0 = 0, m = 0;
+  int J[kOut];
+  double pl[kOut], pm[kOut];
+  double em[2] = {0.0, 0.0}, el[2] = {0.0, 0.0};
+  if (valid) {
+    i = fpts[f];
+    a0 = prp[i];
+    m = min(prp[i + 1] - a0, kOut);
     for (int t = 0; t < m; ++t) {
       J[t] = cpts[pci[a0 + t]];
       pl[t] = (double)Pv[a0 + t];
-      pm[t] = pl[t] + (double)Y[(size_t)f * kOut + t];
+      pm[t] = pl[t] + (double)y[t];
     }
-    double jm = 0.0, jl = 0.0;
-    for (int k = 0; k < r; ++k) {
-      double em = (double)V[(size_t)i * r + k], el = em;
+    for (int q = 0; q < 2; ++q) {
+      const int k = 2 * g + q;
+      if (k >= r) continue;
+      double e1 = (double)V[(size_t)i * r + k], e2 = e1;
       for (int t = 0; t < m; ++t) {
         const double vj = (double)V[(size_t)J[t] * r + k];
-        em -= pm[t] * vj;
-        el -= pl[t] * vj;
+        e1 -= pm[t] * vj;
+        e2 -= pl[t] * vj;
       }
-      jm += wv[k] * em * em;
-      jl += wv[k] * el * el;
+      em[q] = e1;
+      el[q] = e2;
+    }
+  }
+  // part 0 gathers the residuals of k = 0 .. 7 from the four parts
+  double ems[8], els[8];
+  const int lane = threadIdx.x % kWave, base = lane % 16;
+#pragma unroll
+  for (int gg = 0; gg < 4; ++gg)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      ems[2 * gg + q] = __shfl(em[q], base + 16 * gg, kWave);
+      els[2 * gg + q] = __shfl(el[q], base + 16 * gg, kWave);
+    }
+  bool take = false;
+  if (valid && g == 0) {
+    double jm = 0.0, jl = 0.0;
+    for (int k = 0; k < r; ++k) {
+      jm += wv[k] * ems[k] * ems[k];
+      jl += wv[k] * els[k] * els[k];
     }
     take = jm <= 2.0 * jl;
     if (take)
       for (int t = 0; t < m; ++t) Pv[a0 + t] = (T)pm[t];
   }
-  // one counter update per wave
-  const unsigned long long bt = __ballot(active && take), bf = __ballot(active && !take);
-  if ((threadIdx.x % kWave) == 0) {
+  return __shfl((int)take, base, kWave) != 0;
+}
+
+// The learned F rows of one level in one launch: each wave takes 16 F
+// points, forms their features in LDS (four lanes per point), runs the
+// network on them as k_mlp_infer does (the same BF16 operands and MFMA
+// order) and applies the objective test to its outputs (four lanes per
+// point again), so the 96 inputs and 8 outputs of a point never pass through
+// memory; the results are those of k_mlp_features, k_mlp_infer and the test
+// one after the other. A point reads and writes only its own row of P, so
+// the points of a launch are independent. The hidden layers and the outputs
+// reuse the feature rows' LDS once layer 1 has read them. counts[0] /
+// counts[1]: points that took the network's / kept the exact row.
+template <class T>
+__global__ void __launch_bounds__(kInferWaves * kWave)
+    k_mlp_apply(const __bf16 *__restrict__ wb, const float *__restrict__ par, int nF,
+                const int *__restrict__ fpts, int r, const int *__restrict__ prp,
+                const int *__restrict__ pci, const int *__restrict__ cpts,
+                const T *__restrict__ V, const double *__restrict__ wv,
+                const int *__restrict__ brp, const int *__restrict__ bci,
+                const T *__restrict__ bv, T *__restrict__ Pv, int *__restrict__ counts) {
+  static_assert(kOut == 8, "four lanes of two test vectors and two neighbours each");
+  __shared__ __attribute__((aligned(16))) __bf16 w[kNBf];
+  __shared__ float bias[kHid + kHid + kOut];
+  // per wave: 16 feature rows (6 KB); later h1 | h2 (2 KB each, BF16) and
+  // the 16 outputs (512 B) in the same space
+  __shared__ __attribute__((aligned(16))) float xs[kInferWaves][16 * kIn];
+  for (int e = threadIdx.x; e < kNBf; e += blockDim.x) w[e] = wb[e];
+  for (int e = threadIdx.x; e < kHid; e += blockDim.x) {
+    bias[e] = par[oB1 + e];
+    bias[kHid + e] = par[oB2 + e];
+  }
+  for (int e = threadIdx.x; e < kOut; e += blockDim.x) bias[2 * kHid + e] = par[oB3 + e];
+  const int wv_ = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  const long p0 = ((long)blockIdx.x * kInferWaves + wv_) * 16;
+  float *X = xs[wv_];
+  const int q = l % 16, g = l / 16;
+  const bool valid = p0 + q < nF;
+  mlp_point_features4<T>((int)(p0 + q), valid, g, fpts, r, prp, pci, cpts, V, wv, brp, bci, bv,
+                         Pv, X + q * kIn);
+  __syncthreads();
+  const int row = l % 16, kq = 8 * (l / 16), rq = 4 * (l / 16);
+  const long pr = p0 + row;  // the point whose A row this lane loads
+  __bf16 *h1 = reinterpret_cast<__bf16 *>(X), *h2 = h1 + 16 * kHid;
+  float *ys = X + 16 * kHid;  // after h1 | h2 (2 x 16 x 64 BF16 = 16 x 64 floats)
+  // layer 1: [16 x 96] x [96 x 64]; every lane's A operands are in
+  // registers before the wave's first MFMA, so h1 may overwrite the rows
+  f32x4 acc[4];
+  for (int nb = 0; nb < 4; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  bf16x8 a1[kIn / 32];
+#pragma unroll
+  for (int ks = 0; ks < kIn / 32; ++ks)
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      a1[ks][e] = (__bf16)(pr < nF ? X[row * kIn + 32 * ks + kq + e] : 0.f);
+  __syncthreads();
+#pragma unroll
+  for (int ks = 0; ks < kIn / 32; ++ks)
+    for (int nb = 0; nb < 4; ++nb) {
+      const bf16x8 b = *(const bf16x8 *)&w[bW1 + (16 * nb + row) * kIn + 32 * ks + kq];
+      acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[ks], b, acc[nb], 0, 0, 0);
+    }
+  for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int j = 16 * nb + row;
+      h1[(rq + e) * kHid + j] = (__bf16)fmaxf(acc[nb][e] + bias[j], 0.f);
+    }
+  __syncthreads();
+  // layer 2: [16 x 64] x [64 x 64]
+  for (int nb = 0; nb < 4; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int ks = 0; ks < kHid / 32; ++ks) {
+    const bf16x8 a = *(const bf16x8 *)&h1[row * kHid + 32 * ks + kq];
+    for (int nb = 0; nb < 4; ++nb) {
+      const bf16x8 b = *(const bf16x8 *)&w[bW2 + (16 * nb + row) * kHid + 32 * ks + kq];
+      acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[nb], 0, 0, 0);
+    }
+  }
+  for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int j = 16 * nb + row;
+      h2[(rq + e) * kHid + j] = (__bf16)fmaxf(acc[nb][e] + bias[kHid + j], 0.f);
+    }
+  __syncthreads();
+  // layer 3: [16 x 64] x [64 x 16] (columns 8..15 are zero padding)
+  f32x4 o = {0.f, 0.f, 0.f, 0.f};
+  for (int ks = 0; ks < kHid / 32; ++ks) {
+    const bf16x8 a = *(const bf16x8 *)&h2[row * kHid + 32 * ks + kq];
+    const bf16x8 b = *(const bf16x8 *)&w[bW3 + row * kHid + 32 * ks + kq];
+    o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, o, 0, 0, 0);
+  }
+  if (row < kOut)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) ys[(rq + e) * kOut + row] = o[e] + bias[2 * kHid + row];
+  __syncthreads();
+  const bool take = mlp_point_select4<T>((int)(p0 + q), valid, g, fpts, r, prp, pci, cpts, V, wv,
+                                         ys + q * kOut, Pv);
+  // one counter update per wave (the point's part-0 lanes)
+  const unsigned long long bt = __ballot(valid && g == 0 && take);
+  const unsigned long long bf = __ballot(valid && g == 0 && !take);
+  if (l == 0) {
     if (bt) atomicAdd(&counts[0], (int)__popcll(bt));
     if (bf) atomicAdd(&counts[1], (int)__popcll(bf));
   }
@@ -670,11 +897,13 @@ void mlp_features(const Level &L, int r, const T *V, const double *wv, const T *
 }
 
 template <class T>
-void mlp_select(const Level &L, int r, const T *V, const double *wv, const float *Y, T *Pv,
-                int *counts, hipStream_t s) {
+void mlp_apply(const Level &L, int r, const T *V, const double *wv, const bamg_mlp *m, T *Pv,
+               int *counts, hipStream_t s) {
   if (L.nF <= 0) return;
-  k_mlp_select<T><<<ceil_div(L.nF, 128), 128, 0, s>>>(L.nF, L.fpts, r, L.P.rp, L.P.ci, L.cpts, V,
-                                                      wv, Y, Pv, counts);
+  const long waves = ((long)L.nF + 15) / 16;
+  k_mlp_apply<T><<<ceil_div(waves, kInferWaves), kInferWaves * kWave, 0, s>>>(
+      m->wb, m->p, L.nF, L.fpts, r, L.P.rp, L.P.ci, L.cpts, V, wv, L.B.rp, L.B.ci,
+      (const T *)L.Bv, Pv, counts);
   LAUNCHCHK();
 }
 
@@ -688,8 +917,8 @@ void mlp_targets(const Level &L, const T *Pv, float *Tg, float *Mk, hipStream_t 
 #define INST(T)                                                                              \
   template void mlp_features<T>(const Level &, int, const T *, const double *, const T *,  \
                                 float *, hipStream_t);                                       \
-  template void mlp_select<T>(const Level &, int, const T *, const double *, const float *, \
-                              T *, int *, hipStream_t);                                      \
+  template void mlp_apply<T>(const Level &, int, const T *, const double *, const bamg_mlp *,  \
+                             T *, int *, hipStream_t);                                         \
   template void mlp_targets<T>(const Level &, const T *, float *, float *, hipStream_t);
 INST(double)
 INST(float)

@@ -142,21 +142,9 @@ struct Setup {
       mlp_features<T>(L, r, (const T *)L.V, wv, (const T *)L.Pv, L.feat, s);
       return;
     }
-    // one feature / output buffer for all levels, sized by the first (and
-    // finest) level that uses it
-    if (nf > lcap) {
-      if (lF) pool().release(lF);
-      if (lY) pool().release(lY);
-      lF = pool().template get<float>(nf * BAMG_MLP_IN);
-      lY = pool().template get<float>(nf * BAMG_MLP_OUT);
-      lcap = nf;
-    }
-    mlp_features<T>(L, r, (const T *)L.V, wv, (const T *)L.Pv, lF, s);
-    mlp_forward(h->opt.mlp, lF, L.nF, lY, 1, s);
-    mlp_select<T>(L, r, (const T *)L.V, wv, lY, (T *)L.Pv, h->lcount, s);
+    // features, network and objective test of every F row in one launch
+    mlp_apply<T>(L, r, (const T *)L.V, wv, h->opt.mlp, (T *)L.Pv, h->lcount, s);
   }
-  float *lF = nullptr, *lY = nullptr;  // learned-row scratch
-  size_t lcap = 0;
 
   // Algorithm 1 (bamg_mle) from level l: smoothing, then mu passes of the
   // inner loop (fits, Galerkin products, injection, recursion,
@@ -520,8 +508,6 @@ void setup_all(bamg_handle *h, const bamg_csr *A, const bamg_geometry *geom) {
   philox_testvecs(h->lv[0].U, h->lv[0].V, h->prec, n, r, o.seed, s);
   for (int cyc = 1; cyc <= o.setup_cycles; ++cyc) S.mle(0, cyc);
 
-  if (S.lF) pool.release(S.lF);
-  if (S.lY) pool.release(S.lY);
 
   // ---- coarse pseudo-inverse and x0
   S.pinv();
