@@ -148,6 +148,15 @@ typedef struct {
   double cr_beta;       /* 0.7, in [0, 1] */
   int32_t cr_sweeps;    /* 5, 1..64 */
   int32_t cr_rounds;    /* 10, 0..64 */
+  /* 1 = flexible GMRES: right preconditioning with the preconditioned
+   * vectors z_j = C v_j kept (x = x0 + Z y, and B z_j enters the Arnoldi
+   * process), so a preconditioner that is not exactly one linear map (the
+   * FP32 V-cycles of BAMG_PRECISION_MIXED round differently for each input)
+   * still gives the least true residual over the space it spans; n x restart
+   * more FP64 storage. 0 (default) = GMRES on the left-preconditioned residual
+   * equation C B e = -C B x^(0) of Section 6. In a batch, flexible chains
+   * solve on the library streams, not in the persistent launch. */
+  int32_t flexible;
 } bamg_options;
 
 /* Cycle shapes. A W-cycle takes two cycles of its own shape on the next

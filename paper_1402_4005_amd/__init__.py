@@ -67,7 +67,7 @@ class Options(C.Structure):
                 ("cycle", C.c_int32), ("mu", C.c_int32), ("restriction", C.c_int32),
                 ("profile_setup", C.c_int32), ("learned_max_iters", C.c_int32),
                 ("cr_theta", C.c_double), ("cr_beta", C.c_double), ("cr_sweeps", C.c_int32),
-                ("cr_rounds", C.c_int32)]
+                ("cr_rounds", C.c_int32), ("flexible", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

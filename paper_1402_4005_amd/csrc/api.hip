@@ -224,6 +224,7 @@ bamg_status bamg_default_options(bamg_options *o) {
   o->cr_beta = 0.7;
   o->cr_sweeps = 5;
   o->cr_rounds = 10;
+  o->flexible = 0;
   return BAMG_OK;
 }
 
@@ -268,6 +269,7 @@ static bamg_status check_options(const bamg_options *o) {
   if (!std::isfinite(o->cr_theta) || !(o->cr_beta >= 0.0 && o->cr_beta <= 1.0) ||
       o->cr_sweeps < 1 || o->cr_sweeps > 64 || o->cr_rounds < 0 || o->cr_rounds > 64)
     return BAMG_E_ARG;
+  if (o->flexible != 0 && o->flexible != 1) return BAMG_E_ARG;
   if (o->learned < BAMG_LEARNED_OFF || o->learned > BAMG_LEARNED_RECORD) return BAMG_E_ARG;
   if (o->learned == BAMG_LEARNED_USE && !o->mlp) return BAMG_E_ARG;
   return BAMG_OK;

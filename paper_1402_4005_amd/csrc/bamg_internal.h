@@ -121,6 +121,7 @@ struct bamg_handle {
   // GMRES storage, allocated on first use
   int gm_m = 0;
   double *gV = nullptr, *gBV = nullptr, *gw = nullptr, *gx0 = nullptr, *gbx0 = nullptr;
+  double *gZ = nullptr;  // flexible GMRES: z_j = C v_j (then gBV holds B z_j)
   double *gH = nullptr, *gsc = nullptr;
   void *vb = nullptr, *vx = nullptr;  // FP32 staging for a mixed V-cycle
   double *vcin = nullptr;             // fixed V-cycle input inside GMRES

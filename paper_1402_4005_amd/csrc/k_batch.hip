@@ -852,6 +852,7 @@ bool batch_persistent_eligible(const bamg_handle *h, int restart) {
   if (!h || restart < 1 || restart > kBatchMaxRestart) return false;
   if (h->opt.cycle != BAMG_CYCLE_V && h->opt.cycle != BAMG_CYCLE_NONE) return false;
   if (h->opt.learned == BAMG_LEARNED_USE && h->opt.learned_max_iters > 0) return false;
+  if (h->opt.flexible) return false;  // the launch runs the left-preconditioned GMRES only
   return h->L >= 1 && h->prof_kernel < 0 && !h->aux;  // no validation still running
 }
 

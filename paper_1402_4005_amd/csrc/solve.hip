@@ -204,6 +204,7 @@ void gmres_buffers(bamg_handle *h, int m) {
     h->gx0 = pool.get<double>(n);
     h->gbx0 = pool.get<double>(n);
     h->gH = pool.get<double>((size_t)(m + 1) * m + 4 * (m + 2) + 64);
+    h->gZ = h->opt.flexible ? pool.get<double>((size_t)m * n) : nullptr;
     h->gsc = pool.get<double>((size_t)(m + 2) * nblk * 2 + 2 * nblk + 16);
     if (h->prec != 0) {
       h->vb = pool.get<float>(n);
@@ -252,6 +253,7 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
 
   const Csr &B = L0.B;
   const int lanes = L0.lanes, threads = L0.threads;
+  const bool flex = h->opt.flexible != 0;
   double *hf = h->hred;
   auto read_flags = [&]() {
     HIPCHK(hipMemcpyAsync(hf, flags, sizeof(double) * 16, hipMemcpyDeviceToHost, s));
@@ -268,13 +270,17 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
   bamg_status st = BAMG_OK;
   while (!conv && it < maxit) {
     spmv<double>(B, h->B64, h->gx0, h->gbx0, nullptr, 0, lanes, s, threads);  // B x0
-    negate_copy(h->gbx0, h->vcin, n, s);                              // r0 = -B x0
-    precondition_fixed(h, s);                                         // z = C r0
+    if (flex) {
+      negate_copy(h->gbx0, h->gw, n, s);  // r0 = -B x0
+    } else {
+      negate_copy(h->gbx0, h->vcin, n, s);  // r0 = -B x0
+      precondition_fixed(h, s);             // z = C r0
+    }
     multi_dot(h->gV, n, 0, h->gw, part, nblk, s);
     finalize_multi(part, nblk, 1, c1, s);
     k_krylov_start<<<1, 64, 0, s>>>(c1, g, m, flags);
     LAUNCHCHK();
-    scale_vec(h->gw, flags + 3, h->gV, n, s);  // v_0 = z / beta
+    scale_vec(h->gw, flags + 3, h->gV, n, s);  // v_0 = z / beta (flexible: r0 / beta)
     int used = 0;
     bool broke = false;
     // Iteration j is enqueued with its status flags written by the residual
@@ -286,12 +292,19 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
     // kernel, which is the first to read it.
     auto enqueue = [&](int j) {
       double *vj = h->gV + (size_t)j * n, *bvj = h->gBV + (size_t)j * n;
-      if (j == 0)
+      if (flex) {
+        // flexible: z_j = C v_j kept, w = B z_j (kept too, for the true residual)
+        double *zj = h->gZ + (size_t)j * n;
+        if (j > 0) scale_vec(h->gw, flags + 3, vj, n, s);  // v_j = w / h_{j,j-1}
+        precondition(h, vj, zj, s);
+        spmv_dual(B, h->B64, zj, bvj, h->gw, lanes, s, threads);
+      } else if (j == 0) {
         spmv_dual(B, h->B64, vj, bvj, h->vcin, lanes, s, threads);  // B v_0
-      else
+      } else {
         spmv_dual_scaled(B, h->B64, h->gw, flags + 3, vj, bvj, h->vcin, lanes, s,
                          threads);  // v_j, B v_j
-      precondition_fixed(h, s);  // w = C B v_j
+      }
+      if (!flex) precondition_fixed(h, s);  // w = C B v_j
       // Gram-Schmidt, twice; the first update and the second pass's dots in one kernel
       multi_dot(h->gV, n, j + 1, h->gw, part, nblk, s);
       finalize_multi(part, nblk, j + 2, c1, s);  // c1[0..j], c1[j+1] = |w|^2
@@ -304,7 +317,8 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
       // y goes straight to this iteration's ring slot
       double *ys = yring + (size_t)(j & 1) * (m + 2);
       gmres_arnoldi_update(H, cs, sn, g, ys, c1, c2, part2, nblk, nullptr, j, m, flags, s);
-      residual_check_partials(h->gx0, h->gbx0, h->gV, h->gBV, ys, n, j + 1, part3, nblk, s);
+      residual_check_partials(h->gx0, h->gbx0, flex ? h->gZ : h->gV, h->gBV, ys, n, j + 1, part3,
+                              nblk, s);
       residual_check_finalize(part3, nblk, tol, flags, h->hred_dev + 16 * (j & 1), s);
       HIPCHK(hipEventRecord(h->gm_ev[j & 1], s));
     };
@@ -337,7 +351,8 @@ void gmres_run(bamg_handle *h, double *x, int m, double tol, int maxit, int use_
       }
     }
     if (used > 0)
-      update_iterate(h->gx0, h->gV, yring + (size_t)((used - 1) & 1) * (m + 2), n, used, s);
+      update_iterate(h->gx0, flex ? h->gZ : h->gV, yring + (size_t)((used - 1) & 1) * (m + 2), n,
+                     used, s);
     if (st != BAMG_OK) break;
     if (broke && !conv && ++breakdowns >= 2) {
       st = BAMG_E_BREAKDOWN;

@@ -184,3 +184,20 @@ def test_w_cycle_chain_goes_through_per_chain_solve():
         assert sts[i] == 0 and info.iterations == infos[i].iterations, i
         assert np.array_equal(x.cpu().numpy(), xs[i].cpu().numpy()), i
     b.close()
+
+
+@pytest.mark.parametrize("solver", ["persistent", "auto"])
+def test_flexible_chains_solve_on_the_streams(solver):
+    """Flexible-GMRES chains leave the persistent launch (it runs the
+    left-preconditioned GMRES only) for the per-chain solve on the streams,
+    whatever the solver asked for: the same bits as the streams alone."""
+    ms = [(chaingen.tandem(33, *PAPER), dict(r=8, coarse_max=300, nu_setup=5, precision="mixed",
+                                             flexible=1), 300),
+          (chaingen.delaunay_walk(3000, 21), dict(PLANAR, flexible=1), 300),
+          (chaingen.tandem(17, *PAPER), dict(r=8, coarse_max=30), 300)]
+    per = solve_batch(ms, solver)
+    ref = solve_batch(ms, "streams")
+    for (i, x, inf, st), (_, xr, infr, str_) in zip(per, ref):
+        assert st == 0 and str_ == 0 and inf.converged, (i, st, str_)
+        assert inf.iterations == infr.iterations, i
+        assert np.array_equal(x.cpu().numpy(), xr.cpu().numpy()), i
