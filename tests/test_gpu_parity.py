@@ -80,6 +80,12 @@ CASES = [
      dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=500, interp_rule=0)),
     ("hub4000_plainls", lambda: chaingen.hub_walk(4000, 8, 200, 7),
      dict(r=8, max_interp=3, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99, interp_rule=0)),
+    # more than 8 test vectors or more than 4 interpolation points: the
+    # least-squares fit's wide form (up to 16 vectors and 8 points)
+    ("tandem65_r12", lambda: chaingen.tandem(65, 11 / 31, 10 / 31, 10 / 31),
+     dict(r=12, max_interp=4, coarse_max=300, nu_setup=5)),
+    ("delaunay3000_c6", lambda: chaingen.delaunay_walk(3000, 12),
+     dict(r=8, max_interp=6, nu_pre=5, nu_post=5, nu_setup=5, coarse_max=99)),
     # two passes of the inner loop of Algorithm 1 per level visit (mu = 2)
     ("tandem33_3lev_mu2", lambda: chaingen.tandem(33, 11 / 31, 10 / 31, 10 / 31),
      dict(r=6, max_levels=3, coarse_max=1, mu=2)),
