@@ -286,12 +286,16 @@ __device__ __forceinline__ void svd_pair(int k, int ir, int bs, bool all, int &p
 // al = |w_p|^2, be = |w_q|^2, ga = w_p . w_q: (c, s) with w_p <- c w_p - s w_q,
 // w_q <- s w_p + c w_q, zeroing the new inner product; none when the pair is
 // orthogonal to the tolerance (|ga| <= tol sqrt(al be)).
+constexpr double kSvdTol = 1e-15;
+// whether svd_rotation rotates the pair (the same test, without the angle)
+__device__ __forceinline__ bool svd_needs_rotation(double al, double be, double ga) {
+  return !(ga == 0.0 || ga * ga <= kSvdTol * kSvdTol * (al * be));
+}
 __device__ __forceinline__ bool svd_rotation(double al, double be, double ga, double &c,
                                              double &sn) {
-  const double tol = 1e-15;
   c = 1.0;
   sn = 0.0;
-  if (ga == 0.0 || ga * ga <= tol * tol * (al * be)) return false;
+  if (!svd_needs_rotation(al, be, ga)) return false;
   const double zeta = (be - al) / (2.0 * ga);
   const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
   c = rsqrt(1.0 + t * t);
@@ -479,11 +483,28 @@ __global__ void __launch_bounds__(64 * BS)
   // 32 threads per column (blockDim.x = 32 cols)
   const int lc = threadIdx.x / 32, li = threadIdx.x % 32, lg = gcol(lc);
   const double *jsrc = Jm + (size_t)lg * n;
+  // J fetched at the start. With 8-column blocks straight into the MFMA
+  // operand layout of the J product (tile p of this wave, row tile
+  // it = wv + 8 p: lane ln holds J[16 it + ln % 16][column 4 kk + ln / 16]),
+  // so that product reads registers, not LDS; with 16-column blocks NP rows
+  // of one column per thread, staged through LDS for the product.
   double jr[NP];
+  if constexpr (BS == 8) {
+    static_assert(NP == 36, "9 row tiles of 4 k-steps per lane");
+    const int wv0 = threadIdx.x / kWave, l0 = threadIdx.x % kWave;
 #pragma unroll
-  for (int j = 0; j < NP; ++j) {
-    const int i = li + 32 * j;
-    jr[j] = lg < n && i < n ? jsrc[i] : 0.0;
+    for (int pt = 0; pt < 9; ++pt)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int row = 16 * (wv0 + 8 * pt) + l0 % 16, g = gcol(4 * kk + l0 / 16);
+        jr[4 * pt + kk] = row < n && g < n ? Jm[(size_t)g * n + row] : 0.0;
+      }
+  } else {
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const int i = li + 32 * j;
+      jr[j] = lg < n && i < n ? jsrc[i] : 0.0;
+    }
   }
   {
     // W's columns in chunks of NP rows per thread, every load of a chunk in
@@ -566,10 +587,9 @@ __global__ void __launch_bounds__(64 * BS)
   __syncthreads();
   for (int e = threadIdx.x; e < cc; e += nt) {
     const int a = e / cols, b = e % cols;
-    if (a < b && (round == 0 || (a < bs && b >= bs))) {
-      double c, sn;
-      if (svd_rotation(Ga[a * cols + a], Ga[b * cols + b], Ga[e], c, sn)) need = 1;
-    }
+    if (a < b && (round == 0 || (a < bs && b >= bs)) &&
+        svd_needs_rotation(Ga[a * cols + a], Ga[b * cols + b], Ga[e]))
+      need = 1;
   }
   __syncthreads();
   // Inner rounds: the rotation of each of the bs pairs (lane k: pair k) from
@@ -674,7 +694,8 @@ __global__ void __launch_bounds__(64 * BS)
   const double *R = Ra;
   if (nrot > 0) {
     // X[:, pair] <- X[:, pair] R for X = W (from Ws), then X = J (from the
-    // registers fetched at the start, the rows past NP * 32 from memory).
+    // registers fetched at the start: as MFMA operands with 8-column blocks,
+    // else staged through Ws, the rows past NP * 32 from memory).
     // Each tile is formed transposed, (R^T X^T) for 16 pair columns x 16
     // rows: the FP64 MFMA leaves entry (l / 16 + 4 r, l % 16) of its output
     // tile in lane l, register r, so lane l holds row 16 it + l % 16 and a
@@ -683,6 +704,27 @@ __global__ void __launch_bounds__(64 * BS)
     const int rt = (n + 15) / 16, ntl = rt * ct;
     for (int pass = 0; pass < 2; ++pass) {
       double *__restrict__ Xm = pass == 0 ? Wm : Jm;
+      if (BS == 8 && pass == 1) {
+        // J from the registers: tiles wv + 8 p, p = 0 .. 8 (n <= 1152)
+#pragma unroll
+        for (int pt = 0; pt < 9; ++pt) {
+          const int it = wv + 8 * pt;
+          if (it >= rt) break;
+          svd_d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const int k = 4 * kk + ln / 16;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(R[k * cols + ln % 16], jr[4 * pt + kk], acc,
+                                                       0, 0, 0);
+          }
+          const int i = 16 * it + ln % 16;
+          for (int r = 0; r < 4; ++r) {
+            const int g = gcol(ln / 16 + 4 * r);
+            if (i < n && g < n) Jm[(size_t)g * n + i] = acc[r];
+          }
+        }
+        continue;
+      }
       if (pass == 1) {
         double *dst = Ws + (size_t)lc * n;
 #pragma unroll
@@ -717,7 +759,9 @@ __global__ void __launch_bounds__(64 * BS)
         tile_store(tl, a0);
         if (t2 < ntl) tile_store(t2, a1);
       }
-      __syncthreads();
+      // the J pass of 16-column blocks overwrites Ws; that of 8-column
+      // blocks reads only registers and R, so no wave waits for the others
+      if (BS != 8) __syncthreads();
     }
     if (threadIdx.x == 0) {
       atomicAdd(&ctrl[sweep], nrot);
