@@ -162,6 +162,14 @@ int bamg_handle::finish_validation() {
 // Outcome of the input validation (BAMG_OK when it was not requested).
 int bamg_handle::validation_result() {
   if (!vflag) return BAMG_OK;
+  try {
+    // levels of the search beyond those enqueued with it, if it needs them
+    if (vlevels > 0 && vqueues)
+      bamg::reach_finish(lv[0].B, lv[0].Bt, vvisited, vqueues, vflag, vlevels, pool.s);
+    vlevels = 0;
+  } catch (...) {
+    return BAMG_E_DEVICE;
+  }
   int hv[4] = {0, 0, 0, 0};
   if (hipMemcpyAsync(hv, vflag, sizeof(hv), hipMemcpyDeviceToHost, pool.s) != hipSuccess ||
       hipStreamSynchronize(pool.s) != hipSuccess)

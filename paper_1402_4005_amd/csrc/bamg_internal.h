@@ -145,6 +145,7 @@ struct bamg_handle {
   int *vflag = nullptr;  // device: [colsum bits, reached forward, reached backward, -]
   unsigned *vvisited = nullptr;  // the search's buffers, released after the join
   int *vqueues = nullptr;
+  int vlevels = 0;               // levels the global-form search enqueued
   int vstatus = BAMG_OK;         // outcome once joined
   void join_validation(bool wait_main);
   int validation_result();
@@ -206,8 +207,10 @@ int check_input(Pool &pool, const int *arp, const int *aci, const double *aval, 
 void colsum_launch(const Csr &Bt, const double *btv, int *flag, hipStream_t s);
 // visited: 2 ceil(n / 32) words of device scratch (bitmaps, used when they
 // do not fit in LDS or when force_global is set); queues: 4 n ints
-void reach_launch(const Csr &B, const Csr &Bt, unsigned *visited, int *queues, int *flag,
-                  bool force_global, hipStream_t s);
+int reach_launch(const Csr &B, const Csr &Bt, unsigned *visited, int *queues, int *flag,
+                 bool force_global, hipStream_t s);
+void reach_finish(const Csr &B, const Csr &Bt, unsigned *visited, int *queues, int *flag,
+                  int levels, hipStream_t s);
 int validation_status(const int *h, int n);
 void sym_graph(Pool &pool, const Csr &B, const Csr &Bt, Csr &G, hipStream_t s);
 void geom_cf(int n, int nx, int gkind, int *cf, hipStream_t s);

@@ -96,99 +96,70 @@ __global__ void k_colsum_check(const int *__restrict__ trp, const int *__restric
   if (!(fabs(s - 1.0) <= 1e-12)) atomicOr(flag, 2);
 }
 
-// Reachability from state 0, forward (block 0, rows of B) and backward
-// (block 1, rows of B^T) in one launch, level-synchronous breadth-first
-// search with the frontier queues in global memory. The visited set is a
-// bitmap: in LDS whenever it fits (LDSMAP, n up to about 1.3 M states),
-// else in global memory (n / 8 bytes per direction, 525 KB at 4.2 M states,
-// small enough to stay in the L2 of the CU's XCD), so each level's chain of
-// dependent accesses is an atomic OR on a cached word. An int per state
-// updated by compare-and-swap (16.8 MB per direction at 4.2 M states) sent
-// every access to HBM: 122 ms per tandem 2049^2 setup.
-
-// global-bitmap form: hops per level and stack entries per thread; an entry
-// is the state (below 2^26) packed with its depth, and its row range
+// Reachability from state 0, forward (rows of B) and backward (rows of B^T),
+// in two forms.
+//
+// LDS form (n up to about 1.3 M states): one workgroup per direction,
+// level-synchronous breadth-first search with the visited bitmap in LDS and
+// the frontier queues in global memory.
+//
+// Global form (larger chains): the visited bitmap in global memory (n / 8
+// bytes per direction) and one launch per frontier level, each with many
+// workgroups per direction, so the scattered claims and row loads of a level
+// are spread over many CUs instead of the memory pipeline of one; the kernel
+// boundaries order the levels (no grid barrier, no co-residency needed). The
+// order of the search does not matter for the visited set, so each thread
+// follows the states it claims depth first, up to kReachDepth hops and
+// kReachStack pending states (a per-thread stack in LDS), and hands the rest
+// to the next level's frontier: far fewer levels than the graph's diameter.
+// A neighbour's row pointers are loaded together with the atomic that claims
+// it (used only if the claim succeeds), so a hop is two dependent round
+// trips, not three. Every state is claimed once, so every stack and every
+// frontier is finite, and at most n + 1 levels are non-empty. The states
+// reached are counted from the bitmap at the end.
 constexpr int kReachDepth = 32, kReachStack = 10, kReachStateBits = 26;
+constexpr int kReachThreads = 256, kReachBlocks = 64;  // global form, per direction
+constexpr int kReachLevels = 512;  // levels enqueued at launch; more at the join if needed
 
-template <bool LDSMAP>
 __global__ void __launch_bounds__(1024)
-    k_reach2(const int *__restrict__ rp0, const int *__restrict__ ci0,
-             const int *__restrict__ rp1, const int *__restrict__ ci1, int n,
-             unsigned *__restrict__ visited, int *__restrict__ queues, int *__restrict__ out) {
+    k_reach_lds(const int *__restrict__ rp0, const int *__restrict__ ci0,
+                const int *__restrict__ rp1, const int *__restrict__ ci1, int n,
+                int *__restrict__ queues, int *__restrict__ out) {
   extern __shared__ unsigned lbits[];
-  __shared__ int cur_n, nxt_n, total;
+  __shared__ int cur_n, nxt_n, found;
   const int b = blockIdx.x, t = threadIdx.x;
   const int *rp = b ? rp1 : rp0, *ci = b ? ci1 : ci0;
   const int words = (n + 31) >> 5;
-  unsigned *bits = LDSMAP ? lbits : visited + (size_t)b * words;
   int *qa = queues + (size_t)b * 2 * n, *qb = qa + n;
-  for (int i = t; i < words; i += blockDim.x) bits[i] = i == 0 ? 1u : 0u;
+  for (int i = t; i < words; i += blockDim.x) lbits[i] = i == 0 ? 1u : 0u;
   if (t == 0) {
     qa[0] = 0;
     cur_n = 1;
     nxt_n = 0;
-    total = 1;
+    found = 0;
   }
   __syncthreads();
   int *cur = qa, *nxt = qb;
-  // With the visited bits in global memory every hop costs dependent memory
-  // round trips, and a frontier level costs two barriers on top. The order
-  // of the search does not matter for the visited set, so there each thread
-  // follows the states it claims depth first, up to kReachDepth hops and
-  // kReachStack pending states (a per-thread stack in LDS), and hands the
-  // rest to the next frontier: far fewer levels. A neighbour's row pointers
-  // are loaded together with the atomic that claims it (used only if the
-  // claim succeeds), so a hop is two dependent round trips, not three.
-  // Every state is claimed once (the atomic bit), so every stack and every
-  // frontier is finite.
-  int *stk = reinterpret_cast<int *>(lbits) + (LDSMAP ? 0 : t * 3 * kReachStack);
-  __shared__ int found;
-  if (t == 0) found = 0;
-  __syncthreads();
   while (cur_n > 0) {
     const int cn = cur_n;
     int mine = 0;
     for (int idx = t; idx < cn; idx += blockDim.x) {
-      int sp = 0, d = 0;
       const int v0 = cur[idx];
-      int kb = rp[v0], ke = rp[v0 + 1];
-      for (;;) {
-        // four neighbours per round: their indices are loaded together
-        // (positions past the row end reload its last entry and are skipped)
-        for (int k = kb; k < ke; k += 4) {
-          int us[4], r0[4], r1[4];
-          unsigned old[4];
+      const int kb = rp[v0], ke = rp[v0 + 1];
+      for (int k = kb; k < ke; k += 4) {
+        int us[4];
+        unsigned old[4];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) us[j] = ci[min(k + j, ke - 1)];
+        for (int j = 0; j < 4; ++j) us[j] = ci[min(k + j, ke - 1)];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int u = us[j];
-            old[j] = k + j < ke ? atomicOr(&bits[u >> 5], 1u << (u & 31)) : ~0u;
-            if (!LDSMAP) {
-              r0[j] = rp[u];
-              r1[j] = rp[u + 1];
-            }
-          }
+        for (int j = 0; j < 4; ++j)
+          old[j] = k + j < ke ? atomicOr(&lbits[us[j] >> 5], 1u << (us[j] & 31)) : ~0u;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int u = us[j];
-            if (k + j >= ke || (old[j] >> (u & 31)) & 1u) continue;
-            ++mine;
-            if (!LDSMAP && d + 1 < kReachDepth && sp < kReachStack) {
-              stk[3 * sp] = u | ((d + 1) << kReachStateBits);
-              stk[3 * sp + 1] = r0[j];
-              stk[3 * sp + 2] = r1[j];
-              ++sp;
-            } else {
-              nxt[atomicAdd(&nxt_n, 1)] = u;
-            }
-          }
+        for (int j = 0; j < 4; ++j) {
+          if (k + j >= ke || (old[j] >> (us[j] & 31)) & 1u) continue;
+          ++mine;
+          nxt[atomicAdd(&nxt_n, 1)] = us[j];
         }
-        if (sp == 0) break;
-        --sp;
-        d = stk[3 * sp] >> kReachStateBits;
-        kb = stk[3 * sp + 1];
-        ke = stk[3 * sp + 2];
       }
     }
     if (mine) atomicAdd(&found, mine);
@@ -202,13 +173,128 @@ __global__ void __launch_bounds__(1024)
     cur = nxt;
     nxt = tmp;
   }
-  if (t == 0) out[b] = total + found;
+  if (t == 0) out[b] = 1 + found;
+}
+
+// Global form. ctl + 4 d holds the frontier sizes of direction d for the
+// levels k = 0, 1, 2 (mod 3); direction d's queues are queues + 2 d n (level
+// k reads half k & 1 and appends to the other).
+__global__ void k_reach_init(unsigned *__restrict__ visited, int *__restrict__ queues,
+                             int *__restrict__ ctl, int n) {
+  const long words = (n + 31) >> 5;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < 2 * words) visited[t] = t % words == 0 ? 1u : 0u;
+  if (t < 2) {
+    queues[(size_t)t * 2 * n] = 0;
+    ctl[4 * t] = 1;
+    ctl[4 * t + 1] = 0;
+    ctl[4 * t + 2] = 0;
+  }
+}
+
+// Level `level` of both directions: blocks [0, kReachBlocks) forward, the
+// rest backward. Returns at once when the level's frontier is empty.
+__global__ void __launch_bounds__(kReachThreads)
+    k_reach_level(const int *__restrict__ rp0, const int *__restrict__ ci0,
+                  const int *__restrict__ rp1, const int *__restrict__ ci1, int n,
+                  unsigned *__restrict__ visited, int *__restrict__ queues,
+                  int *__restrict__ ctl, int level) {
+  __shared__ int stk_all[kReachThreads * 3 * kReachStack];
+  const int d = blockIdx.x / kReachBlocks, wg = blockIdx.x % kReachBlocks;
+  int *c = ctl + 4 * d;
+  const int cn = c[level % 3];
+  // the counter the next level appends to holds the previous level's
+  // frontier size, which no block of this launch reads; it is cleared by
+  // every level, empty ones included, so a direction that has finished
+  // keeps reading empty frontiers while the other goes on
+  if (wg == 0 && threadIdx.x == 0) c[(level + 2) % 3] = 0;
+  if (cn == 0) return;
+  const int *rp = d ? rp1 : rp0, *ci = d ? ci1 : ci0;
+  const size_t words = (size_t)((n + 31) >> 5);
+  unsigned *bits = visited + d * words;
+  const int *cur = queues + (size_t)d * 2 * n + (size_t)(level & 1) * n;
+  int *nxt = queues + (size_t)d * 2 * n + (size_t)((level + 1) & 1) * n;
+  int *nxt_n = c + (level + 1) % 3;
+  int *stk = stk_all + threadIdx.x * 3 * kReachStack;
+  for (int idx = wg * kReachThreads + threadIdx.x; idx < cn; idx += kReachBlocks * kReachThreads) {
+    int sp = 0, dep = 0;
+    const int v0 = cur[idx];
+    int kb = rp[v0], ke = rp[v0 + 1];
+    for (;;) {
+      // four neighbours per round: their indices are loaded together
+      // (positions past the row end reload its last entry and are skipped)
+      for (int k = kb; k < ke; k += 4) {
+        int us[4], r0[4], r1[4];
+        unsigned old[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) us[j] = ci[min(k + j, ke - 1)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int u = us[j];
+          old[j] = k + j < ke ? atomicOr(&bits[u >> 5], 1u << (u & 31)) : ~0u;
+          r0[j] = rp[u];
+          r1[j] = rp[u + 1];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int u = us[j];
+          if (k + j >= ke || (old[j] >> (u & 31)) & 1u) continue;
+          if (dep + 1 < kReachDepth && sp < kReachStack) {
+            stk[3 * sp] = dep + 1;
+            stk[3 * sp + 1] = r0[j];
+            stk[3 * sp + 2] = r1[j];
+            ++sp;
+          } else {
+            nxt[atomicAdd(nxt_n, 1)] = u;
+          }
+        }
+      }
+      if (sp == 0) break;
+      --sp;
+      dep = stk[3 * sp];
+      kb = stk[3 * sp + 1];
+      ke = stk[3 * sp + 2];
+    }
+  }
+}
+
+// out[d] += states set in direction d's bitmap; grid (blocks, 2)
+__global__ void k_reach_count(const unsigned *__restrict__ visited, int n, int *__restrict__ out) {
+  __shared__ int sh[4];
+  const long words = (n + 31) >> 5;
+  const unsigned *bits = visited + blockIdx.y * words;
+  int cnt = 0;
+  for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < words;
+       w += (long)gridDim.x * blockDim.x)
+    cnt += __popc(bits[w]);
+  for (int o = kWave / 2; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+  if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(&out[blockIdx.y], sh[0] + sh[1] + sh[2] + sh[3]);
+}
+
+static void reach_levels(const Csr &B, const Csr &Bt, unsigned *visited, int *queues, int k0,
+                         int k1, hipStream_t s) {
+  const int n = B.nr;
+  int *ctl = queues + 4 * (size_t)n;
+  for (int k = k0; k < k1; ++k) {
+    k_reach_level<<<2 * kReachBlocks, kReachThreads, 0, s>>>(B.rp, B.ci, Bt.rp, Bt.ci, n,
+                                                             visited, queues, ctl, k);
+    LAUNCHCHK();
+  }
+}
+
+static void reach_count(unsigned *visited, int n, int *flag, hipStream_t s) {
+  k_reach_count<<<dim3(64, 2), 256, 0, s>>>(visited, n, flag + 1);
+  LAUNCHCHK();
 }
 
 // Launch the reachability search on stream s (the caller's auxiliary
-// stream); results land in flag[1], flag[2] (states reached each way).
-void reach_launch(const Csr &B, const Csr &Bt, unsigned *visited, int *queues, int *flag,
-                  bool force_global, hipStream_t s) {
+// stream); the states reached each way are added to flag[1], flag[2] (zero
+// before). queues: 4 n + 8 ints. Returns the number of levels enqueued in the
+// global form (finish with reach_finish), 0 for the LDS form.
+int reach_launch(const Csr &B, const Csr &Bt, unsigned *visited, int *queues, int *flag,
+                 bool force_global, hipStream_t s) {
   const int n = B.nr;
   const size_t shm = sizeof(unsigned) * (size_t)((n + 31) / 32);
   int dev = 0, maxlds = 65536;
@@ -216,16 +302,44 @@ void reach_launch(const Csr &B, const Csr &Bt, unsigned *visited, int *queues, i
   HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   if (n >= (1 << kReachStateBits)) fail(BAMG_E_ARG, "reachability search: more than 2^26 states");
   if (!force_global && shm + 256 <= (size_t)maxlds) {
-    HIPCHK(hipFuncSetAttribute((const void *)k_reach2<true>,
+    HIPCHK(hipFuncSetAttribute((const void *)k_reach_lds,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-    k_reach2<true><<<2, 1024, shm, s>>>(B.rp, B.ci, Bt.rp, Bt.ci, n, visited, queues, flag + 1);
-  } else {
-    const size_t stk = sizeof(int) * 3 * kReachStack * 1024;  // per-thread stacks
-    HIPCHK(hipFuncSetAttribute((const void *)k_reach2<false>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)stk));
-    k_reach2<false><<<2, 1024, stk, s>>>(B.rp, B.ci, Bt.rp, Bt.ci, n, visited, queues, flag + 1);
+    k_reach_lds<<<2, 1024, shm, s>>>(B.rp, B.ci, Bt.rp, Bt.ci, n, queues, flag + 1);
+    LAUNCHCHK();
+    return 0;
   }
+  const long words = (n + 31) / 32;
+  k_reach_init<<<ceil_div(2 * words, 256), 256, 0, s>>>(visited, queues, queues + 4 * (size_t)n,
+                                                        n);
   LAUNCHCHK();
+  reach_levels(B, Bt, visited, queues, 0, kReachLevels, s);
+  reach_count(visited, n, flag, s);
+  return kReachLevels;
+}
+
+// After the work reach_launch enqueued has completed: a graph whose search
+// needs more than the enqueued levels (a long path: about one level per
+// kReachDepth states) gets further levels, 256 per host check, and is
+// counted again. Runs on stream s; returns when the counts in flag are final.
+void reach_finish(const Csr &B, const Csr &Bt, unsigned *visited, int *queues, int *flag,
+                  int levels, hipStream_t s) {
+  if (levels <= 0) return;
+  const int n = B.nr;
+  int *ctl = queues + 4 * (size_t)n;
+  bool more = false;
+  for (;;) {
+    int hc[8];
+    HIPCHK(hipMemcpyAsync(hc, ctl, sizeof(hc), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hc[levels % 3] == 0 && hc[4 + levels % 3] == 0) break;
+    reach_levels(B, Bt, visited, queues, levels, levels + 256, s);
+    levels += 256;
+    more = true;
+  }
+  if (more) {
+    fill_i32(flag + 1, 0, 2, s);
+    reach_count(visited, n, flag, s);
+  }
 }
 
 // Structural checks of the caller's CSR (indices in range, ascending,

@@ -358,6 +358,35 @@ def test_hub_rows_are_f_points():
     assert ch.indptr[4001] - ch.indptr[4000] > 128
 
 
+def test_reachability_search_more_levels_than_enqueued():
+    """The global form of the strong-connectivity search enqueues a fixed
+    number of frontier levels with the setup; a birth-death chain needs about
+    one level per 31 states (each thread follows at most 32 hops), about
+    1600 at 50,000 states, so the join adds levels. Its verdicts equal the
+    LDS form's: the chain is irreducible (whatever the setup itself then
+    reports, it is not BAMG_E_REDUCIBLE); with the edge into state 0 cut
+    (its mass kept on the diagonal) it is reducible."""
+    ch = chaingen.birth_death(50000, 1.0)
+    A = ch.to_scipy().tolil()
+    A[1, 1] += A[0, 1]
+    A[0, 1] = 0.0
+    A = A.tocsr()
+    A.eliminate_zeros()
+    cut = chaingen.Chain(A, ch.geom)
+
+    def outcome(chain, validate):
+        try:
+            bamg.Hierarchy.from_chain(chain, bamg.options_for(chain, r=4, coarse_max=99,
+                                                              validate=validate)).close()
+            return 0
+        except bamg.BamgError as e:
+            return e.code
+
+    whole = [outcome(ch, v) for v in (1, 2)]
+    assert whole[0] == whole[1] and whole[0] != -3, whole
+    assert [outcome(cut, v) for v in (1, 2)] == [-3, -3]
+
+
 @pytest.mark.parametrize("validate", [1, 2])
 def test_reachability_search_both_forms(validate):
     """The strong-connectivity check in both of its forms (visited bitmap in
@@ -377,6 +406,14 @@ def test_reachability_search_both_forms(validate):
         bamg.Hierarchy.from_chain(bad, bamg.default_options(r=2, coarsening="mis", coarse_max=1,
                                                              max_levels=2, validate=validate))
     assert e.value.code == -3
+    # a setup that stops before its coarsest level (here: no coarsening at
+    # all) still runs the search it had not started, and reports its verdict:
+    # reducible for the two 3-cycles, a bad argument for a valid chain
+    for chain, code in ((bad, -3), (chaingen.tandem(3, 11 / 31, 10 / 31, 10 / 31), -1)):
+        with pytest.raises(bamg.BamgError) as e:
+            bamg.Hierarchy.from_chain(chain, bamg.default_options(
+                r=2, coarsening="mis", coarse_max=100, max_levels=2, validate=validate))
+        assert e.value.code == code
     # one-way edge: every state reachable from 0, but 0 not from state 5
     B = sp.lil_matrix((6, 6))
     for i in range(5):
