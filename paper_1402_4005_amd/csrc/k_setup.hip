@@ -176,9 +176,10 @@ __global__ void __launch_bounds__(1024)
   if (t == 0) out[b] = 1 + found;
 }
 
-// Global form. ctl + 4 d holds the frontier sizes of direction d for the
-// levels k = 0, 1, 2 (mod 3); direction d's queues are queues + 2 d n (level
-// k reads half k & 1 and appends to the other).
+// Global form. ctl + 32 d (a cache line of its own) holds the frontier
+// sizes of direction d for the levels k = 0, 1, 2 (mod 3); direction d's
+// queues are queues + 2 d n (level k reads half k & 1 and appends to the
+// other).
 __global__ void k_reach_init(unsigned *__restrict__ visited, int *__restrict__ queues,
                              int *__restrict__ ctl, int n) {
   const long words = (n + 31) >> 5;
@@ -186,9 +187,9 @@ __global__ void k_reach_init(unsigned *__restrict__ visited, int *__restrict__ q
   if (t < 2 * words) visited[t] = t % words == 0 ? 1u : 0u;
   if (t < 2) {
     queues[(size_t)t * 2 * n] = 0;
-    ctl[4 * t] = 1;
-    ctl[4 * t + 1] = 0;
-    ctl[4 * t + 2] = 0;
+    ctl[32 * t] = 1;
+    ctl[32 * t + 1] = 0;
+    ctl[32 * t + 2] = 0;
   }
 }
 
@@ -201,7 +202,7 @@ __global__ void __launch_bounds__(kReachThreads)
                   int *__restrict__ ctl, int level) {
   __shared__ int stk_all[kReachThreads * 3 * kReachStack];
   const int d = blockIdx.x / kReachBlocks, wg = blockIdx.x % kReachBlocks;
-  int *c = ctl + 4 * d;
+  int *c = ctl + 32 * d;
   const int cn = c[level % 3];
   // the counter the next level appends to holds the previous level's
   // frontier size, which no block of this launch reads; it is cleared by
@@ -245,7 +246,13 @@ __global__ void __launch_bounds__(kReachThreads)
             stk[3 * sp + 2] = r1[j];
             ++sp;
           } else {
-            nxt[atomicAdd(nxt_n, 1)] = u;
+            // one atomic per wave for the lanes appending here together
+            const unsigned long long act = __ballot(1);
+            const int leader = __ffsll((long long)act) - 1;
+            int base = 0;
+            if (threadIdx.x % kWave == leader) base = atomicAdd(nxt_n, __popcll(act));
+            base = __shfl(base, leader);
+            nxt[base + __popcll(act & ((1ull << (threadIdx.x % kWave)) - 1))] = u;
           }
         }
       }
@@ -291,7 +298,7 @@ static void reach_count(unsigned *visited, int n, int *flag, hipStream_t s) {
 
 // Launch the reachability search on stream s (the caller's auxiliary
 // stream); the states reached each way are added to flag[1], flag[2] (zero
-// before). queues: 4 n + 8 ints. Returns the number of levels enqueued in the
+// before). queues: 4 n + 64 ints. Returns the number of levels enqueued in the
 // global form (finish with reach_finish), 0 for the LDS form.
 int reach_launch(const Csr &B, const Csr &Bt, unsigned *visited, int *queues, int *flag,
                  bool force_global, hipStream_t s) {
@@ -328,10 +335,10 @@ void reach_finish(const Csr &B, const Csr &Bt, unsigned *visited, int *queues, i
   int *ctl = queues + 4 * (size_t)n;
   bool more = false;
   for (;;) {
-    int hc[8];
+    int hc[64];
     HIPCHK(hipMemcpyAsync(hc, ctl, sizeof(hc), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (hc[levels % 3] == 0 && hc[4 + levels % 3] == 0) break;
+    if (hc[levels % 3] == 0 && hc[32 + levels % 3] == 0) break;
     reach_levels(B, Bt, visited, queues, levels, levels + 256, s);
     levels += 256;
     more = true;

@@ -349,7 +349,7 @@ void setup_all(bamg_handle *h, const bamg_csr *A, const bamg_geometry *geom) {
       HIPCHK(hipEventRecord(h->aux_ready, s));
       HIPCHK(hipStreamWaitEvent(h->aux, h->aux_ready, 0));
       unsigned *visited = pool.get<unsigned>(2 * (size_t)((n + 31) / 32));
-      int *queues = pool.get<int>(4 * (size_t)n + 8);
+      int *queues = pool.get<int>(4 * (size_t)n + 64);
       h->vlevels = reach_launch(L0.B, L0.Bt, visited, queues, h->vflag, o.validate == 2, h->aux);
       HIPCHK(hipEventRecord(h->aux_done, h->aux));
       h->vvisited = visited;  // released after the join
