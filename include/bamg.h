@@ -48,7 +48,7 @@ enum {
   BAMG_E_BAD_DIAG = -4,        /* a zero or non-finite diagonal entry of some B_l */
   BAMG_E_COARSE = -5,          /* coarsest operator not of rank n_L - 1, or SVD failed */
   BAMG_E_BREAKDOWN = -6,       /* GMRES broke down twice without converging */
-  BAMG_E_NONFINITE = -7,       /* NaN or Inf met in an iterate */
+  BAMG_E_NONFINITE = -7,       /* NaN or Inf in an input entry or met in an iterate */
   BAMG_E_DEVICE = -8,          /* a HIP runtime call failed */
   BAMG_E_NOMEM = -9            /* device allocation failed */
 };
@@ -233,7 +233,12 @@ bamg_status bamg_default_options(bamg_options *out);
  * 1^T Q = 1^T of Section 5), the coarsest pseudo-inverse (eq.
  * coarse_grid_correction) and the initial iterate x0 (Section 6).
  * geom may be NULL. alloc may be NULL. On success *out owns all device
- * memory of the hierarchy; free it with bamg_destroy. */
+ * memory of the hierarchy; free it with bamg_destroy. Input errors:
+ * BAMG_E_ARG for a malformed CSR (row pointers, column range or order),
+ * BAMG_E_NONFINITE for a NaN or Inf entry, BAMG_E_NOT_STOCHASTIC for a
+ * negative entry or a column sum off 1, BAMG_E_REDUCIBLE for a chain that
+ * is not strongly connected (with validate = 3 these two may come from the
+ * first solve instead, as stated for bamg_options.validate). */
 bamg_status bamg_setup(const bamg_csr *A, const bamg_geometry *geom, const bamg_options *opt,
                        const bamg_allocator *alloc, void *hip_stream, bamg_handle **out);
 

@@ -52,7 +52,8 @@ __global__ void k_b_fill(const int *__restrict__ rp, const int *__restrict__ ci,
   }
 }
 
-// Structural checks of the input CSR: indices in range, strictly ascending.
+// Checks of the input CSR: indices in range and strictly ascending (flag
+// bit 0), entries non-negative (bit 1), entries finite (bit 2).
 __global__ void k_check_csr(const int *__restrict__ rp, const int *__restrict__ ci,
                             const double *__restrict__ a, int n, int nnz, int *__restrict__ flag) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -66,7 +67,8 @@ __global__ void k_check_csr(const int *__restrict__ rp, const int *__restrict__ 
     const int j = ci[k];
     if (j < 0 || j >= n || (k > b && j <= ci[k - 1])) atomicOr(flag, 1);
     const double v = a[k];
-    if (!(v >= 0.0) || !isfinite(v)) atomicOr(flag, 2);
+    if (!isfinite(v)) atomicOr(flag, 4);
+    else if (!(v >= 0.0)) atomicOr(flag, 2);
   }
 }
 
@@ -365,6 +367,7 @@ int check_input(Pool &pool, const int *arp, const int *aci, const double *aval, 
   const int f = read_int(flag, s);
   pool.release(flag);
   if (f & 1) return BAMG_E_ARG;
+  if (f & 4) return BAMG_E_NONFINITE;
   if (f & 2) return BAMG_E_NOT_STOCHASTIC;
   return BAMG_OK;
 }

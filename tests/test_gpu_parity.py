@@ -263,6 +263,14 @@ def test_error_codes():
     with pytest.raises(bamg.BamgError) as e:
         bamg.Hierarchy.from_chain(bad, bamg.options_for(ch, r=6, max_levels=2, coarse_max=1))
     assert e.value.code == -2
+    # a non-finite entry of A is BAMG_E_NONFINITE, whatever else is wrong
+    A = ch.to_scipy().tocsr(copy=True)
+    A.data[5] = np.nan
+    A.data[7] = -1.0
+    with pytest.raises(bamg.BamgError) as e:
+        bamg.Hierarchy.from_chain(chaingen.Chain(A, ch.geom),
+                                  bamg.options_for(ch, r=6, max_levels=2, coarse_max=1))
+    assert e.value.code == -7
 
 
 def test_deferred_validation():
