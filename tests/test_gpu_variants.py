@@ -225,3 +225,41 @@ def test_flexible_gmres(name, make, kw):
             h.close()
     assert its["mixed", 1] <= its["fp64", 0] + 1, its
     assert its["mixed", 1] <= its["mixed", 0], its
+
+
+RANDOM_RATES = [
+    # rates of seed 14024003 (0.302, 0.230, 0.468): the drift that stops the
+    # Jacobi-smoothed hierarchies from 513^2 up; with Kaczmarz sweeps 257^2
+    # and 513^2 still converge (the oracle: 34 iterations to 1e-13 and 336
+    # to 1e-10)
+    ("tandem257_random", 257, 1e-13),
+    ("tandem513_random", 513, 1e-10),
+]
+
+
+@pytest.mark.parametrize("name,size,tol", RANDOM_RATES, ids=[c[0] for c in RANDOM_RATES])
+def test_random_rate_tandem_kaczmarz_converges(name, size, tol):
+    """The largest random-rate tandems that converge: GMRES reaches tol with
+    the true residual checked on the host and x is a probability vector; at
+    257^2 (an oracle solve of a few seconds) x and the iteration count agree
+    with the oracle's. The stationary vector is ill-conditioned here (x at
+    1e-10 and at 1e-13 differ by 5e-8 in relative l1), so the comparison is
+    made at 1e-13."""
+    import torch
+    ch = chaingen.tandem(size, *chaingen.tandem_random_rates(14024003))
+    kw = dict(r=8, max_interp=4, coarse_max=300, nu_setup=8, seed=14024003,
+              smoother="kaczmarz")
+    hg = bamg.Hierarchy.from_chain(ch, bamg.options_for(ch, **kw))
+    xg, ig = hg.gmres(restart=20, tol=tol, maxit=1000)
+    torch.cuda.synchronize()
+    print(f"{name}: {ig.iterations} iterations, rel residual {ig.rel_residual:.2e}", flush=True)
+    assert ig.converged
+    x = xg.cpu().numpy()
+    A = ch.to_scipy()
+    assert np.linalg.norm(x - A @ x) / np.linalg.norm(x) < 2 * tol
+    assert abs(x.sum() - 1.0) < 1e-12 and x.min() > -1e-9 * x.max()
+    if size <= 257:
+        ho = oracle.Hierarchy(ch, oracle.options_for(ch, **kw))
+        xo, io = ho.gmres(m=20, tol=tol, maxit=1000)
+        assert io.converged and abs(ig.iterations - io.iterations) <= 20
+        assert rel_l1(x, xo) < 1e-9
