@@ -195,6 +195,10 @@ typedef struct {
   int32_t mlp_fallback;  /* 1 if a learned hierarchy was replaced by the exact-LS one
                             during this solve (bamg_options.learned_max_iters) */
   double t_setup_ms;     /* host wall time of the setup(s) behind the final hierarchy */
+  int64_t mlp_rows;      /* learned form: F rows of the final hierarchy that took the
+                            network's correction (0 otherwise) */
+  int64_t ls_fallbacks;  /* learned form: F rows that kept the exact LS fit because the
+                            network's row failed the objective test (0 otherwise) */
 } bamg_solve_info;
 
 typedef struct bamg_handle bamg_handle;

@@ -74,7 +74,8 @@ class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
                 ("breakdowns", C.c_int32), ("rel_residual", C.c_double), ("x_min", C.c_double),
                 ("t_solve_ms", C.c_double), ("setup_cycles", C.c_int32),
-                ("mlp_fallback", C.c_int32), ("t_setup_ms", C.c_double)]
+                ("mlp_fallback", C.c_int32), ("t_setup_ms", C.c_double),
+                ("mlp_rows", C.c_int64), ("ls_fallbacks", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -467,6 +467,19 @@ static bamg_status gmres_impl(bamg_handle *h, void *x, int32_t restart, double t
                               int32_t max_iters, int32_t use_x0, bamg_solve_info *info,
                               void *hip_stream);
 
+// Learned-row counts of the hierarchy a solve ended on; a read that fails
+// leaves them 0 (the solve's own status is what the caller gets).
+static void learned_counts(const bamg_handle *h, hipStream_t s, bamg_solve_info *inf) {
+  inf->mlp_rows = inf->ls_fallbacks = 0;
+  if (!h->lcount) return;
+  int c[2] = {0, 0};
+  if (hipMemcpyAsync(c, h->lcount, sizeof(c), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return;
+  inf->mlp_rows = c[0];
+  inf->ls_fallbacks = c[1];
+}
+
 bamg_status bamg_gmres_solve(bamg_handle *h, void *x, int32_t restart, double tol,
                              int32_t max_iters, int32_t use_x0, bamg_solve_info *info,
                              void *hip_stream) {
@@ -505,6 +518,7 @@ static bamg_status gmres_impl(bamg_handle *h, void *x, int32_t restart, double t
         cur.mlp_fallback = fell_back ? 1 : 0;
         cur.t_setup_ms = h->t_setup_ms;
         *inf = cur;
+        if (e.code == BAMG_NOT_CONVERGED) learned_counts(h, s, inf);
         throw;
       }
       more = true;
@@ -526,6 +540,7 @@ static bamg_status gmres_impl(bamg_handle *h, void *x, int32_t restart, double t
   inf->setup_cycles = h->opt.setup_cycles;
   inf->mlp_fallback = fell_back ? 1 : 0;
   inf->t_setup_ms = h->t_setup_ms;
+  learned_counts(h, s, inf);
   return BAMG_OK;
   BAMG_CATCH
 }

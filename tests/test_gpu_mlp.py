@@ -159,6 +159,7 @@ def test_learned_rows_follow_the_objective_rule():
     a, b = use.learned_stats()
     assert a + b == sum(int((use.cf(l)[0] == 0).sum()) for l in range(use.levels - 1))
     x, info = use.gmres(restart=20, tol=1e-14, maxit=400)
+    assert (info.mlp_rows, info.ls_fallbacks) == (a, b)
     xo, _ = oracle.Hierarchy(ch, oracle.options_for(ch, **kw)).gmres(m=20, tol=1e-14, maxit=400)
     assert info.converged
     xs = x.cpu().numpy()
@@ -186,6 +187,7 @@ def test_learned_iteration_fallback():
     assert il.iterations >= 2
     assert il.t_setup_ms > 0
     assert hl.learned_stats() == (0, 0)  # the hierarchy now is the exact-LS one
+    assert (il.mlp_rows, il.ls_fallbacks) == (0, 0)
     xl, xp = xl.cpu().numpy(), xp.cpu().numpy()
     assert np.abs(xl - xp).sum() / np.abs(xp).sum() < 1e-10
     # without the cap there is no fallback
