@@ -596,6 +596,9 @@ def main():
             "coarsening": {0: "geometric", 1: "mis", 2: "cr"}[opts.coarsening],
             "validation": {0: "none", 1: "joined by the setup", 2: "joined by the setup",
                            3: "joined by the solve"}[opts.validate],
+            "autotune": ("lanes per row and workgroup size of each level's sweeps, timed "
+                         "during the warm-up steps and reused by the timed steps (the "
+                         "choices change speed only, not results)") if args.autotune else "off",
         },
         "iterations": it,
         "converged": [bool(i.converged) for i in infos],
