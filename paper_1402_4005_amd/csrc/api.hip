@@ -147,6 +147,12 @@ void bamg_handle::join_validation(bool wait_main) {
   aux_ready = aux_done = nullptr;
 }
 
+void bamg_handle::search_more() {
+  if (!vdeferred || !aux || !vqueues) return;
+  vdeferred = false;
+  vlevels = bamg::reach_more(lv[0].B, lv[0].Bt, vvisited, vqueues, vflag, vlevels, aux);
+}
+
 int bamg_handle::finish_validation() {
   if (!aux) return vstatus;
   join_validation(true);

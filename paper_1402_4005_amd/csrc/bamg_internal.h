@@ -146,6 +146,9 @@ struct bamg_handle {
   unsigned *vvisited = nullptr;  // the search's buffers, released after the join
   int *vqueues = nullptr;
   int vlevels = 0;               // levels the global-form search enqueued
+  bool vdeferred = false;        // its later levels are still to be enqueued
+  // enqueue the deferred levels of the global-form search (no-op otherwise)
+  void search_more();
   int vstatus = BAMG_OK;         // outcome once joined
   void join_validation(bool wait_main);
   int validation_result();
@@ -209,6 +212,8 @@ void colsum_launch(const Csr &Bt, const double *btv, int *flag, hipStream_t s);
 // do not fit in LDS or when force_global is set); queues: 4 n ints
 int reach_launch(const Csr &B, const Csr &Bt, unsigned *visited, int *queues, int *flag,
                  bool force_global, hipStream_t s);
+int reach_more(const Csr &B, const Csr &Bt, unsigned *visited, int *queues, int *flag, int k0,
+               hipStream_t s);
 void reach_finish(const Csr &B, const Csr &Bt, unsigned *visited, int *queues, int *flag,
                   int levels, hipStream_t s);
 int validation_status(const int *h, int n);
@@ -275,8 +280,11 @@ int jacobi_svd(Pool &pool, double *W, double *J, int n, hipStream_t s);
 // both SVDs in the same launches (W2 nullable); W, J col-major. prof: a
 // handle whose profiled kernel is the coarsest SVD (its round launches are
 // bracketed by events and their algorithmic bytes summed), else nullptr
+// after_first(ctx), when given, runs on the host once the first group of
+// round launches is enqueued (the stream then holds tens of ms of work)
 int jacobi_svd2(Pool &pool, double *W, double *J, double *W2, double *J2, int n, hipStream_t s,
-                bamg_handle *prof = nullptr);
+                bamg_handle *prof = nullptr, void (*after_first)(void *) = nullptr,
+                void *ctx = nullptr);
 void column_norms(const double *W, int n, double *sv, hipStream_t s);
 void coarse_triplets_out(const double *LM, const double *LN, const double *W, const double *J,
                          const double *sv, int n, int r, void *U, void *V, int prec,

@@ -810,7 +810,7 @@ int jacobi_svd(Pool &pool, double *W, double *J, int n, hipStream_t s) {
 // rotates. Sweeps are enqueued in groups and the convergence flag is read
 // back after each group; launches behind the converged sweep return at once.
 int jacobi_svd2(Pool &pool, double *W, double *J, double *W2, double *J2, int n, hipStream_t s,
-                bamg_handle *prof) {
+                bamg_handle *prof, void (*after_first)(void *), void *ctx) {
   int dev = 0, maxlds = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -865,6 +865,10 @@ int jacobi_svd2(Pool &pool, double *W, double *J, double *W2, double *J2, int n,
       LAUNCHCHK();
     }
     if (prof) profile_mark(prof, s, false);
+    if (after_first) {
+      after_first(ctx);
+      after_first = nullptr;
+    }
     HIPCHK(hipMemcpyAsync(hp, ctrl + kSvdMaxSweeps, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     done = hp[1];

@@ -121,7 +121,11 @@ __global__ void k_colsum_check(const int *__restrict__ trp, const int *__restric
 // reached are counted from the bitmap at the end.
 constexpr int kReachDepth = 32, kReachStack = 10, kReachStateBits = 26;
 constexpr int kReachThreads = 256, kReachBlocks = 64;  // global form, per direction
-constexpr int kReachLevels = 512;  // levels enqueued at launch; more at the join if needed
+// Levels enqueued with the setup: kReachFirst when the search starts, the
+// rest up to kReachLevels by reach_more once the setup's own stream holds a
+// long queue of work (so the host time of those launches does not delay the
+// setup), more at the join if the search needs them.
+constexpr int kReachFirst = 32, kReachLevels = 512;
 
 __global__ void __launch_bounds__(1024)
     k_reach_lds(const int *__restrict__ rp0, const int *__restrict__ ci0,
@@ -321,8 +325,20 @@ int reach_launch(const Csr &B, const Csr &Bt, unsigned *visited, int *queues, in
   k_reach_init<<<ceil_div(2 * words, 256), 256, 0, s>>>(visited, queues, queues + 4 * (size_t)n,
                                                         n);
   LAUNCHCHK();
-  reach_levels(B, Bt, visited, queues, 0, kReachLevels, s);
+  reach_levels(B, Bt, visited, queues, 0, kReachFirst, s);
   reach_count(visited, n, flag, s);
+  return kReachFirst;
+}
+
+// Levels k0 .. kReachLevels - 1 of a global-form search started by
+// reach_launch on the same stream s, then the reached states counted again.
+// Returns the number of levels now enqueued.
+int reach_more(const Csr &B, const Csr &Bt, unsigned *visited, int *queues, int *flag, int k0,
+               hipStream_t s) {
+  if (k0 >= kReachLevels) return k0;
+  reach_levels(B, Bt, visited, queues, k0, kReachLevels, s);
+  fill_i32(flag + 1, 0, 2, s);
+  reach_count(visited, B.nr, flag, s);
   return kReachLevels;
 }
 

@@ -193,6 +193,10 @@ struct Setup {
     }
   }
 
+  // the deferred levels of the strong-connectivity search go beside the
+  // SVD rounds, which leave most CUs and most of the memory bandwidth free
+  static void search_hook(void *p) { static_cast<bamg_handle *>(p)->search_more(); }
+
   // r smallest generalized singular triplets on the coarsest level. In the
   // last setup cycle B_L is final, so its pseudo-inverse (the coarse solve
   // of the V-cycle) is computed in the same launches.
@@ -225,8 +229,8 @@ struct Setup {
     transpose_dense(X, W, n, s);
     trsm_lower_cols(Nd, W, n, n, n, s);  // W = L_N^-1 X^T, i.e. Bt column-major
     bamg_handle *prof = h->prof_kernel == BAMG_PROFILE_COARSEST_SVD ? h : nullptr;
-    if (jacobi_svd2(pool(), W, J, last ? W2 : nullptr, last ? J2 : nullptr, n, s, prof) !=
-        BAMG_OK)
+    if (jacobi_svd2(pool(), W, J, last ? W2 : nullptr, last ? J2 : nullptr, n, s, prof,
+                    &search_hook, h) != BAMG_OK)
       fail(BAMG_E_COARSE, "Jacobi SVD did not converge");
     column_norms(W, n, sv, s);
     coarse_triplets_out(Md, Nd, W, J, sv, n, r, C.U, C.V, h->prec, h->sigma, work, s);
@@ -351,6 +355,7 @@ void setup_all(bamg_handle *h, const bamg_csr *A, const bamg_geometry *geom) {
       unsigned *visited = pool.get<unsigned>(2 * (size_t)((n + 31) / 32));
       int *queues = pool.get<int>(4 * (size_t)n + 64);
       h->vlevels = reach_launch(L0.B, L0.Bt, visited, queues, h->vflag, o.validate == 2, h->aux);
+      h->vdeferred = h->vlevels > 0;  // global form: the rest by search_more
       HIPCHK(hipEventRecord(h->aux_done, h->aux));
       h->vvisited = visited;  // released after the join
       h->vqueues = queues;
@@ -532,6 +537,7 @@ void setup_all(bamg_handle *h, const bamg_csr *A, const bamg_geometry *geom) {
     else
       h->lv[l].lanes = sweep_lanes_default(h->lv[l].n, h->lv[l].B.nnz);
   }
+  h->search_more();  // when no SVD round loop took them
   if (o.validate != 3) {
     st = h->finish_validation();
     if (st != BAMG_OK) fail(st, "transition matrix rejected");
